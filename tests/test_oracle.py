@@ -1,0 +1,266 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+Each test names what fixes the expected value: a number printed in the paper,
+a closed form, an invariant, or a library routine applied to a special case.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import allatonce, condition, sequential
+from oracle.discretization import (jacobian_stencil, level_jacobian, level_residual,
+                                   stencil_to_sparse)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append([float(v) for v in line.split()])
+    return rows
+
+
+def _round_sig(x, digits):
+    return float(f"{x:.{digits - 1}e}")
+
+
+# ----------------------------------------------------------- paper's tables
+
+@pytest.mark.parametrize("row", _golden("table1_heat_linf.txt"), ids=lambda r: f"N{int(r[0])}")
+def test_table1_heat_error_reproduced(row):
+    """Section 8.1, Table 1: the L-inf error of sequential BDF1 to the printed 3 digits."""
+    nint, expected = int(row[0]), row[1]
+    p = W.heat_mms(nint)
+    U, _ = sequential.solve_sequential(p, tol=1e-13)
+    X, Y = p.mesh()
+    err = max(np.max(np.abs(U[n] - W.heat_exact(X, Y, (n + 1) * p.dt))) for n in range(p.nt))
+    assert _round_sig(err, 3) == pytest.approx(expected, rel=1e-9)
+
+
+@pytest.mark.parametrize("row", [r for r in _golden("table4_burgers_l1.txt") if r[2] == 1],
+                         ids=lambda r: f"N{int(r[0])}")
+def test_table4_burgers_error_reproduced(row):
+    """Section 8.2, Table 4 (three finest grids): L1 error within 1% on [-0.5,0.5]^2."""
+    nint, expected = int(row[0]), row[1]
+    p = W.burgers_mms(nint, x0=-0.5, y0=-0.5)
+    U, _ = sequential.solve_sequential(p, tol=1e-13)
+    X, Y = p.mesh()
+    err = sum(np.sum(np.abs(U[n] - W.burgers_exact(X, Y, (n + 1) * p.dt)))
+              for n in range(p.nt)) * p.hx * p.hy * p.dt
+    assert err == pytest.approx(expected, rel=1e-2)
+
+
+def test_condition_example_gives_22_levels():
+    """Section 7: N_x = 64, mu = 1e-3, c = 1 allows at most 22 levels."""
+    assert condition.max_levels_eq_cond(64, 1e-3, c=1.0, eps_rof=1e-16) == 22
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n,kx,ky", [(7, 1, 1), (12, 2, 3), (9, 4, 1)])
+def test_linear_heat_dirichlet_fourier_decay(n, kx, ky):
+    """Linear heat (mu_b = 0), zero Dirichlet: sin modes decay by 1/(1 + tau mu lambda)
+    per level, lambda the five-point Laplacian eigenvalue of Section 7."""
+    mu, dt, nt = 0.7, 2e-3, 6
+    h = 1.0 / (n + 1)
+    x = (np.arange(n) + 1.0) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = np.sin(math.pi * kx * X) * np.sin(math.pi * ky * Y)
+    p = W.heat_dirichlet(n, nt, dt, u0, mu_a=mu, mu_b=0.0)
+    lam = 4.0 / h ** 2 * (math.sin(math.pi * kx * h / 2) ** 2 + math.sin(math.pi * ky * h / 2) ** 2)
+    U, _ = sequential.solve_sequential(p)
+    for lvl in range(nt):
+        expect = u0 / (1.0 + dt * mu * lam) ** (lvl + 1)
+        np.testing.assert_allclose(U[lvl], expect, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,kx,ky", [(8, 1, 0), (10, 2, 3)])
+def test_linear_heat_periodic_fourier_decay(n, kx, ky):
+    """Periodic linear heat: cos(2 pi k.x) decays by 1/(1 + tau mu lambda),
+    lambda = (4/h^2)(sin^2(pi kx h) + sin^2(pi ky h))."""
+    mu, dt, nt = 0.3, 1e-3, 5
+    h = 1.0 / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = np.cos(2 * math.pi * (kx * X + ky * Y))
+    p = W.Problem(W.HEAT, W.PERIODIC, n, n, nt, h, h, dt, mu, 0.0, u0)
+    lam = 4.0 / h ** 2 * (math.sin(math.pi * kx * h) ** 2 + math.sin(math.pi * ky * h) ** 2)
+    U, _ = sequential.solve_sequential(p)
+    for lvl in range(nt):
+        np.testing.assert_allclose(U[lvl], u0 / (1.0 + dt * mu * lam) ** (lvl + 1), atol=1e-14)
+
+
+def test_burgers_linearized_mode():
+    """Burgers about a constant state c: a small Fourier mode moves with the central-difference
+    symbol, amplification 1/(1 + tau[i c (sin 2pi kx h + sin 2pi ky h)/h + nu lambda])."""
+    n, nt, dt, nu, c, eps = 16, 8, 2e-3, 0.02, 0.8, 1e-7
+    kx, ky = 2, 1
+    h = 1.0 / n
+    x = np.arange(n) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    theta = 2 * math.pi * (kx * X + ky * Y)
+    p = W.burgers_periodic(n, nt, dt, nu, c + eps * np.cos(theta))
+    lam = 4.0 / h ** 2 * (math.sin(math.pi * kx * h) ** 2 + math.sin(math.pi * ky * h) ** 2)
+    sym = 1j * c * (math.sin(2 * math.pi * kx * h) + math.sin(2 * math.pi * ky * h)) / h + nu * lam
+    g = 1.0 / (1.0 + dt * sym)
+    U, _ = sequential.solve_sequential(p)
+    for lvl in range(nt):
+        expect = np.real(g ** (lvl + 1) * np.exp(1j * theta))
+        np.testing.assert_allclose((U[lvl] - c) / eps, expect, atol=2e-6)
+
+
+@pytest.mark.parametrize("b", [0.0, 0.37])
+def test_single_node_heat_step_is_cubic_root(b):
+    """One interior node with Dirichlet value b on all sides: the BDF1 equation is the cubic
+    u - u_prev + 4 tau mu((u+b)/2)(u-b)/h^2 = 0, solved here with numpy.roots."""
+    mu_a, mu_b, dt, h, uprev = 0.2, 1.3, 0.05, 0.5, 0.9
+    p = W.Problem(W.HEAT, W.DIRICHLET, 1, 1, 1, h, h, dt, mu_a, mu_b,
+                  np.array([[uprev]]), np.full((1, 4), b))
+    U, _ = sequential.solve_sequential(p, tol=1e-15)
+    # 4 tau/h^2 (mu_a + mu_b (u+b)^2/4)(u - b) + u - uprev as a polynomial in u
+    k = 4.0 * dt / h ** 2
+    poly = np.polynomial.Polynomial
+    u = poly([0.0, 1.0])
+    expr = k * (mu_a + mu_b * (u + b) ** 2 / 4.0) * (u - b) + u - uprev
+    roots = np.roots(expr.coef[::-1])
+    real = roots[np.abs(roots.imag) < 1e-12].real
+    assert len(real) == 1
+    assert U[0, 0, 0] == pytest.approx(real[0], abs=1e-14)
+
+
+# --------------------------------------------------------------- invariants
+
+def test_periodic_burgers_conserves_sum():
+    """Central flux differences and the conservative viscous form telescope on a periodic grid."""
+    p = W.burgers_periodic(12, 6, 5e-3, 0.01, W.fourier_u0_periodic(12, 7))
+    U, _ = sequential.solve_sequential(p)
+    s0 = p.u0.sum()
+    for lvl in range(p.nt):
+        assert U[lvl].sum() == pytest.approx(s0, abs=1e-12)
+
+
+def test_constant_state_is_steady():
+    p = W.burgers_periodic(8, 3, 1e-2, 0.01, np.full((8, 8), 0.6))
+    for bc_kind in (W.BURGERS, W.HEAT):
+        p.kind = bc_kind
+        G = level_residual(p.u0, p.u0, p)
+        assert np.max(np.abs(G)) == 0.0
+
+
+def test_heat_symmetry_preserved():
+    """u0 = sin(pi x) sin(pi y) is symmetric under x <-> y and x -> 1 - x; so is the solution."""
+    p = W.heat32(nt=4)
+    U, _ = sequential.solve_sequential(p)
+    for lvl in range(p.nt):
+        np.testing.assert_allclose(U[lvl], U[lvl].T, atol=1e-14)
+        np.testing.assert_allclose(U[lvl], U[lvl][:, ::-1], atol=1e-14)
+
+
+# --------------------------------------------------------------- Jacobian
+
+def _complex_step_jacobian(u, uprev, p, bvals):
+    ns = u.size
+    Jc = np.zeros((ns, ns))
+    hstep = 1e-30
+    for k in range(ns):
+        v = u.astype(np.complex128).ravel()
+        v[k] += 1j * hstep
+        G = level_residual(v.reshape(u.shape), uprev, p, bvals)
+        Jc[:, k] = G.imag.ravel() / hstep
+    return Jc
+
+
+@pytest.mark.parametrize("case", ["heat_dirichlet", "heat_periodic", "burgers_dirichlet",
+                                  "burgers_periodic", "burgers_periodic_3x5"])
+def test_jacobian_matches_complex_step(case):
+    """A = I + tau dF/du equals the complex-step derivative of G at every point type
+    (interior, edge, corner, periodic wrap, short periodic rows with repeated neighbours)."""
+    rng = np.random.default_rng(11)
+    kind = W.HEAT if case.startswith("heat") else W.BURGERS
+    bc = W.PERIODIC if "periodic" in case else W.DIRICHLET
+    nx, ny = (3, 5) if case.endswith("3x5") else (5, 4)
+    u = rng.uniform(-1, 1.5, size=(ny, nx))
+    mu_b = 0.7 if kind == W.HEAT else 0.0
+    p = W.Problem(kind, bc, nx, ny, 1, 0.3, 0.2, 0.05, 0.4, mu_b, u)
+    bvals = rng.uniform(-1, 1, size=2 * (nx + ny)) if bc == W.DIRICHLET else None
+    J = level_jacobian(u, p, bvals).toarray()
+    Jc = _complex_step_jacobian(u, rng.uniform(size=u.shape), p, bvals)
+    np.testing.assert_allclose(J, Jc, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------ all-at-once system
+
+def _tiny_problems():
+    rng = np.random.default_rng(3)
+    heat = W.heat_dirichlet(4, 5, 2e-3, rng.uniform(0, 1, (4, 4)))
+    burg = W.burgers_periodic(6, 6, 4e-3, 0.02, W.fourier_u0_periodic(6, 5))
+    mms = W.heat_mms(5)
+    return [heat, burg, mms]
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_global_newton_step_forms_agree(idx):
+    """One Newton step of Eq. (6): dense LU of the full space-time Jacobian (numpy) equals
+    the sparse LU, the block inverse of Eq. (7) and Theorem 1's decoupled system (Eq. (8))."""
+    p = _tiny_problems()[idx]
+    rng = np.random.default_rng(idx)
+    U = p.plain_iterate() + 0.05 * rng.standard_normal((p.nt, p.ny, p.nx))
+    M = allatonce.global_jacobian(U, p).toarray()
+    R = allatonce.global_residual(U, p)
+    dense = np.linalg.solve(M, R.ravel()).reshape(U.shape)
+    scale = np.max(np.abs(dense))
+    for step in (allatonce.newton_step_direct, allatonce.newton_step_inverse):
+        dU, _ = step(U, p)
+        assert np.max(np.abs(dU - dense)) <= 1e-12 * scale
+    for window in (None, 1, 2, 3):
+        dU, _ = allatonce.newton_step_theorem1(U, p, window)
+        assert np.max(np.abs(dU - dense)) <= 1e-10 * scale
+
+
+def test_product_matrix_diagonal_count():
+    """Section 5 remark: for n < N_x = N_y, P^n = A_1 ... A_n has 2n^2 + 2n + 1 nonzero diagonals."""
+    n = 10
+    rng = np.random.default_rng(5)
+    p = W.heat_dirichlet(n, 5, 1e-3, rng.uniform(0.5, 1, (n, n)))
+    P = None
+    for lvl in range(1, 5):
+        A = level_jacobian(rng.uniform(0.5, 1.0, (n, n)), p).toarray()
+        P = A if P is None else P @ A
+        rows, cols = np.nonzero(np.abs(P) > 0)
+        assert len(np.unique(cols - rows)) == 2 * lvl * lvl + 2 * lvl + 1
+
+
+def test_allatonce_equals_sequential_heat():
+    p = W.heat_dirichlet(8, 10, 1e-3, np.zeros((8, 8)))
+    X, Y = p.mesh()
+    p.u0 = np.sin(math.pi * X) * np.sin(math.pi * Y) + 0.3 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    Us, _ = sequential.solve_sequential(p)
+    Ua, rh, _ = allatonce.solve_allatonce(p, tol=1e-13)
+    assert rh[-1] <= 1e-13
+    assert np.max(np.abs(Ua - Us)) <= 1e-12 * np.max(np.abs(Us))
+
+
+def test_allatonce_equals_sequential_burgers():
+    p = W.burgers_periodic(16, 12, 5e-3, 0.01, W.fourier_u0_periodic(16, 2))
+    Us, _ = sequential.solve_sequential(p)
+    Ua, rh, _ = allatonce.solve_allatonce(p, tol=1e-13)
+    assert np.max(np.abs(Ua - Us)) <= 1e-12 * np.max(np.abs(Us))
+
+
+def test_global_newton_converges_quadratically():
+    """Section 4: the all-at-once Newton keeps the quadratic rate of sequential Newton."""
+    p = W.heat32(nt=16)
+    _, rh, _ = allatonce.solve_allatonce(p, tol=1e-15, maxit=12)
+    # ratios r_{k+1} / r_k^2 stay bounded while above the roundoff floor
+    ratios = [rh[k + 1] / rh[k] ** 2 for k in range(len(rh) - 1) if rh[k + 1] > 1e-13]
+    assert len(ratios) >= 2
+    assert max(ratios[1:]) < 50.0
+    assert rh[-1] < 1e-13
