@@ -1,0 +1,158 @@
+"""Benchmark: converged space-time DOF/s of the all-at-once BDF1 Newton solve on one MI355X.
+
+One step = one whole solve of the hot path on the resident input: the plain initial
+iterate u^n = u^0, then all-at-once Newton iterations (all-level residual and Jacobian,
+block-inverse coupling, per-level block solves, update and convergence reductions) until
+max |R| <= tol. The default workload is periodic viscous Burgers, nu = 0.01, 256 x 256
+nodes, 512 BDF1 levels, dt = 5e-4, random Fourier initial condition (seed 2406002), FP64.
+
+Prints one JSON line. Run with --help for options.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged space-time DOF/s at 1e-8 rel. err vs FP64 oracle; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import workloads as W
+    if name == "burgers256":
+        return W.burgers256(), {"seed": 2406002, "nu": 0.01}
+    if name == "heat32":
+        return W.heat32(), {"k": "1+u^2"}
+    if name == "burgers512":
+        return W.burgers512_disc(), {"seed": 2406003, "nu": 1e-3}
+    if name == "burgers256nu005":
+        return W.burgers256_learned(), {"seed": 2406055, "nu": 0.005}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(prob, budget_s, U_gpu):
+    """Time the CPU oracle (sequential FP64 BDF1 + Newton) on the first levels of the workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sequential
+    with threadpool_limits(limits=1):
+        # calibrate on a few levels (the first level is cheaper than later ones)
+        cal = min(prob.nt, 4)
+        t0 = time.perf_counter()
+        sequential.solve_sequential(prob, levels=cal)
+        t1 = (time.perf_counter() - t0) / cal
+        levels = int(max(1, min(prob.nt, math.floor(0.7 * budget_s / max(t1, 1e-3)))))
+        t0 = time.perf_counter()
+        Us, iters = sequential.solve_sequential(prob, levels=levels)
+        dt = time.perf_counter() - t0
+    err = float(np.max(np.abs(U_gpu[:levels] - Us)) / np.max(np.abs(Us)))
+    return {
+        "value": levels * prob.ns / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+        "sample": f"first {levels} of {prob.nt} levels ({levels * prob.ns} DOF) in {dt:.1f} s, "
+                  f"numpy/scipy single thread, {sum(iters)} Newton steps",
+    }, err, levels
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="burgers256")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="auto")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(instances and time levels would shard across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2406_00878_amd as P
+
+    prob, extra = workload(args.workload)
+    dev = torch.device("cuda:0")
+    u0 = torch.as_tensor(prob.u0, dtype=torch.float64, device=dev).contiguous()
+    U = torch.empty((prob.nt, prob.ny, prob.nx), dtype=torch.float64, device=dev)
+    ws = P.workspace(prob, args.precision, dev)
+    opts = dict(schedule=args.schedule, use_graph=not args.no_graph)
+    print(f"[bench] {args.workload} {prob.nx}x{prob.ny}x{prob.nt} {args.precision} "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+
+    def step():
+        P.init_plain(prob, U, u0)
+        return P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, **opts)
+
+    for _ in range(args.warmup):
+        st = step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    stats = []
+    for _ in range(args.steps):
+        stats.append(step())
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    st = stats[-1]
+    U_host = U.cpu().numpy()
+    print(f"[bench] {ms:.2f} ms/solve, newton={st['iterations']} sweeps={st['sweeps']} "
+          f"res={st['res_inf'][-1]:.2e}", file=sys.stderr, flush=True)
+
+    # dominant kernel (per-level solve): average launch duration from HIP events recorded
+    # on the launch stream during one extra, profiled solve
+    P.init_plain(prob, U, u0)
+    pst = P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, profile=True,
+                  schedule="bulk")
+    torch.cuda.synchronize()
+    n_ls = max(pst["prof_count"][1], 1)
+    avg_ms = pst["prof_ms"][1] / n_ls
+    bytes_per_launch = pst["level_solve_bytes"] / n_ls
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    print(f"[bench] k_level_solve: {n_ls} launches, avg {avg_ms * 1e3:.2f} us, "
+          f"{bytes_per_launch / 1e6:.2f} MB/launch; kernel split ms {pst['prof_ms']}",
+          file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": prob.dof / (ms * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "nt": prob.nt, "dt": prob.dt,
+                   "precision": args.precision, "tol": args.tol, "newton_steps": st["iterations"],
+                   "inner_sweeps": st["sweeps"], "schedule": st["schedule"], **extra},
+        "roofline": {"bound": "hbm", "kernel": "k_level_solve", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        cb, err, levels = cpu_baseline(prob, args.cpu_seconds, U_host)
+        out["cpu_baseline"] = cb
+        out["rel_err_vs_oracle"] = {"value": err, "levels_checked": levels}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

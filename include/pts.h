@@ -1,0 +1,180 @@
+/*
+ * pts.h - C ABI of the space-time BDF1 Newton library for MI355X (gfx950).
+ *
+ * The library solves the all-at-once BDF1 system of a 2-D scalar conservation
+ * law (Section 3, Eq. (4)):
+ *     (u^n - u^{n-1}) + tau F(u^n) = 0,   n = 1..N_t,
+ * where F is the three-point central discretization of Eq. (3): central
+ * differences of the fluxes f = g = cflux u^2 and the conservative viscous
+ * operator with face viscosity mu((u_i + u_{i+1})/2), mu(u) = mu_a + mu_b u^2.
+ * Each Newton iteration solves the block lower-bidiagonal system of Eq. (6),
+ * whose blocks are A_n = I + tau dF/du(u^n) and -I, by the block inverse of
+ * Eq. (7) (windows of one level) or the decoupled products of Theorem 1 /
+ * Eq. (8) inside windows of W levels.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are DEVICE pointers owned by the caller, float64, contiguous.
+ *     A level is [ny][nx] with x fastest (Section 3, Eq. (4)); the space-time
+ *     iterate U is [nt][ny][nx] and holds levels 1..nt; u0 is [ny][nx].
+ *   - Dirichlet problems count interior unknowns: node (i, j) sits at
+ *     (x0 + (i+1) hx, y0 + (j+1) hy). Periodic problems have nodes
+ *     (x0 + i hx, y0 + j hy) and wrap. The library never needs x0, y0.
+ *   - Dirichlet data (bdata) is a device array [nt][2(nx+ny)]: per level the
+ *     south row (i = 0..nx-1), north row, west column (j = 0..ny-1), east
+ *     column. NULL means zero data. Ignored for periodic problems.
+ *   - Every call is enqueued on `stream` (NULL = the default stream) and is
+ *     asynchronous unless stated otherwise.
+ *   - Return value: PTS_OK or a negative PTS_ERR_* code; pts_last_error()
+ *     returns a message for the calling thread. No C++ exception crosses the
+ *     ABI. On any error the output arrays are left in an unspecified but
+ *     finite-or-untouched state, except where stated.
+ */
+#ifndef PTS_H
+#define PTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pts_stream_t; /* hipStream_t */
+
+enum { PTS_HEAT = 0, PTS_BURGERS = 1 };       /* cflux = 0 | 1/2 (Section 2) */
+enum { PTS_DIRICHLET = 0, PTS_PERIODIC = 1 }; /* Eq. (2) | periodic box      */
+enum { PTS_FP64 = 0, PTS_MIXED = 1 };         /* inner per-level solve type  */
+enum { PTS_SCHED_AUTO = 0, PTS_SCHED_BULK = 1, PTS_SCHED_PIPELINE = 2 };
+
+enum {
+  PTS_OK = 0,
+  PTS_ERR_INVALID_ARG = -1,   /* bad sizes, NULL pointers, unsupported option */
+  PTS_ERR_HIP = -2,           /* a HIP runtime call failed                    */
+  PTS_ERR_NONFINITE = -3,     /* NaN/Inf in the input or in a residual        */
+  PTS_ERR_SINGULAR = -4,      /* a block A_n lost diagonal dominance: the
+                                 per-level solver has no convergence bound
+                                 (Theorem 1 assumes det A_n != 0)             */
+  PTS_ERR_NOT_CONVERGED = -5, /* max_iter reached; U holds the last iterate   */
+  PTS_ERR_WORKSPACE = -6      /* workspace NULL or smaller than required      */
+};
+
+/* One problem instance (Section 2, Eq. (1)-(3)). Read only. */
+typedef struct pts_problem {
+  int32_t kind;      /* PTS_HEAT or PTS_BURGERS                               */
+  int32_t bc;        /* PTS_DIRICHLET or PTS_PERIODIC                         */
+  int32_t nx, ny;    /* unknowns per direction, >= 1                          */
+  int32_t nt;        /* time levels, >= 1                                     */
+  int32_t precision; /* PTS_FP64 or PTS_MIXED (FP32 inner, FP64 refinement)   */
+  double hx, hy;     /* grid spacings > 0                                     */
+  double dt;         /* uniform step tau > 0 (the paper's runs use uniform tau) */
+  double mu_a, mu_b; /* mu(u) = mu_a + mu_b u^2 >= 0                          */
+  const double* bdata; /* device [nt][2(nx+ny)] Dirichlet data or NULL       */
+} pts_problem;
+
+/* Solver options. Zero-initialise for defaults. */
+typedef struct pts_options {
+  int32_t window;    /* Theorem-1 window W (levels decoupled together); 0 = auto
+                        (largest W allowed by the Section 7 condition bound and
+                        the autotuner), 1 = the block inverse of Eq. (7)       */
+  int32_t schedule;  /* PTS_SCHED_*: BULK = one Newton iteration after another,
+                        replayed as a HIP graph; PIPELINE = all iterations in one
+                        persistent launch, overlapped as a wavefront           */
+  int32_t sweeps;    /* inner Chebyshev sweeps per solve; 0 = from lin_tol     */
+  int32_t refine;    /* FP64 refinement passes (PTS_MIXED); < 0 = auto         */
+  double lin_tol;    /* relative reduction asked of each per-level solve;
+                        0 = 1e-9 (FP64) / 1e-6 per pass (MIXED)                */
+  int32_t use_graph; /* BULK only: 1 = capture the iteration in a HIP graph    */
+  int32_t stages;    /* PIPELINE only: Newton iterations per launch, 0 = auto  */
+  int32_t profile;   /* 1 = time every kernel with HIP events on `stream` (BULK
+                        schedule without graph); totals land in pts_stats      */
+} pts_options;
+
+#define PTS_MAX_HIST 64
+
+/* Per-solve statistics, written to HOST memory by pts_solve/pts_newton_step. */
+typedef struct pts_stats {
+  int32_t iterations;            /* Newton steps applied                       */
+  int32_t converged;             /* 1 if ||R||_inf <= tol on exit              */
+  int32_t window;                /* W used                                     */
+  int32_t sweeps;                /* inner sweeps per solve pass (last step)    */
+  int32_t refine;                /* refinement passes per solve (last step)    */
+  int32_t schedule;              /* schedule used                              */
+  int32_t launches;              /* kernel launches + graph replays issued     */
+  int32_t reserved;
+  double res_inf[PTS_MAX_HIST];  /* ||R(U_k)||_inf, k = 0..iterations          */
+  double upd_rms[PTS_MAX_HIST];  /* Section 8.1 RMS update norm, k = 1..       */
+  double rho_max[PTS_MAX_HIST];  /* max Gershgorin radius of D^-1 A_n at U_k   */
+  double solve_ms;               /* wall time inside pts_solve (host clock)    */
+  /* filled when pts_options.profile = 1: summed kernel time (ms) and launch count
+     per kernel class: [0] residual, [1] per-level solve, [2] update + reductions,
+     [3] other (fills, initial iterate)                                          */
+  double prof_ms[4];
+  int32_t prof_count[4];
+  /* algorithmic bytes moved by the per-level solve launches of the solve
+     (reads of u^n, r^n, du^{n-1}, the iterate of a previous launch; one write)  */
+  double level_solve_bytes;
+} pts_stats;
+
+/* Bytes of device workspace pts_newton_step / pts_solve need for `p`.
+   Returns 0 for an invalid problem (see pts_last_error). */
+size_t pts_workspace_bytes(const pts_problem* p);
+
+/* Residual and Jacobian blocks at every level (Eq. (5) right-hand side and
+   A_n of Eq. (6)).
+   U  : device [nt][ny][nx], u0 : device [ny][nx]
+   R  : device [nt][ny][nx] output, r^n = -(u^n - u^{n-1} + tau F(u^n))
+   coef: device [nt][5][ny][nx] output or NULL; planes C, W, E, S, N hold the
+         entries of A_n coupling node (i,j) to itself and to (i-1,j), (i+1,j),
+         (i,j-1), (i,j+1) (wrapped when periodic; 0 for a Dirichlet boundary
+         neighbour).
+   res_inf: device double[1] output or NULL, max |R|. */
+int pts_assemble(const pts_problem* p, const double* U, const double* u0, double* R,
+                 double* coef, double* res_inf, pts_stream_t stream);
+
+/* One all-at-once Newton step U <- U + dU, dU = M^{-1} R (Eq. (6)) computed by
+   the block inverse (Eq. (7)) / Theorem 1 windows with inexact per-level solves
+   of relative accuracy opts->lin_tol. Synchronises the stream once to read
+   ||R||_inf. stats (host, may be NULL) receives res_inf[0] = ||R(U_in)||. */
+int pts_newton_step(const pts_problem* p, double* U, const double* u0, void* workspace,
+                    size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
+                    pts_stream_t stream);
+
+/* Initial space-time iterate of plain Newton: u^n = u^0 for n = 1..nt. */
+int pts_init_plain(const pts_problem* p, double* U, const double* u0, pts_stream_t stream);
+
+/* Newton iteration from the iterate in U until ||R(U)||_inf <= tol (tau-scaled,
+   absolute, all levels) or max_iter steps. U is overwritten with the result;
+   on PTS_ERR_NOT_CONVERGED it holds the last iterate so a later call resumes.
+   Synchronises the stream (once per Newton step, or per launch when
+   pipelined). */
+int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int max_iter,
+              void* workspace, size_t workspace_bytes, const pts_options* opts,
+              pts_stats* stats, pts_stream_t stream);
+
+/* Independent instances solved together, every instance's levels batched in
+   the same launches. U[i], u0[i] are device pointers; workspace is one block of
+   pts_workspace_bytes_batched bytes; stats is a host array of nprob entries
+   (may be NULL). */
+size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob);
+int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U,
+                      const double* const* u0, double tol, int max_iter, void* workspace,
+                      size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
+                      pts_stream_t stream);
+
+/* Section 7, Eq. (cond): largest number of levels W whose product of blocks
+   keeps the estimated condition number K^W below c h^4 / eps, with
+   K = (1 + 8 mu tau/h^2)/(1 + 2 pi^2 mu tau). If tau <= 0 the paper's setting
+   tau = 1/W is used (the worked example N_x = 64, mu = 1e-3, c = 1,
+   eps = 1e-16 gives 22). Host function, no device work. */
+int pts_window_bound(double h, double mu, double tau, double c, double eps, int wmax);
+
+/* Thread-local message describing the last error (never NULL). */
+const char* pts_last_error(void);
+
+/* Library version string. */
+const char* pts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTS_H */

@@ -1,0 +1,217 @@
+"""Space-time BDF1 Newton solver (ParaDIn direct-inverse method) on MI355X.
+
+Thin Python binding of libpts.so (include/pts.h). Every step of the method runs
+in the library's HIP kernels; this module only checks tensors, fills the C
+structures and passes device pointers plus the current HIP stream. PyTorch
+provides device memory and streams.
+
+Arrays: float64 CUDA (HIP) tensors, contiguous. U has shape (nt, ny, nx) and
+holds levels 1..nt, u0 has shape (ny, nx) (Section 3, Eq. (4) ordering, x fastest).
+A problem is any object with the attributes kind, bc, nx, ny, nt, hx, hy, dt,
+mu_a, mu_b (for instance workloads.Problem), plus an optional device tensor of
+Dirichlet data of shape (nt, 2 (nx + ny)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_FP64, PTS_HEAT, PTS_MIXED, PTS_PERIODIC,
+                   PTS_SCHED_AUTO, PTS_SCHED_BULK, PTS_SCHED_PIPELINE, pts_options, pts_problem,
+                   pts_stats)
+
+__all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve",
+           "solve_batched", "window_bound", "library_path", "version"]
+
+
+class PTSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pts error {code}: {msg}")
+        self.code = code
+
+
+def _lib_checked():
+    return _lib.load()
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def version() -> str:
+    return _lib_checked().pts_version().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PTSError(rc, _lib_checked().pts_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev_f64(t: torch.Tensor, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def make_problem(prob, precision: str = "fp64", bdata: Optional[torch.Tensor] = None) -> pts_problem:
+    """Fill a pts_problem from a problem description."""
+    p = pts_problem()
+    p.kind = int(prob.kind)
+    p.bc = int(prob.bc)
+    p.nx, p.ny, p.nt = int(prob.nx), int(prob.ny), int(prob.nt)
+    p.precision = PTS_MIXED if precision == "mixed" else PTS_FP64
+    p.hx, p.hy, p.dt = float(prob.hx), float(prob.hy), float(prob.dt)
+    p.mu_a, p.mu_b = float(prob.mu_a), float(prob.mu_b)
+    if bdata is not None:
+        _dev_f64(bdata, (p.nt, 2 * (p.nx + p.ny)), "bdata")
+        p.bdata = bdata.data_ptr()
+    else:
+        p.bdata = None
+    return p
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def workspace(prob, precision: str = "fp64", device="cuda") -> torch.Tensor:
+    """Allocate the device workspace pts_solve / pts_newton_step need for `prob`."""
+    p = make_problem(prob, precision)
+    nbytes = _lib_checked().pts_workspace_bytes(C.byref(p))
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_graph=True, stages=0,
+             profile=False):
+    o = pts_options()
+    o.window = int(window)
+    o.schedule = {"auto": PTS_SCHED_AUTO, "bulk": PTS_SCHED_BULK, "pipeline": PTS_SCHED_PIPELINE}[schedule]
+    o.sweeps = int(sweeps)
+    o.refine = int(refine)
+    o.lin_tol = float(lin_tol)
+    o.use_graph = 1 if use_graph else 0
+    o.stages = int(stages)
+    o.profile = 1 if profile else 0
+    return o
+
+
+def _stats_dict(st: pts_stats) -> dict:
+    k = st.iterations
+    n = min(k + 1, _lib.PTS_MAX_HIST)
+    return {
+        "iterations": k, "converged": bool(st.converged), "window": st.window, "sweeps": st.sweeps,
+        "refine": st.refine, "schedule": st.schedule, "launches": st.launches,
+        "res_inf": list(st.res_inf[:n]), "upd_rms": list(st.upd_rms[1:n]),
+        "rho_max": list(st.rho_max[:n]), "solve_ms": st.solve_ms,
+        "prof_ms": list(st.prof_ms), "prof_count": list(st.prof_count),
+        "level_solve_bytes": st.level_solve_bytes,
+    }
+
+
+def init_plain(prob, U, u0, stream=None):
+    """U <- u^0 at every level (plain Newton start), on the device."""
+    p = make_problem(prob)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    _check(_lib_checked().pts_init_plain(C.byref(p), _ptr(U), _ptr(u0), _stream(stream)))
+
+
+def assemble(prob, U, u0, bdata=None, coef: bool = False, stream=None):
+    """Residual r^n and (optionally) the five rows of A_n at every level.
+
+    Returns (R, coef or None, max|R| as a 0-d device tensor)."""
+    p = make_problem(prob, "fp64", bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    R = torch.empty_like(U)
+    cf = torch.empty((p.nt, 5, p.ny, p.nx), dtype=torch.float64, device=U.device) if coef else None
+    rinf = torch.empty((), dtype=torch.float64, device=U.device)
+    _check(_lib_checked().pts_assemble(C.byref(p), _ptr(U), _ptr(u0), _ptr(R), _ptr(cf), _ptr(rinf),
+                                       _stream(stream)))
+    return R, cf, rinf
+
+
+def newton_step(prob, U, u0, bdata=None, precision="fp64", ws=None, stream=None, **opts) -> dict:
+    """One all-at-once Newton step applied to U in place; returns the statistics."""
+    p = make_problem(prob, precision, bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = workspace(prob, precision, U.device) if ws is None else ws
+    o = _options(**opts)
+    st = pts_stats()
+    _check(_lib_checked().pts_newton_step(C.byref(p), _ptr(U), _ptr(u0), _ptr(ws), ws.numel(), C.byref(o),
+                                          C.byref(st), _stream(stream)))
+    return _stats_dict(st)
+
+
+def solve(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", ws=None, stream=None,
+          raise_on_error=True, **opts) -> dict:
+    """Newton iteration on U in place until max|R| <= tol; returns the statistics.
+
+    With raise_on_error=False the return code is reported in the dict instead."""
+    p = make_problem(prob, precision, bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = workspace(prob, precision, U.device) if ws is None else ws
+    o = _options(**opts)
+    st = pts_stats()
+    rc = _lib_checked().pts_solve(C.byref(p), _ptr(U), _ptr(u0), float(tol), int(max_iter), _ptr(ws),
+                                  ws.numel(), C.byref(o), C.byref(st), _stream(stream))
+    out = _stats_dict(st)
+    out["rc"] = rc
+    if rc != 0:
+        out["error"] = _lib_checked().pts_last_error().decode()
+        if raise_on_error:
+            _check(rc)
+    return out
+
+
+def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
+                  **opts):
+    """Solve independent instances together; returns one statistics dict per instance."""
+    n = len(probs)
+    bdatas = bdatas or [None] * n
+    arr = (pts_problem * n)(*[make_problem(q, precision, b) for q, b in zip(probs, bdatas)])
+    for q, U, u0 in zip(probs, Us, u0s):
+        _dev_f64(U, (q.nt, q.ny, q.nx), "U")
+        _dev_f64(u0, (q.ny, q.nx), "u0")
+    lib = _lib_checked()
+    nbytes = lib.pts_workspace_bytes_batched(arr, n)
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=Us[0].device)
+    off = (-raw.data_ptr()) % 256
+    ws = raw[off:off + nbytes]
+    uptr = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
+    u0ptr = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
+    o = _options(**opts)
+    sts = (pts_stats * n)()
+    rc = lib.pts_solve_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws), nbytes, C.byref(o),
+                               sts, _stream(stream))
+    _check(rc)
+    return [_stats_dict(s) for s in sts]
+
+
+def window_bound(h, mu, tau=0.0, c=1.0, eps=1e-16, wmax=100000) -> int:
+    """Section 7, Eq. (cond): largest window W with K^W < c h^4 / eps (host only)."""
+    r = _lib_checked().pts_window_bound(float(h), float(mu), float(tau), float(c), float(eps), int(wmax))
+    if r < 0:
+        _check(r)
+    return r

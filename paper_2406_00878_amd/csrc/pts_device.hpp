@@ -1,0 +1,171 @@
+// Device-side building blocks of the space-time BDF1 kernels (gfx950).
+//
+// Discretization (Section 2, Eq. (3)), tau-scaled as in Section 3, Eq. (5):
+//   G_P = u_P - u_P^{prev} + tau F_P,
+//   F_P = cflux[(u_E^2 - u_W^2)/(2hx) + (u_N^2 - u_S^2)/(2hy)]
+//         - [mu_e(u_E - u_P) - mu_w(u_P - u_W)]/hx^2 - [mu_n(u_N - u_P) - mu_s(u_P - u_S)]/hy^2
+// with face viscosity mu_e = mu((u_P + u_E)/2), mu(v) = mu_a + mu_b v^2.
+// Newton block A = I + tau dF/du (Eq. (6)); d mu_e / d u_P = d mu_e / d u_E = mu_b (u_P + u_E)/2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pts {
+
+constexpr int kWave = 64;
+
+// Problem scalars as the kernels see them (passed by value).
+struct KProb {
+  int nx, ny, nt, bc;  // bc: 0 Dirichlet, 1 periodic
+  double dt, mu_a, mu_b, cf;
+  double ihx, ihy, ihx2, ihy2;  // 1/hx, 1/hy, 1/hx^2, 1/hy^2
+  const double* bdata;          // [nt][2(nx+ny)] or nullptr
+};
+
+// Tiling of a level for the register-resident solve: a 64 x 64 region per work-group,
+// of which the central TX x TY tile is written.
+struct Geo {
+  int TX, TY;  // tile edge
+  int H;       // halo depth (neighbour exchanges one launch may perform)
+  int tilesx;  // tiles along x
+  int whole;   // 1: one region covers the whole Dirichlet domain (no halo needed)
+};
+
+struct Nb {
+  double P, W, E, S, N;
+};
+
+__device__ __forceinline__ double mu_of(const KProb& p, double v) { return p.mu_a + p.mu_b * v * v; }
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Value of level field `un` at (gx, gy) where (gx, gy) may be one node outside the
+// domain: periodic wrap, or the level's Dirichlet data (zero if none).
+__device__ __forceinline__ double node_value(const KProb& p, const double* __restrict__ un,
+                                             const double* __restrict__ bd, int gx, int gy) {
+  if (p.bc == 1) return un[(size_t)wrap(gy, p.ny) * p.nx + wrap(gx, p.nx)];
+  if (gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny) return un[(size_t)gy * p.nx + gx];
+  if (bd == nullptr) return 0.0;
+  if (gy < 0) return bd[gx];
+  if (gy >= p.ny) return bd[p.nx + gx];
+  if (gx < 0) return bd[2 * p.nx + gy];
+  return bd[2 * p.nx + p.ny + gy];
+}
+
+// Neighbours of the in-domain node (x, y). Periodic indices wrap by one step (no
+// integer division); Dirichlet neighbours outside the domain read the boundary data.
+__device__ __forceinline__ Nb gather(const KProb& p, const double* __restrict__ un,
+                                     const double* __restrict__ bd, int x, int y) {
+  Nb u;
+  const size_t row = (size_t)y * p.nx;
+  u.P = un[row + x];
+  if (p.bc == 1) {
+    const int xw = x == 0 ? p.nx - 1 : x - 1, xe = x == p.nx - 1 ? 0 : x + 1;
+    const int ys = y == 0 ? p.ny - 1 : y - 1, yn = y == p.ny - 1 ? 0 : y + 1;
+    u.W = un[row + xw];
+    u.E = un[row + xe];
+    u.S = un[(size_t)ys * p.nx + x];
+    u.N = un[(size_t)yn * p.nx + x];
+  } else {
+    u.W = node_value(p, un, bd, x - 1, y);
+    u.E = node_value(p, un, bd, x + 1, y);
+    u.S = node_value(p, un, bd, x, y - 1);
+    u.N = node_value(p, un, bd, x, y + 1);
+  }
+  return u;
+}
+
+// F_P of Eq. (3).
+__device__ __forceinline__ double spatial_op(const KProb& p, const Nb& u) {
+  const double me = mu_of(p, 0.5 * (u.P + u.E)), mw = mu_of(p, 0.5 * (u.P + u.W));
+  const double mn = mu_of(p, 0.5 * (u.P + u.N)), ms = mu_of(p, 0.5 * (u.P + u.S));
+  const double conv = p.cf * (0.5 * p.ihx * (u.E * u.E - u.W * u.W) + 0.5 * p.ihy * (u.N * u.N - u.S * u.S));
+  const double visc = p.ihx2 * (me * (u.E - u.P) - mw * (u.P - u.W)) + p.ihy2 * (mn * (u.N - u.P) - ms * (u.P - u.S));
+  return conv - visc;
+}
+
+// Row of A = I + tau dF/du at node (x, y): C (self), W, E, S, N. Dirichlet boundary
+// neighbours are data, so their entries are zero.
+struct Row5 {
+  double C, W, E, S, N;
+};
+
+__device__ __forceinline__ Row5 jac_row(const KProb& p, const Nb& u, int x, int y) {
+  const double me = mu_of(p, 0.5 * (u.P + u.E)), mw = mu_of(p, 0.5 * (u.P + u.W));
+  const double mn = mu_of(p, 0.5 * (u.P + u.N)), ms = mu_of(p, 0.5 * (u.P + u.S));
+  const double hb = 0.5 * p.mu_b;
+  const double P2 = u.P * u.P;
+  const double qe = hb * (u.E * u.E - P2), qw = hb * (P2 - u.W * u.W);
+  const double qn = hb * (u.N * u.N - P2), qs = hb * (P2 - u.S * u.S);
+  const double dE = -(me + qe) * p.ihx2 + p.cf * u.E * p.ihx;
+  const double dW = -(mw - qw) * p.ihx2 - p.cf * u.W * p.ihx;
+  const double dN = -(mn + qn) * p.ihy2 + p.cf * u.N * p.ihy;
+  const double dS = -(ms - qs) * p.ihy2 - p.cf * u.S * p.ihy;
+  const double dP = (me + mw - qe + qw) * p.ihx2 + (mn + ms - qn + qs) * p.ihy2;
+  Row5 r;
+  r.C = 1.0 + p.dt * dP;
+  r.W = p.dt * dW;
+  r.E = p.dt * dE;
+  r.S = p.dt * dS;
+  r.N = p.dt * dN;
+  if (p.bc == 0) {
+    if (x == 0) r.W = 0.0;
+    if (x == p.nx - 1) r.E = 0.0;
+    if (y == 0) r.S = 0.0;
+    if (y == p.ny - 1) r.N = 0.0;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- lane shifts
+// DPP wavefront shifts by one lane. shr: lane i receives lane i-1 (lane 0 gets 0);
+// shl: lane i receives lane i+1 (lane 63 gets 0).
+__device__ __forceinline__ int dpp_shr1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_shl1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+
+__device__ __forceinline__ float lane_from_left(float v) {
+  return __builtin_bit_cast(float, dpp_shr1_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float lane_from_right(float v) {
+  return __builtin_bit_cast(float, dpp_shl1_i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_from_left(double v) {
+  int2 q = __builtin_bit_cast(int2, v);
+  q.x = dpp_shr1_i(q.x);
+  q.y = dpp_shr1_i(q.y);
+  return __builtin_bit_cast(double, q);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+  int2 q = __builtin_bit_cast(int2, v);
+  q.x = dpp_shl1_i(q.x);
+  q.y = dpp_shl1_i(q.y);
+  return __builtin_bit_cast(double, q);
+}
+
+// ------------------------------------------------------------- reductions
+// max that propagates NaN (fmax would drop it)
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(a, b);
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Max of non-negative doubles (NaN propagates as the largest bit pattern).
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* slot, double v) {
+  unsigned long long b = __double_as_longlong(v);
+  if (v != v) b = 0x7ff8000000000000ull;
+  atomicMax(slot, b);
+}
+
+}  // namespace pts

@@ -1,0 +1,346 @@
+// HIP kernels of the space-time BDF1 Newton iteration for gfx950.
+//
+//  k_residual      all levels at once: r^n = -(u^n - u^{n-1} + tau F(u^n)) (Eq. (5)
+//                  right-hand side), the rows of A_n when requested, the per-level
+//                  Gershgorin radius of D^{-1} A_n (which fixes the inner Chebyshev
+//                  interval) and max |r|.
+//  k_level_solve   one level of the block inverse of Eq. (7): b = r^n + du^{n-1}
+//                  (the -I block of Eq. (6)), then A_n du^n = b by restarted
+//                  Jacobi-preconditioned Chebyshev passes. Each work-group owns a
+//                  tile and keeps a 64 x 64 region (tile + halo) in registers, so all
+//                  sweeps of a launch run without leaving the chip: x-neighbours move
+//                  between lanes by DPP, y-neighbours between waves through LDS. The
+//                  halo is as deep as the number of neighbour exchanges of the launch,
+//                  which makes the tile values identical to a global sweep.
+//  k_update        U += dU at every level and per-block sums of dU^2 (the RMS update
+//                  norm of Section 8.1), reduced in fixed order by k_reduce_sum.
+#include "pts_device.hpp"
+
+namespace pts {
+
+// ------------------------------------------------------------------ residual
+// Block of 64 x 4 threads sweeping kResRows rows of one level; grid.x = tiles of the
+// level, grid.y = level. Per-level maxima of |r| and of the Gershgorin radius go to
+// lvl_bits[2n] and lvl_bits[2n+1] (zeroed before the launch); k_level_max folds them.
+constexpr int kResRows = 16;
+
+__global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restrict__ U,
+                                                  const double* __restrict__ u0,
+                                                  double* __restrict__ R, double* __restrict__ coef,
+                                                  unsigned long long* __restrict__ lvl_bits) {
+  const int n = blockIdx.y;
+  const int tilesx = (p.nx + 63) >> 6;
+  const int x = (blockIdx.x % tilesx) * 64 + (threadIdx.x & 63);
+  const int y0 = (blockIdx.x / tilesx) * kResRows + (threadIdx.x >> 6);
+  const size_t ns = (size_t)p.nx * p.ny;
+  const double* un = U + (size_t)n * ns;
+  const double* up = n == 0 ? u0 : U + (size_t)(n - 1) * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+  double rabs = 0.0, rho = 0.0;
+  for (int y = y0; y < y0 + kResRows; y += 4) {
+    if (x < p.nx && y < p.ny) {
+      const Nb u = gather(p, un, bd, x, y);
+      const size_t i = (size_t)y * p.nx + x;
+      const double r = -(u.P - up[i] + p.dt * spatial_op(p, u));
+      R[(size_t)n * ns + i] = r;
+      rabs = nanmax(rabs, fabs(r));
+      const Row5 a = jac_row(p, u, x, y);
+      double g = (fabs(a.W) + fabs(a.E) + fabs(a.S) + fabs(a.N)) / fabs(a.C);
+      if (!(a.C > 0.0) || g != g) g = __longlong_as_double(0x7ff0000000000000ll);
+      rho = nanmax(rho, g);
+      if (coef) {
+        double* c = coef + (size_t)n * 5 * ns + i;
+        c[0] = a.C;
+        c[ns] = a.W;
+        c[2 * ns] = a.E;
+        c[3 * ns] = a.S;
+        c[4 * ns] = a.N;
+      }
+    }
+  }
+  __shared__ double red[2][4];
+  rabs = wave_max(rabs);
+  rho = wave_max(rho);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = rabs;
+    red[1][w] = rho;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && lvl_bits) {
+    atomic_max_nonneg(lvl_bits + 2 * n, nanmax(nanmax(red[0][0], red[0][1]), nanmax(red[0][2], red[0][3])));
+    atomic_max_nonneg(lvl_bits + 2 * n + 1, nanmax(nanmax(red[1][0], red[1][1]), nanmax(red[1][2], red[1][3])));
+  }
+}
+
+// out[0] = max_n lvl[2n] (max |r|), out[1] = max_n lvl[2n+1] (max radius); one block.
+__global__ __launch_bounds__(256) void k_level_max(const unsigned long long* __restrict__ lvl, int nt,
+                                                   unsigned long long* __restrict__ out) {
+  unsigned long long a = 0, b = 0;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+    a = lvl[2 * i] > a ? lvl[2 * i] : a;
+    b = lvl[2 * i + 1] > b ? lvl[2 * i + 1] : b;
+  }
+  __shared__ unsigned long long ra[256], rb[256];
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      ra[threadIdx.x] = ra[threadIdx.x + o] > ra[threadIdx.x] ? ra[threadIdx.x + o] : ra[threadIdx.x];
+      rb[threadIdx.x] = rb[threadIdx.x + o] > rb[threadIdx.x] ? rb[threadIdx.x + o] : rb[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = ra[0];
+    out[1] = rb[0];
+  }
+}
+
+// -------------------------------------------------------------- level solve
+// Geometry of the register-resident region: 64 lanes (x) by 8 waves x kRows (y).
+constexpr int kRows = 8;
+constexpr int kWaves = 8;
+constexpr int kRegion = 64;  // region edge in both directions
+
+// Exchange of one register row set between neighbouring waves via LDS.
+// buf holds 2 parities x kWaves x {bottom row, top row} x 64 lanes.
+template <typename T>
+struct YNb {
+  T s0, nM;  // south neighbour of row 0, north neighbour of row kRows-1
+};
+
+template <typename T>
+__device__ __forceinline__ YNb<T> y_exchange(const T (&v)[kRows], T* buf, int& par, int wave, int lane) {
+  T* b = buf + par * (kWaves * 2 * 64);
+  b[(wave * 2 + 0) * 64 + lane] = v[0];
+  b[(wave * 2 + 1) * 64 + lane] = v[kRows - 1];
+  __syncthreads();
+  YNb<T> r;
+  r.s0 = wave > 0 ? b[((wave - 1) * 2 + 1) * 64 + lane] : T(0);
+  r.nM = wave < kWaves - 1 ? b[((wave + 1) * 2 + 0) * 64 + lane] : T(0);
+  par ^= 1;
+  return r;
+}
+
+// Chebyshev weights for the Jacobi iteration matrix with spectral radius bound rho:
+// omega_1 = 1, omega_2 = 1/(1 - rho^2/2), omega_{k+1} = 1/(1 - rho^2 omega_k / 4).
+__device__ __forceinline__ double cheb_next(double omega, double rho2, int k) {
+  if (k == 1) return 1.0;
+  if (k == 2) return 1.0 / (1.0 - 0.5 * rho2);
+  return 1.0 / (1.0 - 0.25 * rho2 * omega);
+}
+
+// One launch: `passes` restarted Chebyshev passes of `sweeps` sweeps each, inner
+// arithmetic in T, FP64 residual and accumulation. Xin (nullable) is the starting
+// iterate of the level (a previous launch), Xout receives the tile values.
+template <typename T>
+__global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const double* __restrict__ U,
+                                                     const double* __restrict__ R,
+                                                     const double* __restrict__ dUprev,
+                                                     const double* __restrict__ Xin,
+                                                     double* __restrict__ Xout,
+                                                     const double* __restrict__ rho_lvl, Geo g,
+                                                     int passes, int sweeps) {
+  __shared__ double lds_raw[2 * kWaves * 2 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tx = blockIdx.x % g.tilesx, ty = blockIdx.x / g.tilesx;
+  const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
+  const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
+  const size_t ns = (size_t)p.nx * p.ny;
+  const double* un = U + (size_t)n * ns;
+  const double* rn = R + (size_t)n * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+
+  // FP64 rows are kept only when the inner arithmetic is FP32 (they form the FP64
+  // refinement residual); the FP64 inner path works with the Jacobi-scaled rows alone.
+  constexpr bool kF64 = sizeof(T) == sizeof(double);
+  double cC[kRows], cW[kRows], cE[kRows], cS[kRows], cN[kRows], bb[kRows], X[kRows];
+  T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
+  int idx[kRows];
+  const int gx = rx0 + lane;
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int gy = ry0 + wave * kRows + k;
+    int x = gx, y = gy;
+    bool act;
+    if (p.bc == 1) {
+      x = wrap(gx, p.nx);
+      y = wrap(gy, p.ny);
+      act = true;
+    } else {
+      act = gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
+    }
+    idx[k] = act ? y * p.nx + x : -1;
+    Row5 a;
+    if (act) {
+      const Nb u = gather(p, un, bd, x, y);
+      a = jac_row(p, u, x, y);
+      bb[k] = rn[idx[k]] + (dUprev ? dUprev[idx[k]] : 0.0);
+      X[k] = Xin ? Xin[idx[k]] : 0.0;
+    } else {
+      a.C = 1.0;
+      a.W = a.E = a.S = a.N = 0.0;
+      bb[k] = 0.0;
+      X[k] = 0.0;
+    }
+    const double inv = 1.0 / a.C;
+    iC[k] = T(inv);
+    sW[k] = T(a.W * inv);
+    sE[k] = T(a.E * inv);
+    sS[k] = T(a.S * inv);
+    sN[k] = T(a.N * inv);
+    if (!kF64) {
+      cC[k] = a.C;
+      cW[k] = a.W;
+      cE[k] = a.E;
+      cS[k] = a.S;
+      cN[k] = a.N;
+    }
+  }
+  double rho = rho_lvl[2 * n + 1];
+  rho = fmin(fmax(rho, 1e-3), 0.999);
+  const double rho2 = rho * rho;
+
+  int par = 0;
+  double* ldsd = lds_raw;
+  T* ldst = reinterpret_cast<T*>(lds_raw);
+  bool haveX = Xin != nullptr;
+  for (int pass = 0; pass < passes; ++pass) {
+    // FP64 residual of the current iterate: d = b - A X
+    T d[kRows];
+    if (haveX) {
+      const YNb<double> yn = y_exchange<double>(X, ldsd, par, wave, lane);
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const double xs = k == 0 ? yn.s0 : X[k - 1];
+        const double xn = k == kRows - 1 ? yn.nM : X[k + 1];
+        const double xw = lane_from_left(X[k]);
+        const double xe = lane_from_right(X[k]);
+        if (kF64) {
+          // (b - A X) / C with the Jacobi-scaled row
+          d[k] = T(double(iC[k]) * bb[k] -
+                   (X[k] + double(sW[k]) * xw + double(sE[k]) * xe + double(sS[k]) * xs + double(sN[k]) * xn));
+        } else {
+          const double ax = cC[k] * X[k] + cW[k] * xw + cE[k] * xe + cS[k] * xs + cN[k] * xn;
+          d[k] = T((bb[k] - ax) / cC[k]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) d[k] = T(bb[k]) * iC[k];
+    }
+    // Chebyshev on D^{-1} A x = D^{-1} d from x = 0; first sweep x_1 = D^{-1} d
+    T xc[kRows], xm[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      xc[k] = d[k];
+      xm[k] = T(0);
+    }
+    double omega = 1.0;
+    for (int s = 2; s <= sweeps; ++s) {
+      omega = cheb_next(omega, rho2, s);
+      const T om = T(omega);
+      const YNb<T> yn = y_exchange<T>(xc, ldst, par, wave, lane);
+      T xnw[kRows];
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const T xs = k == 0 ? yn.s0 : xc[k - 1];
+        const T xn = k == kRows - 1 ? yn.nM : xc[k + 1];
+        const T xw = lane_from_left(xc[k]);
+        const T xe = lane_from_right(xc[k]);
+        // z = D^{-1}(d - A x) with unit diagonal after scaling
+        const T z = d[k] - (xc[k] + sW[k] * xw + sE[k] * xe + sS[k] * xs + sN[k] * xn);
+        xnw[k] = xm[k] + om * (xc[k] - xm[k] + z);
+      }
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        xm[k] = xc[k];
+        xc[k] = xnw[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) X[k] += double(xc[k]);
+    haveX = true;
+  }
+
+  // write the tile
+  const int lx = g.whole ? lane : lane - g.H;
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int ly = g.whole ? wave * kRows + k : wave * kRows + k - g.H;
+    const int gy = ry0 + wave * kRows + k;
+    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx < p.nx && gy < p.ny && gx >= 0 &&
+                        gy >= 0 && idx[k] >= 0;
+    if (inside) Xout[idx[k]] = X[k];
+  }
+}
+
+template __global__ void k_level_solve<double>(KProb, int, const double*, const double*, const double*,
+                                               const double*, double*, const double*, Geo, int, int);
+template __global__ void k_level_solve<float>(KProb, int, const double*, const double*, const double*,
+                                              const double*, double*, const double*, Geo, int, int);
+
+// ------------------------------------------------------------------- update
+__global__ __launch_bounds__(256) void k_update(size_t count, double* __restrict__ U,
+                                                const double* __restrict__ dU, double* __restrict__ partial) {
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const double d = dU[i];
+    U[i] += d;
+    acc += d * d;
+  }
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Fixed-order sum of `count` partials into out[0] (one block).
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ partial, int count,
+                                                    double* __restrict__ out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+  __shared__ double red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out = max |a[i]| over count values (one block, fixed order; NaN propagates).
+__global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ a, size_t count,
+                                                unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  for (size_t i = threadIdx.x; i < count; i += blockDim.x) {
+    const double v = a[i];
+    m = nanmax(m, fabs(v));
+  }
+  m = wave_max(m);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double r = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+    out[0] = __double_as_longlong(r);
+  }
+}
+
+// u^n = u^0 at every level (the plain Newton start).
+__global__ __launch_bounds__(256) void k_broadcast(size_t ns, int nt, double* __restrict__ U,
+                                                   const double* __restrict__ u0) {
+  const size_t total = ns * (size_t)nt;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+    U[i] = u0[i % ns];
+}
+
+// Fill a small array of 64-bit words with zero (used instead of a memset node so that
+// the sequence can be captured in a HIP graph).
+__global__ void k_zero(unsigned long long* __restrict__ a, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) a[i] = 0ull;
+}
+
+}  // namespace pts

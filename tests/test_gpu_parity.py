@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: FP64 path 1e-10 relative max error, mixed path 1e-8, both measured as
+max |U - U_oracle| / max |U_oracle| over all levels and nodes.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2406_00878_amd as P
+import workloads as W
+from oracle import allatonce, sequential
+from oracle.discretization import jacobian_stencil, level_bvals
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_solve(p, tol=1e-12, precision="fp64", U0=None, **opts):
+    U = dev(p.plain_iterate() if U0 is None else U0)
+    u0 = dev(p.u0)
+    bd = dev(p.bdata) if p.bdata is not None else None
+    print(f"[gpu_solve] {p.name} {p.nx}x{p.ny}x{p.nt} bc={p.bc} {precision}", flush=True)
+    st = P.solve(p, U, u0, tol=tol, max_iter=60, bdata=bd, precision=precision, **opts)
+    return host(U), st
+
+
+def _rand_problem(case, rng):
+    if case == "heat_dirichlet_bdata":
+        p = W.heat_dirichlet(37, 3, 2e-4, rng.uniform(0, 1, (37, 37)))
+        p.ny = 23
+        p.u0 = rng.uniform(0, 1, (23, 37))
+        p.hy = 1.0 / 24
+        p.bdata = rng.uniform(-1, 1, (3, 2 * (37 + 23)))
+        return p
+    if case == "burgers_periodic_ragged":
+        p = W.burgers_periodic(70, 2, 5e-4, 0.01, rng.uniform(-1, 1, (70, 70)))
+        p.ny, p.hy, p.u0 = 45, 1.0 / 45, rng.uniform(-1, 1, (45, 70))
+        return p
+    if case == "burgers_dirichlet_tiled":
+        p = W.Problem(W.BURGERS, W.DIRICHLET, 100, 67, 2, 0.01, 0.012, 1e-3, 0.02, 0.0,
+                      rng.uniform(-1, 1, (67, 100)), rng.uniform(-1, 1, (2, 2 * 167)))
+        return p
+    if case == "heat_paper_mms":
+        return W.heat_mms(12)
+    if case == "single_node":
+        return W.Problem(W.HEAT, W.DIRICHLET, 1, 1, 2, 0.5, 0.5, 0.05, 0.2, 1.3, np.array([[0.9]]),
+                         rng.uniform(0, 1, (2, 4)))
+    if case == "periodic_3x3":
+        return W.Problem(W.BURGERS, W.PERIODIC, 3, 3, 2, 1 / 3, 1 / 3, 1e-2, 0.05, 0.0,
+                         rng.uniform(-1, 1, (3, 3)))
+    raise KeyError(case)
+
+
+CASES = ["heat_dirichlet_bdata", "burgers_periodic_ragged", "burgers_dirichlet_tiled", "heat_paper_mms",
+         "single_node", "periodic_3x3"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_assemble_matches_oracle(case):
+    rng = np.random.default_rng(CASES.index(case))
+    p = _rand_problem(case, rng)
+    U = p.plain_iterate() + 0.1 * rng.standard_normal((p.nt, p.ny, p.nx))
+    bd = dev(p.bdata) if p.bdata is not None else None
+    R, cf, rinf = P.assemble(p, dev(U), dev(p.u0), bdata=bd, coef=True)
+    R, cf, rinf = host(R), host(cf), float(host(rinf))
+    Ro = allatonce.global_residual(U, p)
+    scale = max(1.0, np.max(np.abs(Ro)))
+    np.testing.assert_allclose(R, Ro, rtol=0, atol=1e-13 * scale)
+    assert rinf == pytest.approx(np.max(np.abs(Ro)), rel=1e-12)
+    for n in range(p.nt):
+        co = jacobian_stencil(U[n], p, level_bvals(p, n + 1))
+        cscale = max(1.0, max(np.max(np.abs(c)) for c in co))
+        for k in range(5):
+            np.testing.assert_allclose(cf[n, k], co[k], rtol=0, atol=1e-13 * cscale)
+
+
+@pytest.mark.parametrize("case", ["heat_dirichlet_bdata", "burgers_periodic_ragged", "burgers_dirichlet_tiled",
+                                  "heat_paper_mms"])
+def test_newton_step_matches_sparse_direct_step(case):
+    """One Newton step of Eq. (6) equals the sparse-LU step of the whole space-time matrix."""
+    rng = np.random.default_rng(7)
+    p = _rand_problem(case, rng)
+    p.nt = 5
+    if p.bdata is not None:
+        p.bdata = p.bdata[:5] if p.bdata.shape[0] >= 5 else rng.uniform(-1, 1, (5, p.bdata.shape[1]))
+    U = p.plain_iterate() + 0.01 * rng.standard_normal((p.nt, p.ny, p.nx))
+    dU, _ = allatonce.newton_step_direct(U, p)
+    Ud = dev(U)
+    bd = dev(p.bdata) if p.bdata is not None else None
+    st = P.newton_step(p, Ud, dev(p.u0), bdata=bd, lin_tol=1e-14)
+    assert st["iterations"] == 1
+    got = host(Ud) - U
+    assert np.max(np.abs(got - dU)) <= 1e-10 * np.max(np.abs(dU))
+
+
+def test_solve_heat32_matches_oracle():
+    """Nonlinear heat k(u) = 1 + u^2, 32x32, 64 levels, dt = 1e-3 (the small workload)."""
+    p = W.heat32()
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12)
+    assert st["converged"] and st["iterations"] <= 10
+    assert relerr(U, Us) <= 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_solve_burgers_periodic_ragged_tiles(precision, tol):
+    """Periodic Burgers on a grid that is not a multiple of the tile (several tiles + ragged tail)."""
+    n1, n2 = 80, 72
+    p = W.burgers_periodic(n1, 40, 5e-4, 0.01, W.fourier_u0_periodic(n1, 2406002)[:n2, :])
+    p.ny, p.hy = n2, 1.0 / n2
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12, precision=precision)
+    assert st["converged"]
+    assert relerr(U, Us) <= tol
+
+
+def test_solve_paper_heat_mms_with_boundary_data():
+    p = W.heat_mms(24)
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-11)
+    assert st["converged"]
+    assert relerr(U, Us) <= 1e-10
+
+
+def test_solve_dirichlet_tiled_ragged():
+    rng = np.random.default_rng(4)
+    n = 90
+    p = W.heat_dirichlet(n, 12, 1e-3, W.sine_u0_dirichlet(n, rng))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12)
+    assert relerr(U, Us) <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["single_node", "periodic_3x3"])
+def test_solve_degenerate_grids(case):
+    p = _rand_problem(case, np.random.default_rng(1))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-13)
+    assert relerr(U, Us) <= 1e-10
+
+
+def test_single_level():
+    p = W.burgers_periodic(64, 1, 5e-4, 0.01, W.fourier_u0_periodic(64, 3))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p)
+    assert relerr(U, Us) <= 1e-10
+
+
+def test_full_size_burgers256_sampled():
+    """Full-size periodic Burgers 256^2 x 512 levels in the benchmark's configuration:
+    the first levels against the sequential oracle, and the oracle's residual of the
+    GPU result at sampled levels."""
+    p = W.burgers256()
+    U, st = gpu_solve(p, tol=1e-12)
+    assert st["converged"]
+    L = 4
+    Us, _ = sequential.solve_sequential(p, levels=L)
+    assert relerr(U[:L], Us) <= 1e-10
+    from oracle.discretization import level_residual
+    for n in (1, 2, 100, 255, 256, 511, 512):
+        prev = p.u0 if n == 1 else U[n - 2]
+        assert np.max(np.abs(level_residual(U[n - 1], prev, p))) <= 1e-11
+
+
+def test_nonfinite_input_is_reported():
+    p = W.heat32(nt=4)
+    u0 = p.u0.copy()
+    u0[3, 5] = np.nan
+    U = dev(p.plain_iterate())
+    with pytest.raises(P.PTSError) as e:
+        P.solve(p, U, dev(u0))
+    assert e.value.code == P._lib.PTS_ERR_NONFINITE
+
+
+def test_small_workspace_is_rejected():
+    p = W.heat32(nt=4)
+    ws = P.workspace(p)[:100]
+    with pytest.raises(P.PTSError) as e:
+        P.solve(p, dev(p.plain_iterate()), dev(p.u0), ws=ws)
+    assert e.value.code == P._lib.PTS_ERR_WORKSPACE
+
+
+def test_not_converged_leaves_last_iterate_and_resumes():
+    p = W.heat32(nt=16)
+    Ua = dev(p.plain_iterate())
+    st = P.solve(p, Ua, dev(p.u0), tol=1e-12, max_iter=2, raise_on_error=False)
+    assert st["rc"] == P._lib.PTS_ERR_NOT_CONVERGED and st["iterations"] == 2
+    Ub = dev(p.plain_iterate())
+    P.newton_step(p, Ub, dev(p.u0))
+    P.newton_step(p, Ub, dev(p.u0))
+    assert relerr(host(Ua), host(Ub)) <= 1e-12
+    st2 = P.solve(p, Ua, dev(p.u0), tol=1e-12)
+    Us, _ = sequential.solve_sequential(p)
+    assert st2["converged"] and relerr(host(Ua), Us) <= 1e-10
+
+
+def test_repeat_runs_are_bitwise_identical():
+    p = W.burgers_periodic(96, 16, 5e-4, 0.01, W.fourier_u0_periodic(96, 9))
+    U1, _ = gpu_solve(p)
+    U2, _ = gpu_solve(p)
+    assert np.array_equal(U1, U2)
+
+
+def test_quadratic_convergence_history():
+    """Section 4: the all-at-once Newton on the GPU keeps the quadratic rate (smooth heat)."""
+    p = W.heat32()
+    _, st = gpu_solve(p, tol=1e-14, lin_tol=1e-13)
+    r = st["res_inf"]
+    ratios = [r[k + 1] / r[k] ** 2 for k in range(len(r) - 1) if r[k + 1] > 1e-12]
+    assert len(ratios) >= 2 and max(ratios[1:]) < 100.0
