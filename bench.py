@@ -116,14 +116,16 @@ def main():
     # dominant kernel (per-level solve): average launch duration from HIP events recorded
     # on the launch stream during one extra, profiled solve
     P.init_plain(prob, U, u0)
+    sched = {1: "bulk", 2: "pipeline"}.get(st["schedule"], "auto")
     pst = P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, profile=True,
-                  schedule="bulk")
+                  schedule=sched)
     torch.cuda.synchronize()
     n_ls = max(pst["prof_count"][1], 1)
     avg_ms = pst["prof_ms"][1] / n_ls
     bytes_per_launch = pst["level_solve_bytes"] / n_ls
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    print(f"[bench] k_level_solve: {n_ls} launches, avg {avg_ms * 1e3:.2f} us, "
+    kname = "k_level_wave" if st["schedule"] == 2 else "k_level_solve"
+    print(f"[bench] {kname}: {n_ls} launches, avg {avg_ms * 1e3:.2f} us, "
           f"{bytes_per_launch / 1e6:.2f} MB/launch; kernel split ms {pst['prof_ms']}",
           file=sys.stderr, flush=True)
 
@@ -143,7 +145,7 @@ def main():
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "nt": prob.nt, "dt": prob.dt,
                    "precision": args.precision, "tol": args.tol, "newton_steps": st["iterations"],
                    "inner_sweeps": st["sweeps"], "schedule": st["schedule"], **extra},
-        "roofline": {"bound": "hbm", "kernel": "k_level_solve", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},
     }

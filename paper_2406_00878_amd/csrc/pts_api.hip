@@ -83,8 +83,10 @@ KProb kprob(const pts_problem* p) {
 }
 
 // Workspace layout of one instance.
+constexpr int kMaxStages = 16;  // Newton iterations overlapped by one wavefront sequence
+
 struct Layout {
-  size_t R, dU, Xs, rho, scal, partial, rms, total;
+  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, total;
 };
 
 Layout layout(const pts_problem* p) {
@@ -105,6 +107,14 @@ Layout layout(const pts_problem* p) {
   o = align_up(o + kUpdateBlocks * 8);
   L.rms = o;
   o = align_up(o + 8);
+  L.U1 = o;  // second iterate slot of the wavefront schedule
+  o = align_up(o + st * 8);
+  L.dU2 = o;  // second update slot of the wavefront schedule
+  o = align_up(o + st * 8);
+  L.rho_st = o;
+  o = align_up(o + (size_t)(kMaxStages + 1) * p->nt * 8);
+  L.res_st = o;
+  o = align_up(o + (kMaxStages + 1) * 8);
   L.total = o;
   return L;
 }
@@ -162,6 +172,8 @@ Plan make_plan(const pts_problem* p, const pts_options* o, double rho_max, const
   // One pass from zero needs s - 1 neighbour exchanges, a pass from an iterate s; the
   // halo bounds the exchanges of one launch.
   const bool fp32_fixed = pl.fp32 && o && o->refine > 0;
+  // a pass runs at most kMaxSweeps - 1 sweeps (size of the kernel's weight table)
+  s = std::min(s, kMaxSweeps - 1);
   bool one_pass = !fp32_fixed && (g.whole || s - 1 <= g.H) && cheb_reduction(s, rho) <= lin_tol;
   if (!g.whole && !one_pass) s = std::min(s, g.H);
   if (!g.whole && one_pass) s = std::min(s, g.H + 1);
@@ -245,7 +257,8 @@ int launch_chain(const pts_problem* p, const KProb& kp, const double* U, const d
 }
 
 struct HostScalars {
-  double* h = nullptr;  // pinned: [0] max|r|, [1] rho_max, [2] sum dU^2
+  double* h = nullptr;  // pinned, 512 doubles: [0] max|r|, [1] rho_max, [2] sum dU^2, or the
+                        // per-stage residuals of a wavefront sequence
   ~HostScalars() {
     if (h) (void)hipHostFree(h);
   }
@@ -253,7 +266,7 @@ struct HostScalars {
 thread_local HostScalars g_host;
 
 int host_scalars(double** out) {
-  if (!g_host.h) HIPCHK(hipHostMalloc((void**)&g_host.h, 64, hipHostMallocDefault));
+  if (!g_host.h) HIPCHK(hipHostMalloc((void**)&g_host.h, 4096, hipHostMallocDefault));
   *out = g_host.h;
   return PTS_OK;
 }
@@ -373,8 +386,9 @@ int check_opts(const pts_options* o) {
   if (o->window > 1) return fail(PTS_ERR_INVALID_ARG, "window %d: only window 1 is available", o->window);
   if (o->window < 0 || o->sweeps < 0 || o->lin_tol < 0)
     return fail(PTS_ERR_INVALID_ARG, "negative option");
-  if (o->schedule != PTS_SCHED_AUTO && o->schedule != PTS_SCHED_BULK)
+  if (o->schedule != PTS_SCHED_AUTO && o->schedule != PTS_SCHED_BULK && o->schedule != PTS_SCHED_PIPELINE)
     return fail(PTS_ERR_INVALID_ARG, "schedule %d not available", o->schedule);
+  if (o->stages < 0 || o->stages > kMaxStages) return fail(PTS_ERR_INVALID_ARG, "stages %d", o->stages);
   return PTS_OK;
 }
 
@@ -498,6 +512,289 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
   }
 }
 
+
+// ------------------------------------------------------------ wavefront schedule
+// Inner-solve plan for the wavefront kernel: every pass of a level runs in the one launch
+// and the tile must stay valid one node beyond its edge, so the neighbour exchanges are
+// bounded by H - 1. Returns false when no plan reaches a useful reduction (< 1e-3).
+bool make_wave_plan(const pts_problem* p, const pts_options* o, double rho_max, const Geo& g, Plan* out) {
+  Plan pl;
+  pl.fp32 = p->precision == PTS_MIXED;
+  const double rho = std::min(std::max(rho_max, 1e-3), 0.999);
+  const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : (pl.fp32 ? 1e-6 : 1e-9);
+  const int emax = g.whole ? (1 << 20) : g.H - 1;
+  const double floor_red = pl.fp32 ? 1e-6 : 1e-15;
+  if (!pl.fp32 || !(o && o->refine > 0)) {
+    // one pass if it reaches lin_tol within the exchange budget
+    int s = 1;
+    if (o && o->sweeps > 0)
+      s = o->sweeps;
+    else
+      while (s < 4096 && cheb_reduction(s, rho) > std::max(lin_tol, floor_red)) ++s;
+    if (s - 1 <= emax && (s < kMaxSweeps) && (cheb_reduction(s, rho) <= lin_tol || !pl.fp32)) {
+      if (s - 1 > emax) s = emax + 1;
+      pl.sweeps = s;
+      pl.passes = 1;
+      pl.packs = {1};
+      *out = pl;
+      return cheb_reduction(s, rho) <= 1e-3;
+    }
+  }
+  // several passes of s sweeps: (s - 1) + (P - 1) s exchanges
+  int best_s = 0, best_p = 0;
+  double best_red = 1.0;
+  for (int s = 2; s < kMaxSweeps; ++s) {
+    const double red1 = std::max(cheb_reduction(s, rho), floor_red);
+    for (int P = 1; P <= 8; ++P) {
+      const int ex = (s - 1) + (P - 1) * s;
+      if (ex > emax) break;
+      if (o && o->refine > 0 && P != 1 + o->refine) continue;
+      if (o && o->sweeps > 0 && s != o->sweeps) continue;
+      const double red = std::pow(red1, P);
+      const double work = (double)s * P;
+      const bool ok = red <= lin_tol;
+      const bool best_ok = best_red <= lin_tol;
+      if (best_p == 0 || (ok && !best_ok) || (ok && best_ok && work < (double)best_s * best_p) ||
+          (!ok && !best_ok && red < best_red)) {
+        best_s = s;
+        best_p = P;
+        best_red = red;
+      }
+    }
+  }
+  if (best_p == 0) return false;
+  pl.sweeps = best_s;
+  pl.passes = best_p;
+  pl.packs = {best_p};
+  *out = pl;
+  return best_red <= 1e-3;
+}
+
+// Newton steps needed last time for a problem signature (autotuned stage count).
+struct StageCache {
+  struct E {
+    int nx, ny, nt, kind, bc, prec;
+    double dt, mu_a, mu_b, tol;
+    int steps;
+  };
+  std::vector<E> v;
+  int* find(const pts_problem* p, double tol) {
+    for (auto& e : v)
+      if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
+          e.prec == p->precision && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b && e.tol == tol)
+        return &e.steps;
+    return nullptr;
+  }
+  void put(const pts_problem* p, double tol, int steps) {
+    if (int* s = find(p, tol)) {
+      *s = steps;
+      return;
+    }
+    if (v.size() > 64) v.clear();
+    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, p->dt, p->mu_a, p->mu_b, tol, steps});
+  }
+};
+thread_local StageCache g_stage_cache;
+
+// Executable graph of one wavefront sequence, reused while the launch arguments match.
+struct WaveGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<char> key;
+};
+thread_local std::vector<WaveGraph> g_wave_graphs;
+
+int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
+                         hipStream_t s, Prof* pr, int* launches) {
+  const int tl = tiles(p, g);
+  const int ndiag = p->nt + 2 * (wa.stages - 1);
+  for (int d = 0; d < ndiag; ++d) {
+    prof_begin(pr, 1, s);
+    if (pl.fp32)
+      hipLaunchKernelGGL(k_level_wave<float>, dim3(wa.stages * tl), dim3(512), 0, s, kp, wa, g, d, pl.passes,
+                         pl.sweeps);
+    else
+      hipLaunchKernelGGL(k_level_wave<double>, dim3(wa.stages * tl), dim3(512), 0, s, kp, wa, g, d, pl.passes,
+                         pl.sweeps);
+    if (pr) {
+      const int active = std::min(wa.stages, d / 2 + 1) - std::max(0, (d - p->nt + 2) / 2);
+      pr->end(s);
+      // per active (stage, level): reads U_j^n, U_j^{n-1}, du_j^{n-1}; writes du_j^n, U_{j+1}^n
+      pr->bytes += 8.0 * 5.0 * (double)p->nx * p->ny * std::max(active, 0);
+    }
+    ++*launches;
+  }
+  HIPCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
+                      hipStream_t s, bool use_graph, Prof* pr, int* launches) {
+  if (!use_graph || pr) return launch_wave_sequence(p, kp, wa, g, pl, s, pr, launches);
+  std::vector<char> key(sizeof(KProb) + sizeof(WaveArgs) + sizeof(Geo) + 3 * sizeof(int));
+  char* k = key.data();
+  std::memcpy(k, &kp, sizeof kp);
+  k += sizeof kp;
+  std::memcpy(k, &wa, sizeof wa);
+  k += sizeof wa;
+  std::memcpy(k, &g, sizeof g);
+  k += sizeof g;
+  const int extra[3] = {pl.passes, pl.sweeps, pl.fp32 ? 1 : 0};
+  std::memcpy(k, extra, sizeof extra);
+  for (auto& wg : g_wave_graphs) {
+    if (wg.key == key) {
+      HIPCHK(hipGraphLaunch(wg.exec, s));
+      ++*launches;
+      return PTS_OK;
+    }
+  }
+  static thread_local hipStream_t cap = nullptr;
+  if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int dummy = 0;
+  int rc = launch_wave_sequence(p, kp, wa, g, pl, cap, nullptr, &dummy);
+  hipError_t e = hipStreamEndCapture(cap, &graph);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(PTS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  WaveGraph wg;
+  e = hipGraphInstantiate(&wg.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(PTS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  wg.key = key;
+  if (g_wave_graphs.size() >= 8) {
+    for (auto& old : g_wave_graphs) (void)hipGraphExecDestroy(old.exec);
+    g_wave_graphs.clear();
+  }
+  g_wave_graphs.push_back(wg);
+  HIPCHK(hipGraphLaunch(wg.exec, s));
+  ++*launches;
+  return PTS_OK;
+}
+
+// Newton iterations overlapped in wavefront sequences of K stages each. Returns
+// PTS_ERR_INVALID_ARG with *fallback = true when the inner solve does not fit the
+// wavefront kernel (the caller then uses the bulk schedule).
+int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
+               const pts_options* o, pts_stats* st, hipStream_t s, bool* fallback) {
+  *fallback = false;
+  Instance in;
+  in.bind(p, ws);
+  Prof prof;
+  const bool profiling = o && o->profile;
+  if (profiling) in.prof = &prof;
+  const bool use_graph = !profiling && (!o || o->use_graph != 0);
+  double* hs;
+  int rc = host_scalars(&hs);
+  if (rc) return rc;
+  char* wsb = (char*)ws;
+  double* U1 = (double*)(wsb + in.L.U1);
+  double* dU2 = (double*)(wsb + in.L.dU2);
+  unsigned long long* rho_st = (unsigned long long*)(wsb + in.L.rho_st);
+  unsigned long long* res_st = (unsigned long long*)(wsb + in.L.res_st);
+  int launches = 0, it = 0;
+  const size_t st_count = (size_t)p->nx * p->ny * p->nt;
+  rc = in.residual(U, u0, s, &launches);
+  if (rc) return rc;
+  rc = in.read_scalars(hs, false, s);
+  if (rc) return rc;
+  double res = hs[0], rhom = hs[1];
+  int* cached = g_stage_cache.find(p, tol);
+  int needed = -1;  // Newton steps after which |R| <= tol was first seen
+  for (;;) {
+    if (st && it < PTS_MAX_HIST) {
+      st->res_inf[it] = res;
+      st->rho_max[it] = rhom;
+    }
+    if (!std::isfinite(res) || !std::isfinite(rhom)) {
+      if (st) st->iterations = it;
+      return fail(PTS_ERR_NONFINITE, "non-finite residual at Newton step %d", it);
+    }
+    if (res <= tol && needed < 0) needed = it;
+    if (res <= tol) break;
+    if (rhom >= 1.0) {
+      if (st) st->iterations = it;
+      return fail(PTS_ERR_SINGULAR, "block A_n not diagonally dominant (Gershgorin radius %.3g)", rhom);
+    }
+    if (it >= max_iter) {
+      if (st) {
+        st->iterations = it;
+        st->launches = launches;
+      }
+      if (profiling) prof.collect(st);
+      return fail(PTS_ERR_NOT_CONVERGED, "not converged after %d Newton steps (|R| = %.3e)", it, res);
+    }
+    Plan pl;
+    if (!make_wave_plan(p, o, std::min(rhom * 1.02, 0.999), in.g, &pl)) {
+      if (it == 0) {
+        *fallback = true;
+        return PTS_ERR_INVALID_ARG;
+      }
+      return fail(PTS_ERR_SINGULAR, "inner solve cannot reach the requested reduction (radius %.3g)", rhom);
+    }
+    int K = (o && o->stages > 0) ? o->stages : (cached && *cached > it ? *cached - it : 4);
+    K = std::max(1, std::min(std::min(K, kMaxStages), max_iter - it));
+    if (st) {
+      st->sweeps = pl.sweeps;
+      st->refine = pl.passes - 1;
+      st->window = 1;
+      st->schedule = PTS_SCHED_PIPELINE;
+    }
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(((K + 1) * p->nt + 255) / 256)), dim3(256), 0, s, rho_st,
+                       (K + 1) * p->nt);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, res_st, K + 1);
+    launches += 2;
+    WaveArgs wa;
+    wa.Ur[0] = U;
+    wa.Ur[1] = U1;
+    wa.dUr[0] = in.dU;
+    wa.dUr[1] = dU2;
+    wa.u0 = u0;
+    wa.rho_in = (const double*)in.rho;
+    wa.rho_st = rho_st;
+    wa.res_st = res_st;
+    wa.stages = K;
+    rc = run_wave_sequence(p, in.kp, wa, in.g, pl, s, use_graph, profiling ? &prof : nullptr, &launches);
+    if (rc) return rc;
+    if (K & 1) {
+      HIPCHK(hipMemcpyAsync(U, U1, st_count * 8, hipMemcpyDeviceToDevice, s));
+    }
+    double rk[kMaxStages + 1];
+    HIPCHK(hipMemcpyAsync(hs, res_st, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 1; k <= K; ++k) rk[k] = hs[k];
+    for (int k = 1; k <= K; ++k) {
+      if (st && it + k < PTS_MAX_HIST) st->res_inf[it + k] = rk[k];
+      if (rk[k] <= tol && needed < 0) needed = it + k;
+      if (!std::isfinite(rk[k])) {
+        if (st) st->iterations = it + k;
+        return fail(PTS_ERR_NONFINITE, "non-finite residual at Newton step %d", it + k);
+      }
+    }
+    it += K;
+    res = rk[K];
+    if (res > tol) {
+      // radii of the new iterate for the next sequence (and a check of the last residual)
+      rc = in.residual(U, u0, s, &launches);
+      if (rc) return rc;
+      rc = in.read_scalars(hs, false, s);
+      if (rc) return rc;
+      res = hs[0];
+      rhom = hs[1];
+    }
+    // the residual reported at `it` must be the one of the final iterate
+    if (st && it < PTS_MAX_HIST) st->res_inf[it] = res;
+    if (res <= tol) break;
+  }
+  if (needed >= 0) g_stage_cache.put(p, tol, std::max(needed, 1));
+  if (st) {
+    st->iterations = it;
+    st->converged = 1;
+    st->launches = launches;
+  }
+  if (profiling) prof.collect(st);
+  return PTS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -579,7 +876,17 @@ int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_solve: NULL array");
   if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
   const auto t0 = std::chrono::steady_clock::now();
-  rc = solve_bulk(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream, false);
+  const int sched = opts ? opts->schedule : PTS_SCHED_AUTO;
+  bool fallback = true;
+  if (sched != PTS_SCHED_BULK) {
+    rc = solve_wave(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream, &fallback);
+    if (fallback && sched == PTS_SCHED_PIPELINE)
+      rc = fail(PTS_ERR_INVALID_ARG, "the inner solve does not fit the wavefront schedule");
+  }
+  if (fallback && sched != PTS_SCHED_PIPELINE) {
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    rc = solve_bulk(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream, false);
+  }
   if (stats)
     stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;

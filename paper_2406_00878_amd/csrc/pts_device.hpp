@@ -121,10 +121,10 @@ __device__ __forceinline__ Row5 jac_row(const KProb& p, const Nb& u, int x, int 
 }
 
 // ---------------------------------------------------------------- lane shifts
-// DPP wavefront shifts by one lane. shr: lane i receives lane i-1 (lane 0 gets 0);
-// shl: lane i receives lane i+1 (lane 63 gets 0).
-__device__ __forceinline__ int dpp_shr1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_shl1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+// DPP wavefront shifts by one lane with zero fill (bound_ctrl): shr makes lane i
+// receive lane i-1 (lane 0 gets 0), shl makes lane i receive lane i+1 (lane 63 gets 0).
+__device__ __forceinline__ int dpp_shr1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_shl1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
 
 __device__ __forceinline__ float lane_from_left(float v) {
   return __builtin_bit_cast(float, dpp_shr1_i(__builtin_bit_cast(int, v)));

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_level_max(const unsigned long long* __r
 // Geometry of the register-resident region: 64 lanes (x) by 8 waves x kRows (y).
 constexpr int kRows = 8;
 constexpr int kWaves = 8;
-constexpr int kRegion = 64;  // region edge in both directions
+constexpr int kMaxSweeps = 64;  // longest Chebyshev pass one launch may run
 
 // Exchange of one register row set between neighbouring waves via LDS.
 // buf holds 2 parities x kWaves x {bottom row, top row} x 64 lanes.
@@ -124,17 +124,117 @@ __device__ __forceinline__ YNb<T> y_exchange(const T (&v)[kRows], T* buf, int& p
   return r;
 }
 
-// Chebyshev weights for the Jacobi iteration matrix with spectral radius bound rho:
-// omega_1 = 1, omega_2 = 1/(1 - rho^2/2), omega_{k+1} = 1/(1 - rho^2 omega_k / 4).
-__device__ __forceinline__ double cheb_next(double omega, double rho2, int k) {
-  if (k == 1) return 1.0;
-  if (k == 2) return 1.0 / (1.0 - 0.5 * rho2);
-  return 1.0 / (1.0 - 0.25 * rho2 * omega);
+// Chebyshev weights for the Jacobi iteration matrix with spectral radius bound rho
+// (Golub-Varga semi-iteration): omega_1 = 1, omega_2 = 1/(1 - rho^2/2),
+// omega_{k+1} = 1/(1 - rho^2 omega_k / 4). One thread fills the table in LDS.
+__device__ __forceinline__ void cheb_table(double* om, double rho, int sweeps) {
+  if (threadIdx.x == 0) {
+    const double r2 = rho * rho;
+    double w = 1.0;
+    om[1] = 1.0;
+    for (int s = 2; s <= sweeps && s < kMaxSweeps; ++s) {
+      w = s == 2 ? 1.0 / (1.0 - 0.5 * r2) : 1.0 / (1.0 - 0.25 * r2 * w);
+      om[s] = w;
+    }
+  }
 }
 
-// One launch: `passes` restarted Chebyshev passes of `sweeps` sweeps each, inner
-// arithmetic in T, FP64 residual and accumulation. Xin (nullable) is the starting
-// iterate of the level (a previous launch), Xout receives the tile values.
+// Register-resident state of one 64 x 64 region of a level: Jacobi-scaled rows of A_n
+// (T), the FP64 rows (only for FP32 inner arithmetic), right-hand side b and iterate X.
+template <typename T>
+struct RegionSolve {
+  static constexpr bool kF64 = sizeof(T) == sizeof(double);
+  double cC[kRows], cW[kRows], cE[kRows], cS[kRows], cN[kRows];
+  double bb[kRows], X[kRows];
+  T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
+
+  __device__ __forceinline__ void set_row(int k, const Row5& a) {
+    const double inv = 1.0 / a.C;
+    iC[k] = T(inv);
+    sW[k] = T(a.W * inv);
+    sE[k] = T(a.E * inv);
+    sS[k] = T(a.S * inv);
+    sN[k] = T(a.N * inv);
+    if (!kF64) {
+      cC[k] = a.C;
+      cW[k] = a.W;
+      cE[k] = a.E;
+      cS[k] = a.S;
+      cN[k] = a.N;
+    }
+  }
+
+  // `passes` restarted Chebyshev passes of `sweeps` sweeps on A X = b, each pass from the
+  // FP64 residual of the current X (haveX = false: X = 0 and the first residual is b).
+  // Neighbour exchanges: (sweeps - 1) per pass, plus one per pass that starts from X.
+  __device__ void run(int passes, int sweeps, bool haveX, const double* om, double* lds, int wave, int lane) {
+    int par = 0;
+    T* ldst = reinterpret_cast<T*>(lds);
+    for (int pass = 0; pass < passes; ++pass) {
+      T d[kRows];
+      if (haveX) {
+        const YNb<double> yn = y_exchange<double>(X, lds, par, wave, lane);
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+          const double xs = k == 0 ? yn.s0 : X[k - 1];
+          const double xn = k == kRows - 1 ? yn.nM : X[k + 1];
+          const double xw = lane_from_left(X[k]);
+          const double xe = lane_from_right(X[k]);
+          if (kF64) {
+            d[k] = T(double(iC[k]) * bb[k] -
+                     (X[k] + double(sW[k]) * xw + double(sE[k]) * xe + double(sS[k]) * xs + double(sN[k]) * xn));
+          } else {
+            const double ax = cC[k] * X[k] + cW[k] * xw + cE[k] * xe + cS[k] * xs + cN[k] * xn;
+            d[k] = T((bb[k] - ax) / cC[k]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) d[k] = T(bb[k]) * iC[k];
+      }
+      // Chebyshev on D^{-1} A x = D^{-1} d from x_0 = 0, x_1 = D^{-1} d; with the scaled
+      // rows, x_{s} = x_{s-2} + omega_s (d - x_{s-2} - offdiag(x_{s-1})). xa and xb hold
+      // the two most recent iterates and are updated in place, alternately.
+      T xa[kRows], xb[kRows];
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        xa[k] = T(0);
+        xb[k] = d[k];
+      }
+      int s = 2;
+      for (; s + 1 <= sweeps; s += 2) {
+        sweep(xa, xb, d, T(om[s]), ldst, par, wave, lane);
+        sweep(xb, xa, d, T(om[s + 1]), ldst, par, wave, lane);
+      }
+      const bool odd = s <= sweeps;
+      if (odd) sweep(xa, xb, d, T(om[s]), ldst, par, wave, lane);
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) X[k] += double(odd ? xa[k] : xb[k]);
+      haveX = true;
+    }
+  }
+
+  // xold <- xold + w (d - xold - offdiag(xcur)): one Chebyshev step written over x_{s-2}.
+  __device__ __forceinline__ void sweep(T (&xold)[kRows], const T (&xcur)[kRows], const T (&d)[kRows], T w,
+                                        T* ldst, int& par, int wave, int lane) {
+    const YNb<T> yn = y_exchange<T>(xcur, ldst, par, wave, lane);
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const T xs = k == 0 ? yn.s0 : xcur[k - 1];
+      const T xn = k == kRows - 1 ? yn.nM : xcur[k + 1];
+      const T xw = lane_from_left(xcur[k]);
+      const T xe = lane_from_right(xcur[k]);
+      const T off = sW[k] * xw + sE[k] * xe + sS[k] * xs + sN[k] * xn;
+      xold[k] = xold[k] + w * (d[k] - xold[k] - off);
+    }
+  }
+};
+
+__device__ __forceinline__ double clamp_rho(double rho) { return fmin(fmax(rho, 1e-3), 0.999); }
+
+// Bulk schedule, one launch per level (or per group of passes of a level):
+// du^n = A_n^{-1}(r^n + du^{n-1}). Xin (nullable) is the starting iterate of the level
+// from a previous launch; Xout receives the tile values.
 template <typename T>
 __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const double* __restrict__ U,
                                                      const double* __restrict__ R,
@@ -144,6 +244,7 @@ __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const doubl
                                                      const double* __restrict__ rho_lvl, Geo g,
                                                      int passes, int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
+  __shared__ double om[kMaxSweeps];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tx = blockIdx.x % g.tilesx, ty = blockIdx.x / g.tilesx;
@@ -153,12 +254,9 @@ __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const doubl
   const double* un = U + (size_t)n * ns;
   const double* rn = R + (size_t)n * ns;
   const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+  cheb_table(om, clamp_rho(rho_lvl[2 * n + 1]), sweeps);
 
-  // FP64 rows are kept only when the inner arithmetic is FP32 (they form the FP64
-  // refinement residual); the FP64 inner path works with the Jacobi-scaled rows alone.
-  constexpr bool kF64 = sizeof(T) == sizeof(double);
-  double cC[kRows], cW[kRows], cE[kRows], cS[kRows], cN[kRows], bb[kRows], X[kRows];
-  T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
+  RegionSolve<T> rs;
   int idx[kRows];
   const int gx = rx0 + lane;
 #pragma unroll
@@ -178,103 +276,27 @@ __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const doubl
     if (act) {
       const Nb u = gather(p, un, bd, x, y);
       a = jac_row(p, u, x, y);
-      bb[k] = rn[idx[k]] + (dUprev ? dUprev[idx[k]] : 0.0);
-      X[k] = Xin ? Xin[idx[k]] : 0.0;
+      rs.bb[k] = rn[idx[k]] + (dUprev ? dUprev[idx[k]] : 0.0);
+      rs.X[k] = Xin ? Xin[idx[k]] : 0.0;
     } else {
       a.C = 1.0;
       a.W = a.E = a.S = a.N = 0.0;
-      bb[k] = 0.0;
-      X[k] = 0.0;
+      rs.bb[k] = 0.0;
+      rs.X[k] = 0.0;
     }
-    const double inv = 1.0 / a.C;
-    iC[k] = T(inv);
-    sW[k] = T(a.W * inv);
-    sE[k] = T(a.E * inv);
-    sS[k] = T(a.S * inv);
-    sN[k] = T(a.N * inv);
-    if (!kF64) {
-      cC[k] = a.C;
-      cW[k] = a.W;
-      cE[k] = a.E;
-      cS[k] = a.S;
-      cN[k] = a.N;
-    }
+    rs.set_row(k, a);
   }
-  double rho = rho_lvl[2 * n + 1];
-  rho = fmin(fmax(rho, 1e-3), 0.999);
-  const double rho2 = rho * rho;
+  __syncthreads();  // omega table
+  rs.run(passes, sweeps, Xin != nullptr, om, lds_raw, wave, lane);
 
-  int par = 0;
-  double* ldsd = lds_raw;
-  T* ldst = reinterpret_cast<T*>(lds_raw);
-  bool haveX = Xin != nullptr;
-  for (int pass = 0; pass < passes; ++pass) {
-    // FP64 residual of the current iterate: d = b - A X
-    T d[kRows];
-    if (haveX) {
-      const YNb<double> yn = y_exchange<double>(X, ldsd, par, wave, lane);
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const double xs = k == 0 ? yn.s0 : X[k - 1];
-        const double xn = k == kRows - 1 ? yn.nM : X[k + 1];
-        const double xw = lane_from_left(X[k]);
-        const double xe = lane_from_right(X[k]);
-        if (kF64) {
-          // (b - A X) / C with the Jacobi-scaled row
-          d[k] = T(double(iC[k]) * bb[k] -
-                   (X[k] + double(sW[k]) * xw + double(sE[k]) * xe + double(sS[k]) * xs + double(sN[k]) * xn));
-        } else {
-          const double ax = cC[k] * X[k] + cW[k] * xw + cE[k] * xe + cS[k] * xs + cN[k] * xn;
-          d[k] = T((bb[k] - ax) / cC[k]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) d[k] = T(bb[k]) * iC[k];
-    }
-    // Chebyshev on D^{-1} A x = D^{-1} d from x = 0; first sweep x_1 = D^{-1} d
-    T xc[kRows], xm[kRows];
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) {
-      xc[k] = d[k];
-      xm[k] = T(0);
-    }
-    double omega = 1.0;
-    for (int s = 2; s <= sweeps; ++s) {
-      omega = cheb_next(omega, rho2, s);
-      const T om = T(omega);
-      const YNb<T> yn = y_exchange<T>(xc, ldst, par, wave, lane);
-      T xnw[kRows];
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const T xs = k == 0 ? yn.s0 : xc[k - 1];
-        const T xn = k == kRows - 1 ? yn.nM : xc[k + 1];
-        const T xw = lane_from_left(xc[k]);
-        const T xe = lane_from_right(xc[k]);
-        // z = D^{-1}(d - A x) with unit diagonal after scaling
-        const T z = d[k] - (xc[k] + sW[k] * xw + sE[k] * xe + sS[k] * xs + sN[k] * xn);
-        xnw[k] = xm[k] + om * (xc[k] - xm[k] + z);
-      }
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        xm[k] = xc[k];
-        xc[k] = xnw[k];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) X[k] += double(xc[k]);
-    haveX = true;
-  }
-
-  // write the tile
   const int lx = g.whole ? lane : lane - g.H;
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
     const int ly = g.whole ? wave * kRows + k : wave * kRows + k - g.H;
     const int gy = ry0 + wave * kRows + k;
-    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx < p.nx && gy < p.ny && gx >= 0 &&
-                        gy >= 0 && idx[k] >= 0;
-    if (inside) Xout[idx[k]] = X[k];
+    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx >= 0 && gx < p.nx && gy >= 0 &&
+                        gy < p.ny && idx[k] >= 0;
+    if (inside) Xout[idx[k]] = rs.X[k];
   }
 }
 
@@ -282,6 +304,151 @@ template __global__ void k_level_solve<double>(KProb, int, const double*, const 
                                                const double*, double*, const double*, Geo, int, int);
 template __global__ void k_level_solve<float>(KProb, int, const double*, const double*, const double*,
                                               const double*, double*, const double*, Geo, int, int);
+
+// ---------------------------------------------------------- wavefront schedule
+// Newton iteration j at level n needs the iterate U_j at levels n-1, n (written by
+// iteration j-1) and du_j^{n-1} (iteration j, level n-1). All pairs (j, n) on the
+// anti-diagonal n + 2j = diag are therefore independent and run in one launch; the
+// launch order d = 0, 1, 2, ... carries every dependency, and no two pairs of one launch
+// touch the same level of the same buffer. Pair (j, n) forms r_j^n = -G^n(U_j) and the
+// rows of A_n(U_j) from U_j, solves A_n du_j^n = r_j^n + du_j^{n-1} on its tile, writes
+// du_j^n and U_{j+1}^n = U_j^n + du_j^n, and from the tile's U_{j+1} also the next
+// iterate's residual r_{j+1}^n and Gershgorin radius (reduced per level and per stage).
+struct WaveArgs {
+  double* Ur[2];                  // iterate ring: stage j reads Ur[j & 1], writes Ur[(j + 1) & 1]
+  double* dUr[2];                 // update ring: stage j writes dUr[j & 1]
+  const double* u0;               // initial condition (level 0)
+  const double* rho_in;           // radius of A_n(U_0) at rho_in[2n + 1] (bit pattern)
+  unsigned long long* rho_st;     // [(stages + 1) * nt]: radius of A_n(U_j) at [j * nt + n]
+  unsigned long long* res_st;     // [stages + 1]: max |r(U_j)| at [j]
+  int stages;
+};
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
+                                                    int sweeps) {
+  __shared__ double lds_raw[2 * kWaves * 2 * 64];
+  __shared__ double om[kMaxSweeps];
+  __shared__ double red[2][kWaves];
+  const int tiles_per_level = gridDim.x / a.stages;
+  const int j = blockIdx.x / tiles_per_level;
+  const int tile = blockIdx.x % tiles_per_level;
+  const int n = diag - 2 * j;
+  if (n < 0 || n >= p.nt) return;  // uniform over the work-group
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tx = tile % g.tilesx, ty = tile / g.tilesx;
+  const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
+  const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
+  const size_t ns = (size_t)p.nx * p.ny;
+  const double* Uj = a.Ur[j & 1];
+  const double* un = Uj + (size_t)n * ns;
+  const double* up = n == 0 ? a.u0 : Uj + (size_t)(n - 1) * ns;
+  const double* dup = n == 0 ? nullptr : a.dUr[j & 1] + (size_t)(n - 1) * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+  const double rho_j = j == 0 ? a.rho_in[2 * n + 1] : __longlong_as_double(a.rho_st[(size_t)j * p.nt + n]);
+  cheb_table(om, clamp_rho(rho_j), sweeps);
+
+  RegionSolve<T> rs;
+  double uc[kRows], upn[kRows];  // U_j^n and U_{j+1}^{n-1} at the region nodes
+  int idx[kRows];
+  const int gx = rx0 + lane;
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int gy = ry0 + wave * kRows + k;
+    int x = gx, y = gy;
+    bool act;
+    if (p.bc == 1) {
+      x = wrap(gx, p.nx);
+      y = wrap(gy, p.ny);
+      act = true;
+    } else {
+      act = gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
+    }
+    idx[k] = act ? y * p.nx + x : -1;
+    Row5 r5;
+    if (act) {
+      const Nb u = gather(p, un, bd, x, y);
+      r5 = jac_row(p, u, x, y);
+      const double prev = up[idx[k]];
+      const double dprev = dup ? dup[idx[k]] : 0.0;
+      rs.bb[k] = -(u.P - prev + p.dt * spatial_op(p, u)) + dprev;
+      uc[k] = u.P;
+      upn[k] = prev + dprev;
+    } else {
+      r5.C = 1.0;
+      r5.W = r5.E = r5.S = r5.N = 0.0;
+      rs.bb[k] = 0.0;
+      uc[k] = 0.0;
+      upn[k] = 0.0;
+    }
+    rs.X[k] = 0.0;
+    rs.set_row(k, r5);
+  }
+  __syncthreads();  // omega table
+  rs.run(passes, sweeps, false, om, lds_raw, wave, lane);
+
+  // U_{j+1} on the region (valid one node beyond the tile), its neighbours, and the
+  // residual and radius of the next iterate on the tile
+  double unew[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) unew[k] = uc[k] + rs.X[k];
+  int par = 0;
+  const YNb<double> yn = y_exchange<double>(unew, lds_raw, par, wave, lane);
+  const int lx = g.whole ? lane : lane - g.H;
+  double rmax = 0.0, gmax = 0.0;
+  double* dUo = a.dUr[j & 1] + (size_t)n * ns;
+  double* Uo = a.Ur[(j + 1) & 1] + (size_t)n * ns;
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    Nb u;
+    u.P = unew[k];
+    u.S = k == 0 ? yn.s0 : unew[k - 1];
+    u.N = k == kRows - 1 ? yn.nM : unew[k + 1];
+    u.W = lane_from_left(unew[k]);
+    u.E = lane_from_right(unew[k]);
+    const int ly = g.whole ? wave * kRows + k : wave * kRows + k - g.H;
+    const int gy = ry0 + wave * kRows + k;
+    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx >= 0 && gx < p.nx && gy >= 0 &&
+                        gy < p.ny && idx[k] >= 0;
+    if (inside) {
+      const int x = gx, y = gy;
+      if (p.bc == 0) {  // Dirichlet neighbours outside the domain are data
+        if (x == 0) u.W = node_value(p, un, bd, -1, y);
+        if (x == p.nx - 1) u.E = node_value(p, un, bd, p.nx, y);
+        if (y == 0) u.S = node_value(p, un, bd, x, -1);
+        if (y == p.ny - 1) u.N = node_value(p, un, bd, x, p.ny);
+      }
+      const double r = -(u.P - upn[k] + p.dt * spatial_op(p, u));
+      const Row5 q = jac_row(p, u, x, y);
+      double gr = (fabs(q.W) + fabs(q.E) + fabs(q.S) + fabs(q.N)) / fabs(q.C);
+      if (!(q.C > 0.0) || gr != gr) gr = __longlong_as_double(0x7ff0000000000000ll);
+      rmax = nanmax(rmax, fabs(r));
+      gmax = nanmax(gmax, gr);
+      dUo[idx[k]] = rs.X[k];
+      Uo[idx[k]] = unew[k];
+    }
+  }
+  rmax = wave_max(rmax);
+  gmax = wave_max(gmax);
+  if (lane == 0) {
+    red[0][wave] = rmax;
+    red[1][wave] = gmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0][0], q = red[1][0];
+    for (int w = 1; w < kWaves; ++w) {
+      r = nanmax(r, red[0][w]);
+      q = nanmax(q, red[1][w]);
+    }
+    atomic_max_nonneg(a.res_st + j + 1, r);
+    atomic_max_nonneg(a.rho_st + (size_t)(j + 1) * p.nt + n, q);
+  }
+}
+
+template __global__ void k_level_wave<double>(KProb, WaveArgs, Geo, int, int, int);
+template __global__ void k_level_wave<float>(KProb, WaveArgs, Geo, int, int, int);
 
 // ------------------------------------------------------------------- update
 __global__ __launch_bounds__(256) void k_update(size_t count, double* __restrict__ U,

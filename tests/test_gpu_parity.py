@@ -223,3 +223,50 @@ def test_quadratic_convergence_history():
     r = st["res_inf"]
     ratios = [r[k + 1] / r[k] ** 2 for k in range(len(r) - 1) if r[k + 1] > 1e-12]
     assert len(ratios) >= 2 and max(ratios[1:]) < 100.0
+
+
+# ------------------------------------------------------------- wavefront schedule
+
+def test_wavefront_matches_bulk_bitwise():
+    """The wavefront schedule overlaps Newton iterations but computes the same arithmetic
+    as one-iteration-after-another: with a fixed inner sweep count the results agree bit for bit."""
+    n1, n2 = 80, 72
+    p = W.burgers_periodic(n1, 24, 5e-4, 0.01, W.fourier_u0_periodic(n1, 11)[:n2, :])
+    p.ny, p.hy = n2, 1.0 / n2
+    Ub, sb = gpu_solve(p, tol=1e-12, schedule="bulk", sweeps=12)
+    Uw, sw = gpu_solve(p, tol=1e-12, schedule="pipeline", sweeps=12, stages=sb["iterations"])
+    assert sw["schedule"] == P.PTS_SCHED_PIPELINE and sb["schedule"] == P.PTS_SCHED_BULK
+    assert sw["iterations"] == sb["iterations"]
+    assert np.array_equal(Ub, Uw)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3, 7])
+def test_wavefront_stage_counts(stages):
+    p = W.burgers_periodic(64, 30, 5e-4, 0.01, W.fourier_u0_periodic(64, 5))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12, schedule="pipeline", stages=stages)
+    assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE
+    assert relerr(U, Us) <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["mms_whole", "dirichlet_tiled_bdata"])
+def test_wavefront_dirichlet_boundary_data(case):
+    """The next-iterate residual formed inside the wavefront kernel reads the Dirichlet data."""
+    if case == "mms_whole":
+        p = W.heat_mms(20)
+    else:
+        rng = np.random.default_rng(9)
+        p = W.Problem(W.BURGERS, W.DIRICHLET, 75, 70, 6, 1 / 76, 1 / 71, 1e-3, 0.02, 0.0,
+                      0.5 * rng.uniform(-1, 1, (70, 75)), 0.5 * rng.uniform(-1, 1, (6, 2 * 145)))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12, schedule="pipeline")
+    assert st["converged"]
+    assert relerr(U, Us) <= 1e-10
+
+
+def test_wavefront_mixed_precision():
+    p = W.burgers_periodic(96, 32, 2.5e-4, 1e-3, W.disc_u0_periodic(96, 2406003))
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12, precision="mixed", schedule="pipeline")
+    assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE
+    assert relerr(U, Us) <= 1e-8
