@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the inner-plan autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -92,6 +93,12 @@ def main():
     opts = dict(schedule=args.schedule, use_graph=not args.no_graph)
     print(f"[bench] {args.workload} {prob.nx}x{prob.ny}x{prob.nt} {args.precision} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+
+    tuned = None
+    if args.schedule in ("auto", "pipeline") and not args.no_autotune:
+        P.init_plain(prob, U, u0)
+        tuned = P.autotune(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
 
     def step():
         P.init_plain(prob, U, u0)
@@ -144,7 +151,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "nx": prob.nx, "ny": prob.ny, "nt": prob.nt, "dt": prob.dt,
                    "precision": args.precision, "tol": args.tol, "newton_steps": st["iterations"],
-                   "inner_sweeps": st["sweeps"], "schedule": st["schedule"], **extra},
+                   "inner_sweeps": st["sweeps"], "inner_passes": st["refine"] + 1,
+                   "schedule": {1: "bulk", 2: "wavefront"}.get(st["schedule"], st["schedule"]),
+                   "autotuned": tuned is not None, **extra},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},

@@ -151,6 +151,16 @@ int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int
               void* workspace, size_t workspace_bytes, const pts_options* opts,
               pts_stats* stats, pts_stream_t stream);
 
+/* Autotuner of the wavefront schedule: tries inner sweep/pass plans on this problem
+   (each a full solve from the iterate in U, timed with HIP events on `stream`), and
+   keeps the fastest converging plan with its Newton step count in a per-thread cache
+   keyed by the problem and tol; later pts_solve calls with default options use it.
+   U is restored before returning. stats (host, may be NULL) receives the chosen plan
+   (sweeps, refine, iterations) and its time in solve_ms. Synchronises the stream. */
+int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, int max_iter,
+                 void* workspace, size_t workspace_bytes, const pts_options* opts,
+                 pts_stats* stats, pts_stream_t stream);
+
 /* Independent instances solved together, every instance's levels batched in
    the same launches. U[i], u0[i] are device pointers; workspace is one block of
    pts_workspace_bytes_batched bytes; stats is a host array of nprob entries

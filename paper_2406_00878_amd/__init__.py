@@ -23,7 +23,7 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_FP64, PTS_HEAT, PTS_MIXED, PT
                    PTS_SCHED_AUTO, PTS_SCHED_BULK, PTS_SCHED_PIPELINE, pts_options, pts_problem,
                    pts_stats)
 
-__all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve",
+__all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve", "autotune",
            "solve_batched", "window_bound", "library_path", "version"]
 
 
@@ -181,6 +181,20 @@ def solve(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", ws=
         if raise_on_error:
             _check(rc)
     return out
+
+
+def autotune(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", ws=None, stream=None,
+             **opts) -> dict:
+    """Pick the fastest inner plan of the wavefront schedule for this problem (U is restored)."""
+    p = make_problem(prob, precision, bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = workspace(prob, precision, U.device) if ws is None else ws
+    o = _options(**opts)
+    st = pts_stats()
+    _check(_lib_checked().pts_autotune(C.byref(p), _ptr(U), _ptr(u0), float(tol), int(max_iter), _ptr(ws),
+                                       ws.numel(), C.byref(o), C.byref(st), _stream(stream)))
+    return {"sweeps": st.sweeps, "passes": st.refine + 1, "newton_steps": st.iterations, "ms": st.solve_ms}
 
 
 def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,

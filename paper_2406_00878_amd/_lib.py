@@ -61,6 +61,7 @@ def load():
         "pts_init_plain": (I, [P, V, V, V]),
         "pts_newton_step": (I, [P, V, V, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_solve": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
+        "pts_autotune": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_workspace_bytes_batched": (S, [P, I]),
         "pts_solve_batched": (I, [P, I, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_window_bound": (I, [D, D, D, D, D, I]),

@@ -55,7 +55,7 @@ int validate(const pts_problem* p) {
   if (p->kind != PTS_HEAT && p->kind != PTS_BURGERS) return fail(PTS_ERR_INVALID_ARG, "kind %d", p->kind);
   if (p->bc != PTS_DIRICHLET && p->bc != PTS_PERIODIC) return fail(PTS_ERR_INVALID_ARG, "bc %d", p->bc);
   if (p->nx < 1 || p->ny < 1 || p->nt < 1) return fail(PTS_ERR_INVALID_ARG, "sizes %d x %d x %d", p->nx, p->ny, p->nt);
-  if ((long long)p->nx * p->ny > (1ll << 30)) return fail(PTS_ERR_INVALID_ARG, "level too large");
+  if ((long long)p->nx * p->ny > (1ll << 28)) return fail(PTS_ERR_INVALID_ARG, "level exceeds 2^28 nodes");
   if (p->nt > 65535) return fail(PTS_ERR_INVALID_ARG, "nt %d exceeds 65535", p->nt);
   if (p->precision != PTS_FP64 && p->precision != PTS_MIXED)
     return fail(PTS_ERR_INVALID_ARG, "precision %d", p->precision);
@@ -119,7 +119,7 @@ Layout layout(const pts_problem* p) {
   return L;
 }
 
-Geo geometry(const pts_problem* p) {
+Geo geometry(const pts_problem* p, int halo = kHalo) {
   Geo g;
   if (p->bc == PTS_DIRICHLET && p->nx <= 64 && p->ny <= 64) {
     g.whole = 1;
@@ -129,9 +129,9 @@ Geo geometry(const pts_problem* p) {
     g.tilesx = 1;
   } else {
     g.whole = 0;
-    g.H = kHalo;
-    g.TX = 64 - 2 * kHalo;
-    g.TY = 64 - 2 * kHalo;
+    g.H = halo;
+    g.TX = 64 - 2 * halo;
+    g.TY = 64 - 2 * halo;
     g.tilesx = (p->nx + g.TX - 1) / g.TX;
   }
   return g;
@@ -217,7 +217,10 @@ int launch_residual(const pts_problem* p, const KProb& kp, const double* U, cons
   const int tilesx = (p->nx + 63) / 64, tilesy = (p->ny + kResRows - 1) / kResRows;
   if (lvl_bits) hipLaunchKernelGGL(k_zero, dim3((2 * p->nt + 255) / 256), dim3(256), 0, s, lvl_bits, 2 * p->nt);
   dim3 grid((unsigned)(tilesx * tilesy), (unsigned)p->nt);
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
+  if (p->bc == PTS_PERIODIC)
+    hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
+  else
+    hipLaunchKernelGGL(k_residual<0>, grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
   if (scal) hipLaunchKernelGGL(k_level_max, dim3(1), dim3(256), 0, s, lvl_bits, p->nt, scal);
   HIPCHK(hipGetLastError());
   return PTS_OK;
@@ -241,12 +244,11 @@ int launch_chain(const pts_problem* p, const KProb& kp, const double* U, const d
     for (int l = 0; l < nl; ++l) {
       double* xo = ((nl - 1 - l) % 2 == 0) ? out : Xs;
       prof_begin(pr, 1, s);
-      if (pl.fp32)
-        hipLaunchKernelGGL(k_level_solve<float>, dim3(nb), dim3(512), 0, s, kp, n, U, R, prev, xin, xo, rho, g,
-                           pl.packs[l], pl.sweeps);
-      else
-        hipLaunchKernelGGL(k_level_solve<double>, dim3(nb), dim3(512), 0, s, kp, n, U, R, prev, xin, xo, rho, g,
-                           pl.packs[l], pl.sweeps);
+      const bool per = p->bc == PTS_PERIODIC;
+      auto kern = pl.fp32 ? (per ? k_level_solve<float, 1> : k_level_solve<float, 0>)
+                          : (per ? k_level_solve<double, 1> : k_level_solve<double, 0>);
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, kp, n, U, R, prev, xin, xo, rho, g, pl.packs[l],
+                         pl.sweeps);
       prof_end(pr, s, 8.0 * (double)ns * (3 + (prev ? 1 : 0) + (xin ? 1 : 0)));
       xin = xo;
       ++*launches;
@@ -344,10 +346,10 @@ struct Instance {
 
   // residual at U with per-level and global maxima (fill kernels, so the sequence is
   // graph-safe)
-  int residual(const double* U, const double* u0, hipStream_t s, int* launches) {
+  int residual(const double* U, const double* u0, hipStream_t s, int* launches, bool store_r = true) {
     *launches += 3;
     prof_begin(prof, 0, s);
-    int rc = launch_residual(p, kp, U, u0, R, nullptr, rho, scal, s);
+    int rc = launch_residual(p, kp, U, u0, store_r ? R : nullptr, nullptr, rho, scal, s);
     if (prof) prof->end(s);
     return rc;
   }
@@ -514,84 +516,83 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
 
 
 // ------------------------------------------------------------ wavefront schedule
-// Inner-solve plan for the wavefront kernel: every pass of a level runs in the one launch
-// and the tile must stay valid one node beyond its edge, so the neighbour exchanges are
-// bounded by H - 1. Returns false when no plan reaches a useful reduction (< 1e-3).
-bool make_wave_plan(const pts_problem* p, const pts_options* o, double rho_max, const Geo& g, Plan* out) {
-  Plan pl;
-  pl.fp32 = p->precision == PTS_MIXED;
+// Inner-solve plan for the wavefront kernel. Every pass of a level runs in the one launch
+// and the tile must stay valid one node beyond its edge, so the halo is the number of
+// neighbour exchanges plus one: H = (s - 1) + (P - 1) s + 1, tile edge 64 - 2H. Fewer
+// sweeps therefore also mean larger tiles and fewer work-groups per level.
+constexpr int kMaxWaveHalo = 24;  // tile edge >= 16
+
+int wave_halo(const Plan& pl) { return (pl.sweeps - 1) + (pl.passes - 1) * pl.sweeps + 1; }
+
+// Work of one (stage, level) in region-sweeps: tiles x sweeps x passes.
+double wave_cost(const pts_problem* p, const Plan& pl) {
+  const Geo g = geometry(p, wave_halo(pl));
+  return (double)tiles(p, g) * pl.sweeps * pl.passes;
+}
+
+// Cheapest plan whose reduction reaches lin_tol (explicit sweeps/refine options are obeyed).
+bool make_wave_plan(const pts_problem* p, const pts_options* o, double rho_max, double lin_tol, Plan* out) {
+  const bool fp32 = p->precision == PTS_MIXED;
+  const bool whole = geometry(p).whole;
   const double rho = std::min(std::max(rho_max, 1e-3), 0.999);
-  const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : (pl.fp32 ? 1e-6 : 1e-9);
-  const int emax = g.whole ? (1 << 20) : g.H - 1;
-  const double floor_red = pl.fp32 ? 1e-6 : 1e-15;
-  if (!pl.fp32 || !(o && o->refine > 0)) {
-    // one pass if it reaches lin_tol within the exchange budget
-    int s = 1;
-    if (o && o->sweeps > 0)
-      s = o->sweeps;
-    else
-      while (s < 4096 && cheb_reduction(s, rho) > std::max(lin_tol, floor_red)) ++s;
-    if (s - 1 <= emax && (s < kMaxSweeps) && (cheb_reduction(s, rho) <= lin_tol || !pl.fp32)) {
-      if (s - 1 > emax) s = emax + 1;
-      pl.sweeps = s;
-      pl.passes = 1;
-      pl.packs = {1};
-      *out = pl;
-      return cheb_reduction(s, rho) <= 1e-3;
-    }
-  }
-  // several passes of s sweeps: (s - 1) + (P - 1) s exchanges
-  int best_s = 0, best_p = 0;
-  double best_red = 1.0;
-  for (int s = 2; s < kMaxSweeps; ++s) {
-    const double red1 = std::max(cheb_reduction(s, rho), floor_red);
+  const double floor_red = fp32 ? 1e-6 : 1e-15;
+  Plan best;
+  double best_cost = 0.0, best_red = 1.0;
+  bool found = false;
+  for (int s = 1; s < kMaxSweeps; ++s) {
+    if (o && o->sweeps > 0 && s != o->sweeps) continue;
     for (int P = 1; P <= 8; ++P) {
-      const int ex = (s - 1) + (P - 1) * s;
-      if (ex > emax) break;
-      if (o && o->refine > 0 && P != 1 + o->refine) continue;
-      if (o && o->sweeps > 0 && s != o->sweeps) continue;
-      const double red = std::pow(red1, P);
-      const double work = (double)s * P;
+      if (!fp32 && P > 1) break;  // FP64 passes are one long Chebyshev run
+      if (fp32 && o && o->refine >= 0 && !(o->refine == 0 && o->sweeps == 0) && P != 1 + o->refine) continue;
+      Plan pl;
+      pl.fp32 = fp32;
+      pl.sweeps = s;
+      pl.passes = P;
+      pl.packs = {P};
+      if (!whole && wave_halo(pl) > kMaxWaveHalo) continue;
+      const double red = std::pow(std::max(cheb_reduction(s, rho), floor_red), P);
+      const double cost = whole ? (double)s * P : wave_cost(p, pl);
       const bool ok = red <= lin_tol;
-      const bool best_ok = best_red <= lin_tol;
-      if (best_p == 0 || (ok && !best_ok) || (ok && best_ok && work < (double)best_s * best_p) ||
-          (!ok && !best_ok && red < best_red)) {
-        best_s = s;
-        best_p = P;
+      const bool best_ok = found && best_red <= lin_tol;
+      if (!found || (ok && !best_ok) || (ok && best_ok && cost < best_cost) || (!ok && !best_ok && red < best_red)) {
+        best = pl;
+        best_cost = cost;
         best_red = red;
+        found = true;
       }
     }
   }
-  if (best_p == 0) return false;
-  pl.sweeps = best_s;
-  pl.passes = best_p;
-  pl.packs = {best_p};
-  *out = pl;
-  return best_red <= 1e-3;
+  if (!found) return false;
+  *out = best;
+  return best_red <= 1e-2;
 }
 
-// Newton steps needed last time for a problem signature (autotuned stage count).
+// Autotuned choices per problem signature and tolerance: inner sweeps and passes of the
+// wavefront kernel and the Newton steps they needed.
 struct StageCache {
   struct E {
     int nx, ny, nt, kind, bc, prec;
     double dt, mu_a, mu_b, tol;
-    int steps;
+    int sweeps, passes, steps;
   };
   std::vector<E> v;
-  int* find(const pts_problem* p, double tol) {
+  E* find(const pts_problem* p, double tol) {
     for (auto& e : v)
       if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
           e.prec == p->precision && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b && e.tol == tol)
-        return &e.steps;
+        return &e;
     return nullptr;
   }
-  void put(const pts_problem* p, double tol, int steps) {
-    if (int* s = find(p, tol)) {
-      *s = steps;
+  void put(const pts_problem* p, double tol, int sweeps, int passes, int steps) {
+    if (E* e = find(p, tol)) {
+      e->sweeps = sweeps;
+      e->passes = passes;
+      e->steps = steps;
       return;
     }
     if (v.size() > 64) v.clear();
-    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, p->dt, p->mu_a, p->mu_b, tol, steps});
+    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, p->dt, p->mu_a, p->mu_b, tol, sweeps, passes,
+                 steps});
   }
 };
 thread_local StageCache g_stage_cache;
@@ -609,12 +610,10 @@ int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& 
   const int ndiag = p->nt + 2 * (wa.stages - 1);
   for (int d = 0; d < ndiag; ++d) {
     prof_begin(pr, 1, s);
-    if (pl.fp32)
-      hipLaunchKernelGGL(k_level_wave<float>, dim3(wa.stages * tl), dim3(512), 0, s, kp, wa, g, d, pl.passes,
-                         pl.sweeps);
-    else
-      hipLaunchKernelGGL(k_level_wave<double>, dim3(wa.stages * tl), dim3(512), 0, s, kp, wa, g, d, pl.passes,
-                         pl.sweeps);
+    const bool per = p->bc == PTS_PERIODIC;
+    auto kern = pl.fp32 ? (per ? k_level_wave<float, 1> : k_level_wave<float, 0>)
+                        : (per ? k_level_wave<double, 1> : k_level_wave<double, 0>);
+    hipLaunchKernelGGL(kern, dim3(wa.stages * tl), dim3(kThreads), 0, s, kp, wa, g, d, pl.passes, pl.sweeps);
     if (pr) {
       const int active = std::min(wa.stages, d / 2 + 1) - std::max(0, (d - p->nt + 2) / 2);
       pr->end(s);
@@ -693,13 +692,13 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
   unsigned long long* res_st = (unsigned long long*)(wsb + in.L.res_st);
   int launches = 0, it = 0;
   const size_t st_count = (size_t)p->nx * p->ny * p->nt;
-  rc = in.residual(U, u0, s, &launches);
+  rc = in.residual(U, u0, s, &launches, false);
   if (rc) return rc;
   rc = in.read_scalars(hs, false, s);
   if (rc) return rc;
   double res = hs[0], rhom = hs[1];
-  int* cached = g_stage_cache.find(p, tol);
   int needed = -1;  // Newton steps after which |R| <= tol was first seen
+  Plan plan_used;
   for (;;) {
     if (st && it < PTS_MAX_HIST) {
       st->res_inf[it] = res;
@@ -723,16 +722,33 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
       if (profiling) prof.collect(st);
       return fail(PTS_ERR_NOT_CONVERGED, "not converged after %d Newton steps (|R| = %.3e)", it, res);
     }
+    // inner plan: explicit options, else the autotuned entry, else the cheapest plan that
+    // reaches lin_tol (default 1e-4: the wavefront runs inexact Newton steps)
     Plan pl;
-    if (!make_wave_plan(p, o, std::min(rhom * 1.02, 0.999), in.g, &pl)) {
+    const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
+    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
+    bool ok;
+    if (ce && !explicit_inner && ce->sweeps > 0) {
+      pl.fp32 = p->precision == PTS_MIXED;
+      pl.sweeps = ce->sweeps;
+      pl.passes = ce->passes;
+      pl.packs = {pl.passes};
+      ok = true;
+    } else {
+      ok = make_wave_plan(p, o, std::min(rhom * 1.02, 0.999), lin_tol, &pl);
+    }
+    if (!ok) {
       if (it == 0) {
         *fallback = true;
         return PTS_ERR_INVALID_ARG;
       }
       return fail(PTS_ERR_SINGULAR, "inner solve cannot reach the requested reduction (radius %.3g)", rhom);
     }
-    int K = (o && o->stages > 0) ? o->stages : (cached && *cached > it ? *cached - it : 4);
+    const Geo g = in.g.whole ? in.g : geometry(p, wave_halo(pl));
+    int K = (o && o->stages > 0) ? o->stages : (ce && ce->steps > it ? ce->steps - it : 4);
     K = std::max(1, std::min(std::min(K, kMaxStages), max_iter - it));
+    plan_used = pl;
     if (st) {
       st->sweeps = pl.sweeps;
       st->refine = pl.passes - 1;
@@ -753,28 +769,29 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     wa.rho_st = rho_st;
     wa.res_st = res_st;
     wa.stages = K;
-    rc = run_wave_sequence(p, in.kp, wa, in.g, pl, s, use_graph, profiling ? &prof : nullptr, &launches);
+    rc = run_wave_sequence(p, in.kp, wa, g, pl, s, use_graph, profiling ? &prof : nullptr, &launches);
     if (rc) return rc;
     if (K & 1) {
       HIPCHK(hipMemcpyAsync(U, U1, st_count * 8, hipMemcpyDeviceToDevice, s));
     }
-    double rk[kMaxStages + 1];
-    HIPCHK(hipMemcpyAsync(hs, res_st, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+    // residuals of the iterates U_{it+1..it+K} formed by the stages; when the sequence
+    // has not converged, the all-level residual of U_{it+K} also gives the radii with
+    // which the next sequence starts
+    HIPCHK(hipMemcpyAsync(hs + 8, res_st, (K + 1) * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int k = 1; k <= K; ++k) rk[k] = hs[k];
     for (int k = 1; k <= K; ++k) {
-      if (st && it + k < PTS_MAX_HIST) st->res_inf[it + k] = rk[k];
-      if (rk[k] <= tol && needed < 0) needed = it + k;
-      if (!std::isfinite(rk[k])) {
+      const double rk = hs[8 + k];
+      if (st && it + k < PTS_MAX_HIST) st->res_inf[it + k] = rk;
+      if (rk <= tol && needed < 0) needed = it + k;
+      if (!std::isfinite(rk)) {
         if (st) st->iterations = it + k;
         return fail(PTS_ERR_NONFINITE, "non-finite residual at Newton step %d", it + k);
       }
     }
     it += K;
-    res = rk[K];
+    res = hs[8 + K];
     if (res > tol) {
-      // radii of the new iterate for the next sequence (and a check of the last residual)
-      rc = in.residual(U, u0, s, &launches);
+      rc = in.residual(U, u0, s, &launches, false);
       if (rc) return rc;
       rc = in.read_scalars(hs, false, s);
       if (rc) return rc;
@@ -785,13 +802,104 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     if (st && it < PTS_MAX_HIST) st->res_inf[it] = res;
     if (res <= tol) break;
   }
-  if (needed >= 0) g_stage_cache.put(p, tol, std::max(needed, 1));
+  if (needed >= 0 && plan_used.sweeps > 0) {
+    // remember the step count for this plan (an autotuned plan stays the cached one)
+    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
+      g_stage_cache.put(p, tol, plan_used.sweeps, plan_used.passes, std::max(needed, 1));
+  }
   if (st) {
     st->iterations = it;
     st->converged = 1;
     st->launches = launches;
   }
   if (profiling) prof.collect(st);
+  return PTS_OK;
+}
+
+
+// Try inner plans for the wavefront schedule on this problem (each a full solve from the
+// iterate in U, run twice: once to learn its Newton step count, once timed with HIP
+// events on the stream) and cache the fastest. U is restored on return.
+int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
+                  const pts_options* o, pts_stats* st, hipStream_t s) {
+  Instance in;
+  in.bind(p, ws);
+  const size_t bytes = (size_t)p->nx * p->ny * p->nt * 8;
+  double* backup = in.R;  // the residual array is not used by the wavefront schedule
+  HIPCHK(hipMemcpyAsync(backup, U, bytes, hipMemcpyDeviceToDevice, s));
+  const bool fp32 = p->precision == PTS_MIXED;
+  std::vector<std::pair<int, int>> cands;
+  if (!fp32) {
+    for (int sw : {4, 5, 6, 7, 8, 10, 12, 16}) cands.push_back({sw, 1});
+  } else {
+    for (int sw : {3, 4, 5, 6}) cands.push_back({sw, 2});
+    for (int sw : {3, 4}) cands.push_back({sw, 3});
+    for (int sw : {5, 6, 8}) cands.push_back({sw, 1});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best_sw = 0, best_pa = 0, best_steps = 0;
+  pts_options oo = o ? *o : pts_options{};
+  oo.schedule = PTS_SCHED_PIPELINE;
+  oo.profile = 0;
+  oo.lin_tol = 0;
+  for (auto& c : cands) {
+    oo.sweeps = c.first;
+    oo.refine = c.second - 1;
+    oo.stages = 0;
+    Plan probe;
+    probe.sweeps = c.first;
+    probe.passes = c.second;
+    if (!geometry(p).whole && wave_halo(probe) > kMaxWaveHalo) continue;
+    // run 1: discover the step count (uncached plan -> stage guesses of 4)
+    g_stage_cache.put(p, tol, c.first, c.second, 4);
+    HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
+    bool fb = false;
+    pts_stats s1;
+    std::memset(&s1, 0, sizeof s1);
+    pts_options o1 = oo;
+    o1.sweeps = 0;
+    o1.refine = -1;  // take the plan from the cache entry just written
+    int rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb);
+    if (rc || !s1.converged) continue;
+    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    const int steps = ce ? ce->steps : s1.iterations;
+    // run 2: timed with the learned step count
+    HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipEventRecord(e0, s));
+    rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    if (rc || !s1.converged) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_sw = c.first;
+      best_pa = c.second;
+      best_steps = steps;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (best_sw == 0) {
+    g_stage_cache.put(p, tol, 0, 0, 0);
+    return fail(PTS_ERR_NOT_CONVERGED, "autotune: no wavefront plan converged");
+  }
+  g_stage_cache.put(p, tol, best_sw, best_pa, best_steps);
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->sweeps = best_sw;
+    st->refine = best_pa - 1;
+    st->iterations = best_steps;
+    st->solve_ms = best_ms;
+    st->schedule = PTS_SCHED_PIPELINE;
+  }
   return PTS_OK;
 }
 
@@ -845,7 +953,10 @@ int pts_assemble(const pts_problem* p, const double* U, const double* u0, double
   KProb kp = kprob(p);
   const int tilesx = (p->nx + 63) / 64, tilesy = (p->ny + kResRows - 1) / kResRows;
   dim3 grid((unsigned)(tilesx * tilesy), (unsigned)p->nt);
-  hipLaunchKernelGGL(k_residual, grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
+  if (p->bc == PTS_PERIODIC)
+    hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
+  else
+    hipLaunchKernelGGL(k_residual<0>, grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
   HIPCHK(hipGetLastError());
   if (res_inf) {
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, R, (size_t)p->nx * p->ny * p->nt,
@@ -890,6 +1001,16 @@ int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int
   if (stats)
     stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
+}
+
+int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* workspace,
+                 size_t workspace_bytes, const pts_options* opts, pts_stats* stats, pts_stream_t stream) {
+  int rc = validate(p);
+  if (!rc) rc = check_opts(opts);
+  if (!rc) rc = check_ws(p, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_autotune: NULL array");
+  return autotune_wave(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream);
 }
 
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob) {

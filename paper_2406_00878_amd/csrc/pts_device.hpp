@@ -35,6 +35,16 @@ struct Nb {
   double P, W, E, S, N;
 };
 
+// Element i of a level array through a 32-bit byte offset from the (wave-uniform) level
+// base, which lets the loads and stores use scalar base + vector offset addressing.
+// Levels hold at most 2^28 nodes, so the offset cannot wrap.
+__device__ __forceinline__ double ld(const double* __restrict__ base, unsigned i) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (i << 3));
+}
+__device__ __forceinline__ void st(double* __restrict__ base, unsigned i, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (i << 3)) = v;
+}
+
 __device__ __forceinline__ double mu_of(const KProb& p, double v) { return p.mu_a + p.mu_b * v * v; }
 
 __device__ __forceinline__ int wrap(int i, int n) {
@@ -55,20 +65,21 @@ __device__ __forceinline__ double node_value(const KProb& p, const double* __res
   return bd[2 * p.nx + p.ny + gy];
 }
 
-// Neighbours of the in-domain node (x, y). Periodic indices wrap by one step (no
-// integer division); Dirichlet neighbours outside the domain read the boundary data.
+// Neighbours of the in-domain node (x, y). BC = 1: periodic indices wrap by one step
+// (no integer division); BC = 0: Dirichlet neighbours outside the domain read the data.
+template <int BC>
 __device__ __forceinline__ Nb gather(const KProb& p, const double* __restrict__ un,
                                      const double* __restrict__ bd, int x, int y) {
   Nb u;
-  const size_t row = (size_t)y * p.nx;
-  u.P = un[row + x];
-  if (p.bc == 1) {
+  const unsigned row = (unsigned)y * (unsigned)p.nx;
+  u.P = ld(un, row + x);
+  if (BC == 1) {
     const int xw = x == 0 ? p.nx - 1 : x - 1, xe = x == p.nx - 1 ? 0 : x + 1;
     const int ys = y == 0 ? p.ny - 1 : y - 1, yn = y == p.ny - 1 ? 0 : y + 1;
-    u.W = un[row + xw];
-    u.E = un[row + xe];
-    u.S = un[(size_t)ys * p.nx + x];
-    u.N = un[(size_t)yn * p.nx + x];
+    u.W = ld(un, row + xw);
+    u.E = ld(un, row + xe);
+    u.S = ld(un, (unsigned)ys * (unsigned)p.nx + x);
+    u.N = ld(un, (unsigned)yn * (unsigned)p.nx + x);
   } else {
     u.W = node_value(p, un, bd, x - 1, y);
     u.E = node_value(p, un, bd, x + 1, y);
@@ -78,13 +89,9 @@ __device__ __forceinline__ Nb gather(const KProb& p, const double* __restrict__ 
   return u;
 }
 
-// F_P of Eq. (3).
-__device__ __forceinline__ double spatial_op(const KProb& p, const Nb& u) {
-  const double me = mu_of(p, 0.5 * (u.P + u.E)), mw = mu_of(p, 0.5 * (u.P + u.W));
-  const double mn = mu_of(p, 0.5 * (u.P + u.N)), ms = mu_of(p, 0.5 * (u.P + u.S));
-  const double conv = p.cf * (0.5 * p.ihx * (u.E * u.E - u.W * u.W) + 0.5 * p.ihy * (u.N * u.N - u.S * u.S));
-  const double visc = p.ihx2 * (me * (u.E - u.P) - mw * (u.P - u.W)) + p.ihy2 * (mn * (u.N - u.P) - ms * (u.P - u.S));
-  return conv - visc;
+__device__ __forceinline__ Nb gather(const KProb& p, const double* __restrict__ un,
+                                     const double* __restrict__ bd, int x, int y) {
+  return p.bc == 1 ? gather<1>(p, un, bd, x, y) : gather<0>(p, un, bd, x, y);
 }
 
 // Row of A = I + tau dF/du at node (x, y): C (self), W, E, S, N. Dirichlet boundary
@@ -93,31 +100,37 @@ struct Row5 {
   double C, W, E, S, N;
 };
 
-__device__ __forceinline__ Row5 jac_row(const KProb& p, const Nb& u, int x, int y) {
+// F_P of Eq. (3) and the row of A at P from one evaluation of the face viscosities.
+template <int BC>
+__device__ __forceinline__ double eval_point(const KProb& p, const Nb& u, int x, int y, Row5& r) {
   const double me = mu_of(p, 0.5 * (u.P + u.E)), mw = mu_of(p, 0.5 * (u.P + u.W));
   const double mn = mu_of(p, 0.5 * (u.P + u.N)), ms = mu_of(p, 0.5 * (u.P + u.S));
+  const double E2 = u.E * u.E, W2 = u.W * u.W, N2 = u.N * u.N, S2 = u.S * u.S, P2 = u.P * u.P;
+  const double conv = p.cf * (0.5 * p.ihx * (E2 - W2) + 0.5 * p.ihy * (N2 - S2));
+  const double visc = p.ihx2 * (me * (u.E - u.P) - mw * (u.P - u.W)) + p.ihy2 * (mn * (u.N - u.P) - ms * (u.P - u.S));
+  // d mu_face / d u_node = mu_b (u_P + u_X) / 2 for either node of the face
   const double hb = 0.5 * p.mu_b;
-  const double P2 = u.P * u.P;
-  const double qe = hb * (u.E * u.E - P2), qw = hb * (P2 - u.W * u.W);
-  const double qn = hb * (u.N * u.N - P2), qs = hb * (P2 - u.S * u.S);
-  const double dE = -(me + qe) * p.ihx2 + p.cf * u.E * p.ihx;
-  const double dW = -(mw - qw) * p.ihx2 - p.cf * u.W * p.ihx;
-  const double dN = -(mn + qn) * p.ihy2 + p.cf * u.N * p.ihy;
-  const double dS = -(ms - qs) * p.ihy2 - p.cf * u.S * p.ihy;
-  const double dP = (me + mw - qe + qw) * p.ihx2 + (mn + ms - qn + qs) * p.ihy2;
-  Row5 r;
-  r.C = 1.0 + p.dt * dP;
-  r.W = p.dt * dW;
-  r.E = p.dt * dE;
-  r.S = p.dt * dS;
-  r.N = p.dt * dN;
-  if (p.bc == 0) {
+  const double qe = hb * (E2 - P2), qw = hb * (P2 - W2);
+  const double qn = hb * (N2 - P2), qs = hb * (P2 - S2);
+  r.C = 1.0 + p.dt * ((me + mw - qe + qw) * p.ihx2 + (mn + ms - qn + qs) * p.ihy2);
+  r.W = p.dt * (-(mw - qw) * p.ihx2 - p.cf * u.W * p.ihx);
+  r.E = p.dt * (-(me + qe) * p.ihx2 + p.cf * u.E * p.ihx);
+  r.S = p.dt * (-(ms - qs) * p.ihy2 - p.cf * u.S * p.ihy);
+  r.N = p.dt * (-(mn + qn) * p.ihy2 + p.cf * u.N * p.ihy);
+  if (BC == 0) {
     if (x == 0) r.W = 0.0;
     if (x == p.nx - 1) r.E = 0.0;
     if (y == 0) r.S = 0.0;
     if (y == p.ny - 1) r.N = 0.0;
   }
-  return r;
+  return conv - visc;
+}
+
+// Gershgorin radius of row r of D^{-1} A (infinite when the diagonal is not positive).
+__device__ __forceinline__ double gersh(const Row5& r) {
+  double g = (fabs(r.W) + fabs(r.E) + fabs(r.S) + fabs(r.N)) / fabs(r.C);
+  if (!(r.C > 0.0) || g != g) g = __longlong_as_double(0x7ff0000000000000ll);
+  return g;
 }
 
 // ---------------------------------------------------------------- lane shifts

@@ -22,8 +22,10 @@ namespace pts {
 // Block of 64 x 4 threads sweeping kResRows rows of one level; grid.x = tiles of the
 // level, grid.y = level. Per-level maxima of |r| and of the Gershgorin radius go to
 // lvl_bits[2n] and lvl_bits[2n+1] (zeroed before the launch); k_level_max folds them.
+// R and coef may be NULL.
 constexpr int kResRows = 16;
 
+template <int BC>
 __global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restrict__ U,
                                                   const double* __restrict__ u0,
                                                   double* __restrict__ R, double* __restrict__ coef,
@@ -37,17 +39,17 @@ __global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restr
   const double* up = n == 0 ? u0 : U + (size_t)(n - 1) * ns;
   const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
   double rabs = 0.0, rho = 0.0;
+#pragma unroll 1
   for (int y = y0; y < y0 + kResRows; y += 4) {
     if (x < p.nx && y < p.ny) {
-      const Nb u = gather(p, un, bd, x, y);
+      const Nb u = gather<BC>(p, un, bd, x, y);
       const size_t i = (size_t)y * p.nx + x;
-      const double r = -(u.P - up[i] + p.dt * spatial_op(p, u));
-      R[(size_t)n * ns + i] = r;
+      Row5 a;
+      const double F = eval_point<BC>(p, u, x, y, a);
+      const double r = -(u.P - up[i] + p.dt * F);
+      if (R) R[(size_t)n * ns + i] = r;
       rabs = nanmax(rabs, fabs(r));
-      const Row5 a = jac_row(p, u, x, y);
-      double g = (fabs(a.W) + fabs(a.E) + fabs(a.S) + fabs(a.N)) / fabs(a.C);
-      if (!(a.C > 0.0) || g != g) g = __longlong_as_double(0x7ff0000000000000ll);
-      rho = nanmax(rho, g);
+      rho = nanmax(rho, gersh(a));
       if (coef) {
         double* c = coef + (size_t)n * 5 * ns + i;
         c[0] = a.C;
@@ -99,12 +101,13 @@ __global__ __launch_bounds__(256) void k_level_max(const unsigned long long* __r
 }
 
 // -------------------------------------------------------------- level solve
-// Geometry of the register-resident region: 64 lanes (x) by 8 waves x kRows (y).
-constexpr int kRows = 8;
-constexpr int kWaves = 8;
+// The register-resident region is 64 lanes (x) by kWaves waves of kRows rows (y).
+constexpr int kRows = 4;
+constexpr int kWaves = 16;
+constexpr int kThreads = 64 * kWaves;
 constexpr int kMaxSweeps = 64;  // longest Chebyshev pass one launch may run
 
-// Exchange of one register row set between neighbouring waves via LDS.
+// Exchange of the first and last row of every wave with the neighbouring waves via LDS.
 // buf holds 2 parities x kWaves x {bottom row, top row} x 64 lanes.
 template <typename T>
 struct YNb {
@@ -126,7 +129,8 @@ __device__ __forceinline__ YNb<T> y_exchange(const T (&v)[kRows], T* buf, int& p
 
 // Chebyshev weights for the Jacobi iteration matrix with spectral radius bound rho
 // (Golub-Varga semi-iteration): omega_1 = 1, omega_2 = 1/(1 - rho^2/2),
-// omega_{k+1} = 1/(1 - rho^2 omega_k / 4). One thread fills the table in LDS.
+// omega_{k+1} = 1/(1 - rho^2 omega_k / 4). One thread fills the table in LDS while the
+// other threads load the region.
 __device__ __forceinline__ void cheb_table(double* om, double rho, int sweeps) {
   if (threadIdx.x == 0) {
     const double r2 = rho * rho;
@@ -139,8 +143,10 @@ __device__ __forceinline__ void cheb_table(double* om, double rho, int sweeps) {
   }
 }
 
-// Register-resident state of one 64 x 64 region of a level: Jacobi-scaled rows of A_n
-// (T), the FP64 rows (only for FP32 inner arithmetic), right-hand side b and iterate X.
+__device__ __forceinline__ double clamp_rho(double rho) { return fmin(fmax(rho, 1e-3), 0.999); }
+
+// Register-resident state of one region of a level: Jacobi-scaled rows of A_n (T), the
+// FP64 rows (only for FP32 inner arithmetic), right-hand side b and iterate X.
 template <typename T>
 struct RegionSolve {
   static constexpr bool kF64 = sizeof(T) == sizeof(double);
@@ -193,8 +199,8 @@ struct RegionSolve {
         for (int k = 0; k < kRows; ++k) d[k] = T(bb[k]) * iC[k];
       }
       // Chebyshev on D^{-1} A x = D^{-1} d from x_0 = 0, x_1 = D^{-1} d; with the scaled
-      // rows, x_{s} = x_{s-2} + omega_s (d - x_{s-2} - offdiag(x_{s-1})). xa and xb hold
-      // the two most recent iterates and are updated in place, alternately.
+      // rows, x_s = x_{s-2} + omega_s (d - x_{s-2} - offdiag(x_{s-1})). xa and xb hold the
+      // two most recent iterates and are overwritten alternately.
       T xa[kRows], xb[kRows];
 #pragma unroll
       for (int k = 0; k < kRows; ++k) {
@@ -230,19 +236,44 @@ struct RegionSolve {
   }
 };
 
-__device__ __forceinline__ double clamp_rho(double rho) { return fmin(fmax(rho, 1e-3), 0.999); }
+// Region node of (lane, row) in domain coordinates; returns false for a Dirichlet node
+// outside the domain (inactive: zero row, zero data).
+template <int BC>
+__device__ __forceinline__ bool region_node(const KProb& p, int gx, int gy, int& x, int& y) {
+  if (BC == 1) {
+    // regions start at most kMaxHalo nodes before the domain and end at most 64 nodes
+    // after a tile origin, so one conditional step wraps when the level is >= 64 wide
+    if (p.nx >= 64 && p.ny >= 64) {
+      x = gx < 0 ? gx + p.nx : (gx >= p.nx ? gx - p.nx : gx);
+      y = gy < 0 ? gy + p.ny : (gy >= p.ny ? gy - p.ny : gy);
+    } else {
+      x = wrap(gx, p.nx);
+      y = wrap(gy, p.ny);
+    }
+    return true;
+  }
+  x = gx;
+  y = gy;
+  return gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
+}
+
+__device__ __forceinline__ bool in_tile(const Geo& g, const KProb& p, int lane, int row, int gx, int gy) {
+  const int lx = g.whole ? lane : lane - g.H;
+  const int ly = g.whole ? row : row - g.H;
+  return lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
+}
 
 // Bulk schedule, one launch per level (or per group of passes of a level):
 // du^n = A_n^{-1}(r^n + du^{n-1}). Xin (nullable) is the starting iterate of the level
 // from a previous launch; Xout receives the tile values.
-template <typename T>
-__global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const double* __restrict__ U,
-                                                     const double* __restrict__ R,
-                                                     const double* __restrict__ dUprev,
-                                                     const double* __restrict__ Xin,
-                                                     double* __restrict__ Xout,
-                                                     const double* __restrict__ rho_lvl, Geo g,
-                                                     int passes, int sweeps) {
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const double* __restrict__ U,
+                                                          const double* __restrict__ R,
+                                                          const double* __restrict__ dUprev,
+                                                          const double* __restrict__ Xin,
+                                                          double* __restrict__ Xout,
+                                                          const double* __restrict__ rho_lvl, Geo g,
+                                                          int passes, int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
   __shared__ double om[kMaxSweeps];
   const int lane = threadIdx.x & 63;
@@ -257,27 +288,19 @@ __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const doubl
   cheb_table(om, clamp_rho(rho_lvl[2 * n + 1]), sweeps);
 
   RegionSolve<T> rs;
-  int idx[kRows];
+  unsigned idx[kRows];
   const int gx = rx0 + lane;
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
-    const int gy = ry0 + wave * kRows + k;
-    int x = gx, y = gy;
-    bool act;
-    if (p.bc == 1) {
-      x = wrap(gx, p.nx);
-      y = wrap(gy, p.ny);
-      act = true;
-    } else {
-      act = gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
-    }
-    idx[k] = act ? y * p.nx + x : -1;
+    int x, y;
+    const bool act = region_node<BC>(p, gx, ry0 + wave * kRows + k, x, y);
+    idx[k] = act ? (unsigned)y * (unsigned)p.nx + x : ~0u;
     Row5 a;
     if (act) {
-      const Nb u = gather(p, un, bd, x, y);
-      a = jac_row(p, u, x, y);
-      rs.bb[k] = rn[idx[k]] + (dUprev ? dUprev[idx[k]] : 0.0);
-      rs.X[k] = Xin ? Xin[idx[k]] : 0.0;
+      Nb u = gather<BC>(p, un, bd, x, y);
+      (void)eval_point<BC>(p, u, x, y, a);
+      rs.bb[k] = ld(rn, idx[k]) + (dUprev ? ld(dUprev, idx[k]) : 0.0);
+      rs.X[k] = Xin ? ld(Xin, idx[k]) : 0.0;
     } else {
       a.C = 1.0;
       a.W = a.E = a.S = a.N = 0.0;
@@ -288,22 +311,12 @@ __global__ __launch_bounds__(512) void k_level_solve(KProb p, int n, const doubl
   }
   __syncthreads();  // omega table
   rs.run(passes, sweeps, Xin != nullptr, om, lds_raw, wave, lane);
-
-  const int lx = g.whole ? lane : lane - g.H;
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
-    const int ly = g.whole ? wave * kRows + k : wave * kRows + k - g.H;
-    const int gy = ry0 + wave * kRows + k;
-    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx >= 0 && gx < p.nx && gy >= 0 &&
-                        gy < p.ny && idx[k] >= 0;
-    if (inside) Xout[idx[k]] = rs.X[k];
+    const int row = wave * kRows + k;
+    if (idx[k] != ~0u && in_tile(g, p, lane, row, gx, ry0 + row)) st(Xout, idx[k], rs.X[k]);
   }
 }
-
-template __global__ void k_level_solve<double>(KProb, int, const double*, const double*, const double*,
-                                               const double*, double*, const double*, Geo, int, int);
-template __global__ void k_level_solve<float>(KProb, int, const double*, const double*, const double*,
-                                              const double*, double*, const double*, Geo, int, int);
 
 // ---------------------------------------------------------- wavefront schedule
 // Newton iteration j at level n needs the iterate U_j at levels n-1, n (written by
@@ -313,7 +326,8 @@ template __global__ void k_level_solve<float>(KProb, int, const double*, const d
 // touch the same level of the same buffer. Pair (j, n) forms r_j^n = -G^n(U_j) and the
 // rows of A_n(U_j) from U_j, solves A_n du_j^n = r_j^n + du_j^{n-1} on its tile, writes
 // du_j^n and U_{j+1}^n = U_j^n + du_j^n, and from the tile's U_{j+1} also the next
-// iterate's residual r_{j+1}^n and Gershgorin radius (reduced per level and per stage).
+// iterate's residual r_{j+1}^n and Gershgorin radius (reduced per level and per stage):
+// the radius of level n fixes the Chebyshev interval of stage j+1 at that level.
 struct WaveArgs {
   double* Ur[2];                  // iterate ring: stage j reads Ur[j & 1], writes Ur[(j + 1) & 1]
   double* dUr[2];                 // update ring: stage j writes dUr[j & 1]
@@ -324,9 +338,9 @@ struct WaveArgs {
   int stages;
 };
 
-template <typename T>
-__global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
-                                                    int sweeps) {
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
+                                                         int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
   __shared__ double om[kMaxSweeps];
   __shared__ double red[2][kWaves];
@@ -351,28 +365,20 @@ __global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, 
 
   RegionSolve<T> rs;
   double uc[kRows], upn[kRows];  // U_j^n and U_{j+1}^{n-1} at the region nodes
-  int idx[kRows];
+  unsigned idx[kRows];
   const int gx = rx0 + lane;
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
-    const int gy = ry0 + wave * kRows + k;
-    int x = gx, y = gy;
-    bool act;
-    if (p.bc == 1) {
-      x = wrap(gx, p.nx);
-      y = wrap(gy, p.ny);
-      act = true;
-    } else {
-      act = gx >= 0 && gx < p.nx && gy >= 0 && gy < p.ny;
-    }
-    idx[k] = act ? y * p.nx + x : -1;
+    int x, y;
+    const bool act = region_node<BC>(p, gx, ry0 + wave * kRows + k, x, y);
+    idx[k] = act ? (unsigned)y * (unsigned)p.nx + x : ~0u;
     Row5 r5;
     if (act) {
-      const Nb u = gather(p, un, bd, x, y);
-      r5 = jac_row(p, u, x, y);
-      const double prev = up[idx[k]];
-      const double dprev = dup ? dup[idx[k]] : 0.0;
-      rs.bb[k] = -(u.P - prev + p.dt * spatial_op(p, u)) + dprev;
+      const Nb u = gather<BC>(p, un, bd, x, y);
+      const double F = eval_point<BC>(p, u, x, y, r5);
+      const double prev = ld(up, idx[k]);
+      const double dprev = dup ? ld(dup, idx[k]) : 0.0;
+      rs.bb[k] = -(u.P - prev + p.dt * F) + dprev;
       uc[k] = u.P;
       upn[k] = prev + dprev;
     } else {
@@ -395,7 +401,6 @@ __global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, 
   for (int k = 0; k < kRows; ++k) unew[k] = uc[k] + rs.X[k];
   int par = 0;
   const YNb<double> yn = y_exchange<double>(unew, lds_raw, par, wave, lane);
-  const int lx = g.whole ? lane : lane - g.H;
   double rmax = 0.0, gmax = 0.0;
   double* dUo = a.dUr[j & 1] + (size_t)n * ns;
   double* Uo = a.Ur[(j + 1) & 1] + (size_t)n * ns;
@@ -407,26 +412,23 @@ __global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, 
     u.N = k == kRows - 1 ? yn.nM : unew[k + 1];
     u.W = lane_from_left(unew[k]);
     u.E = lane_from_right(unew[k]);
-    const int ly = g.whole ? wave * kRows + k : wave * kRows + k - g.H;
-    const int gy = ry0 + wave * kRows + k;
-    const bool inside = lx >= 0 && lx < g.TX && ly >= 0 && ly < g.TY && gx >= 0 && gx < p.nx && gy >= 0 &&
-                        gy < p.ny && idx[k] >= 0;
-    if (inside) {
+    const int row = wave * kRows + k;
+    const int gy = ry0 + row;
+    if (idx[k] != ~0u && in_tile(g, p, lane, row, gx, gy)) {
       const int x = gx, y = gy;
-      if (p.bc == 0) {  // Dirichlet neighbours outside the domain are data
+      if (BC == 0) {  // Dirichlet neighbours outside the domain are data
         if (x == 0) u.W = node_value(p, un, bd, -1, y);
         if (x == p.nx - 1) u.E = node_value(p, un, bd, p.nx, y);
         if (y == 0) u.S = node_value(p, un, bd, x, -1);
         if (y == p.ny - 1) u.N = node_value(p, un, bd, x, p.ny);
       }
-      const double r = -(u.P - upn[k] + p.dt * spatial_op(p, u));
-      const Row5 q = jac_row(p, u, x, y);
-      double gr = (fabs(q.W) + fabs(q.E) + fabs(q.S) + fabs(q.N)) / fabs(q.C);
-      if (!(q.C > 0.0) || gr != gr) gr = __longlong_as_double(0x7ff0000000000000ll);
+      Row5 q;
+      const double F = eval_point<BC>(p, u, x, y, q);
+      const double r = -(u.P - upn[k] + p.dt * F);
       rmax = nanmax(rmax, fabs(r));
-      gmax = nanmax(gmax, gr);
-      dUo[idx[k]] = rs.X[k];
-      Uo[idx[k]] = unew[k];
+      gmax = nanmax(gmax, gersh(q));
+      st(dUo, idx[k], rs.X[k]);
+      st(Uo, idx[k], unew[k]);
     }
   }
   rmax = wave_max(rmax);
@@ -446,9 +448,6 @@ __global__ __launch_bounds__(512) void k_level_wave(KProb p, WaveArgs a, Geo g, 
     atomic_max_nonneg(a.rho_st + (size_t)(j + 1) * p.nt + n, q);
   }
 }
-
-template __global__ void k_level_wave<double>(KProb, WaveArgs, Geo, int, int, int);
-template __global__ void k_level_wave<float>(KProb, WaveArgs, Geo, int, int, int);
 
 // ------------------------------------------------------------------- update
 __global__ __launch_bounds__(256) void k_update(size_t count, double* __restrict__ U,
