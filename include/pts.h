@@ -100,8 +100,13 @@ typedef struct pts_stats {
   int32_t refine;                /* refinement passes per solve (last step)    */
   int32_t schedule;              /* schedule used                              */
   int32_t launches;              /* kernel launches + graph replays issued     */
-  int32_t reserved;
-  double res_inf[PTS_MAX_HIST];  /* ||R(U_k)||_inf, k = 0..iterations          */
+  int32_t slab;                  /* levels solved all-at-once together: nt, or
+                                    the slab length after plain Newton over the
+                                    whole domain diverged (see pts_solve)       */
+  int32_t hist;                  /* valid entries of the histories below (the
+                                    last slab's steps + 1)                      */
+  int32_t pad;
+  double res_inf[PTS_MAX_HIST];  /* ||R(U_k)||_inf, k = 0..hist-1               */
   double upd_rms[PTS_MAX_HIST];  /* Section 8.1 RMS update norm, k = 1..       */
   double rho_max[PTS_MAX_HIST];  /* max Gershgorin radius of D^-1 A_n at U_k   */
   double solve_ms;               /* wall time inside pts_solve (host clock)    */
@@ -145,6 +150,11 @@ int pts_init_plain(const pts_problem* p, double* U, const double* u0, pts_stream
 /* Newton iteration from the iterate in U until ||R(U)||_inf <= tol (tau-scaled,
    absolute, all levels) or max_iter steps. U is overwritten with the result;
    on PTS_ERR_NOT_CONVERGED it holds the last iterate so a later call resumes.
+   Safeguard: if the Newton iteration over the whole domain diverges (non-finite or
+   exploding residual), the levels are solved in consecutive slabs of L levels, each
+   all-at-once from the plain iterate of its own initial level, L halved until every
+   slab converges; the root is unchanged. The working L is remembered per problem
+   and reported in stats->slab; iterations then counts the steps of all slabs.
    Synchronises the stream (once per Newton step, or per launch when
    pipelined). */
 int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int max_iter,

@@ -114,10 +114,10 @@ def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_gr
 
 def _stats_dict(st: pts_stats) -> dict:
     k = st.iterations
-    n = min(k + 1, _lib.PTS_MAX_HIST)
+    n = min(st.hist if st.hist > 0 else k + 1, _lib.PTS_MAX_HIST)
     return {
         "iterations": k, "converged": bool(st.converged), "window": st.window, "sweeps": st.sweeps,
-        "refine": st.refine, "schedule": st.schedule, "launches": st.launches,
+        "refine": st.refine, "schedule": st.schedule, "launches": st.launches, "slab": st.slab,
         "res_inf": list(st.res_inf[:n]), "upd_rms": list(st.upd_rms[1:n]),
         "rho_max": list(st.rho_max[:n]), "solve_ms": st.solve_ms,
         "prof_ms": list(st.prof_ms), "prof_count": list(st.prof_count),
@@ -194,7 +194,8 @@ def autotune(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", 
     st = pts_stats()
     _check(_lib_checked().pts_autotune(C.byref(p), _ptr(U), _ptr(u0), float(tol), int(max_iter), _ptr(ws),
                                        ws.numel(), C.byref(o), C.byref(st), _stream(stream)))
-    return {"sweeps": st.sweeps, "passes": st.refine + 1, "newton_steps": st.iterations, "ms": st.solve_ms}
+    return {"sweeps": st.sweeps, "passes": st.refine + 1, "newton_steps": st.iterations, "ms": st.solve_ms,
+            "slab": st.slab}
 
 
 def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,

@@ -36,7 +36,7 @@ class pts_options(C.Structure):
 class pts_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("window", C.c_int32),
                 ("sweeps", C.c_int32), ("refine", C.c_int32), ("schedule", C.c_int32),
-                ("launches", C.c_int32), ("reserved", C.c_int32),
+                ("launches", C.c_int32), ("slab", C.c_int32), ("hist", C.c_int32), ("pad", C.c_int32),
                 ("res_inf", C.c_double * PTS_MAX_HIST), ("upd_rms", C.c_double * PTS_MAX_HIST),
                 ("rho_max", C.c_double * PTS_MAX_HIST), ("solve_ms", C.c_double),
                 ("prof_ms", C.c_double * 4), ("prof_count", C.c_int32 * 4),

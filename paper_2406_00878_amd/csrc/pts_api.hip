@@ -899,8 +899,123 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
     st->iterations = best_steps;
     st->solve_ms = best_ms;
     st->schedule = PTS_SCHED_PIPELINE;
+    st->slab = p->nt;
   }
   return PTS_OK;
+}
+
+
+// One all-at-once Newton solve of `p` with the requested schedule (wavefront by default,
+// bulk when the inner plan does not fit the wavefront kernel).
+int solve_core(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
+               const pts_options* o, pts_stats* st, hipStream_t s) {
+  const int sched = o ? o->schedule : PTS_SCHED_AUTO;
+  bool fallback = true;
+  int rc = PTS_OK;
+  if (sched != PTS_SCHED_BULK) {
+    rc = solve_wave(p, U, u0, tol, max_iter, ws, o, st, s, &fallback);
+    if (fallback && sched == PTS_SCHED_PIPELINE)
+      rc = fail(PTS_ERR_INVALID_ARG, "the inner solve does not fit the wavefront schedule");
+  }
+  if (fallback && sched != PTS_SCHED_PIPELINE) {
+    if (st) std::memset(st, 0, sizeof *st);
+    rc = solve_bulk(p, U, u0, tol, max_iter, ws, o, st, s, false);
+  }
+  return rc;
+}
+
+// Divergence of plain Newton: a non-finite or exploding residual, or a block that lost
+// diagonal dominance on the way.
+bool diverged(int rc, const pts_stats& st) {
+  if (rc == PTS_ERR_NONFINITE || rc == PTS_ERR_SINGULAR) return true;
+  if (rc != PTS_ERR_NOT_CONVERGED) return false;
+  const int n = std::min(st.iterations, PTS_MAX_HIST - 1);
+  double mx = 0.0;
+  for (int k = 0; k <= n; ++k) mx = std::max(mx, st.res_inf[k]);
+  return !(mx <= 100.0 * st.res_inf[0]);
+}
+
+// Newton slab length that worked last time per problem signature (levels solved
+// all-at-once together; nt = the whole space-time domain).
+struct SlabCache {
+  struct E {
+    int nx, ny, nt, kind, bc, prec;
+    double dt, mu_a, mu_b;
+    int slab;
+  };
+  std::vector<E> v;
+  int get(const pts_problem* p) const {
+    for (auto& e : v)
+      if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
+          e.prec == p->precision && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b)
+        return e.slab;
+    return p->nt;
+  }
+  void put(const pts_problem* p, int slab) {
+    for (auto& e : v)
+      if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
+          e.prec == p->precision && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b) {
+        e.slab = slab;
+        return;
+      }
+    if (v.size() > 64) v.clear();
+    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, p->dt, p->mu_a, p->mu_b, slab});
+  }
+};
+thread_local SlabCache g_slab_cache;
+
+// All-at-once Newton over the whole space-time domain; if it diverges from the given
+// iterate, the levels are solved in consecutive slabs, each all-at-once from the plain
+// iterate of its own initial level, halving the slab until every slab converges (the
+// root is the same: each slab's first level takes the previous slab's converged last
+// level as u^{n-1}).
+int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
+                const pts_options* o, pts_stats* st, hipStream_t s) {
+  pts_stats local;
+  pts_stats* sp = st ? st : &local;
+  std::memset(sp, 0, sizeof *sp);
+  int L = g_slab_cache.get(p);
+  bool reinit = false;
+  if (L >= p->nt) {
+    int rc = solve_core(p, U, u0, tol, max_iter, ws, o, sp, s);
+    sp->slab = p->nt;
+    sp->hist = std::min(sp->iterations + 1, PTS_MAX_HIST);
+    if (!diverged(rc, *sp)) return rc;
+    L = std::max(1, p->nt / 2);
+    reinit = true;
+  }
+  const size_t ns = (size_t)p->nx * p->ny;
+  const int bstride = 2 * (p->nx + p->ny);
+  int total_iters = 0, rc = PTS_OK;
+  for (int s0 = 0; s0 < p->nt;) {
+    pts_problem sub = *p;
+    sub.nt = std::min(L, p->nt - s0);
+    if (p->bdata) sub.bdata = p->bdata + (size_t)s0 * bstride;
+    double* Us = U + (size_t)s0 * ns;
+    const double* u0s = s0 == 0 ? u0 : U + (size_t)(s0 - 1) * ns;
+    if (reinit) {
+      const size_t total = ns * sub.nt;
+      const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+      hipLaunchKernelGGL(k_broadcast, dim3(blocks), dim3(256), 0, s, ns, sub.nt, Us, u0s);
+      HIPCHK(hipGetLastError());
+    }
+    std::memset(sp, 0, sizeof *sp);
+    rc = solve_core(&sub, Us, u0s, tol, max_iter, ws, o, sp, s);
+    if (diverged(rc, *sp)) {
+      if (L == 1) return rc;
+      L = std::max(1, L / 2);
+      reinit = true;
+      continue;  // redo this slab, shorter, from the plain iterate
+    }
+    total_iters += sp->iterations;
+    sp->hist = std::min(sp->iterations + 1, PTS_MAX_HIST);
+    if (rc) return rc;
+    s0 += sub.nt;
+  }
+  g_slab_cache.put(p, L);
+  sp->iterations = total_iters;
+  sp->slab = L;
+  return rc;
 }
 
 }  // namespace
@@ -987,17 +1102,7 @@ int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_solve: NULL array");
   if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
   const auto t0 = std::chrono::steady_clock::now();
-  const int sched = opts ? opts->schedule : PTS_SCHED_AUTO;
-  bool fallback = true;
-  if (sched != PTS_SCHED_BULK) {
-    rc = solve_wave(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream, &fallback);
-    if (fallback && sched == PTS_SCHED_PIPELINE)
-      rc = fail(PTS_ERR_INVALID_ARG, "the inner solve does not fit the wavefront schedule");
-  }
-  if (fallback && sched != PTS_SCHED_PIPELINE) {
-    if (stats) std::memset(stats, 0, sizeof *stats);
-    rc = solve_bulk(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream, false);
-  }
+  rc = solve_slabs(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream);
   if (stats)
     stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return rc;
@@ -1010,7 +1115,43 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
   if (!rc) rc = check_ws(p, workspace, workspace_bytes);
   if (rc) return rc;
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_autotune: NULL array");
-  return autotune_wave(p, U, u0, tol, max_iter, workspace, opts, stats, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t ns = (size_t)p->nx * p->ny;
+  const size_t bytes = ns * p->nt * 8;
+  // U is kept in a temporary device copy while trial solves overwrite it (the only
+  // allocation the library makes, freed before returning)
+  double* backup = nullptr;
+  HIPCHK(hipMalloc((void**)&backup, bytes));
+  struct Free {
+    double* b;
+    ~Free() { (void)hipFree(b); }
+  } guard{backup};
+  HIPCHK(hipMemcpyAsync(backup, U, bytes, hipMemcpyDeviceToDevice, s));
+  // slab length first: one safeguarded solve from the given iterate
+  if (g_slab_cache.get(p) >= p->nt) {
+    pts_stats st0;
+    rc = solve_slabs(p, U, u0, tol, max_iter, workspace, opts, &st0, s);
+    HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (rc) return rc;
+  }
+  const int L = g_slab_cache.get(p);
+  if (L >= p->nt) {
+    rc = autotune_wave(p, U, u0, tol, max_iter, workspace, opts, stats, s);
+  } else {
+    // tune the inner plan on the first slab, from its plain iterate
+    pts_problem sub = *p;
+    sub.nt = L;
+    const size_t total = ns * L;
+    const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_broadcast, dim3(blocks), dim3(256), 0, s, ns, L, U, u0);
+    HIPCHK(hipGetLastError());
+    rc = autotune_wave(&sub, U, u0, tol, max_iter, workspace, opts, stats, s);
+    if (stats) stats->slab = L;
+  }
+  HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return rc;
 }
 
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob) {

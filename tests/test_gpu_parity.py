@@ -284,3 +284,22 @@ def test_autotune_restores_iterate_and_tuned_solve_matches_oracle():
     assert st["converged"] and st["sweeps"] == tuned["sweeps"]
     Us, _ = sequential.solve_sequential(p)
     assert relerr(host(U), Us) <= 1e-10
+
+
+# --------------------------------------------------- 512^2 x 1024 disc, mixed precision
+
+def test_full_size_burgers512_disc_mixed_sampled():
+    """Periodic Burgers 512^2 x 1024 levels, nu = 1e-3, discontinuous disc initial condition,
+    FP32 inner solves with FP64 residuals. Plain Newton over the whole domain diverges here;
+    the safeguard solves slabs of levels all-at-once. Checked against the sequential oracle on
+    the first levels and by the oracle's residual at sampled levels."""
+    p = W.burgers512_disc()
+    U, st = gpu_solve(p, tol=1e-12, precision="mixed")
+    assert st["converged"] and st["slab"] < p.nt
+    L = 3
+    Us, _ = sequential.solve_sequential(p, levels=L)
+    assert relerr(U[:L], Us) <= 1e-8
+    from oracle.discretization import level_residual
+    for n in (1, 127, 128, 129, 130, 700, 1024):
+        prev = p.u0 if n == 1 else U[n - 2]
+        assert np.max(np.abs(level_residual(U[n - 1], prev, p))) <= 1e-11
