@@ -73,9 +73,11 @@ typedef struct pts_problem {
 
 /* Solver options. Zero-initialise for defaults. */
 typedef struct pts_options {
-  int32_t window;    /* Theorem-1 window W (levels decoupled together); 0 = auto
-                        (largest W allowed by the Section 7 condition bound and
-                        the autotuner), 1 = the block inverse of Eq. (7)       */
+  int32_t window;    /* Theorem-1 window W <= 64 (levels decoupled together, Eq. (8)
+                        inside each window; runs in the bulk schedule). 0 or 1 =
+                        the block inverse of Eq. (7), the stable and cheapest form;
+                        pts_window_bound gives the largest W the Section 7
+                        condition estimate allows                               */
   int32_t schedule;  /* PTS_SCHED_*: BULK = one Newton iteration after another,
                         replayed as a HIP graph; PIPELINE = all iterations in one
                         persistent launch, overlapped as a wavefront           */

@@ -84,9 +84,10 @@ KProb kprob(const pts_problem* p) {
 
 // Workspace layout of one instance.
 constexpr int kMaxStages = 16;  // Newton iterations overlapped by one wavefront sequence
+constexpr int kMaxWindow = 64;  // longest Theorem-1 window
 
 struct Layout {
-  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, total;
+  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, win, total;
 };
 
 Layout layout(const pts_problem* p) {
@@ -115,6 +116,8 @@ Layout layout(const pts_problem* p) {
   o = align_up(o + (size_t)(kMaxStages + 1) * p->nt * 8);
   L.res_st = o;
   o = align_up(o + (kMaxStages + 1) * 8);
+  L.win = o;  // Theorem-1 windows: right-hand sides of a window plus two chain vectors
+  o = align_up(o + (size_t)(std::min(kMaxWindow, p->nt) + 2) * ns * 8);
   L.total = o;
   return L;
 }
@@ -247,11 +250,75 @@ int launch_chain(const pts_problem* p, const KProb& kp, const double* U, const d
       const bool per = p->bc == PTS_PERIODIC;
       auto kern = pl.fp32 ? (per ? k_level_solve<float, 1> : k_level_solve<float, 0>)
                           : (per ? k_level_solve<double, 1> : k_level_solve<double, 0>);
-      hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, kp, n, U, R, prev, xin, xo, rho, g, pl.packs[l],
-                         pl.sweeps);
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, kp, n, U, R + (size_t)n * ns, prev, xin, xo, rho,
+                         g, pl.packs[l], pl.sweeps);
       prof_end(pr, s, 8.0 * (double)ns * (3 + (prev ? 1 : 0) + (xin ? 1 : 0)));
       xin = xo;
       ++*launches;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+
+// Theorem 1 inside windows of W levels (Section 4, Eq. (8); recursion of Section 5):
+// level w of the window [w0, w0+W) solves P_w du^w = rt^w with P_w = A_{w0} ... A_w,
+// rt^{w0} = r^{w0} + du^{w0-1} (the -I block of Eq. (6) carried into the window) and
+// rt^w = rt^{w-1} + A_{w0}(A_{w0+1}(... A_{w-1} r^w)). P_w is applied through its factors:
+// du^w = A_w^{-1}(... A_{w0}^{-1} rt^w). Every window's levels are decoupled from each
+// other; W = 1 is the block inverse of Eq. (7).
+int launch_windows(const pts_problem* p, const KProb& kp, const double* U, const double* R, double* dU,
+                   double* Xs, const double* rho, const Plan& pl, const Geo& g, int W, char* ws, const Layout& L,
+                   hipStream_t s, int* launches) {
+  const size_t ns = (size_t)p->nx * p->ny;
+  const int nb = tiles(p, g);
+  double* rt = (double*)(ws + L.win);
+  double* t1 = rt + (size_t)std::min(kMaxWindow, p->nt) * ns;
+  double* t2 = t1 + ns;
+  const unsigned ablocks = (unsigned)((ns + 255) / 256);
+  const unsigned cblocks = (unsigned)std::min<size_t>((ns + 255) / 256, 4096);
+  const bool per = p->bc == PTS_PERIODIC;
+  auto apply = per ? k_apply<1> : k_apply<0>;
+  auto solve = pl.fp32 ? (per ? k_level_solve<float, 1> : k_level_solve<float, 0>)
+                       : (per ? k_level_solve<double, 1> : k_level_solve<double, 0>);
+  const int nl = (int)pl.packs.size();
+  for (int w0 = 0; w0 < p->nt; w0 += W) {
+    const int Wc = std::min(W, p->nt - w0);
+    // rt^{w0}
+    hipLaunchKernelGGL(k_add, dim3(cblocks), dim3(256), 0, s, ns, R + (size_t)w0 * ns,
+                       w0 > 0 ? dU + (size_t)(w0 - 1) * ns : nullptr, rt);
+    ++*launches;
+    for (int k = 1; k < Wc; ++k) {
+      // v = A_{w0} ... A_{w0+k-1} r^{w0+k}, innermost factor first
+      const double* src = R + (size_t)(w0 + k) * ns;
+      double* dst = t1;
+      for (int m = w0 + k - 1; m >= w0; --m) {
+        hipLaunchKernelGGL(apply, dim3(ablocks), dim3(256), 0, s, kp, m, U, src, dst);
+        ++*launches;
+        src = dst;
+        dst = dst == t1 ? t2 : t1;
+      }
+      hipLaunchKernelGGL(k_add, dim3(cblocks), dim3(256), 0, s, ns, rt + (size_t)(k - 1) * ns, src,
+                         rt + (size_t)k * ns);
+      ++*launches;
+    }
+    for (int k = 0; k < Wc; ++k) {
+      // du^{w0+k} = A_{w0+k}^{-1} ... A_{w0}^{-1} rt^{w0+k}
+      const double* y = rt + (size_t)k * ns;
+      for (int i = w0; i <= w0 + k; ++i) {
+        double* out = i == w0 + k ? dU + (size_t)(w0 + k) * ns : (y == t1 ? t2 : t1);
+        const double* xin = nullptr;
+        for (int l = 0; l < nl; ++l) {
+          // restarted passes ping-pong through the scratch level, the last one into `out`
+          double* xo = ((nl - 1 - l) % 2 == 0) ? out : Xs;
+          hipLaunchKernelGGL(solve, dim3(nb), dim3(kThreads), 0, s, kp, i, U, y, nullptr, xin, xo, rho, g,
+                             pl.packs[l], pl.sweeps);
+          ++*launches;
+          xin = xo;
+        }
+        y = out;
+      }
     }
   }
   HIPCHK(hipGetLastError());
@@ -330,6 +397,7 @@ struct Instance {
   double* rms;
 
   void bind(const pts_problem* pp, void* w) {
+    wsb = (char*)w;
     p = pp;
     kp = kprob(pp);
     L = layout(pp);
@@ -354,8 +422,12 @@ struct Instance {
     return rc;
   }
 
+  int window = 1;
+  char* wsb = nullptr;
+
   int step_body(double* U, const Plan& pl, hipStream_t s, int* launches) {
-    int rc = launch_chain(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, s, launches, prof);
+    int rc = window > 1 ? launch_windows(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, window, wsb, L, s, launches)
+                        : launch_chain(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, s, launches, prof);
     if (rc) return rc;
     const size_t count = (size_t)p->nx * p->ny * p->nt;
     prof_begin(prof, 2, s);
@@ -385,7 +457,9 @@ int check_ws(const pts_problem* p, void* ws, size_t bytes) {
 
 int check_opts(const pts_options* o) {
   if (!o) return PTS_OK;
-  if (o->window > 1) return fail(PTS_ERR_INVALID_ARG, "window %d: only window 1 is available", o->window);
+  if (o->window > kMaxWindow) return fail(PTS_ERR_INVALID_ARG, "window %d exceeds %d", o->window, kMaxWindow);
+  if (o->window > 1 && o->schedule == PTS_SCHED_PIPELINE)
+    return fail(PTS_ERR_INVALID_ARG, "Theorem-1 windows run in the bulk schedule");
   if (o->window < 0 || o->sweeps < 0 || o->lin_tol < 0)
     return fail(PTS_ERR_INVALID_ARG, "negative option");
   if (o->schedule != PTS_SCHED_AUTO && o->schedule != PTS_SCHED_BULK && o->schedule != PTS_SCHED_PIPELINE)
@@ -433,6 +507,7 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
                const pts_options* o, pts_stats* st, hipStream_t s, bool single_step) {
   Instance in;
   in.bind(p, ws);
+  in.window = (o && o->window > 1) ? std::min(o->window, std::min(kMaxWindow, p->nt)) : 1;
   Prof prof;
   const bool profiling = o && o->profile;
   if (profiling) in.prof = &prof;
@@ -492,7 +567,7 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
     if (st) {
       st->sweeps = pl.sweeps;
       st->refine = pl.passes - 1;
-      st->window = 1;
+      st->window = in.window;
       st->schedule = PTS_SCHED_BULK;
     }
     if (use_graph) {
@@ -909,7 +984,7 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
 // bulk when the inner plan does not fit the wavefront kernel).
 int solve_core(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
                const pts_options* o, pts_stats* st, hipStream_t s) {
-  const int sched = o ? o->schedule : PTS_SCHED_AUTO;
+  const int sched = (o && o->window > 1) ? PTS_SCHED_BULK : (o ? o->schedule : PTS_SCHED_AUTO);
   bool fallback = true;
   int rc = PTS_OK;
   if (sched != PTS_SCHED_BULK) {

@@ -264,11 +264,12 @@ __device__ __forceinline__ bool in_tile(const Geo& g, const KProb& p, int lane, 
 }
 
 // Bulk schedule, one launch per level (or per group of passes of a level):
-// du^n = A_n^{-1}(r^n + du^{n-1}). Xin (nullable) is the starting iterate of the level
-// from a previous launch; Xout receives the tile values.
+// X = A_n^{-1}(rn + dUprev), rn the level's right-hand side (r^n for the block inverse of
+// Eq. (7), or a Theorem-1 chain vector), dUprev (nullable) du^{n-1}. Xin (nullable) is the
+// starting iterate from a previous launch; Xout receives the tile values.
 template <typename T, int BC>
 __global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const double* __restrict__ U,
-                                                          const double* __restrict__ R,
+                                                          const double* __restrict__ rn,
                                                           const double* __restrict__ dUprev,
                                                           const double* __restrict__ Xin,
                                                           double* __restrict__ Xout,
@@ -283,7 +284,6 @@ __global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const 
   const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
   const size_t ns = (size_t)p.nx * p.ny;
   const double* un = U + (size_t)n * ns;
-  const double* rn = R + (size_t)n * ns;
   const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
   cheb_table(om, clamp_rho(rho_lvl[2 * n + 1]), sweeps);
 
@@ -447,6 +447,33 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
     atomic_max_nonneg(a.res_st + j + 1, r);
     atomic_max_nonneg(a.rho_st + (size_t)(j + 1) * p.nt + n, q);
   }
+}
+
+// ------------------------------------------------------------ Theorem 1 windows
+// y = A_m x at every node of level m (rows from U_m, Eq. (6)); products P^{w-1} r^w of
+// the Section 5 recursion are chains of these. One thread per node.
+template <int BC>
+__global__ __launch_bounds__(256) void k_apply(KProb p, int m, const double* __restrict__ U,
+                                               const double* __restrict__ x, double* __restrict__ y) {
+  const unsigned i = blockIdx.x * 256u + threadIdx.x;
+  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
+  if (i >= ns) return;
+  const int xi = (int)(i % (unsigned)p.nx), yi = (int)(i / (unsigned)p.nx);
+  const double* um = U + (size_t)m * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)m * 2 * (p.nx + p.ny) : nullptr;
+  const Nb u = gather<BC>(p, um, bd, xi, yi);
+  Row5 a;
+  (void)eval_point<BC>(p, u, xi, yi, a);
+  // neighbour values of x (periodic wrap; absent Dirichlet columns have zero rows)
+  const Nb v = gather<BC>(p, x, nullptr, xi, yi);
+  y[i] = a.C * v.P + a.W * v.W + a.E * v.E + a.S * v.S + a.N * v.N;
+}
+
+// z = x + y (n values); y may be NULL (copy).
+__global__ __launch_bounds__(256) void k_add(size_t n, const double* __restrict__ x, const double* __restrict__ y,
+                                             double* __restrict__ z) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    z[i] = x[i] + (y ? y[i] : 0.0);
 }
 
 // ------------------------------------------------------------------- update

@@ -303,3 +303,43 @@ def test_full_size_burgers512_disc_mixed_sampled():
     for n in (1, 127, 128, 129, 130, 700, 1024):
         prev = p.u0 if n == 1 else U[n - 2]
         assert np.max(np.abs(level_residual(U[n - 1], prev, p))) <= 1e-11
+
+
+# ------------------------------------------------------------------ Theorem-1 windows
+
+@pytest.mark.parametrize("case", ["heat_paper_mms", "burgers_periodic_ragged", "heat_dirichlet_bdata"])
+def test_newton_step_theorem1_full_window_matches_oracle(case):
+    """Theorem 1 with one window over all levels (the paper's fully decoupled form,
+    Eq. (8)) gives the Newton step of Eq. (6) when the products are well conditioned."""
+    rng = np.random.default_rng(17)
+    p = _rand_problem(case, rng)
+    p.nt = 5
+    if p.bdata is not None:
+        p.bdata = p.bdata[:5] if p.bdata.shape[0] >= 5 else rng.uniform(-1, 1, (5, p.bdata.shape[1]))
+    U = p.plain_iterate() + 0.01 * rng.standard_normal((p.nt, p.ny, p.nx))
+    dU_direct, _ = allatonce.newton_step_direct(U, p)
+    dU_thm1, _ = allatonce.newton_step_theorem1(U, p, window=None)
+    assert np.max(np.abs(dU_thm1 - dU_direct)) <= 1e-9 * np.max(np.abs(dU_direct))
+    Ud = dev(U)
+    bd = dev(p.bdata) if p.bdata is not None else None
+    st = P.newton_step(p, Ud, dev(p.u0), bdata=bd, lin_tol=1e-14, window=5)
+    assert st["window"] == 5
+    got = host(Ud) - U
+    assert np.max(np.abs(got - dU_direct)) <= 1e-8 * np.max(np.abs(dU_direct))
+
+
+@pytest.mark.parametrize("which", ["heat32", "burgers_periodic"])
+def test_solve_with_condition_bounded_window(which):
+    """Windows chosen by the Section 7 estimate (Eq. (cond)) reach the same root."""
+    if which == "heat32":
+        p = W.heat32()
+        mu_max = 2.0
+    else:
+        p = W.burgers_periodic(80, 40, 5e-4, 0.01, W.fourier_u0_periodic(80, 2406002))
+        mu_max = 0.01
+    w = P.window_bound(p.hx, mu_max, tau=p.dt, c=1.0, eps=1e-16, wmax=min(64, p.nt))
+    assert w >= 2
+    Us, _ = sequential.solve_sequential(p)
+    U, st = gpu_solve(p, tol=1e-12, window=w, schedule="bulk")
+    assert st["converged"] and st["window"] == w
+    assert relerr(U, Us) <= 1e-10
