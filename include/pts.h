@@ -89,6 +89,10 @@ typedef struct pts_options {
   int32_t stages;    /* PIPELINE only: Newton iterations per launch, 0 = auto  */
   int32_t profile;   /* 1 = time every kernel with HIP events on `stream` (BULK
                         schedule without graph); totals land in pts_stats      */
+  int32_t cache_tag; /* solves with different tags keep separate autotuned plans
+                        and Newton step counts for the same problem signature
+                        (e.g. 1 for starts from a learned initial iterate, which
+                        need fewer steps than the plain one); 0 = default      */
 } pts_options;
 
 #define PTS_MAX_HIST 64

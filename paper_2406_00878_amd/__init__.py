@@ -99,7 +99,7 @@ def workspace(prob, precision: str = "fp64", device="cuda") -> torch.Tensor:
 
 
 def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_graph=True, stages=0,
-             profile=False):
+             profile=False, cache_tag=0):
     o = pts_options()
     o.window = int(window)
     o.schedule = {"auto": PTS_SCHED_AUTO, "bulk": PTS_SCHED_BULK, "pipeline": PTS_SCHED_PIPELINE}[schedule]
@@ -109,6 +109,7 @@ def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_gr
     o.use_graph = 1 if use_graph else 0
     o.stages = int(stages)
     o.profile = 1 if profile else 0
+    o.cache_tag = int(cache_tag)
     return o
 
 
@@ -176,6 +177,9 @@ def solve(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", ws=
                                   ws.numel(), C.byref(o), C.byref(st), _stream(stream))
     out = _stats_dict(st)
     out["rc"] = rc
+    # Newton steps after which |R| <= tol was first reached (the pipelined schedule may
+    # apply a few more in the same launch sequence)
+    out["needed"] = next((k for k, r in enumerate(out["res_inf"]) if r <= tol), None)
     if rc != 0:
         out["error"] = _lib_checked().pts_last_error().decode()
         if raise_on_error:

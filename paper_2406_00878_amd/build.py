@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpts.so")
-SOURCES = [os.path.join(HERE, "csrc", "pts_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "pts_api.hip"), os.path.join(HERE, "csrc", "pts_no.hip")]
 ARCH = os.environ.get("PTS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -20,13 +20,20 @@
 #include <vector>
 
 #include "../../include/pts.h"
+#include "../../include/pts_no.h"
 #include "pts_kernels.hip"
 
 using namespace pts;
 
 namespace {
-
 thread_local std::string g_err = "no error";
+}
+
+namespace pts_internal {
+void set_error(const char* msg) { g_err = msg; }
+}  // namespace pts_internal
+
+namespace {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -646,31 +653,33 @@ bool make_wave_plan(const pts_problem* p, const pts_options* o, double rho_max, 
 // wavefront kernel and the Newton steps they needed.
 struct StageCache {
   struct E {
-    int nx, ny, nt, kind, bc, prec;
+    int nx, ny, nt, kind, bc, prec, tag;
     double dt, mu_a, mu_b, tol;
     int sweeps, passes, steps;
   };
   std::vector<E> v;
-  E* find(const pts_problem* p, double tol) {
+  E* find(const pts_problem* p, double tol, int tag) {
     for (auto& e : v)
       if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
-          e.prec == p->precision && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b && e.tol == tol)
+          e.prec == p->precision && e.tag == tag && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b &&
+          e.tol == tol)
         return &e;
     return nullptr;
   }
-  void put(const pts_problem* p, double tol, int sweeps, int passes, int steps) {
-    if (E* e = find(p, tol)) {
+  void put(const pts_problem* p, double tol, int tag, int sweeps, int passes, int steps) {
+    if (E* e = find(p, tol, tag)) {
       e->sweeps = sweeps;
       e->passes = passes;
       e->steps = steps;
       return;
     }
     if (v.size() > 64) v.clear();
-    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, p->dt, p->mu_a, p->mu_b, tol, sweeps, passes,
-                 steps});
+    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, tag, p->dt, p->mu_a, p->mu_b, tol, sweeps,
+                 passes, steps});
   }
 };
 thread_local StageCache g_stage_cache;
+int ctag(const pts_options* o) { return o ? o->cache_tag : 0; }
 
 // Executable graph of one wavefront sequence, reused while the launch arguments match.
 struct WaveGraph {
@@ -801,7 +810,7 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     // reaches lin_tol (default 1e-4: the wavefront runs inexact Newton steps)
     Plan pl;
     const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
-    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
     const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
     bool ok;
     if (ce && !explicit_inner && ce->sweeps > 0) {
@@ -879,9 +888,9 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
   }
   if (needed >= 0 && plan_used.sweeps > 0) {
     // remember the step count for this plan (an autotuned plan stays the cached one)
-    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
     if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
-      g_stage_cache.put(p, tol, plan_used.sweeps, plan_used.passes, std::max(needed, 1));
+      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(needed, 1));
   }
   if (st) {
     st->iterations = it;
@@ -930,7 +939,7 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
     probe.passes = c.second;
     if (!geometry(p).whole && wave_halo(probe) > kMaxWaveHalo) continue;
     // run 1: discover the step count (uncached plan -> stage guesses of 4)
-    g_stage_cache.put(p, tol, c.first, c.second, 4);
+    g_stage_cache.put(p, tol, ctag(o), c.first, c.second, 4);
     HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
     bool fb = false;
     pts_stats s1;
@@ -940,7 +949,7 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
     o1.refine = -1;  // take the plan from the cache entry just written
     int rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb);
     if (rc || !s1.converged) continue;
-    const StageCache::E* ce = g_stage_cache.find(p, tol);
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
     const int steps = ce ? ce->steps : s1.iterations;
     // run 2: timed with the learned step count
     HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
@@ -963,10 +972,10 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
   HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   if (best_sw == 0) {
-    g_stage_cache.put(p, tol, 0, 0, 0);
+    g_stage_cache.put(p, tol, ctag(o), 0, 0, 0);
     return fail(PTS_ERR_NOT_CONVERGED, "autotune: no wavefront plan converged");
   }
-  g_stage_cache.put(p, tol, best_sw, best_pa, best_steps);
+  g_stage_cache.put(p, tol, ctag(o), best_sw, best_pa, best_steps);
   if (st) {
     std::memset(st, 0, sizeof *st);
     st->sweeps = best_sw;
@@ -1227,6 +1236,57 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
   HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return rc;
+}
+
+int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const float* params, const double* u0,
+                           double* U, void* no_ws, size_t no_ws_bytes, void* solver_ws, size_t solver_ws_bytes,
+                           int judge, int* chosen, double* res_pred, double* res_plain, pts_stream_t stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!cfg || p->bc != PTS_PERIODIC || cfg->nx != p->nx || cfg->ny != p->ny || cfg->nt != p->nt)
+    return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: network and problem disagree");
+  if (judge != PTS_NO_JUDGE_RESIDUAL && judge != PTS_NO_JUDGE_ACCUMULATED)
+    return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: judge %d", judge);
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: NULL array");
+  if ((rc = check_ws(p, solver_ws, solver_ws_bytes))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = pts_no_forward(cfg, params, u0, U, no_ws, no_ws_bytes, stream);
+  if (rc) return rc;
+  Instance in;
+  in.bind(p, solver_ws);
+  double* hs;
+  if ((rc = host_scalars(&hs))) return rc;
+  int dummy = 0;
+  const size_t ns = (size_t)p->nx * p->ny;
+  // residual of the prediction, in the judge's norm
+  if ((rc = in.residual(U, u0, s, &dummy, judge == PTS_NO_JUDGE_ACCUMULATED))) return rc;
+  if (judge == PTS_NO_JUDGE_ACCUMULATED) {
+    const unsigned blocks = (unsigned)std::min<size_t>((ns + 255) / 256, kUpdateBlocks);
+    hipLaunchKernelGGL(k_cumsum_absmax, dim3(blocks), dim3(256), 0, s, ns, p->nt, in.R, in.partial);
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, in.partial, (size_t)blocks, in.scal);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipMemcpyAsync(hs, in.scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double rp = hs[0];
+  // the plain iterate's residual is -tau F(u^0) at every level (u^n - u^{n-1} = 0), i.e. the
+  // one-level residual at u^0; its accumulated form at level n is n times that
+  pts_problem one = *p;
+  one.nt = 1;
+  if ((rc = launch_residual(&one, kprob(&one), u0, u0, nullptr, nullptr, in.rho, in.scal, s))) return rc;
+  HIPCHK(hipMemcpyAsync(hs, in.scal, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double r0 = hs[0] * (judge == PTS_NO_JUDGE_ACCUMULATED ? (double)p->nt : 1.0);
+  const bool use = std::isfinite(rp) && rp < r0;
+  if (!use) {
+    const unsigned blocks = (unsigned)std::min<size_t>((ns * p->nt + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_broadcast, dim3(blocks), dim3(256), 0, s, ns, p->nt, U, u0);
+    HIPCHK(hipGetLastError());
+  }
+  if (chosen) *chosen = use ? 1 : 0;
+  if (res_pred) *res_pred = rp;
+  if (res_plain) *res_plain = r0;
+  return PTS_OK;
 }
 
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob) {

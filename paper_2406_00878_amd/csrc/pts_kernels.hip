@@ -522,6 +522,26 @@ __global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ a, si
   }
 }
 
+// part[b] = max over the block's points p of max_n |sum_{m<=n} R[m][p]| (NaN propagates):
+// the block forward substitution of Eq. (7) with identity diagonal blocks. Grid-stride
+// over the ns points of a level; fold part with k_absmax.
+__global__ __launch_bounds__(256) void k_cumsum_absmax(size_t ns, int nt, const double* __restrict__ R,
+                                                       double* __restrict__ part) {
+  double m = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (size_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int n = 0; n < nt; ++n) {
+      acc += R[(size_t)n * ns + i];
+      m = nanmax(m, fabs(acc));
+    }
+  }
+  m = wave_max(m);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+}
+
 // u^n = u^0 at every level (the plain Newton start).
 __global__ __launch_bounds__(256) void k_broadcast(size_t ns, int nt, double* __restrict__ U,
                                                    const double* __restrict__ u0) {

@@ -1,0 +1,858 @@
+// Spectral neural operator for the learned initial space-time iterate (include/pts_no.h).
+//
+// Every matrix product runs in k_gemm: float32 operands in memory, rounded to bfloat16 when
+// staged into LDS, multiplied on MFMA 16x16x16 bf16 tiles with float32 accumulation. The
+// separable trigonometric transforms of the spectral layers, the pointwise channel
+// mixes, the projection to the levels and all their transposes in the backward pass are
+// strided views of that one kernel; reductions over the grid (weight gradients) split K
+// across work-groups and sum the partial tiles in fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/pts_no.h"
+
+namespace pts_no {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __builtin_bit_cast(unsigned, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+struct Gemm {
+  const float* A;
+  const float* B;
+  float* C;
+  int M, N, K;
+  long sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc;
+  float alpha, beta;
+  int ksplit;       // K ranges per product; > 1 writes partial tiles to P
+  float* P;         // [batch][ksplit][M][N] partials (ksplit > 1)
+};
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// grid: x = N tiles, y = M tiles, z = batch * ksplit; 256 threads (4 waves, 32 x 32 each)
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+  __shared__ unsigned short As[BM][BK + 4];
+  __shared__ unsigned short Bs[BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const int b = blockIdx.z / g.ksplit, sp = blockIdx.z % g.ksplit;
+  const float* A = g.A + (long)b * g.bsa;
+  const float* B = g.B + (long)b * g.bsb;
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = sp * kchunk, kend = min(g.K, kbeg + kchunk);
+  float4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // stage A (64 x 16) and B (16 x 64): 4 elements per thread each
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      const int am = e / BK, ak = e % BK;
+      const int gm = m0 + am, gk = k0 + ak;
+      const float av = (gm < g.M && gk < kend) ? A[(long)gm * g.sam + (long)gk * g.sak] : 0.f;
+      As[am][ak] = f2bf(av);
+      const int bk = e / BN, bn = e % BN;
+      const int gk2 = k0 + bk, gn = n0 + bn;
+      const float bv = (gk2 < kend && gn < g.N) ? B[(long)gk2 * g.sbk + (long)gn * g.sbn] : 0.f;
+      Bs[bk][bn] = f2bf(bv);
+    }
+    __syncthreads();
+    const int kq = 4 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm + 16 * i + (lane & 15);
+      short4_t a;
+      a[0] = (short)As[row][kq];
+      a[1] = (short)As[row][kq + 1];
+      a[2] = (short)As[row][kq + 2];
+      a[3] = (short)As[row][kq + 3];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wn + 16 * j + (lane & 15);
+        short4_t bb;
+        bb[0] = (short)Bs[kq][col];
+        bb[1] = (short)Bs[kq + 1][col];
+        bb[2] = (short)Bs[kq + 2][col];
+        bb[3] = (short)Bs[kq + 3][col];
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // lane l holds rows 4 (l / 16) + r, column l % 16 of each 16 x 16 tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn + 16 * j + (lane & 15);
+        if (gm >= g.M || gn >= g.N) continue;
+        if (g.ksplit > 1) {
+          g.P[(((long)b * g.ksplit + sp) * g.M + gm) * g.N + gn] = acc[i][j][r];
+        } else {
+          float* c = g.C + (long)b * g.bsc + (long)gm * g.scm + (long)gn * g.scn;
+          *c = g.alpha * acc[i][j][r] + (g.beta != 0.f ? g.beta * *c : 0.f);
+        }
+      }
+}
+
+// C_b = alpha * sum_s P[b][s] + beta C_b, summed over s in order
+__global__ __launch_bounds__(256) void k_gemm_reduce(Gemm g, int batch) {
+  const long total = (long)batch * g.M * g.N;
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const int b = (int)(t / ((long)g.M * g.N));
+    const long mn = t % ((long)g.M * g.N);
+    const int m = (int)(mn / g.N), n = (int)(mn % g.N);
+    float s = 0.f;
+    for (int k = 0; k < g.ksplit; ++k) s += g.P[((long)b * g.ksplit + k) * g.M * g.N + mn];
+    float* c = g.C + (long)b * g.bsc + (long)m * g.scm + (long)n * g.scn;
+    *c = g.alpha * s + (g.beta != 0.f ? g.beta * *c : 0.f);
+  }
+}
+
+// ------------------------------------------------------------------ elementwise
+__device__ __forceinline__ float gelu(float z) {
+  const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+  const float t = 1.f - 2.f / (expf(2.f * a) + 1.f);  // tanh(a)
+  return 0.5f * z * (1.f + t);
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+  const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+  const float t = 1.f - 2.f / (expf(2.f * a) + 1.f);
+  const float da = 0.7978845608028654f * (1.f + 3.f * 0.044715f * z * z);
+  return 0.5f * (1.f + t) + 0.5f * z * (1.f - t * t) * da;
+}
+
+// Trigonometric basis phi[i][k] on n periodic nodes x_i = i/n: cos(2 pi k x), k < m;
+// sin(2 pi (k - m + 1) x), m <= k < 2m - 1.
+__global__ void k_basis(int n, int m, float* phi) {
+  const int m2 = 2 * m - 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * m2) return;
+  const int i = t / m2, k = t % m2;
+  const double x = (double)i / n;
+  const double v = k < m ? cos(2.0 * M_PI * k * x) : sin(2.0 * M_PI * (k - m + 1) * x);
+  phi[t] = (float)v;
+}
+
+// v0[c][p] = lw[c] u0[p] + lb[c]
+__global__ void k_lift(int C, long np, const float* __restrict__ lw, const float* __restrict__ lb,
+                       const double* __restrict__ u0, float* __restrict__ v0) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < C * np; t += (long)gridDim.x * 256) {
+    const int c = (int)(t / np);
+    v0[t] = lw[c] * (float)u0[t % np] + lb[c];
+  }
+}
+
+// z[c][p] += b[c]; y = gelu(z)
+__global__ void k_bias_gelu(int C, long np, const float* __restrict__ b, float* __restrict__ z,
+                            float* __restrict__ y) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < C * np; t += (long)gridDim.x * 256) {
+    const float zz = z[t] + b[t / np];
+    z[t] = zz;
+    y[t] = gelu(zz);
+  }
+}
+
+// dz = dy * gelu'(z)
+__global__ void k_gelu_back(long n, const float* __restrict__ z, const float* __restrict__ dy,
+                            float* __restrict__ dz) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) dz[t] = dy[t] * gelu_grad(z[t]);
+}
+
+// Spectral mixing: every complex Fourier mode of the band (|kx|, |ky| < m) is multiplied by a
+// complex width x width matrix W = alpha + i beta. Coefficients live in the real basis
+// (index q = a * m2 + b, row a = y, column b = x; cos k at k, sin k at m - 1 + k). For a
+// frequency block kx, ky >= 1 with coefficients A (cos y cos x), B (cos y sin x), C (sin y cos x),
+// D (sin y sin x), the amplitudes of exp(i(x + y)) and exp(i(x - y)) are
+// (P_c - i P_s) and (M_c - i M_s) with P = ((A - D), (B + C)) / 2, M = ((A + D), (B - C)) / 2;
+// multiplying by alpha + i beta maps a pair (c, s) to (alpha c + beta s, alpha s - beta c),
+// and A' = P_c' + M_c', D' = M_c' - P_c', B' = P_s' + M_s', C' = P_s' - M_s'. alpha+ / beta+ /
+// alpha- / beta- are the matrices R at (cos ky, cos kx) / (cos ky, sin kx) / (sin ky, cos kx) /
+// (sin ky, sin kx). A block with one zero frequency is one (cos, sin) pair with alpha at the
+// cosine and beta at the sine position; the mean is real.
+struct Block {
+  int n;       // 1, 2 or 4 coefficients
+  int q[4];    // 4: cc, cs, sc, ss; 2: cos, sin; 1: mean
+};
+__device__ __forceinline__ Block block_of(int m, int ky, int kx) {
+  const int m2 = 2 * m - 1;
+  Block b;
+  if (kx > 0 && ky > 0) {
+    b.n = 4;
+    b.q[0] = ky * m2 + kx;
+    b.q[1] = ky * m2 + (m - 1 + kx);
+    b.q[2] = (m - 1 + ky) * m2 + kx;
+    b.q[3] = (m - 1 + ky) * m2 + (m - 1 + kx);
+  } else if (kx > 0) {
+    b.n = 2;
+    b.q[0] = kx;
+    b.q[1] = m - 1 + kx;
+  } else if (ky > 0) {
+    b.n = 2;
+    b.q[0] = ky * m2;
+    b.q[1] = (m - 1 + ky) * m2;
+  } else {
+    b.n = 1;
+    b.q[0] = 0;
+  }
+  return b;
+}
+
+// what = mix(vhat); one thread per (output channel, frequency block)
+__global__ void k_mix(int C, int m, const float* __restrict__ R, const float* __restrict__ vh,
+                      float* __restrict__ wh) {
+  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C * nb) return;
+  const int co = t / nb, blk = t % nb;
+  const Block b = block_of(m, blk / m, blk % m);
+  const float* r[4];
+  for (int i = 0; i < b.n; ++i) r[i] = R + ((long)b.q[i] * C + co) * C;
+  float* w = wh + (long)co * Q;
+  if (b.n == 4) {
+    float pc = 0.f, ps = 0.f, mc = 0.f, ms = 0.f;
+    for (int c = 0; c < C; ++c) {
+      const float* v = vh + (long)c * Q;
+      const float A = v[b.q[0]], B = v[b.q[1]], Cc = v[b.q[2]], D = v[b.q[3]];
+      const float Pc = 0.5f * (A - D), Ps = 0.5f * (B + Cc), Mc = 0.5f * (A + D), Ms = 0.5f * (B - Cc);
+      const float ap = r[0][c], bp = r[1][c], am = r[2][c], bm = r[3][c];
+      pc += ap * Pc + bp * Ps;
+      ps += ap * Ps - bp * Pc;
+      mc += am * Mc + bm * Ms;
+      ms += am * Ms - bm * Mc;
+    }
+    w[b.q[0]] = pc + mc;
+    w[b.q[3]] = mc - pc;
+    w[b.q[1]] = ps + ms;
+    w[b.q[2]] = ps - ms;
+  } else if (b.n == 2) {
+    float ac = 0.f, as = 0.f;
+    for (int c = 0; c < C; ++c) {
+      const float* v = vh + (long)c * Q;
+      const float A = v[b.q[0]], S = v[b.q[1]];
+      ac += r[0][c] * A + r[1][c] * S;
+      as += r[0][c] * S - r[1][c] * A;
+    }
+    w[b.q[0]] = ac;
+    w[b.q[1]] = as;
+  } else {
+    float a = 0.f;
+    for (int c = 0; c < C; ++c) a += r[0][c] * vh[(long)c * Q];
+    w[0] = a;
+  }
+}
+
+// Adjoint of k_mix: dvhat (written) and dR (accumulated); one thread per (input channel, block),
+// so every dR entry has one writer.
+__global__ void k_mix_back(int C, int m, const float* __restrict__ R, const float* __restrict__ vh,
+                           const float* __restrict__ dwh, float* __restrict__ dvh, float* __restrict__ dR) {
+  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= C * nb) return;
+  const int c = t / nb, blk = t % nb;
+  const Block b = block_of(m, blk / m, blk % m);
+  const float* v = vh + (long)c * Q;
+  float* dv = dvh + (long)c * Q;
+  if (b.n == 4) {
+    const float A = v[b.q[0]], B = v[b.q[1]], Cc = v[b.q[2]], D = v[b.q[3]];
+    const float Pc = 0.5f * (A - D), Ps = 0.5f * (B + Cc), Mc = 0.5f * (A + D), Ms = 0.5f * (B - Cc);
+    float gPc = 0.f, gPs = 0.f, gMc = 0.f, gMs = 0.f;
+    for (int co = 0; co < C; ++co) {
+      const float* d = dwh + (long)co * Q;
+      const float dA = d[b.q[0]], dB = d[b.q[1]], dC = d[b.q[2]], dD = d[b.q[3]];
+      const float dPc = dA - dD, dMc = dA + dD, dPs = dB + dC, dMs = dB - dC;
+      const long o = (long)co * C + c;
+      const float ap = R[(long)b.q[0] * C * C + o], bp = R[(long)b.q[1] * C * C + o];
+      const float am = R[(long)b.q[2] * C * C + o], bm = R[(long)b.q[3] * C * C + o];
+      gPc += ap * dPc - bp * dPs;
+      gPs += bp * dPc + ap * dPs;
+      gMc += am * dMc - bm * dMs;
+      gMs += bm * dMc + am * dMs;
+      dR[(long)b.q[0] * C * C + o] += dPc * Pc + dPs * Ps;
+      dR[(long)b.q[1] * C * C + o] += dPc * Ps - dPs * Pc;
+      dR[(long)b.q[2] * C * C + o] += dMc * Mc + dMs * Ms;
+      dR[(long)b.q[3] * C * C + o] += dMc * Ms - dMs * Mc;
+    }
+    dv[b.q[0]] = 0.5f * (gPc + gMc);
+    dv[b.q[3]] = 0.5f * (gMc - gPc);
+    dv[b.q[1]] = 0.5f * (gPs + gMs);
+    dv[b.q[2]] = 0.5f * (gPs - gMs);
+  } else if (b.n == 2) {
+    const float A = v[b.q[0]], S = v[b.q[1]];
+    float gA = 0.f, gS = 0.f;
+    for (int co = 0; co < C; ++co) {
+      const float* d = dwh + (long)co * Q;
+      const float dA = d[b.q[0]], dS = d[b.q[1]];
+      const long o = (long)co * C + c;
+      const float al = R[(long)b.q[0] * C * C + o], be = R[(long)b.q[1] * C * C + o];
+      gA += al * dA - be * dS;
+      gS += be * dA + al * dS;
+      dR[(long)b.q[0] * C * C + o] += dA * A + dS * S;
+      dR[(long)b.q[1] * C * C + o] += dA * S - dS * A;
+    }
+    dv[b.q[0]] = gA;
+    dv[b.q[1]] = gS;
+  } else {
+    const float A = v[0];
+    float g = 0.f;
+    for (int co = 0; co < C; ++co) {
+      const long o = (long)co * C + c;
+      g += R[o] * dwh[(long)co * Q];
+      dR[o] += dwh[(long)co * Q] * A;
+    }
+    dv[0] = g;
+  }
+}
+
+constexpr int kMaxT = 64;  // temporal modes
+
+// Temporal basis: Phi [nt][K] (float32) = Q of the thin QR of S[n][k] = sin(pi (k + 1/2)(n + 1) / nt)
+// with a positive diagonal of R, formed as Cholesky QR in float64 (S^T S = L L^T, Q = S L^-T):
+// the sines are close to orthogonal, so the Gram matrix is well conditioned. One work-group;
+// S64 is [nt][K] float64 scratch.
+__global__ __launch_bounds__(256) void k_tbasis(int nt, int K, double* __restrict__ S64, float* __restrict__ phi) {
+  __shared__ double G[kMaxT][kMaxT + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nt * K; e += 256) {
+    const int n = e / K, k = e % K;
+    S64[e] = sin(M_PI * (k + 0.5) * (double)(n + 1) / (double)nt);
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += 256) {
+    const int a = e / K, b = e % K;
+    if (a > b) continue;
+    double g = 0.0;
+    for (int n = 0; n < nt; ++n) g += S64[(long)n * K + a] * S64[(long)n * K + b];
+    G[a][b] = g;
+    G[b][a] = g;
+  }
+  __syncthreads();
+  // Cholesky G = L L^T in place (lower triangle), column by column
+  for (int j = 0; j < K; ++j) {
+    if (tid == 0) {
+      double d = G[j][j];
+      for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
+      G[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < K; i += 256) {
+      double v = G[i][j];
+      for (int k = 0; k < j; ++k) v -= G[i][k] * G[j][k];
+      G[i][j] = v / G[j][j];
+    }
+    __syncthreads();
+  }
+  // rows of Q: L q = s (forward substitution), in place in S64
+  for (int n = tid; n < nt; n += 256) {
+    double* r = S64 + (long)n * K;
+    for (int k = 0; k < K; ++k) {
+      double v = r[k];
+      for (int j = 0; j < k; ++j) v -= G[k][j] * r[j];
+      r[k] = v / G[k][k];
+      phi[(long)n * K + k] = (float)r[k];
+    }
+  }
+}
+
+// U[n][p] = u0[p] + sum_k Phi[n][k] (coef[k][p] + pb[k]) in float32, stored as float64.
+// grid: x over points (grid-stride), y over chunks of kSynthLevels levels.
+constexpr int kSynthLevels = 32;
+__global__ __launch_bounds__(256) void k_synth(int nt, int K, long np, const double* __restrict__ u0,
+                                               const float* __restrict__ coef, const float* __restrict__ pb,
+                                               const float* __restrict__ phi, double* __restrict__ U) {
+  const int n0 = blockIdx.y * kSynthLevels, n1 = min(nt, n0 + kSynthLevels);
+  for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < np; p += (long)gridDim.x * 256) {
+    float c[kMaxT];
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k) c[k] = k < K ? coef[(long)k * np + p] + pb[k] : 0.f;
+    const double base = u0[p];
+    for (int n = n0; n < n1; ++n) {
+      const float* f = phi + (long)n * K;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < kMaxT; ++k)
+        if (k < K) acc += f[k] * c[k];
+      U[(long)n * np + p] = base + (double)acc;
+    }
+  }
+}
+
+// out[k][p] = scale * sum_n Phi[n][k] (A[n][p] - B[p or n][p]); with DIFF, B is [nt][np] and
+// the block partial sums of (A - B)^2 go to part[blockIdx.x]; else B is u0 [np].
+// 128 threads per block, grid-stride over points.
+template <bool DIFF>
+__global__ __launch_bounds__(128) void k_encode(int nt, int K, long np, const double* __restrict__ A,
+                                                const double* __restrict__ B, const float* __restrict__ phi,
+                                                float scale, float* __restrict__ out, double* __restrict__ part) {
+  double lsum = 0.0;
+  for (long p = (long)blockIdx.x * 128 + threadIdx.x; p < np; p += (long)gridDim.x * 128) {
+    float acc[kMaxT];
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k) acc[k] = 0.f;
+    for (int n = 0; n < nt; ++n) {
+      const double d = A[(long)n * np + p] - (DIFF ? B[(long)n * np + p] : B[p]);
+      if (DIFF) lsum += d * d;
+      const float df = (float)d;
+      const float* f = phi + (long)n * K;
+#pragma unroll
+      for (int k = 0; k < kMaxT; ++k)
+        if (k < K) acc[k] += f[k] * df;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxT; ++k)
+      if (k < K) out[(long)k * np + p] = scale * acc[k];
+  }
+  if (DIFF) {
+    __shared__ double red[128];
+    red[threadIdx.x] = lsum;
+    __syncthreads();
+    for (int o = 64; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  }
+}
+
+// d = coef + pb - ctrue; dcoef = scale d; block partial sums of d^2 into part
+__global__ __launch_bounds__(256) void k_coef_diff(int K, long np, const float* __restrict__ coef,
+                                                   const float* __restrict__ pb, const float* __restrict__ ct,
+                                                   float scale, float* __restrict__ dcoef,
+                                                   double* __restrict__ part) {
+  double acc = 0.0;
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < (long)K * np; t += (long)gridDim.x * 256) {
+    const float d = coef[t] + pb[t / np] - ct[t];
+    dcoef[t] = scale * d;
+    acc += (double)d * (double)d;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss[0] += sum(part) / n (one block, fixed order)
+__global__ void k_mse_finish(int nb, long n, const double* __restrict__ part, double* __restrict__ loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    loss[0] += s / (double)n;
+  }
+}
+
+// row sums of a [rows][len] float array accumulated into out[rows] (one block per row)
+__global__ __launch_bounds__(256) void k_rowsum(long len, const float* __restrict__ a, float* __restrict__ out) {
+  const float* r = a + (long)blockIdx.x * len;
+  float s = 0.f;
+  for (long t = threadIdx.x; t < len; t += 256) s += r[t];
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] += red[0];
+}
+
+// out[c] += sum_p a[c][p] * w[p] (one block per row); w is float64 (u0)
+__global__ __launch_bounds__(256) void k_rowdot(long len, const float* __restrict__ a, const double* __restrict__ w,
+                                                float* __restrict__ out) {
+  const float* r = a + (long)blockIdx.x * len;
+  float s = 0.f;
+  for (long t = threadIdx.x; t < len; t += 256) s += r[t] * (float)w[t];
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] += red[0];
+}
+
+__global__ void k_adam(long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float gs, float c1, float c2) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) {
+    const float gt = g[t] * gs;
+    const float mt = b1 * m[t] + (1.f - b1) * gt;
+    const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    p[t] -= lr * (mt / c1) / (sqrtf(vt / c2) + eps);
+  }
+}
+
+__global__ void k_fill(long n, float* __restrict__ a, float v) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) a[t] = v;
+}
+
+}  // namespace pts_no
+
+using namespace pts_no;
+
+namespace pts_internal {
+void set_error(const char* msg);  // shared with pts_last_error (pts_api.hip)
+}
+
+namespace {
+
+int nofail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  pts_internal::set_error(buf);
+  return code;
+}
+
+#define NOCHK(expr)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return nofail(PTS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int valid(const pts_no_config* c) {
+  if (!c) return nofail(PTS_ERR_INVALID_ARG, "config is NULL");
+  if (c->nx < 4 || c->ny < 4 || c->nt < 1) return nofail(PTS_ERR_INVALID_ARG, "grid/levels");
+  if ((long long)c->nx * c->ny > (1ll << 24)) return nofail(PTS_ERR_INVALID_ARG, "grid too large");
+  if (c->width < 16 || c->width > 64 || c->width % 16) return nofail(PTS_ERR_INVALID_ARG, "width %d", c->width);
+  if (c->modes < 1 || c->modes > 32 || 2 * c->modes > std::min(c->nx, c->ny))
+    return nofail(PTS_ERR_INVALID_ARG, "modes %d", c->modes);
+  if (c->layers < 1 || c->layers > 8) return nofail(PTS_ERR_INVALID_ARG, "layers %d", c->layers);
+  if (c->tmodes < 1 || c->tmodes > kMaxT || c->tmodes > c->nt)
+    return nofail(PTS_ERR_INVALID_ARG, "tmodes %d", c->tmodes);
+  return PTS_OK;
+}
+
+// parameter offsets (floats)
+struct Par {
+  size_t lw, lb, W[8], b[8], R[8], pw, pb, total;
+};
+Par par_layout(const pts_no_config* c) {
+  Par P;
+  const size_t C = c->width, Q = (size_t)(2 * c->modes - 1) * (2 * c->modes - 1);
+  size_t o = 0;
+  P.lw = o;
+  o += C;
+  P.lb = o;
+  o += C;
+  for (int l = 0; l < c->layers; ++l) {
+    P.W[l] = o;
+    o += C * C;
+    P.b[l] = o;
+    o += C;
+    P.R[l] = o;
+    o += Q * C * C;
+  }
+  P.pw = o;
+  o += (size_t)c->tmodes * C;
+  P.pb = o;
+  o += c->tmodes;
+  P.total = o;
+  return P;
+}
+
+// workspace offsets (bytes, 256-aligned)
+struct Ws {
+  size_t phix, phiy, tphi, s64, v, z, vh, wh, t1, t2, coef, dcoef, dv, dv2, dz, dvh, dwh, part, gpart, total;
+};
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
+constexpr int kSplit = 32;
+constexpr int kPartSlots = 4096;  // loss partial sums (one per block of the loss kernels)
+Ws ws_layout(const pts_no_config* c) {
+  Ws w;
+  const size_t C = c->width, np = (size_t)c->nx * c->ny, m2 = 2 * c->modes - 1, Q = m2 * m2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = al(o + bytes);
+    return at;
+  };
+  w.phix = take(c->nx * m2 * 4);
+  w.phiy = take(c->ny * m2 * 4);
+  w.tphi = take((size_t)c->nt * c->tmodes * 4);
+  w.s64 = take((size_t)c->nt * c->tmodes * 8);
+  w.v = take((c->layers + 1) * C * np * 4);
+  w.z = take(c->layers * C * np * 4);
+  w.vh = take(c->layers * C * Q * 4);
+  w.wh = take(C * Q * 4);
+  w.t1 = take(C * c->ny * m2 * 4);
+  w.t2 = take(C * c->ny * m2 * 4);
+  w.coef = take((size_t)c->tmodes * np * 4);
+  w.dcoef = take((size_t)c->tmodes * np * 4);
+  w.dv = take(C * np * 4);
+  w.dv2 = take(C * np * 4);
+  w.dz = take(C * np * 4);
+  w.dvh = take(C * Q * 4);
+  w.dwh = take(C * Q * 4);
+  w.part = take(kPartSlots * 8);
+  w.gpart = take((size_t)kSplit * std::max((size_t)c->tmodes, C) * C * 4);
+  w.total = o;
+  return w;
+}
+
+unsigned eblocks(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
+
+// C = alpha op(A) op(B) + beta C via k_gemm; ksplit > 1 needs P scratch
+int gemm(hipStream_t s, int M, int N, int K, float alpha, const float* A, long sam, long sak, long bsa,
+         const float* B, long sbk, long sbn, long bsb, float beta, float* C, long scm, long scn, long bsc,
+         int batch = 1, int ksplit = 1, float* P = nullptr) {
+  Gemm g{A, B, C, M, N, K, sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc, alpha, beta, ksplit, P};
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)(batch * ksplit));
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+  if (ksplit > 1) hipLaunchKernelGGL(k_gemm_reduce, dim3(eblocks((long)batch * M * N)), dim3(256), 0, s, g, batch);
+  NOCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+struct Net {
+  const pts_no_config* c;
+  Par P;
+  Ws W;
+  char* ws;
+  int C, nx, ny, m2, Q;
+  long np;
+  float* f(size_t off) const { return (float*)(ws + off); }
+  float* v(int l) const { return f(W.v) + (size_t)l * C * np; }
+  float* z(int l) const { return f(W.z) + (size_t)l * C * np; }
+  float* vh(int l) const { return f(W.vh) + (size_t)l * C * Q; }
+  void bind(const pts_no_config* cfg, void* w) {
+    c = cfg;
+    P = par_layout(cfg);
+    W = ws_layout(cfg);
+    ws = (char*)w;
+    C = cfg->width;
+    nx = cfg->nx;
+    ny = cfg->ny;
+    m2 = 2 * cfg->modes - 1;
+    Q = m2 * m2;
+    np = (long)nx * ny;
+  }
+  // vh = (1/np) phiy^T v phix  for the C channels of v [C][ny][nx]
+  int forward_transform(hipStream_t s, const float* vin, float* vhat) {
+    const float* phix = f(W.phix);
+    const float* phiy = f(W.phiy);
+    float* t1 = f(W.t1);
+    int rc = gemm(s, C * ny, m2, nx, 1.f, vin, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0);
+    if (rc) return rc;
+    return gemm(s, m2, m2, ny, 1.f / (float)np, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, vhat, m2, 1, Q, C);
+  }
+  // out (+)= phiy what phix^T for C channels; beta = 0 writes, 1 accumulates
+  int inverse_transform(hipStream_t s, const float* what, float* out, float beta) {
+    const float* phix = f(W.phix);
+    const float* phiy = f(W.phiy);
+    float* t2 = f(W.t2);
+    int rc = gemm(s, ny, m2, m2, 1.f, phiy, m2, 1, 0, what, m2, 1, Q, 0.f, t2, m2, 1, (long)ny * m2, C);
+    if (rc) return rc;
+    return gemm(s, C * ny, nx, m2, 1.f, t2, m2, 1, 0, phix, 1, m2, 0, beta, out, nx, 1, 0);
+  }
+  // gradients of a loss from dcoef = dL/dc (workspace) back through the network, accumulated
+  int backward_from_coef(hipStream_t s, const float* params, const double* u0, float* grads) {
+    int rc;
+    const int K = c->tmodes;
+    float* dco = f(W.dcoef);
+    float* gp = f(W.gpart);
+    float* vL = v(c->layers);
+    // projection: dpw += dcoef v_L^T (K = np, split), dpb += rowsum(dcoef), dv = pw^T dcoef
+    if ((rc = gemm(s, K, C, (int)np, 1.f, dco, np, 1, 0, vL, 1, np, 0, 1.f, grads + P.pw, C, 1, 0, 1, kSplit, gp)))
+      return rc;
+    hipLaunchKernelGGL(k_rowsum, dim3(K), dim3(256), 0, s, np, dco, grads + P.pb);
+    float* dv = f(W.dv);
+    float* dv2 = f(W.dv2);
+    float* dz = f(W.dz);
+    if ((rc = gemm(s, C, (int)np, K, 1.f, params + P.pw, 1, C, 0, dco, np, 1, 0, 0.f, dv, np, 1, 0))) return rc;
+    const float* phix = f(W.phix);
+    const float* phiy = f(W.phiy);
+    for (int l = c->layers - 1; l >= 0; --l) {
+      float* vin = v(l);
+      hipLaunchKernelGGL(k_gelu_back, dim3(eblocks(C * np)), dim3(256), 0, s, C * np, z(l), dv, dz);
+      hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, s, np, dz, grads + P.b[l]);
+      // dW += dz v^T ; dv2 = W^T dz
+      if ((rc = gemm(s, C, C, (int)np, 1.f, dz, np, 1, 0, vin, 1, np, 0, 1.f, grads + P.W[l], C, 1, 0, 1, kSplit,
+                     gp)))
+        return rc;
+      if ((rc = gemm(s, C, (int)np, C, 1.f, params + P.W[l], 1, C, 0, dz, np, 1, 0, 0.f, dv2, np, 1, 0))) return rc;
+      // spectral branch: dwhat = phiy^T dz phix (adjoint of the inverse transform)
+      float* t1 = f(W.t1);
+      if ((rc = gemm(s, C * ny, m2, nx, 1.f, dz, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0))) return rc;
+      if ((rc = gemm(s, m2, m2, ny, 1.f, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, f(W.dwh), m2, 1, Q, C)))
+        return rc;
+      hipLaunchKernelGGL(k_mix_back, dim3((C * c->modes * c->modes + 255) / 256), dim3(256), 0, s, C, c->modes,
+                         params + P.R[l], vh(l),
+                         f(W.dwh), f(W.dvh), grads + P.R[l]);
+      // dv2 += (1/np) phiy dvhat phix^T (adjoint of the forward transform)
+      float* t2 = f(W.t2);
+      if ((rc = gemm(s, ny, m2, m2, 1.f / (float)np, phiy, m2, 1, 0, f(W.dvh), m2, 1, Q, 0.f, t2, m2, 1,
+                     (long)ny * m2, C)))
+        return rc;
+      if ((rc = gemm(s, C * ny, nx, m2, 1.f, t2, m2, 1, 0, phix, 1, m2, 0, 1.f, dv2, nx, 1, 0))) return rc;
+      std::swap(dv, dv2);
+    }
+    // lift: dlw += sum_p dv0 u0, dlb += sum_p dv0
+    hipLaunchKernelGGL(k_rowdot, dim3(C), dim3(256), 0, s, np, dv, u0, grads + P.lw);
+    hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, s, np, dv, grads + P.lb);
+    NOCHK(hipGetLastError());
+    return PTS_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t pts_no_param_count(const pts_no_config* cfg) {
+  if (valid(cfg)) return 0;
+  return par_layout(cfg).total;
+}
+
+size_t pts_no_workspace_bytes(const pts_no_config* cfg) {
+  if (valid(cfg)) return 0;
+  return ws_layout(cfg).total;
+}
+
+int pts_no_gemm(int M, int N, int K, float alpha, const float* A, long sam, long sak, long bsa, const float* B,
+                long sbk, long sbn, long bsb, float beta, float* C, long scm, long scn, long bsc, int batch,
+                pts_stream_t stream) {
+  if (M < 1 || N < 1 || K < 1 || batch < 1 || !A || !B || !C) return nofail(PTS_ERR_INVALID_ARG, "pts_no_gemm");
+  return gemm((hipStream_t)stream, M, N, K, alpha, A, sam, sak, bsa, B, sbk, sbn, bsb, beta, C, scm, scn, bsc,
+              batch);
+}
+
+int pts_no_forward(const pts_no_config* cfg, const float* params, const double* u0, double* U_pred, void* workspace,
+                   size_t workspace_bytes, pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (!params || !u0 || !workspace) return nofail(PTS_ERR_INVALID_ARG, "pts_no_forward: NULL");
+  if (workspace_bytes < ws_layout(cfg).total) return nofail(PTS_ERR_WORKSPACE, "pts_no_forward: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace);
+  const int C = n.C;
+  const long np = n.np;
+  hipLaunchKernelGGL(k_basis, dim3((n.nx * n.m2 + 255) / 256), dim3(256), 0, s, n.nx, cfg->modes, n.f(n.W.phix));
+  hipLaunchKernelGGL(k_basis, dim3((n.ny * n.m2 + 255) / 256), dim3(256), 0, s, n.ny, cfg->modes, n.f(n.W.phiy));
+  hipLaunchKernelGGL(k_lift, dim3(eblocks(C * np)), dim3(256), 0, s, C, np, params + n.P.lw, params + n.P.lb, u0,
+                     n.v(0));
+  for (int l = 0; l < cfg->layers; ++l) {
+    float* vin = n.v(l);
+    float* z = n.z(l);
+    // spectral part into z, then z += W v (pointwise channel mix)
+    if ((rc = n.forward_transform(s, vin, n.vh(l)))) return rc;
+    hipLaunchKernelGGL(k_mix, dim3((C * cfg->modes * cfg->modes + 255) / 256), dim3(256), 0, s, C, cfg->modes,
+                       params + n.P.R[l], n.vh(l),
+                       n.f(n.W.wh));
+    if ((rc = n.inverse_transform(s, n.f(n.W.wh), z, 0.f))) return rc;
+    if ((rc = gemm(s, C, (int)np, C, 1.f, params + n.P.W[l], C, 1, 0, vin, np, 1, 0, 1.f, z, np, 1, 0))) return rc;
+    hipLaunchKernelGGL(k_bias_gelu, dim3(eblocks(C * np)), dim3(256), 0, s, C, np, params + n.P.b[l], z, n.v(l + 1));
+  }
+  // coefficient fields coef[K][np] = pw v_L (bias added by the consumers)
+  if ((rc = gemm(s, cfg->tmodes, (int)np, C, 1.f, params + n.P.pw, C, 1, 0, n.v(cfg->layers), np, 1, 0, 0.f,
+                 n.f(n.W.coef), np, 1, 0)))
+    return rc;
+  if (U_pred) {
+    hipLaunchKernelGGL(k_tbasis, dim3(1), dim3(256), 0, s, cfg->nt, cfg->tmodes, (double*)(n.ws + n.W.s64),
+                       n.f(n.W.tphi));
+    dim3 grid(std::min<unsigned>((unsigned)((np + 255) / 256), 2048u),
+              (unsigned)((cfg->nt + kSynthLevels - 1) / kSynthLevels));
+    hipLaunchKernelGGL(k_synth, grid, dim3(256), 0, s, cfg->nt, cfg->tmodes, np, u0, n.f(n.W.coef),
+                       params + n.P.pb, n.f(n.W.tphi), U_pred);
+  }
+  NOCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+int pts_no_backward(const pts_no_config* cfg, const float* params, const double* u0, const double* U_pred,
+                    const double* U_true, float* grads, double* loss, void* workspace, size_t workspace_bytes,
+                    pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (!params || !u0 || !U_pred || !U_true || !grads || !loss || !workspace)
+    return nofail(PTS_ERR_INVALID_ARG, "pts_no_backward: NULL");
+  if (workspace_bytes < ws_layout(cfg).total) return nofail(PTS_ERR_WORKSPACE, "pts_no_backward: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace);
+  const long count = (long)cfg->nt * n.np;
+  // dL/dc = Phi^T dL/dU with dL/dU = 2 (U_pred - U_true) / count; loss partials alongside
+  double* part = (double*)(n.ws + n.W.part);
+  const unsigned eb = (unsigned)std::min<long>((n.np + 127) / 128, kPartSlots);
+  hipLaunchKernelGGL(k_encode<true>, dim3(eb), dim3(128), 0, s, cfg->nt, cfg->tmodes, n.np, U_pred, U_true,
+                     n.f(n.W.tphi), (float)(2.0 / (double)count), n.f(n.W.dcoef), part);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, s, (int)eb, count, part, loss);
+  NOCHK(hipGetLastError());
+  return n.backward_from_coef(s, params, u0, grads);
+}
+
+int pts_no_backward_coef(const pts_no_config* cfg, const float* params, const double* u0, const float* coef_true,
+                         float* grads, double* loss, void* workspace, size_t workspace_bytes, pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (!params || !u0 || !coef_true || !grads || !loss || !workspace)
+    return nofail(PTS_ERR_INVALID_ARG, "pts_no_backward_coef: NULL");
+  if (workspace_bytes < ws_layout(cfg).total) return nofail(PTS_ERR_WORKSPACE, "pts_no_backward_coef: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace);
+  const long count = (long)cfg->nt * n.np;
+  double* part = (double*)(n.ws + n.W.part);
+  const unsigned eb = std::min<unsigned>(eblocks((long)cfg->tmodes * n.np), kPartSlots);
+  hipLaunchKernelGGL(k_coef_diff, dim3(eb), dim3(256), 0, s, cfg->tmodes, n.np, n.f(n.W.coef), params + n.P.pb,
+                     coef_true, (float)(2.0 / (double)count), n.f(n.W.dcoef), part);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, s, (int)eb, count, part, loss);
+  NOCHK(hipGetLastError());
+  return n.backward_from_coef(s, params, u0, grads);
+}
+
+int pts_no_encode(const pts_no_config* cfg, const double* u0, const double* U, float* coef, void* workspace,
+                  size_t workspace_bytes, pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (!u0 || !U || !coef || !workspace) return nofail(PTS_ERR_INVALID_ARG, "pts_no_encode: NULL");
+  if (workspace_bytes < ws_layout(cfg).total) return nofail(PTS_ERR_WORKSPACE, "pts_no_encode: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace);
+  hipLaunchKernelGGL(k_tbasis, dim3(1), dim3(256), 0, s, cfg->nt, cfg->tmodes, (double*)(n.ws + n.W.s64),
+                     n.f(n.W.tphi));
+  const unsigned eb = (unsigned)std::min<long>((n.np + 127) / 128, 8192);
+  hipLaunchKernelGGL(k_encode<false>, dim3(eb), dim3(128), 0, s, cfg->nt, cfg->tmodes, n.np, U, u0, n.f(n.W.tphi),
+                     1.f, coef, nullptr);
+  NOCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+int pts_no_adam(size_t n, float* params, const float* grads, float* m, float* v, int step, float lr, float beta1,
+                float beta2, float eps, float grad_scale, pts_stream_t stream) {
+  if (!params || !grads || !m || !v || step < 1 || n == 0) return nofail(PTS_ERR_INVALID_ARG, "pts_no_adam");
+  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(eblocks((long)n)), dim3(256), 0, (hipStream_t)stream, (long)n, params, grads, m, v,
+                     lr, beta1, beta2, eps, grad_scale, c1, c2);
+  NOCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+}  // extern "C"

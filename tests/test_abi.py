@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every entry point include/pts.h declares (no GPU needed)."""
+"""The C-ABI library loads and exports every entry point include/*.h declares (no GPU needed)."""
 import ctypes
 import os
 import re
@@ -8,10 +8,15 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "pts.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pts_[a-z_]+)\s*\(", src)))
+def _declared(header=None):
+    inc = os.path.join(ROOT, "include")
+    names = set()
+    for h in sorted(os.listdir(inc)) if header is None else [header]:
+        if not h.endswith(".h"):
+            continue
+        src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+        names |= set(re.findall(r"\b(pts_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -19,6 +24,9 @@ def test_header_declares_the_boundary():
     for n in ("pts_assemble", "pts_newton_step", "pts_solve", "pts_solve_batched", "pts_workspace_bytes",
               "pts_last_error", "pts_window_bound"):
         assert n in names
+    no = _declared("pts_no.h")
+    for n in ("pts_no_forward", "pts_no_backward", "pts_no_adam", "pts_no_initial_iterate", "pts_no_gemm"):
+        assert n in no
 
 
 def test_library_exports_every_declared_symbol():
@@ -51,3 +59,16 @@ def test_workspace_and_validation_on_host():
     st.nx = 0
     assert lib.pts_workspace_bytes(ctypes.byref(st)) == 0
     assert b"sizes" in lib.pts_last_error()
+
+
+def test_neural_config_validation_on_host():
+    """Parameter count follows the documented layout; invalid widths are rejected."""
+    import paper_2406_00878_amd.neural as N
+    cfg = N.NOConfig(64, 64, 16, width=32, modes=8, layers=2)
+    lib = N._lib()
+    c = cfg.c()
+    import numpy as np
+    assert lib.pts_no_param_count(ctypes.byref(c)) == sum(int(np.prod(s)) for _, s in cfg.layout())
+    assert lib.pts_no_workspace_bytes(ctypes.byref(c)) > 0
+    bad = N.NOConfig(64, 64, 16, width=24).c()
+    assert lib.pts_no_param_count(ctypes.byref(bad)) == 0

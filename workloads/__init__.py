@@ -108,13 +108,18 @@ def fourier_u0_periodic(n: int, seed: int, kmax: int = 8, power: float = 2.0) ->
     rng = np.random.default_rng(seed)
     a = rng.standard_normal(len(modes))
     b = rng.standard_normal(len(modes))
+    # separable evaluation: cos(p + q) = cos p cos q - sin p sin q, sin(p + q) = sin p cos q + cos p sin q
     x = np.arange(n, dtype=np.float64) / n
-    X, Y = np.meshgrid(x, x, indexing="xy")
-    u = np.zeros((n, n))
+    ks = np.arange(-kmax, kmax + 1)
+    cx, sx = np.cos(2 * math.pi * np.outer(ks, x)), np.sin(2 * math.pi * np.outer(ks, x))
+    A = np.zeros((2 * kmax + 1, 2 * kmax + 1))  # [ky, kx] coefficients of cos(2 pi k.x)
+    B = np.zeros_like(A)  # of sin(2 pi k.x)
     for (kx, ky), ak, bk in zip(modes, a, b):
         amp = (kx * kx + ky * ky) ** (-power / 2.0)
-        ph = 2.0 * math.pi * (kx * X + ky * Y)
-        u += amp * (ak * np.cos(ph) + bk * np.sin(ph))
+        A[ky + kmax, kx + kmax] = amp * ak
+        B[ky + kmax, kx + kmax] = amp * bk
+    # u[j, i] = sum_k A (cy cx - sy sx) + B (sy cx + cy sx), rows j = y, columns i = x
+    u = cx.T @ A @ cx - sx.T @ A @ sx + sx.T @ B @ cx + cx.T @ B @ sx
     return _normalize_max(u)
 
 
