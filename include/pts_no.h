@@ -78,8 +78,14 @@ typedef struct pts_no_config {
 /* Number of float32 parameters (layout above). 0 for an invalid configuration. */
 size_t pts_no_param_count(const pts_no_config* cfg);
 
-/* Device workspace for one sample: activations kept for the backward pass and scratch. */
+/* Device workspace for one sample: the spatial and temporal bases, activations kept for the
+   backward pass, and scratch. */
 size_t pts_no_workspace_bytes(const pts_no_config* cfg);
+
+/* Fill the bases of a workspace (the trigonometric basis in x and y and Phi), once after it
+   is allocated and before any other call uses it; the other calls read them and leave them
+   intact. A workspace is tied to its configuration. */
+int pts_no_prepare(const pts_no_config* cfg, void* workspace, size_t workspace_bytes, pts_stream_t stream);
 
 /* U_pred [nt][ny][nx] (float64) from u0 [ny][nx] (float64). Keeps the activations and the
    coefficient fields in the workspace for a following pts_no_backward or
@@ -119,8 +125,9 @@ int pts_no_adam(size_t n, float* params, const float* grads, float* m, float* v,
    a non-finite prediction always falls back. p must be periodic with p->nx = cfg->nx,
    p->ny = cfg->ny, p->nt = cfg->nt. chosen (host int, may be NULL) receives 1 for the
    prediction, 0 for the fallback; res_pred / res_plain (host doubles, may be NULL)
-   receive both norms. solver_ws is a pts_workspace_bytes(p) workspace (its residual
-   buffer is overwritten). Synchronises the stream. */
+   receive both norms. The decision is taken on the device: with all three NULL the call
+   only enqueues work on the stream; otherwise it synchronises the stream to report them.
+   solver_ws is a pts_workspace_bytes(p) workspace (its residual buffer is overwritten). */
 int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const float* params, const double* u0,
                            double* U, void* no_ws, size_t no_ws_bytes, void* solver_ws, size_t solver_ws_bytes,
                            int judge, int* chosen, double* res_pred, double* res_plain, pts_stream_t stream);

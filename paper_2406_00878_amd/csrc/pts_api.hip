@@ -94,7 +94,7 @@ constexpr int kMaxStages = 16;  // Newton iterations overlapped by one wavefront
 constexpr int kMaxWindow = 64;  // longest Theorem-1 window
 
 struct Layout {
-  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, win, total;
+  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, u0copy, win, total;
 };
 
 Layout layout(const pts_problem* p) {
@@ -123,6 +123,8 @@ Layout layout(const pts_problem* p) {
   o = align_up(o + (size_t)(kMaxStages + 1) * p->nt * 8);
   L.res_st = o;
   o = align_up(o + (kMaxStages + 1) * 8);
+  L.u0copy = o;  // copy of u^0 for the wavefront sequences (keeps captured graphs independent of it)
+  o = align_up(o + ns * 8);
   L.win = o;  // Theorem-1 windows: right-hand sides of a window plus two chain vectors
   o = align_up(o + (size_t)(std::min(kMaxWindow, p->nt) + 2) * ns * 8);
   L.total = o;
@@ -666,8 +668,11 @@ struct StageCache {
         return &e;
     return nullptr;
   }
-  void put(const pts_problem* p, double tol, int tag, int sweeps, int passes, int steps) {
+  // keep_max: the entry keeps the largest step count seen with this plan. A sequence with a
+  // spare stage costs two more diagonal launches, one stage short costs a second sequence.
+  void put(const pts_problem* p, double tol, int tag, int sweeps, int passes, int steps, bool keep_max = false) {
     if (E* e = find(p, tol, tag)) {
+      if (keep_max && e->sweeps == sweeps && e->passes == passes) steps = std::max(steps, e->steps);
       e->sweeps = sweeps;
       e->passes = passes;
       e->steps = steps;
@@ -713,6 +718,8 @@ int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& 
 int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
                       hipStream_t s, bool use_graph, Prof* pr, int* launches) {
   if (!use_graph || pr) return launch_wave_sequence(p, kp, wa, g, pl, s, pr, launches);
+  // graphs are keyed on every launch argument; the solver passes u^0 through a workspace
+  // copy, so for a given workspace they differ only with the caller's U
   std::vector<char> key(sizeof(KProb) + sizeof(WaveArgs) + sizeof(Geo) + 3 * sizeof(int));
   char* k = key.data();
   std::memcpy(k, &kp, sizeof kp);
@@ -744,9 +751,9 @@ int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa,
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(PTS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   wg.key = key;
-  if (g_wave_graphs.size() >= 8) {
-    for (auto& old : g_wave_graphs) (void)hipGraphExecDestroy(old.exec);
-    g_wave_graphs.clear();
+  if (g_wave_graphs.size() >= 32) {  // drop the oldest
+    (void)hipGraphExecDestroy(g_wave_graphs.front().exec);
+    g_wave_graphs.erase(g_wave_graphs.begin());
   }
   g_wave_graphs.push_back(wg);
   HIPCHK(hipGraphLaunch(wg.exec, s));
@@ -774,6 +781,8 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
   double* dU2 = (double*)(wsb + in.L.dU2);
   unsigned long long* rho_st = (unsigned long long*)(wsb + in.L.rho_st);
   unsigned long long* res_st = (unsigned long long*)(wsb + in.L.res_st);
+  double* u0w = (double*)(wsb + in.L.u0copy);
+  HIPCHK(hipMemcpyAsync(u0w, u0, (size_t)p->nx * p->ny * 8, hipMemcpyDeviceToDevice, s));
   int launches = 0, it = 0;
   const size_t st_count = (size_t)p->nx * p->ny * p->nt;
   rc = in.residual(U, u0, s, &launches, false);
@@ -848,7 +857,7 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     wa.Ur[1] = U1;
     wa.dUr[0] = in.dU;
     wa.dUr[1] = dU2;
-    wa.u0 = u0;
+    wa.u0 = u0w;
     wa.rho_in = (const double*)in.rho;
     wa.rho_st = rho_st;
     wa.res_st = res_st;
@@ -890,7 +899,7 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     // remember the step count for this plan (an autotuned plan stays the cached one)
     const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
     if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
-      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(needed, 1));
+      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(needed, 1), true);
   }
   if (st) {
     st->iterations = it;
@@ -1254,38 +1263,35 @@ int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const
   if (rc) return rc;
   Instance in;
   in.bind(p, solver_ws);
-  double* hs;
-  if ((rc = host_scalars(&hs))) return rc;
   int dummy = 0;
   const size_t ns = (size_t)p->nx * p->ny;
-  // residual of the prediction, in the judge's norm
-  if ((rc = in.residual(U, u0, s, &dummy, judge == PTS_NO_JUDGE_ACCUMULATED))) return rc;
-  if (judge == PTS_NO_JUDGE_ACCUMULATED) {
-    const unsigned blocks = (unsigned)std::min<size_t>((ns + 255) / 256, kUpdateBlocks);
-    hipLaunchKernelGGL(k_cumsum_absmax, dim3(blocks), dim3(256), 0, s, ns, p->nt, in.R, in.partial);
+  const bool acc = judge == PTS_NO_JUDGE_ACCUMULATED;
+  // residual of the prediction in the judge's norm -> scal[0]
+  if ((rc = in.residual(U, u0, s, &dummy, acc))) return rc;
+  if (acc) {
+    const unsigned blocks = (unsigned)std::min<size_t>((ns + 63) / 64, kUpdateBlocks);
+    hipLaunchKernelGGL(k_cumsum_absmax, dim3(blocks), dim3(64), 0, s, ns, p->nt, in.R, in.partial);
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, in.partial, (size_t)blocks, in.scal);
-    HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipMemcpyAsync(hs, in.scal, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const double rp = hs[0];
   // the plain iterate's residual is -tau F(u^0) at every level (u^n - u^{n-1} = 0), i.e. the
-  // one-level residual at u^0; its accumulated form at level n is n times that
+  // one-level residual at u^0 (-> scal[2]); its accumulated form at level n is n times that
   pts_problem one = *p;
   one.nt = 1;
-  if ((rc = launch_residual(&one, kprob(&one), u0, u0, nullptr, nullptr, in.rho, in.scal, s))) return rc;
-  HIPCHK(hipMemcpyAsync(hs, in.scal, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const double r0 = hs[0] * (judge == PTS_NO_JUDGE_ACCUMULATED ? (double)p->nt : 1.0);
-  const bool use = std::isfinite(rp) && rp < r0;
-  if (!use) {
-    const unsigned blocks = (unsigned)std::min<size_t>((ns * p->nt + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_broadcast, dim3(blocks), dim3(256), 0, s, ns, p->nt, U, u0);
-    HIPCHK(hipGetLastError());
+  if ((rc = launch_residual(&one, kprob(&one), u0, u0, nullptr, nullptr, in.rho, in.scal + 2, s))) return rc;
+  const double mult = acc ? (double)p->nt : 1.0;
+  const unsigned blocks = (unsigned)std::min<size_t>((ns * p->nt + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_judge_apply, dim3(blocks), dim3(256), 0, s, ns, p->nt, U, u0, in.scal, mult);
+  HIPCHK(hipGetLastError());
+  if (chosen || res_pred || res_plain) {
+    double* hs;
+    if ((rc = host_scalars(&hs))) return rc;
+    HIPCHK(hipMemcpyAsync(hs, in.scal, 4 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rp = hs[0], r0 = hs[2] * mult;
+    if (chosen) *chosen = (std::isfinite(rp) && rp < r0) ? 1 : 0;
+    if (res_pred) *res_pred = rp;
+    if (res_plain) *res_plain = r0;
   }
-  if (chosen) *chosen = use ? 1 : 0;
-  if (res_pred) *res_pred = rp;
-  if (res_plain) *res_plain = r0;
   return PTS_OK;
 }
 

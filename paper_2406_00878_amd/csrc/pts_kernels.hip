@@ -523,23 +523,49 @@ __global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ a, si
 }
 
 // part[b] = max over the block's points p of max_n |sum_{m<=n} R[m][p]| (NaN propagates):
-// the block forward substitution of Eq. (7) with identity diagonal blocks. Grid-stride
-// over the ns points of a level; fold part with k_absmax.
-__global__ __launch_bounds__(256) void k_cumsum_absmax(size_t ns, int nt, const double* __restrict__ R,
-                                                       double* __restrict__ part) {
+// the block forward substitution of Eq. (7) with identity diagonal blocks. 64-thread work-
+// groups, grid-stride over the ns points of a level, levels read four at a time; fold part
+// with k_absmax.
+__global__ __launch_bounds__(64) void k_cumsum_absmax(size_t ns, int nt, const double* __restrict__ R,
+                                                      double* __restrict__ part) {
   double m = 0.0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)blockIdx.x * 64 + threadIdx.x; i < ns; i += (size_t)gridDim.x * 64) {
     double acc = 0.0;
-    for (int n = 0; n < nt; ++n) {
+    int n = 0;
+    for (; n + 4 <= nt; n += 4) {
+      const double r0 = R[(size_t)n * ns + i], r1 = R[(size_t)(n + 1) * ns + i];
+      const double r2 = R[(size_t)(n + 2) * ns + i], r3 = R[(size_t)(n + 3) * ns + i];
+      acc += r0;
+      m = nanmax(m, fabs(acc));
+      acc += r1;
+      m = nanmax(m, fabs(acc));
+      acc += r2;
+      m = nanmax(m, fabs(acc));
+      acc += r3;
+      m = nanmax(m, fabs(acc));
+    }
+    for (; n < nt; ++n) {
       acc += R[(size_t)n * ns + i];
       m = nanmax(m, fabs(acc));
     }
   }
   m = wave_max(m);
-  __shared__ double red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Judge of the learned initial iterate, decided on the device: with rp = max|R| of the
+// prediction already in U (bits at scal[0]) and r0 = mult * max|R| of the plain iterate
+// (bits at scal[2]), U keeps the prediction if rp is finite and rp < r0, else U <- u^0 at
+// every level. Every thread evaluates the same decision.
+__global__ __launch_bounds__(256) void k_judge_apply(size_t ns, int nt, double* __restrict__ U,
+                                                     const double* __restrict__ u0,
+                                                     const unsigned long long* __restrict__ scal, double mult) {
+  const double rp = __longlong_as_double(scal[0]);
+  const double r0 = __longlong_as_double(scal[2]) * mult;
+  if (isfinite(rp) && rp < r0) return;
+  const size_t total = ns * (size_t)nt;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+    U[i] = u0[i % ns];
 }
 
 // u^n = u^0 at every level (the plain Newton start).

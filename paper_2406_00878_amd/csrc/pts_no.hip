@@ -38,14 +38,21 @@ struct Gemm {
   float alpha, beta;
   int ksplit;       // K ranges per product; > 1 writes partial tiles to P
   float* P;         // [batch][ksplit][M][N] partials (ksplit > 1)
+  const float* bias;  // optional epilogue (ksplit == 1): c += bias[m], then act = GELU(c)
+  float* act;         // same layout as C
 };
 
-constexpr int BM = 64, BN = 64, BK = 16;
+__device__ __forceinline__ float gelu(float z);
 
-// grid: x = N tiles, y = M tiles, z = batch * ksplit; 256 threads (4 waves, 32 x 32 each)
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int kStage = BM * BK / 256;  // elements of A (and of B) each thread stages per K step
+
+// grid: x = N tiles, y = M tiles, z = batch * ksplit; 256 threads (4 waves, 32 x 32 each).
+// Staging follows the unit stride of each operand (coalesced loads for either layout), and
+// the next K step is loaded into registers while the current one is multiplied.
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
-  __shared__ unsigned short As[BM][BK + 4];
-  __shared__ unsigned short Bs[BK][BN + 4];
+  __shared__ unsigned short As[BM][BK + 2];
+  __shared__ unsigned short Bs[BK][BN + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
   const int b = blockIdx.z / g.ksplit, sp = blockIdx.z % g.ksplit;
@@ -53,43 +60,58 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   const float* B = g.B + (long)b * g.bsb;
   const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
   const int kbeg = sp * kchunk, kend = min(g.K, kbeg + kchunk);
+  const bool a_mfast = g.sam == 1 && g.sak != 1;  // A contiguous along m
+  const bool b_kfast = g.sbk == 1 && g.sbn != 1;  // B contiguous along k
   float4_t acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // stage A (64 x 16) and B (16 x 64): 4 elements per thread each
+  float ra[kStage], rb[kStage];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < kStage; ++r) {
       const int e = tid + r * 256;
-      const int am = e / BK, ak = e % BK;
+      const int am = a_mfast ? e % BM : e / BK, ak = a_mfast ? e / BM : e % BK;
       const int gm = m0 + am, gk = k0 + ak;
-      const float av = (gm < g.M && gk < kend) ? A[(long)gm * g.sam + (long)gk * g.sak] : 0.f;
-      As[am][ak] = f2bf(av);
-      const int bk = e / BN, bn = e % BN;
+      ra[r] = (gm < g.M && gk < kend) ? A[(long)gm * g.sam + (long)gk * g.sak] : 0.f;
+      const int bk = b_kfast ? e % BK : e / BN, bn = b_kfast ? e / BK : e % BN;
       const int gk2 = k0 + bk, gn = n0 + bn;
-      const float bv = (gk2 < kend && gn < g.N) ? B[(long)gk2 * g.sbk + (long)gn * g.sbn] : 0.f;
-      Bs[bk][bn] = f2bf(bv);
+      rb[r] = (gk2 < kend && gn < g.N) ? B[(long)gk2 * g.sbk + (long)gn * g.sbn] : 0.f;
+    }
+  };
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int r = 0; r < kStage; ++r) {
+      const int e = tid + r * 256;
+      const int am = a_mfast ? e % BM : e / BK, ak = a_mfast ? e / BM : e % BK;
+      As[am][ak] = f2bf(ra[r]);
+      const int bk = b_kfast ? e % BK : e / BN, bn = b_kfast ? e / BK : e % BN;
+      Bs[bk][bn] = f2bf(rb[r]);
     }
     __syncthreads();
-    const int kq = 4 * (lane >> 4);
+    if (k0 + BK < kend) load(k0 + BK);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int row = wm + 16 * i + (lane & 15);
-      short4_t a;
-      a[0] = (short)As[row][kq];
-      a[1] = (short)As[row][kq + 1];
-      a[2] = (short)As[row][kq + 2];
-      a[3] = (short)As[row][kq + 3];
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = wn + 16 * j + (lane & 15);
-        short4_t bb;
-        bb[0] = (short)Bs[kq][col];
-        bb[1] = (short)Bs[kq + 1][col];
-        bb[2] = (short)Bs[kq + 2][col];
-        bb[3] = (short)Bs[kq + 3][col];
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + 16 * i + (lane & 15);
+        short4_t a;
+        a[0] = (short)As[row][kq];
+        a[1] = (short)As[row][kq + 1];
+        a[2] = (short)As[row][kq + 2];
+        a[3] = (short)As[row][kq + 3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn + 16 * j + (lane & 15);
+          short4_t bb;
+          bb[0] = (short)Bs[kq][col];
+          bb[1] = (short)Bs[kq + 1][col];
+          bb[2] = (short)Bs[kq + 2][col];
+          bb[3] = (short)Bs[kq + 3][col];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -107,8 +129,14 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
         if (g.ksplit > 1) {
           g.P[(((long)b * g.ksplit + sp) * g.M + gm) * g.N + gn] = acc[i][j][r];
         } else {
-          float* c = g.C + (long)b * g.bsc + (long)gm * g.scm + (long)gn * g.scn;
-          *c = g.alpha * acc[i][j][r] + (g.beta != 0.f ? g.beta * *c : 0.f);
+          const long off = (long)b * g.bsc + (long)gm * g.scm + (long)gn * g.scn;
+          float* c = g.C + off;
+          float val = g.alpha * acc[i][j][r] + (g.beta != 0.f ? g.beta * *c : 0.f);
+          if (g.bias) {
+            val += g.bias[gm];
+            g.act[off] = gelu(val);
+          }
+          *c = val;
         }
       }
 }
@@ -128,7 +156,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(Gemm g, int batch) {
 }
 
 // ------------------------------------------------------------------ elementwise
-__device__ __forceinline__ float gelu(float z) {
+__device__ __forceinline__ float gelu(float z) {  // tanh form
   const float a = 0.7978845608028654f * (z + 0.044715f * z * z * z);
   const float t = 1.f - 2.f / (expf(2.f * a) + 1.f);  // tanh(a)
   return 0.5f * z * (1.f + t);
@@ -158,16 +186,6 @@ __global__ void k_lift(int C, long np, const float* __restrict__ lw, const float
   for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < C * np; t += (long)gridDim.x * 256) {
     const int c = (int)(t / np);
     v0[t] = lw[c] * (float)u0[t % np] + lb[c];
-  }
-}
-
-// z[c][p] += b[c]; y = gelu(z)
-__global__ void k_bias_gelu(int C, long np, const float* __restrict__ b, float* __restrict__ z,
-                            float* __restrict__ y) {
-  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < C * np; t += (long)gridDim.x * 256) {
-    const float zz = z[t] + b[t / np];
-    z[t] = zz;
-    y[t] = gelu(zz);
   }
 }
 
@@ -216,109 +234,133 @@ __device__ __forceinline__ Block block_of(int m, int ky, int kx) {
   return b;
 }
 
-// what = mix(vhat); one thread per (output channel, frequency block)
-__global__ void k_mix(int C, int m, const float* __restrict__ R, const float* __restrict__ vh,
-                      float* __restrict__ wh) {
-  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= C * nb) return;
-  const int co = t / nb, blk = t % nb;
+// Sum over the 32 lanes of each half of a wave (the halves stay separate).
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// what = mix(vhat). One wave per (frequency block, pair of output channels): each half of
+// the wave takes one output channel and splits the input channels over its 32 lanes.
+__global__ __launch_bounds__(256) void k_mix(int C, int m, const float* __restrict__ R, const float* __restrict__ vh,
+                                             float* __restrict__ wh) {
+  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1), pairs = C / 2;
+  const int gw = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+  if (gw >= nb * pairs) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63, l = lane & 31;
+  const int blk = gw / pairs, co = 2 * (gw % pairs) + (lane >> 5);
   const Block b = block_of(m, blk / m, blk % m);
-  const float* r[4];
-  for (int i = 0; i < b.n; ++i) r[i] = R + ((long)b.q[i] * C + co) * C;
-  float* w = wh + (long)co * Q;
-  if (b.n == 4) {
-    float pc = 0.f, ps = 0.f, mc = 0.f, ms = 0.f;
-    for (int c = 0; c < C; ++c) {
-      const float* v = vh + (long)c * Q;
+  const long CC = (long)C * C;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  for (int c = l; c < C; c += 32) {
+    const float* v = vh + (long)c * Q;
+    const long o = (long)co * C + c;
+    if (b.n == 4) {
       const float A = v[b.q[0]], B = v[b.q[1]], Cc = v[b.q[2]], D = v[b.q[3]];
       const float Pc = 0.5f * (A - D), Ps = 0.5f * (B + Cc), Mc = 0.5f * (A + D), Ms = 0.5f * (B - Cc);
-      const float ap = r[0][c], bp = r[1][c], am = r[2][c], bm = r[3][c];
-      pc += ap * Pc + bp * Ps;
-      ps += ap * Ps - bp * Pc;
-      mc += am * Mc + bm * Ms;
-      ms += am * Ms - bm * Mc;
-    }
-    w[b.q[0]] = pc + mc;
-    w[b.q[3]] = mc - pc;
-    w[b.q[1]] = ps + ms;
-    w[b.q[2]] = ps - ms;
-  } else if (b.n == 2) {
-    float ac = 0.f, as = 0.f;
-    for (int c = 0; c < C; ++c) {
-      const float* v = vh + (long)c * Q;
+      const float ap = R[b.q[0] * CC + o], bp = R[b.q[1] * CC + o], am = R[b.q[2] * CC + o], bm = R[b.q[3] * CC + o];
+      s0 += ap * Pc + bp * Ps;
+      s1 += ap * Ps - bp * Pc;
+      s2 += am * Mc + bm * Ms;
+      s3 += am * Ms - bm * Mc;
+    } else if (b.n == 2) {
       const float A = v[b.q[0]], S = v[b.q[1]];
-      ac += r[0][c] * A + r[1][c] * S;
-      as += r[0][c] * S - r[1][c] * A;
+      const float al = R[b.q[0] * CC + o], be = R[b.q[1] * CC + o];
+      s0 += al * A + be * S;
+      s1 += al * S - be * A;
+    } else {
+      s0 += R[o] * v[0];
     }
-    w[b.q[0]] = ac;
-    w[b.q[1]] = as;
+  }
+  s0 = half_sum(s0);
+  s1 = half_sum(s1);
+  s2 = half_sum(s2);
+  s3 = half_sum(s3);
+  if (l != 0) return;
+  float* w = wh + (long)co * Q;
+  if (b.n == 4) {  // s0..s3 = P_c', P_s', M_c', M_s'
+    w[b.q[0]] = s0 + s2;
+    w[b.q[3]] = s2 - s0;
+    w[b.q[1]] = s1 + s3;
+    w[b.q[2]] = s1 - s3;
+  } else if (b.n == 2) {
+    w[b.q[0]] = s0;
+    w[b.q[1]] = s1;
   } else {
-    float a = 0.f;
-    for (int c = 0; c < C; ++c) a += r[0][c] * vh[(long)c * Q];
-    w[0] = a;
+    w[0] = s0;
   }
 }
 
-// Adjoint of k_mix: dvhat (written) and dR (accumulated); one thread per (input channel, block),
-// so every dR entry has one writer.
-__global__ void k_mix_back(int C, int m, const float* __restrict__ R, const float* __restrict__ vh,
-                           const float* __restrict__ dwh, float* __restrict__ dvh, float* __restrict__ dR) {
-  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1);
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= C * nb) return;
-  const int c = t / nb, blk = t % nb;
+// Adjoint of k_mix: dvhat (written) and dR (accumulated). One wave per (frequency block,
+// pair of input channels); the lanes of each half split the output channels, so every dR
+// entry has one writer.
+__global__ __launch_bounds__(256) void k_mix_back(int C, int m, const float* __restrict__ R,
+                                                  const float* __restrict__ vh, const float* __restrict__ dwh,
+                                                  float* __restrict__ dvh, float* __restrict__ dR) {
+  const int nb = m * m, Q = (2 * m - 1) * (2 * m - 1), pairs = C / 2;
+  const int gw = (int)((blockIdx.x * 256u + threadIdx.x) >> 6);
+  if (gw >= nb * pairs) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63, l = lane & 31;
+  const int blk = gw / pairs, c = 2 * (gw % pairs) + (lane >> 5);
   const Block b = block_of(m, blk / m, blk % m);
+  const long CC = (long)C * C;
   const float* v = vh + (long)c * Q;
-  float* dv = dvh + (long)c * Q;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f;
   if (b.n == 4) {
     const float A = v[b.q[0]], B = v[b.q[1]], Cc = v[b.q[2]], D = v[b.q[3]];
     const float Pc = 0.5f * (A - D), Ps = 0.5f * (B + Cc), Mc = 0.5f * (A + D), Ms = 0.5f * (B - Cc);
-    float gPc = 0.f, gPs = 0.f, gMc = 0.f, gMs = 0.f;
-    for (int co = 0; co < C; ++co) {
+    for (int co = l; co < C; co += 32) {
       const float* d = dwh + (long)co * Q;
       const float dA = d[b.q[0]], dB = d[b.q[1]], dC = d[b.q[2]], dD = d[b.q[3]];
       const float dPc = dA - dD, dMc = dA + dD, dPs = dB + dC, dMs = dB - dC;
       const long o = (long)co * C + c;
-      const float ap = R[(long)b.q[0] * C * C + o], bp = R[(long)b.q[1] * C * C + o];
-      const float am = R[(long)b.q[2] * C * C + o], bm = R[(long)b.q[3] * C * C + o];
-      gPc += ap * dPc - bp * dPs;
-      gPs += bp * dPc + ap * dPs;
-      gMc += am * dMc - bm * dMs;
-      gMs += bm * dMc + am * dMs;
-      dR[(long)b.q[0] * C * C + o] += dPc * Pc + dPs * Ps;
-      dR[(long)b.q[1] * C * C + o] += dPc * Ps - dPs * Pc;
-      dR[(long)b.q[2] * C * C + o] += dMc * Mc + dMs * Ms;
-      dR[(long)b.q[3] * C * C + o] += dMc * Ms - dMs * Mc;
+      const float ap = R[b.q[0] * CC + o], bp = R[b.q[1] * CC + o], am = R[b.q[2] * CC + o], bm = R[b.q[3] * CC + o];
+      g0 += ap * dPc - bp * dPs;
+      g1 += bp * dPc + ap * dPs;
+      g2 += am * dMc - bm * dMs;
+      g3 += bm * dMc + am * dMs;
+      dR[b.q[0] * CC + o] += dPc * Pc + dPs * Ps;
+      dR[b.q[1] * CC + o] += dPc * Ps - dPs * Pc;
+      dR[b.q[2] * CC + o] += dMc * Mc + dMs * Ms;
+      dR[b.q[3] * CC + o] += dMc * Ms - dMs * Mc;
     }
-    dv[b.q[0]] = 0.5f * (gPc + gMc);
-    dv[b.q[3]] = 0.5f * (gMc - gPc);
-    dv[b.q[1]] = 0.5f * (gPs + gMs);
-    dv[b.q[2]] = 0.5f * (gPs - gMs);
   } else if (b.n == 2) {
     const float A = v[b.q[0]], S = v[b.q[1]];
-    float gA = 0.f, gS = 0.f;
-    for (int co = 0; co < C; ++co) {
+    for (int co = l; co < C; co += 32) {
       const float* d = dwh + (long)co * Q;
       const float dA = d[b.q[0]], dS = d[b.q[1]];
       const long o = (long)co * C + c;
-      const float al = R[(long)b.q[0] * C * C + o], be = R[(long)b.q[1] * C * C + o];
-      gA += al * dA - be * dS;
-      gS += be * dA + al * dS;
-      dR[(long)b.q[0] * C * C + o] += dA * A + dS * S;
-      dR[(long)b.q[1] * C * C + o] += dA * S - dS * A;
+      const float al = R[b.q[0] * CC + o], be = R[b.q[1] * CC + o];
+      g0 += al * dA - be * dS;
+      g1 += be * dA + al * dS;
+      dR[b.q[0] * CC + o] += dA * A + dS * S;
+      dR[b.q[1] * CC + o] += dA * S - dS * A;
     }
-    dv[b.q[0]] = gA;
-    dv[b.q[1]] = gS;
   } else {
     const float A = v[0];
-    float g = 0.f;
-    for (int co = 0; co < C; ++co) {
+    for (int co = l; co < C; co += 32) {
       const long o = (long)co * C + c;
-      g += R[o] * dwh[(long)co * Q];
+      g0 += R[o] * dwh[(long)co * Q];
       dR[o] += dwh[(long)co * Q] * A;
     }
-    dv[0] = g;
+  }
+  g0 = half_sum(g0);
+  g1 = half_sum(g1);
+  g2 = half_sum(g2);
+  g3 = half_sum(g3);
+  if (l != 0) return;
+  float* dv = dvh + (long)c * Q;
+  if (b.n == 4) {  // g0..g3 = gradients of P_c, P_s, M_c, M_s
+    dv[b.q[0]] = 0.5f * (g0 + g2);
+    dv[b.q[3]] = 0.5f * (g2 - g0);
+    dv[b.q[1]] = 0.5f * (g1 + g3);
+    dv[b.q[2]] = 0.5f * (g1 - g3);
+  } else if (b.n == 2) {
+    dv[b.q[0]] = g0;
+    dv[b.q[1]] = g1;
+  } else {
+    dv[0] = g0;
   }
 }
 
@@ -373,23 +415,30 @@ __global__ __launch_bounds__(256) void k_tbasis(int nt, int K, double* __restric
 }
 
 // U[n][p] = u0[p] + sum_k Phi[n][k] (coef[k][p] + pb[k]) in float32, stored as float64.
-// grid: x over points (grid-stride), y over chunks of kSynthLevels levels.
+// grid: x over points (grid-stride), y over chunks of kSynthLevels levels; the chunk's rows
+// of Phi are staged in LDS.
+// KT > 0 fixes K at compile time (no per-mode guards); KT = 0 is the generic form.
 constexpr int kSynthLevels = 32;
+template <int KT>
 __global__ __launch_bounds__(256) void k_synth(int nt, int K, long np, const double* __restrict__ u0,
                                                const float* __restrict__ coef, const float* __restrict__ pb,
                                                const float* __restrict__ phi, double* __restrict__ U) {
+  __shared__ float ph[kSynthLevels * kMaxT];
   const int n0 = blockIdx.y * kSynthLevels, n1 = min(nt, n0 + kSynthLevels);
+  for (int e = threadIdx.x; e < (n1 - n0) * K; e += 256) ph[e] = phi[(long)n0 * K + e];
+  __syncthreads();
   for (long p = (long)blockIdx.x * 256 + threadIdx.x; p < np; p += (long)gridDim.x * 256) {
-    float c[kMaxT];
+    constexpr int KM = KT ? KT : kMaxT;
+    float c[KM];
 #pragma unroll
-    for (int k = 0; k < kMaxT; ++k) c[k] = k < K ? coef[(long)k * np + p] + pb[k] : 0.f;
+    for (int k = 0; k < KM; ++k) c[k] = (KT || k < K) ? coef[(long)k * np + p] + pb[k] : 0.f;
     const double base = u0[p];
     for (int n = n0; n < n1; ++n) {
-      const float* f = phi + (long)n * K;
+      const float* f = ph + (n - n0) * K;
       float acc = 0.f;
 #pragma unroll
-      for (int k = 0; k < kMaxT; ++k)
-        if (k < K) acc += f[k] * c[k];
+      for (int k = 0; k < KM; ++k)
+        if (KT || k < K) acc += f[k] * c[k];
       U[(long)n * np + p] = base + (double)acc;
     }
   }
@@ -398,27 +447,28 @@ __global__ __launch_bounds__(256) void k_synth(int nt, int K, long np, const dou
 // out[k][p] = scale * sum_n Phi[n][k] (A[n][p] - B[p or n][p]); with DIFF, B is [nt][np] and
 // the block partial sums of (A - B)^2 go to part[blockIdx.x]; else B is u0 [np].
 // 128 threads per block, grid-stride over points.
-template <bool DIFF>
+template <bool DIFF, int KT>
 __global__ __launch_bounds__(128) void k_encode(int nt, int K, long np, const double* __restrict__ A,
                                                 const double* __restrict__ B, const float* __restrict__ phi,
                                                 float scale, float* __restrict__ out, double* __restrict__ part) {
   double lsum = 0.0;
   for (long p = (long)blockIdx.x * 128 + threadIdx.x; p < np; p += (long)gridDim.x * 128) {
-    float acc[kMaxT];
+    constexpr int KM = KT ? KT : kMaxT;
+    float acc[KM];
 #pragma unroll
-    for (int k = 0; k < kMaxT; ++k) acc[k] = 0.f;
+    for (int k = 0; k < KM; ++k) acc[k] = 0.f;
     for (int n = 0; n < nt; ++n) {
       const double d = A[(long)n * np + p] - (DIFF ? B[(long)n * np + p] : B[p]);
       if (DIFF) lsum += d * d;
       const float df = (float)d;
       const float* f = phi + (long)n * K;
 #pragma unroll
-      for (int k = 0; k < kMaxT; ++k)
-        if (k < K) acc[k] += f[k] * df;
+      for (int k = 0; k < KM; ++k)
+        if (KT || k < K) acc[k] += f[k] * df;
     }
 #pragma unroll
-    for (int k = 0; k < kMaxT; ++k)
-      if (k < K) out[(long)k * np + p] = scale * acc[k];
+    for (int k = 0; k < KM; ++k)
+      if (KT || k < K) out[(long)k * np + p] = scale * acc[k];
   }
   if (DIFF) {
     __shared__ double red[128];
@@ -453,20 +503,34 @@ __global__ __launch_bounds__(256) void k_coef_diff(int K, long np, const float* 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// loss[0] += sum(part) / n (one block, fixed order)
-__global__ void k_mse_finish(int nb, long n, const double* __restrict__ part, double* __restrict__ loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nb; ++i) s += part[i];
-    loss[0] += s / (double)n;
+// loss[0] += sum(part) / n: one work-group of 256, strided partial sums then a fixed tree
+// (deterministic)
+__global__ __launch_bounds__(256) void k_mse_finish(int nb, long n, const double* __restrict__ part,
+                                                    double* __restrict__ loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) loss[0] += red[0] / (double)n;
 }
 
-// row sums of a [rows][len] float array accumulated into out[rows] (one block per row)
-__global__ __launch_bounds__(256) void k_rowsum(long len, const float* __restrict__ a, float* __restrict__ out) {
-  const float* r = a + (long)blockIdx.x * len;
+// Row sums (W == nullptr) or row dot products with a float64 vector w of a [rows][len] float
+// array, in two passes: grid (kRowSlices, rows) writes per-slice partials to part, then
+// k_row_fold adds each row's partials in order into out[row] (accumulated).
+constexpr int kRowSlices = 64;
+__global__ __launch_bounds__(256) void k_row_partial(long len, const float* __restrict__ a,
+                                                     const double* __restrict__ w, float* __restrict__ part) {
+  const int row = blockIdx.y, sl = blockIdx.x;
+  const long chunk = (len + kRowSlices - 1) / kRowSlices;
+  const long beg = (long)sl * chunk, end = min(len, beg + chunk);
+  const float* r = a + (long)row * len;
   float s = 0.f;
-  for (long t = threadIdx.x; t < len; t += 256) s += r[t];
+  for (long t = beg + threadIdx.x; t < end; t += 256) s += w ? r[t] * (float)w[t] : r[t];
   __shared__ float red[256];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -474,23 +538,14 @@ __global__ __launch_bounds__(256) void k_rowsum(long len, const float* __restric
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] += red[0];
+  if (threadIdx.x == 0) part[(long)row * kRowSlices + sl] = red[0];
 }
-
-// out[c] += sum_p a[c][p] * w[p] (one block per row); w is float64 (u0)
-__global__ __launch_bounds__(256) void k_rowdot(long len, const float* __restrict__ a, const double* __restrict__ w,
-                                                float* __restrict__ out) {
-  const float* r = a + (long)blockIdx.x * len;
+__global__ void k_row_fold(int rows, const float* __restrict__ part, float* __restrict__ out) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
   float s = 0.f;
-  for (long t = threadIdx.x; t < len; t += 256) s += r[t] * (float)w[t];
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[blockIdx.x] += red[0];
+  for (int i = 0; i < kRowSlices; ++i) s += part[(long)row * kRowSlices + i];
+  out[row] += s;
 }
 
 __global__ void k_adam(long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -578,7 +633,7 @@ Par par_layout(const pts_no_config* c) {
 
 // workspace offsets (bytes, 256-aligned)
 struct Ws {
-  size_t phix, phiy, tphi, s64, v, z, vh, wh, t1, t2, coef, dcoef, dv, dv2, dz, dvh, dwh, part, gpart, total;
+  size_t phix, phiy, tphi, s64, v, z, vh, wh, t1, t2, coef, dcoef, dv, dv2, dz, dvh, dwh, part, gpart, rpart, total;
 };
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
 constexpr int kSplit = 32;
@@ -611,17 +666,40 @@ Ws ws_layout(const pts_no_config* c) {
   w.dwh = take(C * Q * 4);
   w.part = take(kPartSlots * 8);
   w.gpart = take((size_t)kSplit * std::max((size_t)c->tmodes, C) * C * 4);
+  w.rpart = take((size_t)kMaxT * kRowSlices * 4);
   w.total = o;
   return w;
 }
+
+// out[row] += sum_t a[row][t] (w[t]) for rows x len (w may be NULL); part holds rows * kRowSlices floats
+void row_reduce(hipStream_t s, int rows, long len, const float* a, const double* w, float* part, float* out) {
+  hipLaunchKernelGGL(k_row_partial, dim3(kRowSlices, rows), dim3(256), 0, s, len, a, w, part);
+  hipLaunchKernelGGL(k_row_fold, dim3((rows + 63) / 64), dim3(64), 0, s, rows, part, out);
+}
+
+// launches of k_synth / k_encode with the mode count fixed at compile time where it is 8, 16 or 32
+void launch_synth(hipStream_t s, dim3 grid, int nt, int K, long np, const double* u0, const float* coef,
+                  const float* pb, const float* phi, double* U) {
+  auto k = K == 8 ? k_synth<8> : K == 16 ? k_synth<16> : K == 32 ? k_synth<32> : k_synth<0>;
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, s, nt, K, np, u0, coef, pb, phi, U);
+}
+template <bool DIFF>
+void launch_encode(hipStream_t s, unsigned blocks, int nt, int K, long np, const double* A, const double* B,
+                   const float* phi, float scale, float* out, double* part) {
+  auto k = K == 8 ? k_encode<DIFF, 8> : K == 16 ? k_encode<DIFF, 16> : K == 32 ? k_encode<DIFF, 32> : k_encode<DIFF, 0>;
+  hipLaunchKernelGGL(k, dim3(blocks), dim3(128), 0, s, nt, K, np, A, B, phi, scale, out, part);
+}
+
+// work-groups of k_mix / k_mix_back: one wave per (frequency block, channel pair), 4 per group
+unsigned mix_blocks(int C, int m) { return (unsigned)((m * m * (C / 2) + 3) / 4); }
 
 unsigned eblocks(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192); }
 
 // C = alpha op(A) op(B) + beta C via k_gemm; ksplit > 1 needs P scratch
 int gemm(hipStream_t s, int M, int N, int K, float alpha, const float* A, long sam, long sak, long bsa,
          const float* B, long sbk, long sbn, long bsb, float beta, float* C, long scm, long scn, long bsc,
-         int batch = 1, int ksplit = 1, float* P = nullptr) {
-  Gemm g{A, B, C, M, N, K, sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc, alpha, beta, ksplit, P};
+         int batch = 1, int ksplit = 1, float* P = nullptr, const float* bias = nullptr, float* act = nullptr) {
+  Gemm g{A, B, C, M, N, K, sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc, alpha, beta, ksplit, P, bias, act};
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)(batch * ksplit));
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
   if (ksplit > 1) hipLaunchKernelGGL(k_gemm_reduce, dim3(eblocks((long)batch * M * N)), dim3(256), 0, s, g, batch);
@@ -680,7 +758,7 @@ struct Net {
     // projection: dpw += dcoef v_L^T (K = np, split), dpb += rowsum(dcoef), dv = pw^T dcoef
     if ((rc = gemm(s, K, C, (int)np, 1.f, dco, np, 1, 0, vL, 1, np, 0, 1.f, grads + P.pw, C, 1, 0, 1, kSplit, gp)))
       return rc;
-    hipLaunchKernelGGL(k_rowsum, dim3(K), dim3(256), 0, s, np, dco, grads + P.pb);
+    row_reduce(s, K, np, dco, nullptr, f(W.rpart), grads + P.pb);
     float* dv = f(W.dv);
     float* dv2 = f(W.dv2);
     float* dz = f(W.dz);
@@ -690,7 +768,7 @@ struct Net {
     for (int l = c->layers - 1; l >= 0; --l) {
       float* vin = v(l);
       hipLaunchKernelGGL(k_gelu_back, dim3(eblocks(C * np)), dim3(256), 0, s, C * np, z(l), dv, dz);
-      hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, s, np, dz, grads + P.b[l]);
+      row_reduce(s, C, np, dz, nullptr, f(W.rpart), grads + P.b[l]);
       // dW += dz v^T ; dv2 = W^T dz
       if ((rc = gemm(s, C, C, (int)np, 1.f, dz, np, 1, 0, vin, 1, np, 0, 1.f, grads + P.W[l], C, 1, 0, 1, kSplit,
                      gp)))
@@ -701,7 +779,7 @@ struct Net {
       if ((rc = gemm(s, C * ny, m2, nx, 1.f, dz, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0))) return rc;
       if ((rc = gemm(s, m2, m2, ny, 1.f, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, f(W.dwh), m2, 1, Q, C)))
         return rc;
-      hipLaunchKernelGGL(k_mix_back, dim3((C * c->modes * c->modes + 255) / 256), dim3(256), 0, s, C, c->modes,
+      hipLaunchKernelGGL(k_mix_back, dim3(mix_blocks(C, c->modes)), dim3(256), 0, s, C, c->modes,
                          params + P.R[l], vh(l),
                          f(W.dwh), f(W.dvh), grads + P.R[l]);
       // dv2 += (1/np) phiy dvhat phix^T (adjoint of the forward transform)
@@ -713,8 +791,8 @@ struct Net {
       std::swap(dv, dv2);
     }
     // lift: dlw += sum_p dv0 u0, dlb += sum_p dv0
-    hipLaunchKernelGGL(k_rowdot, dim3(C), dim3(256), 0, s, np, dv, u0, grads + P.lw);
-    hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, s, np, dv, grads + P.lb);
+    row_reduce(s, C, np, dv, u0, f(W.rpart), grads + P.lw);
+    row_reduce(s, C, np, dv, nullptr, f(W.rpart), grads + P.lb);
     NOCHK(hipGetLastError());
     return PTS_OK;
   }
@@ -732,6 +810,22 @@ size_t pts_no_param_count(const pts_no_config* cfg) {
 size_t pts_no_workspace_bytes(const pts_no_config* cfg) {
   if (valid(cfg)) return 0;
   return ws_layout(cfg).total;
+}
+
+int pts_no_prepare(const pts_no_config* cfg, void* workspace, size_t workspace_bytes, pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (!workspace) return nofail(PTS_ERR_INVALID_ARG, "pts_no_prepare: NULL");
+  if (workspace_bytes < ws_layout(cfg).total) return nofail(PTS_ERR_WORKSPACE, "pts_no_prepare: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace);
+  hipLaunchKernelGGL(k_basis, dim3((n.nx * n.m2 + 255) / 256), dim3(256), 0, s, n.nx, cfg->modes, n.f(n.W.phix));
+  hipLaunchKernelGGL(k_basis, dim3((n.ny * n.m2 + 255) / 256), dim3(256), 0, s, n.ny, cfg->modes, n.f(n.W.phiy));
+  hipLaunchKernelGGL(k_tbasis, dim3(1), dim3(256), 0, s, cfg->nt, cfg->tmodes, (double*)(n.ws + n.W.s64),
+                     n.f(n.W.tphi));
+  NOCHK(hipGetLastError());
+  return PTS_OK;
 }
 
 int pts_no_gemm(int M, int N, int K, float alpha, const float* A, long sam, long sak, long bsa, const float* B,
@@ -753,8 +847,6 @@ int pts_no_forward(const pts_no_config* cfg, const float* params, const double* 
   n.bind(cfg, workspace);
   const int C = n.C;
   const long np = n.np;
-  hipLaunchKernelGGL(k_basis, dim3((n.nx * n.m2 + 255) / 256), dim3(256), 0, s, n.nx, cfg->modes, n.f(n.W.phix));
-  hipLaunchKernelGGL(k_basis, dim3((n.ny * n.m2 + 255) / 256), dim3(256), 0, s, n.ny, cfg->modes, n.f(n.W.phiy));
   hipLaunchKernelGGL(k_lift, dim3(eblocks(C * np)), dim3(256), 0, s, C, np, params + n.P.lw, params + n.P.lb, u0,
                      n.v(0));
   for (int l = 0; l < cfg->layers; ++l) {
@@ -762,24 +854,23 @@ int pts_no_forward(const pts_no_config* cfg, const float* params, const double* 
     float* z = n.z(l);
     // spectral part into z, then z += W v (pointwise channel mix)
     if ((rc = n.forward_transform(s, vin, n.vh(l)))) return rc;
-    hipLaunchKernelGGL(k_mix, dim3((C * cfg->modes * cfg->modes + 255) / 256), dim3(256), 0, s, C, cfg->modes,
+    hipLaunchKernelGGL(k_mix, dim3(mix_blocks(C, cfg->modes)), dim3(256), 0, s, C, cfg->modes,
                        params + n.P.R[l], n.vh(l),
                        n.f(n.W.wh));
     if ((rc = n.inverse_transform(s, n.f(n.W.wh), z, 0.f))) return rc;
-    if ((rc = gemm(s, C, (int)np, C, 1.f, params + n.P.W[l], C, 1, 0, vin, np, 1, 0, 1.f, z, np, 1, 0))) return rc;
-    hipLaunchKernelGGL(k_bias_gelu, dim3(eblocks(C * np)), dim3(256), 0, s, C, np, params + n.P.b[l], z, n.v(l + 1));
+    // z += W v + b, v_{l+1} = GELU(z) in the product's epilogue
+    if ((rc = gemm(s, C, (int)np, C, 1.f, params + n.P.W[l], C, 1, 0, vin, np, 1, 0, 1.f, z, np, 1, 0, 1, 1, nullptr,
+                   params + n.P.b[l], n.v(l + 1))))
+      return rc;
   }
   // coefficient fields coef[K][np] = pw v_L (bias added by the consumers)
   if ((rc = gemm(s, cfg->tmodes, (int)np, C, 1.f, params + n.P.pw, C, 1, 0, n.v(cfg->layers), np, 1, 0, 0.f,
                  n.f(n.W.coef), np, 1, 0)))
     return rc;
   if (U_pred) {
-    hipLaunchKernelGGL(k_tbasis, dim3(1), dim3(256), 0, s, cfg->nt, cfg->tmodes, (double*)(n.ws + n.W.s64),
-                       n.f(n.W.tphi));
     dim3 grid(std::min<unsigned>((unsigned)((np + 255) / 256), 2048u),
               (unsigned)((cfg->nt + kSynthLevels - 1) / kSynthLevels));
-    hipLaunchKernelGGL(k_synth, grid, dim3(256), 0, s, cfg->nt, cfg->tmodes, np, u0, n.f(n.W.coef),
-                       params + n.P.pb, n.f(n.W.tphi), U_pred);
+    launch_synth(s, grid, cfg->nt, cfg->tmodes, np, u0, n.f(n.W.coef), params + n.P.pb, n.f(n.W.tphi), U_pred);
   }
   NOCHK(hipGetLastError());
   return PTS_OK;
@@ -800,9 +891,9 @@ int pts_no_backward(const pts_no_config* cfg, const float* params, const double*
   // dL/dc = Phi^T dL/dU with dL/dU = 2 (U_pred - U_true) / count; loss partials alongside
   double* part = (double*)(n.ws + n.W.part);
   const unsigned eb = (unsigned)std::min<long>((n.np + 127) / 128, kPartSlots);
-  hipLaunchKernelGGL(k_encode<true>, dim3(eb), dim3(128), 0, s, cfg->nt, cfg->tmodes, n.np, U_pred, U_true,
-                     n.f(n.W.tphi), (float)(2.0 / (double)count), n.f(n.W.dcoef), part);
-  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, s, (int)eb, count, part, loss);
+  launch_encode<true>(s, eb, cfg->nt, cfg->tmodes, n.np, U_pred, U_true, n.f(n.W.tphi), (float)(2.0 / (double)count),
+                      n.f(n.W.dcoef), part);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(256), 0, s, (int)eb, count, part, loss);
   NOCHK(hipGetLastError());
   return n.backward_from_coef(s, params, u0, grads);
 }
@@ -822,7 +913,7 @@ int pts_no_backward_coef(const pts_no_config* cfg, const float* params, const do
   const unsigned eb = std::min<unsigned>(eblocks((long)cfg->tmodes * n.np), kPartSlots);
   hipLaunchKernelGGL(k_coef_diff, dim3(eb), dim3(256), 0, s, cfg->tmodes, n.np, n.f(n.W.coef), params + n.P.pb,
                      coef_true, (float)(2.0 / (double)count), n.f(n.W.dcoef), part);
-  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, s, (int)eb, count, part, loss);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(256), 0, s, (int)eb, count, part, loss);
   NOCHK(hipGetLastError());
   return n.backward_from_coef(s, params, u0, grads);
 }
@@ -836,11 +927,8 @@ int pts_no_encode(const pts_no_config* cfg, const double* u0, const double* U, f
   hipStream_t s = (hipStream_t)stream;
   Net n;
   n.bind(cfg, workspace);
-  hipLaunchKernelGGL(k_tbasis, dim3(1), dim3(256), 0, s, cfg->nt, cfg->tmodes, (double*)(n.ws + n.W.s64),
-                     n.f(n.W.tphi));
   const unsigned eb = (unsigned)std::min<long>((n.np + 127) / 128, 8192);
-  hipLaunchKernelGGL(k_encode<false>, dim3(eb), dim3(128), 0, s, cfg->nt, cfg->tmodes, n.np, U, u0, n.f(n.W.tphi),
-                     1.f, coef, nullptr);
+  launch_encode<false>(s, eb, cfg->nt, cfg->tmodes, n.np, U, u0, n.f(n.W.tphi), 1.f, coef, nullptr);
   NOCHK(hipGetLastError());
   return PTS_OK;
 }

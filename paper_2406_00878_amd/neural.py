@@ -38,6 +38,7 @@ def _lib():
         sig = {
             "pts_no_param_count": (S, [P]),
             "pts_no_workspace_bytes": (S, [P]),
+            "pts_no_prepare": (I, [P, V, S, V]),
             "pts_no_forward": (I, [P, V, V, V, V, S, V]),
             "pts_no_backward": (I, [P, V, V, V, V, V, V, V, S, V]),
             "pts_no_backward_coef": (I, [P, V, V, V, V, V, V, S, V]),
@@ -98,6 +99,7 @@ class NeuralOperator:
         raw = torch.empty(nb + 256, dtype=torch.uint8, device=device)
         off = (-raw.data_ptr()) % 256
         self.ws = raw[off:off + nb]
+        _check(lib.pts_no_prepare(C.byref(self._c), _ptr(self.ws), self.ws.numel(), _stream(None)))
         self.params = self.init_params(seed).to(device)
         self.grads = torch.zeros_like(self.params)
         self.m = torch.zeros_like(self.params)
@@ -169,15 +171,19 @@ class NeuralOperator:
         _check(_lib().pts_no_adam(self.n_params, _ptr(self.params), _ptr(self.grads), _ptr(self.m), _ptr(self.v),
                                   self.step, lr, beta1, beta2, eps, grad_scale, _stream(stream)))
 
-    def initial_iterate(self, prob, u0, U, solver_ws=None, judge="accumulated", stream=None) -> dict:
-        """U <- prediction if its Newton residual beats the plain iterate's, else plain."""
+    def initial_iterate(self, prob, u0, U, solver_ws=None, judge="accumulated", report=True,
+                        stream=None) -> Optional[dict]:
+        """U <- prediction if its Newton residual beats the plain iterate's, else plain. The
+        decision is taken on the device; with report=False nothing is read back (no sync)."""
         p = make_problem(prob, "fp64")
         solver_ws = workspace(prob, "fp64", U.device) if solver_ws is None else solver_ws
         ch, rp, r0 = C.c_int(0), C.c_double(0), C.c_double(0)
+        refs = (C.byref(ch), C.byref(rp), C.byref(r0)) if report else (None, None, None)
         _check(_lib().pts_no_initial_iterate(C.cast(C.pointer(p), C.c_void_p), C.byref(self._c), _ptr(self.params),
                                              _ptr(u0), _ptr(U), _ptr(self.ws), self.ws.numel(), _ptr(solver_ws),
-                                             solver_ws.numel(), JUDGES[judge], C.byref(ch), C.byref(rp),
-                                             C.byref(r0), _stream(stream)))
+                                             solver_ws.numel(), JUDGES[judge], *refs, _stream(stream)))
+        if not report:
+            return None
         return {"chosen": "learned" if ch.value else "plain", "res_pred": rp.value, "res_plain": r0.value}
 
 

@@ -235,7 +235,7 @@ TRAIN_CFG = NO.NOConfig(nx=32, ny=32, nt=16, width=16, modes=8, layers=2, tmodes
 
 
 def _burgers(i, seed=91):
-    s = np.random.SeedSequence(seed).spawn(i + 1)[i]
+    s = np.random.SeedSequence(seed, spawn_key=(i,))
     u0 = W.fourier_u0_periodic(32, int(s.generate_state(1)[0]))
     return W.burgers_periodic(32, 16, 5e-4, 0.005, u0, name=f"b32_{i}")
 

@@ -189,7 +189,7 @@ def burgers512_disc(nt: int = 1024, seed: int = 2406003) -> Problem:
 
 def burgers256_learned(nt: int = 256, seed: int = 2406055, index: int = 0) -> Problem:
     """Viscous Burgers nu = 0.005, periodic 256^2, dt = 5e-4 (learned-iterate workload)."""
-    s = np.random.SeedSequence(seed).spawn(index + 1)[index]
+    s = np.random.SeedSequence(seed, spawn_key=(index,))  # child `index` of SeedSequence(seed).spawn
     u0 = fourier_u0_periodic(256, int(s.generate_state(1)[0]))
     return burgers_periodic(256, nt, 5e-4, 0.005, u0, name=f"burgers256nu005_nt{nt}_{index}")
 
