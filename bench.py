@@ -267,7 +267,8 @@ def main():
           f"res={st['res_inf'][-1]:.2e}", file=sys.stderr, flush=True)
 
     # dominant kernel (per-level solve): average launch duration from HIP events recorded
-    # on the launch stream during one extra, profiled solve
+    # on the launch stream during one extra, profiled solve (wavefront schedule: events
+    # around each back-to-back sequence, divided by its launches)
     P.init_plain(prob, U, u0)
     sched = {1: "bulk", 2: "pipeline"}.get(st["schedule"], "auto")
     pst = P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, profile=True,

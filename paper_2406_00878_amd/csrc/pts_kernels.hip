@@ -344,6 +344,9 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
   __shared__ double om[kMaxSweeps];
   __shared__ double red[2][kWaves];
+  // U_j^n and U_{j+1}^{n-1} of the region parked in LDS while the inner solve runs (they
+  // are needed again only afterwards; kept in registers they would spill)
+  __shared__ double park[2][kRows][kThreads];
   const int tiles_per_level = gridDim.x / a.stages;
   const int j = blockIdx.x / tiles_per_level;
   const int tile = blockIdx.x % tiles_per_level;
@@ -391,6 +394,11 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
     rs.X[k] = 0.0;
     rs.set_row(k, r5);
   }
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    park[0][k][threadIdx.x] = uc[k];
+    park[1][k][threadIdx.x] = upn[k];
+  }
   __syncthreads();  // omega table
   rs.run(passes, sweeps, false, om, lds_raw, wave, lane);
 
@@ -398,7 +406,10 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
   // residual and radius of the next iterate on the tile
   double unew[kRows];
 #pragma unroll
-  for (int k = 0; k < kRows; ++k) unew[k] = uc[k] + rs.X[k];
+  for (int k = 0; k < kRows; ++k) {
+    unew[k] = park[0][k][threadIdx.x] + rs.X[k];
+    upn[k] = park[1][k][threadIdx.x];
+  }
   int par = 0;
   const YNb<double> yn = y_exchange<double>(unew, lds_raw, par, wave, lane);
   double rmax = 0.0, gmax = 0.0;
