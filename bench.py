@@ -29,6 +29,44 @@ sys.path.insert(0, ROOT)
 METRIC = "converged space-time DOF/s at 1e-8 rel. err vs FP64 oracle; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_level_wave launch of the default workload and plan, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs (profiles/k_level_wave_burgers256x512_fp64_hbm_counters.md),
+# each scaled by the counter's reading for a 1 GiB fill / 1 GiB sum (--hbm-calibration).
+# Valid only for the kernel sources they were taken with (sha256 of the files below).
+TRAFFIC = {"kernel_sha256": "ce00a6efe60888e16c8224df570393e93d648a761fb2d2b4ed3db36fc712aad2",
+           "fetch_bytes": 26469793, "write_bytes": 6184448}
+KERNEL_SOURCES = ["paper_2406_00878_amd/csrc/pts_kernels.hip", "paper_2406_00878_amd/csrc/pts_device.hpp"]
+
+
+def kernel_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Counter-measured HBM bytes per launch of the default workload's k_level_wave, or None
+    when the kernel sources differ from the ones the counters were taken with."""
+    if TRAFFIC["kernel_sha256"] is None or TRAFFIC["kernel_sha256"] != kernel_sha256():
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
+def hbm_calibration():
+    """Known-size HBM traffic for scaling byte counters: a 1 GiB fill (writes) and, after a
+    second 1 GiB fill that evicts it from the caches, a 1 GiB sum (reads)."""
+    import torch
+    n = 256 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    evict = torch.ones(n, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    total = float(src.sum())
+    del evict
+    print(f"[bench] hbm calibration: 1 GiB fill, 1 GiB sum = {total:.0f}", file=sys.stderr, flush=True)
+
 
 def workload(name):
     import workloads as W
@@ -208,6 +246,10 @@ def main():
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="skip the inner-plan autotuner")
+    ap.add_argument("--sweeps", type=int, default=0, help="explicit inner Chebyshev sweeps (0 = tuned/auto)")
+    ap.add_argument("--passes", type=int, default=0, help="explicit inner passes (0 = tuned/auto)")
+    ap.add_argument("--hbm-calibration", action="store_true",
+                    help="after the bench, run a 1 GiB fill and a 1 GiB sum (counter calibration)")
     ap.add_argument("--learned", action="store_true",
                     help="learned-iterate workload (Burgers nu = 0.005, 256^2 x 256): train, then compare starts")
     ap.add_argument("--train-samples", type=int, default=2000)
@@ -237,6 +279,10 @@ def main():
     U = torch.empty((prob.nt, prob.ny, prob.nx), dtype=torch.float64, device=dev)
     ws = P.workspace(prob, args.precision, dev)
     opts = dict(schedule=args.schedule, use_graph=not args.no_graph)
+    if args.sweeps > 0:
+        opts["sweeps"] = args.sweeps
+    if args.passes > 0:
+        opts["refine"] = args.passes - 1
     print(f"[bench] {args.workload} {prob.nx}x{prob.ny}x{prob.nt} {args.precision} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
 
@@ -271,8 +317,9 @@ def main():
     # around each back-to-back sequence, divided by its launches)
     P.init_plain(prob, U, u0)
     sched = {1: "bulk", 2: "pipeline"}.get(st["schedule"], "auto")
+    popts = {k: v for k, v in opts.items() if k in ("sweeps", "refine")}
     pst = P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, profile=True,
-                  schedule=sched)
+                  schedule=sched, **popts)
     torch.cuda.synchronize()
     n_ls = max(pst["prof_count"][1], 1)
     avg_ms = pst["prof_ms"][1] / n_ls
@@ -302,7 +349,9 @@ def main():
                    "schedule": {1: "bulk", 2: "wavefront"}.get(st["schedule"], st["schedule"]),
                    "autotuned": tuned is not None, **extra},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (args.workload == "burgers256" and args.precision == "fp64")
+                     else None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu_baseline:
@@ -310,6 +359,8 @@ def main():
         out["cpu_baseline"] = cb
         out["rel_err_vs_oracle"] = {"value": err, "levels_checked": levels}
     print(json.dumps(out), flush=True)
+    if args.hbm_calibration:
+        hbm_calibration()
 
 
 if __name__ == "__main__":

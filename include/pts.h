@@ -118,9 +118,9 @@ typedef struct pts_stats {
   double solve_ms;               /* wall time inside pts_solve (host clock)    */
   /* filled when pts_options.profile = 1: summed kernel time (ms) and launch count
      per kernel class: [0] residual, [1] per-level solve, [2] update + reductions,
-     [3] other (fills, initial iterate). HIP events bracket each launch, except in
-     the wavefront schedule, where they bracket each back-to-back sequence of
-     per-level solve launches (time / count is then the mean launch interval)     */
+     [3] other (fills, initial iterate). HIP events bracket each launch, except for
+     the per-level solves, where they bracket each back-to-back chain (bulk) or
+     sequence (wavefront) of launches: time / count is the mean launch interval  */
   double prof_ms[4];
   int32_t prof_count[4];
   /* algorithmic bytes moved by the per-level solve launches of the solve

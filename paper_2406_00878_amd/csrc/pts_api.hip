@@ -242,12 +242,16 @@ int launch_residual(const pts_problem* p, const KProb& kp, const double* U, cons
 struct Prof;
 void prof_begin(Prof* pr, int kind, hipStream_t s);
 void prof_end(Prof* pr, hipStream_t s, double bytes);
+void prof_end_count(Prof* pr, hipStream_t s, double bytes, int count);  // interval covering `count` launches
 
 int launch_chain(const pts_problem* p, const KProb& kp, const double* U, const double* R, double* dU, double* Xs,
                  const double* rho, const Plan& pl, const Geo& g, hipStream_t s, int* launches, Prof* pr) {
   const size_t ns = (size_t)p->nx * p->ny;
   const int nb = tiles(p, g);
   const int nl = (int)pl.packs.size();
+  // profiling brackets the whole chain (per-launch events would add their own overhead)
+  prof_begin(pr, 1, s);
+  double bytes = 0.0;
   for (int n = 0; n < p->nt; ++n) {
     const double* prev = n == 0 ? nullptr : dU + (size_t)(n - 1) * ns;
     double* out = dU + (size_t)n * ns;
@@ -255,17 +259,17 @@ int launch_chain(const pts_problem* p, const KProb& kp, const double* U, const d
     const double* xin = nullptr;
     for (int l = 0; l < nl; ++l) {
       double* xo = ((nl - 1 - l) % 2 == 0) ? out : Xs;
-      prof_begin(pr, 1, s);
       const bool per = p->bc == PTS_PERIODIC;
       auto kern = pl.fp32 ? (per ? k_level_solve<float, 1> : k_level_solve<float, 0>)
                           : (per ? k_level_solve<double, 1> : k_level_solve<double, 0>);
       hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, kp, n, U, R + (size_t)n * ns, prev, xin, xo, rho,
                          g, pl.packs[l], pl.sweeps);
-      prof_end(pr, s, 8.0 * (double)ns * (3 + (prev ? 1 : 0) + (xin ? 1 : 0)));
+      bytes += 8.0 * (double)ns * (3 + (prev ? 1 : 0) + (xin ? 1 : 0));
       xin = xo;
       ++*launches;
     }
   }
+  prof_end_count(pr, s, bytes, p->nt * nl);
   HIPCHK(hipGetLastError());
   return PTS_OK;
 }
@@ -389,6 +393,12 @@ void prof_end(Prof* pr, hipStream_t s, double bytes) {
   if (pr) {
     pr->end(s);
     pr->bytes += bytes;
+  }
+}
+void prof_end_count(Prof* pr, hipStream_t s, double bytes, int count) {
+  if (pr) {
+    prof_end(pr, s, bytes);
+    pr->recs.back().count = count;
   }
 }
 
