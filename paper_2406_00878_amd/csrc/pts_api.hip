@@ -1129,6 +1129,189 @@ int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, i
 
 }  // namespace
 
+// ---------------------------------------------------------------- batched bulk solve
+// Workspace of a batch: a header with the instance descriptors and the (instance, tile)
+// work items, then every instance's own workspace.
+size_t batch_header_bytes(const pts_problem* probs, int nprob) {
+  size_t tiles_total = 0;
+  for (int i = 0; i < nprob; ++i) tiles_total += (size_t)tiles(probs + i, geometry(probs + i));
+  return align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
+}
+
+// Pinned staging for the descriptor upload (the batched solve synchronises every Newton step
+// before it writes the staging again).
+struct HostStage {
+  char* h = nullptr;
+  size_t n = 0;
+};
+thread_local HostStage g_stage;
+int host_stage(size_t bytes, char** out) {
+  if (g_stage.n < bytes) {
+    if (g_stage.h) HIPCHK(hipHostFree(g_stage.h));
+    g_stage.h = nullptr;
+    g_stage.n = 0;
+    HIPCHK(hipHostMalloc((void**)&g_stage.h, bytes, hipHostMallocDefault));
+    g_stage.n = bytes;
+  }
+  *out = g_stage.h;
+  return PTS_OK;
+}
+
+// Newton on every instance at once: per step, the all-level residuals, then for each level n
+// and launch l of the inner plans one launch over the tiles of every instance that has them
+// (k_level_solve_batched), then the updates. Instances leave the batch when they converge.
+int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
+                       int max_iter, char* header, char* wsb, const pts_options* o, pts_stats* stats,
+                       hipStream_t s) {
+  std::vector<Instance> in(nprob);
+  std::vector<int> ntiles(nprob);
+  char* w = wsb;
+  int maxnt = 0;
+  size_t tiles_total = 0;
+  for (int i = 0; i < nprob; ++i) {
+    in[i].bind(probs + i, w);
+    w += in[i].L.total;
+    ntiles[i] = tiles(probs + i, in[i].g);
+    tiles_total += ntiles[i];
+    maxnt = std::max(maxnt, probs[i].nt);
+    if (stats) std::memset(stats + i, 0, sizeof(pts_stats));
+  }
+  BatchDesc* d_desc = (BatchDesc*)header;
+  int2* d_items = (int2*)(header + align_up((size_t)nprob * sizeof(BatchDesc)));
+  const size_t stage_bytes = (size_t)nprob * sizeof(BatchDesc) + tiles_total * sizeof(int2) + (size_t)nprob * 24;
+  char* stage;
+  int rc = host_stage(stage_bytes, &stage);
+  if (rc) return rc;
+  BatchDesc* h_desc = (BatchDesc*)stage;
+  int2* h_items = (int2*)(stage + (size_t)nprob * sizeof(BatchDesc));
+  double* h_sc = (double*)(stage + (size_t)nprob * sizeof(BatchDesc) + tiles_total * sizeof(int2));
+  const bool fp32 = probs[0].precision == PTS_MIXED;
+  const bool per = probs[0].bc == PTS_PERIODIC;
+  auto kern = fp32 ? (per ? k_level_solve_batched<float, 1> : k_level_solve_batched<float, 0>)
+                   : (per ? k_level_solve_batched<double, 1> : k_level_solve_batched<double, 0>);
+
+  std::vector<char> active(nprob, 1);
+  std::vector<Plan> plans(nprob);
+  int launches = 0, worst = PTS_OK;
+  auto read_all = [&](bool with_rms) -> int {
+    for (int i = 0; i < nprob; ++i) {
+      if (!active[i]) continue;
+      HIPCHK(hipMemcpyAsync(h_sc + 3 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
+      if (with_rms) HIPCHK(hipMemcpyAsync(h_sc + 3 * i + 2, in[i].rms, 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return PTS_OK;
+  };
+  for (int i = 0; i < nprob; ++i)
+    if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
+  if ((rc = read_all(false))) return rc;
+  for (int it = 0;; ++it) {
+    int nactive = 0;
+    for (int i = 0; i < nprob; ++i) {
+      if (!active[i]) continue;
+      const pts_problem* p = probs + i;
+      const double res = h_sc[3 * i], rhom = h_sc[3 * i + 1];
+      pts_stats* st = stats ? stats + i : nullptr;
+      if (st) {
+        if (it < PTS_MAX_HIST) {
+          st->res_inf[it] = res;
+          st->rho_max[it] = rhom;
+          if (it > 0) st->upd_rms[it] = std::sqrt(h_sc[3 * i + 2] / ((double)p->nx * p->ny * p->nt));
+        }
+        st->iterations = it;
+        st->hist = std::min(it + 1, PTS_MAX_HIST);
+        st->slab = p->nt;
+        st->window = 1;
+        st->schedule = PTS_SCHED_BULK;
+      }
+      int err = PTS_OK;
+      if (!std::isfinite(res) || !std::isfinite(rhom)) {
+        err = fail(PTS_ERR_NONFINITE, "instance %d: non-finite residual at Newton step %d", i, it);
+      } else if (res <= tol) {
+        if (st) st->converged = 1;
+        active[i] = 0;
+        continue;
+      } else if (rhom >= 1.0) {
+        err = fail(PTS_ERR_SINGULAR, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom);
+      } else if (it >= max_iter) {
+        err = fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i, it,
+                   res);
+      }
+      if (err) {
+        if (!worst) worst = err;
+        active[i] = 0;
+        continue;
+      }
+      plans[i] = make_plan(p, o, std::min(rhom * 1.02, 0.999), in[i].g);
+      if (st) {
+        st->sweeps = plans[i].sweeps;
+        st->refine = plans[i].passes - 1;
+      }
+      ++nactive;
+    }
+    if (nactive == 0) break;
+    // descriptors (inactive instances have no launches) and work items, longest first
+    std::vector<int> order;
+    for (int i = 0; i < nprob; ++i) {
+      BatchDesc& d = h_desc[i];
+      std::memset(&d, 0, sizeof d);
+      d.p = in[i].kp;
+      d.g = in[i].g;
+      d.U = U[i];
+      d.R = in[i].R;
+      d.dU = in[i].dU;
+      d.Xs = in[i].Xs;
+      d.rho = (const double*)in[i].rho;
+      if (active[i]) {
+        d.npacks = (int)std::min<size_t>(plans[i].packs.size(), kMaxPacks);
+        d.sweeps = plans[i].sweeps;
+        for (int l = 0; l < d.npacks; ++l) d.packs[l] = plans[i].packs[l];
+        order.push_back(i);
+      }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].nt > probs[b].nt; });
+    size_t nitems = 0;
+    for (int i : order)
+      for (int t = 0; t < ntiles[i]; ++t) h_items[nitems++] = make_int2(i, t);
+    HIPCHK(hipMemcpyAsync(d_desc, h_desc, (size_t)nprob * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_items, h_items, nitems * sizeof(int2), hipMemcpyHostToDevice, s));
+    // level n: the prefix of instances with nt > n; as many launches as the longest plan among them
+    std::vector<size_t> cum(order.size() + 1, 0);
+    std::vector<int> lmax(order.size() + 1, 0);
+    for (size_t q = 0; q < order.size(); ++q) {
+      cum[q + 1] = cum[q] + ntiles[order[q]];
+      lmax[q + 1] = std::max(lmax[q], h_desc[order[q]].npacks);
+    }
+    std::vector<size_t> cnt(maxnt, 0);
+    std::vector<int> lcount(maxnt, 0);
+    for (int n = 0, k = (int)order.size(); n < maxnt; ++n) {  // the prefix shrinks as n grows
+      while (k > 0 && probs[order[k - 1]].nt <= n) --k;
+      cnt[n] = cum[k];
+      lcount[n] = lmax[k];
+    }
+    for (int n = 0; n < maxnt; ++n) {
+      if (cnt[n] == 0) continue;
+      for (int l = 0; l < lcount[n]; ++l) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)cnt[n]), dim3(kThreads), 0, s, d_desc, d_items, n, l);
+        ++launches;
+      }
+    }
+    HIPCHK(hipGetLastError());
+    for (int i : order) {
+      const size_t count = (size_t)probs[i].nx * probs[i].ny * probs[i].nt;
+      hipLaunchKernelGGL(k_update, dim3(kUpdateBlocks), dim3(256), 0, s, count, U[i], in[i].dU, in[i].partial);
+      hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in[i].partial, kUpdateBlocks, in[i].rms);
+      launches += 2;
+      if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    if ((rc = read_all(true))) return rc;
+  }
+  if (stats)
+    for (int i = 0; i < nprob; ++i) stats[i].launches = launches;
+  return worst;
+}
+
 extern "C" {
 
 const char* pts_last_error(void) { return g_err.c_str(); }
@@ -1321,7 +1504,7 @@ size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob) {
     if (validate(probs + i)) return 0;
     t += layout(probs + i).total;
   }
-  return t;
+  return batch_header_bytes(probs, nprob) + t;
 }
 
 int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
@@ -1330,12 +1513,27 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, con
   const size_t need = pts_workspace_bytes_batched(probs, nprob);
   if (need == 0) return PTS_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < need) return fail(PTS_ERR_WORKSPACE, "batched workspace too small");
-  char* w = (char*)workspace;
+  if ((uintptr_t)workspace % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "NULL array list");
+  for (int i = 0; i < nprob; ++i)
+    if (!U[i] || !u0[i]) return fail(PTS_ERR_INVALID_ARG, "instance %d: NULL array", i);
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
+  bool uniform = true;
+  for (int i = 1; i < nprob; ++i)
+    uniform = uniform && probs[i].bc == probs[0].bc && probs[i].precision == probs[0].precision;
+  const bool shared = uniform && !(opts && (opts->schedule == PTS_SCHED_PIPELINE || opts->window > 1));
+  char* w = (char*)workspace + batch_header_bytes(probs, nprob);
+  if (shared) return solve_batched_bulk(probs, nprob, U, u0, tol, max_iter, (char*)workspace, w, opts, stats,
+                                        (hipStream_t)stream);
+  // one instance after another (mixed boundary kinds or precisions, the wavefront schedule,
+  // Theorem-1 windows)
   int worst = PTS_OK;
   for (int i = 0; i < nprob; ++i) {
     const size_t b = layout(probs + i).total;
-    int rc = pts_solve(probs + i, U[i], u0[i], tol, max_iter, w, b, opts, stats ? stats + i : nullptr, stream);
-    if (rc && !worst) worst = rc;
+    int r = pts_solve(probs + i, U[i], u0[i], tol, max_iter, w, b, opts, stats ? stats + i : nullptr, stream);
+    if (r && !worst) worst = r;
     w += b;
   }
   return worst;

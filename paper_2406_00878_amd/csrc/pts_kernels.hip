@@ -266,20 +266,18 @@ __device__ __forceinline__ bool in_tile(const Geo& g, const KProb& p, int lane, 
 // Bulk schedule, one launch per level (or per group of passes of a level):
 // X = A_n^{-1}(rn + dUprev), rn the level's right-hand side (r^n for the block inverse of
 // Eq. (7), or a Theorem-1 chain vector), dUprev (nullable) du^{n-1}. Xin (nullable) is the
-// starting iterate from a previous launch; Xout receives the tile values.
+// starting iterate from a previous launch; Xout receives the tile values. One work-group
+// per tile of the level.
 template <typename T, int BC>
-__global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const double* __restrict__ U,
-                                                          const double* __restrict__ rn,
-                                                          const double* __restrict__ dUprev,
-                                                          const double* __restrict__ Xin,
-                                                          double* __restrict__ Xout,
-                                                          const double* __restrict__ rho_lvl, Geo g,
-                                                          int passes, int sweeps) {
-  __shared__ double lds_raw[2 * kWaves * 2 * 64];
-  __shared__ double om[kMaxSweeps];
+__device__ __forceinline__ void level_solve_tile(const KProb& p, int n, int tile, const double* __restrict__ U,
+                                                 const double* __restrict__ rn,
+                                                 const double* __restrict__ dUprev,
+                                                 const double* __restrict__ Xin, double* __restrict__ Xout,
+                                                 const double* __restrict__ rho_lvl, const Geo& g, int passes,
+                                                 int sweeps, double* lds_raw, double* om) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int tx = blockIdx.x % g.tilesx, ty = blockIdx.x / g.tilesx;
+  const int tx = tile % g.tilesx, ty = tile / g.tilesx;
   const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
   const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
   const size_t ns = (size_t)p.nx * p.ny;
@@ -316,6 +314,58 @@ __global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const 
     const int row = wave * kRows + k;
     if (idx[k] != ~0u && in_tile(g, p, lane, row, gx, ry0 + row)) st(Xout, idx[k], rs.X[k]);
   }
+}
+
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const double* __restrict__ U,
+                                                          const double* __restrict__ rn,
+                                                          const double* __restrict__ dUprev,
+                                                          const double* __restrict__ Xin,
+                                                          double* __restrict__ Xout,
+                                                          const double* __restrict__ rho_lvl, Geo g,
+                                                          int passes, int sweeps) {
+  __shared__ double lds_raw[2 * kWaves * 2 * 64];
+  __shared__ double om[kMaxSweeps];
+  level_solve_tile<T, BC>(p, n, blockIdx.x, U, rn, dUprev, Xin, Xout, rho_lvl, g, passes, sweeps, lds_raw, om);
+}
+
+// Batched bulk schedule: independent instances with their own sizes, level counts and
+// inner plans. Launch (n, l) solves, for every instance that has level n and at least
+// l + 1 launches in its plan, launch l of that level (packs[l] passes of its sweeps, the
+// same ping-pong between its scratch level and du^n as the one-instance chain). Work items
+// are (instance, tile) pairs sorted by level count, so the grid of level n is a prefix.
+constexpr int kMaxPacks = 64;
+struct BatchDesc {
+  KProb p;
+  Geo g;
+  const double* U;
+  const double* R;
+  double* dU;
+  double* Xs;
+  const double* rho;
+  int npacks;  // launches per level of this instance's plan (0: instance inactive)
+  int sweeps;
+  int packs[kMaxPacks];
+};
+
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDesc* __restrict__ descs,
+                                                                  const int2* __restrict__ items, int n, int l) {
+  __shared__ double lds_raw[2 * kWaves * 2 * 64];
+  __shared__ double om[kMaxSweeps];
+  const int2 it = items[blockIdx.x];
+  const BatchDesc* d = descs + it.x;
+  const int nl = d->npacks;
+  if (n >= d->p.nt || l >= nl) return;  // uniform over the work-group
+  const KProb p = d->p;
+  const Geo g = d->g;
+  const size_t ns = (size_t)p.nx * p.ny;
+  double* out = d->dU + (size_t)n * ns;
+  double* xo = ((nl - 1 - l) % 2 == 0) ? out : d->Xs;
+  const double* xin = l == 0 ? nullptr : (((nl - l) % 2 == 0) ? out : d->Xs);
+  const double* prev = n == 0 ? nullptr : d->dU + (size_t)(n - 1) * ns;
+  level_solve_tile<T, BC>(p, n, it.y, d->U, d->R + (size_t)n * ns, prev, xin, xo, d->rho, g, d->packs[l], d->sweeps,
+                          lds_raw, om);
 }
 
 // ---------------------------------------------------------- wavefront schedule

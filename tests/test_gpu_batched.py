@@ -1,0 +1,84 @@
+"""Batched solves of independent instances with uneven grids and level counts (one launch per
+level and inner launch over every instance's tiles) against the time-stepping oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2406_00878_amd as P
+import workloads as W
+from oracle import sequential
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _heat_batch(seed, sizes, dt=1e-3):
+    rng = np.random.default_rng(seed)
+    return [W.heat_dirichlet(n, L, dt, W.sine_u0_dirichlet(n, rng), name=f"h{n}x{L}") for n, L in sizes]
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-12, 1e-10), ("mixed", 1e-12, 1e-8)])
+def test_uneven_heat_batch_matches_oracle(precision, tol, bar):
+    # sizes span one whole-domain region (<= 64), several tiles, ragged tiles, and level counts
+    probs = _heat_batch(5, [(20, 6), (64, 3), (37, 9), (70, 5), (100, 2)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    u0s = [dev(p.u0) for p in probs]
+    print(f"[batched] heat {precision} {[(p.nx, p.nt) for p in probs]}", flush=True)
+    sts = P.solve_batched(probs, Us, u0s, tol=tol, max_iter=40, precision=precision)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"], st
+        assert st["schedule"] == 1  # bulk, shared launches
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        assert err <= bar, (p.name, err)
+
+
+def test_batch_equals_one_by_one_solves():
+    probs = _heat_batch(6, [(33, 4), (65, 6), (48, 2)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, schedule="bulk")
+    for p, U, st in zip(probs, Us, sts):
+        V = dev(p.plain_iterate())
+        st1 = P.solve(p, V, dev(p.u0), tol=1e-12, max_iter=40, schedule="bulk")
+        assert st["iterations"] == st1["iterations"]
+        np.testing.assert_allclose(host(U), host(V), rtol=0, atol=1e-12 * np.max(np.abs(host(V))))
+
+
+def test_periodic_burgers_batch():
+    rng = np.random.default_rng(8)
+    probs = [W.burgers_periodic(n, L, 5e-4, 0.01, W.fourier_u0_periodic(n, int(rng.integers(1 << 30)), kmax=4),
+                                name=f"b{n}") for n, L in [(64, 4), (96, 3), (128, 2)]]
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print("[batched] burgers periodic", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"]
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+
+
+def test_mixed_boundary_kinds_fall_back_to_one_by_one():
+    rng = np.random.default_rng(9)
+    probs = [W.heat_dirichlet(24, 3, 1e-3, W.sine_u0_dirichlet(24, rng)),
+             W.burgers_periodic(64, 2, 5e-4, 0.01, W.fourier_u0_periodic(64, 3, kmax=4))]
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"]
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+
+
+def test_nonconverging_instance_reports_and_others_finish():
+    probs = _heat_batch(10, [(30, 4), (40, 3)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    with pytest.raises(P.PTSError):
+        P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-30, max_iter=2)
