@@ -233,6 +233,63 @@ def bench_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_heatbatch(args):
+    """64 independent nonlinear heat instances (k(u) = 1 + u^2, zero Dirichlet, dt = 1e-3) with
+    uneven grids 64^2..512^2 and 128..1024 levels, solved together in shared launches; FP32
+    inner solves with FP64 residuals and refinement."""
+    import numpy as np
+    import torch
+
+    import paper_2406_00878_amd as P
+    import workloads as W
+    from oracle import sequential
+
+    log = lambda m: print(f"[bench-heatbatch] {m}", file=sys.stderr, flush=True)
+    probs = W.heat_batch()
+    dof = sum(p.dof for p in probs)
+    dev = torch.device("cuda:0")
+    Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
+    u0s = [torch.as_tensor(p.u0, dtype=torch.float64, device=dev).contiguous() for p in probs]
+    log(f"{len(probs)} instances, {dof / 1e9:.2f} G space-time DOF, grids {min(p.nx for p in probs)}.."
+        f"{max(p.nx for p in probs)}, levels {min(p.nt for p in probs)}..{max(p.nt for p in probs)}")
+
+    def step():
+        for p, U, u0 in zip(probs, Us, u0s):
+            P.init_plain(p, U, u0)
+        return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(args.steps):
+        sts = step()
+        log(f"solve {k + 1}/{args.steps} done")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    its = [st["iterations"] for st in sts]
+    log(f"{ms:.0f} ms per batch, Newton steps {min(its)}..{max(its)}")
+    # accuracy: the smallest instance against the time-stepping oracle on its first levels
+    i = min(range(len(probs)), key=lambda q: probs[q].dof)
+    levels = min(8, probs[i].nt)
+    Uo, _ = sequential.solve_sequential(probs[i], levels=levels)
+    Ug = Us[i][:levels].cpu().numpy()
+    err = float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo)))
+    out = {
+        "metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "heatbatch64", "instances": len(probs), "space_time_dof": dof, "dt": 1e-3,
+                   "tol": args.tol, "precision": "mixed", "schedule": "batched bulk",
+                   "newton_steps_min_max": [min(its), max(its)],
+                   "inner_passes_max": max(st["refine"] + 1 for st in sts)},
+        "rel_err_vs_oracle": {"value": err, "instance": i, "levels_checked": levels},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +318,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(instances and time levels would shard across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "heatbatch":
+        return bench_heatbatch(args)
     if args.learned:
         if args.tol == 1e-12:
             # relative error well inside 1e-8 for every start (checked at every level against

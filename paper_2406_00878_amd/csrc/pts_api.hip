@@ -1132,10 +1132,79 @@ int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, i
 // ---------------------------------------------------------------- batched bulk solve
 // Workspace of a batch: a header with the instance descriptors and the (instance, tile)
 // work items, then every instance's own workspace.
+// Dirichlet heat on square grids with equal spacings: the spectral (DST-preconditioned)
+// level solve applies.
+bool dst_eligible(const pts_problem* probs, int nprob) {
+  for (int i = 0; i < nprob; ++i) {
+    const pts_problem& q = probs[i];
+    if (q.kind != PTS_HEAT || q.bc != PTS_DIRICHLET || q.nx != q.ny || q.hx != q.hy) return false;
+  }
+  return true;
+}
+
+// Layout of the spectral solve's part of a batch header (after the level-solve part).
+struct DstLayout {
+  size_t desc, gemm, items_g, items_e, inst0, total;
+  std::vector<size_t> S, lam, r, z, t1, t2, d;
+  size_t ng = 0, ne = 0;  // work items of the products and of the node kernels
+};
+DstLayout dst_layout(const pts_problem* probs, int nprob) {
+  DstLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  for (int i = 0; i < nprob; ++i) {
+    const size_t N = probs[i].nx, t = (N + pts_mm::BM - 1) / pts_mm::BM;
+    L.ng += t * t;
+    L.ne += (N * N + 255) / 256;
+  }
+  L.desc = take((size_t)nprob * sizeof(DstDesc));
+  L.gemm = take((size_t)4 * nprob * sizeof(pts_mm::Gemm));
+  L.items_g = take(L.ng * sizeof(int4));
+  L.items_e = take(L.ne * sizeof(int2));
+  for (int i = 0; i < nprob; ++i) {
+    const size_t nn = (size_t)probs[i].nx * probs[i].nx;
+    L.S.push_back(take(nn * 4));
+    L.lam.push_back(take((size_t)probs[i].nx * 4));
+    L.r.push_back(take(nn * 4));
+    L.z.push_back(take(nn * 4));
+    L.t1.push_back(take(nn * 4));
+    L.t2.push_back(take(nn * 4));
+    L.d.push_back(take(nn * 8));
+  }
+  L.total = o;
+  return L;
+}
+
 size_t batch_header_bytes(const pts_problem* probs, int nprob) {
   size_t tiles_total = 0;
   for (int i = 0; i < nprob; ++i) tiles_total += (size_t)tiles(probs + i, geometry(probs + i));
-  return align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
+  size_t b = align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
+  if (dst_eligible(probs, nprob)) b += dst_layout(probs, nprob).total;
+  return b;
+}
+
+// Chebyshev for a spectrum in [a, b]: d_0 = z_0 / theta; d_k = rho_k rho_{k-1} d_{k-1} +
+// (2 rho_k / delta) z_k, rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
+// Returns the iterations that reach `target` (error bound 2 q^K, q = (sqrt(b/a) - 1) / (sqrt(b/a) + 1)).
+int cheb_coefficients(double a, double b, double target, float* c0, float* c1) {
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double q = (std::sqrt(b / a) - 1.0) / (std::sqrt(b / a) + 1.0);
+  int K = q > 0 ? (int)std::ceil(std::log(0.5 * target) / std::log(q)) : 1;
+  K = std::max(1, std::min(K, kMaxCheb));
+  double rho = delta / theta;
+  c0[0] = 0.f;
+  c1[0] = (float)(1.0 / theta);
+  for (int k = 1; k < K; ++k) {
+    const double rn = 1.0 / (2.0 * theta / delta - rho);
+    c0[k] = (float)(rn * rho);
+    c1[k] = (float)(2.0 * rn / delta);
+    rho = rn;
+  }
+  return K;
 }
 
 // Pinned staging for the descriptor upload (the batched solve synchronises every Newton step
@@ -1160,6 +1229,9 @@ int host_stage(size_t bytes, char** out) {
 // Newton on every instance at once: per step, the all-level residuals, then for each level n
 // and launch l of the inner plans one launch over the tiles of every instance that has them
 // (k_level_solve_batched), then the updates. Instances leave the batch when they converge.
+// Stiff Dirichlet heat batches (Gershgorin radius >= kDstRho) solve their levels with the
+// DST-preconditioned Chebyshev iteration instead (k_dst_*), also in shared launches.
+constexpr double kDstRho = 0.97;
 int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
                        int max_iter, char* header, char* wsb, const pts_options* o, pts_stats* stats,
                        hipStream_t s) {
@@ -1176,15 +1248,34 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     maxnt = std::max(maxnt, probs[i].nt);
     if (stats) std::memset(stats + i, 0, sizeof(pts_stats));
   }
+  const bool eligible = dst_eligible(probs, nprob);
   BatchDesc* d_desc = (BatchDesc*)header;
   int2* d_items = (int2*)(header + align_up((size_t)nprob * sizeof(BatchDesc)));
-  const size_t stage_bytes = (size_t)nprob * sizeof(BatchDesc) + tiles_total * sizeof(int2) + (size_t)nprob * 24;
+  char* dst_base = header + align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
+  DstLayout DL;
+  if (eligible) DL = dst_layout(probs, nprob);
+  // host staging: descriptors and items of both solvers, then the scalars read back
+  size_t so = 0;
+  auto stake = [&](size_t bytes) {
+    const size_t at = so;
+    so = align_up(so + bytes);
+    return at;
+  };
+  const size_t s_desc = stake((size_t)nprob * sizeof(BatchDesc)), s_items = stake(tiles_total * sizeof(int2));
+  const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(DstDesc) : 0);
+  const size_t s_gm = stake(eligible ? (size_t)4 * nprob * sizeof(pts_mm::Gemm) : 0);
+  const size_t s_ig = stake(eligible ? DL.ng * sizeof(int4) : 0), s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  const size_t s_sc = stake((size_t)nprob * 4 * sizeof(double));
   char* stage;
-  int rc = host_stage(stage_bytes, &stage);
+  int rc = host_stage(so, &stage);
   if (rc) return rc;
-  BatchDesc* h_desc = (BatchDesc*)stage;
-  int2* h_items = (int2*)(stage + (size_t)nprob * sizeof(BatchDesc));
-  double* h_sc = (double*)(stage + (size_t)nprob * sizeof(BatchDesc) + tiles_total * sizeof(int2));
+  BatchDesc* h_desc = (BatchDesc*)(stage + s_desc);
+  int2* h_items = (int2*)(stage + s_items);
+  DstDesc* h_dd = (DstDesc*)(stage + s_dd);
+  pts_mm::Gemm* h_gm = (pts_mm::Gemm*)(stage + s_gm);
+  int4* h_ig = (int4*)(stage + s_ig);
+  int2* h_ie = (int2*)(stage + s_ie);
+  double* h_sc = (double*)(stage + s_sc);  // per instance: max|r|, rho_max, rms, max|u^0|
   const bool fp32 = probs[0].precision == PTS_MIXED;
   const bool per = probs[0].bc == PTS_PERIODIC;
   auto kern = fp32 ? (per ? k_level_solve_batched<float, 1> : k_level_solve_batched<float, 0>)
@@ -1193,30 +1284,89 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   std::vector<char> active(nprob, 1);
   std::vector<Plan> plans(nprob);
   int launches = 0, worst = PTS_OK;
-  auto read_all = [&](bool with_rms) -> int {
+  auto read_all = [&](bool with_rms, bool with_u0) -> int {
     for (int i = 0; i < nprob; ++i) {
       if (!active[i]) continue;
-      HIPCHK(hipMemcpyAsync(h_sc + 3 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
-      if (with_rms) HIPCHK(hipMemcpyAsync(h_sc + 3 * i + 2, in[i].rms, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(h_sc + 4 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
+      if (with_rms) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 2, in[i].rms, 8, hipMemcpyDeviceToHost, s));
+      if (with_u0) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 3, in[i].scal + 3, 8, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     return PTS_OK;
   };
-  for (int i = 0; i < nprob; ++i)
+  for (int i = 0; i < nprob; ++i) {
     if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
-  if ((rc = read_all(false))) return rc;
+    if (eligible) {
+      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, u0[i], (size_t)probs[i].nx * probs[i].ny,
+                         in[i].scal + 3);
+      ++launches;
+    }
+  }
+  if ((rc = read_all(false, eligible))) return rc;
+  std::vector<double> u0max(nprob, 0.0);
+  double rho0 = 0.0;
+  for (int i = 0; i < nprob; ++i) {
+    u0max[i] = eligible ? h_sc[4 * i + 3] : 0.0;
+    rho0 = std::max(rho0, h_sc[4 * i + 1]);
+  }
+  const bool use_dst = eligible && rho0 >= kDstRho;
+  if (use_dst) {
+    // bases, and the four products of M^{-1} per instance (fixed for the solve)
+    for (int i = 0; i < nprob; ++i) {
+      const int N = probs[i].nx;
+      float* S = (float*)(dst_base + DL.S[i]);
+      float* lam = (float*)(dst_base + DL.lam[i]);
+      hipLaunchKernelGGL(k_dst_setup, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, s, N,
+                         probs[i].hx, S, lam);
+      ++launches;
+      const double mu_lo = probs[i].mu_a, mu_hi = probs[i].mu_a + probs[i].mu_b * u0max[i] * u0max[i];
+      const float c = (float)(probs[i].dt * 0.5 * (mu_lo + mu_hi));
+      float* r = (float*)(dst_base + DL.r[i]);
+      float* z = (float*)(dst_base + DL.z[i]);
+      float* t1 = (float*)(dst_base + DL.t1[i]);
+      float* t2 = (float*)(dst_base + DL.t2[i]);
+      auto mk = [&](const float* A, const float* B, float* C, bool scale) {
+        pts_mm::Gemm g{};
+        g.A = A;
+        g.B = B;
+        g.C = C;
+        g.M = g.N = g.K = N;
+        g.sam = N;
+        g.sak = 1;
+        g.sbk = N;
+        g.sbn = 1;
+        g.scm = N;
+        g.scn = 1;
+        g.alpha = 1.f;
+        g.beta = 0.f;
+        g.ksplit = 1;
+        if (scale) {
+          g.lam_m = lam;
+          g.lam_n = lam;
+          g.lam_c = c;
+        }
+        return g;
+      };
+      h_gm[0 * nprob + i] = mk(S, r, t1, false);
+      h_gm[1 * nprob + i] = mk(t1, S, t2, true);
+      h_gm[2 * nprob + i] = mk(S, t2, t1, false);
+      h_gm[3 * nprob + i] = mk(t1, S, z, false);
+    }
+    HIPCHK(hipMemcpyAsync(dst_base + DL.gemm, h_gm, (size_t)4 * nprob * sizeof(pts_mm::Gemm), hipMemcpyHostToDevice,
+                          s));
+  }
   for (int it = 0;; ++it) {
     int nactive = 0;
     for (int i = 0; i < nprob; ++i) {
       if (!active[i]) continue;
       const pts_problem* p = probs + i;
-      const double res = h_sc[3 * i], rhom = h_sc[3 * i + 1];
+      const double res = h_sc[4 * i], rhom = h_sc[4 * i + 1];
       pts_stats* st = stats ? stats + i : nullptr;
       if (st) {
         if (it < PTS_MAX_HIST) {
           st->res_inf[it] = res;
           st->rho_max[it] = rhom;
-          if (it > 0) st->upd_rms[it] = std::sqrt(h_sc[3 * i + 2] / ((double)p->nx * p->ny * p->nt));
+          if (it > 0) st->upd_rms[it] = std::sqrt(h_sc[4 * i + 2] / ((double)p->nx * p->ny * p->nt));
         }
         st->iterations = it;
         st->hist = std::min(it + 1, PTS_MAX_HIST);
@@ -1242,58 +1392,118 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         active[i] = 0;
         continue;
       }
-      plans[i] = make_plan(p, o, std::min(rhom * 1.02, 0.999), in[i].g);
-      if (st) {
-        st->sweeps = plans[i].sweeps;
-        st->refine = plans[i].passes - 1;
+      if (!use_dst) {
+        plans[i] = make_plan(p, o, std::min(rhom * 1.02, 0.999), in[i].g);
+        if (st) {
+          st->sweeps = plans[i].sweeps;
+          st->refine = plans[i].passes - 1;
+        }
       }
       ++nactive;
     }
     if (nactive == 0) break;
-    // descriptors (inactive instances have no launches) and work items, longest first
     std::vector<int> order;
-    for (int i = 0; i < nprob; ++i) {
-      BatchDesc& d = h_desc[i];
-      std::memset(&d, 0, sizeof d);
-      d.p = in[i].kp;
-      d.g = in[i].g;
-      d.U = U[i];
-      d.R = in[i].R;
-      d.dU = in[i].dU;
-      d.Xs = in[i].Xs;
-      d.rho = (const double*)in[i].rho;
-      if (active[i]) {
-        d.npacks = (int)std::min<size_t>(plans[i].packs.size(), kMaxPacks);
-        d.sweeps = plans[i].sweeps;
-        for (int l = 0; l < d.npacks; ++l) d.packs[l] = plans[i].packs[l];
-        order.push_back(i);
-      }
-    }
+    for (int i = 0; i < nprob; ++i)
+      if (active[i]) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].nt > probs[b].nt; });
-    size_t nitems = 0;
-    for (int i : order)
-      for (int t = 0; t < ntiles[i]; ++t) h_items[nitems++] = make_int2(i, t);
-    HIPCHK(hipMemcpyAsync(d_desc, h_desc, (size_t)nprob * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_items, h_items, nitems * sizeof(int2), hipMemcpyHostToDevice, s));
-    // level n: the prefix of instances with nt > n; as many launches as the longest plan among them
-    std::vector<size_t> cum(order.size() + 1, 0);
-    std::vector<int> lmax(order.size() + 1, 0);
-    for (size_t q = 0; q < order.size(); ++q) {
-      cum[q + 1] = cum[q] + ntiles[order[q]];
-      lmax[q + 1] = std::max(lmax[q], h_desc[order[q]].npacks);
-    }
-    std::vector<size_t> cnt(maxnt, 0);
-    std::vector<int> lcount(maxnt, 0);
+    // per level n: the instances with nt > n form a prefix of `order`
+    std::vector<int> kpref(maxnt, 0);
     for (int n = 0, k = (int)order.size(); n < maxnt; ++n) {  // the prefix shrinks as n grows
       while (k > 0 && probs[order[k - 1]].nt <= n) --k;
-      cnt[n] = cum[k];
-      lcount[n] = lmax[k];
+      kpref[n] = k;
     }
-    for (int n = 0; n < maxnt; ++n) {
-      if (cnt[n] == 0) continue;
-      for (int l = 0; l < lcount[n]; ++l) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)cnt[n]), dim3(kThreads), 0, s, d_desc, d_items, n, l);
-        ++launches;
+    if (use_dst) {
+      const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : (fp32 ? 1e-6 : 1e-9);
+      std::vector<size_t> cg(order.size() + 1, 0), ce(order.size() + 1, 0);
+      std::vector<int> km(order.size() + 1, 0);
+      size_t ng = 0, ne = 0;
+      for (int i = 0; i < nprob; ++i) {
+        DstDesc& d = h_dd[i];
+        std::memset(&d, 0, sizeof d);
+        d.p = in[i].kp;
+        d.U = U[i];
+        d.R = in[i].R;
+        d.dU = in[i].dU;
+        d.r = (float*)(dst_base + DL.r[i]);
+        d.z = (float*)(dst_base + DL.z[i]);
+        d.d = (double*)(dst_base + DL.d[i]);
+        if (active[i]) {
+          // preconditioned spectrum within [mu_lo, mu_hi] / mu_ref, widened for the
+          // non-symmetric mu' terms of the Jacobian and the bfloat16 products
+          const double mu_lo = probs[i].mu_a, mu_hi = probs[i].mu_a + probs[i].mu_b * u0max[i] * u0max[i];
+          const double mref = 0.5 * (mu_lo + mu_hi);
+          d.K = cheb_coefficients(0.8 * std::min(1.0, mu_lo / mref), 1.2 * std::max(1.0, mu_hi / mref), lin_tol,
+                                  d.c0, d.c1);
+          if (stats) {
+            stats[i].sweeps = d.K;
+            stats[i].refine = 0;
+          }
+        }
+      }
+      for (size_t q = 0; q < order.size(); ++q) {
+        const int i = order[q];
+        const int N = probs[i].nx, t = (N + pts_mm::BM - 1) / pts_mm::BM, ch = (N * N + 255) / 256;
+        for (int a = 0; a < t; ++a)
+          for (int b = 0; b < t; ++b) h_ig[ng++] = make_int4(i, a, b, 0);
+        for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(i, c);
+        cg[q + 1] = ng;
+        ce[q + 1] = ne;
+        km[q + 1] = std::max(km[q], h_dd[i].K);
+      }
+      HIPCHK(hipMemcpyAsync(dst_base + DL.desc, h_dd, (size_t)nprob * sizeof(DstDesc), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dst_base + DL.items_g, h_ig, ng * sizeof(int4), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(dst_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
+      const DstDesc* dd = (const DstDesc*)(dst_base + DL.desc);
+      const pts_mm::Gemm* gm = (const pts_mm::Gemm*)(dst_base + DL.gemm);
+      const int4* ig = (const int4*)(dst_base + DL.items_g);
+      const int2* ie = (const int2*)(dst_base + DL.items_e);
+      for (int n = 0; n < maxnt; ++n) {
+        const int k = kpref[n];
+        if (k == 0) continue;
+        for (int kk = 0; kk < km[k]; ++kk) {
+          hipLaunchKernelGGL(k_dst_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
+          for (int stg = 0; stg < 4; ++stg)
+            hipLaunchKernelGGL(k_dst_gemm, dim3((unsigned)cg[k]), dim3(256), 0, s, gm, dd, ig, nprob, stg, n, kk);
+          hipLaunchKernelGGL(k_dst_update, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
+          launches += 6;
+        }
+      }
+    } else {
+      // descriptors (inactive instances have no launches) and work items, longest first
+      for (int i = 0; i < nprob; ++i) {
+        BatchDesc& d = h_desc[i];
+        std::memset(&d, 0, sizeof d);
+        d.p = in[i].kp;
+        d.g = in[i].g;
+        d.U = U[i];
+        d.R = in[i].R;
+        d.dU = in[i].dU;
+        d.Xs = in[i].Xs;
+        d.rho = (const double*)in[i].rho;
+        if (active[i]) {
+          d.npacks = (int)std::min<size_t>(plans[i].packs.size(), kMaxPacks);
+          d.sweeps = plans[i].sweeps;
+          for (int l = 0; l < d.npacks; ++l) d.packs[l] = plans[i].packs[l];
+        }
+      }
+      size_t nitems = 0;
+      std::vector<size_t> cum(order.size() + 1, 0);
+      std::vector<int> lmax(order.size() + 1, 0);
+      for (size_t q = 0; q < order.size(); ++q) {
+        const int i = order[q];
+        for (int t = 0; t < ntiles[i]; ++t) h_items[nitems++] = make_int2(i, t);
+        cum[q + 1] = nitems;
+        lmax[q + 1] = std::max(lmax[q], h_desc[i].npacks);
+      }
+      HIPCHK(hipMemcpyAsync(d_desc, h_desc, (size_t)nprob * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(d_items, h_items, nitems * sizeof(int2), hipMemcpyHostToDevice, s));
+      for (int n = 0; n < maxnt; ++n) {
+        const int k = kpref[n];
+        if (k == 0) continue;
+        for (int l = 0; l < lmax[k]; ++l) {
+          hipLaunchKernelGGL(kern, dim3((unsigned)cum[k]), dim3(kThreads), 0, s, d_desc, d_items, n, l);
+          ++launches;
+        }
       }
     }
     HIPCHK(hipGetLastError());
@@ -1305,7 +1515,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
     }
     HIPCHK(hipGetLastError());
-    if ((rc = read_all(true))) return rc;
+    if ((rc = read_all(true, false))) return rc;
   }
   if (stats)
     for (int i = 0; i < nprob; ++i) stats[i].launches = launches;

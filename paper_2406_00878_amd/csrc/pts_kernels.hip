@@ -15,6 +15,7 @@
 //  k_update        U += dU at every level and per-block sums of dU^2 (the RMS update
 //                  norm of Section 8.1), reduced in fixed order by k_reduce_sum.
 #include "pts_device.hpp"
+#include "pts_mfma.hpp"
 
 namespace pts {
 
@@ -366,6 +367,100 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
   const double* prev = n == 0 ? nullptr : d->dU + (size_t)(n - 1) * ns;
   level_solve_tile<T, BC>(p, n, it.y, d->U, d->R + (size_t)n * ns, prev, xin, xo, d->rho, g, d->packs[l], d->sweeps,
                           lds_raw, om);
+}
+
+// ------------------------------------------------ spectral level solves (Dirichlet heat)
+// For stiff Dirichlet heat levels the block A_n = I + tau dF/du is solved by Chebyshev
+// iteration preconditioned with M = I + tau mu_ref (-Delta_h), the constant-coefficient
+// five-point operator. The orthonormal DST-I matrix S (S = S^T = S^{-1}) diagonalises the
+// Dirichlet Laplacian: -Delta_h = S diag(lam_i + lam_j) S with
+// lam_k = (4 / h^2) sin^2(pi k / (2 (N + 1))), so M^{-1} r = S ((S r S) ./ (1 + tau mu_ref
+// (lam_i + lam_j))) S: four dense N x N products (MFMA) and a diagonal scaling.
+// With mu in [mu_lo, mu_hi] and mu_ref their midpoint, the preconditioned spectrum lies near
+// [mu_lo, mu_hi] / mu_ref (times a margin for the non-symmetric mu' terms of the Jacobian).
+constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
+struct DstDesc {
+  KProb p;
+  const double* U;   // iterate [nt][N][N]
+  const double* R;   // residual [nt][N][N]
+  double* dU;        // update [nt][N][N]; the level solve iterates in dU[n]
+  float* r;          // [N][N] level residual b - A x (float32)
+  float* z;          // [N][N] M^{-1} r
+  double* d;         // [N][N] Chebyshev direction
+  int K;             // iterations of this instance (0: inactive)
+  float c0[kMaxCheb], c1[kMaxCheb];  // d_k = c0[k] d_{k-1} + c1[k] z_k (c0[0] = 0)
+};
+
+// S[i][j] = sqrt(2/(N+1)) sin(pi (i+1)(j+1) / (N+1)), lam[k] = (4/h^2) sin^2(pi (k+1) / (2(N+1)))
+__global__ __launch_bounds__(256) void k_dst_setup(int N, double h, float* __restrict__ S, float* __restrict__ lam) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;
+  const long nn = (long)N * N;
+  if (t < nn) {
+    const int i = (int)(t / N), j = (int)(t % N);
+    S[t] = (float)(sqrt(2.0 / (N + 1)) * sin(M_PI * (double)(i + 1) * (double)(j + 1) / (double)(N + 1)));
+  }
+  if (t < N) {
+    const double sv = sin(M_PI * (double)(t + 1) / (2.0 * (N + 1)));
+    lam[t] = (float)(4.0 / (h * h) * sv * sv);
+  }
+}
+
+// Work items (instance, chunk of 256 nodes), sorted by level count. Iteration k of level n:
+// r = b - A x with b = r^n + du^{n-1} (Eq. (7)) and x = du^n (x = 0 at k = 0, written here).
+__global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ ds, const int2* __restrict__ items,
+                                                   int n, int k) {
+  const int2 it = items[blockIdx.x];
+  const DstDesc* d = ds + it.x;
+  if (n >= d->p.nt || k >= d->K) return;
+  const KProb p = d->p;
+  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
+  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
+  if (i >= ns) return;
+  const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
+  const size_t lev = (size_t)n * ns;
+  double b = d->R[lev + i] + (n > 0 ? d->dU[lev - ns + i] : 0.0);
+  double* X = d->dU + lev;
+  if (k == 0) {
+    X[i] = 0.0;
+  } else {
+    const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+    const Nb u = gather<0>(p, d->U + lev, bd, x, y);
+    Row5 a;
+    (void)eval_point<0>(p, u, x, y, a);
+    double ax = a.C * X[i];
+    if (x > 0) ax += a.W * X[i - 1];
+    if (x < p.nx - 1) ax += a.E * X[i + 1];
+    if (y > 0) ax += a.S * X[i - p.nx];
+    if (y < p.ny - 1) ax += a.N * X[i + p.nx];
+    b -= ax;
+  }
+  d->r[i] = (float)b;
+}
+
+// d = c0 d + c1 z, x += d
+__global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ ds, const int2* __restrict__ items,
+                                                    int n, int k) {
+  const int2 it = items[blockIdx.x];
+  const DstDesc* d = ds + it.x;
+  if (n >= d->p.nt || k >= d->K) return;
+  const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
+  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
+  if (i >= ns) return;
+  const double dir = (k == 0 ? 0.0 : (double)d->c0[k] * d->d[i]) + (double)d->c1[k] * (double)d->z[i];
+  d->d[i] = dir;
+  d->dU[(size_t)n * ns + i] += dir;
+}
+
+// One 64 x 64 tile of the product of group it.x (instance) in stage `stage`'s descriptors;
+// items (instance, tile row, tile column), sorted by level count. Groups whose instance has
+// no level n or no iteration k return.
+__global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict__ gs, const DstDesc* __restrict__ ds,
+                                                  const int4* __restrict__ items, int nprob, int stage, int n, int k) {
+  const int4 it = items[blockIdx.x];
+  const DstDesc* d = ds + it.x;
+  if (n >= d->p.nt || k >= d->K) return;
+  const pts_mm::Gemm g = gs[(size_t)stage * nprob + it.x];
+  pts_mm::mm_tile(g, it.y * pts_mm::BM, it.z * pts_mm::BN, 0, 0);
 }
 
 // ---------------------------------------------------------- wavefront schedule

@@ -82,3 +82,20 @@ def test_nonconverging_instance_reports_and_others_finish():
     Us = [dev(p.plain_iterate()) for p in probs]
     with pytest.raises(P.PTSError):
         P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-30, max_iter=2)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_stiff_heat_batch_spectral_level_solves_match_oracle(precision, bar):
+    """Stiff Dirichlet heat levels (Gershgorin radius >= 0.976) take the DST-preconditioned
+    Chebyshev solve: few iterations per level, no restarted passes, same converged result."""
+    probs = _heat_batch(12, [(128, 3), (100, 4), (150, 2)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print(f"[batched] stiff heat {precision}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision=precision)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"], st
+        assert st["refine"] == 0 and st["sweeps"] <= 32, st  # spectral path: Chebyshev iterations, one pass
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err)
+        assert err <= bar, (p.name, err)
