@@ -245,7 +245,7 @@ def bench_heatbatch(args):
     from oracle import sequential
 
     log = lambda m: print(f"[bench-heatbatch] {m}", file=sys.stderr, flush=True)
-    probs = W.heat_batch()
+    probs = W.heat_batch()[:args.instances]
     dof = sum(p.dof for p in probs)
     dev = torch.device("cuda:0")
     Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
@@ -305,6 +305,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the inner-plan autotuner")
     ap.add_argument("--sweeps", type=int, default=0, help="explicit inner Chebyshev sweeps (0 = tuned/auto)")
     ap.add_argument("--passes", type=int, default=0, help="explicit inner passes (0 = tuned/auto)")
+    ap.add_argument("--instances", type=int, default=64, help="heatbatch: first instances of the batch")
     ap.add_argument("--hbm-calibration", action="store_true",
                     help="after the bench, run a 1 GiB fill and a 1 GiB sum (counter calibration)")
     ap.add_argument("--learned", action="store_true",

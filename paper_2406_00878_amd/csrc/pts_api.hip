@@ -1137,7 +1137,7 @@ int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, i
 bool dst_eligible(const pts_problem* probs, int nprob) {
   for (int i = 0; i < nprob; ++i) {
     const pts_problem& q = probs[i];
-    if (q.kind != PTS_HEAT || q.bc != PTS_DIRICHLET || q.nx != q.ny || q.hx != q.hy) return false;
+    if (q.kind != PTS_HEAT || q.bc != PTS_DIRICHLET || q.nx != q.ny || q.hx != q.hy || !(q.mu_a > 0)) return false;
   }
   return true;
 }
@@ -1145,7 +1145,7 @@ bool dst_eligible(const pts_problem* probs, int nprob) {
 // Layout of the spectral solve's part of a batch header (after the level-solve part).
 struct DstLayout {
   size_t desc, gemm, items_g, items_e, inst0, total;
-  std::vector<size_t> S, lam, r, z, t1, t2, d;
+  std::vector<size_t> S, lam, r, z, t1, t2, d, K, coef, lmax;
   size_t ng = 0, ne = 0;  // work items of the products and of the node kernels
 };
 DstLayout dst_layout(const pts_problem* probs, int nprob) {
@@ -1174,6 +1174,9 @@ DstLayout dst_layout(const pts_problem* probs, int nprob) {
     L.t1.push_back(take(nn * 4));
     L.t2.push_back(take(nn * 4));
     L.d.push_back(take(nn * 8));
+    L.K.push_back(take((size_t)probs[i].nt * 4));
+    L.coef.push_back(take((size_t)probs[i].nt * kMaxCheb * sizeof(float2)));
+    L.lmax.push_back(take((size_t)probs[i].nt * 8));
   }
   L.total = o;
   return L;
@@ -1265,6 +1268,11 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(DstDesc) : 0);
   const size_t s_gm = stake(eligible ? (size_t)4 * nprob * sizeof(pts_mm::Gemm) : 0);
   const size_t s_ig = stake(eligible ? DL.ng * sizeof(int4) : 0), s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  size_t sum_nt = 0;
+  for (int i = 0; i < nprob; ++i) sum_nt += probs[i].nt;
+  const size_t s_kt = stake(eligible ? sum_nt * 4 : 0);
+  const size_t s_cf = stake(eligible ? sum_nt * kMaxCheb * sizeof(float2) : 0);
+  const size_t s_lm = stake(eligible ? sum_nt * 8 : 0);
   const size_t s_sc = stake((size_t)nprob * 4 * sizeof(double));
   char* stage;
   int rc = host_stage(so, &stage);
@@ -1276,6 +1284,12 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   int4* h_ig = (int4*)(stage + s_ig);
   int2* h_ie = (int2*)(stage + s_ie);
   double* h_sc = (double*)(stage + s_sc);  // per instance: max|r|, rho_max, rms, max|u^0|
+  std::vector<size_t> ofs_nt(nprob, 0);      // instance i's levels start at ofs_nt[i] in the per-level tables
+  for (int i = 1; i < nprob; ++i) ofs_nt[i] = ofs_nt[i - 1] + probs[i - 1].nt;
+  int* h_kt = (int*)(stage + s_kt);
+  float2* h_cf = (float2*)(stage + s_cf);
+  double* h_lm = (double*)(stage + s_lm);
+  bool use_dst = false;
   const bool fp32 = probs[0].precision == PTS_MIXED;
   const bool per = probs[0].bc == PTS_PERIODIC;
   auto kern = fp32 ? (per ? k_level_solve_batched<float, 1> : k_level_solve_batched<float, 0>)
@@ -1284,32 +1298,33 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   std::vector<char> active(nprob, 1);
   std::vector<Plan> plans(nprob);
   int launches = 0, worst = PTS_OK;
-  auto read_all = [&](bool with_rms, bool with_u0) -> int {
+  auto read_all = [&](bool with_rms, bool with_u0, bool with_levels) -> int {
     for (int i = 0; i < nprob; ++i) {
       if (!active[i]) continue;
       HIPCHK(hipMemcpyAsync(h_sc + 4 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
       if (with_rms) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 2, in[i].rms, 8, hipMemcpyDeviceToHost, s));
       if (with_u0) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 3, in[i].scal + 3, 8, hipMemcpyDeviceToHost, s));
+      if (with_levels)
+        HIPCHK(hipMemcpyAsync(h_lm + ofs_nt[i], dst_base + DL.lmax[i], (size_t)probs[i].nt * 8, hipMemcpyDeviceToHost,
+                              s));
     }
     HIPCHK(hipStreamSynchronize(s));
     return PTS_OK;
   };
+  // max |u^n| per level of the current iterate (the spectral solve's Chebyshev intervals)
+  auto level_max = [&](int i) {
+    hipLaunchKernelGGL(k_level_absmax, dim3((unsigned)probs[i].nt), dim3(256), 0, s, U[i],
+                       (size_t)probs[i].nx * probs[i].ny, (unsigned long long*)(dst_base + DL.lmax[i]));
+    ++launches;
+  };
   for (int i = 0; i < nprob; ++i) {
     if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
-    if (eligible) {
-      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, u0[i], (size_t)probs[i].nx * probs[i].ny,
-                         in[i].scal + 3);
-      ++launches;
-    }
+    if (eligible) level_max(i);
   }
-  if ((rc = read_all(false, eligible))) return rc;
-  std::vector<double> u0max(nprob, 0.0);
+  if ((rc = read_all(false, false, eligible))) return rc;
   double rho0 = 0.0;
-  for (int i = 0; i < nprob; ++i) {
-    u0max[i] = eligible ? h_sc[4 * i + 3] : 0.0;
-    rho0 = std::max(rho0, h_sc[4 * i + 1]);
-  }
-  const bool use_dst = eligible && rho0 >= kDstRho;
+  for (int i = 0; i < nprob; ++i) rho0 = std::max(rho0, h_sc[4 * i + 1]);
+  use_dst = eligible && rho0 >= kDstRho;
   if (use_dst) {
     // bases, and the four products of M^{-1} per instance (fixed for the solve)
     for (int i = 0; i < nprob; ++i) {
@@ -1319,8 +1334,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       hipLaunchKernelGGL(k_dst_setup, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, s, N,
                          probs[i].hx, S, lam);
       ++launches;
-      const double mu_lo = probs[i].mu_a, mu_hi = probs[i].mu_a + probs[i].mu_b * u0max[i] * u0max[i];
-      const float c = (float)(probs[i].dt * 0.5 * (mu_lo + mu_hi));
+      const float c = (float)(probs[i].dt * probs[i].mu_a);  // M = I + tau mu_a (-Delta_h)
       float* r = (float*)(dst_base + DL.r[i]);
       float* z = (float*)(dst_base + DL.z[i]);
       float* t1 = (float*)(dst_base + DL.t1[i]);
@@ -1415,7 +1429,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     if (use_dst) {
       const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : (fp32 ? 1e-6 : 1e-9);
       std::vector<size_t> cg(order.size() + 1, 0), ce(order.size() + 1, 0);
-      std::vector<int> km(order.size() + 1, 0);
       size_t ng = 0, ne = 0;
       for (int i = 0; i < nprob; ++i) {
         DstDesc& d = h_dd[i];
@@ -1427,17 +1440,30 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         d.r = (float*)(dst_base + DL.r[i]);
         d.z = (float*)(dst_base + DL.z[i]);
         d.d = (double*)(dst_base + DL.d[i]);
-        if (active[i]) {
-          // preconditioned spectrum within [mu_lo, mu_hi] / mu_ref, widened for the
-          // non-symmetric mu' terms of the Jacobian and the bfloat16 products
-          const double mu_lo = probs[i].mu_a, mu_hi = probs[i].mu_a + probs[i].mu_b * u0max[i] * u0max[i];
-          const double mref = 0.5 * (mu_lo + mu_hi);
-          d.K = cheb_coefficients(0.8 * std::min(1.0, mu_lo / mref), 1.2 * std::max(1.0, mu_hi / mref), lin_tol,
-                                  d.c0, d.c1);
-          if (stats) {
-            stats[i].sweeps = d.K;
-            stats[i].refine = 0;
-          }
+        d.K = (const int*)(dst_base + DL.K[i]);
+        d.c = (const float2*)(dst_base + DL.coef[i]);
+        d.active = active[i];
+        if (!active[i]) continue;
+        // level n: with M = I + tau mu_a (-Delta_h) the preconditioned spectrum lies in
+        // [1, mu_hi / mu_a], mu_hi = mu(1.1 max |u^n|); the margin m covers the non-symmetric
+        // mu' terms of the Jacobian (they grow with u) and the bfloat16 products
+        int kmax_i = 0;
+        for (int n = 0; n < probs[i].nt; ++n) {
+          const double um = 1.1 * h_lm[ofs_nt[i] + n];
+          const double ratio = (probs[i].mu_a + probs[i].mu_b * um * um) / probs[i].mu_a;
+          const double m = 0.05 + 0.15 * (ratio - 1.0);
+          float c0[kMaxCheb], c1[kMaxCheb];
+          const int K = cheb_coefficients(1.0 - std::min(m, 0.5), ratio * (1.0 + m), lin_tol, c0, c1);
+          h_kt[ofs_nt[i] + n] = K;
+          for (int k = 0; k < K; ++k) h_cf[(ofs_nt[i] + n) * kMaxCheb + k] = make_float2(c0[k], c1[k]);
+          kmax_i = std::max(kmax_i, K);
+        }
+        HIPCHK(hipMemcpyAsync(dst_base + DL.K[i], h_kt + ofs_nt[i], (size_t)probs[i].nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dst_base + DL.coef[i], h_cf + ofs_nt[i] * kMaxCheb,
+                              (size_t)probs[i].nt * kMaxCheb * sizeof(float2), hipMemcpyHostToDevice, s));
+        if (stats) {
+          stats[i].sweeps = kmax_i;
+          stats[i].refine = 0;
         }
       }
       for (size_t q = 0; q < order.size(); ++q) {
@@ -1448,7 +1474,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(i, c);
         cg[q + 1] = ng;
         ce[q + 1] = ne;
-        km[q + 1] = std::max(km[q], h_dd[i].K);
       }
       HIPCHK(hipMemcpyAsync(dst_base + DL.desc, h_dd, (size_t)nprob * sizeof(DstDesc), hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(dst_base + DL.items_g, h_ig, ng * sizeof(int4), hipMemcpyHostToDevice, s));
@@ -1460,7 +1485,9 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       for (int n = 0; n < maxnt; ++n) {
         const int k = kpref[n];
         if (k == 0) continue;
-        for (int kk = 0; kk < km[k]; ++kk) {
+        int kn = 0;  // iterations of level n: the most any instance in the prefix needs
+        for (int q = 0; q < k; ++q) kn = std::max(kn, h_kt[ofs_nt[order[q]] + n]);
+        for (int kk = 0; kk < kn; ++kk) {
           hipLaunchKernelGGL(k_dst_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
           for (int stg = 0; stg < 4; ++stg)
             hipLaunchKernelGGL(k_dst_gemm, dim3((unsigned)cg[k]), dim3(256), 0, s, gm, dd, ig, nprob, stg, n, kk);
@@ -1513,9 +1540,10 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in[i].partial, kUpdateBlocks, in[i].rms);
       launches += 2;
       if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
+      if (use_dst) level_max(i);
     }
     HIPCHK(hipGetLastError());
-    if ((rc = read_all(true, false))) return rc;
+    if ((rc = read_all(true, false, use_dst))) return rc;
   }
   if (stats)
     for (int i = 0; i < nprob; ++i) stats[i].launches = launches;

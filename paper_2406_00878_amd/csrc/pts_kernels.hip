@@ -381,15 +381,29 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
 struct DstDesc {
   KProb p;
-  const double* U;   // iterate [nt][N][N]
-  const double* R;   // residual [nt][N][N]
-  double* dU;        // update [nt][N][N]; the level solve iterates in dU[n]
-  float* r;          // [N][N] level residual b - A x (float32)
-  float* z;          // [N][N] M^{-1} r
-  double* d;         // [N][N] Chebyshev direction
-  int K;             // iterations of this instance (0: inactive)
-  float c0[kMaxCheb], c1[kMaxCheb];  // d_k = c0[k] d_{k-1} + c1[k] z_k (c0[0] = 0)
+  const double* U;    // iterate [nt][N][N]
+  const double* R;    // residual [nt][N][N]
+  double* dU;         // update [nt][N][N]; the level solve iterates in dU[n]
+  float* r;           // [N][N] level residual b - A x (float32)
+  float* z;           // [N][N] M^{-1} r
+  double* d;          // [N][N] Chebyshev direction
+  const int* K;       // [nt] iterations of level n (the interval follows the level's max |u|)
+  const float2* c;    // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
+  int active;
 };
+
+// out[n] = max |U^n| (bit pattern of a non-negative double), one work-group per level
+__global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__ U, size_t ns,
+                                                      unsigned long long* __restrict__ out) {
+  const double* u = U + (size_t)blockIdx.x * ns;
+  double m = 0.0;
+  for (size_t i = threadIdx.x; i < ns; i += 256) m = nanmax(m, fabs(u[i]));
+  m = wave_max(m);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
+}
 
 // S[i][j] = sqrt(2/(N+1)) sin(pi (i+1)(j+1) / (N+1)), lam[k] = (4/h^2) sin^2(pi (k+1) / (2(N+1)))
 __global__ __launch_bounds__(256) void k_dst_setup(int N, double h, float* __restrict__ S, float* __restrict__ lam) {
@@ -411,7 +425,7 @@ __global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ d
                                                    int n, int k) {
   const int2 it = items[blockIdx.x];
   const DstDesc* d = ds + it.x;
-  if (n >= d->p.nt || k >= d->K) return;
+  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
   const KProb p = d->p;
   const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
@@ -442,11 +456,12 @@ __global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ 
                                                     int n, int k) {
   const int2 it = items[blockIdx.x];
   const DstDesc* d = ds + it.x;
-  if (n >= d->p.nt || k >= d->K) return;
+  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
   const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
   if (i >= ns) return;
-  const double dir = (k == 0 ? 0.0 : (double)d->c0[k] * d->d[i]) + (double)d->c1[k] * (double)d->z[i];
+  const float2 c = d->c[(size_t)n * kMaxCheb + k];
+  const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)d->z[i];
   d->d[i] = dir;
   d->dU[(size_t)n * ns + i] += dir;
 }
@@ -458,7 +473,7 @@ __global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict
                                                   const int4* __restrict__ items, int nprob, int stage, int n, int k) {
   const int4 it = items[blockIdx.x];
   const DstDesc* d = ds + it.x;
-  if (n >= d->p.nt || k >= d->K) return;
+  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
   const pts_mm::Gemm g = gs[(size_t)stage * nprob + it.x];
   pts_mm::mm_tile(g, it.y * pts_mm::BM, it.z * pts_mm::BN, 0, 0);
 }

@@ -40,14 +40,16 @@ __device__ __forceinline__ float gelu(float z) {
   return 0.5f * z * (1.f + t);
 }
 
-constexpr int BM = 64, BN = 64, BK = 32;
-constexpr int kStage = BM * BK / 256;  // elements of A (and of B) each thread stages per K step
+constexpr int BM = 64, BN = 64, BK = 32;  // BK: default K step (the template parameter of mm_tile)
 
 // One 64 x 64 output tile (rows m0.., columns n0..) of product b, K range sp, computed by a
 // 256-thread work-group (4 waves, 32 x 32 each). Staging follows the unit stride of each
 // operand (coalesced loads for either layout), and the next K step is loaded into
 // registers while the current one is multiplied.
+template <int BKT = BK>
 __device__ __forceinline__ void mm_tile(const Gemm& g, int m0, int n0, int b, int sp) {
+  constexpr int BK = BKT;
+  constexpr int kStage = BM * BK / 256;  // elements of A (and of B) each thread stages per K step
   __shared__ unsigned short As[BM][BK + 2];
   __shared__ unsigned short Bs[BK][BN + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
