@@ -1142,6 +1142,9 @@ bool dst_eligible(const pts_problem* probs, int nprob) {
   return true;
 }
 
+// Row stride of the spectral solve's float32 arrays (16-byte rows for vector loads).
+int dst_ld(int N) { return (N + 3) / 4 * 4; }
+
 // Layout of the spectral solve's part of a batch header (after the level-solve part).
 struct DstLayout {
   size_t desc, gemm, items_g, items_e, inst0, total;
@@ -1166,13 +1169,13 @@ DstLayout dst_layout(const pts_problem* probs, int nprob) {
   L.items_g = take(L.ng * sizeof(int4));
   L.items_e = take(L.ne * sizeof(int2));
   for (int i = 0; i < nprob; ++i) {
-    const size_t nn = (size_t)probs[i].nx * probs[i].nx;
-    L.S.push_back(take(nn * 4));
-    L.lam.push_back(take((size_t)probs[i].nx * 4));
-    L.r.push_back(take(nn * 4));
-    L.z.push_back(take(nn * 4));
-    L.t1.push_back(take(nn * 4));
-    L.t2.push_back(take(nn * 4));
+    const size_t N = probs[i].nx, nn = N * N, nl = N * dst_ld(probs[i].nx);
+    L.S.push_back(take(nl * 4));
+    L.lam.push_back(take(N * 4));
+    L.r.push_back(take(nl * 4));
+    L.z.push_back(take(nl * 4));
+    L.t1.push_back(take(nl * 4));
+    L.t2.push_back(take(nl * 4));
     L.d.push_back(take(nn * 8));
     L.K.push_back(take((size_t)probs[i].nt * 4));
     L.coef.push_back(take((size_t)probs[i].nt * kMaxCheb * sizeof(float2)));
@@ -1328,12 +1331,18 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   if (use_dst) {
     // bases, and the four products of M^{-1} per instance (fixed for the solve)
     for (int i = 0; i < nprob; ++i) {
-      const int N = probs[i].nx;
+      const int N = probs[i].nx, ld = dst_ld(N);
       float* S = (float*)(dst_base + DL.S[i]);
       float* lam = (float*)(dst_base + DL.lam[i]);
-      hipLaunchKernelGGL(k_dst_setup, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, s, N,
+      hipLaunchKernelGGL(k_dst_setup, dim3((unsigned)(((size_t)N * ld + 255) / 256)), dim3(256), 0, s, N, ld,
                          probs[i].hx, S, lam);
-      ++launches;
+      // r, z and the two intermediates: the columns beyond N are read as zeros by the products
+      for (size_t off : {DL.r[i], DL.z[i], DL.t1[i], DL.t2[i]}) {
+        const int words = (int)((size_t)N * ld * 4 / 8);
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0, s,
+                           (unsigned long long*)(dst_base + off), words);
+      }
+      launches += 5;
       const float c = (float)(probs[i].dt * probs[i].mu_a);  // M = I + tau mu_a (-Delta_h)
       float* r = (float*)(dst_base + DL.r[i]);
       float* z = (float*)(dst_base + DL.z[i]);
@@ -1345,11 +1354,11 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         g.B = B;
         g.C = C;
         g.M = g.N = g.K = N;
-        g.sam = N;
+        g.sam = ld;
         g.sak = 1;
-        g.sbk = N;
+        g.sbk = ld;
         g.sbn = 1;
-        g.scm = N;
+        g.scm = ld;
         g.scn = 1;
         g.alpha = 1.f;
         g.beta = 0.f;
@@ -1443,6 +1452,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         d.K = (const int*)(dst_base + DL.K[i]);
         d.c = (const float2*)(dst_base + DL.coef[i]);
         d.active = active[i];
+        d.ld = dst_ld(probs[i].nx);
         if (!active[i]) continue;
         // level n: with M = I + tau mu_a (-Delta_h) the preconditioned spectrum lies in
         // [1, mu_hi / mu_a], mu_hi = mu(1.1 max |u^n|); the margin m covers the non-symmetric

@@ -384,12 +384,13 @@ struct DstDesc {
   const double* U;    // iterate [nt][N][N]
   const double* R;    // residual [nt][N][N]
   double* dU;         // update [nt][N][N]; the level solve iterates in dU[n]
-  float* r;           // [N][N] level residual b - A x (float32)
-  float* z;           // [N][N] M^{-1} r
+  float* r;           // [N][ld] level residual b - A x (float32; columns N..ld-1 stay zero)
+  float* z;           // [N][ld] M^{-1} r
   double* d;          // [N][N] Chebyshev direction
   const int* K;       // [nt] iterations of level n (the interval follows the level's max |u|)
   const float2* c;    // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
   int active;
+  int ld;             // row stride of the float32 arrays: N rounded up to a multiple of 4
 };
 
 // out[n] = max |U^n| (bit pattern of a non-negative double), one work-group per level
@@ -405,13 +406,16 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
   if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
 }
 
-// S[i][j] = sqrt(2/(N+1)) sin(pi (i+1)(j+1) / (N+1)), lam[k] = (4/h^2) sin^2(pi (k+1) / (2(N+1)))
-__global__ __launch_bounds__(256) void k_dst_setup(int N, double h, float* __restrict__ S, float* __restrict__ lam) {
+// S[i][j] = sqrt(2/(N+1)) sin(pi (i+1)(j+1) / (N+1)) (row stride ld, zero beyond column N),
+// lam[k] = (4/h^2) sin^2(pi (k+1) / (2(N+1)))
+__global__ __launch_bounds__(256) void k_dst_setup(int N, int ld, double h, float* __restrict__ S,
+                                                   float* __restrict__ lam) {
   const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  const long nn = (long)N * N;
+  const long nn = (long)N * ld;
   if (t < nn) {
-    const int i = (int)(t / N), j = (int)(t % N);
-    S[t] = (float)(sqrt(2.0 / (N + 1)) * sin(M_PI * (double)(i + 1) * (double)(j + 1) / (double)(N + 1)));
+    const int i = (int)(t / ld), j = (int)(t % ld);
+    S[t] = j < N ? (float)(sqrt(2.0 / (N + 1)) * sin(M_PI * (double)(i + 1) * (double)(j + 1) / (double)(N + 1)))
+                 : 0.f;
   }
   if (t < N) {
     const double sv = sin(M_PI * (double)(t + 1) / (2.0 * (N + 1)));
@@ -448,7 +452,7 @@ __global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ d
     if (y < p.ny - 1) ax += a.N * X[i + p.nx];
     b -= ax;
   }
-  d->r[i] = (float)b;
+  d->r[(size_t)y * d->ld + x] = (float)b;
 }
 
 // d = c0 d + c1 z, x += d
@@ -461,7 +465,8 @@ __global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ 
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
   if (i >= ns) return;
   const float2 c = d->c[(size_t)n * kMaxCheb + k];
-  const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)d->z[i];
+  const float zi = d->z[(size_t)(i / (unsigned)d->p.nx) * d->ld + (i % (unsigned)d->p.nx)];
+  const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)zi;
   d->d[i] = dir;
   d->dU[(size_t)n * ns + i] += dir;
 }
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict
   const DstDesc* d = ds + it.x;
   if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
   const pts_mm::Gemm g = gs[(size_t)stage * nprob + it.x];
-  pts_mm::mm_tile(g, it.y * pts_mm::BM, it.z * pts_mm::BN, 0, 0);
+  pts_mm::mm_tile_vec(g, it.y * pts_mm::BM, it.z * pts_mm::BN);
 }
 
 // ---------------------------------------------------------- wavefront schedule

@@ -140,4 +140,92 @@ __device__ __forceinline__ void mm_tile(const Gemm& g, int m0, int n0, int b, in
 }
 
 
+// Vectorised variant for row-major operands: A contiguous along k, B contiguous along n, all
+// row strides multiples of 4 floats and every array 16-byte aligned; columns up to the row
+// stride may be read (they must hold zeros beyond K or N). K steps of 64, loaded four floats
+// at a time, the next step prefetched into registers. No split K, no epilogue but alpha, beta
+// and the lam scaling.
+__device__ __forceinline__ void mm_tile_vec(const Gemm& g, int m0, int n0) {
+  constexpr int BKV = 64;
+  __shared__ unsigned short As[BM][BKV + 4];
+  __shared__ unsigned short Bs[BKV][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  float4 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      const int am = e >> 4, ak = (e & 15) * 4;  // 16 vectors per 64-wide row
+      const int gm = m0 + am, gk = k0 + ak;
+      ra[r] = (gm < g.M && gk < g.K) ? *reinterpret_cast<const float4*>(g.A + (long)gm * g.sam + gk)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int bk = e >> 4, bn = (e & 15) * 4;
+      const int gk2 = k0 + bk, gn = n0 + bn;
+      rb[r] = (gk2 < g.K && gn < g.N) ? *reinterpret_cast<const float4*>(g.B + (long)gk2 * g.sbk + gn)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < g.K; k0 += BKV) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + r * 256;
+      const int am = e >> 4, ak = (e & 15) * 4;
+      As[am][ak] = f2bf(ra[r].x);
+      As[am][ak + 1] = f2bf(ra[r].y);
+      As[am][ak + 2] = f2bf(ra[r].z);
+      As[am][ak + 3] = f2bf(ra[r].w);
+      const int bk = e >> 4, bn = (e & 15) * 4;
+      Bs[bk][bn] = f2bf(rb[r].x);
+      Bs[bk][bn + 1] = f2bf(rb[r].y);
+      Bs[bk][bn + 2] = f2bf(rb[r].z);
+      Bs[bk][bn + 3] = f2bf(rb[r].w);
+    }
+    __syncthreads();
+    if (k0 + BKV < g.K) load(k0 + BKV);
+#pragma unroll
+    for (int kk = 0; kk < BKV; kk += 16) {
+      const int kq = kk + 4 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + 16 * i + (lane & 15);
+        short4_t a;
+        a[0] = (short)As[row][kq];
+        a[1] = (short)As[row][kq + 1];
+        a[2] = (short)As[row][kq + 2];
+        a[3] = (short)As[row][kq + 3];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn + 16 * j + (lane & 15);
+          short4_t bb;
+          bb[0] = (short)Bs[kq][col];
+          bb[1] = (short)Bs[kq + 1][col];
+          bb[2] = (short)Bs[kq + 2][col];
+          bb[3] = (short)Bs[kq + 3][col];
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn + 16 * j + (lane & 15);
+        if (gm >= g.M || gn >= g.N) continue;
+        float* c = g.C + (long)gm * g.scm + gn;
+        float val = g.alpha * acc[i][j][r] + (g.beta != 0.f ? g.beta * *c : 0.f);
+        if (g.lam_m) val *= 1.f / (1.f + g.lam_c * (g.lam_m[gm] + g.lam_n[gn]));
+        *c = val;
+      }
+}
+
 }  // namespace pts_mm
