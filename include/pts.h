@@ -179,10 +179,23 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
                  void* workspace, size_t workspace_bytes, const pts_options* opts,
                  pts_stats* stats, pts_stream_t stream);
 
-/* Independent instances solved together, every instance's levels batched in
-   the same launches. U[i], u0[i] are device pointers; workspace is one block of
+/* Independent instances (Theorem 1 per instance; sizes, level counts and inner
+   plans may differ) solved together: every Newton step runs the level solves of
+   all instances that have level n in shared launches (bulk schedule, work items
+   sorted by level count, per-instance descriptors in the workspace header).
+   Batches of Dirichlet heat on square grids with h_x = h_y and mu_a > 0 whose
+   blocks are stiff (Jacobi Gershgorin radius >= 0.97) solve each level with
+   Chebyshev iteration preconditioned by I + tau mu_a (-Delta_h), applied
+   through the DST-I (dense MFMA products; inexact, residual reduced 1e3-fold per
+   level solve unless opts->lin_tol says otherwise). Instances with different
+   boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE or
+   opts->window > 1 are solved one after another with pts_solve.
+   U[i], u0[i] are device pointers; workspace is one 256-byte aligned block of
    pts_workspace_bytes_batched bytes; stats is a host array of nprob entries
-   (may be NULL). */
+   (may be NULL). Every instance is attempted; the return code is the first
+   error met (pts_last_error names the instance), converged instances hold their
+   solutions, failed ones their last iterate. Synchronises the stream once per
+   Newton step. */
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob);
 int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U,
                       const double* const* u0, double tol, int max_iter, void* workspace,

@@ -1,11 +1,13 @@
 // Spectral neural operator for the learned initial space-time iterate (include/pts_no.h).
 //
-// Every matrix product runs in k_gemm: float32 operands in memory, rounded to bfloat16 when
-// staged into LDS, multiplied on MFMA 16x16x16 bf16 tiles with float32 accumulation. The
-// separable trigonometric transforms of the spectral layers, the pointwise channel
-// mixes, the projection to the levels and all their transposes in the backward pass are
-// strided views of that one kernel; reductions over the grid (weight gradients) split K
-// across work-groups and sum the partial tiles in fixed order (deterministic).
+// Every matrix product runs in k_gemm (the MFMA tile of pts_mfma.hpp): float32 operands in
+// memory, rounded to bfloat16 when staged into LDS, multiplied on MFMA 16x16x16 bf16 tiles
+// with float32 accumulation. The separable trigonometric transforms of the spectral layers,
+// the pointwise channel mixes (with bias and GELU in the epilogue), the projection to the
+// temporal modes and all their transposes in the backward pass are strided views of that one
+// kernel; reductions over the grid (weight gradients) split K across work-groups and sum the
+// partial tiles in fixed order (deterministic). The temporal synthesis and encoding run in
+// float32 vector arithmetic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -444,9 +446,6 @@ __global__ void k_adam(long n, float* __restrict__ p, const float* __restrict__ 
   }
 }
 
-__global__ void k_fill(long n, float* __restrict__ a, float v) {
-  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long)gridDim.x * 256) a[t] = v;
-}
 
 }  // namespace pts_no
 
