@@ -99,3 +99,22 @@ def test_stiff_heat_batch_spectral_level_solves_match_oracle(precision, bar):
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err)
         assert err <= bar, (p.name, err)
+
+
+def test_windows_option_solves_instances_one_after_another():
+    probs = _heat_batch(14, [(20, 5), (33, 4)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, window=2)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"] and st["window"] == 2
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+
+
+def test_single_instance_batch_and_single_levels():
+    probs = _heat_batch(15, [(50, 1)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40)
+    Uo, _ = sequential.solve_sequential(probs[0])
+    assert sts[0]["converged"]
+    assert np.max(np.abs(host(Us[0]) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
