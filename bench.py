@@ -32,18 +32,27 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per k_level_wave launch of the default workload and plan, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs (profiles/k_level_wave_burgers256x512_fp64_hbm_counters.md),
 # each scaled by the counter's reading for a 1 GiB fill / 1 GiB sum (--hbm-calibration).
-# Valid only for the kernel sources they were taken with (sha256 of the files below).
-TRAFFIC = {"kernel_sha256": "ce00a6efe60888e16c8224df570393e93d648a761fb2d2b4ed3db36fc712aad2",
-           "fetch_bytes": 26469793, "write_bytes": 6184448}
-KERNEL_SOURCES = ["paper_2406_00878_amd/csrc/pts_kernels.hip", "paper_2406_00878_amd/csrc/pts_device.hpp"]
+# Valid only for the kernel source they were taken with: sha256 of the device header and of
+# the parts of the kernel file the wavefront kernel is built from (the register-resident
+# region solve and the wavefront section).
+TRAFFIC = {"kernel_sha256": None, "fetch_bytes": None, "write_bytes": None}
+KERNEL_HEADER = "paper_2406_00878_amd/csrc/pts_device.hpp"
+KERNEL_FILE = "paper_2406_00878_amd/csrc/pts_kernels.hip"
+KERNEL_SECTIONS = [("// -------------------------------------------------------------- level solve",
+                    "// Bulk schedule, one launch per level"),
+                   ("// ---------------------------------------------------------- wavefront schedule",
+                    "// ------------------------------------------------------------ Theorem 1 windows")]
 
 
 def kernel_sha256():
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, KERNEL_HEADER), "rb") as fh:
+        h.update(fh.read())
+    src = open(os.path.join(ROOT, KERNEL_FILE)).read()
+    for a, b in KERNEL_SECTIONS:
+        i = src.index(a)
+        h.update(src[i:src.index(b, i)].encode())
     return h.hexdigest()
 
 
@@ -82,26 +91,30 @@ def workload(name):
 
 
 def cpu_baseline(prob, budget_s, U_gpu):
-    """Time the CPU oracle (sequential FP64 BDF1 + Newton) on the first levels of the workload."""
+    """Time the CPU oracle (sequential FP64 BDF1 + Newton) level by level on the first levels of
+    the workload, stopping after the level that exhausts the time budget."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import sequential
+    Us, iters = [], 0
     with threadpool_limits(limits=1):
-        # calibrate on a few levels (the first level is cheaper than later ones)
-        cal = min(prob.nt, 4)
+        u = np.array(prob.u0, dtype=np.float64)
         t0 = time.perf_counter()
-        sequential.solve_sequential(prob, levels=cal)
-        t1 = (time.perf_counter() - t0) / cal
-        levels = int(max(1, min(prob.nt, math.floor(0.7 * budget_s / max(t1, 1e-3)))))
-        t0 = time.perf_counter()
-        Us, iters = sequential.solve_sequential(prob, levels=levels)
+        for n in range(1, prob.nt + 1):
+            u, it, _ = sequential.bdf1_step(u, prob, n)
+            Us.append(u)
+            iters += it
+            if time.perf_counter() - t0 >= budget_s:
+                break
         dt = time.perf_counter() - t0
+    levels = len(Us)
+    Us = np.stack(Us)
     err = float(np.max(np.abs(U_gpu[:levels] - Us)) / np.max(np.abs(Us)))
     return {
         "value": levels * prob.ns / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
         "sample": f"first {levels} of {prob.nt} levels ({levels * prob.ns} DOF) in {dt:.1f} s, "
-                  f"numpy/scipy single thread, {sum(iters)} Newton steps",
+                  f"numpy/scipy single thread, {iters} Newton steps",
     }, err, levels
 
 
