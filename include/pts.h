@@ -79,8 +79,9 @@ typedef struct pts_options {
                         pts_window_bound gives the largest W the Section 7
                         condition estimate allows                               */
   int32_t schedule;  /* PTS_SCHED_*: BULK = one Newton iteration after another,
-                        replayed as a HIP graph; PIPELINE = all iterations in one
-                        persistent launch, overlapped as a wavefront           */
+                        replayed as a HIP graph; PIPELINE = Newton iterations
+                        overlapped as a wavefront, `stages` of them per
+                        sequence (see wave_launch)                             */
   int32_t sweeps;    /* inner Chebyshev sweeps per solve; 0 = from lin_tol     */
   int32_t refine;    /* FP64 refinement passes (PTS_MIXED); < 0 = auto         */
   double lin_tol;    /* relative reduction asked of each per-level solve;
@@ -93,6 +94,15 @@ typedef struct pts_options {
                         and Newton step counts for the same problem signature
                         (e.g. 1 for starts from a learned initial iterate, which
                         need fewer steps than the plain one); 0 = default      */
+  int32_t wave_launch; /* PIPELINE: 0 = one launch per anti-diagonal, replayed
+                        from a HIP graph (the faster form on MI355X); 1 = each
+                        wavefront sequence as one cooperative launch with a
+                        grid barrier between anti-diagonals, when the device
+                        holds all its work-groups at once (else as 0)          */
+  int32_t barrier_spins; /* PIPELINE, cooperative launch: polls one grid-barrier
+                        wait may take before the sequence is abandoned
+                        (PTS_ERR_HIP, U left partly updated); 0 = 2^20
+                        (about a second)                                       */
 } pts_options;
 
 #define PTS_MAX_HIST 64

@@ -19,7 +19,7 @@ from typing import Optional
 import torch
 
 from . import _lib
-from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_FP64, PTS_HEAT, PTS_MIXED, PTS_PERIODIC,
+from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, PTS_MIXED, PTS_PERIODIC,
                    PTS_SCHED_AUTO, PTS_SCHED_BULK, PTS_SCHED_PIPELINE, pts_options, pts_problem,
                    pts_stats)
 
@@ -99,7 +99,7 @@ def workspace(prob, precision: str = "fp64", device="cuda") -> torch.Tensor:
 
 
 def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_graph=True, stages=0,
-             profile=False, cache_tag=0):
+             profile=False, cache_tag=0, wave_launch="diagonal", barrier_spins=0):
     o = pts_options()
     o.window = int(window)
     o.schedule = {"auto": PTS_SCHED_AUTO, "bulk": PTS_SCHED_BULK, "pipeline": PTS_SCHED_PIPELINE}[schedule]
@@ -110,6 +110,8 @@ def _options(window=0, schedule="auto", sweeps=0, refine=-1, lin_tol=0.0, use_gr
     o.stages = int(stages)
     o.profile = 1 if profile else 0
     o.cache_tag = int(cache_tag)
+    o.wave_launch = {"diagonal": 0, "sequence": 1}[wave_launch]
+    o.barrier_spins = int(barrier_spins)
     return o
 
 

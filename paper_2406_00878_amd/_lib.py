@@ -30,7 +30,8 @@ class pts_problem(C.Structure):
 class pts_options(C.Structure):
     _fields_ = [("window", C.c_int32), ("schedule", C.c_int32), ("sweeps", C.c_int32),
                 ("refine", C.c_int32), ("lin_tol", C.c_double), ("use_graph", C.c_int32),
-                ("stages", C.c_int32), ("profile", C.c_int32), ("cache_tag", C.c_int32)]
+                ("stages", C.c_int32), ("profile", C.c_int32), ("cache_tag", C.c_int32),
+                ("wave_launch", C.c_int32), ("barrier_spins", C.c_int32)]
 
 
 class pts_stats(C.Structure):

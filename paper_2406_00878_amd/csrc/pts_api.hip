@@ -54,6 +54,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 constexpr int kUpdateBlocks = 1024;
 constexpr int kHalo = 16;  // halo of the 64 x 64 register region: tile 32 x 32
+constexpr int kMaxWaveHalo = 24;  // deepest halo of a wavefront plan: tile edge >= 16
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -94,8 +95,16 @@ constexpr int kMaxStages = 16;  // Newton iterations overlapped by one wavefront
 constexpr int kMaxWindow = 64;  // longest Theorem-1 window
 
 struct Layout {
-  size_t R, dU, Xs, rho, scal, partial, rms, U1, dU2, rho_st, res_st, u0copy, win, total;
+  size_t R, dU, Xs, rho, scal, partial, rms, U1, rho_part, res_part, res_st, bar, u0copy, win, total;
 };
+
+// Most tiles per level any wavefront plan uses: the deepest halo leaves 16 x 16 tiles (a
+// small Dirichlet domain is one whole region).
+size_t wave_tiles_max(const pts_problem* p) {
+  if (p->bc == PTS_DIRICHLET && p->nx <= 64 && p->ny <= 64) return 1;
+  const size_t e = 64 - 2 * kMaxWaveHalo;
+  return ((p->nx + e - 1) / e) * ((p->ny + e - 1) / e);
+}
 
 Layout layout(const pts_problem* p) {
   const size_t ns = (size_t)p->nx * p->ny, st = ns * p->nt;
@@ -117,12 +126,17 @@ Layout layout(const pts_problem* p) {
   o = align_up(o + 8);
   L.U1 = o;  // second iterate slot of the wavefront schedule
   o = align_up(o + st * 8);
-  L.dU2 = o;  // second update slot of the wavefront schedule
-  o = align_up(o + st * 8);
-  L.rho_st = o;
-  o = align_up(o + (size_t)(kMaxStages + 1) * p->nt * 8);
+  {  // per-tile slots of the wavefront sequences, for the smallest tile any plan uses
+    const size_t nt_max = wave_tiles_max(p);
+    L.rho_part = o;
+    o = align_up(o + (size_t)(kMaxStages + 1) * 4 * nt_max * 8);
+    L.res_part = o;
+    o = align_up(o + (size_t)(kMaxStages + 1) * nt_max * 8);
+  }
   L.res_st = o;
   o = align_up(o + (kMaxStages + 1) * 8);
+  L.bar = o;  // grid-barrier state of the cooperative wavefront sequence
+  o = align_up(o + 8);
   L.u0copy = o;  // copy of u^0 for the wavefront sequences (keeps captured graphs independent of it)
   o = align_up(o + ns * 8);
   L.win = o;  // Theorem-1 windows: right-hand sides of a window plus two chain vectors
@@ -485,6 +499,8 @@ int check_opts(const pts_options* o) {
   if (o->schedule != PTS_SCHED_AUTO && o->schedule != PTS_SCHED_BULK && o->schedule != PTS_SCHED_PIPELINE)
     return fail(PTS_ERR_INVALID_ARG, "schedule %d not available", o->schedule);
   if (o->stages < 0 || o->stages > kMaxStages) return fail(PTS_ERR_INVALID_ARG, "stages %d", o->stages);
+  if (o->wave_launch != 0 && o->wave_launch != 1) return fail(PTS_ERR_INVALID_ARG, "wave_launch %d", o->wave_launch);
+  if (o->barrier_spins < 0) return fail(PTS_ERR_INVALID_ARG, "negative option");
   return PTS_OK;
 }
 
@@ -615,7 +631,6 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
 // and the tile must stay valid one node beyond its edge, so the halo is the number of
 // neighbour exchanges plus one: H = (s - 1) + (P - 1) s + 1, tile edge 64 - 2H. Fewer
 // sweeps therefore also mean larger tiles and fewer work-groups per level.
-constexpr int kMaxWaveHalo = 24;  // tile edge >= 16
 
 int wave_halo(const Plan& pl) { return (pl.sweeps - 1) + (pl.passes - 1) * pl.sweeps + 1; }
 
@@ -704,6 +719,63 @@ struct WaveGraph {
 };
 thread_local std::vector<WaveGraph> g_wave_graphs;
 
+// algorithmic bytes of anti-diagonal d: per active (stage, level) pair, U_j^n and
+// U_{j+1}^{n-1} read, U_{j+1}^n written
+double wave_bytes(const pts_problem* p, int stages, int d) {
+  const int active = std::min(stages, d / 2 + 1) - std::max(0, (d - p->nt + 2) / 2);
+  return 8.0 * 3.0 * (double)p->nx * p->ny * std::max(active, 0);
+}
+
+// Whether the cooperative form of a sequence fits: the device supports cooperative launches
+// and holds every work-group at once (checked once per kernel and device).
+bool wave_seq_fits(const void* kern, int blocks) {
+  struct E {
+    int dev;
+    const void* k;
+    int capacity;
+  };
+  static thread_local std::vector<E> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  for (const E& e : cache)
+    if (e.dev == dev && e.k == kern) return blocks <= e.capacity;
+  int coop = 0, cus = 0, per = 0;
+  int cap = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kThreads, 0) == hipSuccess)
+    cap = per * cus;
+  cache.push_back({dev, kern, cap});
+  return blocks <= cap;
+}
+
+// One cooperative launch for the whole sequence (k_level_wave_seq). *used = false when it
+// does not fit the device (nothing launched; the caller launches per anti-diagonal).
+int launch_wave_coop(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
+                     hipStream_t s, Prof* pr, int* launches, unsigned* bar, unsigned spins, bool* used) {
+  const bool per = p->bc == PTS_PERIODIC;
+  auto kern = pl.fp32 ? (per ? k_level_wave_seq<float, 1> : k_level_wave_seq<float, 0>)
+                      : (per ? k_level_wave_seq<double, 1> : k_level_wave_seq<double, 0>);
+  const int blocks = wa.stages * tiles(p, g);
+  *used = wave_seq_fits((const void*)kern, blocks);
+  if (!*used) return PTS_OK;
+  KProb a0 = kp;
+  WaveArgs a1 = wa;
+  Geo a2 = g;
+  int ndiag = p->nt + 2 * (wa.stages - 1), passes = pl.passes, sweeps = pl.sweeps;
+  void* args[] = {&a0, &a1, &a2, &ndiag, &passes, &sweeps, &bar, &spins};
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, (unsigned long long*)bar, 1);
+  prof_begin(pr, 1, s);
+  HIPCHK(hipLaunchCooperativeKernel((const void*)kern, dim3(blocks), dim3(kThreads), args, 0, s));
+  if (pr) {
+    for (int d = 0; d < ndiag; ++d) pr->bytes += wave_bytes(p, wa.stages, d);
+    pr->end(s);
+    pr->recs.back().count = ndiag;
+  }
+  *launches += 2;
+  return PTS_OK;
+}
+
 int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
                          hipStream_t s, Prof* pr, int* launches) {
   const int tl = tiles(p, g);
@@ -716,11 +788,7 @@ int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& 
     auto kern = pl.fp32 ? (per ? k_level_wave<float, 1> : k_level_wave<float, 0>)
                         : (per ? k_level_wave<double, 1> : k_level_wave<double, 0>);
     hipLaunchKernelGGL(kern, dim3(wa.stages * tl), dim3(kThreads), 0, s, kp, wa, g, d, pl.passes, pl.sweeps);
-    if (pr) {
-      const int active = std::min(wa.stages, d / 2 + 1) - std::max(0, (d - p->nt + 2) / 2);
-      // per active (stage, level): reads U_j^n, U_j^{n-1}, du_j^{n-1}; writes du_j^n, U_{j+1}^n
-      pr->bytes += 8.0 * 5.0 * (double)p->nx * p->ny * std::max(active, 0);
-    }
+    if (pr) pr->bytes += wave_bytes(p, wa.stages, d);
     ++*launches;
   }
   if (pr) {
@@ -794,9 +862,9 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
   if (rc) return rc;
   char* wsb = (char*)ws;
   double* U1 = (double*)(wsb + in.L.U1);
-  double* dU2 = (double*)(wsb + in.L.dU2);
-  unsigned long long* rho_st = (unsigned long long*)(wsb + in.L.rho_st);
-  unsigned long long* res_st = (unsigned long long*)(wsb + in.L.res_st);
+  double* rho_part = (double*)(wsb + in.L.rho_part);
+  double* res_part = (double*)(wsb + in.L.res_part);
+  double* res_st = (double*)(wsb + in.L.res_st);
   double* u0w = (double*)(wsb + in.L.u0copy);
   HIPCHK(hipMemcpyAsync(u0w, u0, (size_t)p->nx * p->ny * 8, hipMemcpyDeviceToDevice, s));
   int launches = 0, it = 0;
@@ -864,22 +932,32 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
       st->window = 1;
       st->schedule = PTS_SCHED_PIPELINE;
     }
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)(((K + 1) * p->nt + 255) / 256)), dim3(256), 0, s, rho_st,
-                       (K + 1) * p->nt);
-    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, res_st, K + 1);
-    launches += 2;
+    const int tl = tiles(p, g);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(((K + 1) * tl + 255) / 256)), dim3(256), 0, s,
+                       (unsigned long long*)res_part, (K + 1) * tl);
+    launches += 1;
     WaveArgs wa;
     wa.Ur[0] = U;
     wa.Ur[1] = U1;
-    wa.dUr[0] = in.dU;
-    wa.dUr[1] = dU2;
     wa.u0 = u0w;
     wa.rho_in = (const double*)in.rho;
-    wa.rho_st = rho_st;
-    wa.res_st = res_st;
+    wa.rho_part = rho_part;
+    wa.res_part = res_part;
+    wa.tiles = tl;
     wa.stages = K;
-    rc = run_wave_sequence(p, in.kp, wa, g, pl, s, use_graph, profiling ? &prof : nullptr, &launches);
-    if (rc) return rc;
+    unsigned* bar = (unsigned*)(wsb + in.L.bar);
+    bool coop = false;
+    if (o && o->wave_launch == 1) {
+      const unsigned spins = (o && o->barrier_spins > 0) ? (unsigned)o->barrier_spins : (1u << 20);
+      rc = launch_wave_coop(p, in.kp, wa, g, pl, s, profiling ? &prof : nullptr, &launches, bar, spins, &coop);
+      if (rc) return rc;
+    }
+    if (!coop) {
+      rc = run_wave_sequence(p, in.kp, wa, g, pl, s, use_graph, profiling ? &prof : nullptr, &launches);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_stage_max, dim3(K + 1), dim3(256), 0, s, res_part, tl, res_st);
+    ++launches;
     if (K & 1) {
       HIPCHK(hipMemcpyAsync(U, U1, st_count * 8, hipMemcpyDeviceToDevice, s));
     }
@@ -887,7 +965,12 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     // has not converged, the all-level residual of U_{it+K} also gives the radii with
     // which the next sequence starts
     HIPCHK(hipMemcpyAsync(hs + 8, res_st, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+    if (coop) HIPCHK(hipMemcpyAsync(hs + 40, bar, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (coop && ((const unsigned*)(hs + 40))[1] != 0) {
+      if (st) st->iterations = it;
+      return fail(PTS_ERR_HIP, "wavefront sequence abandoned: a grid-barrier wait exceeded its poll limit");
+    }
     for (int k = 1; k <= K; ++k) {
       const double rk = hs[8 + k];
       if (st && it + k < PTS_MAX_HIST) st->res_inf[it + k] = rk;
@@ -1716,11 +1799,26 @@ int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const
   const size_t ns = (size_t)p->nx * p->ny;
   const bool acc = judge == PTS_NO_JUDGE_ACCUMULATED;
   // residual of the prediction in the judge's norm -> scal[0]
-  if ((rc = in.residual(U, u0, s, &dummy, acc))) return rc;
-  if (acc) {
-    const unsigned blocks = (unsigned)std::min<size_t>((ns + 63) / 64, kUpdateBlocks);
-    hipLaunchKernelGGL(k_cumsum_absmax, dim3(blocks), dim3(64), 0, s, ns, p->nt, in.R, in.partial);
+  const int nchunks = (p->nt + kJudgeLevels - 1) / kJudgeLevels;
+  if (acc && 3 * nchunks <= p->nt) {
+    // accumulated form in two passes over U; the residual buffer (nt levels) holds the three
+    // chunk summaries
+    double* tot = in.R;
+    double* hi = tot + (size_t)nchunks * ns;
+    double* lo = hi + (size_t)nchunks * ns;
+    const dim3 g1((unsigned)((ns + 255) / 256), (unsigned)nchunks);
+    hipLaunchKernelGGL(k_judge_chunks<1>, g1, dim3(256), 0, s, in.kp, U, u0, tot, hi, lo);
+    const unsigned blocks = (unsigned)std::min<size_t>((ns + 255) / 256, kUpdateBlocks);
+    hipLaunchKernelGGL(k_judge_fold, dim3(blocks), dim3(256), 0, s, ns, nchunks, tot, hi, lo, in.partial);
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, in.partial, (size_t)blocks, in.scal);
+  } else {
+    // stored residual (nt < 3 leaves no room for the summaries), accumulated if asked
+    if ((rc = in.residual(U, u0, s, &dummy, acc))) return rc;
+    if (acc) {
+      const unsigned blocks = (unsigned)std::min<size_t>((ns + 63) / 64, kUpdateBlocks);
+      hipLaunchKernelGGL(k_cumsum_absmax, dim3(blocks), dim3(64), 0, s, ns, p->nt, in.R, in.partial);
+      hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, in.partial, (size_t)blocks, in.scal);
+    }
   }
   // the plain iterate's residual is -tau F(u^0) at every level (u^n - u^{n-1} = 0), i.e. the
   // one-level residual at u^0 (-> scal[2]); its accumulated form at level n is n times that

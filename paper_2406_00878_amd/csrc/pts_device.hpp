@@ -31,6 +31,14 @@ struct Geo {
   int whole;   // 1: one region covers the whole Dirichlet domain (no halo needed)
 };
 
+// Work-groups go to the chip's 8 XCDs round-robin by linear id, and each XCD has an L2 of its
+// own. xcd_band(b, n) renumbers index b of n (n a multiple of 8, else unchanged) so that each
+// XCD receives one contiguous band of n/8 indices: tiles that share halo data then share an L2.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned n) {
+  return n % kXcds ? b : (b % kXcds) * (n / kXcds) + b / kXcds;
+}
+
 struct Nb {
   double P, W, E, S, N;
 };

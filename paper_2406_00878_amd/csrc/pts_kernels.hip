@@ -484,37 +484,41 @@ __global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict
 }
 
 // ---------------------------------------------------------- wavefront schedule
-// Newton iteration j at level n needs the iterate U_j at levels n-1, n (written by
-// iteration j-1) and du_j^{n-1} (iteration j, level n-1). All pairs (j, n) on the
-// anti-diagonal n + 2j = diag are therefore independent and run in one launch; the
+// Newton iteration j at level n needs the iterate U_j at level n (written by iteration
+// j-1) and U_{j+1}^{n-1} = U_j^{n-1} + du_j^{n-1} (iteration j, level n-1). All pairs (j, n)
+// on the anti-diagonal n + 2j = diag are therefore independent and run in one launch; the
 // launch order d = 0, 1, 2, ... carries every dependency, and no two pairs of one launch
-// touch the same level of the same buffer. Pair (j, n) forms r_j^n = -G^n(U_j) and the
-// rows of A_n(U_j) from U_j, solves A_n du_j^n = r_j^n + du_j^{n-1} on its tile, writes
-// du_j^n and U_{j+1}^n = U_j^n + du_j^n, and from the tile's U_{j+1} also the next
-// iterate's residual r_{j+1}^n and Gershgorin radius (reduced per level and per stage):
-// the radius of level n fixes the Chebyshev interval of stage j+1 at that level.
+// touch the same level of the same buffer. Pair (j, n) forms the rows of A_n(U_j) and the
+// right-hand side of Eq. (7), r_j^n + du_j^{n-1} = -(U_j^n - U_{j+1}^{n-1} + tau F(U_j^n))
+// (the -I block moves du_j^{n-1} into the time difference, so the update itself is never
+// stored), solves A_n du_j^n = that on its tile, writes U_{j+1}^n = U_j^n + du_j^n, and from
+// the tile's U_{j+1} also the next iterate's residual r_{j+1}^n and Gershgorin radius. The
+// radius of level n fixes the Chebyshev interval of stage j+1 at that level: each tile
+// leaves its value in a slot of its own (a ring of four levels per stage, read two
+// anti-diagonals later and overwritten four later), and the consuming pair takes the
+// maximum. The residual maxima go to one running slot per (stage, tile), folded after the
+// sequence (k_stage_max). Plain stores throughout: every slot has one writer at a time.
+// Per node and pair: U_j^n and U_{j+1}^{n-1} read, U_{j+1}^n written.
 struct WaveArgs {
   double* Ur[2];                  // iterate ring: stage j reads Ur[j & 1], writes Ur[(j + 1) & 1]
-  double* dUr[2];                 // update ring: stage j writes dUr[j & 1]
   const double* u0;               // initial condition (level 0)
   const double* rho_in;           // radius of A_n(U_0) at rho_in[2n + 1] (bit pattern)
-  unsigned long long* rho_st;     // [(stages + 1) * nt]: radius of A_n(U_j) at [j * nt + n]
-  unsigned long long* res_st;     // [stages + 1]: max |r(U_j)| at [j]
+  double* rho_part;               // [stages + 1][4][tiles]: radius of A_n(U_j) on a tile, slot n % 4
+  double* res_part;               // [stages + 1][tiles]: running max |r(U_j)| of a tile (zero at start)
+  int tiles;                      // tiles per level
   int stages;
 };
 
+// The pair (stage j, level n = diag - 2j) on one tile; nothing when n is outside the levels.
 template <typename T, int BC>
-__global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
-                                                         int sweeps) {
+__device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, const Geo& g, int j, int tile, int diag,
+                                          int passes, int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
   __shared__ double om[kMaxSweeps];
   __shared__ double red[2][kWaves];
   // U_j^n and U_{j+1}^{n-1} of the region parked in LDS while the inner solve runs (they
   // are needed again only afterwards; kept in registers they would spill)
   __shared__ double park[2][kRows][kThreads];
-  const int tiles_per_level = gridDim.x / a.stages;
-  const int j = blockIdx.x / tiles_per_level;
-  const int tile = blockIdx.x % tiles_per_level;
   const int n = diag - 2 * j;
   if (n < 0 || n >= p.nt) return;  // uniform over the work-group
   const int lane = threadIdx.x & 63;
@@ -523,13 +527,21 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
   const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
   const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
   const size_t ns = (size_t)p.nx * p.ny;
-  const double* Uj = a.Ur[j & 1];
-  const double* un = Uj + (size_t)n * ns;
-  const double* up = n == 0 ? a.u0 : Uj + (size_t)(n - 1) * ns;
-  const double* dup = n == 0 ? nullptr : a.dUr[j & 1] + (size_t)(n - 1) * ns;
+  const double* un = a.Ur[j & 1] + (size_t)n * ns;
+  // U_{j+1}^{n-1}, stored by the pair (j, n-1) on the previous anti-diagonal (u^0 at n = 0)
+  const double* upn_in = n == 0 ? a.u0 : a.Ur[(j + 1) & 1] + (size_t)(n - 1) * ns;
   const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
-  const double rho_j = j == 0 ? a.rho_in[2 * n + 1] : __longlong_as_double(a.rho_st[(size_t)j * p.nt + n]);
-  cheb_table(om, clamp_rho(rho_j), sweeps);
+  if (wave == 0) {  // radius of A_n(U_j): the residual kernel's at j = 0, else the tiles' maximum
+    double rho_j = 0.0;
+    if (j == 0) {
+      rho_j = a.rho_in[2 * n + 1];
+    } else {
+      const double* rp = a.rho_part + ((size_t)j * 4 + (n & 3)) * a.tiles;
+      for (int t = lane; t < a.tiles; t += 64) rho_j = nanmax(rho_j, rp[t]);
+      rho_j = wave_max(rho_j);
+    }
+    cheb_table(om, clamp_rho(rho_j), sweeps);
+  }
 
   RegionSolve<T> rs;
   double uc[kRows], upn[kRows];  // U_j^n and U_{j+1}^{n-1} at the region nodes
@@ -544,11 +556,10 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
     if (act) {
       const Nb u = gather<BC>(p, un, bd, x, y);
       const double F = eval_point<BC>(p, u, x, y, r5);
-      const double prev = ld(up, idx[k]);
-      const double dprev = dup ? ld(dup, idx[k]) : 0.0;
-      rs.bb[k] = -(u.P - prev + p.dt * F) + dprev;
+      const double prev = ld(upn_in, idx[k]);
+      rs.bb[k] = -(u.P - prev + p.dt * F);
       uc[k] = u.P;
-      upn[k] = prev + dprev;
+      upn[k] = prev;
     } else {
       r5.C = 1.0;
       r5.W = r5.E = r5.S = r5.N = 0.0;
@@ -578,7 +589,6 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
   int par = 0;
   const YNb<double> yn = y_exchange<double>(unew, lds_raw, par, wave, lane);
   double rmax = 0.0, gmax = 0.0;
-  double* dUo = a.dUr[j & 1] + (size_t)n * ns;
   double* Uo = a.Ur[(j + 1) & 1] + (size_t)n * ns;
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
@@ -603,7 +613,6 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
       const double r = -(u.P - upn[k] + p.dt * F);
       rmax = nanmax(rmax, fabs(r));
       gmax = nanmax(gmax, gersh(q));
-      st(dUo, idx[k], rs.X[k]);
       st(Uo, idx[k], unew[k]);
     }
   }
@@ -620,8 +629,69 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
       r = nanmax(r, red[0][w]);
       q = nanmax(q, red[1][w]);
     }
-    atomic_max_nonneg(a.res_st + j + 1, r);
-    atomic_max_nonneg(a.rho_st + (size_t)(j + 1) * p.nt + n, q);
+    double* rs = a.res_part + (size_t)(j + 1) * a.tiles + tile;
+    *rs = nanmax(*rs, r);
+    a.rho_part[((size_t)(j + 1) * 4 + (n & 3)) * a.tiles + tile] = q;
+  }
+}
+
+// One launch per anti-diagonal: grid = stages x tiles per level, blockIdx.x = j * tiles + tile.
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
+                                                         int sweeps) {
+  const int tiles_per_level = gridDim.x / a.stages;
+  wave_pair<T, BC>(p, a, g, blockIdx.x / tiles_per_level, blockIdx.x % tiles_per_level, diag, passes, sweeps);
+}
+
+// The whole sequence in one cooperative launch (every work-group resident): work-group
+// (j, tile) takes its pair on each anti-diagonal in turn, and a grid barrier separates
+// consecutive anti-diagonals, in place of the kernel boundary. bar[0] counts arrivals (zero
+// at launch), bar[1] is set when a barrier wait exceeds spin_limit polls: every work-group
+// then leaves, the sequence is incomplete and the host reports it. Before arriving, each wave
+// waits for its stores and one release fence per work-group writes the XCD's L2 back, making
+// them visible to the other XCDs; after the wait one acquire fence per work-group drops stale
+// lines before the next anti-diagonal reads its neighbours' data. (Fences in every thread
+// would repeat the L2 write-back and invalidation once per wave.)
+template <typename T, int BC>
+__global__ __launch_bounds__(kThreads) void k_level_wave_seq(KProb p, WaveArgs a, Geo g, int ndiag, int passes,
+                                                             int sweeps, unsigned* bar, unsigned spin_limit) {
+  __shared__ int stop;
+  const int tiles_per_level = gridDim.x / a.stages;
+  const int j = blockIdx.x / tiles_per_level, tile = blockIdx.x % tiles_per_level;
+  for (int d = 0; d < ndiag; ++d) {
+    // j and tile pass through an empty asm statement, so the pair's region indices are formed
+    // anew on every anti-diagonal rather than hoisted out of the loop and held in registers
+    int jj = j, tt = tile;
+    asm volatile("" : "+s"(jj), "+s"(tt));
+    wave_pair<T, BC>(p, a, g, jj, tt, d, passes, sweeps);
+    if (d + 1 == ndiag) break;
+    // every wave waits until its stores have reached the L2 (all counters to zero); then one
+    // thread writes the XCD's L2 back (it holds the stores of all waves) and arrives
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);  // the write-back has completed before the arrival
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = (unsigned)(d + 1) * gridDim.x;
+      int quit = 0;
+      for (unsigned spins = 0;
+           __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++spins) {
+        if (spins >= spin_limit || __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          quit = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (quit) __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // invalidates the XCD's L2 and this compute unit's L1, which all waves read through,
+      // complete before the other waves pass the work-group barrier
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
+      stop = quit;
+    }
+    __syncthreads();
+    if (stop) return;
   }
 }
 
@@ -698,6 +768,20 @@ __global__ __launch_bounds__(256) void k_absmax(const double* __restrict__ a, si
   }
 }
 
+// out[k] = max_t part[k][t] over `tiles` slots for k = 0..stages (one block per k; NaN
+// propagates): the residual maxima of a wavefront sequence.
+__global__ __launch_bounds__(256) void k_stage_max(const double* __restrict__ part, int tiles,
+                                                   double* __restrict__ out) {
+  const double* pk = part + (size_t)blockIdx.x * tiles;
+  double m = 0.0;
+  for (int t = threadIdx.x; t < tiles; t += 256) m = nanmax(m, pk[t]);
+  m = wave_max(m);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+}
+
 // part[b] = max over the block's points p of max_n |sum_{m<=n} R[m][p]| (NaN propagates):
 // the block forward substitution of Eq. (7) with identity diagonal blocks. 64-thread work-
 // groups, grid-stride over the ns points of a level, levels read four at a time; fold part
@@ -727,6 +811,71 @@ __global__ __launch_bounds__(64) void k_cumsum_absmax(size_t ns, int nt, const d
   }
   m = wave_max(m);
   if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Accumulated-residual norm max_{n,p} |sum_{m<=n} r^m_p| of an iterate without storing R, in
+// two passes. Pass 1 (grid: points x chunks of kJudgeLevels levels): per point, the residuals
+// r^n = -(u^n - u^{n-1} + tau F(u^n)) of the chunk's levels, their total and the largest and
+// smallest partial sum inside the chunk -> tot, hi, lo [chunk][point]. Pass 2: per point, the
+// prefix P of the earlier chunks gives max |P + s| over the chunk's partial sums s as
+// max(|P + hi|, |P + lo|); block maxima -> part (fold with k_absmax). NaN propagates.
+constexpr int kJudgeLevels = 16;
+template <int BC>
+__global__ __launch_bounds__(256) void k_judge_chunks(KProb p, const double* __restrict__ U,
+                                                      const double* __restrict__ u0, double* __restrict__ tot,
+                                                      double* __restrict__ hi, double* __restrict__ lo) {
+  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
+  // gridDim.x is the fast index of the linear id, so a multiple of 8 keeps bands per XCD
+  const unsigned i = xcd_band(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (i >= ns) return;
+  const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
+  const int c = blockIdx.y, n0 = c * kJudgeLevels, n1 = min(p.nt, n0 + kJudgeLevels);
+  double acc = 0.0, mx = -__longlong_as_double(0x7ff0000000000000ll), mn = -mx;
+  // levels four at a time: all neighbour loads of a group are issued before its arithmetic
+  for (int g = n0; g < n1; g += 4) {
+    Nb u[4];
+    double prev[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int n = min(g + k, n1 - 1);
+      const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+      u[k] = gather<BC>(p, U + (size_t)n * ns, bd, x, y);
+      prev[k] = (n == 0 ? u0 : U + (size_t)(n - 1) * ns)[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (g + k < n1) {
+        Row5 r5;
+        const double F = eval_point<BC>(p, u[k], x, y, r5);
+        acc += -(u[k].P - prev[k] + p.dt * F);
+        mx = acc > mx || acc != acc ? acc : mx;
+        mn = acc < mn || acc != acc ? acc : mn;
+      }
+    }
+  }
+  const size_t o = (size_t)c * ns + i;
+  tot[o] = acc;
+  hi[o] = mx;
+  lo[o] = mn;
+}
+
+__global__ __launch_bounds__(256) void k_judge_fold(size_t ns, int nchunks, const double* __restrict__ tot,
+                                                    const double* __restrict__ hi, const double* __restrict__ lo,
+                                                    double* __restrict__ part) {
+  double m = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (size_t)gridDim.x * blockDim.x) {
+    double P = 0.0;
+    for (int c = 0; c < nchunks; ++c) {
+      const size_t o = (size_t)c * ns + i;
+      m = nanmax(m, nanmax(fabs(P + hi[o]), fabs(P + lo[o])));
+      P += tot[o];
+    }
+  }
+  m = wave_max(m);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
 }
 
 // Judge of the learned initial iterate, decided on the device: with rp = max|R| of the

@@ -516,10 +516,18 @@ Par par_layout(const pts_no_config* c) {
 
 // workspace offsets (bytes, 256-aligned)
 struct Ws {
-  size_t phix, phiy, tphi, s64, v, z, vh, wh, t1, t2, coef, dcoef, dv, dv2, dz, dvh, dwh, part, gpart, rpart, total;
+  size_t phix, phiy, tphi, s64, v, z, vh, wh, t1, t2, coef, dcoef, dv, dv2, dz, dvh, dwh, part, gpart, tpart, rpart,
+      total;
 };
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
 constexpr int kSplit = 32;
+// K split of a product with `tiles` output tiles (all batches) and depth K: enough work-groups
+// for two per compute unit, at least one K step of BK each, at most 16 ranges
+int split_of(long tiles, int K) {
+  const long want = (512 + tiles - 1) / tiles;
+  return (int)std::max(1L, std::min({want, (long)(K / BK), 16L}));
+}
+long tiles_of(int M, int N, int batch) { return (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch; }
 constexpr int kPartSlots = 4096;  // loss partial sums (one per block of the loss kernels)
 Ws ws_layout(const pts_no_config* c) {
   Ws w;
@@ -549,6 +557,12 @@ Ws ws_layout(const pts_no_config* c) {
   w.dwh = take(C * Q * 4);
   w.part = take(kPartSlots * 8);
   w.gpart = take((size_t)kSplit * std::max((size_t)c->tmodes, C) * C * 4);
+  {  // partials of the two products onto the modes (x direction, then y direction per channel)
+    const int M1 = (int)C * c->ny, M2 = (int)m2;
+    const size_t p1 = (size_t)split_of(tiles_of(M1, (int)m2, 1), c->nx) * M1 * m2;
+    const size_t p2 = (size_t)split_of(tiles_of(M2, M2, (int)C), c->ny) * C * Q;
+    w.tpart = take(std::max(p1, p2) * 4);
+  }
   w.rpart = take((size_t)kMaxT * kRowSlices * 4);
   w.total = o;
   return w;
@@ -614,15 +628,21 @@ struct Net {
     Q = m2 * m2;
     np = (long)nx * ny;
   }
-  // vh = (1/np) phiy^T v phix  for the C channels of v [C][ny][nx]
-  int forward_transform(hipStream_t s, const float* vin, float* vhat) {
+  // out = alpha phiy^T v phix for the C channels of v [C][ny][nx]; both products are deep
+  // in K (nx, ny) with few output tiles, so they run split in K (partials summed in order)
+  int to_modes(hipStream_t s, const float* vin, float* out, float alpha) {
     const float* phix = f(W.phix);
     const float* phiy = f(W.phiy);
     float* t1 = f(W.t1);
-    int rc = gemm(s, C * ny, m2, nx, 1.f, vin, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0);
+    float* tp = f(W.tpart);
+    int rc = gemm(s, C * ny, m2, nx, 1.f, vin, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0, 1,
+                  split_of(tiles_of(C * ny, m2, 1), nx), tp);
     if (rc) return rc;
-    return gemm(s, m2, m2, ny, 1.f / (float)np, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, vhat, m2, 1, Q, C);
+    return gemm(s, m2, m2, ny, alpha, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, out, m2, 1, Q, C,
+                split_of(tiles_of(m2, m2, C), ny), tp);
   }
+  // vh = (1/np) phiy^T v phix
+  int forward_transform(hipStream_t s, const float* vin, float* vhat) { return to_modes(s, vin, vhat, 1.f / (float)np); }
   // out (+)= phiy what phix^T for C channels; beta = 0 writes, 1 accumulates
   int inverse_transform(hipStream_t s, const float* what, float* out, float beta) {
     const float* phix = f(W.phix);
@@ -659,10 +679,7 @@ struct Net {
         return rc;
       if ((rc = gemm(s, C, (int)np, C, 1.f, params + P.W[l], 1, C, 0, dz, np, 1, 0, 0.f, dv2, np, 1, 0))) return rc;
       // spectral branch: dwhat = phiy^T dz phix (adjoint of the inverse transform)
-      float* t1 = f(W.t1);
-      if ((rc = gemm(s, C * ny, m2, nx, 1.f, dz, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0))) return rc;
-      if ((rc = gemm(s, m2, m2, ny, 1.f, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, f(W.dwh), m2, 1, Q, C)))
-        return rc;
+      if ((rc = to_modes(s, dz, f(W.dwh), 1.f))) return rc;
       hipLaunchKernelGGL(k_mix_back, dim3(mix_blocks(C, c->modes)), dim3(256), 0, s, C, c->modes,
                          params + P.R[l], vh(l),
                          f(W.dwh), f(W.dvh), grads + P.R[l]);

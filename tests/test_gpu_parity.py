@@ -272,6 +272,56 @@ def test_wavefront_mixed_precision():
     assert relerr(U, Us) <= 1e-8
 
 
+def _coop_case(case):
+    rng = np.random.default_rng(31)
+    if case == "periodic_fp64":
+        p = W.burgers_periodic(80, 24, 5e-4, 0.01, W.fourier_u0_periodic(80, 11)[:72, :])
+        p.ny, p.hy = 72, 1.0 / 72
+        return p, "fp64", 8
+    if case == "dirichlet_bdata_fp64":
+        return (W.Problem(W.BURGERS, W.DIRICHLET, 75, 70, 6, 1 / 76, 1 / 71, 1e-3, 0.02, 0.0,
+                          0.5 * rng.uniform(-1, 1, (70, 75)), 0.5 * rng.uniform(-1, 1, (6, 2 * 145))), "fp64", 8)
+    return W.burgers_periodic(96, 32, 2.5e-4, 1e-3, W.disc_u0_periodic(96, 2406003)), "mixed", 6
+
+
+@pytest.mark.parametrize("case", ["periodic_fp64", "dirichlet_bdata_fp64", "periodic_mixed"])
+def test_cooperative_sequence_matches_per_diagonal_launches(case):
+    """One cooperative launch per wavefront sequence (grid barrier between anti-diagonals) and
+    one launch per anti-diagonal run the same pairs in the same order: bit-identical iterates
+    for a fixed plan, and both match the oracle."""
+    p, prec, sweeps = _coop_case(case)
+    plan = dict(schedule="pipeline", stages=4, sweeps=sweeps, refine=0 if prec == "fp64" else 1)
+    Uc, sc = gpu_solve(p, tol=1e-12, precision=prec, wave_launch="sequence", **plan)
+    Ud, sd = gpu_solve(p, tol=1e-12, precision=prec, wave_launch="diagonal", **plan)
+    assert sc["converged"] and sd["converged"] and sc["iterations"] == sd["iterations"]
+    assert np.array_equal(Uc, Ud)
+    # the cooperative form issues a couple of launches per sequence instead of one per anti-diagonal
+    assert sc["launches"] < sd["launches"] or sd["launches"] <= 4 * sd["iterations"]
+    Us, _ = sequential.solve_sequential(p)
+    assert relerr(Uc, Us) <= (1e-10 if prec == "fp64" else 1e-8)
+
+
+def test_cooperative_barrier_poll_limit_reports_error_and_recovers():
+    """A grid-barrier wait that exceeds its poll limit (forced from the host with a limit of one
+    poll: work-groups of later stages wait at the first barrier while stage 0 works) abandons
+    the sequence with an error, every work-group having left; the next solve on the same
+    workspace is unaffected."""
+    p = W.burgers_periodic(64, 30, 5e-4, 0.01, W.fourier_u0_periodic(64, 5))
+    ws = P.workspace(p, "fp64")
+    u0 = dev(p.u0)
+    U = dev(p.plain_iterate())
+    print("[coop] poll limit 1", flush=True)
+    st = P.solve(p, U, u0, tol=1e-12, ws=ws, schedule="pipeline", stages=4, sweeps=8, refine=0,
+                 wave_launch="sequence", barrier_spins=1, raise_on_error=False)
+    assert st["rc"] == P.PTS_ERR_HIP and "grid-barrier" in st["error"], st.get("error")
+    U = dev(p.plain_iterate())
+    st = P.solve(p, U, u0, tol=1e-12, ws=ws, schedule="pipeline", stages=4, sweeps=8, refine=0,
+                 wave_launch="sequence")
+    assert st["converged"]
+    Us, _ = sequential.solve_sequential(p)
+    assert relerr(host(U), Us) <= 1e-10
+
+
 def test_autotune_restores_iterate_and_tuned_solve_matches_oracle():
     p = W.burgers_periodic(64, 40, 5e-4, 0.01, W.fourier_u0_periodic(64, 21))
     U = dev(p.plain_iterate())
