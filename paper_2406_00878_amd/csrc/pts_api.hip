@@ -87,6 +87,15 @@ KProb kprob(const pts_problem* p) {
   k.ihx2 = k.ihx * k.ihx;
   k.ihy2 = k.ihy * k.ihy;
   k.bdata = p->bc == PTS_DIRICHLET ? p->bdata : nullptr;
+  k.cx = 0.5 * k.cf * k.ihx;
+  k.cy = 0.5 * k.cf * k.ihy;
+  k.vx = k.mu_a * k.ihx2;
+  k.vy = k.mu_a * k.ihy2;
+  k.ax = k.dt * k.vx;
+  k.ay = k.dt * k.vy;
+  k.bx = k.dt * k.cf * k.ihx;
+  k.by = k.dt * k.cf * k.ihy;
+  k.c0 = 1.0 + 2.0 * (k.ax + k.ay);
   return k;
 }
 
@@ -719,6 +728,34 @@ struct WaveGraph {
 };
 thread_local std::vector<WaveGraph> g_wave_graphs;
 
+// Flux form of a problem (see eval_point): constant viscosity, no convection, or general.
+int flux_form(const pts_problem* p) {
+  if (p->mu_b == 0.0) return kFormConstVisc;
+  if (p->kind == PTS_HEAT) return kFormNoConv;
+  return kFormGeneral;
+}
+
+// The wavefront kernel for a problem (inner type, boundary kind, flux form): one launch per
+// anti-diagonal, or with seq the cooperative whole-sequence form.
+typedef void (*WaveKernel)(KProb, WaveArgs, Geo, int, int, int);
+typedef void (*WaveSeqKernel)(KProb, WaveArgs, Geo, int, int, int, unsigned*, unsigned);
+template <typename T, int BC>
+const void* wave_kernel_bc(int form, bool seq) {
+  if (seq)
+    return (const void*)(form == kFormConstVisc ? (WaveSeqKernel)k_level_wave_seq<T, BC, kFormConstVisc>
+                         : form == kFormNoConv  ? (WaveSeqKernel)k_level_wave_seq<T, BC, kFormNoConv>
+                                                : (WaveSeqKernel)k_level_wave_seq<T, BC, kFormGeneral>);
+  return (const void*)(form == kFormConstVisc ? (WaveKernel)k_level_wave<T, BC, kFormConstVisc>
+                       : form == kFormNoConv  ? (WaveKernel)k_level_wave<T, BC, kFormNoConv>
+                                              : (WaveKernel)k_level_wave<T, BC, kFormGeneral>);
+}
+const void* wave_kernel(const pts_problem* p, bool fp32, bool seq) {
+  const bool per = p->bc == PTS_PERIODIC;
+  const int f = flux_form(p);
+  return fp32 ? (per ? wave_kernel_bc<float, 1>(f, seq) : wave_kernel_bc<float, 0>(f, seq))
+              : (per ? wave_kernel_bc<double, 1>(f, seq) : wave_kernel_bc<double, 0>(f, seq));
+}
+
 // algorithmic bytes of anti-diagonal d: per active (stage, level) pair, U_j^n and
 // U_{j+1}^{n-1} read, U_{j+1}^n written
 double wave_bytes(const pts_problem* p, int stages, int d) {
@@ -753,9 +790,7 @@ bool wave_seq_fits(const void* kern, int blocks) {
 // does not fit the device (nothing launched; the caller launches per anti-diagonal).
 int launch_wave_coop(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
                      hipStream_t s, Prof* pr, int* launches, unsigned* bar, unsigned spins, bool* used) {
-  const bool per = p->bc == PTS_PERIODIC;
-  auto kern = pl.fp32 ? (per ? k_level_wave_seq<float, 1> : k_level_wave_seq<float, 0>)
-                      : (per ? k_level_wave_seq<double, 1> : k_level_wave_seq<double, 0>);
+  auto kern = wave_kernel(p, pl.fp32, true);
   const int blocks = wa.stages * tiles(p, g);
   *used = wave_seq_fits((const void*)kern, blocks);
   if (!*used) return PTS_OK;
@@ -783,10 +818,8 @@ int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& 
   // profiling brackets the whole back-to-back sequence (per-launch events would add their
   // own overhead to every launch); the average launch is the interval over ndiag
   prof_begin(pr, 1, s);
+  const WaveKernel kern = (WaveKernel)wave_kernel(p, pl.fp32, false);
   for (int d = 0; d < ndiag; ++d) {
-    const bool per = p->bc == PTS_PERIODIC;
-    auto kern = pl.fp32 ? (per ? k_level_wave<float, 1> : k_level_wave<float, 0>)
-                        : (per ? k_level_wave<double, 1> : k_level_wave<double, 0>);
     hipLaunchKernelGGL(kern, dim3(wa.stages * tl), dim3(kThreads), 0, s, kp, wa, g, d, pl.passes, pl.sweeps);
     if (pr) pr->bytes += wave_bytes(p, wa.stages, d);
     ++*launches;

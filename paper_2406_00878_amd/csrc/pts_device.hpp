@@ -20,6 +20,11 @@ struct KProb {
   double dt, mu_a, mu_b, cf;
   double ihx, ihy, ihx2, ihy2;  // 1/hx, 1/hy, 1/hx^2, 1/hy^2
   const double* bdata;          // [nt][2(nx+ny)] or nullptr
+  // constant-viscosity form: F = cx (E^2 - W^2) + cy (N^2 - S^2) - vx (E - 2P + W)
+  // - vy (N - 2P + S); row of A: C = c0, W = -ax - bx u_W, E = -ax + bx u_E, S = -ay - by u_S,
+  // N = -ay + by u_N (cx = cf / 2hx, vx = mu_a / hx^2, ax = tau vx, bx = tau cf / hx, c0 =
+  // 1 + 2 (ax + ay))
+  double cx, cy, vx, vy, ax, ay, bx, by, c0;
 };
 
 // Tiling of a level for the register-resident solve: a 64 x 64 region per work-group,
@@ -108,23 +113,53 @@ struct Row5 {
   double C, W, E, S, N;
 };
 
+// Forms of the flux that fix terms at compile time: general; constant viscosity (mu_b = 0,
+// the viscous Burgers equation: coefficients folded into constants, E^2 - W^2 formed as
+// (E - W)(E + W)); no convection (cf = 0, the heat equation: the convective terms, exact
+// zeros there, are dropped). On its problems a special form agrees with the general form up
+// to rounding.
+enum { kFormGeneral = 0, kFormConstVisc = 1, kFormNoConv = 2 };
+
 // F_P of Eq. (3) and the row of A at P from one evaluation of the face viscosities.
-template <int BC>
+template <int BC, int FORM = kFormGeneral>
 __device__ __forceinline__ double eval_point(const KProb& p, const Nb& u, int x, int y, Row5& r) {
-  const double me = mu_of(p, 0.5 * (u.P + u.E)), mw = mu_of(p, 0.5 * (u.P + u.W));
-  const double mn = mu_of(p, 0.5 * (u.P + u.N)), ms = mu_of(p, 0.5 * (u.P + u.S));
+  if constexpr (FORM == kFormConstVisc) {
+    // the same discrete operator with the constant coefficients folded on the host
+    const double sx = u.E + u.W, sy = u.N + u.S;
+    const double conv = p.cx * ((u.E - u.W) * sx) + p.cy * ((u.N - u.S) * sy);
+    const double visc = p.vx * fma(-2.0, u.P, sx) + p.vy * fma(-2.0, u.P, sy);
+    r.C = p.c0;
+    r.W = fma(-p.bx, u.W, -p.ax);
+    r.E = fma(p.bx, u.E, -p.ax);
+    r.S = fma(-p.by, u.S, -p.ay);
+    r.N = fma(p.by, u.N, -p.ay);
+    if (BC == 0) {
+      if (x == 0) r.W = 0.0;
+      if (x == p.nx - 1) r.E = 0.0;
+      if (y == 0) r.S = 0.0;
+      if (y == p.ny - 1) r.N = 0.0;
+    }
+    return conv - visc;
+  }
+  constexpr bool var_visc = FORM != kFormConstVisc, has_conv = FORM != kFormNoConv;
+  const double me = var_visc ? mu_of(p, 0.5 * (u.P + u.E)) : p.mu_a;
+  const double mw = var_visc ? mu_of(p, 0.5 * (u.P + u.W)) : p.mu_a;
+  const double mn = var_visc ? mu_of(p, 0.5 * (u.P + u.N)) : p.mu_a;
+  const double ms = var_visc ? mu_of(p, 0.5 * (u.P + u.S)) : p.mu_a;
   const double E2 = u.E * u.E, W2 = u.W * u.W, N2 = u.N * u.N, S2 = u.S * u.S, P2 = u.P * u.P;
-  const double conv = p.cf * (0.5 * p.ihx * (E2 - W2) + 0.5 * p.ihy * (N2 - S2));
+  const double conv = has_conv ? p.cf * (0.5 * p.ihx * (E2 - W2) + 0.5 * p.ihy * (N2 - S2)) : 0.0;
   const double visc = p.ihx2 * (me * (u.E - u.P) - mw * (u.P - u.W)) + p.ihy2 * (mn * (u.N - u.P) - ms * (u.P - u.S));
   // d mu_face / d u_node = mu_b (u_P + u_X) / 2 for either node of the face
   const double hb = 0.5 * p.mu_b;
-  const double qe = hb * (E2 - P2), qw = hb * (P2 - W2);
-  const double qn = hb * (N2 - P2), qs = hb * (P2 - S2);
+  const double qe = var_visc ? hb * (E2 - P2) : 0.0, qw = var_visc ? hb * (P2 - W2) : 0.0;
+  const double qn = var_visc ? hb * (N2 - P2) : 0.0, qs = var_visc ? hb * (P2 - S2) : 0.0;
+  const double cw = has_conv ? p.cf * u.W * p.ihx : 0.0, ce = has_conv ? p.cf * u.E * p.ihx : 0.0;
+  const double cs = has_conv ? p.cf * u.S * p.ihy : 0.0, cn = has_conv ? p.cf * u.N * p.ihy : 0.0;
   r.C = 1.0 + p.dt * ((me + mw - qe + qw) * p.ihx2 + (mn + ms - qn + qs) * p.ihy2);
-  r.W = p.dt * (-(mw - qw) * p.ihx2 - p.cf * u.W * p.ihx);
-  r.E = p.dt * (-(me + qe) * p.ihx2 + p.cf * u.E * p.ihx);
-  r.S = p.dt * (-(ms - qs) * p.ihy2 - p.cf * u.S * p.ihy);
-  r.N = p.dt * (-(mn + qn) * p.ihy2 + p.cf * u.N * p.ihy);
+  r.W = p.dt * (-(mw - qw) * p.ihx2 - cw);
+  r.E = p.dt * (-(me + qe) * p.ihx2 + ce);
+  r.S = p.dt * (-(ms - qs) * p.ihy2 - cs);
+  r.N = p.dt * (-(mn + qn) * p.ihy2 + cn);
   if (BC == 0) {
     if (x == 0) r.W = 0.0;
     if (x == p.nx - 1) r.E = 0.0;
@@ -174,6 +209,17 @@ __device__ __forceinline__ double nanmax(double a, double b) {
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+// max of two values that are >= 0 or a NaN with a clear sign bit, NaN winning: read as
+// unsigned 64-bit integers, the bit patterns of such values are ordered like the values and
+// the NaN patterns lie above +inf (one integer compare instead of a NaN test and fmax)
+__device__ __forceinline__ double max_nn(double a, double b) {
+  return (unsigned long long)__double_as_longlong(a) > (unsigned long long)__double_as_longlong(b) ? a : b;
+}
+// max_nn over the lanes of each aligned group of `width` lanes (a power of two <= 64)
+__device__ __forceinline__ double group_max_nn(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v = max_nn(v, __shfl_xor(v, o, kWave));
   return v;
 }
 __device__ __forceinline__ double wave_sum(double v) {

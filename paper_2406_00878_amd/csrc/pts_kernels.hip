@@ -277,7 +277,9 @@ __device__ __forceinline__ void level_solve_tile(const KProb& p, int n, int tile
                                                  const double* __restrict__ rho_lvl, const Geo& g, int passes,
                                                  int sweeps, double* lds_raw, double* om) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave index as a wave-uniform value: row indices, their products with the row stride and
+  // the periodic wrap of rows are then scalar work
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tx = tile % g.tilesx, ty = tile / g.tilesx;
   const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
   const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
@@ -510,7 +512,7 @@ struct WaveArgs {
 };
 
 // The pair (stage j, level n = diag - 2j) on one tile; nothing when n is outside the levels.
-template <typename T, int BC>
+template <typename T, int BC, int FORM>
 __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, const Geo& g, int j, int tile, int diag,
                                           int passes, int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
@@ -522,7 +524,9 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
   const int n = diag - 2 * j;
   if (n < 0 || n >= p.nt) return;  // uniform over the work-group
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave index as a wave-uniform value: row indices, their products with the row stride and
+  // the periodic wrap of rows are then scalar work
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tx = tile % g.tilesx, ty = tile / g.tilesx;
   const int rx0 = g.whole ? 0 : tx * g.TX - g.H;
   const int ry0 = g.whole ? 0 : ty * g.TY - g.H;
@@ -537,8 +541,8 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       rho_j = a.rho_in[2 * n + 1];
     } else {
       const double* rp = a.rho_part + ((size_t)j * 4 + (n & 3)) * a.tiles;
-      for (int t = lane; t < a.tiles; t += 64) rho_j = nanmax(rho_j, rp[t]);
-      rho_j = wave_max(rho_j);
+      for (int t = lane; t < a.tiles; t += 64) rho_j = max_nn(rho_j, rp[t]);
+      rho_j = group_max_nn(rho_j, 64);
     }
     cheb_table(om, clamp_rho(rho_j), sweeps);
   }
@@ -555,7 +559,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
     Row5 r5;
     if (act) {
       const Nb u = gather<BC>(p, un, bd, x, y);
-      const double F = eval_point<BC>(p, u, x, y, r5);
+      const double F = eval_point<BC, FORM>(p, u, x, y, r5);
       const double prev = ld(upn_in, idx[k]);
       rs.bb[k] = -(u.P - prev + p.dt * F);
       uc[k] = u.P;
@@ -609,38 +613,39 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
         if (y == p.ny - 1) u.N = node_value(p, un, bd, x, p.ny);
       }
       Row5 q;
-      const double F = eval_point<BC>(p, u, x, y, q);
+      const double F = eval_point<BC, FORM>(p, u, x, y, q);
       const double r = -(u.P - upn[k] + p.dt * F);
-      rmax = nanmax(rmax, fabs(r));
-      gmax = nanmax(gmax, gersh(q));
+      // |r| and the radius are >= 0 or NaN with a clear sign bit (max_nn applies)
+      rmax = max_nn(rmax, fabs(r));
+      gmax = max_nn(gmax, gersh(q));
       st(Uo, idx[k], unew[k]);
     }
   }
-  rmax = wave_max(rmax);
-  gmax = wave_max(gmax);
+  rmax = group_max_nn(rmax, 64);
+  gmax = group_max_nn(gmax, 64);
   if (lane == 0) {
     red[0][wave] = rmax;
     red[1][wave] = gmax;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = red[0][0], q = red[1][0];
-    for (int w = 1; w < kWaves; ++w) {
-      r = nanmax(r, red[0][w]);
-      q = nanmax(q, red[1][w]);
+  if (wave == 0) {  // the kWaves wave maxima, folded across lanes
+    const double r = group_max_nn(lane < kWaves ? red[0][lane] : 0.0, kWaves);
+    const double q = group_max_nn(lane < kWaves ? red[1][lane] : 0.0, kWaves);
+    if (lane == 0) {
+      double* rs = a.res_part + (size_t)(j + 1) * a.tiles + tile;
+      *rs = max_nn(*rs, r);
+      a.rho_part[((size_t)(j + 1) * 4 + (n & 3)) * a.tiles + tile] = q;
     }
-    double* rs = a.res_part + (size_t)(j + 1) * a.tiles + tile;
-    *rs = nanmax(*rs, r);
-    a.rho_part[((size_t)(j + 1) * 4 + (n & 3)) * a.tiles + tile] = q;
   }
 }
 
 // One launch per anti-diagonal: grid = stages x tiles per level, blockIdx.x = j * tiles + tile.
-template <typename T, int BC>
+template <typename T, int BC, int FORM>
 __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Geo g, int diag, int passes,
                                                          int sweeps) {
   const int tiles_per_level = gridDim.x / a.stages;
-  wave_pair<T, BC>(p, a, g, blockIdx.x / tiles_per_level, blockIdx.x % tiles_per_level, diag, passes, sweeps);
+  wave_pair<T, BC, FORM>(p, a, g, blockIdx.x / tiles_per_level, blockIdx.x % tiles_per_level, diag, passes,
+                         sweeps);
 }
 
 // The whole sequence in one cooperative launch (every work-group resident): work-group
@@ -652,7 +657,7 @@ __global__ __launch_bounds__(kThreads) void k_level_wave(KProb p, WaveArgs a, Ge
 // them visible to the other XCDs; after the wait one acquire fence per work-group drops stale
 // lines before the next anti-diagonal reads its neighbours' data. (Fences in every thread
 // would repeat the L2 write-back and invalidation once per wave.)
-template <typename T, int BC>
+template <typename T, int BC, int FORM>
 __global__ __launch_bounds__(kThreads) void k_level_wave_seq(KProb p, WaveArgs a, Geo g, int ndiag, int passes,
                                                              int sweeps, unsigned* bar, unsigned spin_limit) {
   __shared__ int stop;
@@ -663,7 +668,7 @@ __global__ __launch_bounds__(kThreads) void k_level_wave_seq(KProb p, WaveArgs a
     // anew on every anti-diagonal rather than hoisted out of the loop and held in registers
     int jj = j, tt = tile;
     asm volatile("" : "+s"(jj), "+s"(tt));
-    wave_pair<T, BC>(p, a, g, jj, tt, d, passes, sweeps);
+    wave_pair<T, BC, FORM>(p, a, g, jj, tt, d, passes, sweeps);
     if (d + 1 == ndiag) break;
     // every wave waits until its stores have reached the L2 (all counters to zero); then one
     // thread writes the XCD's L2 back (it holds the stores of all waves) and arrives
