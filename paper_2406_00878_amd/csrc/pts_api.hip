@@ -96,6 +96,7 @@ KProb kprob(const pts_problem* p) {
   k.bx = k.dt * k.cf * k.ihx;
   k.by = k.dt * k.cf * k.ihy;
   k.c0 = 1.0 + 2.0 * (k.ax + k.ay);
+  k.ic0 = 1.0 / k.c0;
   return k;
 }
 

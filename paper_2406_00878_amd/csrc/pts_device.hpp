@@ -24,7 +24,7 @@ struct KProb {
   // - vy (N - 2P + S); row of A: C = c0, W = -ax - bx u_W, E = -ax + bx u_E, S = -ay - by u_S,
   // N = -ay + by u_N (cx = cf / 2hx, vx = mu_a / hx^2, ax = tau vx, bx = tau cf / hx, c0 =
   // 1 + 2 (ax + ay))
-  double cx, cy, vx, vy, ax, ay, bx, by, c0;
+  double cx, cy, vx, vy, ax, ay, bx, by, c0, ic0;  // ic0 = 1 / c0
 };
 
 // Tiling of a level for the register-resident solve: a 64 x 64 region per work-group,
@@ -172,6 +172,12 @@ __device__ __forceinline__ double eval_point(const KProb& p, const Nb& u, int x,
 // Gershgorin radius of row r of D^{-1} A (infinite when the diagonal is not positive).
 __device__ __forceinline__ double gersh(const Row5& r) {
   double g = (fabs(r.W) + fabs(r.E) + fabs(r.S) + fabs(r.N)) / fabs(r.C);
+  if (!(r.C > 0.0) || g != g) g = __longlong_as_double(0x7ff0000000000000ll);
+  return g;
+}
+// The same with 1 / C known (the constant-viscosity form's diagonal is the constant c0).
+__device__ __forceinline__ double gersh(const Row5& r, double inv_c) {
+  double g = (fabs(r.W) + fabs(r.E) + fabs(r.S) + fabs(r.N)) * inv_c;
   if (!(r.C > 0.0) || g != g) g = __longlong_as_double(0x7ff0000000000000ll);
   return g;
 }

@@ -132,16 +132,27 @@ __device__ __forceinline__ YNb<T> y_exchange(const T (&v)[kRows], T* buf, int& p
 // (Golub-Varga semi-iteration): omega_1 = 1, omega_2 = 1/(1 - rho^2/2),
 // omega_{k+1} = 1/(1 - rho^2 omega_k / 4). One thread fills the table in LDS while the
 // other threads load the region.
+// Called by (at least) the first wave with the same rho in every lane: lane s writes
+// omega_s = 2 T_{s-1}(1/rho) / (rho T_s(1/rho)) (omega_1 = 1), the closed form of the
+// recurrence omega_{s+1} = 1 / (1 - rho^2 omega_s / 4), omega_2 = 2 / (2 - rho^2); each lane
+// runs the three-term recurrence of the Chebyshev polynomials T to its own s, so the
+// divisions are independent instead of a dependent chain. (rho >= 1e-3 keeps T_63(1/rho)
+// below 1e210.)
 __device__ __forceinline__ void cheb_table(double* om, double rho, int sweeps) {
-  if (threadIdx.x == 0) {
-    const double r2 = rho * rho;
-    double w = 1.0;
+  const int s = threadIdx.x;
+  if (s < 1 || s > sweeps || s >= kMaxSweeps) return;
+  if (s == 1) {
     om[1] = 1.0;
-    for (int s = 2; s <= sweeps && s < kMaxSweeps; ++s) {
-      w = s == 2 ? 1.0 / (1.0 - 0.5 * r2) : 1.0 / (1.0 - 0.25 * r2 * w);
-      om[s] = w;
-    }
+    return;
   }
+  const double x = 1.0 / rho;
+  double tp = 1.0, tc = x;  // T_{k-1}, T_k at k = 1
+  for (int k = 1; k < s; ++k) {
+    const double tn = 2.0 * x * tc - tp;
+    tp = tc;
+    tc = tn;
+  }
+  om[s] = 2.0 * tp / (rho * tc);
 }
 
 __device__ __forceinline__ double clamp_rho(double rho) { return fmin(fmax(rho, 1e-3), 0.999); }
@@ -155,8 +166,9 @@ struct RegionSolve {
   double bb[kRows], X[kRows];
   T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
 
-  __device__ __forceinline__ void set_row(int k, const Row5& a) {
-    const double inv = 1.0 / a.C;
+  __device__ __forceinline__ void set_row(int k, const Row5& a) { set_row(k, a, 1.0 / a.C); }
+  // inv = 1 / a.C given (known without a division for some forms)
+  __device__ __forceinline__ void set_row(int k, const Row5& a, double inv) {
     iC[k] = T(inv);
     sW[k] = T(a.W * inv);
     sE[k] = T(a.E * inv);
@@ -557,6 +569,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
     const bool act = region_node<BC>(p, gx, ry0 + wave * kRows + k, x, y);
     idx[k] = act ? (unsigned)y * (unsigned)p.nx + x : ~0u;
     Row5 r5;
+    double inv_c = 1.0;
     if (act) {
       const Nb u = gather<BC>(p, un, bd, x, y);
       const double F = eval_point<BC, FORM>(p, u, x, y, r5);
@@ -564,6 +577,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       rs.bb[k] = -(u.P - prev + p.dt * F);
       uc[k] = u.P;
       upn[k] = prev;
+      inv_c = FORM == kFormConstVisc ? p.ic0 : 1.0 / r5.C;
     } else {
       r5.C = 1.0;
       r5.W = r5.E = r5.S = r5.N = 0.0;
@@ -572,7 +586,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       upn[k] = 0.0;
     }
     rs.X[k] = 0.0;
-    rs.set_row(k, r5);
+    rs.set_row(k, r5, inv_c);
   }
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
@@ -617,7 +631,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       const double r = -(u.P - upn[k] + p.dt * F);
       // |r| and the radius are >= 0 or NaN with a clear sign bit (max_nn applies)
       rmax = max_nn(rmax, fabs(r));
-      gmax = max_nn(gmax, gersh(q));
+      gmax = max_nn(gmax, FORM == kFormConstVisc ? gersh(q, p.ic0) : gersh(q));
       st(Uo, idx[k], unew[k]);
     }
   }
