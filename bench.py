@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken with: sha256 of the device header and of
 # the parts of the kernel file the wavefront kernel is built from (the register-resident
 # region solve and the wavefront section).
-TRAFFIC = {"kernel_sha256": "fc1cbfec7ae70131a58699bc1a16f5b2e74f55e974daad8776aae1f33a7180c9",
-           "fetch_bytes": 26470303, "write_bytes": 6184489}
+TRAFFIC = {"kernel_sha256": "f4d31acf10b2bd0ba52e79ff7469631ef4db7c8d3bbc2168eb6dd4ed8e0db516",
+           "fetch_bytes": 17737806, "write_bytes": 3099024}
 KERNEL_HEADER = "paper_2406_00878_amd/csrc/pts_device.hpp"
 KERNEL_FILE = "paper_2406_00878_amd/csrc/pts_kernels.hip"
 KERNEL_SECTIONS = [("// -------------------------------------------------------------- level solve",
