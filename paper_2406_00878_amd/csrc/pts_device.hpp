@@ -223,10 +223,34 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ double max_nn(double a, double b) {
   return (unsigned long long)__double_as_longlong(a) > (unsigned long long)__double_as_longlong(b) ? a : b;
 }
-// max_nn over the lanes of each aligned group of `width` lanes (a power of two <= 64)
-__device__ __forceinline__ double group_max_nn(double v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v = max_nn(v, __shfl_xor(v, o, kWave));
+// A 64-bit value moved between lanes by one DPP control (applied to both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+  int2 q = __builtin_bit_cast(int2, v);
+  q.x = __builtin_amdgcn_mov_dpp(q.x, CTRL, 0xF, 0xF, false);
+  q.y = __builtin_amdgcn_mov_dpp(q.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, q);
+}
+// max_nn over each row of 16 lanes, left in every lane of the row: lane ^ 1 and lane ^ 2
+// (quad permutations), then the half-row mirror (i <-> 7 - i) joins the two quads of each
+// half row and the row mirror (i <-> 15 - i) the two halves. All in registers, no LDS.
+__device__ __forceinline__ double row_max_nn(double v) {
+  v = max_nn(v, dpp64<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = max_nn(v, dpp64<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = max_nn(v, dpp64<0x141>(v));  // row_half_mirror
+  v = max_nn(v, dpp64<0x140>(v));  // row_mirror
   return v;
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  int2 q = __builtin_bit_cast(int2, v);
+  q.x = __builtin_amdgcn_readlane(q.x, lane);
+  q.y = __builtin_amdgcn_readlane(q.y, lane);
+  return __builtin_bit_cast(double, q);
+}
+// max_nn over the whole wave, as a wave-uniform value (the four rows' maxima read back)
+__device__ __forceinline__ double wave_max_nn(double v) {
+  v = row_max_nn(v);
+  return max_nn(max_nn(lane_value(v, 0), lane_value(v, 16)), max_nn(lane_value(v, 32), lane_value(v, 48)));
 }
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

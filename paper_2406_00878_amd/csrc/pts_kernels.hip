@@ -554,7 +554,7 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
     } else {
       const double* rp = a.rho_part + ((size_t)j * 4 + (n & 3)) * a.tiles;
       for (int t = lane; t < a.tiles; t += 64) rho_j = max_nn(rho_j, rp[t]);
-      rho_j = group_max_nn(rho_j, 64);
+      rho_j = wave_max_nn(rho_j);
     }
     cheb_table(om, clamp_rho(rho_j), sweeps);
   }
@@ -635,16 +635,17 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       st(Uo, idx[k], unew[k]);
     }
   }
-  rmax = group_max_nn(rmax, 64);
-  gmax = group_max_nn(gmax, 64);
+  rmax = wave_max_nn(rmax);
+  gmax = wave_max_nn(gmax);
   if (lane == 0) {
     red[0][wave] = rmax;
     red[1][wave] = gmax;
   }
   __syncthreads();
-  if (wave == 0) {  // the kWaves wave maxima, folded across lanes
-    const double r = group_max_nn(lane < kWaves ? red[0][lane] : 0.0, kWaves);
-    const double q = group_max_nn(lane < kWaves ? red[1][lane] : 0.0, kWaves);
+  static_assert(kWaves == 16, "the fold of the wave maxima is one row of 16 lanes");
+  if (wave == 0) {  // the kWaves wave maxima, folded across the first row's lanes
+    const double r = lane_value(row_max_nn(lane < kWaves ? red[0][lane] : 0.0), 0);
+    const double q = lane_value(row_max_nn(lane < kWaves ? red[1][lane] : 0.0), 0);
     if (lane == 0) {
       double* rs = a.res_part + (size_t)(j + 1) * a.tiles + tile;
       *rs = max_nn(*rs, r);
