@@ -97,6 +97,11 @@ KProb kprob(const pts_problem* p) {
   k.by = k.dt * k.cf * k.ihy;
   k.c0 = 1.0 + 2.0 * (k.ax + k.ay);
   k.ic0 = 1.0 / k.c0;
+  k.vp = 2.0 * (k.vx + k.vy);
+  k.axs = k.ax * k.ic0;
+  k.ays = k.ay * k.ic0;
+  k.bxs = k.bx * k.ic0;
+  k.bys = k.by * k.ic0;
   return k;
 }
 

@@ -23,8 +23,9 @@ struct KProb {
   // constant-viscosity form: F = cx (E^2 - W^2) + cy (N^2 - S^2) - vx (E - 2P + W)
   // - vy (N - 2P + S); row of A: C = c0, W = -ax - bx u_W, E = -ax + bx u_E, S = -ay - by u_S,
   // N = -ay + by u_N (cx = cf / 2hx, vx = mu_a / hx^2, ax = tau vx, bx = tau cf / hx, c0 =
-  // 1 + 2 (ax + ay))
-  double cx, cy, vx, vy, ax, ay, bx, by, c0, ic0;  // ic0 = 1 / c0
+  // 1 + 2 (ax + ay), vp = 2 (vx + vy))
+  double cx, cy, vx, vy, ax, ay, bx, by, c0, ic0, vp;  // ic0 = 1 / c0
+  double axs, ays, bxs, bys;  // ax, ay, bx, by times 1 / c0: the rows of D^{-1} A
 };
 
 // Tiling of a level for the register-resident solve: a 64 x 64 region per work-group,
@@ -124,10 +125,11 @@ enum { kFormGeneral = 0, kFormConstVisc = 1, kFormNoConv = 2 };
 template <int BC, int FORM = kFormGeneral>
 __device__ __forceinline__ double eval_point(const KProb& p, const Nb& u, int x, int y, Row5& r) {
   if constexpr (FORM == kFormConstVisc) {
-    // the same discrete operator with the constant coefficients folded on the host
+    // the same discrete operator with the constant coefficients folded on the host, grouped
+    // as F = (E + W)(cx (E - W) - vx) + (N + S)(cy (N - S) - vy) + vp P (nine operations)
     const double sx = u.E + u.W, sy = u.N + u.S;
-    const double conv = p.cx * ((u.E - u.W) * sx) + p.cy * ((u.N - u.S) * sy);
-    const double visc = p.vx * fma(-2.0, u.P, sx) + p.vy * fma(-2.0, u.P, sy);
+    const double fx = sx * fma(p.cx, u.E - u.W, -p.vx);
+    const double F = fma(p.vp, u.P, fma(sy, fma(p.cy, u.N - u.S, -p.vy), fx));
     r.C = p.c0;
     r.W = fma(-p.bx, u.W, -p.ax);
     r.E = fma(p.bx, u.E, -p.ax);
@@ -139,7 +141,7 @@ __device__ __forceinline__ double eval_point(const KProb& p, const Nb& u, int x,
       if (y == 0) r.S = 0.0;
       if (y == p.ny - 1) r.N = 0.0;
     }
-    return conv - visc;
+    return F;
   }
   constexpr bool var_visc = FORM != kFormConstVisc, has_conv = FORM != kFormNoConv;
   const double me = var_visc ? mu_of(p, 0.5 * (u.P + u.E)) : p.mu_a;

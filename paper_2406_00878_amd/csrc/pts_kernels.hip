@@ -167,6 +167,23 @@ struct RegionSolve {
   T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
 
   __device__ __forceinline__ void set_row(int k, const Row5& a) { set_row(k, a, 1.0 / a.C); }
+  // The constant-viscosity form's Jacobi-scaled row straight from the host-folded coefficients
+  // (one fused multiply-add per entry, no scaling pass); a (unscaled) feeds the FP64 rows of
+  // the FP32 inner type.
+  __device__ __forceinline__ void set_row_const_visc(int k, const KProb& p, const Nb& u, const Row5& a) {
+    iC[k] = T(p.ic0);
+    sW[k] = T(fma(-p.bxs, u.W, -p.axs));
+    sE[k] = T(fma(p.bxs, u.E, -p.axs));
+    sS[k] = T(fma(-p.bys, u.S, -p.ays));
+    sN[k] = T(fma(p.bys, u.N, -p.ays));
+    if (!kF64) {
+      cC[k] = a.C;
+      cW[k] = a.W;
+      cE[k] = a.E;
+      cS[k] = a.S;
+      cN[k] = a.N;
+    }
+  }
   // inv = 1 / a.C given (known without a division for some forms)
   __device__ __forceinline__ void set_row(int k, const Row5& a, double inv) {
     iC[k] = T(inv);
@@ -569,7 +586,6 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
     const bool act = region_node<BC>(p, gx, ry0 + wave * kRows + k, x, y);
     idx[k] = act ? (unsigned)y * (unsigned)p.nx + x : ~0u;
     Row5 r5;
-    double inv_c = 1.0;
     if (act) {
       const Nb u = gather<BC>(p, un, bd, x, y);
       const double F = eval_point<BC, FORM>(p, u, x, y, r5);
@@ -577,16 +593,20 @@ __device__ __forceinline__ void wave_pair(const KProb& p, const WaveArgs& a, con
       rs.bb[k] = -(u.P - prev + p.dt * F);
       uc[k] = u.P;
       upn[k] = prev;
-      inv_c = FORM == kFormConstVisc ? p.ic0 : 1.0 / r5.C;
+      // (periodic only: Dirichlet boundary rows drop neighbours the folded form would keep)
+      if constexpr (BC == 1 && FORM == kFormConstVisc)
+        rs.set_row_const_visc(k, p, u, r5);
+      else
+        rs.set_row(k, r5, FORM == kFormConstVisc ? p.ic0 : 1.0 / r5.C);
     } else {
       r5.C = 1.0;
       r5.W = r5.E = r5.S = r5.N = 0.0;
       rs.bb[k] = 0.0;
       uc[k] = 0.0;
       upn[k] = 0.0;
+      rs.set_row(k, r5, 1.0);
     }
     rs.X[k] = 0.0;
-    rs.set_row(k, r5, inv_c);
   }
 #pragma unroll
   for (int k = 0; k < kRows; ++k) {
