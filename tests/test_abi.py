@@ -72,3 +72,20 @@ def test_neural_config_validation_on_host():
     assert lib.pts_no_workspace_bytes(ctypes.byref(c)) > 0
     bad = N.NOConfig(64, 64, 16, width=24).c()
     assert lib.pts_no_param_count(ctypes.byref(bad)) == 0
+
+
+def test_solver_option_validation_on_host():
+    """Out-of-range launch options are rejected before any device work (host-side checks)."""
+    import paper_2406_00878_amd as P
+    import workloads as W
+    p = P.make_problem(W.burgers_periodic(32, 4, 5e-4, 0.01, W.fourier_u0_periodic(32, 1)))
+    lib = P._lib.load()
+    opts = P._options()
+    opts.wave_launch = 2
+    rc = lib.pts_solve(ctypes.byref(p), None, None, 1e-12, 10, None, 0, ctypes.byref(opts), None, None)
+    assert rc == P._lib.PTS_ERR_INVALID_ARG and b"wave_launch" in lib.pts_last_error()
+    opts = P._options(barrier_spins=-1)
+    rc = lib.pts_solve(ctypes.byref(p), None, None, 1e-12, 10, None, 0, ctypes.byref(opts), None, None)
+    assert rc == P._lib.PTS_ERR_INVALID_ARG and b"negative" in lib.pts_last_error()
+    with pytest.raises(KeyError):
+        P._options(wave_launch="persistent")
