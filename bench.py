@@ -29,14 +29,16 @@ sys.path.insert(0, ROOT)
 METRIC = "converged space-time DOF/s at 1e-8 rel. err vs FP64 oracle; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per k_level_wave launch of the default workload and plan, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs (profiles/k_level_wave_burgers256x512_fp64_hbm_counters.md),
+# HBM bytes per k_level_wave launch of the default workload, per inner plan (sweeps, passes,
+# Newton stages per sequence: the plans the autotuner picks on this workload), from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE runs (profiles/k_level_wave_burgers256x512_fp64_hbm_counters.md),
 # each scaled by the counter's reading for a 1 GiB fill / 1 GiB sum (--hbm-calibration).
 # Valid only for the kernel source they were taken with: sha256 of the device header and of
 # the parts of the kernel file the wavefront kernel is built from (the register-resident
 # region solve and the wavefront section).
-TRAFFIC = {"kernel_sha256": "091ad5c328c5887c2e6ec150ddb4e7d3f7ca77341c150ed41f6e1bd06da26961",
-           "fetch_bytes": 17728675, "write_bytes": 3099024}
+TRAFFIC = {"kernel_sha256": "1b89303ef642adbcae53319ac6b2720e3e5c82b139d2c085a01e03064aa359d1",
+           "plans": {(8, 1, 6): {"fetch_bytes": 17717276, "write_bytes": 3099024},
+                     (7, 1, 7): {"fetch_bytes": 19726926, "write_bytes": 3769821}}}
 KERNEL_HEADER = "paper_2406_00878_amd/csrc/pts_device.hpp"
 KERNEL_FILE = "paper_2406_00878_amd/csrc/pts_kernels.hip"
 KERNEL_SECTIONS = [("// -------------------------------------------------------------- level solve",
@@ -57,12 +59,14 @@ def kernel_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Counter-measured HBM bytes per launch of the default workload's k_level_wave, or None
-    when the kernel sources differ from the ones the counters were taken with."""
-    if TRAFFIC["kernel_sha256"] is None or TRAFFIC["kernel_sha256"] != kernel_sha256():
+def measured_traffic(plan):
+    """Counter-measured HBM bytes per launch of the default workload's k_level_wave for the
+    timed plan (sweeps, passes, stages), or None when the counters were not taken for that plan
+    or the kernel sources differ from the ones they were taken with."""
+    if TRAFFIC["kernel_sha256"] != kernel_sha256() or plan not in TRAFFIC["plans"]:
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    t = TRAFFIC["plans"][plan]
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def hbm_calibration():
@@ -400,6 +404,10 @@ def main():
     bytes_per_launch = pst["level_solve_bytes"] / n_ls
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kname = "k_level_wave" if st["schedule"] == 2 else "k_level_solve"
+    # Newton stages of the profiled wavefront solve when it was one sequence of N_t + 2(K-1)
+    # launches (the stage count of the counter runs)
+    stages = (n_ls - prob.nt) // 2 + 1 if (kname == "k_level_wave" and n_ls >= prob.nt
+                                           and (n_ls - prob.nt) % 2 == 0) else None
     print(f"[bench] {kname}: {n_ls} launches, avg {avg_ms * 1e3:.2f} us, "
           f"{bytes_per_launch / 1e6:.2f} MB/launch; kernel split ms {pst['prof_ms']}",
           file=sys.stderr, flush=True)
@@ -424,8 +432,8 @@ def main():
                    "autotuned": tuned is not None, **extra},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (args.workload == "burgers256" and args.precision == "fp64")
-                     else None,
+                     "traffic": measured_traffic((st["sweeps"], st["refine"] + 1, stages))
+                     if (args.workload == "burgers256" and args.precision == "fp64" and stages) else None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_cpu_baseline:
