@@ -251,6 +251,24 @@ Plan make_plan(const pts_problem* p, const pts_options* o, double rho_max, const
 }
 
 
+// Flux form of a problem (see eval_point): constant viscosity, no convection, or general.
+int flux_form(const pts_problem* p) {
+  if (p->mu_b == 0.0) return kFormConstVisc;
+  if (p->kind == PTS_HEAT) return kFormNoConv;
+  return kFormGeneral;
+}
+
+// The all-level residual kernel for a problem's boundary kind and flux form.
+typedef void (*ResidualKernel)(KProb, const double*, const double*, double*, double*, unsigned long long*);
+ResidualKernel residual_kernel(const pts_problem* p) {
+  const bool per = p->bc == PTS_PERIODIC;
+  switch (flux_form(p)) {
+    case kFormConstVisc: return per ? k_residual<1, kFormConstVisc> : k_residual<0, kFormConstVisc>;
+    case kFormNoConv: return per ? k_residual<1, kFormNoConv> : k_residual<0, kFormNoConv>;
+    default: return per ? k_residual<1, kFormGeneral> : k_residual<0, kFormGeneral>;
+  }
+}
+
 // lvl_bits: 2 words per level (max |r|, max radius), zeroed here; scal (nullable)
 // receives the maxima over levels.
 int launch_residual(const pts_problem* p, const KProb& kp, const double* U, const double* u0, double* R,
@@ -258,10 +276,7 @@ int launch_residual(const pts_problem* p, const KProb& kp, const double* U, cons
   const int tilesx = (p->nx + 63) / 64, tilesy = (p->ny + kResRows - 1) / kResRows;
   if (lvl_bits) hipLaunchKernelGGL(k_zero, dim3((2 * p->nt + 255) / 256), dim3(256), 0, s, lvl_bits, 2 * p->nt);
   dim3 grid((unsigned)(tilesx * tilesy), (unsigned)p->nt);
-  if (p->bc == PTS_PERIODIC)
-    hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
-  else
-    hipLaunchKernelGGL(k_residual<0>, grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
+  hipLaunchKernelGGL(residual_kernel(p), grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
   if (scal) hipLaunchKernelGGL(k_level_max, dim3(1), dim3(256), 0, s, lvl_bits, p->nt, scal);
   HIPCHK(hipGetLastError());
   return PTS_OK;
@@ -734,12 +749,6 @@ struct WaveGraph {
 };
 thread_local std::vector<WaveGraph> g_wave_graphs;
 
-// Flux form of a problem (see eval_point): constant viscosity, no convection, or general.
-int flux_form(const pts_problem* p) {
-  if (p->mu_b == 0.0) return kFormConstVisc;
-  if (p->kind == PTS_HEAT) return kFormNoConv;
-  return kFormGeneral;
-}
 
 // The wavefront kernel for a problem (inner type, boundary kind, flux form): one launch per
 // anti-diagonal, or with seq the cooperative whole-sequence form.
@@ -1732,10 +1741,7 @@ int pts_assemble(const pts_problem* p, const double* U, const double* u0, double
   KProb kp = kprob(p);
   const int tilesx = (p->nx + 63) / 64, tilesy = (p->ny + kResRows - 1) / kResRows;
   dim3 grid((unsigned)(tilesx * tilesy), (unsigned)p->nt);
-  if (p->bc == PTS_PERIODIC)
-    hipLaunchKernelGGL(k_residual<1>, grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
-  else
-    hipLaunchKernelGGL(k_residual<0>, grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
+  hipLaunchKernelGGL(residual_kernel(p), grid, dim3(256), 0, s, kp, U, u0, R, coef, nullptr);
   HIPCHK(hipGetLastError());
   if (res_inf) {
     hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, R, (size_t)p->nx * p->ny * p->nt,

@@ -26,7 +26,7 @@ namespace pts {
 // R and coef may be NULL.
 constexpr int kResRows = 16;
 
-template <int BC>
+template <int BC, int FORM>
 __global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restrict__ U,
                                                   const double* __restrict__ u0,
                                                   double* __restrict__ R, double* __restrict__ coef,
@@ -46,11 +46,11 @@ __global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restr
       const Nb u = gather<BC>(p, un, bd, x, y);
       const size_t i = (size_t)y * p.nx + x;
       Row5 a;
-      const double F = eval_point<BC>(p, u, x, y, a);
+      const double F = eval_point<BC, FORM>(p, u, x, y, a);
       const double r = -(u.P - up[i] + p.dt * F);
       if (R) R[(size_t)n * ns + i] = r;
       rabs = nanmax(rabs, fabs(r));
-      rho = nanmax(rho, gersh(a));
+      rho = nanmax(rho, (FORM == kFormConstVisc ? gersh(a, p.ic0) : gersh(a)));
       if (coef) {
         double* c = coef + (size_t)n * 5 * ns + i;
         c[0] = a.C;
