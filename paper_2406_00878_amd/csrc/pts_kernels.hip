@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ d
     const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
     const Nb u = gather<0>(p, d->U + lev, bd, x, y);
     Row5 a;
-    (void)eval_point<0>(p, u, x, y, a);
+    (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // spectral solves are for heat only (no convection)
     double ax = a.C * X[i];
     if (x > 0) ax += a.W * X[i - 1];
     if (x < p.nx - 1) ax += a.E * X[i + 1];
