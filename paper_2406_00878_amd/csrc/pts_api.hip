@@ -1297,7 +1297,7 @@ DstLayout dst_layout(const pts_problem* probs, int nprob) {
   }
   L.desc = take((size_t)nprob * sizeof(DstDesc));
   L.gemm = take((size_t)4 * nprob * sizeof(pts_mm::Gemm));
-  L.items_g = take(L.ng * sizeof(int4));
+  L.items_g = take((size_t)nprob * L.ng * sizeof(int4));  // one list per prefix of the instances
   L.items_e = take(L.ne * sizeof(int2));
   for (int i = 0; i < nprob; ++i) {
     const size_t N = probs[i].nx, nn = N * N, nl = N * dst_ld(probs[i].nx);
@@ -1401,7 +1401,8 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   const size_t s_desc = stake((size_t)nprob * sizeof(BatchDesc)), s_items = stake(tiles_total * sizeof(int2));
   const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(DstDesc) : 0);
   const size_t s_gm = stake(eligible ? (size_t)4 * nprob * sizeof(pts_mm::Gemm) : 0);
-  const size_t s_ig = stake(eligible ? DL.ng * sizeof(int4) : 0), s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  const size_t s_ig = stake(eligible ? (size_t)nprob * DL.ng * sizeof(int4) : 0);
+  const size_t s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
   size_t sum_nt = 0;
   for (int i = 0; i < nprob; ++i) sum_nt += probs[i].nt;
   const size_t s_kt = stake(eligible ? sum_nt * 4 : 0);
@@ -1570,7 +1571,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       // inexact Newton: each level solve reduces its residual 1e3-fold by default (measured on
       // the heat batch: one Newton step more than at 1e-6, 30 % less time, same converged result)
       const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
-      std::vector<size_t> cg(order.size() + 1, 0), ce(order.size() + 1, 0);
+      std::vector<size_t> cg(order.size() + 1, 0), og(order.size() + 1, 0), ce(order.size() + 1, 0);
       size_t ng = 0, ne = 0;
       for (int i = 0; i < nprob; ++i) {
         DstDesc& d = h_dd[i];
@@ -1609,14 +1610,25 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           stats[i].refine = 0;
         }
       }
+      // node items: the instances that have level n are a prefix of `order`
       for (size_t q = 0; q < order.size(); ++q) {
         const int i = order[q];
-        const int N = probs[i].nx, t = (N + pts_mm::BM - 1) / pts_mm::BM, ch = (N * N + 255) / 256;
-        for (int a = 0; a < t; ++a)
-          for (int b = 0; b < t; ++b) h_ig[ng++] = make_int4(i, a, b, 0);
+        const int N = probs[i].nx, ch = (N * N + 255) / 256;
         for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(i, c);
-        cg[q + 1] = ng;
         ce[q + 1] = ne;
+      }
+      // product items: one list per prefix, its instances' tiles by grid size, largest first, so
+      // the longest chains of dependent K steps are dispatched in the first round of a launch
+      for (size_t k = 1; k <= order.size(); ++k) {
+        std::vector<int> inst(order.begin(), order.begin() + k);
+        std::stable_sort(inst.begin(), inst.end(), [&](int a, int b) { return probs[a].nx > probs[b].nx; });
+        og[k] = ng;
+        for (int i : inst) {
+          const int t = (probs[i].nx + pts_mm::BM - 1) / pts_mm::BM;
+          for (int a = 0; a < t; ++a)
+            for (int b = 0; b < t; ++b) h_ig[ng++] = make_int4(i, a, b, 0);
+        }
+        cg[k] = ng - og[k];
       }
       HIPCHK(hipMemcpyAsync(dst_base + DL.desc, h_dd, (size_t)nprob * sizeof(DstDesc), hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(dst_base + DL.items_g, h_ig, ng * sizeof(int4), hipMemcpyHostToDevice, s));
@@ -1633,7 +1645,8 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         for (int kk = 0; kk < kn; ++kk) {
           hipLaunchKernelGGL(k_dst_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
           for (int stg = 0; stg < 4; ++stg)
-            hipLaunchKernelGGL(k_dst_gemm, dim3((unsigned)cg[k]), dim3(256), 0, s, gm, dd, ig, nprob, stg, n, kk);
+            hipLaunchKernelGGL(k_dst_gemm, dim3((unsigned)cg[k]), dim3(256), 0, s, gm, dd, ig + og[k], nprob, stg,
+                               n, kk);
           hipLaunchKernelGGL(k_dst_update, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
           launches += 6;
         }

@@ -503,8 +503,8 @@ __global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ 
 }
 
 // One 64 x 64 tile of the product of group it.x (instance) in stage `stage`'s descriptors;
-// items (instance, tile row, tile column), sorted by level count. Groups whose instance has
-// no level n or no iteration k return.
+// items (instance, tile row, tile column) of the instances that have level n, largest grids
+// first. Groups whose instance has no level n or no iteration k return.
 __global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict__ gs, const DstDesc* __restrict__ ds,
                                                   const int4* __restrict__ items, int nprob, int stage, int n, int k) {
   const int4 it = items[blockIdx.x];
