@@ -147,8 +147,10 @@ __device__ __forceinline__ void mm_tile(const Gemm& g, int m0, int n0, int b, in
 // and the lam scaling.
 __device__ __forceinline__ void mm_tile_vec(const Gemm& g, int m0, int n0) {
   constexpr int BKV = 64;
+  // A tile row-major (k contiguous); B tile transposed (k contiguous per column), so both MFMA
+  // fragments (four consecutive k) are single 8-byte LDS reads
   __shared__ unsigned short As[BM][BKV + 4];
-  __shared__ unsigned short Bs[BKV][BN + 4];
+  __shared__ unsigned short Bt[BN][BKV + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   float4_t acc[2][2];
   for (int i = 0; i < 2; ++i)
@@ -175,15 +177,15 @@ __device__ __forceinline__ void mm_tile_vec(const Gemm& g, int m0, int n0) {
     for (int r = 0; r < 4; ++r) {
       const int e = tid + r * 256;
       const int am = e >> 4, ak = (e & 15) * 4;
-      As[am][ak] = f2bf(ra[r].x);
-      As[am][ak + 1] = f2bf(ra[r].y);
-      As[am][ak + 2] = f2bf(ra[r].z);
-      As[am][ak + 3] = f2bf(ra[r].w);
+      uint2 pk;  // four consecutive k of row am, one 8-byte store
+      pk.x = (unsigned)f2bf(ra[r].x) | ((unsigned)f2bf(ra[r].y) << 16);
+      pk.y = (unsigned)f2bf(ra[r].z) | ((unsigned)f2bf(ra[r].w) << 16);
+      *reinterpret_cast<uint2*>(&As[am][ak]) = pk;
       const int bk = e >> 4, bn = (e & 15) * 4;
-      Bs[bk][bn] = f2bf(rb[r].x);
-      Bs[bk][bn + 1] = f2bf(rb[r].y);
-      Bs[bk][bn + 2] = f2bf(rb[r].z);
-      Bs[bk][bn + 3] = f2bf(rb[r].w);
+      Bt[bn][bk] = f2bf(rb[r].x);
+      Bt[bn + 1][bk] = f2bf(rb[r].y);
+      Bt[bn + 2][bk] = f2bf(rb[r].z);
+      Bt[bn + 3][bk] = f2bf(rb[r].w);
     }
     __syncthreads();
     if (k0 + BKV < g.K) load(k0 + BKV);
@@ -193,19 +195,11 @@ __device__ __forceinline__ void mm_tile_vec(const Gemm& g, int m0, int n0) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm + 16 * i + (lane & 15);
-        short4_t a;
-        a[0] = (short)As[row][kq];
-        a[1] = (short)As[row][kq + 1];
-        a[2] = (short)As[row][kq + 2];
-        a[3] = (short)As[row][kq + 3];
+        const short4_t a = *reinterpret_cast<const short4_t*>(&As[row][kq]);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           const int col = wn + 16 * j + (lane & 15);
-          short4_t bb;
-          bb[0] = (short)Bs[kq][col];
-          bb[1] = (short)Bs[kq + 1][col];
-          bb[2] = (short)Bs[kq + 2][col];
-          bb[3] = (short)Bs[kq + 3][col];
+          const short4_t bb = *reinterpret_cast<const short4_t*>(&Bt[col][kq]);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
         }
       }
