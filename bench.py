@@ -123,6 +123,50 @@ def cpu_baseline(prob, budget_s, U_gpu):
     }, err, levels
 
 
+_BATCH = None  # the heat batch's problems, inherited by the forked CPU-baseline workers
+
+
+def _oracle_prefix(job):
+    """CPU-baseline worker: the oracle time-steps instance i of the batch, one thread, until
+    budget_s is spent (stopping after the level that exhausts it); returns (DOF solved, s)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import sequential
+    i, budget_s = job
+    prob = _BATCH[i]
+    with threadpool_limits(limits=1):
+        u = np.array(prob.u0, dtype=np.float64)
+        t0 = time.perf_counter()
+        levels = 0
+        for n in range(1, prob.nt + 1):
+            u, _, _ = sequential.bdf1_step(u, prob, n)
+            levels += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+    return levels * prob.ns, time.perf_counter() - t0
+
+
+def cpu_baseline_batch(probs, budget_s, max_cores=16):
+    """The oracle on the host's cores for the batch: one single-threaded worker per core, each
+    time-stepping the first levels of one instance (the batch's first instances, one round) for
+    about budget_s (a worker stops after the level that exhausts it, and single levels of the
+    largest grids take seconds); DOF/s = the sum of the workers' rates, each over its own busy
+    time. Runs before the GPU is touched (the workers are forked)."""
+    import multiprocessing as mp
+    global _BATCH
+    _BATCH = probs
+    cores = max(1, min(len(os.sched_getaffinity(0)), max_cores, len(probs)))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_prefix, [(i, budget_s) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    dof = sum(r[0] for r in res)
+    return {"value": sum(d / t for d, t in res), "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"instances 0..{cores - 1} of the batch, first levels of each for {budget_s:.0f} s "
+                      f"({dof} DOF in {wall:.1f} s wall), numpy/scipy, one thread per process"}
+
+
 def bench_learned(args):
     """Learned initial iterate vs the plain one on the nu = 0.005 Burgers workload."""
     import numpy as np
@@ -265,6 +309,10 @@ def bench_heatbatch(args):
     log = lambda m: print(f"[bench-heatbatch] {m}", file=sys.stderr, flush=True)
     probs = W.heat_batch()[:args.instances]
     dof = sum(p.dof for p in probs)
+    cb = None
+    if not args.no_cpu_baseline:  # before the GPU is initialised: the pool forks this process
+        cb = cpu_baseline_batch(probs, args.cpu_seconds)
+        log(f"cpu baseline: {cb['value']:.3g} DOF/s on {cb['cores']} cores")
     dev = torch.device("cuda:0")
     Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
     u0s = [torch.as_tensor(p.u0, dtype=torch.float64, device=dev).contiguous() for p in probs]
@@ -305,6 +353,8 @@ def bench_heatbatch(args):
                    "inner_passes_max": max(st["refine"] + 1 for st in sts)},
         "rel_err_vs_oracle": {"value": err, "instance": i, "levels_checked": levels},
     }
+    if cb is not None:
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
