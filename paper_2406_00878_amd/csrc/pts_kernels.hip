@@ -157,14 +157,15 @@ __device__ __forceinline__ void cheb_table(double* om, double rho, int sweeps) {
 
 __device__ __forceinline__ double clamp_rho(double rho) { return fmin(fmax(rho, 1e-3), 0.999); }
 
-// Register-resident state of one region of a level: Jacobi-scaled rows of A_n (T), the
+// Register-resident state of one region of a level: Jacobi-scaled rows of A_n (T; the
+// off-diagonals stored negated, so a sweep is a chain of fused multiply-adds from d), the
 // FP64 rows (only for FP32 inner arithmetic), right-hand side b and iterate X.
 template <typename T>
 struct RegionSolve {
   static constexpr bool kF64 = sizeof(T) == sizeof(double);
   double cC[kRows], cW[kRows], cE[kRows], cS[kRows], cN[kRows];
   double bb[kRows], X[kRows];
-  T sW[kRows], sE[kRows], sS[kRows], sN[kRows], iC[kRows];
+  T nW[kRows], nE[kRows], nS[kRows], nN[kRows], iC[kRows];  // -W/C, -E/C, -S/C, -N/C and 1/C
 
   __device__ __forceinline__ void set_row(int k, const Row5& a) { set_row(k, a, 1.0 / a.C); }
   // The constant-viscosity form's Jacobi-scaled row straight from the host-folded coefficients
@@ -172,10 +173,10 @@ struct RegionSolve {
   // the FP32 inner type.
   __device__ __forceinline__ void set_row_const_visc(int k, const KProb& p, const Nb& u, const Row5& a) {
     iC[k] = T(p.ic0);
-    sW[k] = T(fma(-p.bxs, u.W, -p.axs));
-    sE[k] = T(fma(p.bxs, u.E, -p.axs));
-    sS[k] = T(fma(-p.bys, u.S, -p.ays));
-    sN[k] = T(fma(p.bys, u.N, -p.ays));
+    nW[k] = T(fma(p.bxs, u.W, p.axs));
+    nE[k] = T(fma(-p.bxs, u.E, p.axs));
+    nS[k] = T(fma(p.bys, u.S, p.ays));
+    nN[k] = T(fma(-p.bys, u.N, p.ays));
     if (!kF64) {
       cC[k] = a.C;
       cW[k] = a.W;
@@ -187,10 +188,10 @@ struct RegionSolve {
   // inv = 1 / a.C given (known without a division for some forms)
   __device__ __forceinline__ void set_row(int k, const Row5& a, double inv) {
     iC[k] = T(inv);
-    sW[k] = T(a.W * inv);
-    sE[k] = T(a.E * inv);
-    sS[k] = T(a.S * inv);
-    sN[k] = T(a.N * inv);
+    nW[k] = T(-a.W * inv);
+    nE[k] = T(-a.E * inv);
+    nS[k] = T(-a.S * inv);
+    nN[k] = T(-a.N * inv);
     if (!kF64) {
       cC[k] = a.C;
       cW[k] = a.W;
@@ -217,8 +218,11 @@ struct RegionSolve {
           const double xw = lane_from_left(X[k]);
           const double xe = lane_from_right(X[k]);
           if (kF64) {
-            d[k] = T(double(iC[k]) * bb[k] -
-                     (X[k] + double(sW[k]) * xw + double(sE[k]) * xe + double(sS[k]) * xs + double(sN[k]) * xn));
+            double t = fma(double(iC[k]), bb[k], -X[k]);
+            t = fma(double(nW[k]), xw, t);
+            t = fma(double(nE[k]), xe, t);
+            t = fma(double(nS[k]), xs, t);
+            d[k] = T(fma(double(nN[k]), xn, t));
           } else {
             const double ax = cC[k] * X[k] + cW[k] * xw + cE[k] * xe + cS[k] * xs + cN[k] * xn;
             d[k] = T((bb[k] - ax) / cC[k]);
@@ -250,7 +254,7 @@ struct RegionSolve {
     }
   }
 
-  // xold <- xold + w (d - xold - offdiag(xcur)): one Chebyshev step written over x_{s-2}.
+  // xold <- xold + w (d - offdiag(xcur) - xold): one Chebyshev step written over x_{s-2}.
   __device__ __forceinline__ void sweep(T (&xold)[kRows], const T (&xcur)[kRows], const T (&d)[kRows], T w,
                                         T* ldst, int& par, int wave, int lane) {
     const YNb<T> yn = y_exchange<T>(xcur, ldst, par, wave, lane);
@@ -260,8 +264,11 @@ struct RegionSolve {
       const T xn = k == kRows - 1 ? yn.nM : xcur[k + 1];
       const T xw = lane_from_left(xcur[k]);
       const T xe = lane_from_right(xcur[k]);
-      const T off = sW[k] * xw + sE[k] * xe + sS[k] * xs + sN[k] * xn;
-      xold[k] = xold[k] + w * (d[k] - xold[k] - off);
+      T t = fma(nW[k], xw, d[k]);
+      t = fma(nE[k], xe, t);
+      t = fma(nS[k], xs, t);
+      t = fma(nN[k], xn, t);  // d - offdiag(xcur)
+      xold[k] = fma(w, t - xold[k], xold[k]);
     }
   }
 };
