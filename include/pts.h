@@ -189,23 +189,35 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
                  void* workspace, size_t workspace_bytes, const pts_options* opts,
                  pts_stats* stats, pts_stream_t stream);
 
-/* Independent instances (Theorem 1 per instance; sizes, level counts and inner
-   plans may differ) solved together: every Newton step runs the level solves of
-   all instances that have level n in shared launches (bulk schedule, work items
-   sorted by level count, per-instance descriptors in the workspace header).
+/* Independent instances (Theorem 1 per instance) solved together.
+   Instances of one problem (equal kind, bc, sizes, spacings, dt, mu_a, mu_b,
+   precision and bdata pointer; only u0 and the starting iterate differ) run
+   batched wavefront sequences unless opts asks for the bulk schedule, windows,
+   profiling or the cooperative launch: each anti-diagonal of a sequence is one
+   launch over (stages x tiles, instances), all instances run the same stage
+   count, and an instance leaves the batch when max|R| <= tol (stats report
+   schedule PTS_SCHED_PIPELINE). An instance whose Newton iteration turns
+   non-finite or loses diagonal dominance is then solved alone as pts_solve does
+   (slabs from the plain iterate). If the inner solve does not fit the wavefront
+   kernel the batch takes the bulk schedule (PIPELINE asked: PTS_ERR_INVALID_ARG).
+   Otherwise (sizes, level counts and inner plans may differ) every Newton step
+   runs the level solves of all instances that have level n in shared launches
+   (bulk schedule, work items sorted by level count, per-instance descriptors in
+   the workspace header).
    Batches of Dirichlet heat on square grids with h_x = h_y and mu_a > 0 whose
    blocks are stiff (Jacobi Gershgorin radius >= 0.97) solve each level with
    Chebyshev iteration preconditioned by I + tau mu_a (-Delta_h), applied
    through the DST-I (dense MFMA products; inexact, residual reduced 1e3-fold per
    level solve unless opts->lin_tol says otherwise). Instances with different
-   boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE or
-   opts->window > 1 are solved one after another with pts_solve.
+   boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for
+   instances that are not one problem) or opts->window > 1 are solved one after
+   another with pts_solve.
    U[i], u0[i] are device pointers; workspace is one 256-byte aligned block of
    pts_workspace_bytes_batched bytes; stats is a host array of nprob entries
    (may be NULL). Every instance is attempted; the return code is the first
    error met (pts_last_error names the instance), converged instances hold their
    solutions, failed ones their last iterate. Synchronises the stream once per
-   Newton step. */
+   Newton step (bulk) or per wavefront sequence (batched wavefront). */
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob);
 int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U,
                       const double* const* u0, double tol, int max_iter, void* workspace,

@@ -227,7 +227,10 @@ def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision
     rc = lib.pts_solve_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws), nbytes, C.byref(o),
                                sts, _stream(stream))
     _check(rc)
-    return [_stats_dict(s) for s in sts]
+    out = [_stats_dict(s) for s in sts]
+    for d in out:  # Newton steps after which |R| <= tol was first reached
+        d["needed"] = next((k for k, r in enumerate(d["res_inf"]) if r <= tol), None)
+    return out
 
 
 def window_bound(h, mu, tau=0.0, c=1.0, eps=1e-16, wmax=100000) -> int:

@@ -771,6 +771,21 @@ const void* wave_kernel(const pts_problem* p, bool fp32, bool seq) {
               : (per ? wave_kernel_bc<double, 1>(f, seq) : wave_kernel_bc<double, 0>(f, seq));
 }
 
+// The batched wavefront kernel (instances of one problem in each launch).
+typedef void (*WaveBatchKernel)(KProb, const WaveArgs*, Geo, int, int, int);
+template <typename T, int BC>
+WaveBatchKernel wave_batch_kernel_bc(int form) {
+  return form == kFormConstVisc ? k_level_wave_batch<T, BC, kFormConstVisc>
+         : form == kFormNoConv  ? k_level_wave_batch<T, BC, kFormNoConv>
+                                : k_level_wave_batch<T, BC, kFormGeneral>;
+}
+WaveBatchKernel wave_batch_kernel(const pts_problem* p, bool fp32) {
+  const bool per = p->bc == PTS_PERIODIC;
+  const int f = flux_form(p);
+  return fp32 ? (per ? wave_batch_kernel_bc<float, 1>(f) : wave_batch_kernel_bc<float, 0>(f))
+              : (per ? wave_batch_kernel_bc<double, 1>(f) : wave_batch_kernel_bc<double, 0>(f));
+}
+
 // algorithmic bytes of anti-diagonal d: per active (stage, level) pair, U_j^n and
 // U_{j+1}^{n-1} read, U_{j+1}^n written
 double wave_bytes(const pts_problem* p, int stages, int d) {
@@ -847,21 +862,10 @@ int launch_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& 
   return PTS_OK;
 }
 
-int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
-                      hipStream_t s, bool use_graph, Prof* pr, int* launches) {
-  if (!use_graph || pr) return launch_wave_sequence(p, kp, wa, g, pl, s, pr, launches);
-  // graphs are keyed on every launch argument; the solver passes u^0 through a workspace
-  // copy, so for a given workspace they differ only with the caller's U
-  std::vector<char> key(sizeof(KProb) + sizeof(WaveArgs) + sizeof(Geo) + 3 * sizeof(int));
-  char* k = key.data();
-  std::memcpy(k, &kp, sizeof kp);
-  k += sizeof kp;
-  std::memcpy(k, &wa, sizeof wa);
-  k += sizeof wa;
-  std::memcpy(k, &g, sizeof g);
-  k += sizeof g;
-  const int extra[3] = {pl.passes, pl.sweeps, pl.fp32 ? 1 : 0};
-  std::memcpy(k, extra, sizeof extra);
+// Replays the cached graph whose key matches, else captures `launch(stream)` into a new
+// graph (on a capture stream of this thread) and replays that.
+template <typename F>
+int replay_or_capture(const std::vector<char>& key, hipStream_t s, int* launches, F&& launch) {
   for (auto& wg : g_wave_graphs) {
     if (wg.key == key) {
       HIPCHK(hipGraphLaunch(wg.exec, s));
@@ -873,8 +877,7 @@ int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa,
   if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t graph;
   HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  int dummy = 0;
-  int rc = launch_wave_sequence(p, kp, wa, g, pl, cap, nullptr, &dummy);
+  int rc = launch(cap);
   hipError_t e = hipStreamEndCapture(cap, &graph);
   if (rc) return rc;
   if (e != hipSuccess) return fail(PTS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -891,6 +894,26 @@ int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa,
   HIPCHK(hipGraphLaunch(wg.exec, s));
   ++*launches;
   return PTS_OK;
+}
+
+// Appends the bytes of each value to a graph key.
+template <typename... A>
+void key_append(std::vector<char>& key, const A&... vals) {
+  (key.insert(key.end(), (const char*)&vals, (const char*)&vals + sizeof(vals)), ...);
+}
+
+int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa, const Geo& g, const Plan& pl,
+                      hipStream_t s, bool use_graph, Prof* pr, int* launches) {
+  if (!use_graph || pr) return launch_wave_sequence(p, kp, wa, g, pl, s, pr, launches);
+  // graphs are keyed on every launch argument; the solver passes u^0 through a workspace
+  // copy, so for a given workspace they differ only with the caller's U
+  std::vector<char> key;
+  const int extra[4] = {0, pl.passes, pl.sweeps, pl.fp32 ? 1 : 0};  // extra[0]: one instance
+  key_append(key, kp, wa, g, extra);
+  return replay_or_capture(key, s, launches, [&](hipStream_t cs) -> int {
+    int dummy = 0;
+    return launch_wave_sequence(p, kp, wa, g, pl, cs, nullptr, &dummy);
+  });
 }
 
 // Newton iterations overlapped in wavefront sequences of K stages each. Returns
@@ -1706,6 +1729,235 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   return worst;
 }
 
+// ---------------------------------------------------------------- batched wavefront
+// Whether the instances are one problem with different initial conditions: same sizes,
+// coefficients, precision and boundary data.
+bool same_problem(const pts_problem* probs, int nprob) {
+  const pts_problem& a = probs[0];
+  for (int i = 1; i < nprob; ++i) {
+    const pts_problem& b = probs[i];
+    if (a.kind != b.kind || a.bc != b.bc || a.nx != b.nx || a.ny != b.ny || a.nt != b.nt ||
+        a.precision != b.precision || a.hx != b.hx || a.hy != b.hy || a.dt != b.dt || a.mu_a != b.mu_a ||
+        a.mu_b != b.mu_b || a.bdata != b.bdata)
+      return false;
+  }
+  return true;
+}
+
+// Wavefront sequences over every instance at once: each anti-diagonal is one launch of
+// grid (K stages x tiles, active instances), the per-instance arguments in the batch
+// header. All instances run the same K per sequence (the plan follows the largest radius
+// of the active instances); an instance leaves the batch once its residual meets tol.
+// Returns PTS_ERR_INVALID_ARG with *fallback = true, before anything is written, when the
+// inner solve does not fit the wavefront kernel.
+int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
+                       int max_iter, char* header, char* wsb, const pts_options* o, pts_stats* stats,
+                       hipStream_t s, bool* fallback, int* codes) {
+  *fallback = false;
+  const pts_problem* p = probs;
+  for (int i = 0; i < nprob; ++i) codes[i] = PTS_OK;
+  const bool use_graph = !o || o->use_graph != 0;
+  const size_t ns = (size_t)p->nx * p->ny, st_count = ns * p->nt;
+  std::vector<Instance> in(nprob);
+  std::vector<char*> base(nprob);
+  char* w = wsb;
+  for (int i = 0; i < nprob; ++i) {
+    base[i] = w;
+    in[i].bind(probs + i, w);
+    w += in[i].L.total;
+    if (stats) std::memset(stats + i, 0, sizeof(pts_stats));
+  }
+  const Layout& L = in[0].L;
+  // host staging: the arguments of the active instances, then per instance the two
+  // residual scalars and the stage maxima of the last sequence
+  const size_t s_sc = align_up((size_t)nprob * sizeof(WaveArgs));
+  const size_t s_st = s_sc + align_up((size_t)nprob * 2 * 8);
+  char* stage;
+  int rc = host_stage(s_st + (size_t)nprob * (kMaxStages + 1) * 8, &stage);
+  if (rc) return rc;
+  WaveArgs* h_args = (WaveArgs*)stage;
+  double* h_sc = (double*)(stage + s_sc);
+  double* h_st = (double*)(stage + s_st);
+  WaveArgs* d_args = (WaveArgs*)header;  // the bulk schedule's descriptor area (larger entries)
+  static_assert(sizeof(WaveArgs) <= sizeof(BatchDesc), "batched wavefront arguments fit the header");
+  int launches = 0;
+  for (int i = 0; i < nprob; ++i) {
+    HIPCHK(hipMemcpyAsync(base[i] + L.u0copy, u0[i], ns * 8, hipMemcpyDeviceToDevice, s));
+    if ((rc = in[i].residual(U[i], u0[i], s, &launches, false))) return rc;
+    HIPCHK(hipMemcpyAsync(h_sc + 2 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<char> active(nprob, 1);
+  std::vector<int> needed(nprob, -1);
+  int it = 0, worst = PTS_OK;
+  Plan plan_used;
+  auto drop = [&](int i, int err) {
+    active[i] = 0;
+    codes[i] = err;
+    if (err && !worst) worst = err;
+  };
+  for (;;) {
+    std::vector<int> act;
+    double rho_all = 0.0;
+    for (int i = 0; i < nprob; ++i) {
+      if (!active[i]) continue;
+      const double res = h_sc[2 * i], rhom = h_sc[2 * i + 1];
+      pts_stats* st = stats ? stats + i : nullptr;
+      if (st) {
+        if (it < PTS_MAX_HIST) {
+          st->res_inf[it] = res;
+          st->rho_max[it] = rhom;
+        }
+        st->iterations = it;
+        st->hist = std::min(it + 1, PTS_MAX_HIST);
+        st->slab = p->nt;
+        st->window = 1;
+        st->schedule = PTS_SCHED_PIPELINE;
+      }
+      if (!std::isfinite(res) || !std::isfinite(rhom)) {
+        drop(i, fail(PTS_ERR_NONFINITE, "instance %d: non-finite residual at Newton step %d", i, it));
+      } else if (res <= tol) {
+        if (needed[i] < 0) needed[i] = it;
+        if (st) st->converged = 1;
+        drop(i, PTS_OK);
+      } else if (rhom >= 1.0) {
+        drop(i, fail(PTS_ERR_SINGULAR, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom));
+      } else if (it >= max_iter) {
+        drop(i, fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i,
+                     it, res));
+      } else {
+        act.push_back(i);
+        rho_all = std::max(rho_all, rhom);
+      }
+    }
+    if (act.empty()) break;
+    // inner plan and stage count as for one instance (explicit options, else the
+    // autotuned entry of the problem, else the cheapest plan reaching lin_tol)
+    Plan pl;
+    const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
+    const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
+    bool ok;
+    if (ce && !explicit_inner && ce->sweeps > 0) {
+      pl.fp32 = p->precision == PTS_MIXED;
+      pl.sweeps = ce->sweeps;
+      pl.passes = ce->passes;
+      pl.packs = {pl.passes};
+      ok = true;
+    } else {
+      ok = make_wave_plan(p, o, std::min(rho_all * 1.02, 0.999), lin_tol, &pl);
+    }
+    if (!ok) {
+      if (it == 0) {
+        *fallback = true;
+        return PTS_ERR_INVALID_ARG;
+      }
+      for (int i : act)
+        drop(i, fail(PTS_ERR_SINGULAR, "instance %d: inner solve cannot reach the requested reduction", i));
+      break;
+    }
+    const Geo g = in[0].g.whole ? in[0].g : geometry(p, wave_halo(pl));
+    int K = (o && o->stages > 0) ? o->stages : (ce && ce->steps > it ? ce->steps - it : 4);
+    K = std::max(1, std::min(std::min(K, kMaxStages), max_iter - it));
+    plan_used = pl;
+    const int tl = tiles(p, g);
+    const int nb = (int)act.size();
+    for (int q = 0; q < nb; ++q) {
+      const int i = act[q];
+      if (stats) {
+        stats[i].sweeps = pl.sweeps;
+        stats[i].refine = pl.passes - 1;
+      }
+      double* res_part = (double*)(base[i] + L.res_part);
+      hipLaunchKernelGGL(k_zero, dim3((unsigned)(((K + 1) * tl + 255) / 256)), dim3(256), 0, s,
+                         (unsigned long long*)res_part, (K + 1) * tl);
+      WaveArgs& wa = h_args[q];
+      wa.Ur[0] = U[i];
+      wa.Ur[1] = (double*)(base[i] + L.U1);
+      wa.u0 = (const double*)(base[i] + L.u0copy);
+      wa.rho_in = (const double*)in[i].rho;
+      wa.rho_part = (double*)(base[i] + L.rho_part);
+      wa.res_part = res_part;
+      wa.tiles = tl;
+      wa.stages = K;
+    }
+    launches += nb;
+    HIPCHK(hipMemcpyAsync(d_args, h_args, (size_t)nb * sizeof(WaveArgs), hipMemcpyHostToDevice, s));
+    const WaveBatchKernel kern = wave_batch_kernel(p, pl.fp32);
+    const int ndiag = p->nt + 2 * (K - 1);
+    auto launch_seq = [&](hipStream_t ls) -> int {
+      for (int d = 0; d < ndiag; ++d)
+        hipLaunchKernelGGL(kern, dim3((unsigned)(K * tl), (unsigned)nb), dim3(kThreads), 0, ls, in[0].kp,
+                           (const WaveArgs*)d_args, g, d, pl.passes, pl.sweeps);
+      HIPCHK(hipGetLastError());
+      return PTS_OK;
+    };
+    if (use_graph) {
+      // the arguments are read from the header at run time: the key holds what the
+      // launches themselves carry
+      std::vector<char> key;
+      const int extra[6] = {1, pl.passes, pl.sweeps, pl.fp32 ? 1 : 0, K, nb};
+      key_append(key, in[0].kp, g, d_args, extra);
+      rc = replay_or_capture(key, s, &launches, launch_seq);
+    } else {
+      rc = launch_seq(s);
+      launches += ndiag;
+    }
+    if (rc) return rc;
+    for (int i : act) {
+      double* res_st = (double*)(base[i] + L.res_st);
+      hipLaunchKernelGGL(k_stage_max, dim3(K + 1), dim3(256), 0, s, (const double*)(base[i] + L.res_part), tl,
+                         res_st);
+      if (K & 1) HIPCHK(hipMemcpyAsync(U[i], base[i] + L.U1, st_count * 8, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(h_st + (size_t)i * (kMaxStages + 1), res_st, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+    }
+    launches += nb;
+    HIPCHK(hipStreamSynchronize(s));
+    // residuals of the iterates U_{it+1..it+K}; an instance still above tol gets the
+    // all-level residual of U_{it+K} (the radii the next sequence starts from)
+    bool again = false;
+    for (int i : act) {
+      const double* rs = h_st + (size_t)i * (kMaxStages + 1);
+      bool bad = false;
+      for (int k = 1; k <= K && !bad; ++k) {
+        if (stats && it + k < PTS_MAX_HIST) stats[i].res_inf[it + k] = rs[k];
+        if (rs[k] <= tol && needed[i] < 0) needed[i] = it + k;
+        if (!std::isfinite(rs[k])) {
+          if (stats) stats[i].iterations = it + k;
+          drop(i, fail(PTS_ERR_NONFINITE, "instance %d: non-finite residual at Newton step %d", i, it + k));
+          bad = true;
+        }
+      }
+      if (bad) continue;
+      if (rs[K] > tol) {
+        if ((rc = in[i].residual(U[i], u0[i], s, &launches, false))) return rc;
+        HIPCHK(hipMemcpyAsync(h_sc + 2 * i, in[i].scal, 16, hipMemcpyDeviceToHost, s));
+        again = true;
+      } else {
+        h_sc[2 * i] = rs[K];
+        h_sc[2 * i + 1] = 0.0;
+      }
+    }
+    if (again) HIPCHK(hipStreamSynchronize(s));
+    it += K;
+  }
+  // remember the largest step count any instance needed with this plan
+  int most = -1;
+  bool all = true;
+  for (int i = 0; i < nprob; ++i) {
+    most = std::max(most, needed[i]);
+    all = all && needed[i] >= 0;
+  }
+  if (all && plan_used.sweeps > 0) {
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
+    if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
+      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(most, 1), true);
+  }
+  if (stats)
+    for (int i = 0; i < nprob; ++i) stats[i].launches = launches;
+  return worst;
+}
+
 extern "C" {
 
 const char* pts_last_error(void) { return g_err.c_str(); }
@@ -1929,8 +2181,36 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, con
   bool uniform = true;
   for (int i = 1; i < nprob; ++i)
     uniform = uniform && probs[i].bc == probs[0].bc && probs[i].precision == probs[0].precision;
-  const bool shared = uniform && !(opts && (opts->schedule == PTS_SCHED_PIPELINE || opts->window > 1));
+  const int sched = opts ? opts->schedule : PTS_SCHED_AUTO;
   char* w = (char*)workspace + batch_header_bytes(probs, nprob);
+  // one problem with different initial conditions: batched wavefront sequences
+  if (same_problem(probs, nprob) && sched != PTS_SCHED_BULK &&
+      !(opts && (opts->window > 1 || opts->profile || opts->wave_launch == 1)) &&
+      g_slab_cache.get(probs) >= probs[0].nt) {
+    std::vector<int> codes(nprob);
+    bool fb = false;
+    rc = solve_wave_batched(probs, nprob, U, u0, tol, max_iter, (char*)workspace, w, opts, stats,
+                            (hipStream_t)stream, &fb, codes.data());
+    if (!fb) {
+      // an instance whose Newton iteration diverged from its given iterate is solved alone,
+      // with the slab safeguard of pts_solve (from the plain iterate of each slab)
+      int worst = PTS_OK;
+      const size_t b = layout(probs).total;
+      for (int i = 0; i < nprob; ++i) {
+        int r = codes[i];
+        if (r == PTS_ERR_NONFINITE || r == PTS_ERR_SINGULAR) {
+          pts_stats one;
+          pts_stats* sp = stats ? stats + i : &one;
+          std::memset(sp, 0, sizeof *sp);
+          r = solve_slabs(probs + i, U[i], u0[i], tol, max_iter, w + (size_t)i * b, opts, sp, (hipStream_t)stream);
+        }
+        if (r && !worst) worst = r;
+      }
+      return rc == PTS_ERR_HIP ? rc : worst;
+    }
+    if (sched == PTS_SCHED_PIPELINE) return fail(PTS_ERR_INVALID_ARG, "the inner solve does not fit the wavefront schedule");
+  }
+  const bool shared = uniform && !(opts && (opts->schedule == PTS_SCHED_PIPELINE || opts->window > 1));
   if (shared) return solve_batched_bulk(probs, nprob, U, u0, tol, max_iter, (char*)workspace, w, opts, stats,
                                         (hipStream_t)stream);
   // one instance after another (mixed boundary kinds or precisions, the wavefront schedule,

@@ -742,6 +742,20 @@ __global__ __launch_bounds__(kThreads) void k_level_wave_seq(KProb p, WaveArgs a
   }
 }
 
+// ------------------------------------------------------------ batched wavefront
+// Instances of one problem (same sizes, coefficients and boundary data; own initial
+// conditions and iterates) share each anti-diagonal launch: grid (stages x tiles,
+// instances), blockIdx.y selects the instance's arguments. Every instance runs the same
+// stage count, so a launch carries all of their pairs of that anti-diagonal.
+template <typename T, int BC, int FORM>
+__global__ __launch_bounds__(kThreads) void k_level_wave_batch(KProb p, const WaveArgs* __restrict__ as, Geo g,
+                                                               int diag, int passes, int sweeps) {
+  const WaveArgs a = as[blockIdx.y];
+  const int tiles_per_level = gridDim.x / a.stages;
+  wave_pair<T, BC, FORM>(p, a, g, blockIdx.x / tiles_per_level, blockIdx.x % tiles_per_level, diag, passes,
+                         sweeps);
+}
+
 // ------------------------------------------------------------ Theorem 1 windows
 // y = A_m x at every node of level m (rows from U_m, Eq. (6)); products P^{w-1} r^w of
 // the Section 5 recursion are chains of these. One thread per node.

@@ -1,5 +1,6 @@
-"""Batched solves of independent instances with uneven grids and level counts (one launch per
-level and inner launch over every instance's tiles) against the time-stepping oracle."""
+"""Batched solves against the time-stepping oracle: independent instances with uneven grids and
+level counts (one launch per level and inner launch over every instance's tiles), and instances
+of one problem with different initial conditions (batched wavefront sequences)."""
 import numpy as np
 import pytest
 import torch
@@ -117,4 +118,88 @@ def test_single_instance_batch_and_single_levels():
     sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40)
     Uo, _ = sequential.solve_sequential(probs[0])
     assert sts[0]["converged"]
+    assert np.max(np.abs(host(Us[0]) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+
+
+# ------------------------------------------------------- one problem, many initial conditions
+def _burgers_family(n, nt, seeds, nu=0.01, dt=5e-4):
+    return [W.burgers_periodic(n, nt, dt, nu, W.fourier_u0_periodic(n, s, kmax=4), name=f"b{n}s{s}") for s in seeds]
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-8)])
+def test_one_problem_batch_runs_batched_wavefront(precision, bar):
+    """Instances that differ only in u^0 share every anti-diagonal launch (ragged tiles at 80^2,
+    several sequences) and each reaches the time-stepping oracle's solution."""
+    probs = _burgers_family(80, 7, [21, 22, 23])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print(f"[batched-wave] burgers 80x80x7 x3 {precision}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision=precision,
+                          stages=2)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        assert err <= bar, (p.name, err)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_batched_wavefront_equals_one_by_one_wavefront(bc):
+    """With the plan and stage count fixed, the batched launches compute each instance's pairs
+    exactly as the one-instance launches do."""
+    if bc == "periodic":
+        probs = _burgers_family(96, 9, [31, 32, 33, 34])
+    else:
+        rng = np.random.default_rng(35)
+        # 100^2 Dirichlet heat at tau = 2e-5: several tiles per level, Jacobi radius ~0.6
+        probs = [W.heat_dirichlet(100, 6, 2e-5, W.sine_u0_dirichlet(100, rng), name=f"h100_{k}") for k in range(3)]
+    plan = dict(sweeps=8, refine=0, stages=3)
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print(f"[batched-wave] equals one-by-one {bc}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, **plan)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["schedule"] == P.PTS_SCHED_PIPELINE
+        V = dev(p.plain_iterate())
+        st1 = P.solve(p, V, dev(p.u0), tol=1e-12, max_iter=40, schedule="pipeline", **plan)
+        assert st["converged"] and st1["converged"]
+        assert st["iterations"] == st1["iterations"], (st["iterations"], st1["iterations"])
+        np.testing.assert_allclose(host(U), host(V), rtol=0, atol=1e-13 * np.max(np.abs(host(V))))
+
+
+def test_batched_wavefront_replays_and_whole_region_heat():
+    """C1-sized Dirichlet heat (one whole-domain region per level): the same batch solved twice
+    (the second from cached graphs) gives the same answer, matching the oracle."""
+    rng = np.random.default_rng(41)
+    probs = [W.heat_dirichlet(32, 12, 1e-3, W.sine_u0_dirichlet(32, rng), name=f"h32_{k}") for k in range(5)]
+    outs = []
+    for rep in range(2):
+        Us = [dev(p.plain_iterate()) for p in probs]
+        print(f"[batched-wave] heat 32x32x12 x5 pass {rep}", flush=True)
+        sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, stages=4)
+        assert all(st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE for st in sts)
+        outs.append([host(U) for U in Us])
+    for p, a, b in zip(probs, outs[0], outs[1]):
+        assert np.array_equal(a, b)
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(a - Uo)) <= 1e-10 * np.max(np.abs(Uo)), p.name
+
+
+def test_batched_wavefront_mixed_convergence_and_limit():
+    """Instances that need different Newton step counts leave the batch one by one; with a step
+    limit below what one needs, that one reports not converged and the others finish."""
+    n = 64
+    u_small = 1e-3 * W.fourier_u0_periodic(n, 51, kmax=2)
+    u_big = W.fourier_u0_periodic(n, 52, kmax=4)
+    probs = [W.burgers_periodic(n, 6, 5e-4, 0.01, u, name=nm) for u, nm in ((u_small, "small"), (u_big, "big"))]
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, stages=1)
+    assert all(st["converged"] for st in sts)
+    assert sts[0]["iterations"] < sts[1]["iterations"], [st["iterations"] for st in sts]
+    for p, U in zip(probs, Us):
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+    lim = sts[0]["iterations"]
+    Us = [dev(p.plain_iterate()) for p in probs]
+    with pytest.raises(P.PTSError):
+        P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=lim, stages=1)
+    Uo, _ = sequential.solve_sequential(probs[0])
     assert np.max(np.abs(host(Us[0]) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
