@@ -284,17 +284,35 @@ def bench_learned(args):
             P.solve(prob, U, u0, tol=args.ref_tol, max_iter=60, ws=ws["fp64"], cache_tag=7)
             refs_b.append(U.clone())
 
-        def start_b(kind, j, report=False):
+        # inference + judge of the instances on a few streams at once (each call is a chain of
+        # small launches), each stream with its own network and judge workspaces
+        NS = max(1, args.infer_streams)
+        side = [torch.cuda.Stream(device=dev) for _ in range(NS)]
+        net_ws = [net.workspace(dev) for _ in range(NS)]
+        judge_ws = [P.workspace(prob, "fp64", dev) for _ in range(NS)]
+
+        def start_all(kind, report=False):
             if kind == "plain":
-                P.init_plain(prob, U_b[j], u0_b[j])
-                return None
-            return net.initial_iterate(prob, u0_b[j], U_b[j], solver_ws=ws["fp64"], report=report)
+                for j in range(EB):
+                    P.init_plain(prob, U_b[j], u0_b[j])
+                return []
+            cur = torch.cuda.current_stream()
+            for sd in side:
+                sd.wait_stream(cur)
+            out = [net.initial_iterate(prob, u0_b[j], U_b[j], solver_ws=judge_ws[j % NS], net_ws=net_ws[j % NS],
+                                       report=report, stream=side[j % NS]) for j in range(EB)]
+            for sd in side:
+                cur.wait_stream(sd)
+            return out
 
         for kind in ("plain", "learned"):
             tag = 1 if kind == "learned" else 0
             for pr in ("fp64", "mixed"):
+                if not args.no_autotune:
+                    start_all(kind)
+                    P.autotune_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
                 # untimed batch: settles the stage count for the batch and measures the errors
-                chosen = [start_b(kind, j, report=True) for j in range(EB)]
+                chosen = start_all(kind, report=True)
                 sts = P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
                 errs = [float((U_b[j] - refs_b[j]).abs().max() / refs_b[j].abs().max()) for j in range(EB)]
                 needed = [st["needed"] for st in sts]
@@ -302,8 +320,7 @@ def bench_learned(args):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
                 for _ in range(args.batch_reps):
-                    for j in range(EB):
-                        start_b(kind, j)
+                    start_all(kind)
                     P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
                 e1.record()
                 torch.cuda.synchronize()
@@ -440,6 +457,8 @@ def main():
     ap.add_argument("--learned-batch", type=int, default=16,
                     help="--learned: held-out initial conditions solved as one batch (0 = single solves only)")
     ap.add_argument("--batch-reps", type=int, default=3, help="--learned: timed repetitions of the batch")
+    ap.add_argument("--infer-streams", type=int, default=4,
+                    help="--learned: streams the batch's inference + judge calls are spread over")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -224,6 +224,22 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U,
                       size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
                       pts_stream_t stream);
 
+/* Autotuner of the batched wavefront schedule, for instances of one problem (as
+   pts_solve_batched defines it; PTS_ERR_INVALID_ARG otherwise): tries inner
+   sweep/pass plans on the whole batch (each a full batched solve from the
+   iterates in U, timed with HIP events on `stream`) and keeps the fastest
+   converging plan with its Newton step count in a per-thread cache keyed by the
+   problem, tol and opts->cache_tag, used by later pts_solve_batched calls on
+   such batches (a batch is throughput-bound where one instance is
+   latency-bound, so its best plan differs from the one pts_autotune keeps for
+   pts_solve). U is restored before returning. Arguments as pts_solve_batched;
+   stats (host array of nprob entries, may be NULL) receive the chosen plan and
+   its time in solve_ms. Synchronises the stream. */
+int pts_autotune_batched(const pts_problem* probs, int nprob, double* const* U,
+                         const double* const* u0, double tol, int max_iter, void* workspace,
+                         size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
+                         pts_stream_t stream);
+
 /* Section 7, Eq. (cond): largest number of levels W whose product of blocks
    keeps the estimated condition number K^W below c h^4 / eps, with
    K = (1 + 8 mu tau/h^2)/(1 + 2 pi^2 mu tau). If tau <= 0 the paper's setting

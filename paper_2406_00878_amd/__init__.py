@@ -24,7 +24,7 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, 
                    pts_stats)
 
 __all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve", "autotune",
-           "solve_batched", "window_bound", "library_path", "version"]
+           "solve_batched", "autotune_batched", "window_bound", "library_path", "version"]
 
 
 class PTSError(RuntimeError):
@@ -204,17 +204,14 @@ def autotune(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", 
             "slab": st.slab}
 
 
-def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
-                  **opts):
-    """Solve independent instances together; returns one statistics dict per instance."""
+def _batched_args(probs, Us, u0s, bdatas, precision):
     n = len(probs)
     bdatas = bdatas or [None] * n
     arr = (pts_problem * n)(*[make_problem(q, precision, b) for q, b in zip(probs, bdatas)])
     for q, U, u0 in zip(probs, Us, u0s):
         _dev_f64(U, (q.nt, q.ny, q.nx), "U")
         _dev_f64(u0, (q.ny, q.nx), "u0")
-    lib = _lib_checked()
-    nbytes = lib.pts_workspace_bytes_batched(arr, n)
+    nbytes = _lib_checked().pts_workspace_bytes_batched(arr, n)
     if nbytes == 0:
         _check(_lib.PTS_ERR_INVALID_ARG)
     raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=Us[0].device)
@@ -222,15 +219,37 @@ def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision
     ws = raw[off:off + nbytes]
     uptr = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
     u0ptr = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
+    return arr, ws, uptr, u0ptr
+
+
+def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
+                  **opts):
+    """Solve independent instances together; returns one statistics dict per instance."""
+    n = len(probs)
+    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision)
     o = _options(**opts)
     sts = (pts_stats * n)()
-    rc = lib.pts_solve_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws), nbytes, C.byref(o),
-                               sts, _stream(stream))
+    rc = _lib_checked().pts_solve_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws), ws.numel(),
+                                          C.byref(o), sts, _stream(stream))
     _check(rc)
     out = [_stats_dict(s) for s in sts]
     for d in out:  # Newton steps after which |R| <= tol was first reached
         d["needed"] = next((k for k, r in enumerate(d["res_inf"]) if r <= tol), None)
     return out
+
+
+def autotune_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
+                     **opts) -> dict:
+    """Pick the fastest wavefront plan for batches of one problem (Us restored); returns the
+    chosen plan (sweeps, refine, iterations, solve_ms)."""
+    n = len(probs)
+    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision)
+    o = _options(**opts)
+    sts = (pts_stats * n)()
+    _check(_lib_checked().pts_autotune_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws),
+                                               ws.numel(), C.byref(o), sts, _stream(stream)))
+    return {"sweeps": sts[0].sweeps, "refine": sts[0].refine, "iterations": sts[0].iterations,
+            "solve_ms": sts[0].solve_ms}
 
 
 def window_bound(h, mu, tau=0.0, c=1.0, eps=1e-16, wmax=100000) -> int:

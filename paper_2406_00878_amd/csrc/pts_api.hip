@@ -709,25 +709,29 @@ bool make_wave_plan(const pts_problem* p, const pts_options* o, double rho_max, 
 
 // Autotuned choices per problem signature and tolerance: inner sweeps and passes of the
 // wavefront kernel and the Newton steps they needed.
+// Entries for one instance and for batches of instances of the problem (batch = 1) are kept
+// apart: a batch's launches are throughput-bound, one instance's latency-bound, and the
+// fastest plans differ.
 struct StageCache {
   struct E {
-    int nx, ny, nt, kind, bc, prec, tag;
+    int nx, ny, nt, kind, bc, prec, tag, batch;
     double dt, mu_a, mu_b, tol;
     int sweeps, passes, steps;
   };
   std::vector<E> v;
-  E* find(const pts_problem* p, double tol, int tag) {
+  E* find(const pts_problem* p, double tol, int tag, int batch = 0) {
     for (auto& e : v)
       if (e.nx == p->nx && e.ny == p->ny && e.nt == p->nt && e.kind == p->kind && e.bc == p->bc &&
-          e.prec == p->precision && e.tag == tag && e.dt == p->dt && e.mu_a == p->mu_a && e.mu_b == p->mu_b &&
-          e.tol == tol)
+          e.prec == p->precision && e.tag == tag && e.batch == batch && e.dt == p->dt && e.mu_a == p->mu_a &&
+          e.mu_b == p->mu_b && e.tol == tol)
         return &e;
     return nullptr;
   }
   // keep_max: the entry keeps the largest step count seen with this plan. A sequence with a
   // spare stage costs two more diagonal launches, one stage short costs a second sequence.
-  void put(const pts_problem* p, double tol, int tag, int sweeps, int passes, int steps, bool keep_max = false) {
-    if (E* e = find(p, tol, tag)) {
+  void put(const pts_problem* p, double tol, int tag, int sweeps, int passes, int steps, bool keep_max = false,
+           int batch = 0) {
+    if (E* e = find(p, tol, tag, batch)) {
       if (keep_max && e->sweeps == sweeps && e->passes == passes) steps = std::max(steps, e->steps);
       e->sweeps = sweeps;
       e->passes = passes;
@@ -735,8 +739,8 @@ struct StageCache {
       return;
     }
     if (v.size() > 64) v.clear();
-    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, tag, p->dt, p->mu_a, p->mu_b, tol, sweeps,
-                 passes, steps});
+    v.push_back({p->nx, p->ny, p->nt, p->kind, p->bc, p->precision, tag, batch, p->dt, p->mu_a, p->mu_b, tol,
+                 sweeps, passes, steps});
   }
 };
 thread_local StageCache g_stage_cache;
@@ -1835,7 +1839,8 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
     // autotuned entry of the problem, else the cheapest plan reaching lin_tol)
     Plan pl;
     const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
-    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o), 1);
+    if (!ce) ce = g_stage_cache.find(p, tol, ctag(o), 0);
     const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
     bool ok;
     if (ce && !explicit_inner && ce->sweeps > 0) {
@@ -1949,13 +1954,108 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
     all = all && needed[i] >= 0;
   }
   if (all && plan_used.sweeps > 0) {
-    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
+    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o), 1);
     if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
-      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(most, 1), true);
+      g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(most, 1), true, 1);
   }
   if (stats)
     for (int i = 0; i < nprob; ++i) stats[i].launches = launches;
   return worst;
+}
+
+// Try inner plans on a batch of instances of one problem (each a full batched solve from the
+// iterates in U, run twice: once to learn its Newton step count, once timed with HIP events)
+// and cache the fastest for batches of this problem. U is restored on return (kept in each
+// instance's residual array, which the wavefront schedule does not use).
+int autotune_wave_batched(const pts_problem* probs, int nprob, double* const* U, const double* const* u0,
+                          double tol, int max_iter, char* header, char* wsb, const pts_options* o, pts_stats* stats,
+                          hipStream_t s) {
+  const pts_problem* p = probs;
+  const size_t bytes = (size_t)p->nx * p->ny * p->nt * 8, wb = layout(p).total;
+  std::vector<double*> backup(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    backup[i] = (double*)(wsb + (size_t)i * wb + layout(p).R);
+    HIPCHK(hipMemcpyAsync(backup[i], U[i], bytes, hipMemcpyDeviceToDevice, s));
+  }
+  auto restore = [&]() -> int {
+    for (int i = 0; i < nprob; ++i) HIPCHK(hipMemcpyAsync(U[i], backup[i], bytes, hipMemcpyDeviceToDevice, s));
+    return PTS_OK;
+  };
+  const bool fp32 = p->precision == PTS_MIXED;
+  std::vector<std::pair<int, int>> cands;
+  if (!fp32) {
+    for (int sw : {4, 5, 6, 7, 8, 10}) cands.push_back({sw, 1});
+  } else {
+    for (int sw : {3, 4, 5}) cands.push_back({sw, 2});
+    for (int sw : {4, 5, 6, 8}) cands.push_back({sw, 1});
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  int best_sw = 0, best_pa = 0, best_steps = 0;
+  pts_options o1 = o ? *o : pts_options{};
+  o1.schedule = PTS_SCHED_PIPELINE;
+  o1.profile = 0;
+  o1.lin_tol = 0;
+  o1.sweeps = 0;
+  o1.refine = -1;  // the plan comes from the cache entry written for the candidate
+  o1.stages = 0;
+  std::vector<pts_stats> st(nprob);
+  std::vector<int> codes(nprob);
+  int rc = PTS_OK;
+  for (auto& c : cands) {
+    Plan probe;
+    probe.sweeps = c.first;
+    probe.passes = c.second;
+    if (!geometry(p).whole && wave_halo(probe) > kMaxWaveHalo) continue;
+    g_stage_cache.put(p, tol, ctag(o), c.first, c.second, 4, false, 1);
+    bool fb = false, conv = true;
+    for (int run = 0; run < 2 && conv; ++run) {
+      if ((rc = restore())) break;
+      if (run == 1) HIPCHK(hipEventRecord(e0, s));
+      rc = solve_wave_batched(probs, nprob, U, u0, tol, max_iter, header, wsb, &o1, st.data(), s, &fb,
+                              codes.data());
+      if (run == 1) HIPCHK(hipEventRecord(e1, s));
+      if (rc == PTS_ERR_HIP) break;
+      for (int i = 0; i < nprob; ++i) conv = conv && st[i].converged;
+      conv = conv && !fb;
+    }
+    if (rc == PTS_ERR_HIP) break;
+    if (!conv) continue;
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o), 1);
+      best_ms = ms;
+      best_sw = c.first;
+      best_pa = c.second;
+      best_steps = ce ? ce->steps : st[0].iterations;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int rr = restore();
+  if (rc == PTS_ERR_HIP) return rc;
+  if (rr) return rr;
+  HIPCHK(hipStreamSynchronize(s));
+  if (best_sw == 0) {
+    g_stage_cache.put(p, tol, ctag(o), 0, 0, 0, false, 1);
+    return fail(PTS_ERR_NOT_CONVERGED, "autotune: no wavefront plan converged on the batch");
+  }
+  g_stage_cache.put(p, tol, ctag(o), best_sw, best_pa, best_steps, false, 1);
+  if (stats)
+    for (int i = 0; i < nprob; ++i) {
+      std::memset(stats + i, 0, sizeof(pts_stats));
+      stats[i].sweeps = best_sw;
+      stats[i].refine = best_pa - 1;
+      stats[i].iterations = best_steps;
+      stats[i].solve_ms = best_ms;
+      stats[i].schedule = PTS_SCHED_PIPELINE;
+      stats[i].slab = p->nt;
+    }
+  return PTS_OK;
 }
 
 extern "C" {
@@ -2223,6 +2323,26 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, con
     w += b;
   }
   return worst;
+}
+
+int pts_autotune_batched(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
+                         int max_iter, void* workspace, size_t workspace_bytes, const pts_options* opts,
+                         pts_stats* stats, pts_stream_t stream) {
+  const size_t need = pts_workspace_bytes_batched(probs, nprob);
+  if (need == 0) return PTS_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < need) return fail(PTS_ERR_WORKSPACE, "batched workspace too small");
+  if ((uintptr_t)workspace % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "NULL array list");
+  for (int i = 0; i < nprob; ++i)
+    if (!U[i] || !u0[i]) return fail(PTS_ERR_INVALID_ARG, "instance %d: NULL array", i);
+  int rc = check_opts(opts);
+  if (rc) return rc;
+  if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
+  if (!same_problem(probs, nprob))
+    return fail(PTS_ERR_INVALID_ARG, "pts_autotune_batched: the instances are not one problem");
+  char* w = (char*)workspace + batch_header_bytes(probs, nprob);
+  return autotune_wave_batched(probs, nprob, U, u0, tol, max_iter, (char*)workspace, w, opts, stats,
+                               (hipStream_t)stream);
 }
 
 }  // extern "C"

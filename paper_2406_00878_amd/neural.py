@@ -95,17 +95,24 @@ class NeuralOperator:
         self.n_params = lib.pts_no_param_count(C.byref(self._c))
         if self.n_params == 0:
             _check(-1)
-        nb = lib.pts_no_workspace_bytes(C.byref(self._c))
-        raw = torch.empty(nb + 256, dtype=torch.uint8, device=device)
-        off = (-raw.data_ptr()) % 256
-        self.ws = raw[off:off + nb]
-        _check(lib.pts_no_prepare(C.byref(self._c), _ptr(self.ws), self.ws.numel(), _stream(None)))
+        self.ws = self.workspace(device)
         self.params = self.init_params(seed).to(device)
         self.grads = torch.zeros_like(self.params)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step = 0
         self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        """A prepared network workspace (basis tables filled). Inference calls on different
+        streams at once need one each."""
+        lib = _lib()
+        nb = lib.pts_no_workspace_bytes(C.byref(self._c))
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        ws = raw[off:off + nb]
+        _check(lib.pts_no_prepare(C.byref(self._c), _ptr(ws), ws.numel(), _stream(None)))
+        return ws
 
     def init_params(self, seed: int) -> torch.Tensor:
         """Random initial weights (host generator): lift ~ N(0,1), channel mixes ~ N(0, 1/width),
@@ -172,15 +179,17 @@ class NeuralOperator:
                                   self.step, lr, beta1, beta2, eps, grad_scale, _stream(stream)))
 
     def initial_iterate(self, prob, u0, U, solver_ws=None, judge="accumulated", report=True,
-                        stream=None) -> Optional[dict]:
+                        stream=None, net_ws=None) -> Optional[dict]:
         """U <- prediction if its Newton residual beats the plain iterate's, else plain. The
-        decision is taken on the device; with report=False nothing is read back (no sync)."""
+        decision is taken on the device; with report=False nothing is read back (no sync).
+        net_ws: a network workspace from workspace() (default: the network's own)."""
         p = make_problem(prob, "fp64")
         solver_ws = workspace(prob, "fp64", U.device) if solver_ws is None else solver_ws
+        net_ws = self.ws if net_ws is None else net_ws
         ch, rp, r0 = C.c_int(0), C.c_double(0), C.c_double(0)
         refs = (C.byref(ch), C.byref(rp), C.byref(r0)) if report else (None, None, None)
         _check(_lib().pts_no_initial_iterate(C.cast(C.pointer(p), C.c_void_p), C.byref(self._c), _ptr(self.params),
-                                             _ptr(u0), _ptr(U), _ptr(self.ws), self.ws.numel(), _ptr(solver_ws),
+                                             _ptr(u0), _ptr(U), _ptr(net_ws), net_ws.numel(), _ptr(solver_ws),
                                              solver_ws.numel(), JUDGES[judge], *refs, _stream(stream)))
         if not report:
             return None

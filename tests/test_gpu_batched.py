@@ -203,3 +203,23 @@ def test_batched_wavefront_mixed_convergence_and_limit():
         P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=lim, stages=1)
     Uo, _ = sequential.solve_sequential(probs[0])
     assert np.max(np.abs(host(Us[0]) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+
+
+def test_batched_autotune_restores_iterates_and_sets_the_batch_plan():
+    probs = _burgers_family(64, 6, [61, 62, 63])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    before = [host(U) for U in Us]
+    u0s = [dev(p.u0) for p in probs]
+    print("[batched-wave] autotune 64x64x6 x3", flush=True)
+    plan = P.autotune_batched(probs, Us, u0s, tol=1e-12, max_iter=40, cache_tag=5)
+    assert plan["sweeps"] > 0 and plan["solve_ms"] > 0, plan
+    for a, U in zip(before, Us):
+        assert np.array_equal(a, host(U))
+    sts = P.solve_batched(probs, Us, u0s, tol=1e-12, max_iter=40, cache_tag=5)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"] and st["sweeps"] == plan["sweeps"], (st["sweeps"], plan)
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-10 * np.max(np.abs(Uo))
+    other = _heat_batch(64, [(20, 3), (24, 3)])
+    with pytest.raises(P.PTSError):
+        P.autotune_batched(other, [dev(p.plain_iterate()) for p in other], [dev(p.u0) for p in other])
