@@ -16,6 +16,8 @@ Modules
                   Jacobian, by the block inverse of Eq. (7), and by the decoupled
                   system of Theorem 1 / Eq. (8)-(9) with explicit products.
   condition       the condition-number estimate of Section 7, Eq. (cond).
+  coarse          the coarse-grid initial iterate of Section 4 (sequential solve on a
+                  grid coarsened by c_f in space and time, 1-D cubic splines back).
   neural          FP64 reference forward/backward of the spectral neural operator
                   used for the learned initial iterate.
 

@@ -1,0 +1,88 @@
+"""Coarse-grid initial iterate (oracle, test infrastructure only).
+
+Section 4 (initial guess of the all-at-once Newton iteration): the problem is solved
+sequentially on a grid coarsened by the same factor c_f in each spatial direction and in
+time, and the coarse solution is carried to the fine space-time grid by 1-D cubic splines.
+Sections 8.1 and 8.2 use c_f = 4 (heat) and c_f = 3 (Burgers).
+
+Readings where the paper is silent (the same on the HIP side):
+  * coarse nodes are every c_f-th fine node: periodic node x_k = k c_f h_x (fine index
+    k c_f, so c_f divides n_x); Dirichlet interior node k at (k + 1) c_f h_x (fine interior
+    index (k + 1) c_f - 1, so c_f divides n_x + 1), the domain edges staying where they are;
+    coarse step c_f tau, coarse level m at t = m c_f tau (c_f divides N_t); u^0 restricted
+    by injection; zero Dirichlet data only;
+  * spatial splines: x first, then y; periodic lines close with the period, Dirichlet lines
+    take the zero boundary values as end nodes with natural end conditions;
+  * time: after the spatial splines, a spline through t = 0 (the fine u^0) and the coarse
+    levels at every fine node, natural end conditions.
+
+The coarse solve is the sequential oracle itself; the splines are scipy's CubicSpline.
+Parity: pinned in tests/test_oracle.py (interpolation property at coarse nodes, fourth-order
+convergence on smooth periodic and Dirichlet fields, exact reproduction of data linear in t).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+from scipy.interpolate import CubicSpline
+
+from .sequential import solve_sequential
+
+PERIODIC = 1
+
+
+def coarse_problem(p, cf):
+    """The problem on the grid coarsened by cf in x, y and t (u^0 by injection)."""
+    if cf < 2 or p.nt % cf:
+        raise ValueError("cf must be >= 2 and divide nt")
+    if p.bc == PERIODIC:
+        if p.nx % cf or p.ny % cf:
+            raise ValueError("cf must divide nx and ny")
+        nx, ny = p.nx // cf, p.ny // cf
+        u0 = np.asarray(p.u0)[::cf, ::cf]
+    else:
+        if (p.nx + 1) % cf or (p.ny + 1) % cf:
+            raise ValueError("cf must divide nx + 1 and ny + 1")
+        if p.bdata is not None:
+            raise ValueError("nonzero Dirichlet data is not supported")
+        nx, ny = (p.nx + 1) // cf - 1, (p.ny + 1) // cf - 1
+        u0 = np.asarray(p.u0)[cf - 1::cf, cf - 1::cf][:ny, :nx]
+    return dataclasses.replace(p, nx=nx, ny=ny, nt=p.nt // cf, hx=cf * p.hx, hy=cf * p.hy, dt=cf * p.dt,
+                               u0=np.ascontiguousarray(u0), bdata=None, name=p.name + f"/cf{cf}")
+
+
+def _spline_axis(vals, cf, n_fine, h_fine, periodic, axis):
+    """Cubic spline of coarse values along `axis`, evaluated at the fine nodes of that axis."""
+    vals = np.moveaxis(vals, axis, -1)
+    nc = vals.shape[-1]
+    if periodic:
+        xc = np.arange(nc + 1) * cf * h_fine
+        yc = np.concatenate([vals, vals[..., :1]], axis=-1)
+        s = CubicSpline(xc, yc, axis=-1, bc_type="periodic")
+        xf = np.arange(n_fine) * h_fine
+    else:
+        xc = np.arange(nc + 2) * cf * h_fine  # edges at 0 and (nc + 1) cf h = (n_fine + 1) h
+        zero = np.zeros(vals.shape[:-1] + (1,))
+        yc = np.concatenate([zero, vals, zero], axis=-1)
+        s = CubicSpline(xc, yc, axis=-1, bc_type="natural")
+        xf = (np.arange(n_fine) + 1.0) * h_fine
+    return np.moveaxis(s(xf), -1, axis)
+
+
+def interpolate(p, cf, Uc):
+    """Fine space-time iterate [nt][ny][nx] from coarse levels Uc [nt/cf][ny_c][nx_c]."""
+    per = p.bc == PERIODIC
+    V = _spline_axis(np.asarray(Uc, dtype=np.float64), cf, p.nx, p.hx, per, axis=2)
+    V = _spline_axis(V, cf, p.ny, p.hy, per, axis=1)
+    tc = np.arange(p.nt // cf + 1) * cf * p.dt
+    data = np.concatenate([np.asarray(p.u0, dtype=np.float64)[None], V], axis=0)
+    s = CubicSpline(tc, data, axis=0, bc_type="natural")
+    return s(np.arange(1, p.nt + 1) * p.dt)
+
+
+def coarse_initial_iterate(p, cf, tol=1e-13):
+    """Section 4's initial iterate: sequential coarse solve, then the splines."""
+    pc = coarse_problem(p, cf)
+    Uc, _ = solve_sequential(pc, tol=tol)
+    return interpolate(p, cf, Uc), Uc

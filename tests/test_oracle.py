@@ -3,6 +3,7 @@
 Each test names what fixes the expected value: a number printed in the paper,
 a closed form, an invariant, or a library routine applied to a special case.
 """
+import dataclasses
 import math
 import os
 
@@ -264,3 +265,75 @@ def test_global_newton_converges_quadratically():
     assert len(ratios) >= 2
     assert max(ratios[1:]) < 50.0
     assert rh[-1] < 1e-13
+
+
+# --------------------------------------------- coarse-grid initial iterate (Section 4)
+def _field_problem(bc, n, nt, dt=1e-2):
+    if bc == "periodic":
+        return W.burgers_periodic(n, nt, dt, 0.01, np.zeros((n, n)))
+    return W.heat_dirichlet(n, nt, dt, np.zeros((n, n)))
+
+
+def _sample(p, f, t):
+    X, Y = p.mesh()
+    return f(X, Y, t)
+
+
+@pytest.mark.parametrize("bc,f", [
+    ("periodic", lambda x, y, t: (1.0 + 2.0 * t) * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.3),
+    # sin(pi x) sin(pi y): zero at the edges and zero second derivative there (natural ends exact)
+    ("dirichlet", lambda x, y, t: (1.0 - t) * np.sin(np.pi * x) * np.sin(np.pi * y)),
+])
+def test_coarse_interpolation_is_fourth_order_and_exact_at_coarse_nodes(bc, f):
+    """Cubic splines: interpolation property at coarse nodes, and the error on smooth data falls
+    16-fold per halving of the coarse spacing (O(h^4)); data linear in t is interpolated in
+    time without error, so the error is the spatial one."""
+    from oracle import coarse
+    errs = []
+    for n in ((32, 64) if bc == "periodic" else (31, 63)):
+        cf = 4
+        p = _field_problem(bc, n, 8)
+        p = dataclasses.replace(p, u0=_sample(p, f, 0.0))
+        pc = coarse.coarse_problem(p, cf)
+        Uc = np.stack([_sample(pc, f, (m + 1) * pc.dt) for m in range(pc.nt)])
+        U = coarse.interpolate(p, cf, Uc)
+        exact = np.stack([_sample(p, f, (n1 + 1) * p.dt) for n1 in range(p.nt)])
+        # fine levels m cf hold the coarse levels at the coarse nodes exactly
+        sl = (slice(None, None, cf), slice(None, None, cf)) if bc == "periodic" else \
+            (slice(cf - 1, None, cf), slice(cf - 1, None, cf))
+        for m in range(pc.nt):
+            np.testing.assert_allclose(U[(m + 1) * cf - 1][sl][:pc.ny, :pc.nx], Uc[m], rtol=0, atol=1e-13)
+        errs.append(np.max(np.abs(U - exact)))
+    ratio = errs[0] / errs[1]
+    assert 12.0 < ratio < 20.0, (errs, ratio)
+    assert errs[1] < 2e-4, errs
+
+
+def test_coarse_problem_sizes_and_injection():
+    from oracle import coarse
+    rng = np.random.default_rng(3)
+    p = W.heat_dirichlet(31, 12, 1e-3, W.sine_u0_dirichlet(31, rng))
+    pc = coarse.coarse_problem(p, 4)
+    assert (pc.nx, pc.ny, pc.nt) == (7, 7, 3) and pc.dt == 4e-3 and pc.hx == 4 * p.hx
+    # coarse interior node k sits at (k + 1) 4 h: the same physical points as fine node 4(k+1) - 1
+    np.testing.assert_array_equal(pc.x_nodes(), p.x_nodes()[3::4])
+    np.testing.assert_array_equal(pc.u0, p.u0[3::4, 3::4])
+    q = W.burgers_periodic(32, 8, 5e-4, 0.01, W.fourier_u0_periodic(32, 4, kmax=3))
+    qc = coarse.coarse_problem(q, 4)
+    assert (qc.nx, qc.nt) == (8, 2)
+    np.testing.assert_array_equal(qc.x_nodes(), q.x_nodes()[::4])
+    with pytest.raises(ValueError):
+        coarse.coarse_problem(q, 3)
+
+
+def test_coarse_initial_iterate_is_close_to_the_solution():
+    """The coarse start is an approximation of the fine solution (the Newton root): on smooth
+    heat its error is far below the plain start's (the paper's reason for using it)."""
+    from oracle import coarse
+    rng = np.random.default_rng(5)
+    p = W.heat_dirichlet(31, 16, 2e-3, W.sine_u0_dirichlet(31, rng))
+    Ug, _ = coarse.coarse_initial_iterate(p, 4)
+    Uo, _ = sequential.solve_sequential(p)
+    e_coarse = np.max(np.abs(Ug - Uo))
+    e_plain = np.max(np.abs(p.plain_iterate() - Uo))
+    assert e_coarse < 0.1 * e_plain, (e_coarse, e_plain)
