@@ -240,6 +240,29 @@ int pts_autotune_batched(const pts_problem* probs, int nprob, double* const* U,
                          size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
                          pts_stream_t stream);
 
+/* Section 4: the paper's initial iterate. The problem is solved on a grid coarsened
+   by cf in each spatial direction and in time, and the coarse solution is carried to
+   the fine space-time grid by 1-D cubic splines.
+   Coarse grid: node k is fine node k cf (periodic) or fine interior node (k+1) cf - 1
+   (Dirichlet: the domain edges stay), step cf dt, u0 by injection; solved in FP64 by
+   the all-at-once Newton iteration of pts_solve from its plain iterate (by Theorem 1
+   the root is the sequential coarse solution) to max|R| <= tol within max_iter steps.
+   Splines: along x, then y (periodic lines closed with the period; Dirichlet lines
+   through the zero edge values, natural end conditions), then along t through u0
+   (t = 0) and the coarse levels (t = m cf dt), natural end conditions, evaluated at
+   every fine node and level.
+   Requirements: cf >= 2 divides nt, and nx and ny leaving >= 3 coarse nodes
+   (periodic) or nx + 1 and ny + 1 (Dirichlet, zero data: bdata NULL); otherwise
+   PTS_ERR_INVALID_ARG (pts_coarse_workspace_bytes then returns 0).
+   u0: device [ny][nx]; U: device [nt][ny][nx], written; workspace: device, 256-byte
+   aligned, pts_coarse_workspace_bytes(p, cf) bytes; stats (host, may be NULL): the
+   coarse solve's statistics. An error of the coarse solve is returned as it is (U is
+   then not written). Synchronises the stream. */
+size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf);
+int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, double* U,
+                               double tol, int max_iter, void* workspace,
+                               size_t workspace_bytes, pts_stats* stats, pts_stream_t stream);
+
 /* Section 7, Eq. (cond): largest number of levels W whose product of blocks
    keeps the estimated condition number K^W below c h^4 / eps, with
    K = (1 + 8 mu tau/h^2)/(1 + 2 pi^2 mu tau). If tau <= 0 the paper's setting

@@ -24,7 +24,8 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, 
                    pts_stats)
 
 __all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve", "autotune",
-           "solve_batched", "autotune_batched", "window_bound", "library_path", "version"]
+           "solve_batched", "autotune_batched", "coarse_workspace", "coarse_initial_iterate", "window_bound",
+           "library_path", "version"]
 
 
 class PTSError(RuntimeError):
@@ -250,6 +251,31 @@ def autotune_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precis
                                                ws.numel(), C.byref(o), sts, _stream(stream)))
     return {"sweeps": sts[0].sweeps, "refine": sts[0].refine, "iterations": sts[0].iterations,
             "solve_ms": sts[0].solve_ms}
+
+
+def coarse_workspace(prob, cf, device="cuda") -> torch.Tensor:
+    """Device workspace of coarse_initial_iterate for `prob` and coarsening factor cf."""
+    p = make_problem(prob)
+    nbytes = _lib_checked().pts_coarse_workspace_bytes(C.byref(p), int(cf))
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def coarse_initial_iterate(prob, U, u0, cf, tol=1e-12, max_iter=50, ws=None, stream=None) -> dict:
+    """Section 4's initial iterate into U: solve on the grid coarsened by cf in space and time,
+    cubic splines back to the fine grid. Returns the coarse solve's statistics."""
+    p = make_problem(prob)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = coarse_workspace(prob, cf, U.device) if ws is None else ws
+    st = pts_stats()
+    _check(_lib_checked().pts_coarse_initial_iterate(C.byref(p), int(cf), _ptr(u0), _ptr(U), float(tol),
+                                                     int(max_iter), _ptr(ws), ws.numel(), C.byref(st),
+                                                     _stream(stream)))
+    return _stats_dict(st)
 
 
 def window_bound(h, mu, tau=0.0, c=1.0, eps=1e-16, wmax=100000) -> int:

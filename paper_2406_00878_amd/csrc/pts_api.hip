@@ -2058,6 +2058,145 @@ int autotune_wave_batched(const pts_problem* probs, int nprob, double* const* U,
   return PTS_OK;
 }
 
+// ------------------------------------------------ coarse-grid initial iterate (Section 4)
+// A cubic spline is linear in its data: at a point s (in units of the node spacing) the spline
+// through nodes z = 0..N-1 is sum_k w_k(s) y_k. The weights are formed here, column k being the
+// spline through the k-th unit vector, and the kernels apply them along each axis.
+
+// Tridiagonal solve with unit off-diagonals (Thomas): x = T^{-1} d, T = tridiag(1, diag, 1).
+void thomas_unit(const std::vector<double>& diag, const std::vector<double>& d, std::vector<double>& x) {
+  const size_t n = diag.size();
+  std::vector<double> cp(n), dp(n);
+  for (size_t i = 0; i < n; ++i) {
+    const double den = diag[i] - (i ? cp[i - 1] : 0.0);
+    cp[i] = 1.0 / den;
+    dp[i] = (d[i] - (i ? dp[i - 1] : 0.0)) / den;
+  }
+  x.assign(n, 0.0);
+  for (size_t i = n; i-- > 0;) x[i] = dp[i] - (i + 1 < n ? cp[i] * x[i + 1] : 0.0);
+}
+
+// Second derivatives M of the cubic spline through y at unit spacing: M_{z-1} + 4 M_z +
+// M_{z+1} = 6 (y_{z-1} - 2 y_z + y_{z+1}); natural ends (M_0 = M_{N-1} = 0), or periodic (indices
+// modulo N, N >= 3; the cyclic system by the Sherman-Morrison correction of a tridiagonal one).
+void spline_second(const std::vector<double>& y, bool periodic, std::vector<double>& M) {
+  const int N = (int)y.size();
+  M.assign(N, 0.0);
+  if (!periodic) {
+    if (N < 3) return;
+    std::vector<double> diag(N - 2, 4.0), d(N - 2), x;
+    for (int z = 1; z < N - 1; ++z) d[z - 1] = 6.0 * (y[z - 1] - 2.0 * y[z] + y[z + 1]);
+    thomas_unit(diag, d, x);
+    for (int z = 1; z < N - 1; ++z) M[z] = x[z - 1];
+    return;
+  }
+  // A = T + u v^T with corner entries 1: gamma = -4, T = A with diag[0] = 4 - gamma and
+  // diag[N-1] = 4 - 1/gamma, u = (gamma, 0, .., 0, 1), v = (1, 0, .., 0, 1/gamma)
+  const double gamma = -4.0;
+  std::vector<double> diag(N, 4.0), d(N), u(N, 0.0), x, q;
+  diag[0] = 4.0 - gamma;
+  diag[N - 1] = 4.0 - 1.0 / gamma;
+  for (int z = 0; z < N; ++z) d[z] = 6.0 * (y[(z + N - 1) % N] - 2.0 * y[z] + y[(z + 1) % N]);
+  u[0] = gamma;
+  u[N - 1] = 1.0;
+  thomas_unit(diag, d, x);
+  thomas_unit(diag, u, q);
+  const double f = (x[0] + x[N - 1] / gamma) / (1.0 + q[0] + q[N - 1] / gamma);
+  for (int z = 0; z < N; ++z) M[z] = x[z] - f * q[z];
+}
+
+// W[i][k] = w_k(s_i) for the spline through N nodes (natural ends or periodic).
+std::vector<double> spline_weights(int N, bool periodic, const std::vector<double>& s) {
+  std::vector<double> W(s.size() * (size_t)N), y(N, 0.0), M;
+  for (int k = 0; k < N; ++k) {
+    y.assign(N, 0.0);
+    y[k] = 1.0;
+    spline_second(y, periodic, M);
+    for (size_t i = 0; i < s.size(); ++i) {
+      int z0 = (int)std::floor(s[i]);
+      z0 = periodic ? ((z0 % N) + N) % N : std::max(0, std::min(z0, N - 2));
+      const int z1 = periodic ? (z0 + 1) % N : z0 + 1;
+      const double t = periodic ? s[i] - std::floor(s[i]) : s[i] - z0, a = 1.0 - t;
+      W[i * N + k] = a * y[z0] + t * y[z1] + ((a * a * a - a) * M[z0] + (t * t * t - t) * M[z1]) / 6.0;
+    }
+  }
+  return W;
+}
+
+// The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve).
+int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
+  if (cf < 2 || p->nt % cf) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must be >= 2 and divide nt");
+  *pc = *p;
+  if (p->bc == PTS_PERIODIC) {
+    if (p->nx % cf || p->ny % cf || p->nx / cf < 3 || p->ny / cf < 3)
+      return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must divide nx and ny, leaving >= 3 nodes");
+    pc->nx = p->nx / cf;
+    pc->ny = p->ny / cf;
+  } else {
+    if ((p->nx + 1) % cf || (p->ny + 1) % cf || (p->nx + 1) / cf < 2 || (p->ny + 1) / cf < 2)
+      return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must divide nx + 1 and ny + 1");
+    if (p->bdata) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: nonzero Dirichlet data is not supported");
+    pc->nx = (p->nx + 1) / cf - 1;
+    pc->ny = (p->ny + 1) / cf - 1;
+  }
+  pc->nt = p->nt / cf;
+  pc->hx = cf * p->hx;
+  pc->hy = cf * p->hy;
+  pc->dt = cf * p->dt;
+  pc->bdata = nullptr;
+  pc->precision = PTS_FP64;
+  return validate(pc);
+}
+
+struct CoarseLayout {
+  size_t solver, Uc, u0c, T1, V, Wx, Wy, Wt, total;
+};
+CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc) {
+  CoarseLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t nsc = (size_t)pc->nx * pc->ny;
+  L.solver = take(layout(pc).total);
+  L.Uc = take(nsc * pc->nt * 8);
+  L.u0c = take(nsc * 8);
+  L.T1 = take((size_t)pc->nt * pc->ny * p->nx * 8);
+  L.V = take((size_t)pc->nt * p->ny * p->nx * 8);
+  L.Wx = take((size_t)p->nx * pc->nx * 8);
+  L.Wy = take((size_t)p->ny * pc->ny * 8);
+  L.Wt = take((size_t)p->nt * (pc->nt + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+// The interpolation weights along one spatial axis: n fine nodes, nc coarse nodes.
+std::vector<double> axis_weights(bool periodic, int n, int nc, int cf) {
+  std::vector<double> s(n);
+  if (periodic) {  // fine node i at i h = (i / cf) coarse spacings
+    for (int i = 0; i < n; ++i) s[i] = (double)i / cf;
+    return spline_weights(nc, true, s);
+  }
+  // Dirichlet: spline nodes z = 0 (edge), 1..nc (coarse interior), nc + 1 (edge); fine
+  // interior node i at (i + 1) h; the zero edge values drop out
+  for (int i = 0; i < n; ++i) s[i] = (double)(i + 1) / cf;
+  const std::vector<double> Wf = spline_weights(nc + 2, false, s);
+  std::vector<double> W((size_t)n * nc);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < nc; ++k) W[(size_t)i * nc + k] = Wf[(size_t)i * (nc + 2) + k + 1];
+  return W;
+}
+
+void launch_interp(hipStream_t s, const double* W, int nf, int nc, const double* in, long isa, long isk, long isb,
+                   const double* in0, double* out, long osa, long osi, long osb, long na, long nb) {
+  const long total = na * nf * nb;
+  const unsigned blocks = (unsigned)std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_interp_axis, dim3(blocks), dim3(256), 0, s, W, nf, nc, in, isa, isk, isb, in0, out, osa, osi,
+                     osb, na, nb);
+}
+
 extern "C" {
 
 const char* pts_last_error(void) { return g_err.c_str(); }
@@ -2083,6 +2222,69 @@ int pts_window_bound(double h, double mu, double tau, double c, double eps, int 
       break;
   }
   return best;
+}
+
+size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf) {
+  if (validate(p)) return 0;
+  pts_problem pc;
+  if (coarse_problem(p, cf, &pc)) return 0;
+  return coarse_layout(p, &pc).total;
+}
+
+int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, double* U, double tol, int max_iter,
+                               void* workspace, size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  int rc = validate(p);
+  if (rc) return rc;
+  pts_problem pc;
+  if ((rc = coarse_problem(p, cf, &pc))) return rc;
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_coarse_initial_iterate: NULL array");
+  if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
+  const CoarseLayout L = coarse_layout(p, &pc);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(PTS_ERR_WORKSPACE, "coarse workspace %zu bytes < required %zu", workspace_bytes, L.total);
+  if ((uintptr_t)workspace % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)workspace;
+  double* Uc = (double*)(w + L.Uc);
+  double* u0c = (double*)(w + L.u0c);
+  double* T1 = (double*)(w + L.T1);
+  double* V = (double*)(w + L.V);
+  double* Wx = (double*)(w + L.Wx);
+  double* Wy = (double*)(w + L.Wy);
+  double* Wt = (double*)(w + L.Wt);
+  const bool per = p->bc == PTS_PERIODIC;
+  // weights: x, y, then time (nodes t = m cf tau, m = 0..nt/cf; fine level n at n / cf)
+  const std::vector<double> wx = axis_weights(per, p->nx, pc.nx, cf), wy = axis_weights(per, p->ny, pc.ny, cf);
+  std::vector<double> st(p->nt);
+  for (int n = 0; n < p->nt; ++n) st[n] = (double)(n + 1) / cf;
+  const std::vector<double> wt = spline_weights(pc.nt + 1, false, st);
+  char* hst;
+  if ((rc = host_stage((wx.size() + wy.size() + wt.size()) * 8, &hst))) return rc;
+  std::memcpy(hst, wx.data(), wx.size() * 8);
+  std::memcpy(hst + wx.size() * 8, wy.data(), wy.size() * 8);
+  std::memcpy(hst + (wx.size() + wy.size()) * 8, wt.data(), wt.size() * 8);
+  HIPCHK(hipMemcpyAsync(Wx, hst, wx.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(Wy, hst + wx.size() * 8, wy.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(Wt, hst + (wx.size() + wy.size()) * 8, wt.size() * 8, hipMemcpyHostToDevice, s));
+  // coarse u^0 by injection, the plain coarse iterate, and the coarse solve (all-at-once
+  // Newton: by Theorem 1 its root is the sequential coarse solution)
+  const size_t nsc = (size_t)pc.nx * pc.ny;
+  hipLaunchKernelGGL(k_cf_inject, dim3((unsigned)((nsc + 255) / 256)), dim3(256), 0, s, u0, p->nx, pc.nx, pc.ny, cf,
+                     per ? 0 : cf - 1, u0c);
+  const unsigned bb = (unsigned)std::min<size_t>((nsc * pc.nt + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_broadcast, dim3(bb), dim3(256), 0, s, nsc, pc.nt, Uc, (const double*)u0c);
+  HIPCHK(hipGetLastError());
+  rc = solve_slabs(&pc, Uc, u0c, tol, max_iter, w + L.solver, nullptr, stats, s);
+  if (rc) return rc;
+  // splines: x (coarse rows -> T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V -> U[n])
+  const long nx = p->nx, ny = p->ny, ns = nx * ny;
+  launch_interp(s, Wx, p->nx, pc.nx, Uc, pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1);
+  launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx);
+  launch_interp(s, Wt, p->nt, pc.nt + 1, V, 0, ns, 1, u0, U, 0, ns, 1, 1, ns);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return PTS_OK;
 }
 
 int pts_init_plain(const pts_problem* p, double* U, const double* u0, pts_stream_t stream) {

@@ -962,6 +962,39 @@ __global__ __launch_bounds__(256) void k_broadcast(size_t ns, int nt, double* __
     U[i] = u0[i % ns];
 }
 
+// ------------------------------------------------ coarse-grid initial iterate (Section 4)
+// u0c[yc][xc] = u0[yc cf + off][xc cf + off]: injection onto every cf-th node (off = 0 for a
+// periodic grid, cf - 1 for the interior nodes of a Dirichlet grid).
+__global__ __launch_bounds__(256) void k_cf_inject(const double* __restrict__ u0, int nx, int nxc, int nyc, int cf,
+                                                   int off, double* __restrict__ u0c) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nxc * nyc) return;
+  const int xc = i % nxc, yc = i / nxc;
+  u0c[i] = u0[(size_t)(yc * cf + off) * nx + (xc * cf + off)];
+}
+
+// One 1-D interpolation pass: out[a][i][b] = sum_k W[i][k] v_k[a][b] over the nc nodes of
+// the axis, v_k = in[a][k][b], or with in0 given v_0 = in0[b] and v_k = in[a][k - 1][b].
+// Strides in elements; one thread per output, b fastest (threads of a wave then share i and
+// read the weight row as uniform values).
+__global__ __launch_bounds__(256) void k_interp_axis(const double* __restrict__ W, int nf, int nc,
+                                                     const double* __restrict__ in, long isa, long isk, long isb,
+                                                     const double* __restrict__ in0, double* __restrict__ out,
+                                                     long osa, long osi, long osb, long na, long nb) {
+  const long total = na * nf * nb;
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long b = t % nb, r = t / nb;
+    const int i = (int)(r % nf);
+    const long a = r / nf;
+    const double* w = W + (size_t)i * nc;
+    const int k0 = in0 ? 1 : 0;
+    double acc = in0 ? w[0] * in0[b] : 0.0;
+    const long base = a * isa + b * isb;
+    for (int k = k0; k < nc; ++k) acc = fma(w[k], in[base + (long)(k - k0) * isk], acc);
+    out[a * osa + (long)i * osi + b * osb] = acc;
+  }
+}
+
 // Fill a small array of 64-bit words with zero (used instead of a memset node so that
 // the sequence can be captured in a HIP graph).
 __global__ void k_zero(unsigned long long* __restrict__ a, int count) {

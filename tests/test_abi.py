@@ -3,6 +3,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -89,3 +90,18 @@ def test_solver_option_validation_on_host():
     assert rc == P._lib.PTS_ERR_INVALID_ARG and b"negative" in lib.pts_last_error()
     with pytest.raises(KeyError):
         P._options(wave_launch="persistent")
+
+
+def test_coarse_workspace_bytes_validates_on_host():
+    """pts_coarse_workspace_bytes is host-only: 0 when cf does not divide the sizes."""
+    import paper_2406_00878_amd as P
+    import workloads as W
+    lib = P._lib.load()
+    q = W.burgers_periodic(32, 8, 5e-4, 0.01, np.zeros((32, 32)))
+    p = P.make_problem(q)
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 4) > 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 3) == 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 1) == 0
+    h = W.heat_dirichlet(31, 12, 1e-3, np.zeros((31, 31)))
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 4) > 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 5) == 0
