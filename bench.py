@@ -214,15 +214,21 @@ def bench_learned(args):
         P.solve(prob, U, u0, tol=args.ref_tol, max_iter=60, ws=ws["fp64"], cache_tag=7)
         refs.append(U.clone())
 
+    cf = args.coarse_factor
+    cws = P.coarse_workspace(prob, cf, dev) if cf > 1 else None
+
     def start(kind, u0, report=True):
         if kind == "plain":
             P.init_plain(prob, U, u0)
             return None
+        if kind == "coarse":  # the paper's start: coarse-grid solve + cubic splines
+            P.coarse_initial_iterate(prob, U, u0, cf, tol=tol, ws=cws)
+            return None
         return net.initial_iterate(prob, u0, U, solver_ws=ws["fp64"], report=report)
 
     results = {}
-    for kind in ("plain", "learned"):
-        tag = 1 if kind == "learned" else 0
+    for kind in ("plain", "learned") + (("coarse",) if cf > 1 else ()):
+        tag = {"plain": 0, "learned": 1, "coarse": 2}[kind]
         for pr in ("fp64", "mixed"):
             if not args.no_autotune:
                 start(kind, u0_eval[0])
@@ -268,6 +274,14 @@ def bench_learned(args):
     e1.record()
     torch.cuda.synchronize()
     infer_ms = e0.elapsed_time(e1) / args.steps
+    coarse_ms = None
+    if cf > 1:  # coarse-grid start alone (the coarse solve synchronises; host clock)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            start("coarse", u0_eval[k % E])
+        torch.cuda.synchronize()
+        coarse_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # the held-out initial conditions as one batch (one problem, different u^0): every
     # anti-diagonal launch carries the pairs of all instances, so the total work of the stages,
@@ -358,7 +372,8 @@ def bench_learned(args):
                    "network": {"width": 32, "modes": 12, "layers": 4, "tmodes": 16},
                    "train_samples": n_train, "train_epochs": args.train_epochs,
                    "train_loss_first_last": [hist[0], hist[-1]], "generate_s": gen_s, "train_s": train_s,
-                   "inference_plus_judge_ms": infer_ms, "held_out": E, "held_out_batch": EB,
+                   "inference_plus_judge_ms": infer_ms, "coarse_start_ms": coarse_ms, "coarse_factor": cf,
+                   "held_out": E, "held_out_batch": EB,
                    "timed": "one batch of held-out initial conditions" if batched else "one solve"},
         "compare": results,
         "compare_batched": batched,
@@ -457,6 +472,8 @@ def main():
     ap.add_argument("--learned-batch", type=int, default=16,
                     help="--learned: held-out initial conditions solved as one batch (0 = single solves only)")
     ap.add_argument("--batch-reps", type=int, default=3, help="--learned: timed repetitions of the batch")
+    ap.add_argument("--coarse-factor", type=int, default=4,
+                    help="--learned: also time the coarse-grid start (Section 4) with this factor (0 = off)")
     ap.add_argument("--infer-streams", type=int, default=4,
                     help="--learned: streams the batch's inference + judge calls are spread over")
     args = ap.parse_args()
