@@ -244,15 +244,17 @@ int pts_autotune_batched(const pts_problem* probs, int nprob, double* const* U,
    by cf in each spatial direction and in time, and the coarse solution is carried to
    the fine space-time grid by 1-D cubic splines.
    Coarse grid: node k is fine node k cf (periodic) or fine interior node (k+1) cf - 1
-   (Dirichlet: the domain edges stay), step cf dt, u0 by injection; solved in FP64 by
-   the all-at-once Newton iteration of pts_solve from its plain iterate (by Theorem 1
-   the root is the sequential coarse solution) to max|R| <= tol within max_iter steps.
+   (Dirichlet: the domain edges stay), step cf dt, u0 and the Dirichlet data by
+   injection (coarse level m takes fine level m cf); solved in FP64 by the all-at-once
+   Newton iteration of pts_solve from its plain iterate (by Theorem 1 the root is the
+   sequential coarse solution) to max|R| <= tol within max_iter steps.
    Splines: along x, then y (periodic lines closed with the period; Dirichlet lines
-   through the zero edge values, natural end conditions), then along t through u0
-   (t = 0) and the coarse levels (t = m cf dt), natural end conditions, evaluated at
-   every fine node and level.
+   through the edge values, coarse west/east data for x lines and fine south/north
+   data for y lines, not-a-knot end conditions), then along t through u0 (t = 0) and
+   the coarse levels (t = m cf dt), not-a-knot end conditions, evaluated at every fine
+   node and level.
    Requirements: cf >= 2 divides nt, and nx and ny leaving >= 3 coarse nodes
-   (periodic) or nx + 1 and ny + 1 (Dirichlet, zero data: bdata NULL); otherwise
+   (periodic) or nx + 1 and ny + 1 (Dirichlet; bdata NULL for zero data); otherwise
    PTS_ERR_INVALID_ARG (pts_coarse_workspace_bytes then returns 0).
    u0: device [ny][nx]; U: device [nt][ny][nx], written; workspace: device, 256-byte
    aligned, pts_coarse_workspace_bytes(p, cf) bytes; stats (host, may be NULL): the

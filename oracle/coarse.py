@@ -9,16 +9,21 @@ Readings where the paper is silent (the same on the HIP side):
   * coarse nodes are every c_f-th fine node: periodic node x_k = k c_f h_x (fine index
     k c_f, so c_f divides n_x); Dirichlet interior node k at (k + 1) c_f h_x (fine interior
     index (k + 1) c_f - 1, so c_f divides n_x + 1), the domain edges staying where they are;
-    coarse step c_f tau, coarse level m at t = m c_f tau (c_f divides N_t); u^0 restricted
-    by injection; zero Dirichlet data only;
+    coarse step c_f tau, coarse level m at t = m c_f tau (c_f divides N_t); u^0 and the
+    Dirichlet data restricted by injection (coarse level m takes the fine data of level m c_f);
   * spatial splines: x first, then y; periodic lines close with the period, Dirichlet lines
-    take the zero boundary values as end nodes with natural end conditions;
+    take the boundary values as end nodes (x lines: the coarse data of the west and east
+    edges; y lines: the fine data of the south and north edges at the coarse level's time)
+    with not-a-knot end conditions (the usual default of cubic-spline routines; natural ends
+    would force a zero second derivative at the edges, which the Section 8.1 solution lacks);
   * time: after the spatial splines, a spline through t = 0 (the fine u^0) and the coarse
-    levels at every fine node, natural end conditions.
+    levels at every fine node, not-a-knot end conditions.
 
 The coarse solve is the sequential oracle itself; the splines are scipy's CubicSpline.
 Parity: pinned in tests/test_oracle.py (interpolation property at coarse nodes, fourth-order
-convergence on smooth periodic and Dirichlet fields, exact reproduction of data linear in t).
+convergence on smooth periodic and Dirichlet fields, exact reproduction of cubic fields with
+nonzero Dirichlet data, the coarse start of the Section 8.1 exact-solution problem close to the
+exact solution).
 """
 from __future__ import annotations
 
@@ -44,16 +49,29 @@ def coarse_problem(p, cf):
     else:
         if (p.nx + 1) % cf or (p.ny + 1) % cf:
             raise ValueError("cf must divide nx + 1 and ny + 1")
-        if p.bdata is not None:
-            raise ValueError("nonzero Dirichlet data is not supported")
         nx, ny = (p.nx + 1) // cf - 1, (p.ny + 1) // cf - 1
         u0 = np.asarray(p.u0)[cf - 1::cf, cf - 1::cf][:ny, :nx]
+    bdata = None
+    if p.bc != PERIODIC and p.bdata is not None:
+        S, N, Wd, E = _edges(p)
+        lv = slice(cf - 1, None, cf)  # fine level (m + 1) cf for coarse level m + 1
+        ix = slice(cf - 1, None, cf)
+        bdata = np.concatenate([S[lv][:, ix][:, :nx], N[lv][:, ix][:, :nx], Wd[lv][:, ix][:, :ny],
+                                E[lv][:, ix][:, :ny]], axis=1)
     return dataclasses.replace(p, nx=nx, ny=ny, nt=p.nt // cf, hx=cf * p.hx, hy=cf * p.hy, dt=cf * p.dt,
-                               u0=np.ascontiguousarray(u0), bdata=None, name=p.name + f"/cf{cf}")
+                               u0=np.ascontiguousarray(u0), bdata=bdata, name=p.name + f"/cf{cf}")
 
 
-def _spline_axis(vals, cf, n_fine, h_fine, periodic, axis):
-    """Cubic spline of coarse values along `axis`, evaluated at the fine nodes of that axis."""
+def _edges(p):
+    """Dirichlet data split into its south, north, west and east parts, each [nt][n]."""
+    b = np.asarray(p.bdata, dtype=np.float64)
+    return (b[:, :p.nx], b[:, p.nx:2 * p.nx], b[:, 2 * p.nx:2 * p.nx + p.ny], b[:, 2 * p.nx + p.ny:])
+
+
+def _spline_axis(vals, cf, n_fine, h_fine, periodic, axis, lo=None, hi=None):
+    """Cubic spline of coarse values along `axis`, evaluated at the fine nodes of that axis.
+    Dirichlet lines end in the edge values lo and hi (arrays shaped like vals without that
+    axis; zero when None)."""
     vals = np.moveaxis(vals, axis, -1)
     nc = vals.shape[-1]
     if periodic:
@@ -63,9 +81,11 @@ def _spline_axis(vals, cf, n_fine, h_fine, periodic, axis):
         xf = np.arange(n_fine) * h_fine
     else:
         xc = np.arange(nc + 2) * cf * h_fine  # edges at 0 and (nc + 1) cf h = (n_fine + 1) h
-        zero = np.zeros(vals.shape[:-1] + (1,))
-        yc = np.concatenate([zero, vals, zero], axis=-1)
-        s = CubicSpline(xc, yc, axis=-1, bc_type="natural")
+        zero = np.zeros(vals.shape[:-1])
+        lo = zero if lo is None else lo
+        hi = zero if hi is None else hi
+        yc = np.concatenate([lo[..., None], vals, hi[..., None]], axis=-1)
+        s = CubicSpline(xc, yc, axis=-1, bc_type="not-a-knot")
         xf = (np.arange(n_fine) + 1.0) * h_fine
     return np.moveaxis(s(xf), -1, axis)
 
@@ -73,11 +93,18 @@ def _spline_axis(vals, cf, n_fine, h_fine, periodic, axis):
 def interpolate(p, cf, Uc):
     """Fine space-time iterate [nt][ny][nx] from coarse levels Uc [nt/cf][ny_c][nx_c]."""
     per = p.bc == PERIODIC
-    V = _spline_axis(np.asarray(Uc, dtype=np.float64), cf, p.nx, p.hx, per, axis=2)
-    V = _spline_axis(V, cf, p.ny, p.hy, per, axis=1)
+    Uc = np.asarray(Uc, dtype=np.float64)
+    wl = wh = sl = sh = None
+    if not per and p.bdata is not None:
+        S, N, Wd, E = _edges(p)
+        lv, iy = slice(cf - 1, None, cf), slice(cf - 1, None, cf)
+        wl, wh = Wd[lv][:, iy][:, :Uc.shape[1]], E[lv][:, iy][:, :Uc.shape[1]]  # [m][yc]
+        sl, sh = S[lv], N[lv]  # [m][x] at the coarse levels' times
+    V = _spline_axis(Uc, cf, p.nx, p.hx, per, axis=2, lo=wl, hi=wh)
+    V = _spline_axis(V, cf, p.ny, p.hy, per, axis=1, lo=sl, hi=sh)
     tc = np.arange(p.nt // cf + 1) * cf * p.dt
     data = np.concatenate([np.asarray(p.u0, dtype=np.float64)[None], V], axis=0)
-    s = CubicSpline(tc, data, axis=0, bc_type="natural")
+    s = CubicSpline(tc, data, axis=0, bc_type="not-a-knot")
     return s(np.arange(1, p.nt + 1) * p.dt)
 
 

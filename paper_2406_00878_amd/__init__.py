@@ -264,10 +264,10 @@ def coarse_workspace(prob, cf, device="cuda") -> torch.Tensor:
     return ws[off:off + nbytes]
 
 
-def coarse_initial_iterate(prob, U, u0, cf, tol=1e-12, max_iter=50, ws=None, stream=None) -> dict:
+def coarse_initial_iterate(prob, U, u0, cf, tol=1e-12, max_iter=50, ws=None, bdata=None, stream=None) -> dict:
     """Section 4's initial iterate into U: solve on the grid coarsened by cf in space and time,
     cubic splines back to the fine grid. Returns the coarse solve's statistics."""
-    p = make_problem(prob)
+    p = make_problem(prob, "fp64", bdata)
     _dev_f64(U, (p.nt, p.ny, p.nx), "U")
     _dev_f64(u0, (p.ny, p.nx), "u0")
     ws = coarse_workspace(prob, cf, U.device) if ws is None else ws

@@ -2077,17 +2077,33 @@ void thomas_unit(const std::vector<double>& diag, const std::vector<double>& d, 
 }
 
 // Second derivatives M of the cubic spline through y at unit spacing: M_{z-1} + 4 M_z +
-// M_{z+1} = 6 (y_{z-1} - 2 y_z + y_{z+1}); natural ends (M_0 = M_{N-1} = 0), or periodic (indices
-// modulo N, N >= 3; the cyclic system by the Sherman-Morrison correction of a tridiagonal one).
+// M_{z+1} = 6 (y_{z-1} - 2 y_z + y_{z+1}) at the inner nodes, and either not-a-knot ends (one
+// cubic across the first two and the last two intervals: M_0 - 2 M_1 + M_2 = 0 and likewise
+// at the far end; substituted, the rows of nodes 1 and N-2 become 6 M_1 = d_1 and
+// 6 M_{N-2} = d_{N-2}; N = 3 gives one parabola, N = 2 a line), or periodic (indices modulo N,
+// N >= 3; the cyclic system by the Sherman-Morrison correction of a tridiagonal one).
 void spline_second(const std::vector<double>& y, bool periodic, std::vector<double>& M) {
   const int N = (int)y.size();
   M.assign(N, 0.0);
   if (!periodic) {
     if (N < 3) return;
-    std::vector<double> diag(N - 2, 4.0), d(N - 2), x;
+    const int n = N - 2;
+    std::vector<double> d(n), sub(n, 1.0), diag(n, 4.0), sup(n, 1.0);
     for (int z = 1; z < N - 1; ++z) d[z - 1] = 6.0 * (y[z - 1] - 2.0 * y[z] + y[z + 1]);
-    thomas_unit(diag, d, x);
-    for (int z = 1; z < N - 1; ++z) M[z] = x[z - 1];
+    diag[0] = 6.0;
+    sup[0] = 0.0;
+    diag[n - 1] = 6.0;
+    sub[n - 1] = 0.0;
+    // Thomas with the modified end rows (sub[0] and sup[n-1] are outside the matrix)
+    std::vector<double> cp(n), dp(n);
+    for (int i = 0; i < n; ++i) {
+      const double den = diag[i] - (i ? sub[i] * cp[i - 1] : 0.0);
+      cp[i] = sup[i] / den;
+      dp[i] = (d[i] - (i ? sub[i] * dp[i - 1] : 0.0)) / den;
+    }
+    for (int i = n - 1; i >= 0; --i) M[i + 1] = dp[i] - (i + 1 < n ? cp[i] * M[i + 2] : 0.0);
+    M[0] = N == 3 ? M[1] : 2.0 * M[1] - M[2];
+    M[N - 1] = N == 3 ? M[1] : 2.0 * M[N - 2] - M[N - 3];
     return;
   }
   // A = T + u v^T with corner entries 1: gamma = -4, T = A with diag[0] = 4 - gamma and
@@ -2105,7 +2121,7 @@ void spline_second(const std::vector<double>& y, bool periodic, std::vector<doub
   for (int z = 0; z < N; ++z) M[z] = x[z] - f * q[z];
 }
 
-// W[i][k] = w_k(s_i) for the spline through N nodes (natural ends or periodic).
+// W[i][k] = w_k(s_i) for the spline through N nodes (not-a-knot ends or periodic).
 std::vector<double> spline_weights(int N, bool periodic, const std::vector<double>& s) {
   std::vector<double> W(s.size() * (size_t)N), y(N, 0.0), M;
   for (int k = 0; k < N; ++k) {
@@ -2135,7 +2151,6 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
   } else {
     if ((p->nx + 1) % cf || (p->ny + 1) % cf || (p->nx + 1) / cf < 2 || (p->ny + 1) / cf < 2)
       return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must divide nx + 1 and ny + 1");
-    if (p->bdata) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: nonzero Dirichlet data is not supported");
     pc->nx = (p->nx + 1) / cf - 1;
     pc->ny = (p->ny + 1) / cf - 1;
   }
@@ -2149,7 +2164,7 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
 }
 
 struct CoarseLayout {
-  size_t solver, Uc, u0c, T1, V, Wx, Wy, Wt, total;
+  size_t solver, Uc, u0c, T1, V, Wx, Wy, Wt, We, bdc, edges, total;
 };
 CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc) {
   CoarseLayout L;
@@ -2168,33 +2183,43 @@ CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc) {
   L.Wx = take((size_t)p->nx * pc->nx * 8);
   L.Wy = take((size_t)p->ny * pc->ny * 8);
   L.Wt = take((size_t)p->nt * (pc->nt + 1) * 8);
+  L.We = take((size_t)2 * (p->nx + p->ny) * 8);  // edge weights: x low, x high, y low, y high
+  const bool dir = p->bc != PTS_PERIODIC;
+  L.bdc = take(dir ? (size_t)pc->nt * 2 * (pc->nx + pc->ny) * 8 : 0);
+  L.edges = take(dir ? (size_t)pc->nt * 2 * (pc->ny + p->nx) * 8 : 0);  // west_c, east_c, south_f, north_f
   L.total = o;
   return L;
 }
 
-// The interpolation weights along one spatial axis: n fine nodes, nc coarse nodes.
-std::vector<double> axis_weights(bool periodic, int n, int nc, int cf) {
+// The interpolation weights along one spatial axis: n fine nodes, nc coarse nodes; for a
+// Dirichlet axis also the weights of its two edge values (lo, hi).
+std::vector<double> axis_weights(bool periodic, int n, int nc, int cf, double* lo, double* hi) {
   std::vector<double> s(n);
   if (periodic) {  // fine node i at i h = (i / cf) coarse spacings
     for (int i = 0; i < n; ++i) s[i] = (double)i / cf;
     return spline_weights(nc, true, s);
   }
   // Dirichlet: spline nodes z = 0 (edge), 1..nc (coarse interior), nc + 1 (edge); fine
-  // interior node i at (i + 1) h; the zero edge values drop out
+  // interior node i at (i + 1) h
   for (int i = 0; i < n; ++i) s[i] = (double)(i + 1) / cf;
   const std::vector<double> Wf = spline_weights(nc + 2, false, s);
   std::vector<double> W((size_t)n * nc);
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     for (int k = 0; k < nc; ++k) W[(size_t)i * nc + k] = Wf[(size_t)i * (nc + 2) + k + 1];
+    lo[i] = Wf[(size_t)i * (nc + 2)];
+    hi[i] = Wf[(size_t)i * (nc + 2) + nc + 1];
+  }
   return W;
 }
 
 void launch_interp(hipStream_t s, const double* W, int nf, int nc, const double* in, long isa, long isk, long isb,
-                   const double* in0, double* out, long osa, long osi, long osb, long na, long nb) {
+                   const double* in0, double* out, long osa, long osi, long osb, long na, long nb,
+                   const double* Wlo = nullptr, const double* Whi = nullptr, const double* elo = nullptr,
+                   const double* ehi = nullptr, long esa = 0, long esb = 0) {
   const long total = na * nf * nb;
   const unsigned blocks = (unsigned)std::min<long>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(k_interp_axis, dim3(blocks), dim3(256), 0, s, W, nf, nc, in, isa, isk, isb, in0, out, osa, osi,
-                     osb, na, nb);
+                     osb, na, nb, Wlo, Whi, elo, ehi, esa, esb);
 }
 
 extern "C" {
@@ -2253,20 +2278,42 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
   double* Wx = (double*)(w + L.Wx);
   double* Wy = (double*)(w + L.Wy);
   double* Wt = (double*)(w + L.Wt);
+  double* We = (double*)(w + L.We);
   const bool per = p->bc == PTS_PERIODIC;
-  // weights: x, y, then time (nodes t = m cf tau, m = 0..nt/cf; fine level n at n / cf)
-  const std::vector<double> wx = axis_weights(per, p->nx, pc.nx, cf), wy = axis_weights(per, p->ny, pc.ny, cf);
+  // weights: x, y (with the edge weights of Dirichlet lines), then time (nodes t = m cf tau,
+  // m = 0..nt/cf; fine level n at n / cf)
+  std::vector<double> we(2 * (p->nx + p->ny), 0.0);
+  const std::vector<double> wx = axis_weights(per, p->nx, pc.nx, cf, we.data(), we.data() + p->nx);
+  const std::vector<double> wy = axis_weights(per, p->ny, pc.ny, cf, we.data() + 2 * p->nx,
+                                              we.data() + 2 * p->nx + p->ny);
   std::vector<double> st(p->nt);
   for (int n = 0; n < p->nt; ++n) st[n] = (double)(n + 1) / cf;
   const std::vector<double> wt = spline_weights(pc.nt + 1, false, st);
   char* hst;
-  if ((rc = host_stage((wx.size() + wy.size() + wt.size()) * 8, &hst))) return rc;
-  std::memcpy(hst, wx.data(), wx.size() * 8);
-  std::memcpy(hst + wx.size() * 8, wy.data(), wy.size() * 8);
-  std::memcpy(hst + (wx.size() + wy.size()) * 8, wt.data(), wt.size() * 8);
+  const size_t nw = wx.size() + wy.size() + wt.size() + we.size();
+  if ((rc = host_stage(nw * 8, &hst))) return rc;
+  size_t at = 0;
+  for (const std::vector<double>* v : {&wx, &wy, &wt, (const std::vector<double>*)&we}) {
+    std::memcpy(hst + at, v->data(), v->size() * 8);
+    at += v->size() * 8;
+  }
   HIPCHK(hipMemcpyAsync(Wx, hst, wx.size() * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(Wy, hst + wx.size() * 8, wy.size() * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(Wt, hst + (wx.size() + wy.size()) * 8, wt.size() * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(We, hst + (wx.size() + wy.size() + wt.size()) * 8, we.size() * 8, hipMemcpyHostToDevice, s));
+  // Dirichlet data of the coarse problem and the ends of the spline lines
+  double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
+  if (!per && p->bdata) {
+    double* bdc = (double*)(w + L.bdc);
+    west_c = (double*)(w + L.edges);
+    east_c = west_c + (size_t)pc.nt * pc.ny;
+    south_f = east_c + (size_t)pc.nt * pc.ny;
+    north_f = south_f + (size_t)pc.nt * p->nx;
+    const int count = pc.nt * (2 * (pc.nx + pc.ny) + 2 * p->nx);
+    hipLaunchKernelGGL(k_cf_bdata, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p->bdata, p->nx, p->ny,
+                       pc.nx, pc.ny, cf, pc.nt, bdc, west_c, east_c, south_f, north_f);
+    pc.bdata = bdc;
+  }
   // coarse u^0 by injection, the plain coarse iterate, and the coarse solve (all-at-once
   // Newton: by Theorem 1 its root is the sequential coarse solution)
   const size_t nsc = (size_t)pc.nx * pc.ny;
@@ -2279,8 +2326,12 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
   if (rc) return rc;
   // splines: x (coarse rows -> T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V -> U[n])
   const long nx = p->nx, ny = p->ny, ns = nx * ny;
-  launch_interp(s, Wx, p->nx, pc.nx, Uc, pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1);
-  launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx);
+  // (x lines of row yc at level m end in west_c/east_c[m][yc]; y lines of column x in
+  // south_f/north_f[m][x])
+  launch_interp(s, Wx, p->nx, pc.nx, Uc, pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1, We,
+                We + p->nx, west_c, east_c, 1, 0);
+  launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx,
+                We + 2 * p->nx, We + 2 * p->nx + p->ny, south_f, north_f, nx, 1);
   launch_interp(s, Wt, p->nt, pc.nt + 1, V, 0, ns, 1, u0, U, 0, ns, 1, 1, ns);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

@@ -973,14 +973,53 @@ __global__ __launch_bounds__(256) void k_cf_inject(const double* __restrict__ u0
   u0c[i] = u0[(size_t)(yc * cf + off) * nx + (xc * cf + off)];
 }
 
+// Dirichlet data restricted to the coarse grid, for coarse levels m = 0..ntc-1 (fine level
+// (m+1) cf - 1, layout south, north, west, east per level): the coarse problem's data bdc,
+// its west and east parts as [m][yc] (the ends of the x lines), and the fine south and north
+// rows of the same levels as [m][x] (the ends of the y lines).
+__global__ __launch_bounds__(256) void k_cf_bdata(const double* __restrict__ bd, int nx, int ny, int nxc, int nyc,
+                                                  int cf, int ntc, double* __restrict__ bdc,
+                                                  double* __restrict__ west_c, double* __restrict__ east_c,
+                                                  double* __restrict__ south_f, double* __restrict__ north_f) {
+  const int nbc = 2 * (nxc + nyc), nbf = 2 * (nx + ny);
+  const int per_level = nbc + 2 * nx;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= ntc * per_level) return;
+  const int m = t / per_level, k = t % per_level;
+  const double* b = bd + (size_t)((m + 1) * cf - 1) * nbf;
+  if (k < nbc) {
+    double v;
+    if (k < nxc) {
+      v = b[(k + 1) * cf - 1];
+    } else if (k < 2 * nxc) {
+      v = b[nx + (k - nxc + 1) * cf - 1];
+    } else if (k < 2 * nxc + nyc) {
+      v = b[2 * nx + (k - 2 * nxc + 1) * cf - 1];
+      west_c[m * nyc + (k - 2 * nxc)] = v;
+    } else {
+      v = b[2 * nx + ny + (k - 2 * nxc - nyc + 1) * cf - 1];
+      east_c[m * nyc + (k - 2 * nxc - nyc)] = v;
+    }
+    bdc[(size_t)m * nbc + k] = v;
+  } else if (k < nbc + nx) {
+    south_f[(size_t)m * nx + (k - nbc)] = b[k - nbc];
+  } else {
+    north_f[(size_t)m * nx + (k - nbc - nx)] = b[nx + (k - nbc - nx)];
+  }
+}
+
 // One 1-D interpolation pass: out[a][i][b] = sum_k W[i][k] v_k[a][b] over the nc nodes of
-// the axis, v_k = in[a][k][b], or with in0 given v_0 = in0[b] and v_k = in[a][k - 1][b].
-// Strides in elements; one thread per output, b fastest (threads of a wave then share i and
-// read the weight row as uniform values).
+// the axis, v_k = in[a][k][b], or with in0 given v_0 = in0[b] and v_k = in[a][k - 1][b]; with
+// edge values given (Dirichlet lines) also + Wlo[i] elo[a][b] + Whi[i] ehi[a][b]. Strides in
+// elements; one thread per output, b fastest (threads of a wave then share i and read the
+// weight row as uniform values).
 __global__ __launch_bounds__(256) void k_interp_axis(const double* __restrict__ W, int nf, int nc,
                                                      const double* __restrict__ in, long isa, long isk, long isb,
                                                      const double* __restrict__ in0, double* __restrict__ out,
-                                                     long osa, long osi, long osb, long na, long nb) {
+                                                     long osa, long osi, long osb, long na, long nb,
+                                                     const double* __restrict__ Wlo, const double* __restrict__ Whi,
+                                                     const double* __restrict__ elo, const double* __restrict__ ehi,
+                                                     long esa, long esb) {
   const long total = na * nf * nb;
   for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
     const long b = t % nb, r = t / nb;
@@ -991,6 +1030,11 @@ __global__ __launch_bounds__(256) void k_interp_axis(const double* __restrict__ 
     double acc = in0 ? w[0] * in0[b] : 0.0;
     const long base = a * isa + b * isb;
     for (int k = k0; k < nc; ++k) acc = fma(w[k], in[base + (long)(k - k0) * isk], acc);
+    if (elo) {
+      const long e = a * esa + b * esb;
+      acc = fma(Wlo[i], elo[e], acc);
+      acc = fma(Whi[i], ehi[e], acc);
+    }
     out[a * osa + (long)i * osi + b * osb] = acc;
   }
 }

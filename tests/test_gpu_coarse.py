@@ -67,3 +67,52 @@ def test_coarse_iterate_rejects_sizes_cf_does_not_divide():
         P.coarse_initial_iterate(p, U, dev(p.u0), 3)  # 3 divides neither 32 nor 8
     with pytest.raises(P.PTSError):
         P.coarse_initial_iterate(p, U, dev(p.u0), 16)  # 2 coarse nodes per direction
+
+
+def _mms(kind, nint, nt):
+    import dataclasses
+    if kind == "heat":
+        p = W.heat_mms(nint)
+        ex = lambda x, y, t: W.heat_exact(x, y, t)
+    else:
+        p = W.burgers_mms(nint, x0=-0.5, y0=-0.5)
+        ex = lambda x, y, t: W.burgers_exact(x, y, t)
+    p = dataclasses.replace(p, nt=nt, dt=1.0 / nt, bdata=W.boundary_data(p, ex, [(n + 1) / nt for n in range(nt)]))
+    return p, ex
+
+
+# (The Section 8.2 Burgers problem is not a case here: at its step sizes tau |u| / h reaches 5,
+# the blocks are not diagonally dominant and the Jacobi-preconditioned level solves refuse them.)
+@pytest.mark.parametrize("kind,nint,nt,cf", [("heat", 64, 8, 4), ("heat", 64, 8, 2)])
+def test_coarse_iterate_with_dirichlet_data_matches_oracle(kind, nint, nt, cf):
+    """Section 8.1 exact-solution problem (nonzero Dirichlet data; the paper's c_f = 4, and 2)."""
+    p, _ = _mms(kind, nint, nt)
+    U = torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda")
+    print(f"[coarse] {kind} mms {nint} x {nt} cf {cf}", flush=True)
+    P.coarse_initial_iterate(p, U, dev(p.u0), cf, tol=1e-13, bdata=dev(p.bdata))
+    Ug, _ = coarse.coarse_initial_iterate(p, cf)
+    err = np.max(np.abs(host(U) - Ug)) / np.max(np.abs(Ug))
+    assert err <= 1e-10, err
+
+
+def test_table3_newton_counts_from_the_coarse_start():
+    """Section 8.1, Table 3: from the coarse-grid start (c_f = 4) ParaDIn needs 3 Newton
+    iterations at N_t = 4 and 2 at N_t = 8, 16, 24, 32 (64 x 64 intervals) to bring the RMS
+    update norm below a tenth of the discretization error. Reproduced for N_t = 8..32; at
+    N_t = 4 (one coarse level) this start needs 2 where the paper prints 3 (the first update
+    is 4.4e-5, the second 8.6e-10, against a tolerance of 4.8e-7)."""
+    counts = []
+    for nt in (4, 8, 16, 24, 32):
+        p, ex = _mms("heat", 64, nt)
+        bd, u0 = dev(p.bdata), dev(p.u0)
+        U = torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        print(f"[coarse] table 3, N_t = {nt}", flush=True)
+        P.coarse_initial_iterate(p, U, u0, 4, tol=1e-12, bdata=bd)
+        st = P.solve(p, U, u0, tol=1e-12, max_iter=8, bdata=bd, schedule="bulk")
+        X, Y = p.mesh()
+        exact = np.stack([ex(X, Y, (n + 1) * p.dt) for n in range(p.nt)])
+        err = np.max(np.abs(host(U) - exact))
+        k = next(k + 1 for k, r in enumerate(st["upd_rms"]) if r <= 0.1 * err)
+        counts.append(k)
+    print("Newton iterations", counts)
+    assert counts[1:] == [2, 2, 2, 2] and counts[0] <= 3, counts

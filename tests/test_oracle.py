@@ -281,13 +281,12 @@ def _sample(p, f, t):
 
 @pytest.mark.parametrize("bc,f", [
     ("periodic", lambda x, y, t: (1.0 + 2.0 * t) * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.3),
-    # sin(pi x) sin(pi y): zero at the edges and zero second derivative there (natural ends exact)
     ("dirichlet", lambda x, y, t: (1.0 - t) * np.sin(np.pi * x) * np.sin(np.pi * y)),
 ])
 def test_coarse_interpolation_is_fourth_order_and_exact_at_coarse_nodes(bc, f):
     """Cubic splines: interpolation property at coarse nodes, and the error on smooth data falls
-    16-fold per halving of the coarse spacing (O(h^4)); data linear in t is interpolated in
-    time without error, so the error is the spatial one."""
+    at least 12-fold per halving of the coarse spacing (O(h^4)); data linear in t is interpolated
+    in time without error, so the error is the spatial one."""
     from oracle import coarse
     errs = []
     for n in ((32, 64) if bc == "periodic" else (31, 63)):
@@ -304,8 +303,8 @@ def test_coarse_interpolation_is_fourth_order_and_exact_at_coarse_nodes(bc, f):
         for m in range(pc.nt):
             np.testing.assert_allclose(U[(m + 1) * cf - 1][sl][:pc.ny, :pc.nx], Uc[m], rtol=0, atol=1e-13)
         errs.append(np.max(np.abs(U - exact)))
-    ratio = errs[0] / errs[1]
-    assert 12.0 < ratio < 20.0, (errs, ratio)
+    ratio = errs[0] / errs[1]  # about 16 for O(h^4); an O(h^2) or O(h) defect gives 4 or 2
+    assert ratio > 12.0, (errs, ratio)
     assert errs[1] < 2e-4, errs
 
 
@@ -336,4 +335,41 @@ def test_coarse_initial_iterate_is_close_to_the_solution():
     Uo, _ = sequential.solve_sequential(p)
     e_coarse = np.max(np.abs(Ug - Uo))
     e_plain = np.max(np.abs(p.plain_iterate() - Uo))
+    assert e_coarse < 0.1 * e_plain, (e_coarse, e_plain)
+
+
+def test_coarse_interpolation_with_dirichlet_data_reproduces_cubic_fields():
+    """Not-a-knot cubic splines reproduce cubic data exactly: with u = 1 + x^3 + 2y^2 - x y + 3t
+    - t^2 on the grid and its boundary, every fine node and level is recovered (the edge values
+    enter the x lines from the coarse west/east data and the y lines from the fine south/north
+    data; natural ends, or a dropped edge, would leave an error)."""
+    from oracle import coarse
+    f = lambda x, y, t: 1.0 + x ** 3 + 2.0 * y ** 2 - x * y + 3.0 * t - t ** 2
+    p = W.heat_dirichlet(23, 12, 1e-2, np.zeros((23, 23)))
+    X, Y = p.mesh()
+    p = dataclasses.replace(p, u0=f(X, Y, 0.0),
+                            bdata=W.boundary_data(p, f, [(n + 1) * p.dt for n in range(p.nt)]))
+    pc = coarse.coarse_problem(p, 4)
+    assert pc.bdata.shape == (3, 2 * (pc.nx + pc.ny))
+    np.testing.assert_allclose(pc.bdata, W.boundary_data(pc, f, [(m + 1) * pc.dt for m in range(pc.nt)]),
+                               rtol=0, atol=1e-14)
+    Xc, Yc = pc.mesh()
+    Uc = np.stack([f(Xc, Yc, (m + 1) * pc.dt) for m in range(pc.nt)])
+    U = coarse.interpolate(p, 4, Uc)
+    exact = np.stack([f(X, Y, (n + 1) * p.dt) for n in range(p.nt)])
+    np.testing.assert_allclose(U, exact, rtol=0, atol=1e-12)
+
+
+def test_coarse_start_of_the_heat_exact_solution_problem():
+    """Section 8.1 problem (64 intervals, 8 levels, c_f = 4 as in the paper): the coarse start
+    is far closer to the exact solution than the plain start."""
+    from oracle import coarse
+    p = W.heat_mms(64)
+    p = dataclasses.replace(p, nt=8, dt=1.0 / 8, bdata=W.boundary_data(
+        p, lambda x, y, t: W.heat_exact(x, y, t), [(n + 1) / 8 for n in range(8)]))
+    Ug, _ = coarse.coarse_initial_iterate(p, 4)
+    X, Y = p.mesh()
+    exact = np.stack([W.heat_exact(X, Y, (n + 1) * p.dt) for n in range(p.nt)])
+    e_coarse = np.max(np.abs(Ug - exact))
+    e_plain = np.max(np.abs(p.plain_iterate() - exact))
     assert e_coarse < 0.1 * e_plain, (e_coarse, e_plain)
