@@ -746,6 +746,28 @@ struct StageCache {
 thread_local StageCache g_stage_cache;
 int ctag(const pts_options* o) { return o ? o->cache_tag : 0; }
 
+// Inner plan and stage count of the next wavefront sequence after `it` Newton steps: explicit
+// options, else the cached entry (ce, may be NULL), else the cheapest plan that reaches lin_tol
+// (default 1e-4: the wavefront runs inexact Newton steps) for the radius rho. K: options, else
+// the steps the cached entry still expects, else 4; at most max_iter - it. False when no plan
+// reaches the reduction.
+bool next_wave_plan(const pts_problem* p, const pts_options* o, const StageCache::E* ce, double rho, int it,
+                    int max_iter, Plan* pl, int* K) {
+  const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
+  const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
+  if (ce && !explicit_inner && ce->sweeps > 0) {
+    pl->fp32 = p->precision == PTS_MIXED;
+    pl->sweeps = ce->sweeps;
+    pl->passes = ce->passes;
+    pl->packs = {pl->passes};
+  } else if (!make_wave_plan(p, o, std::min(rho * 1.02, 0.999), lin_tol, pl)) {
+    return false;
+  }
+  int k = (o && o->stages > 0) ? o->stages : (ce && ce->steps > it ? ce->steps - it : 4);
+  *K = std::max(1, std::min(std::min(k, kMaxStages), max_iter - it));
+  return true;
+}
+
 // Executable graph of one wavefront sequence, reused while the launch arguments match.
 struct WaveGraph {
   hipGraphExec_t exec = nullptr;
@@ -974,23 +996,9 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
       if (profiling) prof.collect(st);
       return fail(PTS_ERR_NOT_CONVERGED, "not converged after %d Newton steps (|R| = %.3e)", it, res);
     }
-    // inner plan: explicit options, else the autotuned entry, else the cheapest plan that
-    // reaches lin_tol (default 1e-4: the wavefront runs inexact Newton steps)
     Plan pl;
-    const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
-    const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
-    const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
-    bool ok;
-    if (ce && !explicit_inner && ce->sweeps > 0) {
-      pl.fp32 = p->precision == PTS_MIXED;
-      pl.sweeps = ce->sweeps;
-      pl.passes = ce->passes;
-      pl.packs = {pl.passes};
-      ok = true;
-    } else {
-      ok = make_wave_plan(p, o, std::min(rhom * 1.02, 0.999), lin_tol, &pl);
-    }
-    if (!ok) {
+    int K = 1;
+    if (!next_wave_plan(p, o, g_stage_cache.find(p, tol, ctag(o)), rhom, it, max_iter, &pl, &K)) {
       if (it == 0) {
         *fallback = true;
         return PTS_ERR_INVALID_ARG;
@@ -998,8 +1006,6 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
       return fail(PTS_ERR_SINGULAR, "inner solve cannot reach the requested reduction (radius %.3g)", rhom);
     }
     const Geo g = in.g.whole ? in.g : geometry(p, wave_halo(pl));
-    int K = (o && o->stages > 0) ? o->stages : (ce && ce->steps > it ? ce->steps - it : 4);
-    K = std::max(1, std::min(std::min(K, kMaxStages), max_iter - it));
     plan_used = pl;
     if (st) {
       st->sweeps = pl.sweeps;
@@ -1835,24 +1841,13 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
       }
     }
     if (act.empty()) break;
-    // inner plan and stage count as for one instance (explicit options, else the
-    // autotuned entry of the problem, else the cheapest plan reaching lin_tol)
+    // inner plan and stage count as for one instance, from the batch entry of the problem
+    // (else its one-instance entry) and the largest radius of the active instances
     Plan pl;
-    const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-4;
+    int K = 1;
     const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o), 1);
     if (!ce) ce = g_stage_cache.find(p, tol, ctag(o), 0);
-    const bool explicit_inner = o && (o->sweeps > 0 || o->refine > 0 || o->lin_tol > 0);
-    bool ok;
-    if (ce && !explicit_inner && ce->sweeps > 0) {
-      pl.fp32 = p->precision == PTS_MIXED;
-      pl.sweeps = ce->sweeps;
-      pl.passes = ce->passes;
-      pl.packs = {pl.passes};
-      ok = true;
-    } else {
-      ok = make_wave_plan(p, o, std::min(rho_all * 1.02, 0.999), lin_tol, &pl);
-    }
-    if (!ok) {
+    if (!next_wave_plan(p, o, ce, rho_all, it, max_iter, &pl, &K)) {
       if (it == 0) {
         *fallback = true;
         return PTS_ERR_INVALID_ARG;
@@ -1862,8 +1857,6 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
       break;
     }
     const Geo g = in[0].g.whole ? in[0].g : geometry(p, wave_halo(pl));
-    int K = (o && o->stages > 0) ? o->stages : (ce && ce->steps > it ? ce->steps - it : 4);
-    K = std::max(1, std::min(std::min(K, kMaxStages), max_iter - it));
     plan_used = pl;
     const int tl = tiles(p, g);
     const int nb = (int)act.size();
