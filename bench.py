@@ -304,11 +304,17 @@ def bench_learned(args):
         side = [torch.cuda.Stream(device=dev) for _ in range(NS)]
         net_ws = [net.workspace(dev) for _ in range(NS)]
         judge_ws = [P.workspace(prob, "fp64", dev) for _ in range(NS)]
+        # one workspace per precision for every batched call (the captured graphs hold its address)
+        ws_b = {pr: P.batched_workspace(probs_b, pr, dev) for pr in ("fp64", "mixed")}
+        cws_b = P.coarse_workspace_batched(prob, cf, EB, dev) if cf > 1 else None
 
         def start_all(kind, report=False):
             if kind == "plain":
                 for j in range(EB):
                     P.init_plain(prob, U_b[j], u0_b[j])
+                return []
+            if kind == "coarse":  # the coarse solves of the batch share batched launches
+                P.coarse_initial_iterate_batched(prob, U_b, u0_b, cf, tol=tol, ws=cws_b)
                 return []
             cur = torch.cuda.current_stream()
             for sd in side:
@@ -319,32 +325,41 @@ def bench_learned(args):
                 cur.wait_stream(sd)
             return out
 
-        for kind in ("plain", "learned"):
-            tag = 1 if kind == "learned" else 0
+        for kind in ("plain", "learned") + (("coarse",) if cf > 1 else ()):
+            tag = {"plain": 0, "learned": 1, "coarse": 2}[kind]
             for pr in ("fp64", "mixed"):
                 if not args.no_autotune:
                     start_all(kind)
-                    P.autotune_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
+                    P.autotune_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag,
+                                       ws=ws_b[pr])
                 # untimed batch: settles the stage count for the batch and measures the errors
                 chosen = start_all(kind, report=True)
-                sts = P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
+                sts = P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag,
+                                      ws=ws_b[pr])
                 errs = [float((U_b[j] - refs_b[j]).abs().max() / refs_b[j].abs().max()) for j in range(EB)]
                 needed = [st["needed"] for st in sts]
                 torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                for _ in range(args.batch_reps):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.batch_reps)]
+                rep_steps = []
+                for r in range(args.batch_reps):
+                    ev[3 * r].record()
                     start_all(kind)
-                    P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag)
-                e1.record()
+                    ev[3 * r + 1].record()
+                    stt = P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision=pr, cache_tag=tag,
+                                          ws=ws_b[pr])
+                    ev[3 * r + 2].record()
+                    rep_steps.append(max(st["iterations"] for st in stt))
                 torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / args.batch_reps
+                ms = sum(ev[3 * r].elapsed_time(ev[3 * r + 2]) for r in range(args.batch_reps)) / args.batch_reps
+                start_ms = sum(ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(args.batch_reps)) / args.batch_reps
                 key = f"{kind}_{pr}"
-                batched[key] = {"ms_per_batch": ms, "ms_per_solve": ms / EB,
+                batched[key] = {"ms_per_batch": ms, "ms_per_solve": ms / EB, "start_ms_per_batch": start_ms,
+                                "newton_steps_timed": rep_steps,
                                 "dof_per_s": EB * prob.dof / (ms * 1e-3),
                                 "newton_steps_needed_mean": float(np.mean(needed)),
                                 "newton_steps_applied": sts[0]["iterations"],
                                 "schedule": sts[0]["schedule"], "sweeps": sts[0]["sweeps"],
+                                "passes": sts[0]["refine"] + 1, "launches": stt[0]["launches"],
                                 "max_rel_err_vs_fp64_reference": max(errs)}
                 if kind == "learned":
                     batched[key]["judge_picked_learned"] = [c["chosen"] for c in chosen].count("learned") / EB

@@ -265,6 +265,18 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
                                double tol, int max_iter, void* workspace,
                                size_t workspace_bytes, pts_stats* stats, pts_stream_t stream);
 
+/* The coarse-grid start of nprob instances of the problem p (one description; the
+   instances differ in u0[i] and receive U[i], device arrays): the coarse problems
+   share batched wavefront launches (pts_solve_batched) and the interpolation weights.
+   workspace: pts_coarse_workspace_bytes_batched(p, cf, nprob) bytes, 256-byte aligned;
+   stats: host array of nprob entries or NULL. Errors as pts_coarse_initial_iterate (an
+   instance's coarse solve error is returned as pts_solve_batched returns it). */
+size_t pts_coarse_workspace_bytes_batched(const pts_problem* p, int cf, int nprob);
+int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf,
+                                       const double* const* u0, double* const* U, double tol,
+                                       int max_iter, void* workspace, size_t workspace_bytes,
+                                       pts_stats* stats, pts_stream_t stream);
+
 /* Section 7, Eq. (cond): largest number of levels W whose product of blocks
    keeps the estimated condition number K^W below c h^4 / eps, with
    K = (1 + 8 mu tau/h^2)/(1 + 2 pi^2 mu tau). If tau <= 0 the paper's setting

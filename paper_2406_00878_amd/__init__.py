@@ -24,7 +24,8 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, 
                    pts_stats)
 
 __all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve", "autotune",
-           "solve_batched", "autotune_batched", "coarse_workspace", "coarse_initial_iterate", "window_bound",
+           "solve_batched", "autotune_batched", "batched_workspace", "coarse_workspace", "coarse_initial_iterate",
+           "coarse_workspace_batched", "coarse_initial_iterate_batched", "window_bound",
            "library_path", "version"]
 
 
@@ -205,29 +206,44 @@ def autotune(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", 
             "slab": st.slab}
 
 
-def _batched_args(probs, Us, u0s, bdatas, precision):
+def _aligned_bytes(nbytes, device):
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + nbytes]
+
+
+def batched_workspace(probs, precision="fp64", device="cuda", bdatas=None) -> torch.Tensor:
+    """Device workspace of solve_batched / autotune_batched for these instances. Reusing one
+    across calls keeps the captured wavefront graphs valid (they hold its address)."""
+    n = len(probs)
+    bdatas = bdatas or [None] * n
+    arr = (pts_problem * n)(*[make_problem(q, precision, b) for q, b in zip(probs, bdatas)])
+    nbytes = _lib_checked().pts_workspace_bytes_batched(arr, n)
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    return _aligned_bytes(nbytes, device)
+
+
+def _batched_args(probs, Us, u0s, bdatas, precision, ws):
     n = len(probs)
     bdatas = bdatas or [None] * n
     arr = (pts_problem * n)(*[make_problem(q, precision, b) for q, b in zip(probs, bdatas)])
     for q, U, u0 in zip(probs, Us, u0s):
         _dev_f64(U, (q.nt, q.ny, q.nx), "U")
         _dev_f64(u0, (q.ny, q.nx), "u0")
-    nbytes = _lib_checked().pts_workspace_bytes_batched(arr, n)
-    if nbytes == 0:
-        _check(_lib.PTS_ERR_INVALID_ARG)
-    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=Us[0].device)
-    off = (-raw.data_ptr()) % 256
-    ws = raw[off:off + nbytes]
+    if ws is None:
+        ws = batched_workspace(probs, precision, Us[0].device, bdatas)
     uptr = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
     u0ptr = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
     return arr, ws, uptr, u0ptr
 
 
-def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
+def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None, ws=None,
                   **opts):
-    """Solve independent instances together; returns one statistics dict per instance."""
+    """Solve independent instances together; returns one statistics dict per instance.
+    ws: a batched_workspace (allocated per call when None)."""
     n = len(probs)
-    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision)
+    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision, ws)
     o = _options(**opts)
     sts = (pts_stats * n)()
     rc = _lib_checked().pts_solve_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws), ws.numel(),
@@ -240,11 +256,11 @@ def solve_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision
 
 
 def autotune_batched(probs, Us, u0s, tol=1e-12, max_iter=50, bdatas=None, precision="fp64", stream=None,
-                     **opts) -> dict:
+                     ws=None, **opts) -> dict:
     """Pick the fastest wavefront plan for batches of one problem (Us restored); returns the
-    chosen plan (sweeps, refine, iterations, solve_ms)."""
+    chosen plan (sweeps, refine, iterations, solve_ms). ws: as for solve_batched."""
     n = len(probs)
-    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision)
+    arr, ws, uptr, u0ptr = _batched_args(probs, Us, u0s, bdatas, precision, ws)
     o = _options(**opts)
     sts = (pts_stats * n)()
     _check(_lib_checked().pts_autotune_batched(arr, n, uptr, u0ptr, float(tol), int(max_iter), _ptr(ws),
@@ -276,6 +292,35 @@ def coarse_initial_iterate(prob, U, u0, cf, tol=1e-12, max_iter=50, ws=None, bda
                                                      int(max_iter), _ptr(ws), ws.numel(), C.byref(st),
                                                      _stream(stream)))
     return _stats_dict(st)
+
+
+def coarse_workspace_batched(prob, cf, n, device="cuda") -> torch.Tensor:
+    """Device workspace of coarse_initial_iterate_batched for n instances of `prob`."""
+    p = make_problem(prob)
+    nbytes = _lib_checked().pts_coarse_workspace_bytes_batched(C.byref(p), int(cf), int(n))
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    return _aligned_bytes(nbytes, device)
+
+
+def coarse_initial_iterate_batched(prob, Us, u0s, cf, tol=1e-12, max_iter=50, bdata=None, ws=None,
+                                   stream=None) -> list:
+    """The coarse-grid start of several instances of one problem (different u^0): the coarse
+    solves share batched launches. Returns the coarse solves' statistics. ws: a
+    coarse_workspace_batched (allocated per call when None)."""
+    n = len(Us)
+    p = make_problem(prob, "fp64", bdata)
+    for U, u0 in zip(Us, u0s):
+        _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+        _dev_f64(u0, (p.ny, p.nx), "u0")
+    lib = _lib_checked()
+    ws = coarse_workspace_batched(prob, cf, n, Us[0].device) if ws is None else ws
+    uptr = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
+    u0ptr = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
+    sts = (pts_stats * n)()
+    _check(lib.pts_coarse_initial_iterate_batched(C.byref(p), n, int(cf), u0ptr, uptr, float(tol), int(max_iter),
+                                                  _ptr(ws), ws.numel(), sts, _stream(stream)))
+    return [_stats_dict(s) for s in sts]
 
 
 def window_bound(h, mu, tau=0.0, c=1.0, eps=1e-16, wmax=100000) -> int:

@@ -68,6 +68,8 @@ def load():
         "pts_autotune_batched": (I, [P, I, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_coarse_workspace_bytes": (S, [P, I]),
         "pts_coarse_initial_iterate": (I, [P, I, V, V, D, I, V, S, C.POINTER(pts_stats), V]),
+        "pts_coarse_workspace_bytes_batched": (S, [P, I, I]),
+        "pts_coarse_initial_iterate_batched": (I, [P, I, I, V, V, D, I, V, S, C.POINTER(pts_stats), V]),
         "pts_window_bound": (I, [D, D, D, D, D, I]),
         "pts_last_error": (C.c_char_p, []),
         "pts_version": (C.c_char_p, []),

@@ -2156,10 +2156,18 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
   return validate(pc);
 }
 
+// Workspace of the coarse start of nprob instances of one problem: the coarse solve's (one
+// instance: pts_solve's; several: pts_solve_batched's), each instance's coarse iterate and
+// u^0, and the interpolation buffers and weights the instances share (used one after another).
 struct CoarseLayout {
   size_t solver, Uc, u0c, T1, V, Wx, Wy, Wt, We, bdc, edges, total;
 };
-CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc) {
+size_t coarse_solver_bytes(const pts_problem* pc, int nprob) {
+  if (nprob == 1) return layout(pc).total;
+  const std::vector<pts_problem> pcs(nprob, *pc);
+  return batch_header_bytes(pcs.data(), nprob) + (size_t)nprob * layout(pc).total;
+}
+CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc, int nprob = 1) {
   CoarseLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -2168,9 +2176,9 @@ CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc) {
     return at;
   };
   const size_t nsc = (size_t)pc->nx * pc->ny;
-  L.solver = take(layout(pc).total);
-  L.Uc = take(nsc * pc->nt * 8);
-  L.u0c = take(nsc * 8);
+  L.solver = take(coarse_solver_bytes(pc, nprob));
+  L.Uc = take((size_t)nprob * align_up(nsc * pc->nt * 8));
+  L.u0c = take((size_t)nprob * align_up(nsc * 8));
   L.T1 = take((size_t)pc->nt * pc->ny * p->nx * 8);
   L.V = take((size_t)pc->nt * p->ny * p->nx * 8);
   L.Wx = take((size_t)p->nx * pc->nx * 8);
@@ -2242,30 +2250,46 @@ int pts_window_bound(double h, double mu, double tau, double c, double eps, int 
   return best;
 }
 
-size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf) {
-  if (validate(p)) return 0;
+size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf) { return pts_coarse_workspace_bytes_batched(p, cf, 1); }
+
+size_t pts_coarse_workspace_bytes_batched(const pts_problem* p, int cf, int nprob) {
+  if (validate(p) || nprob < 1) return 0;
   pts_problem pc;
   if (coarse_problem(p, cf, &pc)) return 0;
-  return coarse_layout(p, &pc).total;
+  return coarse_layout(p, &pc, nprob).total;
 }
 
 int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, double* U, double tol, int max_iter,
                                void* workspace, size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
-  if (stats) std::memset(stats, 0, sizeof *stats);
+  return pts_coarse_initial_iterate_batched(p, 1, cf, &u0, &U, tol, max_iter, workspace, workspace_bytes, stats,
+                                            stream);
+}
+
+int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, const double* const* u0,
+                                       double* const* U, double tol, int max_iter, void* workspace,
+                                       size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
+  if (stats && nprob > 0) std::memset(stats, 0, (size_t)nprob * sizeof(pts_stats));
   int rc = validate(p);
   if (rc) return rc;
+  if (nprob < 1) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: no instances");
   pts_problem pc;
   if ((rc = coarse_problem(p, cf, &pc))) return rc;
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_coarse_initial_iterate: NULL array");
+  for (int i = 0; i < nprob; ++i)
+    if (!U[i] || !u0[i]) return fail(PTS_ERR_INVALID_ARG, "pts_coarse_initial_iterate: instance %d: NULL array", i);
   if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
-  const CoarseLayout L = coarse_layout(p, &pc);
+  const CoarseLayout L = coarse_layout(p, &pc, nprob);
   if (!workspace || workspace_bytes < L.total)
     return fail(PTS_ERR_WORKSPACE, "coarse workspace %zu bytes < required %zu", workspace_bytes, L.total);
   if ((uintptr_t)workspace % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
-  double* Uc = (double*)(w + L.Uc);
-  double* u0c = (double*)(w + L.u0c);
+  const size_t nsc = (size_t)pc.nx * pc.ny;
+  std::vector<double*> Uc(nprob), u0c(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    Uc[i] = (double*)(w + L.Uc + (size_t)i * align_up(nsc * pc.nt * 8));
+    u0c[i] = (double*)(w + L.u0c + (size_t)i * align_up(nsc * 8));
+  }
   double* T1 = (double*)(w + L.T1);
   double* V = (double*)(w + L.V);
   double* Wx = (double*)(w + L.Wx);
@@ -2282,19 +2306,19 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
   std::vector<double> st(p->nt);
   for (int n = 0; n < p->nt; ++n) st[n] = (double)(n + 1) / cf;
   const std::vector<double> wt = spline_weights(pc.nt + 1, false, st);
-  char* hst;
-  const size_t nw = wx.size() + wy.size() + wt.size() + we.size();
-  if ((rc = host_stage(nw * 8, &hst))) return rc;
-  size_t at = 0;
-  for (const std::vector<double>* v : {&wx, &wy, &wt, (const std::vector<double>*)&we}) {
-    std::memcpy(hst + at, v->data(), v->size() * 8);
-    at += v->size() * 8;
+  {
+    // staged in a pinned buffer of this call's own: the coarse solve below reuses the shared one
+    std::vector<double> all;
+    for (const std::vector<double>* v : {&wx, &wy, &wt, (const std::vector<double>*)&we})
+      all.insert(all.end(), v->begin(), v->end());
+    HIPCHK(hipMemcpyAsync(Wx, all.data(), wx.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(Wy, all.data() + wx.size(), wy.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(Wt, all.data() + wx.size() + wy.size(), wt.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(We, all.data() + wx.size() + wy.size() + wt.size(), we.size() * 8, hipMemcpyHostToDevice,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before `all` goes
   }
-  HIPCHK(hipMemcpyAsync(Wx, hst, wx.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(Wy, hst + wx.size() * 8, wy.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(Wt, hst + (wx.size() + wy.size()) * 8, wt.size() * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(We, hst + (wx.size() + wy.size() + wt.size()) * 8, we.size() * 8, hipMemcpyHostToDevice, s));
-  // Dirichlet data of the coarse problem and the ends of the spline lines
+  // Dirichlet data of the coarse problem and the ends of the spline lines (shared)
   double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
   if (!per && p->bdata) {
     double* bdc = (double*)(w + L.bdc);
@@ -2307,25 +2331,35 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
                        pc.nx, pc.ny, cf, pc.nt, bdc, west_c, east_c, south_f, north_f);
     pc.bdata = bdc;
   }
-  // coarse u^0 by injection, the plain coarse iterate, and the coarse solve (all-at-once
-  // Newton: by Theorem 1 its root is the sequential coarse solution)
-  const size_t nsc = (size_t)pc.nx * pc.ny;
-  hipLaunchKernelGGL(k_cf_inject, dim3((unsigned)((nsc + 255) / 256)), dim3(256), 0, s, u0, p->nx, pc.nx, pc.ny, cf,
-                     per ? 0 : cf - 1, u0c);
+  // coarse u^0 by injection and the plain coarse iterates
   const unsigned bb = (unsigned)std::min<size_t>((nsc * pc.nt + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_broadcast, dim3(bb), dim3(256), 0, s, nsc, pc.nt, Uc, (const double*)u0c);
+  for (int i = 0; i < nprob; ++i) {
+    hipLaunchKernelGGL(k_cf_inject, dim3((unsigned)((nsc + 255) / 256)), dim3(256), 0, s, u0[i], p->nx, pc.nx,
+                       pc.ny, cf, per ? 0 : cf - 1, u0c[i]);
+    hipLaunchKernelGGL(k_broadcast, dim3(bb), dim3(256), 0, s, nsc, pc.nt, Uc[i], (const double*)u0c[i]);
+  }
   HIPCHK(hipGetLastError());
-  rc = solve_slabs(&pc, Uc, u0c, tol, max_iter, w + L.solver, nullptr, stats, s);
+  // the coarse solves (all-at-once Newton: by Theorem 1 the root is the sequential coarse
+  // solution); several instances share batched wavefront launches
+  if (nprob == 1) {
+    rc = solve_slabs(&pc, Uc[0], u0c[0], tol, max_iter, w + L.solver, nullptr, stats, s);
+  } else {
+    const std::vector<pts_problem> pcs(nprob, pc);
+    rc = pts_solve_batched(pcs.data(), nprob, Uc.data(), (const double* const*)u0c.data(), tol, max_iter,
+                           w + L.solver, coarse_solver_bytes(&pc, nprob), nullptr, stats, stream);
+  }
   if (rc) return rc;
-  // splines: x (coarse rows -> T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V -> U[n])
+  // splines per instance: x (coarse rows -> T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V ->
+  // U[n]); x lines of row yc at level m end in west_c/east_c[m][yc], y lines of column x in
+  // south_f/north_f[m][x]. The instances reuse T1 and V in stream order.
   const long nx = p->nx, ny = p->ny, ns = nx * ny;
-  // (x lines of row yc at level m end in west_c/east_c[m][yc]; y lines of column x in
-  // south_f/north_f[m][x])
-  launch_interp(s, Wx, p->nx, pc.nx, Uc, pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1, We,
-                We + p->nx, west_c, east_c, 1, 0);
-  launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx,
-                We + 2 * p->nx, We + 2 * p->nx + p->ny, south_f, north_f, nx, 1);
-  launch_interp(s, Wt, p->nt, pc.nt + 1, V, 0, ns, 1, u0, U, 0, ns, 1, 1, ns);
+  for (int i = 0; i < nprob; ++i) {
+    launch_interp(s, Wx, p->nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1, We,
+                  We + p->nx, west_c, east_c, 1, 0);
+    launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx,
+                  We + 2 * p->nx, We + 2 * p->nx + p->ny, south_f, north_f, nx, 1);
+    launch_interp(s, Wt, p->nt, pc.nt + 1, V, 0, ns, 1, u0[i], U[i], 0, ns, 1, 1, ns);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return PTS_OK;

@@ -116,3 +116,26 @@ def test_table3_newton_counts_from_the_coarse_start():
         counts.append(k)
     print("Newton iterations", counts)
     assert counts[1:] == [2, 2, 2, 2] and counts[0] <= 3, counts
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_batched_coarse_start_equals_one_by_one(bc):
+    """Several instances of one problem: the coarse solves share batched launches; each start
+    equals the one-instance start (to the coarse solve's tolerance) and the oracle's."""
+    rng = np.random.default_rng(81)
+    if bc == "periodic":
+        probs = [W.burgers_periodic(64, 8, 5e-4, 0.01, W.fourier_u0_periodic(64, 82 + k, kmax=4)) for k in range(3)]
+    else:
+        probs = [W.heat_dirichlet(31, 8, 1e-3, W.sine_u0_dirichlet(31, rng)) for _ in range(3)]
+    Us = [torch.empty((q.nt, q.ny, q.nx), dtype=torch.float64, device="cuda") for q in probs]
+    u0s = [dev(q.u0) for q in probs]
+    print(f"[coarse] batched {bc}", flush=True)
+    sts = P.coarse_initial_iterate_batched(probs[0], Us, u0s, 4, tol=1e-13)
+    assert all(st["converged"] for st in sts), sts
+    for q, U, u0 in zip(probs, Us, u0s):
+        V = torch.empty_like(U)
+        P.coarse_initial_iterate(q, V, u0, 4, tol=1e-13)
+        a, b = host(U), host(V)
+        assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
+    Ug, _ = coarse.coarse_initial_iterate(probs[1], 4)
+    assert np.max(np.abs(host(Us[1]) - Ug)) <= 1e-10 * np.max(np.abs(Ug))
