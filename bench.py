@@ -19,6 +19,7 @@ Prints one JSON line. Run with --help for options.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -248,12 +249,15 @@ def bench_learned(args):
                 f"launches {st['launches']} steps needed {needed}")
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            gc.collect()
+            gc.disable()  # no collector pause inside the timed region
             e0.record()
             for k in range(args.steps):
                 j = k % E
                 start(kind, u0_eval[j], report=False)
                 P.solve(prob, U, u0_eval[j], tol=tol, max_iter=60, precision=pr, ws=ws[pr], cache_tag=tag)
             e1.record()
+            gc.enable()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
             key = f"{kind}_{pr}"
@@ -268,10 +272,13 @@ def bench_learned(args):
     # inference + judge alone
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()  # no collector pause inside the timed region
     e0.record()
     for k in range(args.steps):
         net.initial_iterate(prob, u0_eval[k % E], U, solver_ws=ws["fp64"], report=False)
     e1.record()
+    gc.enable()
     torch.cuda.synchronize()
     infer_ms = e0.elapsed_time(e1) / args.steps
     coarse_ms = None
@@ -341,6 +348,8 @@ def bench_learned(args):
                 torch.cuda.synchronize()
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.batch_reps)]
                 rep_steps = []
+                gc.collect()
+                gc.disable()  # no collector pause inside the timed repetitions
                 for r in range(args.batch_reps):
                     ev[3 * r].record()
                     start_all(kind)
@@ -350,11 +359,13 @@ def bench_learned(args):
                     ev[3 * r + 2].record()
                     rep_steps.append(max(st["iterations"] for st in stt))
                 torch.cuda.synchronize()
+                gc.enable()
                 ms = sum(ev[3 * r].elapsed_time(ev[3 * r + 2]) for r in range(args.batch_reps)) / args.batch_reps
                 start_ms = sum(ev[3 * r].elapsed_time(ev[3 * r + 1]) for r in range(args.batch_reps)) / args.batch_reps
                 key = f"{kind}_{pr}"
                 batched[key] = {"ms_per_batch": ms, "ms_per_solve": ms / EB, "start_ms_per_batch": start_ms,
                                 "newton_steps_timed": rep_steps,
+                                "rep_ms": [ev[3 * r].elapsed_time(ev[3 * r + 2]) for r in range(args.batch_reps)],
                                 "dof_per_s": EB * prob.dof / (ms * 1e-3),
                                 "newton_steps_needed_mean": float(np.mean(needed)),
                                 "newton_steps_applied": sts[0]["iterations"],
@@ -430,11 +441,14 @@ def bench_heatbatch(args):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()  # no collector pause inside the timed region
     e0.record()
     for k in range(args.steps):
         sts = step()
         log(f"solve {k + 1}/{args.steps} done")
     e1.record()
+    gc.enable()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     its = [st["iterations"] for st in sts]
@@ -537,11 +551,14 @@ def main():
         st = step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()  # no collector pause inside the timed region
     e0.record()
     stats = []
     for _ in range(args.steps):
         stats.append(step())
     e1.record()
+    gc.enable()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     st = stats[-1]
