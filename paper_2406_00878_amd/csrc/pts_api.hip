@@ -2114,22 +2114,81 @@ void spline_second(const std::vector<double>& y, bool periodic, std::vector<doub
   for (int z = 0; z < N; ++z) M[z] = x[z] - f * q[z];
 }
 
-// W[i][k] = w_k(s_i) for the spline through N nodes (not-a-knot ends or periodic).
-std::vector<double> spline_weights(int N, bool periodic, const std::vector<double>& s) {
-  std::vector<double> W(s.size() * (size_t)N), y(N, 0.0), M;
-  for (int k = 0; k < N; ++k) {
+// One axis of the interpolation as the kernels apply it: the second derivatives M = G y at
+// the N spline nodes (column j of G: the M of the spline through the j-th unit vector), then at
+// each fine point s_i (in node spacings) the value (1-t) y_z0 + t y_z1 + ((1-t)^3 - (1-t)) M_z0 / 6
+// + (t^3 - t) M_z1 / 6 on its interval (z0, z1), t = s_i - z0.
+struct AxisSpline {
+  int N = 0;
+  std::vector<double> G;    // [N][N]
+  std::vector<int> zz;      // [nf][2]
+  std::vector<double> w;    // [nf][4]
+};
+AxisSpline axis_spline(int N, bool periodic, const std::vector<double>& s) {
+  AxisSpline A;
+  A.N = N;
+  A.G.assign((size_t)N * N, 0.0);
+  std::vector<double> y(N), M;
+  for (int j = 0; j < N; ++j) {
     y.assign(N, 0.0);
-    y[k] = 1.0;
+    y[j] = 1.0;
     spline_second(y, periodic, M);
-    for (size_t i = 0; i < s.size(); ++i) {
-      int z0 = (int)std::floor(s[i]);
-      z0 = periodic ? ((z0 % N) + N) % N : std::max(0, std::min(z0, N - 2));
-      const int z1 = periodic ? (z0 + 1) % N : z0 + 1;
-      const double t = periodic ? s[i] - std::floor(s[i]) : s[i] - z0, a = 1.0 - t;
-      W[i * N + k] = a * y[z0] + t * y[z1] + ((a * a * a - a) * M[z0] + (t * t * t - t) * M[z1]) / 6.0;
-    }
+    for (int k = 0; k < N; ++k) A.G[(size_t)k * N + j] = M[k];
   }
-  return W;
+  for (double si : s) {
+    int z0 = (int)std::floor(si);
+    z0 = periodic ? ((z0 % N) + N) % N : std::max(0, std::min(z0, N - 2));
+    const int z1 = periodic ? (z0 + 1) % N : z0 + 1;
+    const double t = periodic ? si - std::floor(si) : si - z0, a = 1.0 - t;
+    A.zz.push_back(z0);
+    A.zz.push_back(z1);
+    for (double v : {a, t, (a * a * a - a) / 6.0, (t * t * t - t) / 6.0}) A.w.push_back(v);
+  }
+  return A;
+}
+
+// The spline of a spatial axis with n fine and nc coarse nodes: periodic (nodes = the coarse
+// nodes, fine node i at i / cf), or Dirichlet (nodes: edge, the coarse nodes, edge; fine node i
+// at (i + 1) / cf).
+AxisSpline space_spline(bool periodic, int n, int nc, int cf) {
+  std::vector<double> s(n);
+  for (int i = 0; i < n; ++i) s[i] = periodic ? (double)i / cf : (double)(i + 1) / cf;
+  return axis_spline(periodic ? nc : nc + 2, periodic, s);
+}
+
+// Device image of an AxisSpline for the kernels: G split into its inner columns [N][N - 2e]
+// (e = 1 for an axis with edge nodes) and its edge columns, then the weights and intervals.
+struct AxisDev {
+  size_t g, glo, ghi, w, zz, total;
+};
+AxisDev axis_dev_layout(int N, int nf, bool edges) {
+  AxisDev D;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  D.g = take((size_t)N * (N - (edges ? 2 : 0)) * 8);
+  D.glo = take((size_t)N * 8);
+  D.ghi = take((size_t)N * 8);
+  D.w = take((size_t)nf * 32);
+  D.zz = take((size_t)nf * 8);
+  D.total = o;
+  return D;
+}
+void axis_dev_fill(const AxisSpline& A, bool edges, const AxisDev& D, char* host) {
+  const int N = A.N, nin = N - (edges ? 2 : 0), j0 = edges ? 1 : 0;
+  double* g = (double*)(host + D.g);
+  double* lo = (double*)(host + D.glo);
+  double* hi = (double*)(host + D.ghi);
+  for (int k = 0; k < N; ++k) {
+    for (int j = 0; j < nin; ++j) g[(size_t)k * nin + j] = A.G[(size_t)k * N + j + j0];
+    lo[k] = edges ? A.G[(size_t)k * N] : 0.0;
+    hi[k] = edges ? A.G[(size_t)k * N + N - 1] : 0.0;
+  }
+  std::memcpy(host + D.w, A.w.data(), A.w.size() * 8);
+  std::memcpy(host + D.zz, A.zz.data(), A.zz.size() * 4);
 }
 
 // The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve).
@@ -2160,7 +2219,8 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
 // instance: pts_solve's; several: pts_solve_batched's), each instance's coarse iterate and
 // u^0, and the interpolation buffers and weights the instances share (used one after another).
 struct CoarseLayout {
-  size_t solver, Uc, u0c, T1, V, Wx, Wy, Wt, We, bdc, edges, total;
+  size_t solver, Uc, u0c, T1, V, Mx, My, Mt, Sx, Sy, St, bdc, edges, total;
+  AxisDev dx, dy, dt;
 };
 size_t coarse_solver_bytes(const pts_problem* pc, int nprob) {
   if (nprob == 1) return layout(pc).total;
@@ -2181,36 +2241,32 @@ CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc, int npro
   L.u0c = take((size_t)nprob * align_up(nsc * 8));
   L.T1 = take((size_t)pc->nt * pc->ny * p->nx * 8);
   L.V = take((size_t)pc->nt * p->ny * p->nx * 8);
-  L.Wx = take((size_t)p->nx * pc->nx * 8);
-  L.Wy = take((size_t)p->ny * pc->ny * 8);
-  L.Wt = take((size_t)p->nt * (pc->nt + 1) * 8);
-  L.We = take((size_t)2 * (p->nx + p->ny) * 8);  // edge weights: x low, x high, y low, y high
   const bool dir = p->bc != PTS_PERIODIC;
+  const int Nx = pc->nx + (dir ? 2 : 0), Ny = pc->ny + (dir ? 2 : 0), Nt = pc->nt + 1;
+  L.Mx = take((size_t)pc->nt * pc->ny * Nx * 8);  // second derivatives along each axis
+  L.My = take((size_t)pc->nt * Ny * p->nx * 8);
+  L.Mt = take((size_t)Nt * p->nx * p->ny * 8);
+  L.dx = axis_dev_layout(Nx, p->nx, dir);
+  L.dy = axis_dev_layout(Ny, p->ny, dir);
+  L.dt = axis_dev_layout(Nt, p->nt, false);
+  L.Sx = take(L.dx.total);
+  L.Sy = take(L.dy.total);
+  L.St = take(L.dt.total);
   L.bdc = take(dir ? (size_t)pc->nt * 2 * (pc->nx + pc->ny) * 8 : 0);
   L.edges = take(dir ? (size_t)pc->nt * 2 * (pc->ny + p->nx) * 8 : 0);  // west_c, east_c, south_f, north_f
   L.total = o;
   return L;
 }
 
-// The interpolation weights along one spatial axis: n fine nodes, nc coarse nodes; for a
-// Dirichlet axis also the weights of its two edge values (lo, hi).
-std::vector<double> axis_weights(bool periodic, int n, int nc, int cf, double* lo, double* hi) {
-  std::vector<double> s(n);
-  if (periodic) {  // fine node i at i h = (i / cf) coarse spacings
-    for (int i = 0; i < n; ++i) s[i] = (double)i / cf;
-    return spline_weights(nc, true, s);
-  }
-  // Dirichlet: spline nodes z = 0 (edge), 1..nc (coarse interior), nc + 1 (edge); fine
-  // interior node i at (i + 1) h
-  for (int i = 0; i < n; ++i) s[i] = (double)(i + 1) / cf;
-  const std::vector<double> Wf = spline_weights(nc + 2, false, s);
-  std::vector<double> W((size_t)n * nc);
-  for (int i = 0; i < n; ++i) {
-    for (int k = 0; k < nc; ++k) W[(size_t)i * nc + k] = Wf[(size_t)i * (nc + 2) + k + 1];
-    lo[i] = Wf[(size_t)i * (nc + 2)];
-    hi[i] = Wf[(size_t)i * (nc + 2) + nc + 1];
-  }
-  return W;
+void launch_spline_eval(hipStream_t s, const char* tab, const AxisDev& D, int nf, int N, bool edges,
+                        const double* in, long isa, long isk, long isb, int zoff, const double* in0,
+                        const double* elo, const double* ehi, long esa, long esb, const double* M, long msa,
+                        long msk, long msb, double* out, long osa, long osi, long osb, long na, long nb) {
+  const long total = na * nf * nb;
+  const unsigned blocks = (unsigned)std::min<long>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_spline_eval, dim3(blocks), dim3(256), 0, s, (const int2*)(tab + D.zz),
+                     (const double4*)(tab + D.w), nf, N, edges ? 1 : 0, in, isa, isk, isb, zoff, in0, elo, ehi, esa,
+                     esb, M, msa, msk, msb, out, osa, osi, osb, na, nb);
 }
 
 void launch_interp(hipStream_t s, const double* W, int nf, int nc, const double* in, long isa, long isk, long isb,
@@ -2292,31 +2348,28 @@ int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, 
   }
   double* T1 = (double*)(w + L.T1);
   double* V = (double*)(w + L.V);
-  double* Wx = (double*)(w + L.Wx);
-  double* Wy = (double*)(w + L.Wy);
-  double* Wt = (double*)(w + L.Wt);
-  double* We = (double*)(w + L.We);
-  const bool per = p->bc == PTS_PERIODIC;
-  // weights: x, y (with the edge weights of Dirichlet lines), then time (nodes t = m cf tau,
-  // m = 0..nt/cf; fine level n at n / cf)
-  std::vector<double> we(2 * (p->nx + p->ny), 0.0);
-  const std::vector<double> wx = axis_weights(per, p->nx, pc.nx, cf, we.data(), we.data() + p->nx);
-  const std::vector<double> wy = axis_weights(per, p->ny, pc.ny, cf, we.data() + 2 * p->nx,
-                                              we.data() + 2 * p->nx + p->ny);
-  std::vector<double> st(p->nt);
-  for (int n = 0; n < p->nt; ++n) st[n] = (double)(n + 1) / cf;
-  const std::vector<double> wt = spline_weights(pc.nt + 1, false, st);
+  double* Mx = (double*)(w + L.Mx);
+  double* My = (double*)(w + L.My);
+  double* Mt = (double*)(w + L.Mt);
+  const char* Sx = w + L.Sx;
+  const char* Sy = w + L.Sy;
+  const char* St = w + L.St;
+  const bool per = p->bc == PTS_PERIODIC, dir = !per;
+  // splines: x and y (Dirichlet axes with edge nodes), time (nodes t = m cf tau, m = 0..nt/cf;
+  // fine level n at n / cf)
+  const AxisSpline ax = space_spline(per, p->nx, pc.nx, cf), ay = space_spline(per, p->ny, pc.ny, cf);
+  std::vector<double> stimes(p->nt);
+  for (int n = 0; n < p->nt; ++n) stimes[n] = (double)(n + 1) / cf;
+  const AxisSpline at = axis_spline(pc.nt + 1, false, stimes);
   {
-    // staged in a pinned buffer of this call's own: the coarse solve below reuses the shared one
-    std::vector<double> all;
-    for (const std::vector<double>* v : {&wx, &wy, &wt, (const std::vector<double>*)&we})
-      all.insert(all.end(), v->begin(), v->end());
-    HIPCHK(hipMemcpyAsync(Wx, all.data(), wx.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(Wy, all.data() + wx.size(), wy.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(Wt, all.data() + wx.size() + wy.size(), wt.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(We, all.data() + wx.size() + wy.size() + wt.size(), we.size() * 8, hipMemcpyHostToDevice,
-                          s));
-    HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before `all` goes
+    std::vector<char> host(L.dx.total + L.dy.total + L.dt.total);
+    axis_dev_fill(ax, dir, L.dx, host.data());
+    axis_dev_fill(ay, dir, L.dy, host.data() + L.dx.total);
+    axis_dev_fill(at, false, L.dt, host.data() + L.dx.total + L.dy.total);
+    HIPCHK(hipMemcpyAsync(w + L.Sx, host.data(), L.dx.total, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w + L.Sy, host.data() + L.dx.total, L.dy.total, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w + L.St, host.data() + L.dx.total + L.dy.total, L.dt.total, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before `host` goes
   }
   // Dirichlet data of the coarse problem and the ends of the spline lines (shared)
   double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
@@ -2349,16 +2402,27 @@ int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, 
                            w + L.solver, coarse_solver_bytes(&pc, nprob), nullptr, stats, stream);
   }
   if (rc) return rc;
-  // splines per instance: x (coarse rows -> T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V ->
-  // U[n]); x lines of row yc at level m end in west_c/east_c[m][yc], y lines of column x in
-  // south_f/north_f[m][x]. The instances reuse T1 and V in stream order.
+  // splines per instance, each as second derivatives then evaluation: x (coarse rows ->
+  // T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V -> U[n]); x lines of row yc at level m end in
+  // west_c/east_c[m][yc], y lines of column x in south_f/north_f[m][x]. The instances reuse the
+  // buffers in stream order.
   const long nx = p->nx, ny = p->ny, ns = nx * ny;
+  const int Nx = ax.N, Ny = ay.N, Nt = at.N, zoff = dir ? 1 : 0;
+  const long nax = (long)pc.nt * pc.ny;
   for (int i = 0; i < nprob; ++i) {
-    launch_interp(s, Wx, p->nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, T1, nx, 1, 0, (long)pc.nt * pc.ny, 1, We,
-                  We + p->nx, west_c, east_c, 1, 0);
-    launch_interp(s, Wy, p->ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, V, ns, nx, 1, pc.nt, nx,
-                  We + 2 * p->nx, We + 2 * p->nx + p->ny, south_f, north_f, nx, 1);
-    launch_interp(s, Wt, p->nt, pc.nt + 1, V, 0, ns, 1, u0[i], U[i], 0, ns, 1, 1, ns);
+    launch_interp(s, (const double*)(Sx + L.dx.g), Nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, Mx, Nx, 1, 0, nax, 1,
+                  dir ? (const double*)(Sx + L.dx.glo) : nullptr, (const double*)(Sx + L.dx.ghi), west_c, east_c, 1,
+                  0);
+    launch_spline_eval(s, Sx, L.dx, p->nx, Nx, dir, Uc[i], pc.nx, 1, 0, zoff, nullptr, west_c, east_c, 1, 0, Mx, Nx,
+                       1, 0, T1, nx, 1, 0, nax, 1);
+    launch_interp(s, (const double*)(Sy + L.dy.g), Ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, My,
+                  (long)Ny * nx, nx, 1, pc.nt, nx, dir ? (const double*)(Sy + L.dy.glo) : nullptr,
+                  (const double*)(Sy + L.dy.ghi), south_f, north_f, nx, 1);
+    launch_spline_eval(s, Sy, L.dy, p->ny, Ny, dir, T1, (long)pc.ny * nx, nx, 1, zoff, nullptr, south_f, north_f,
+                       nx, 1, My, (long)Ny * nx, nx, 1, V, ns, nx, 1, pc.nt, nx);
+    launch_interp(s, (const double*)(St + L.dt.g), Nt, Nt, V, 0, ns, 1, u0[i], Mt, 0, ns, 1, 1, ns);
+    launch_spline_eval(s, St, L.dt, p->nt, Nt, false, V, 0, ns, 1, 1, u0[i], nullptr, nullptr, 0, 0, Mt, 0, ns, 1,
+                       U[i], 0, ns, 1, 1, ns);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

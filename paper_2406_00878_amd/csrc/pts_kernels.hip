@@ -1039,6 +1039,43 @@ __global__ __launch_bounds__(256) void k_interp_axis(const double* __restrict__ 
   }
 }
 
+// Evaluation of 1-D cubic splines from node values and second derivatives: fine point i lies
+// in the interval (z0, z1) = zz[i] of the N spline nodes, and out[a][i][b] = w.x y(z0) + w.y
+// y(z1) + w.z M(z0) + w.w M(z1) (w = wt[i]). Node z holds, with edges set, the edge values
+// elo / ehi (zero when NULL) at z = 0 and z = N - 1; with in0 given, in0[b] at z = 0; else
+// in[a][z - zoff][b]. M is [a][z][b] with strides msa, msk, msb.
+__global__ __launch_bounds__(256) void k_spline_eval(const int2* __restrict__ zz, const double4* __restrict__ wt,
+                                                     int nf, int N, int edges, const double* __restrict__ in,
+                                                     long isa, long isk, long isb, int zoff,
+                                                     const double* __restrict__ in0, const double* __restrict__ elo,
+                                                     const double* __restrict__ ehi, long esa, long esb,
+                                                     const double* __restrict__ M, long msa, long msk, long msb,
+                                                     double* __restrict__ out, long osa, long osi, long osb, long na,
+                                                     long nb) {
+  const long total = na * nf * nb;
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long b = t % nb, r = t / nb;
+    const int i = (int)(r % nf);
+    const long a = r / nf;
+    const int2 z = zz[i];
+    const double4 w = wt[i];
+    auto node = [&](int k) -> double {
+      if (edges && (k == 0 || k == N - 1)) {
+        const double* e = k == 0 ? elo : ehi;
+        return e ? e[a * esa + b * esb] : 0.0;
+      }
+      if (in0 && k == 0) return in0[b];
+      return in[a * isa + (long)(k - zoff) * isk + b * isb];
+    };
+    const double* m = M + a * msa + b * msb;
+    double v = w.x * node(z.x);
+    v = fma(w.y, node(z.y), v);
+    v = fma(w.z, m[(long)z.x * msk], v);
+    v = fma(w.w, m[(long)z.y * msk], v);
+    out[a * osa + (long)i * osi + b * osb] = v;
+  }
+}
+
 // Fill a small array of 64-bit words with zero (used instead of a memset node so that
 // the sequence can be captured in a HIP graph).
 __global__ void k_zero(unsigned long long* __restrict__ a, int count) {
