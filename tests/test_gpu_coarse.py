@@ -139,3 +139,37 @@ def test_batched_coarse_start_equals_one_by_one(bc):
         assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
     Ug, _ = coarse.coarse_initial_iterate(probs[1], 4)
     assert np.max(np.abs(host(Us[1]) - Ug)) <= 1e-10 * np.max(np.abs(Ug))
+
+
+def test_coarse_start_edge_cases():
+    """One coarse level (N_t = c_f: the time spline is the line through u^0 and that level), the
+    smallest periodic coarse grid (3 nodes per direction), and a batch of one."""
+    rng = np.random.default_rng(91)
+    cases = [W.heat_dirichlet(31, 4, 1e-3, W.sine_u0_dirichlet(31, rng)),
+             W.burgers_periodic(12, 8, 5e-4, 0.01, W.fourier_u0_periodic(12, 92, kmax=1))]
+    for q in cases:
+        U = torch.empty((q.nt, q.ny, q.nx), dtype=torch.float64, device="cuda")
+        print(f"[coarse] edge case {q.nx}x{q.ny}x{q.nt} bc={q.bc}", flush=True)
+        P.coarse_initial_iterate(q, U, dev(q.u0), 4, tol=1e-13)
+        Ug, _ = coarse.coarse_initial_iterate(q, 4)
+        assert np.max(np.abs(host(U) - Ug)) <= 1e-10 * np.max(np.abs(Ug)), q.name
+    q = cases[0]
+    Ub = [torch.empty((q.nt, q.ny, q.nx), dtype=torch.float64, device="cuda")]
+    P.coarse_initial_iterate_batched(q, Ub, [dev(q.u0)], 4, tol=1e-13)
+    Ug, _ = coarse.coarse_initial_iterate(q, 4)
+    assert np.max(np.abs(host(Ub[0]) - Ug)) <= 1e-10 * np.max(np.abs(Ug))
+
+
+def test_batched_coarse_start_with_dirichlet_data():
+    """Instances of the Section 8.1 problem sharing its Dirichlet data, with different u^0."""
+    import dataclasses
+    p, _ = _mms("heat", 64, 8)
+    bd = dev(p.bdata)
+    X, Y = p.mesh()
+    probs = [dataclasses.replace(p, u0=p.u0 * (1.0 + 0.01 * k)) for k in range(3)]
+    Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda") for _ in probs]
+    print("[coarse] batched mms", flush=True)
+    P.coarse_initial_iterate_batched(p, Us, [dev(q.u0) for q in probs], 4, tol=1e-12, bdata=bd)
+    for q, U in zip(probs, Us):
+        Ug, _ = coarse.coarse_initial_iterate(q, 4)
+        assert np.max(np.abs(host(U) - Ug)) <= 1e-10 * np.max(np.abs(Ug))
