@@ -307,10 +307,11 @@ def bench_learned(args):
 
         # inference + judge of the instances on a few streams at once (each call is a chain of
         # small launches), each stream with its own network and judge workspaces
-        NS = max(1, args.infer_streams)
+        NS = max(0, args.infer_streams)
         side = [torch.cuda.Stream(device=dev) for _ in range(NS)]
         net_ws = [net.workspace(dev) for _ in range(NS)]
-        judge_ws = [P.workspace(prob, "fp64", dev) for _ in range(NS)]
+        net_wsb = net.workspace_batched(EB, dev) if NS == 0 else None
+        judge_ws = [P.workspace(prob, "fp64", dev) for _ in range(max(NS, 1))]
         # one workspace per precision for every batched call (the captured graphs hold its address)
         ws_b = {pr: P.batched_workspace(probs_b, pr, dev) for pr in ("fp64", "mixed")}
         cws_b = P.coarse_workspace_batched(prob, cf, EB, dev) if cf > 1 else None
@@ -323,6 +324,9 @@ def bench_learned(args):
             if kind == "coarse":  # the coarse solves of the batch share batched launches
                 P.coarse_initial_iterate_batched(prob, U_b, u0_b, cf, tol=tol, ws=cws_b)
                 return []
+            if NS == 0:  # one batched forward pass, then the judges
+                ch = net.initial_iterate_batched(prob, u0_b, U_b, net_wsb, solver_ws=judge_ws[0], report=report)
+                return [{"chosen": c} for c in ch] if report else []
             cur = torch.cuda.current_stream()
             for sd in side:
                 sd.wait_stream(cur)
@@ -503,8 +507,9 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3, help="--learned: timed repetitions of the batch")
     ap.add_argument("--coarse-factor", type=int, default=4,
                     help="--learned: also time the coarse-grid start (Section 4) with this factor (0 = off)")
-    ap.add_argument("--infer-streams", type=int, default=4,
-                    help="--learned: streams the batch's inference + judge calls are spread over")
+    ap.add_argument("--infer-streams", type=int, default=0,
+                    help="--learned: 0 = the batch's starts as one batched forward pass, then the judges; "
+                         "N > 0 = one-sample inference + judge calls spread over N streams")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -94,6 +94,15 @@ int pts_no_prepare(const pts_no_config* cfg, void* workspace, size_t workspace_b
 int pts_no_forward(const pts_no_config* cfg, const float* params, const double* u0, double* U_pred,
                    void* workspace, size_t workspace_bytes, pts_stream_t stream);
 
+/* The forward pass of `batch` samples at once: U_pred[b] from u0[b] (device arrays, as
+   pts_no_forward). The spectral transforms run over the channels of all samples together and
+   the channel mixes as batched products, so the launches carry `batch` times the work. The
+   workspace (pts_no_workspace_bytes_batched(cfg, batch) bytes) is prepared with pts_no_prepare
+   like a one-sample workspace; its activations are not kept for a backward pass. */
+size_t pts_no_workspace_bytes_batched(const pts_no_config* cfg, int batch);
+int pts_no_forward_batched(const pts_no_config* cfg, const float* params, int batch, const double* const* u0,
+                           double* const* U_pred, void* workspace, size_t workspace_bytes, pts_stream_t stream);
+
 /* Mean-squared-error loss against U_true [nt][ny][nx] (float64) after pts_no_forward on the
    same sample and workspace: grads (float32, param_count) and loss (device double[1]) are
    ACCUMULATED into (the caller zeroes them before a batch). loss += mean((U_pred-U_true)^2),
@@ -131,6 +140,15 @@ int pts_no_adam(size_t n, float* params, const float* grads, float* m, float* v,
 int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const float* params, const double* u0,
                            double* U, void* no_ws, size_t no_ws_bytes, void* solver_ws, size_t solver_ws_bytes,
                            int judge, int* chosen, double* res_pred, double* res_plain, pts_stream_t stream);
+
+/* pts_no_initial_iterate for `batch` initial conditions of the problem p: one batched
+   forward pass (no_ws: a pts_no_workspace_bytes_batched(cfg, batch) workspace), then the judge
+   of each instance in turn on solver_ws. chosen (host int[batch], may be NULL) as for the
+   one-sample call (then the stream is synchronised). */
+int pts_no_initial_iterate_batched(const pts_problem* p, const pts_no_config* cfg, const float* params, int batch,
+                                   const double* const* u0, double* const* U, void* no_ws, size_t no_ws_bytes,
+                                   void* solver_ws, size_t solver_ws_bytes, int judge, int* chosen,
+                                   pts_stream_t stream);
 
 /* Strided batched GEMM used by the network, exposed for testing: for b in [0, batch)
      C_b[m][n] = alpha * sum_k A_b[m][k] B_b[k][n] + beta * C_b[m][n]

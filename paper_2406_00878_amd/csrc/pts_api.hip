@@ -2279,6 +2279,9 @@ void launch_interp(hipStream_t s, const double* W, int nf, int nc, const double*
                      osb, na, nb, Wlo, Whi, elo, ehi, esa, esb);
 }
 
+int no_judge(const pts_problem* p, const double* u0, double* U, void* solver_ws, int judge, int* chosen,
+             double* res_pred, double* res_plain, hipStream_t s);
+
 extern "C" {
 
 const char* pts_last_error(void) { return g_err.c_str(); }
@@ -2544,9 +2547,39 @@ int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const
     return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: judge %d", judge);
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: NULL array");
   if ((rc = check_ws(p, solver_ws, solver_ws_bytes))) return rc;
-  hipStream_t s = (hipStream_t)stream;
   rc = pts_no_forward(cfg, params, u0, U, no_ws, no_ws_bytes, stream);
   if (rc) return rc;
+  return no_judge(p, u0, U, solver_ws, judge, chosen, res_pred, res_plain, (hipStream_t)stream);
+}
+
+int pts_no_initial_iterate_batched(const pts_problem* p, const pts_no_config* cfg, const float* params, int batch,
+                                   const double* const* u0, double* const* U, void* no_ws, size_t no_ws_bytes,
+                                   void* solver_ws, size_t solver_ws_bytes, int judge, int* chosen,
+                                   pts_stream_t stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!cfg || p->bc != PTS_PERIODIC || cfg->nx != p->nx || cfg->ny != p->ny || cfg->nt != p->nt)
+    return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: network and problem disagree");
+  if (judge != PTS_NO_JUDGE_RESIDUAL && judge != PTS_NO_JUDGE_ACCUMULATED)
+    return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: judge %d", judge);
+  if (batch < 1 || !U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: NULL array");
+  if ((rc = check_ws(p, solver_ws, solver_ws_bytes))) return rc;
+  rc = pts_no_forward_batched(cfg, params, batch, u0, U, no_ws, no_ws_bytes, stream);
+  if (rc) return rc;
+  for (int b = 0; b < batch; ++b)
+    if ((rc = no_judge(p, u0[b], U[b], solver_ws, judge, chosen ? chosen + b : nullptr, nullptr, nullptr,
+                       (hipStream_t)stream)))
+      return rc;
+  return PTS_OK;
+}
+
+}  // extern "C"
+
+// The judge of a predicted iterate in U against the plain one (see pts_no_initial_iterate):
+// U keeps the prediction or becomes the plain iterate.
+int no_judge(const pts_problem* p, const double* u0, double* U, void* solver_ws, int judge, int* chosen,
+             double* res_pred, double* res_plain, hipStream_t s) {
+  int rc;
   Instance in;
   in.bind(p, solver_ws);
   int dummy = 0;
@@ -2595,6 +2628,8 @@ int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const
   }
   return PTS_OK;
 }
+
+extern "C" {
 
 size_t pts_workspace_bytes_batched(const pts_problem* probs, int nprob) {
   if (!probs || nprob < 1) {

@@ -529,9 +529,13 @@ int split_of(long tiles, int K) {
 }
 long tiles_of(int M, int N, int batch) { return (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch; }
 constexpr int kPartSlots = 4096;  // loss partial sums (one per block of the loss kernels)
-Ws ws_layout(const pts_no_config* c) {
+// B > 1: the forward buffers (activations, modes, coefficient fields, transform partials) of
+// B samples at once (pts_no_forward_batched); the basis tables sit at the same offsets for
+// every B, so one preparation serves either form.
+Ws ws_layout(const pts_no_config* c, int B = 1) {
   Ws w;
   const size_t C = c->width, np = (size_t)c->nx * c->ny, m2 = 2 * c->modes - 1, Q = m2 * m2;
+  const size_t CB = C * B;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -542,13 +546,13 @@ Ws ws_layout(const pts_no_config* c) {
   w.phiy = take(c->ny * m2 * 4);
   w.tphi = take((size_t)c->nt * c->tmodes * 4);
   w.s64 = take((size_t)c->nt * c->tmodes * 8);
-  w.v = take((c->layers + 1) * C * np * 4);
-  w.z = take(c->layers * C * np * 4);
-  w.vh = take(c->layers * C * Q * 4);
-  w.wh = take(C * Q * 4);
-  w.t1 = take(C * c->ny * m2 * 4);
-  w.t2 = take(C * c->ny * m2 * 4);
-  w.coef = take((size_t)c->tmodes * np * 4);
+  w.v = take((c->layers + 1) * CB * np * 4);
+  w.z = take(c->layers * CB * np * 4);
+  w.vh = take(c->layers * CB * Q * 4);
+  w.wh = take(CB * Q * 4);
+  w.t1 = take(CB * c->ny * m2 * 4);
+  w.t2 = take(CB * c->ny * m2 * 4);
+  w.coef = take((size_t)B * c->tmodes * np * 4);
   w.dcoef = take((size_t)c->tmodes * np * 4);
   w.dv = take(C * np * 4);
   w.dv2 = take(C * np * 4);
@@ -558,9 +562,9 @@ Ws ws_layout(const pts_no_config* c) {
   w.part = take(kPartSlots * 8);
   w.gpart = take((size_t)kSplit * std::max((size_t)c->tmodes, C) * C * 4);
   {  // partials of the two products onto the modes (x direction, then y direction per channel)
-    const int M1 = (int)C * c->ny, M2 = (int)m2;
+    const int M1 = (int)CB * c->ny, M2 = (int)m2;
     const size_t p1 = (size_t)split_of(tiles_of(M1, (int)m2, 1), c->nx) * M1 * m2;
-    const size_t p2 = (size_t)split_of(tiles_of(M2, M2, (int)C), c->ny) * C * Q;
+    const size_t p2 = (size_t)split_of(tiles_of(M2, M2, (int)CB), c->ny) * CB * Q;
     w.tpart = take(std::max(p1, p2) * 4);
   }
   w.rpart = take((size_t)kMaxT * kRowSlices * 4);
@@ -610,18 +614,19 @@ struct Net {
   Par P;
   Ws W;
   char* ws;
-  int C, nx, ny, m2, Q;
+  int C, CB, nx, ny, m2, Q;  // CB: channels of all samples of a batched forward (C otherwise)
   long np;
   float* f(size_t off) const { return (float*)(ws + off); }
-  float* v(int l) const { return f(W.v) + (size_t)l * C * np; }
-  float* z(int l) const { return f(W.z) + (size_t)l * C * np; }
-  float* vh(int l) const { return f(W.vh) + (size_t)l * C * Q; }
-  void bind(const pts_no_config* cfg, void* w) {
+  float* v(int l) const { return f(W.v) + (size_t)l * CB * np; }
+  float* z(int l) const { return f(W.z) + (size_t)l * CB * np; }
+  float* vh(int l) const { return f(W.vh) + (size_t)l * CB * Q; }
+  void bind(const pts_no_config* cfg, void* w, int B = 1) {
     c = cfg;
     P = par_layout(cfg);
-    W = ws_layout(cfg);
+    W = ws_layout(cfg, B);
     ws = (char*)w;
     C = cfg->width;
+    CB = C * B;
     nx = cfg->nx;
     ny = cfg->ny;
     m2 = 2 * cfg->modes - 1;
@@ -635,11 +640,11 @@ struct Net {
     const float* phiy = f(W.phiy);
     float* t1 = f(W.t1);
     float* tp = f(W.tpart);
-    int rc = gemm(s, C * ny, m2, nx, 1.f, vin, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0, 1,
-                  split_of(tiles_of(C * ny, m2, 1), nx), tp);
+    int rc = gemm(s, CB * ny, m2, nx, 1.f, vin, nx, 1, 0, phix, m2, 1, 0, 0.f, t1, m2, 1, 0, 1,
+                  split_of(tiles_of(CB * ny, m2, 1), nx), tp);
     if (rc) return rc;
-    return gemm(s, m2, m2, ny, alpha, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, out, m2, 1, Q, C,
-                split_of(tiles_of(m2, m2, C), ny), tp);
+    return gemm(s, m2, m2, ny, alpha, phiy, 1, m2, 0, t1, m2, 1, (long)ny * m2, 0.f, out, m2, 1, Q, CB,
+                split_of(tiles_of(m2, m2, CB), ny), tp);
   }
   // vh = (1/np) phiy^T v phix
   int forward_transform(hipStream_t s, const float* vin, float* vhat) { return to_modes(s, vin, vhat, 1.f / (float)np); }
@@ -648,9 +653,9 @@ struct Net {
     const float* phix = f(W.phix);
     const float* phiy = f(W.phiy);
     float* t2 = f(W.t2);
-    int rc = gemm(s, ny, m2, m2, 1.f, phiy, m2, 1, 0, what, m2, 1, Q, 0.f, t2, m2, 1, (long)ny * m2, C);
+    int rc = gemm(s, ny, m2, m2, 1.f, phiy, m2, 1, 0, what, m2, 1, Q, 0.f, t2, m2, 1, (long)ny * m2, CB);
     if (rc) return rc;
-    return gemm(s, C * ny, nx, m2, 1.f, t2, m2, 1, 0, phix, 1, m2, 0, beta, out, nx, 1, 0);
+    return gemm(s, CB * ny, nx, m2, 1.f, t2, m2, 1, 0, phix, 1, m2, 0, beta, out, nx, 1, 0);
   }
   // gradients of a loss from dcoef = dL/dc (workspace) back through the network, accumulated
   int backward_from_coef(hipStream_t s, const float* params, const double* u0, float* grads) {
@@ -773,6 +778,57 @@ int pts_no_forward(const pts_no_config* cfg, const float* params, const double* 
               (unsigned)((cfg->nt + kSynthLevels - 1) / kSynthLevels));
     launch_synth(s, grid, cfg->nt, cfg->tmodes, np, u0, n.f(n.W.coef), params + n.P.pb, n.f(n.W.tphi), U_pred);
   }
+  NOCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+size_t pts_no_workspace_bytes_batched(const pts_no_config* cfg, int batch) {
+  if (valid(cfg) || batch < 1) return 0;
+  return ws_layout(cfg, batch).total;
+}
+
+int pts_no_forward_batched(const pts_no_config* cfg, const float* params, int batch, const double* const* u0,
+                           double* const* U_pred, void* workspace, size_t workspace_bytes, pts_stream_t stream) {
+  int rc = valid(cfg);
+  if (rc) return rc;
+  if (batch < 1 || !params || !u0 || !U_pred || !workspace)
+    return nofail(PTS_ERR_INVALID_ARG, "pts_no_forward_batched: NULL or empty batch");
+  for (int b = 0; b < batch; ++b)
+    if (!u0[b] || !U_pred[b]) return nofail(PTS_ERR_INVALID_ARG, "pts_no_forward_batched: sample %d: NULL", b);
+  if (workspace_bytes < ws_layout(cfg, batch).total)
+    return nofail(PTS_ERR_WORKSPACE, "pts_no_forward_batched: workspace");
+  hipStream_t s = (hipStream_t)stream;
+  Net n;
+  n.bind(cfg, workspace, batch);
+  const int C = n.C;
+  const long np = n.np, cnp = (long)C * np;
+  const long cq = (long)C * n.Q;
+  const int K = cfg->tmodes;
+  // activations of sample b at channel offset b C: the transforms run over all B C channels,
+  // the channel mixes as B products sharing the weights
+  for (int b = 0; b < batch; ++b)
+    hipLaunchKernelGGL(k_lift, dim3(eblocks(C * np)), dim3(256), 0, s, C, np, params + n.P.lw, params + n.P.lb, u0[b],
+                       n.v(0) + b * cnp);
+  for (int l = 0; l < cfg->layers; ++l) {
+    float* vin = n.v(l);
+    float* z = n.z(l);
+    if ((rc = n.forward_transform(s, vin, n.vh(l)))) return rc;
+    for (int b = 0; b < batch; ++b)
+      hipLaunchKernelGGL(k_mix, dim3(mix_blocks(C, cfg->modes)), dim3(256), 0, s, C, cfg->modes, params + n.P.R[l],
+                         n.vh(l) + b * cq, n.f(n.W.wh) + b * cq);
+    if ((rc = n.inverse_transform(s, n.f(n.W.wh), z, 0.f))) return rc;
+    if ((rc = gemm(s, C, (int)np, C, 1.f, params + n.P.W[l], C, 1, 0, vin, np, 1, cnp, 1.f, z, np, 1, cnp, batch, 1,
+                   nullptr, params + n.P.b[l], n.v(l + 1))))
+      return rc;
+  }
+  if ((rc = gemm(s, K, (int)np, C, 1.f, params + n.P.pw, C, 1, 0, n.v(cfg->layers), np, 1, cnp, 0.f, n.f(n.W.coef),
+                 np, 1, (long)K * np, batch)))
+    return rc;
+  dim3 grid(std::min<unsigned>((unsigned)((np + 255) / 256), 2048u),
+            (unsigned)((cfg->nt + kSynthLevels - 1) / kSynthLevels));
+  for (int b = 0; b < batch; ++b)
+    launch_synth(s, grid, cfg->nt, K, np, u0[b], n.f(n.W.coef) + (size_t)b * K * np, params + n.P.pb, n.f(n.W.tphi),
+                 U_pred[b]);
   NOCHK(hipGetLastError());
   return PTS_OK;
 }

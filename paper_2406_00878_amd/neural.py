@@ -47,6 +47,9 @@ def _lib():
             "pts_no_initial_iterate": (I, [C.c_void_p, P, V, V, V, V, S, V, S, I, C.POINTER(I),
                                            C.POINTER(D), C.POINTER(D), V]),
             "pts_no_gemm": (I, [I, I, I, F, V, L, L, L, V, L, L, L, F, V, L, L, L, I, V]),
+            "pts_no_workspace_bytes_batched": (S, [P, I]),
+            "pts_no_forward_batched": (I, [P, V, I, V, V, V, S, V]),
+            "pts_no_initial_iterate_batched": (I, [C.c_void_p, P, V, I, V, V, V, S, V, S, I, C.POINTER(I), V]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -113,6 +116,31 @@ class NeuralOperator:
         ws = raw[off:off + nb]
         _check(lib.pts_no_prepare(C.byref(self._c), _ptr(ws), ws.numel(), _stream(None)))
         return ws
+
+    def workspace_batched(self, batch: int, device="cuda") -> torch.Tensor:
+        """A prepared workspace for forward passes of `batch` samples at once."""
+        lib = _lib()
+        nb = lib.pts_no_workspace_bytes_batched(C.byref(self._c), int(batch))
+        if nb == 0:
+            _check(-1)
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        ws = raw[off:off + nb]
+        _check(lib.pts_no_prepare(C.byref(self._c), _ptr(ws), ws.numel(), _stream(None)))
+        return ws
+
+    def forward_batched(self, u0s, outs, ws, stream=None):
+        """U_pred for several samples in one batched pass (ws from workspace_batched)."""
+        cfg = self.cfg
+        n = len(u0s)
+        for u0, U in zip(u0s, outs):
+            _dev_f64(u0, (cfg.ny, cfg.nx), "u0")
+            _dev_f64(U, (cfg.nt, cfg.ny, cfg.nx), "U")
+        up = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
+        op = (C.c_void_p * n)(*[U.data_ptr() for U in outs])
+        _check(_lib().pts_no_forward_batched(C.byref(self._c), _ptr(self.params), n, up, op, _ptr(ws), ws.numel(),
+                                             _stream(stream)))
+        return outs
 
     def init_params(self, seed: int) -> torch.Tensor:
         """Random initial weights (host generator): lift ~ N(0,1), channel mixes ~ N(0, 1/width),
@@ -194,6 +222,28 @@ class NeuralOperator:
         if not report:
             return None
         return {"chosen": "learned" if ch.value else "plain", "res_pred": rp.value, "res_plain": r0.value}
+
+    def initial_iterate_batched(self, prob, u0s, Us, net_ws, solver_ws=None, judge="accumulated", report=True,
+                                stream=None):
+        """initial_iterate for several initial conditions of `prob`: one batched forward pass
+        (net_ws from workspace_batched(len(u0s))), then each judge. Returns the choices when
+        report (a synchronisation), else None."""
+        p = make_problem(prob, "fp64")
+        n = len(u0s)
+        solver_ws = workspace(prob, "fp64", Us[0].device) if solver_ws is None else solver_ws
+        for u0, U in zip(u0s, Us):
+            _dev_f64(u0, (p.ny, p.nx), "u0")
+            _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+        up = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
+        op = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
+        ch = (C.c_int * n)()
+        _check(_lib().pts_no_initial_iterate_batched(C.cast(C.pointer(p), C.c_void_p), C.byref(self._c),
+                                                     _ptr(self.params), n, up, op, _ptr(net_ws), net_ws.numel(),
+                                                     _ptr(solver_ws), solver_ws.numel(), JUDGES[judge],
+                                                     ch if report else None, _stream(stream)))
+        if not report:
+            return None
+        return ["learned" if c else "plain" for c in ch]
 
 
 def generate(net: NeuralOperator, make_problem_fn: Callable[[int], object], samples: int,

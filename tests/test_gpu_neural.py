@@ -366,3 +366,35 @@ def test_initial_iterate_rejects_mismatched_problem():
     U = torch.zeros((8, 32, 32), dtype=torch.float64, device="cuda")
     with pytest.raises(P.PTSError):
         net.initial_iterate(p, dev(p.u0), U)
+
+
+def test_batched_forward_equals_one_sample_forwards():
+    """The batched forward (transforms over the channels of all samples, batched channel mixes)
+    gives each sample's one-sample forward (the same bfloat16 products; summation order may
+    differ in the split-K transforms)."""
+    cfg = SMALL
+    net = NO.NeuralOperator(cfg)
+    net.params.copy_(dev(_params(cfg, 17), torch.float32))
+    u0s = [dev(_u0(cfg, 20 + b)) for b in range(5)]
+    ws = net.workspace_batched(len(u0s))
+    outs = [torch.empty((cfg.nt, cfg.ny, cfg.nx), dtype=torch.float64, device="cuda") for _ in u0s]
+    print("[forward] batched x5", flush=True)
+    net.forward_batched(u0s, outs, ws)
+    for u0, U in zip(u0s, outs):
+        ref = host(net.forward(u0)) - host(u0)[None]
+        assert _relnorm(host(U) - host(u0)[None], ref) < 1e-5
+
+
+def test_batched_initial_iterate_matches_one_by_one(trained):
+    net, _ = trained
+    probs = [_burgers(2000 + i) for i in range(3)]
+    u0s = [dev(p.u0) for p in probs]
+    Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda") for p in probs]
+    print("[judge] batched x3", flush=True)
+    chosen = net.initial_iterate_batched(probs[0], u0s, Us, net.workspace_batched(3))
+    for p, u0, U, c in zip(probs, u0s, Us, chosen):
+        V = torch.empty_like(U)
+        j = net.initial_iterate(p, u0, V)
+        assert c == j["chosen"], (c, j)
+        ref = host(V) - host(u0)[None]
+        assert _relnorm(host(U) - host(u0)[None], ref) < 1e-5
