@@ -2219,7 +2219,7 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
 // instance: pts_solve's; several: pts_solve_batched's), each instance's coarse iterate and
 // u^0, and the interpolation buffers and weights the instances share (used one after another).
 struct CoarseLayout {
-  size_t solver, Uc, u0c, T1, V, Mx, My, Mt, Sx, Sy, St, bdc, edges, total;
+  size_t solver, Uc, u0c, T1, V, Mx, My, Mt, Sx, Sy, St, Th, bdc, edges, total;
   AxisDev dx, dy, dt;
 };
 size_t coarse_solver_bytes(const pts_problem* pc, int nprob) {
@@ -2252,6 +2252,7 @@ CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc, int npro
   L.Sx = take(L.dx.total);
   L.Sy = take(L.dy.total);
   L.St = take(L.dt.total);
+  L.Th = take((size_t)2 * Nt * 8);  // Thomas elimination of the time spline
   L.bdc = take(dir ? (size_t)pc->nt * 2 * (pc->nx + pc->ny) * 8 : 0);
   L.edges = take(dir ? (size_t)pc->nt * 2 * (pc->ny + p->nx) * 8 : 0);  // west_c, east_c, south_f, north_f
   L.total = o;
@@ -2364,6 +2365,17 @@ int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, 
   std::vector<double> stimes(p->nt);
   for (int n = 0; n < p->nt; ++n) stimes[n] = (double)(n + 1) / cf;
   const AxisSpline at = axis_spline(pc.nt + 1, false, stimes);
+  // the Thomas elimination of the time spline's inner rows (not-a-knot: first and last rows
+  // 6 M = d, no coupling; the others 1, 4, 1): eliminated super-diagonal and reciprocal pivots
+  const int nth = std::max(pc.nt + 1 - 2, 0);
+  std::vector<double> th(2 * (size_t)(pc.nt + 1), 0.0);
+  for (int i = 0; i < nth; ++i) {
+    const bool end = i == 0 || i == nth - 1;
+    const double sub = (i == 0 || i == nth - 1) ? 0.0 : 1.0, sup = i == 0 ? 0.0 : 1.0;
+    const double den = (end ? 6.0 : 4.0) - (i ? sub * th[i - 1] : 0.0);
+    th[i] = sup / den;
+    th[nth + i] = 1.0 / den;
+  }
   {
     std::vector<char> host(L.dx.total + L.dy.total + L.dt.total);
     axis_dev_fill(ax, dir, L.dx, host.data());
@@ -2372,7 +2384,8 @@ int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, 
     HIPCHK(hipMemcpyAsync(w + L.Sx, host.data(), L.dx.total, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(w + L.Sy, host.data() + L.dx.total, L.dy.total, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(w + L.St, host.data() + L.dx.total + L.dy.total, L.dt.total, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before `host` goes
+    HIPCHK(hipMemcpyAsync(w + L.Th, th.data(), th.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // pageable sources: complete before they go
   }
   // Dirichlet data of the coarse problem and the ends of the spline lines (shared)
   double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
@@ -2423,7 +2436,8 @@ int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, 
                   (const double*)(Sy + L.dy.ghi), south_f, north_f, nx, 1);
     launch_spline_eval(s, Sy, L.dy, p->ny, Ny, dir, T1, (long)pc.ny * nx, nx, 1, zoff, nullptr, south_f, north_f,
                        nx, 1, My, (long)Ny * nx, nx, 1, V, ns, nx, 1, pc.nt, nx);
-    launch_interp(s, (const double*)(St + L.dt.g), Nt, Nt, V, 0, ns, 1, u0[i], Mt, 0, ns, 1, 1, ns);
+    hipLaunchKernelGGL(k_spline_m_time, dim3((unsigned)std::min<long>((ns + 255) / 256, 65536)), dim3(256), 0, s,
+                       (const double*)(w + L.Th), Nt, u0[i], (const double*)V, ns, Mt);
     launch_spline_eval(s, St, L.dt, p->nt, Nt, false, V, 0, ns, 1, 1, u0[i], nullptr, nullptr, 0, 0, Mt, 0, ns, 1,
                        U[i], 0, ns, 1, 1, ns);
   }

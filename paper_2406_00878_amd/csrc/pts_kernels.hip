@@ -1039,6 +1039,49 @@ __global__ __launch_bounds__(256) void k_interp_axis(const double* __restrict__ 
   }
 }
 
+// Second derivatives of the not-a-knot spline in time at every node b (one thread each): nodes
+// y_0 = in0[b], y_z = in[(z - 1) ns + b], z < N. The inner rows M_{z-1} + 4 M_z + M_{z+1} =
+// 6 (y_{z-1} - 2 y_z + y_{z+1}) with the first and last rows reduced to 6 M_1 = d_1 and
+// 6 M_{N-2} = d_{N-2} are solved by the Thomas algorithm (th[0..n): the eliminated
+// super-diagonal, th[n..2n): the reciprocal pivots, n = N - 2; dp staged in M), then
+// M_0 = 2 M_1 - M_2 and M_{N-1} = 2 M_{N-2} - M_{N-3}. N = 3 is one parabola, N = 2 a line.
+__global__ __launch_bounds__(256) void k_spline_m_time(const double* __restrict__ th, int N,
+                                                       const double* __restrict__ in0, const double* __restrict__ in,
+                                                       long ns, double* __restrict__ M) {
+  for (long b = (long)blockIdx.x * 256 + threadIdx.x; b < ns; b += (long)gridDim.x * 256) {
+    auto y = [&](int z) -> double { return z == 0 ? in0[b] : in[(long)(z - 1) * ns + b]; };
+    if (N < 3) {
+      for (int z = 0; z < N; ++z) M[(long)z * ns + b] = 0.0;
+      continue;
+    }
+    if (N == 3) {
+      const double m = y(0) - 2.0 * y(1) + y(2);
+      for (int z = 0; z < 3; ++z) M[(long)z * ns + b] = m;
+      continue;
+    }
+    const int n = N - 2;
+    double ym = y(0), y0 = y(1), dpp = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double yp = y(i + 2);
+      const double d = 6.0 * (ym - 2.0 * y0 + yp);
+      const double sub = (i == 0 || i == n - 1) ? 0.0 : 1.0;
+      const double dp = (d - sub * dpp) * th[n + i];
+      M[(long)(i + 1) * ns + b] = dp;
+      dpp = dp;
+      ym = y0;
+      y0 = yp;
+    }
+    double mnext = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double m = M[(long)(i + 1) * ns + b] - (i + 1 < n ? th[i] * mnext : 0.0);
+      M[(long)(i + 1) * ns + b] = m;
+      mnext = m;
+    }
+    M[b] = 2.0 * M[ns + b] - M[2 * ns + b];
+    M[(long)(N - 1) * ns + b] = 2.0 * M[(long)(N - 2) * ns + b] - M[(long)(N - 3) * ns + b];
+  }
+}
+
 // Evaluation of 1-D cubic splines from node values and second derivatives: fine point i lies
 // in the interval (z0, z1) = zz[i] of the N spline nodes, and out[a][i][b] = w.x y(z0) + w.y
 // y(z1) + w.z M(z0) + w.w M(z1) (w = wt[i]). Node z holds, with edges set, the edge values
