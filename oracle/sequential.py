@@ -69,7 +69,7 @@ def bdf1_step(uprev, p, n, tol=1e-13, maxit=50, method=None):
     bv = level_bvals(p, n)
     v = uprev.copy()
     hist = []
-    stall = 0
+    best, stall = np.inf, 0
     for it in range(maxit):
         G = level_residual(v, uprev, p, bv)
         g = float(np.max(np.abs(G)))
@@ -78,16 +78,18 @@ def bdf1_step(uprev, p, n, tol=1e-13, maxit=50, method=None):
             return v, it, hist
         if not np.isfinite(g):
             raise OracleNotConverged(f"level {n}: non-finite residual at Newton step {it}")
-        if len(hist) > 1 and g >= hist[-2]:
+        # stagnation: no new smallest residual over two Newton steps (a residual that
+        # oscillates at the rounding level counts, not only one that rises twice in a row)
+        if g < best:
+            best, vbest, stall = g, v, 0
+        else:
             stall += 1
             if stall >= 2:
-                floor = roundoff_floor(v, uprev, p)
-                if g <= floor:
-                    return v, it, hist
+                floor = roundoff_floor(vbest, uprev, p)
+                if best <= floor:
+                    return vbest, it, hist
                 raise OracleNotConverged(
-                    f"level {n}: residual stalled at {g:.3e} (tol {tol:.1e}, roundoff floor {floor:.1e})")
-        else:
-            stall = 0
+                    f"level {n}: residual stalled at {best:.3e} (tol {tol:.1e}, roundoff floor {floor:.1e})")
         A = level_jacobian(v, p, bv)
         d = linear_solve(A, -G.ravel(), method=method)
         v = v + d.reshape(v.shape)
