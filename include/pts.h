@@ -162,6 +162,25 @@ int pts_newton_step(const pts_problem* p, double* U, const double* u0, void* wor
                     size_t workspace_bytes, const pts_options* opts, pts_stats* stats,
                     pts_stream_t stream);
 
+/* pts_newton_step without a caller workspace and without any allocation: for callers
+   that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc). It computes the same step as
+   pts_newton_step in the bulk schedule (the same kernels, so the same result), with
+   its scratch in a device array of the library, one per GPU, 64 MiB, reserved when
+   the library is loaded on that GPU and held until the process ends. No hipMalloc,
+   hipHostMalloc, hipFree, event or graph creation, and no host heap allocation; the
+   scalars read back per step go through a stack buffer.
+   Limits: problems whose pts_workspace_bytes exceed 64 MiB (about 2.5 M space-time
+   nodes) are rejected with PTS_ERR_WORKSPACE before any device work;
+   opts->profile = 1 is rejected (PTS_ERR_INVALID_ARG). The calling thread's current
+   device must be the device of U, u0 and stream.
+   Every call on one GPU uses that GPU's one scratch array, which keeps the previous
+   call's contents (nothing in it needs to start at zero): calls that overlap on one
+   GPU (other threads, other streams) race and must be serialised by the caller.
+   Synchronises the stream once, as pts_newton_step does. */
+int pts_newton_step_static(const pts_problem* p, double* U, const double* u0, const pts_options* opts,
+                           pts_stats* stats, pts_stream_t stream);
+
 /* Initial space-time iterate of plain Newton: u^n = u^0 for n = 1..nt. */
 int pts_init_plain(const pts_problem* p, double* U, const double* u0, pts_stream_t stream);
 

@@ -23,7 +23,8 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, 
                    PTS_SCHED_AUTO, PTS_SCHED_BULK, PTS_SCHED_PIPELINE, pts_options, pts_problem,
                    pts_stats)
 
-__all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "solve", "autotune",
+__all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "newton_step_static",
+           "solve", "autotune",
            "solve_batched", "autotune_batched", "batched_workspace", "coarse_workspace", "coarse_initial_iterate",
            "coarse_workspace_batched", "coarse_initial_iterate_batched", "window_bound",
            "library_path", "version"]
@@ -163,6 +164,20 @@ def newton_step(prob, U, u0, bdata=None, precision="fp64", ws=None, stream=None,
     st = pts_stats()
     _check(_lib_checked().pts_newton_step(C.byref(p), _ptr(U), _ptr(u0), _ptr(ws), ws.numel(), C.byref(o),
                                           C.byref(st), _stream(stream)))
+    return _stats_dict(st)
+
+
+def newton_step_static(prob, U, u0, bdata=None, precision="fp64", stream=None, **opts) -> dict:
+    """One all-at-once Newton step applied to U in place, with the library's static device
+    scratch instead of a workspace (pts_newton_step_static: allocates nothing); returns the
+    statistics."""
+    p = make_problem(prob, precision, bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    o = _options(**opts)
+    st = pts_stats()
+    _check(_lib_checked().pts_newton_step_static(C.byref(p), _ptr(U), _ptr(u0), C.byref(o), C.byref(st),
+                                                 _stream(stream)))
     return _stats_dict(st)
 
 

@@ -61,6 +61,7 @@ def load():
         "pts_assemble": (I, [P, V, V, V, V, V, V]),
         "pts_init_plain": (I, [P, V, V, V]),
         "pts_newton_step": (I, [P, V, V, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
+        "pts_newton_step_static": (I, [P, V, V, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_solve": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_autotune": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_workspace_bytes_batched": (S, [P, I]),

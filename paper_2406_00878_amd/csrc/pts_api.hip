@@ -16,6 +16,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -184,10 +186,27 @@ int tiles(const pts_problem* p, const Geo& g) {
 }
 
 // Inner-solve plan: sweeps per pass and how passes are packed into launches.
+// Passes per launch of a plan: at most kMaxPacks entries (a plan has at most 64 passes), held
+// in place so that planning allocates nothing.
+struct PackList {
+  int v[kMaxPacks];
+  int n = 0;
+  void push_back(int x) {
+    if (n < kMaxPacks) v[n++] = x;
+  }
+  size_t size() const { return (size_t)n; }
+  int operator[](int i) const { return v[i]; }
+  PackList& operator=(std::initializer_list<int> l) {
+    n = 0;
+    for (int x : l) push_back(x);
+    return *this;
+  }
+};
+
 struct Plan {
   int sweeps = 1;
-  int passes = 1;          // total restarted passes per level
-  std::vector<int> packs;  // passes per launch
+  int passes = 1;   // total restarted passes per level
+  PackList packs;   // passes per launch
   bool fp32 = false;
 };
 
@@ -397,6 +416,31 @@ int host_scalars(double** out) {
   return PTS_OK;
 }
 
+// Scratch of pts_newton_step_static: a file-scope device array, one copy per GPU, held from
+// the library's load on that GPU to the end of the process. The array's name is a host-side
+// stand-in in host code: its device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that address is passed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+int static_scratch(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PTS_ERR_INVALID_ARG, "device %d beyond %d", dev, kMaxDevices);
+  static std::mutex m;
+  static void* addr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> lk(m);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    HIPCHK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    if (!a || (uintptr_t)a % kAlign) return fail(PTS_ERR_HIP, "static scratch has no usable device address");
+    addr[dev] = a;
+  }
+  *out = addr[dev];
+  return PTS_OK;
+}
+
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 struct Prof {
   struct Rec {
@@ -526,6 +570,7 @@ int check_opts(const pts_options* o) {
     return fail(PTS_ERR_INVALID_ARG, "Theorem-1 windows run in the bulk schedule");
   if (o->window < 0 || o->sweeps < 0 || o->lin_tol < 0)
     return fail(PTS_ERR_INVALID_ARG, "negative option");
+  if (o->refine >= kMaxPacks) return fail(PTS_ERR_INVALID_ARG, "refine %d exceeds %d", o->refine, kMaxPacks - 1);
   if (o->schedule != PTS_SCHED_AUTO && o->schedule != PTS_SCHED_BULK && o->schedule != PTS_SCHED_PIPELINE)
     return fail(PTS_ERR_INVALID_ARG, "schedule %d not available", o->schedule);
   if (o->stages < 0 || o->stages > kMaxStages) return fail(PTS_ERR_INVALID_ARG, "stages %d", o->stages);
@@ -569,16 +614,18 @@ int capture_step(Instance& in, double* U, const double* u0, const Plan& pl, hipS
   return PTS_OK;
 }
 
+// hs_caller: host buffer of 4 doubles for the scalars read back per step, or NULL for the
+// thread's pinned buffer.
 int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
-               const pts_options* o, pts_stats* st, hipStream_t s, bool single_step) {
+               const pts_options* o, pts_stats* st, hipStream_t s, bool single_step, double* hs_caller = nullptr) {
   Instance in;
   in.bind(p, ws);
   in.window = (o && o->window > 1) ? std::min(o->window, std::min(kMaxWindow, p->nt)) : 1;
   Prof prof;
   const bool profiling = o && o->profile;
   if (profiling) in.prof = &prof;
-  double* hs;
-  int rc = host_scalars(&hs);
+  double* hs = hs_caller;
+  int rc = hs ? PTS_OK : host_scalars(&hs);
   if (rc) return rc;
   const bool use_graph =
       !single_step && !profiling && (!o || o->use_graph != 0 || o->schedule == PTS_SCHED_AUTO);
@@ -2486,6 +2533,26 @@ int pts_newton_step(const pts_problem* p, double* U, const double* u0, void* wor
   if (rc) return rc;
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_newton_step: NULL array");
   return solve_bulk(p, U, u0, 0.0, 1, workspace, opts, stats, (hipStream_t)stream, true);
+}
+
+int pts_newton_step_static(const pts_problem* p, double* U, const double* u0, const pts_options* opts,
+                           pts_stats* stats, pts_stream_t stream) {
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  int rc = validate(p);
+  if (!rc) rc = check_opts(opts);
+  if (rc) return rc;
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_newton_step_static: NULL array");
+  if (opts && opts->profile)
+    return fail(PTS_ERR_INVALID_ARG, "pts_newton_step_static: profiling creates events; not available here");
+  const size_t need = layout(p).total;
+  if (need > kStaticScratchBytes)
+    return fail(PTS_ERR_WORKSPACE, "pts_newton_step_static: problem needs %zu bytes of scratch, the static "
+                "scratch holds %zu", need, kStaticScratchBytes);
+  void* ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc) return rc;
+  double hs[4] = {0.0, 0.0, 0.0, 0.0};
+  return solve_bulk(p, U, u0, 0.0, 1, ws, opts, stats, (hipStream_t)stream, true, hs);
 }
 
 int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* workspace,
