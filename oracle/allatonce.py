@@ -39,14 +39,14 @@ def global_residual(U, p):
     R = np.empty_like(U)
     prev = p.u0
     for n in range(1, p.nt + 1):
-        R[n - 1] = -level_residual(U[n - 1], prev, p, level_bvals(p, n))
+        R[n - 1] = -level_residual(U[n - 1], prev, p, level_bvals(p, n), p.tau(n))
         prev = U[n - 1]
     return R
 
 
 def level_blocks(U, p):
     """[A_1 .. A_Nt] at the iterate U."""
-    return [level_jacobian(U[n - 1], p, level_bvals(p, n)) for n in range(1, p.nt + 1)]
+    return [level_jacobian(U[n - 1], p, level_bvals(p, n), p.tau(n)) for n in range(1, p.nt + 1)]
 
 
 def global_jacobian(U, p) -> sp.csr_matrix:

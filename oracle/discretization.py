@@ -85,12 +85,13 @@ def spatial_operator(u, p, bvals=None):
     return conv - visc
 
 
-def level_residual(u, uprev, p, bvals=None):
-    """G^n = u^n - u^{n-1} + tau F(u^n): the tau-scaled BDF1 equation of one level."""
-    return u - uprev + p.dt * spatial_operator(u, p, bvals)
+def level_residual(u, uprev, p, bvals=None, tau=None):
+    """G^n = u^n - u^{n-1} + tau_n F(u^n): the tau-scaled BDF1 equation of one level (tau_n =
+    t^n - t^{n-1}, Eq. (3); default the problem's uniform step)."""
+    return u - uprev + (p.dt if tau is None else tau) * spatial_operator(u, p, bvals)
 
 
-def jacobian_stencil(u, p, bvals=None):
+def jacobian_stencil(u, p, bvals=None, tau=None):
     """Five coefficients (C, W, E, S, N) of A = I + tau dF/du at every node.
 
     Entry X at node P is dG_P / du_X for the neighbour X of P. For Dirichlet
@@ -110,7 +111,7 @@ def jacobian_stencil(u, p, bvals=None):
     dS_ = -(mu_s - 0.5 * b * (uP * uP - uS * uS)) / hy2 - cf * uS / p.hy
     dP_ = (mu_e + mu_w - 0.5 * b * (uE * uE - uP * uP) + 0.5 * b * (uP * uP - uW * uW)) / hx2 \
         + (mu_n + mu_s - 0.5 * b * (uN * uN - uP * uP) + 0.5 * b * (uP * uP - uS * uS)) / hy2
-    tau = p.dt
+    tau = p.dt if tau is None else tau
     C = 1.0 + tau * dP_
     W, E, S, N = tau * dW_, tau * dE_, tau * dS_, tau * dN_
     if p.bc == DIRICHLET:
@@ -145,9 +146,9 @@ def stencil_to_sparse(coef, p) -> sp.csr_matrix:
                          shape=(n, n)).tocsr()
 
 
-def level_jacobian(u, p, bvals=None) -> sp.csr_matrix:
-    """A = I + tau dF/du at u, as a sparse matrix (Eq. (6))."""
-    return stencil_to_sparse(jacobian_stencil(u, p, bvals), p)
+def level_jacobian(u, p, bvals=None, tau=None) -> sp.csr_matrix:
+    """A = I + tau_n dF/du at u, as a sparse matrix (Eq. (6))."""
+    return stencil_to_sparse(jacobian_stencil(u, p, bvals, tau), p)
 
 
 def level_bvals(p, n):

@@ -5,7 +5,8 @@ another, n = 1..N_t, each by Newton's method started from the previous level.
 By Theorem 1 the all-at-once Newton iteration has the same root, so this is the
 reference the all-at-once HIP path is compared with.
 
-Per step: v <- u^{n-1}; repeat G = v - u^{n-1} + tau F(v); A = I + tau dF/du(v);
+Per step: v <- u^{n-1}; repeat G = v - u^{n-1} + tau_n F(v); A = I + tau_n dF/du(v) (tau_n =
+t^n - t^{n-1}, Eq. (3));
 solve A d = -G; v <- v + d; until ||G||_inf <= tol. Linear solves are exact sparse
 LU for small levels and BiCGSTAB with a tight relative tolerance for large ones (the
 root does not depend on the linear solver; only the Newton path does).
@@ -52,13 +53,13 @@ def linear_solve(A, b, rtol=1e-14, method=None):
     return x
 
 
-def roundoff_floor(v, uprev, p):
+def roundoff_floor(v, uprev, p, tau=None):
     """Residual level below which rounding of G's own terms dominates (64 ulps of their size)."""
     vmax = float(np.max(np.abs(v)))
     mu_max = p.mu_a + p.mu_b * vmax * vmax
     visc = 2.0 * mu_max * (2.0 / p.hx ** 2 + 2.0 / p.hy ** 2) * vmax
     conv = abs(p.cflux) * vmax * vmax * (1.0 / p.hx + 1.0 / p.hy)
-    return 64.0 * EPS * (vmax + float(np.max(np.abs(uprev))) + p.dt * (visc + conv))
+    return 64.0 * EPS * (vmax + float(np.max(np.abs(uprev))) + (p.dt if tau is None else tau) * (visc + conv))
 
 
 def bdf1_step(uprev, p, n, tol=1e-13, maxit=50, method=None):
@@ -67,11 +68,12 @@ def bdf1_step(uprev, p, n, tol=1e-13, maxit=50, method=None):
     Raises OracleNotConverged when the level is not solved (see the module header).
     """
     bv = level_bvals(p, n)
+    tau = p.tau(n)
     v = uprev.copy()
     hist = []
     best, stall = np.inf, 0
     for it in range(maxit):
-        G = level_residual(v, uprev, p, bv)
+        G = level_residual(v, uprev, p, bv, tau)
         g = float(np.max(np.abs(G)))
         hist.append(g)
         if g <= tol:
@@ -85,12 +87,12 @@ def bdf1_step(uprev, p, n, tol=1e-13, maxit=50, method=None):
         else:
             stall += 1
             if stall >= 2:
-                floor = roundoff_floor(vbest, uprev, p)
+                floor = roundoff_floor(vbest, uprev, p, tau)
                 if best <= floor:
                     return vbest, it, hist
                 raise OracleNotConverged(
                     f"level {n}: residual stalled at {best:.3e} (tol {tol:.1e}, roundoff floor {floor:.1e})")
-        A = level_jacobian(v, p, bv)
+        A = level_jacobian(v, p, bv, tau)
         d = linear_solve(A, -G.ravel(), method=method)
         v = v + d.reshape(v.shape)
     raise OracleNotConverged(f"level {n}: {maxit} Newton steps, residual {hist[-1]:.3e}")

@@ -98,7 +98,7 @@ def test_stall_above_roundoff_raises(monkeypatch):
     mistake: the Jacobian's sign flipped, so every correction points uphill)."""
     p = W.heat32(nt=1)
     real = sequential.level_jacobian
-    monkeypatch.setattr(sequential, "level_jacobian", lambda v, q, bv=None: -real(v, q, bv))
+    monkeypatch.setattr(sequential, "level_jacobian", lambda v, q, bv=None, tau=None: -real(v, q, bv, tau))
     with pytest.raises(sequential.OracleNotConverged):
         sequential.bdf1_step(p.u0, p, 1)
 

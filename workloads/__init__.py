@@ -54,6 +54,7 @@ class Problem:
     mu_b: float
     u0: np.ndarray  # (ny, nx) float64
     bdata: Optional[np.ndarray] = None  # (nt, 2*(nx+ny)) float64 or None (zero)
+    dts: Optional[np.ndarray] = None  # (nt,) step sizes tau_n = t^n - t^{n-1}, or None (all dt)
     x0: float = 0.0
     y0: float = 0.0
     name: str = ""
@@ -61,6 +62,14 @@ class Problem:
     @property
     def cflux(self) -> float:
         return 0.5 if self.kind == BURGERS else 0.0
+
+    def tau(self, n: int) -> float:
+        """Step size of level n (1-based): tau_n = t^n - t^{n-1}."""
+        return float(self.dts[n - 1]) if self.dts is not None else float(self.dt)
+
+    def times(self) -> np.ndarray:
+        """t^1 .. t^nt."""
+        return np.cumsum(self.dts) if self.dts is not None else np.arange(1, self.nt + 1) * self.dt
 
     @property
     def ns(self) -> int:
