@@ -131,43 +131,50 @@ _BATCH = None  # the heat batch's problems, inherited by the forked CPU-baseline
 
 def _oracle_prefix(job):
     """CPU-baseline worker: the oracle time-steps instance i of the batch, one thread, until
-    budget_s is spent (stopping after the level that exhausts it); returns (DOF solved, s)."""
+    budget_s is spent (stopping after the level that exhausts it); returns (DOF solved, s, the
+    levels as float64 [levels][ny][nx])."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import sequential
     i, budget_s = job
     prob = _BATCH[i]
+    out = []
     with threadpool_limits(limits=1):
         u = np.array(prob.u0, dtype=np.float64)
         t0 = time.perf_counter()
-        levels = 0
         for n in range(1, prob.nt + 1):
             u, _, _ = sequential.bdf1_step(u, prob, n)
-            levels += 1
+            out.append(u)
             if time.perf_counter() - t0 >= budget_s:
                 break
-    return levels * prob.ns, time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+    return len(out) * prob.ns, dt, np.stack(out)
 
 
 def cpu_baseline_batch(probs, budget_s, max_cores=16):
     """The oracle on the host's cores for the batch: one single-threaded worker per core, each
-    time-stepping the first levels of one instance (the batch's first instances, one round) for
-    about budget_s (a worker stops after the level that exhausts it, and single levels of the
-    largest grids take seconds); DOF/s = the sum of the workers' rates, each over its own busy
-    time. Runs before the GPU is touched (the workers are forked)."""
+    time-stepping the first levels of one instance for about budget_s (a worker stops after the
+    level that exhausts it). The sample is the batch's smallest instances, one per core: one
+    level of the largest grids takes the oracle over a minute (stiff BiCGSTAB solves), which
+    would not bound the run. DOF/s = the sum of the workers' rates, each over its own busy time.
+    Runs before the GPU is touched (the workers are forked)."""
     import multiprocessing as mp
     global _BATCH
     _BATCH = probs
     cores = max(1, min(len(os.sched_getaffinity(0)), max_cores, len(probs)))
+    pick = sorted(range(len(probs)), key=lambda i: probs[i].nx)[:cores]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_oracle_prefix, [(i, budget_s) for i in range(cores)])
+        res = pool.map(_oracle_prefix, [(i, budget_s) for i in pick])
     wall = time.perf_counter() - t0
     dof = sum(r[0] for r in res)
-    return {"value": sum(d / t for d, t in res), "unit": "DOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"instances 0..{cores - 1} of the batch, first levels of each for {budget_s:.0f} s "
-                      f"({dof} DOF in {wall:.1f} s wall), numpy/scipy, one thread per process"}
+    grids = sorted(probs[i].nx for i in pick)
+    return {"value": sum(r[0] / r[1] for r in res), "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"the {cores} smallest instances of the batch (grids {grids[0]}^2..{grids[-1]}^2), first "
+                      f"levels of each for about {budget_s:.0f} s ({dof} DOF in {wall:.1f} s wall), numpy/scipy, "
+                      f"one thread per process"}, \
+        [(i, r[2]) for i, r in zip(pick, res)]
 
 
 def bench_learned(args):
@@ -228,7 +235,8 @@ def bench_learned(args):
         return net.initial_iterate(prob, u0, U, solver_ws=ws["fp64"], report=report)
 
     results = {}
-    for kind in ("plain", "learned") + (("coarse",) if cf > 1 else ()):
+    kinds = [k for k in args.learned_kinds.split(",") if k != "coarse" or cf > 1]
+    for kind in (kinds if args.learned_single else []):
         tag = {"plain": 0, "learned": 1, "coarse": 2}[kind]
         for pr in ("fp64", "mixed"):
             if not args.no_autotune:
@@ -336,7 +344,7 @@ def bench_learned(args):
                 cur.wait_stream(sd)
             return out
 
-        for kind in ("plain", "learned") + (("coarse",) if cf > 1 else ()):
+        for kind in kinds:
             tag = {"plain": 0, "learned": 1, "coarse": 2}[kind]
             for pr in ("fp64", "mixed"):
                 if not args.no_autotune:
@@ -382,6 +390,24 @@ def bench_learned(args):
 
     best = batched["learned_mixed"] if batched else results["learned_mixed"]
     base = batched["plain_fp64"] if batched else results["plain_fp64"]
+    roof, cb, oerr = None, None, None
+    if batched:
+        # dominant kernel of the learned + mixed batch: k_level_wave_batch, events around each
+        # sequence (its replayed graph) of one more, profiled batched solve
+        start_all("learned")
+        pst = P.solve_batched(probs_b, U_b, u0_b, tol=tol, max_iter=60, precision="mixed", cache_tag=1,
+                              ws=ws_b["mixed"], profile=True)[0]
+        torch.cuda.synchronize()
+        if pst["prof_count"][1]:
+            avg_ms = pst["prof_ms"][1] / pst["prof_count"][1]
+            bpl = pst["level_solve_bytes"] / pst["prof_count"][1]
+            ach = bpl / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": "k_level_wave_batch", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
+                    "bytes_per_launch": bpl}
+        if not args.no_cpu_baseline:  # the oracle on the first levels of held-out instance 0
+            cb, oerr, lv = cpu_baseline(probs_b[0], args.cpu_seconds, U_b[0].cpu().numpy())
+            oerr = {"value": oerr, "levels_checked": lv, "instance": 0, "form": "learned + mixed"}
     out = {
         "metric": METRIC,
         "value": best["dof_per_s"],
@@ -409,37 +435,47 @@ def bench_learned(args):
         "compare_batched": batched,
         "speedup_vs_plain_fp64": base["ms_per_solve"] / best["ms_per_solve"],
     }
-    print(json.dumps(out), flush=True)
+    if roof:
+        out["roofline"] = roof
+    if cb:
+        out["cpu_baseline"] = cb
+        out["rel_err_vs_oracle"] = oerr
+    return out
 
 
-def bench_heatbatch(args):
+KERNEL_NAMES = ["k_pc_resid", "k_mg_down", "k_mg_lds", "k_mg_up", "k_pc_update", "k_residual", "k_update",
+                "k_level_absmax"]
+
+
+def bench_heatbatch(args, extras=None):
     """64 independent nonlinear heat instances (k(u) = 1 + u^2, zero Dirichlet, dt = 1e-3) with
-    uneven grids 64^2..512^2 and 128..1024 levels, solved together in shared launches; FP32
-    inner solves with FP64 residuals and refinement."""
+    uneven grids 64^2..512^2 and 128..1024 levels, solved together in shared launches; the stiff
+    level solves are Chebyshev iterations preconditioned by a multigrid V-cycle in FP32, with
+    FP64 residuals, refinement residual and updates."""
     import numpy as np
     import torch
 
     import paper_2406_00878_amd as P
     import workloads as W
-    from oracle import sequential
 
     log = lambda m: print(f"[bench-heatbatch] {m}", file=sys.stderr, flush=True)
     probs = W.heat_batch()[:args.instances]
     dof = sum(p.dof for p in probs)
-    cb = None
+    cb, oracle_levels = None, []
     if not args.no_cpu_baseline:  # before the GPU is initialised: the pool forks this process
-        cb = cpu_baseline_batch(probs, args.cpu_seconds)
+        cb, oracle_levels = cpu_baseline_batch(probs, args.cpu_seconds)
         log(f"cpu baseline: {cb['value']:.3g} DOF/s on {cb['cores']} cores")
     dev = torch.device("cuda:0")
     Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
     u0s = [torch.as_tensor(p.u0, dtype=torch.float64, device=dev).contiguous() for p in probs]
+    ws = P.batched_workspace(probs, "mixed", dev)
     log(f"{len(probs)} instances, {dof / 1e9:.2f} G space-time DOF, grids {min(p.nx for p in probs)}.."
         f"{max(p.nx for p in probs)}, levels {min(p.nt for p in probs)}..{max(p.nt for p in probs)}")
 
-    def step():
+    def step(**kw):
         for p, U, u0 in zip(probs, Us, u0s):
             P.init_plain(p, U, u0)
-        return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed")
+        return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed", ws=ws, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -457,25 +493,56 @@ def bench_heatbatch(args):
     ms = e0.elapsed_time(e1) / args.steps
     its = [st["iterations"] for st in sts]
     log(f"{ms:.0f} ms per batch, Newton steps {min(its)}..{max(its)}")
-    # accuracy: the smallest instance against the time-stepping oracle on its first levels
-    i = min(range(len(probs)), key=lambda q: probs[q].dof)
-    levels = min(8, probs[i].nt)
-    Uo, _ = sequential.solve_sequential(probs[i], levels=levels)
-    Ug = Us[i][:levels].cpu().numpy()
-    err = float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo)))
+    # accuracy: every level the CPU baseline solved (the first levels of its instances), against
+    # the GPU result of the last timed solve
+    errs = []
+    for i, Uo in oracle_levels:
+        Ug = Us[i][:Uo.shape[0]].cpu().numpy()
+        errs.append(float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo))))
+    # per-kernel split: one more solve with every launch bracketed by HIP events on the launch
+    # stream (the library's profile option); achieved GB/s = algorithmic bytes / event time
+    pst = step(profile=True)[0]
+    torch.cuda.synchronize()
+    split = {}
+    for j, name in enumerate(KERNEL_NAMES):
+        if pst["kern_count"][j]:
+            t = pst["kern_ms"][j]
+            split[name] = {"ms": t, "launches": pst["kern_count"][j],
+                           "avg_us": t * 1e3 / pst["kern_count"][j],
+                           "gb_per_s": pst["kern_bytes"][j] / (t * 1e-3) / 1e9 if t > 0 else None}
+    log(f"kernel split (profiled solve): {json.dumps(split)}")
+    j = max(range(5), key=lambda q: pst["kern_ms"][q])  # dominant kernel of the level solves
+    n = max(pst["kern_count"][j], 1)
+    avg_ms = pst["kern_ms"][j] / n
+    bpl = pst["kern_bytes"][j] / n
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "heatbatch64", "instances": len(probs), "space_time_dof": dof, "dt": 1e-3,
-                   "tol": args.tol, "precision": "mixed", "schedule": "batched bulk",
+        "config": {"workload": "heatbatch64", "instances": len(probs), "space_time_dof": dof,
+                   "grids": [min(p.nx for p in probs), max(p.nx for p in probs)],
+                   "levels": [min(p.nt for p in probs), max(p.nt for p in probs)], "dt": 1e-3, "k": "1+u^2",
+                   "seed": 2406004, "tol": args.tol, "precision": "mixed (FP32 multigrid-preconditioned level "
+                   "solves, FP64 residuals and updates)", "schedule": "batched bulk",
                    "newton_steps_min_max": [min(its), max(its)],
-                   "inner_passes_max": max(st["refine"] + 1 for st in sts)},
-        "rel_err_vs_oracle": {"value": err, "instance": i, "levels_checked": levels},
+                   "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl},
+        "kernel_split": split,
     }
+    if errs:
+        out["rel_err_vs_oracle"] = {"value": max(errs), "levels_checked": sum(Uo.shape[0] for _, Uo in oracle_levels),
+                                    "instances": [i for i, _ in oracle_levels]}
     if cb is not None:
         out["cpu_baseline"] = cb
-    print(json.dumps(out), flush=True)
+    if extras:
+        del Us, ws
+        gc.collect()
+        torch.cuda.empty_cache()
+        out["other_workloads"] = extras()
+    return out
 
 
 def main():
@@ -483,7 +550,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="burgers256")
+    ap.add_argument("--workload", default="heatbatch",
+                    help="heatbatch (default: 64 uneven nonlinear heat instances), burgers256, burgers512, heat32")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -507,23 +575,65 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3, help="--learned: timed repetitions of the batch")
     ap.add_argument("--coarse-factor", type=int, default=4,
                     help="--learned: also time the coarse-grid start (Section 4) with this factor (0 = off)")
+    ap.add_argument("--learned-kinds", default="plain,learned,coarse",
+                    help="--learned: starts compared (plain, learned, coarse)")
+    ap.add_argument("--learned-single", type=int, default=1,
+                    help="--learned: 1 = also time one solve at a time, 0 = batches only")
     ap.add_argument("--infer-streams", type=int, default=0,
                     help="--learned: 0 = the batch's starts as one batched forward pass, then the judges; "
                          "N > 0 = one-sample inference + judge calls spread over N streams")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="heatbatch: skip the other workloads (Burgers 256^2 x 512 FP64, 512^2 x 1024 mixed, learned "
+                         "iterate), which are otherwise measured after the batch and reported under other_workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(instances and time levels would shard across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "heatbatch":
-        return bench_heatbatch(args)
     if args.learned:
         if args.tol == 1e-12:
             # relative error well inside 1e-8 for every start (checked at every level against
             # a reference converged to --ref-tol); 1e-9 leaves learned starts near 1e-7
             args.tol = 1e-10
-        return bench_learned(args)
+        out = bench_learned(args)
+    elif args.workload == "heatbatch":
+        out = bench_heatbatch(args, None if args.no_extras else (lambda: other_workloads(args)))
+    else:
+        out = bench_single(args)
+    print(json.dumps(out), flush=True)
+    if args.hbm_calibration:
+        hbm_calibration()
 
+
+def other_workloads(args):
+    """The other measured workloads of the default run, each with its roofline and CPU baseline:
+    Burgers 256^2 x 512 FP64, Burgers 512^2 x 1024 mixed precision, and the learned initial
+    iterate on Burgers 256^2 x 256 (batched held-out starts). Fewer timed steps than the
+    headline; an error in one is reported in its entry."""
+    import copy
+    res = {}
+    jobs = [("burgers256_fp64", dict(workload="burgers256", precision="fp64", tol=1e-12), bench_single),
+            ("burgers512_mixed", dict(workload="burgers512", precision="mixed", tol=1e-12), bench_single),
+            ("burgers256nu005_learned", dict(learned=True, tol=1e-10, learned_kinds="plain,learned",
+                                             learned_single=False, coarse_factor=0), bench_learned)]
+    for name, kw, fn in jobs:
+        a = copy.copy(args)
+        a.steps, a.warmup = min(args.steps, 5), 1
+        for k, v in kw.items():
+            setattr(a, k, v)
+        print(f"[bench] other workload {name}", file=sys.stderr, flush=True)
+        try:
+            res[name] = fn(a)
+        except Exception as e:  # reported, not fatal for the headline line
+            res[name] = {"error": f"{type(e).__name__}: {e}"}
+        import torch
+        gc.collect()
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_single(args):
+    """One problem solved alone (wavefront schedule by default); returns the result line."""
     import numpy as np
     import torch
 
@@ -621,9 +731,7 @@ def main():
         cb, err, levels = cpu_baseline(prob, args.cpu_seconds, U_host)
         out["cpu_baseline"] = cb
         out["rel_err_vs_oracle"] = {"value": err, "levels_checked": levels}
-    print(json.dumps(out), flush=True)
-    if args.hbm_calibration:
-        hbm_calibration()
+    return out
 
 
 if __name__ == "__main__":

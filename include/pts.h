@@ -51,11 +51,16 @@ enum {
   PTS_ERR_INVALID_ARG = -1,   /* bad sizes, NULL pointers, unsupported option */
   PTS_ERR_HIP = -2,           /* a HIP runtime call failed                    */
   PTS_ERR_NONFINITE = -3,     /* NaN/Inf in the input or in a residual        */
-  PTS_ERR_SINGULAR = -4,      /* a block A_n lost diagonal dominance: the
-                                 per-level solver has no convergence bound
+  PTS_ERR_SINGULAR = -4,      /* a zero pivot in the banded LU of a level block
                                  (Theorem 1 assumes det A_n != 0)             */
   PTS_ERR_NOT_CONVERGED = -5, /* max_iter reached; U holds the last iterate   */
-  PTS_ERR_WORKSPACE = -6      /* workspace NULL or smaller than required      */
+  PTS_ERR_WORKSPACE = -6,     /* workspace NULL or smaller than required      */
+  PTS_ERR_NOT_DOMINANT = -7   /* no level solve with a convergence bound: a
+                                 block's Jacobi-scaled Gershgorin radius is
+                                 >= 1, or above 0.7 with cell Peclet numbers
+                                 above 2 (complex Jacobi spectrum), and the
+                                 banded LU does not apply (Dirichlet grids of
+                                 at most 64 x 64 nodes)                       */
 };
 
 /* One problem instance (Section 2, Eq. (1)-(3)). Read only. */
@@ -69,6 +74,14 @@ typedef struct pts_problem {
   double dt;         /* uniform step tau > 0 (the paper's runs use uniform tau) */
   double mu_a, mu_b; /* mu(u) = mu_a + mu_b u^2 >= 0                          */
   const double* bdata; /* device [nt][2(nx+ny)] Dirichlet data or NULL       */
+  const double* dt_levels; /* device [nt] step sizes tau_n = t^n - t^{n-1} of
+                        Eq. (3), each > 0 (not checked), or NULL: dt on every
+                        level. With variable steps the solve runs the bulk
+                        schedule (Chebyshev or banded level solves); the
+                        wavefront schedule, the batched wavefront and
+                        multigrid forms, the coarse-grid start and the learned
+                        start take uniform steps only (PTS_ERR_INVALID_ARG or
+                        the bulk schedule, as stated at each entry point)   */
 } pts_problem;
 
 /* Solver options. Zero-initialise for defaults. */
@@ -136,6 +149,15 @@ typedef struct pts_stats {
   /* algorithmic bytes moved by the per-level solve launches of the solve
      (reads of u^n, r^n, du^{n-1}, the iterate of a previous launch; one write)  */
   double level_solve_bytes;
+  /* filled by pts_solve_batched with pts_options.profile = 1 on batches whose levels take
+     the multigrid-preconditioned solve (every instance's entry holds the batch totals):
+     per kernel [0] k_pc_resid, [1] k_mg_down, [2] k_mg_lds, [3] k_mg_up, [4] k_pc_update,
+     [5] k_residual, [6] k_update + k_reduce_sum, [7] other: summed time (ms) of the
+     launches, each bracketed by HIP events on `stream`, their number, and their
+     algorithmic bytes (the reads and writes the operation needs, once each)          */
+  double kern_ms[8];
+  int32_t kern_count[8];
+  double kern_bytes[8];
 } pts_stats;
 
 /* Bytes of device workspace pts_newton_step / pts_solve need for `p`.
@@ -181,6 +203,40 @@ int pts_newton_step(const pts_problem* p, double* U, const double* u0, void* wor
 int pts_newton_step_static(const pts_problem* p, double* U, const double* u0, const pts_options* opts,
                            pts_stats* stats, pts_stream_t stream);
 
+/* Theorem 1 in the paper's own form (Section 4, Eq. (8); Section 5, Eq. (9) and
+   Algorithm 1): one Newton step whose levels are decoupled through the explicit
+   products P^l = A_1 A_2 ... A_l (P^1 = A_1, P^l = P^{l-1} A_l) and right-hand
+   sides rt^l = P^{l-1} r^l + rt^{l-1} (rt^1 = r^1), every level then solving
+   P^l du^l = rt^l on its own: rows of P^l and rt^l divided by P^l's diagonal
+   (the Section 7 diagonal preconditioner), banded LU without pivoting (the
+   paper's direct solver for banded matrices; half-bandwidth min(l nx, nx ny - 1)
+   in the x-fastest ordering). P^l is held as the 2 l^2 + 2 l + 1 diagonals of the
+   Section 5 remark. In exact arithmetic the step equals the block inverse of
+   Eq. (7); in floating point the products' condition numbers grow like K^l
+   (Section 7, Eq. (cond)), so the form is meant for the paper's own small
+   workloads (pts_window_bound estimates the safe number of levels).
+   Dirichlet problems only (PTS_ERR_INVALID_ARG otherwise). Workspace:
+   pts_products_workspace_bytes(p) bytes, 256-byte aligned (it grows like
+   nx^2 ny nt^2: 2.1 GB at 63 x 63 x 32). Zero or non-finite pivots:
+   PTS_ERR_SINGULAR. stats (host, may be NULL): res_inf[0] = max |R(U_in)|,
+   upd_rms[1] the RMS update. Synchronises the stream once. */
+size_t pts_products_workspace_bytes(const pts_problem* p);
+int pts_newton_step_products(const pts_problem* p, double* U, const double* u0, void* workspace,
+                             size_t workspace_bytes, pts_stats* stats, pts_stream_t stream);
+
+/* The Newton iteration of pts_solve with every step taken by pts_newton_step_products,
+   until max |R| <= tol or max_iter steps (stats->res_inf / upd_rms: the histories). */
+int pts_solve_products(const pts_problem* p, double* U, const double* u0, double tol, int max_iter,
+                       void* workspace, size_t workspace_bytes, pts_stats* stats, pts_stream_t stream);
+
+/* The product P^n (1 <= n <= nt) of the blocks A_1 .. A_n at the iterate U, in the
+   diamond storage of pts_newton_step_products: out is a device array
+   [2n^2 + 2n + 1][ny][nx], entry e of node (x, y) coupling it to node (x + b, y + a),
+   the entries ordered by a = -n..n, then b = -(n - |a|)..(n - |a|) (0 where that node
+   lies outside the grid). Workspace as pts_newton_step_products. */
+int pts_product_diamond(const pts_problem* p, const double* U, const double* u0, int n, double* out,
+                        void* workspace, size_t workspace_bytes, pts_stream_t stream);
+
 /* Initial space-time iterate of plain Newton: u^n = u^0 for n = 1..nt. */
 int pts_init_plain(const pts_problem* p, double* U, const double* u0, pts_stream_t stream);
 
@@ -211,8 +267,10 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
 /* Independent instances (Theorem 1 per instance) solved together.
    Instances of one problem (equal kind, bc, sizes, spacings, dt, mu_a, mu_b,
    precision and bdata pointer; only u0 and the starting iterate differ) run
-   batched wavefront sequences unless opts asks for the bulk schedule, windows,
-   profiling or the cooperative launch: each anti-diagonal of a sequence is one
+   batched wavefront sequences unless opts asks for the bulk schedule, windows
+   or the cooperative launch (with opts->profile = 1 every sequence is bracketed
+   by HIP events: stats prof_ms[1] / prof_count[1] = mean launch interval of the
+   wavefront kernel, level_solve_bytes its algorithmic bytes): each anti-diagonal of a sequence is one
    launch over (stages x tiles, instances), all instances run the same stage
    count, and an instance leaves the batch when max|R| <= tol (stats report
    schedule PTS_SCHED_PIPELINE). An instance whose Newton iteration turns
@@ -226,8 +284,9 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    Batches of Dirichlet heat on square grids with h_x = h_y and mu_a > 0 whose
    blocks are stiff (Jacobi Gershgorin radius >= 0.97) solve each level with
    Chebyshev iteration preconditioned by I + tau mu_a (-Delta_h), applied
-   through the DST-I (dense MFMA products; inexact, residual reduced 1e3-fold per
-   level solve unless opts->lin_tol says otherwise). Instances with different
+   approximately by one geometric multigrid V-cycle in float32 (residuals and
+   updates in float64; inexact, residual reduced 1e3-fold per level solve unless
+   opts->lin_tol says otherwise). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for
    instances that are not one problem) or opts->window > 1 are solved one after
    another with pts_solve.

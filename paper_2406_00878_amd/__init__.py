@@ -24,6 +24,7 @@ from ._lib import (PTS_BURGERS, PTS_DIRICHLET, PTS_ERR_HIP, PTS_FP64, PTS_HEAT, 
                    pts_stats)
 
 __all__ = ["PTSError", "make_problem", "workspace", "init_plain", "assemble", "newton_step", "newton_step_static",
+           "products_workspace", "newton_step_products", "solve_products", "product_diamond",
            "solve", "autotune",
            "solve_batched", "autotune_batched", "batched_workspace", "coarse_workspace", "coarse_initial_iterate",
            "coarse_workspace_batched", "coarse_initial_iterate_batched", "window_bound",
@@ -68,8 +69,11 @@ def _dev_f64(t: torch.Tensor, shape, name):
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
-def make_problem(prob, precision: str = "fp64", bdata: Optional[torch.Tensor] = None) -> pts_problem:
-    """Fill a pts_problem from a problem description."""
+def make_problem(prob, precision: str = "fp64", bdata: Optional[torch.Tensor] = None,
+                 dts: Optional[torch.Tensor] = None) -> pts_problem:
+    """Fill a pts_problem from a problem description. Per-level step sizes come from `dts` (a
+    device float64 tensor of nt entries) or, when that is None, from the description's `dts`
+    array (copied to the device and kept alive with the returned structure)."""
     p = pts_problem()
     p.kind = int(prob.kind)
     p.bc = int(prob.bc)
@@ -82,6 +86,14 @@ def make_problem(prob, precision: str = "fp64", bdata: Optional[torch.Tensor] = 
         p.bdata = bdata.data_ptr()
     else:
         p.bdata = None
+    if dts is None and getattr(prob, "dts", None) is not None:
+        dts = torch.as_tensor(prob.dts, dtype=torch.float64, device="cuda").contiguous()
+    if dts is not None:
+        _dev_f64(dts, (p.nt,), "dts")
+        p.dt_levels = dts.data_ptr()
+        p._dts = dts  # keeps the device copy alive as long as the structure
+    else:
+        p.dt_levels = None
     return p
 
 
@@ -128,6 +140,7 @@ def _stats_dict(st: pts_stats) -> dict:
         "rho_max": list(st.rho_max[:n]), "solve_ms": st.solve_ms,
         "prof_ms": list(st.prof_ms), "prof_count": list(st.prof_count),
         "level_solve_bytes": st.level_solve_bytes,
+        "kern_ms": list(st.kern_ms), "kern_count": list(st.kern_count), "kern_bytes": list(st.kern_bytes),
     }
 
 
@@ -179,6 +192,51 @@ def newton_step_static(prob, U, u0, bdata=None, precision="fp64", stream=None, *
     _check(_lib_checked().pts_newton_step_static(C.byref(p), _ptr(U), _ptr(u0), C.byref(o), C.byref(st),
                                                  _stream(stream)))
     return _stats_dict(st)
+
+
+def products_workspace(prob, device="cuda") -> torch.Tensor:
+    """Device workspace of the explicit-product form (pts_products_workspace_bytes)."""
+    p = make_problem(prob)
+    nbytes = _lib_checked().pts_products_workspace_bytes(C.byref(p))
+    if nbytes == 0:
+        _check(_lib.PTS_ERR_INVALID_ARG)
+    return _aligned_bytes(nbytes, device)
+
+
+def newton_step_products(prob, U, u0, bdata=None, ws=None, stream=None) -> dict:
+    """One Newton step in the paper's explicit-product form (Theorem 1, Eq. (8))."""
+    p = make_problem(prob, "fp64", bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = products_workspace(prob, U.device) if ws is None else ws
+    st = pts_stats()
+    _check(_lib_checked().pts_newton_step_products(C.byref(p), _ptr(U), _ptr(u0), _ptr(ws), ws.numel(),
+                                                   C.byref(st), _stream(stream)))
+    return _stats_dict(st)
+
+
+def solve_products(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, ws=None, stream=None) -> dict:
+    """Newton iteration with every step in the explicit-product form."""
+    p = make_problem(prob, "fp64", bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = products_workspace(prob, U.device) if ws is None else ws
+    st = pts_stats()
+    _check(_lib_checked().pts_solve_products(C.byref(p), _ptr(U), _ptr(u0), float(tol), int(max_iter), _ptr(ws),
+                                             ws.numel(), C.byref(st), _stream(stream)))
+    return _stats_dict(st)
+
+
+def product_diamond(prob, U, u0, n, bdata=None, ws=None, stream=None) -> torch.Tensor:
+    """P^n = A_1 ... A_n at U in diamond storage, shape (2n^2 + 2n + 1, ny, nx)."""
+    p = make_problem(prob, "fp64", bdata)
+    _dev_f64(U, (p.nt, p.ny, p.nx), "U")
+    _dev_f64(u0, (p.ny, p.nx), "u0")
+    ws = products_workspace(prob, U.device) if ws is None else ws
+    out = torch.empty((2 * n * n + 2 * n + 1, p.ny, p.nx), dtype=torch.float64, device=U.device)
+    _check(_lib_checked().pts_product_diamond(C.byref(p), _ptr(U), _ptr(u0), int(n), _ptr(out), _ptr(ws), ws.numel(),
+                                              _stream(stream)))
+    return out
 
 
 def solve(prob, U, u0, tol=1e-12, max_iter=50, bdata=None, precision="fp64", ws=None, stream=None,
@@ -242,7 +300,9 @@ def batched_workspace(probs, precision="fp64", device="cuda", bdatas=None) -> to
 def _batched_args(probs, Us, u0s, bdatas, precision, ws):
     n = len(probs)
     bdatas = bdatas or [None] * n
-    arr = (pts_problem * n)(*[make_problem(q, precision, b) for q, b in zip(probs, bdatas)])
+    structs = [make_problem(q, precision, b) for q, b in zip(probs, bdatas)]
+    arr = (pts_problem * n)(*structs)
+    arr._keep = structs  # their device copies of per-level steps stay alive with the array
     for q, U, u0 in zip(probs, Us, u0s):
         _dev_f64(U, (q.nt, q.ny, q.nx), "U")
         _dev_f64(u0, (q.ny, q.nx), "u0")

@@ -18,13 +18,15 @@ PTS_ERR_NONFINITE = -3
 PTS_ERR_SINGULAR = -4
 PTS_ERR_NOT_CONVERGED = -5
 PTS_ERR_WORKSPACE = -6
+PTS_ERR_NOT_DOMINANT = -7
 PTS_MAX_HIST = 64
 
 
 class pts_problem(C.Structure):
     _fields_ = [("kind", C.c_int32), ("bc", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nt", C.c_int32), ("precision", C.c_int32), ("hx", C.c_double), ("hy", C.c_double),
-                ("dt", C.c_double), ("mu_a", C.c_double), ("mu_b", C.c_double), ("bdata", C.c_void_p)]
+                ("dt", C.c_double), ("mu_a", C.c_double), ("mu_b", C.c_double), ("bdata", C.c_void_p),
+                ("dt_levels", C.c_void_p)]
 
 
 class pts_options(C.Structure):
@@ -41,7 +43,8 @@ class pts_stats(C.Structure):
                 ("res_inf", C.c_double * PTS_MAX_HIST), ("upd_rms", C.c_double * PTS_MAX_HIST),
                 ("rho_max", C.c_double * PTS_MAX_HIST), ("solve_ms", C.c_double),
                 ("prof_ms", C.c_double * 4), ("prof_count", C.c_int32 * 4),
-                ("level_solve_bytes", C.c_double)]
+                ("level_solve_bytes", C.c_double), ("kern_ms", C.c_double * 8),
+                ("kern_count", C.c_int32 * 8), ("kern_bytes", C.c_double * 8)]
 
 
 _lib = None
@@ -63,6 +66,10 @@ def load():
         "pts_newton_step": (I, [P, V, V, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_newton_step_static": (I, [P, V, V, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_solve": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
+        "pts_products_workspace_bytes": (S, [P]),
+        "pts_newton_step_products": (I, [P, V, V, V, S, C.POINTER(pts_stats), V]),
+        "pts_solve_products": (I, [P, V, V, D, I, V, S, C.POINTER(pts_stats), V]),
+        "pts_product_diamond": (I, [P, V, V, I, V, V, S, V]),
         "pts_autotune": (I, [P, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),
         "pts_workspace_bytes_batched": (S, [P, I]),
         "pts_solve_batched": (I, [P, I, V, V, D, I, V, S, C.POINTER(pts_options), C.POINTER(pts_stats), V]),

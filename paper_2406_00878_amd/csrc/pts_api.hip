@@ -24,6 +24,8 @@
 #include "../../include/pts.h"
 #include "../../include/pts_no.h"
 #include "pts_kernels.hip"
+#include "pts_band.hpp"
+#include "pts_prod.hpp"
 
 using namespace pts;
 
@@ -93,17 +95,9 @@ KProb kprob(const pts_problem* p) {
   k.cy = 0.5 * k.cf * k.ihy;
   k.vx = k.mu_a * k.ihx2;
   k.vy = k.mu_a * k.ihy2;
-  k.ax = k.dt * k.vx;
-  k.ay = k.dt * k.vy;
-  k.bx = k.dt * k.cf * k.ihx;
-  k.by = k.dt * k.cf * k.ihy;
-  k.c0 = 1.0 + 2.0 * (k.ax + k.ay);
-  k.ic0 = 1.0 / k.c0;
   k.vp = 2.0 * (k.vx + k.vy);
-  k.axs = k.ax * k.ic0;
-  k.ays = k.ay * k.ic0;
-  k.bxs = k.bx * k.ic0;
-  k.bys = k.by * k.ic0;
+  fold_tau(k);
+  k.dts = p->dt_levels;
   return k;
 }
 
@@ -112,8 +106,14 @@ constexpr int kMaxStages = 16;  // Newton iterations overlapped by one wavefront
 constexpr int kMaxWindow = 64;  // longest Theorem-1 window
 
 struct Layout {
-  size_t R, dU, Xs, rho, scal, partial, rms, U1, rho_part, res_part, res_st, bar, u0copy, win, total;
+  size_t R, dU, Xs, rho, scal, partial, rms, U1, rho_part, res_part, res_st, bar, u0copy, win, band, bstat, total;
 };
+
+// The banded direct level solve (pts_band.hpp) applies to Dirichlet problems of at most
+// kBandMaxW nodes per direction; its factors take nt x nx ny x (2 nx + 1) doubles.
+bool band_ok(const pts_problem* p) {
+  return p->bc == PTS_DIRICHLET && p->nx <= kBandMaxW && p->ny <= kBandMaxW;
+}
 
 // Most tiles per level any wavefront plan uses: the deepest halo leaves 16 x 16 tiles (a
 // small Dirichlet domain is one whole region).
@@ -158,6 +158,10 @@ Layout layout(const pts_problem* p) {
   o = align_up(o + ns * 8);
   L.win = o;  // Theorem-1 windows: right-hand sides of a window plus two chain vectors
   o = align_up(o + (size_t)(std::min(kMaxWindow, p->nt) + 2) * ns * 8);
+  L.band = o;  // banded LU factors of every level (band_ok problems only)
+  o = align_up(o + (band_ok(p) ? st * (2 * (size_t)p->nx + 1) * 8 : 0));
+  L.bstat = o;  // per-level zero-pivot flags of the factorisation
+  o = align_up(o + (band_ok(p) ? (size_t)p->nt * 4 : 0));
   L.total = o;
   return L;
 }
@@ -277,6 +281,18 @@ int flux_form(const pts_problem* p) {
   return kFormGeneral;
 }
 
+// Level solver for blocks whose Jacobi-scaled Gershgorin radius is rho: the register-resident
+// Chebyshev iteration needs rho < 1 (a Gershgorin disc bounds the Jacobi spectrum) and a real
+// spectrum; with a complex one (central convection at cell Peclet numbers above 2, flagged by
+// cplx) Chebyshev on [-rho, rho] diverges once rho exceeds 1/sqrt(2). Returns 0 (Chebyshev),
+// 1 (banded direct solve) or -1 (neither applies).
+constexpr double kCplxRho = 0.7;
+int level_solver(const pts_problem* p, double rho, bool cplx) {
+  const bool cheb = rho < 1.0 && !(cplx && rho > kCplxRho);
+  if (cheb) return 0;
+  return band_ok(p) ? 1 : -1;
+}
+
 // The all-level residual kernel for a problem's boundary kind and flux form.
 typedef void (*ResidualKernel)(KProb, const double*, const double*, double*, double*, unsigned long long*);
 ResidualKernel residual_kernel(const pts_problem* p) {
@@ -297,6 +313,20 @@ int launch_residual(const pts_problem* p, const KProb& kp, const double* U, cons
   dim3 grid((unsigned)(tilesx * tilesy), (unsigned)p->nt);
   hipLaunchKernelGGL(residual_kernel(p), grid, dim3(256), 0, s, kp, U, u0, R, coef, lvl_bits);
   if (scal) hipLaunchKernelGGL(k_level_max, dim3(1), dim3(256), 0, s, lvl_bits, p->nt, scal);
+  HIPCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+// Eq. (7) by banded direct solves (Section 8): every level's block factorised in one launch,
+// then the chain of substitutions in one work-group; a zero pivot is reported by the next
+// status check (status words per level in the workspace).
+int launch_band(const pts_problem* p, const KProb& kp, const double* U, const double* R, double* dU, double* B,
+                int* bstat, hipStream_t s, int* launches) {
+  auto fac = flux_form(p) == kFormConstVisc ? k_band_factor<kFormConstVisc>
+             : (flux_form(p) == kFormNoConv ? k_band_factor<kFormNoConv> : k_band_factor<kFormGeneral>);
+  hipLaunchKernelGGL(fac, dim3((unsigned)p->nt), dim3(256), 0, s, kp, U, B, bstat);
+  hipLaunchKernelGGL(k_band_chain, dim3(1), dim3(64), 0, s, p->nx, p->ny, p->nt, (const double*)B, R, dU);
+  *launches += 2;
   HIPCHK(hipGetLastError());
   return PTS_OK;
 }
@@ -444,32 +474,57 @@ int static_scratch(void** out) {
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 struct Prof {
   struct Rec {
-    int kind;
+    int kind;  // 0..3: pts_stats.prof_ms classes; kKern + j: pts_stats.kern_ms[j]
     hipEvent_t a, b;
-    int count;  // launches the interval covers
+    int count;     // launches the interval covers
+    double bytes;  // algorithmic bytes of those launches
   };
+  static constexpr int kKern = 8;
   std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;  // events of collected records, reused
   double bytes = 0.0;
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else {
+      (void)hipEventCreate(&e);
+    }
+    return e;
+  }
   void begin(int kind, hipStream_t s) {
-    Rec r{kind, nullptr, nullptr, 1};
-    (void)hipEventCreate(&r.a);
-    (void)hipEventCreate(&r.b);
+    Rec r{kind, event(), event(), 1, 0.0};
     (void)hipEventRecord(r.a, s);
     recs.push_back(r);
   }
   void end(hipStream_t s) { (void)hipEventRecord(recs.back().b, s); }
+  // add the recorded intervals to st (the stream must have reached them)
   void collect(pts_stats* st) {
     for (auto& r : recs) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && st) {
-        st->prof_ms[r.kind] += ms;
-        st->prof_count[r.kind] += r.count;
+        if (r.kind < kKern) {
+          st->prof_ms[r.kind] += ms;
+          st->prof_count[r.kind] += r.count;
+        } else {
+          st->kern_ms[r.kind - kKern] += ms;
+          st->kern_count[r.kind - kKern] += r.count;
+          st->kern_bytes[r.kind - kKern] += r.bytes;
+        }
       }
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+      pool.push_back(r.a);
+      pool.push_back(r.b);
     }
     recs.clear();
     if (st) st->level_solve_bytes = bytes;
+  }
+  ~Prof() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -532,10 +587,22 @@ struct Instance {
 
   int window = 1;
   char* wsb = nullptr;
+  bool band = false;  // level solves by banded LU (pts_band.hpp) instead of Chebyshev
+  int bflag = 0;      // host copy of the zero-pivot flag of the last factorisation
 
   int step_body(double* U, const Plan& pl, hipStream_t s, int* launches) {
-    int rc = window > 1 ? launch_windows(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, window, wsb, L, s, launches)
-                        : launch_chain(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, s, launches, prof);
+    int rc = PTS_OK;
+    if (band) {
+      int* bstat = (int*)(wsb + L.bstat);
+      hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (unsigned long long*)bstat, 1);
+      ++*launches;
+      prof_begin(prof, 1, s);
+      rc = launch_band(p, kp, U, R, dU, (double*)(wsb + L.band), bstat, s, launches);
+      prof_end(prof, s, 0.0);
+    } else {
+      rc = window > 1 ? launch_windows(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, window, wsb, L, s, launches)
+                      : launch_chain(p, kp, U, R, dU, Xs, (const double*)rho, pl, g, s, launches, prof);
+    }
     if (rc) return rc;
     const size_t count = (size_t)p->nx * p->ny * p->nt;
     prof_begin(prof, 2, s);
@@ -550,6 +617,7 @@ struct Instance {
   int read_scalars(double* hs, bool with_rms, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(hs, scal, 16, hipMemcpyDeviceToHost, s));
     if (with_rms) HIPCHK(hipMemcpyAsync(hs + 2, rms, 8, hipMemcpyDeviceToHost, s));
+    if (band) HIPCHK(hipMemcpyAsync(&bflag, wsb + L.bstat, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return PTS_OK;
   }
@@ -614,10 +682,35 @@ int capture_step(Instance& in, double* U, const double* u0, const Plan& pl, hipS
   return PTS_OK;
 }
 
+// Whether central convection may give the Jacobi iteration matrix complex eigenvalues: the
+// off-diagonal pair of a row, -a - b u_W and -a + b u_E (a = tau mu / h^2, b = tau cflux / h),
+// has entries of opposite sign once b |u| > a, i.e. at cell Peclet numbers |u| h / mu above
+// 1 / cflux = 2. |u| is bounded by the data (max |u0|, max |bdata|, with a 5 % margin for
+// overshoots of the discrete solution) and mu >= mu_a. Reads two scalars back (synchronises).
+int convection_flag(const pts_problem* p, const double* u0, void* ws, hipStream_t s, double* hbuf, bool* cplx) {
+  *cplx = false;
+  if (p->kind != PTS_BURGERS) return PTS_OK;
+  const Layout L = layout(p);
+  unsigned long long* sc = (unsigned long long*)((char*)ws + L.scal) + 2;
+  hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, u0, (size_t)p->nx * p->ny, sc);
+  if (p->bdata)
+    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(256), 0, s, p->bdata, (size_t)p->nt * 2 * (p->nx + p->ny), sc + 1);
+  else
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, sc + 1, 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hbuf, sc, 16, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double umax = 1.05 * std::max(hbuf[0], hbuf[1]);
+  const double h = std::max(p->hx, p->hy);
+  *cplx = p->mu_a > 0 ? 0.5 * umax * h / p->mu_a > 1.0 : umax > 0.0;
+  return PTS_OK;
+}
+
 // hs_caller: host buffer of 4 doubles for the scalars read back per step, or NULL for the
-// thread's pinned buffer.
+// thread's pinned buffer. cplx: see convection_flag.
 int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
-               const pts_options* o, pts_stats* st, hipStream_t s, bool single_step, double* hs_caller = nullptr) {
+               const pts_options* o, pts_stats* st, hipStream_t s, bool single_step, bool cplx,
+               double* hs_caller = nullptr) {
   Instance in;
   in.bind(p, ws);
   in.window = (o && o->window > 1) ? std::min(o->window, std::min(kMaxWindow, p->nt)) : 1;
@@ -658,10 +751,18 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
       if (profiling) prof.collect(st);
       return PTS_OK;
     }
-    if (rhom >= 1.0) {
+    if (in.band && in.bflag) {
       if (st) st->iterations = it;
-      return fail(PTS_ERR_SINGULAR, "block A_n not diagonally dominant (Gershgorin radius %.3g)", rhom);
+      return fail(PTS_ERR_SINGULAR, "zero pivot in the banded LU of a level block at Newton step %d", it);
     }
+    const int solver = level_solver(p, rhom, cplx);
+    if (solver < 0) {
+      if (st) st->iterations = it;
+      return fail(PTS_ERR_NOT_DOMINANT, "no convergent level solve: Gershgorin radius %.3g%s, and the banded LU "
+                  "needs a Dirichlet grid of at most %d nodes per direction", rhom,
+                  cplx ? " with cell Peclet numbers above 2" : "", kBandMaxW);
+    }
+    in.band = solver == 1;
     if ((single_step && it == 1) || (!single_step && it >= max_iter)) {
       if (st) {
         st->iterations = it;
@@ -678,12 +779,12 @@ int solve_bulk(const pts_problem* p, double* U, const double* u0, double tol, in
       pl = make_plan(p, o, std::min(planned_rho * 1.02, 0.999), in.g);
     }
     if (st) {
-      st->sweeps = pl.sweeps;
-      st->refine = pl.passes - 1;
-      st->window = in.window;
+      st->sweeps = in.band ? 0 : pl.sweeps;
+      st->refine = in.band ? 0 : pl.passes - 1;
+      st->window = in.band ? 1 : in.window;
       st->schedule = PTS_SCHED_BULK;
     }
-    if (use_graph) {
+    if (use_graph && !in.band) {
       if (sg.sweeps != pl.sweeps || sg.passes != pl.passes) {
         rc = capture_step(in, U, u0, pl, s, sg);
         if (rc) return rc;
@@ -993,7 +1094,7 @@ int run_wave_sequence(const pts_problem* p, const KProb& kp, const WaveArgs& wa,
 // PTS_ERR_INVALID_ARG with *fallback = true when the inner solve does not fit the
 // wavefront kernel (the caller then uses the bulk schedule).
 int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
-               const pts_options* o, pts_stats* st, hipStream_t s, bool* fallback) {
+               const pts_options* o, pts_stats* st, hipStream_t s, bool* fallback, bool cplx) {
   *fallback = false;
   Instance in;
   in.bind(p, ws);
@@ -1031,9 +1132,14 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
     }
     if (res <= tol && needed < 0) needed = it;
     if (res <= tol) break;
-    if (rhom >= 1.0) {
+    if (level_solver(p, rhom, cplx) != 0) {
+      if (it == 0) {  // the bulk schedule has the banded solve (or reports the error)
+        *fallback = true;
+        return PTS_ERR_INVALID_ARG;
+      }
       if (st) st->iterations = it;
-      return fail(PTS_ERR_SINGULAR, "block A_n not diagonally dominant (Gershgorin radius %.3g)", rhom);
+      return fail(PTS_ERR_NOT_DOMINANT, "Chebyshev level solves lost their convergence bound (Gershgorin radius "
+                  "%.3g%s) at Newton step %d", rhom, cplx ? ", cell Peclet numbers above 2" : "", it);
     }
     if (it >= max_iter) {
       if (st) {
@@ -1050,7 +1156,7 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
         *fallback = true;
         return PTS_ERR_INVALID_ARG;
       }
-      return fail(PTS_ERR_SINGULAR, "inner solve cannot reach the requested reduction (radius %.3g)", rhom);
+      return fail(PTS_ERR_NOT_DOMINANT, "inner solve cannot reach the requested reduction (radius %.3g)", rhom);
     }
     const Geo g = in.g.whole ? in.g : geometry(p, wave_halo(pl));
     plan_used = pl;
@@ -1143,6 +1249,13 @@ int solve_wave(const pts_problem* p, double* U, const double* u0, double tol, in
 // events on the stream) and cache the fastest. U is restored on return.
 int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
                   const pts_options* o, pts_stats* st, hipStream_t s) {
+  bool cplx = false;
+  {
+    double* hs;
+    int rc0 = host_scalars(&hs);
+    if (!rc0) rc0 = convection_flag(p, u0, ws, s, hs, &cplx);
+    if (rc0) return rc0;
+  }
   Instance in;
   in.bind(p, ws);
   const size_t bytes = (size_t)p->nx * p->ny * p->nt * 8;
@@ -1183,14 +1296,14 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
     pts_options o1 = oo;
     o1.sweeps = 0;
     o1.refine = -1;  // take the plan from the cache entry just written
-    int rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb);
+    int rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb, cplx);
     if (rc || !s1.converged) continue;
     const StageCache::E* ce = g_stage_cache.find(p, tol, ctag(o));
     const int steps = ce ? ce->steps : s1.iterations;
     // run 2: timed with the learned step count
     HIPCHK(hipMemcpyAsync(U, backup, bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipEventRecord(e0, s));
-    rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb);
+    rc = solve_wave(p, U, u0, tol, max_iter, ws, &o1, &s1, s, &fb, cplx);
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
     if (rc || !s1.converged) continue;
@@ -1229,17 +1342,23 @@ int autotune_wave(const pts_problem* p, double* U, const double* u0, double tol,
 // bulk when the inner plan does not fit the wavefront kernel).
 int solve_core(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* ws,
                const pts_options* o, pts_stats* st, hipStream_t s) {
-  const int sched = (o && o->window > 1) ? PTS_SCHED_BULK : (o ? o->schedule : PTS_SCHED_AUTO);
-  bool fallback = true;
-  int rc = PTS_OK;
+  // variable steps (Eq. (3) with tau_n) run the bulk schedule
+  if (p->dt_levels && o && o->schedule == PTS_SCHED_PIPELINE)
+    return fail(PTS_ERR_INVALID_ARG, "the wavefront schedule takes uniform steps (dt_levels is set)");
+  const int sched = ((o && o->window > 1) || p->dt_levels) ? PTS_SCHED_BULK : (o ? o->schedule : PTS_SCHED_AUTO);
+  bool fallback = true, cplx = false;
+  double* hs;
+  int rc = host_scalars(&hs);
+  if (!rc) rc = convection_flag(p, u0, ws, s, hs, &cplx);
+  if (rc) return rc;
   if (sched != PTS_SCHED_BULK) {
-    rc = solve_wave(p, U, u0, tol, max_iter, ws, o, st, s, &fallback);
+    rc = solve_wave(p, U, u0, tol, max_iter, ws, o, st, s, &fallback, cplx);
     if (fallback && sched == PTS_SCHED_PIPELINE)
       rc = fail(PTS_ERR_INVALID_ARG, "the inner solve does not fit the wavefront schedule");
   }
   if (fallback && sched != PTS_SCHED_PIPELINE) {
     if (st) std::memset(st, 0, sizeof *st);
-    rc = solve_bulk(p, U, u0, tol, max_iter, ws, o, st, s, false);
+    rc = solve_bulk(p, U, u0, tol, max_iter, ws, o, st, s, false, cplx);
   }
   return rc;
 }
@@ -1247,7 +1366,7 @@ int solve_core(const pts_problem* p, double* U, const double* u0, double tol, in
 // Divergence of plain Newton: a non-finite or exploding residual, or a block that lost
 // diagonal dominance on the way.
 bool diverged(int rc, const pts_stats& st) {
-  if (rc == PTS_ERR_NONFINITE || rc == PTS_ERR_SINGULAR) return true;
+  if (rc == PTS_ERR_NONFINITE || rc == PTS_ERR_SINGULAR || rc == PTS_ERR_NOT_DOMINANT) return true;
   if (rc != PTS_ERR_NOT_CONVERGED) return false;
   const int n = std::min(st.iterations, PTS_MAX_HIST - 1);
   double mx = 0.0;
@@ -1340,30 +1459,222 @@ int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, i
 
 }  // namespace
 
+// ------------------------------------------- Theorem 1 with explicit products (Section 5)
+// Workspace of the explicit-product form (pts_newton_step_products): residual, rows of every
+// A_n, two diamonds (P^{l-1}, P^l), the right-hand sides rt^l, the update, every level's band,
+// reduction slots, the zero-pivot flag and the band descriptors.
+struct ProdLayout {
+  size_t R, coef, D0, D1, RT, dU, lvl, scal, partial, rms, flag, desc, band, total;
+  std::vector<size_t> B;  // band of level l
+  std::vector<int> w;     // half-bandwidth of level l
+};
+int prod_w(const pts_problem* p, int l) {
+  const long long ns = (long long)p->nx * p->ny;
+  return (int)std::min<long long>((long long)l * p->nx, ns - 1);
+}
+ProdLayout prod_layout(const pts_problem* p) {
+  ProdLayout L;
+  const size_t ns = (size_t)p->nx * p->ny, st = ns * p->nt;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.R = take(st * 8);
+  L.coef = take(st * 5 * 8);
+  L.D0 = take((size_t)dia_count(p->nt) * ns * 8);
+  L.D1 = take((size_t)dia_count(p->nt) * ns * 8);
+  L.RT = take(st * 8);
+  L.dU = take(st * 8);
+  L.lvl = take((size_t)p->nt * 16);
+  L.scal = take(4 * 8);
+  L.partial = take(kUpdateBlocks * 8);
+  L.rms = take(8);
+  L.flag = take(8);
+  L.desc = take((size_t)p->nt * sizeof(BandLevel));
+  L.band = o;
+  for (int l = 1; l <= p->nt; ++l) {
+    L.w.push_back(prod_w(p, l));
+    L.B.push_back(take(ns * (2 * (size_t)prod_w(p, l) + 1) * 8));
+  }
+  L.total = o;
+  return L;
+}
+int prod_check(const pts_problem* p) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (p->bc != PTS_DIRICHLET)
+    return fail(PTS_ERR_INVALID_ARG, "explicit products: Dirichlet problems only (the band of a periodic grid wraps)");
+  return PTS_OK;
+}
+
+// Residual and rows of every A_n at U (launch_residual), then the recursion of Section 5 up to
+// level `upto`: rt^l and P^l (diamonds alternating between D0 and D1), and with `band` each
+// P^l scaled by its diagonal into level l's band (the bands zeroed beforehand). *last points
+// at the diamond of P^upto.
+int prod_products(const pts_problem* p, const ProdLayout& L, char* ws, const double* U, const double* u0, int upto,
+                  bool band, hipStream_t s, const double** last) {
+  const size_t ns = (size_t)p->nx * p->ny;
+  const KProb kp = kprob(p);
+  double* R = (double*)(ws + L.R);
+  double* coef = (double*)(ws + L.coef);
+  double* RT = (double*)(ws + L.RT);
+  int rc = launch_residual(p, kp, U, u0, R, coef, (unsigned long long*)(ws + L.lvl),
+                           (unsigned long long*)(ws + L.scal), s);
+  if (rc) return rc;
+  double* D[2] = {(double*)(ws + L.D0), (double*)(ws + L.D1)};
+  const unsigned nb = (unsigned)((ns + 255) / 256);
+  for (int l = 1; l <= upto; ++l) {
+    const double* Dp = D[(l + 1) & 1];
+    double* Dc = D[l & 1];
+    double* rt = RT + (size_t)(l - 1) * ns;
+    hipLaunchKernelGGL(k_prod_rhs, dim3(nb), dim3(256), 0, s, p->nx, p->ny, l, Dp, R + (size_t)(l - 1) * ns,
+                       l > 1 ? rt - ns : rt, rt);
+    const size_t ne = (size_t)dia_count(l) * ns;
+    hipLaunchKernelGGL(k_prod_level, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, p->nx, p->ny, l, Dp,
+                       coef + (size_t)(l - 1) * 5 * ns, Dc);
+    if (band)
+      hipLaunchKernelGGL(k_prod_band, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, p->nx, p->ny, l,
+                         L.w[l - 1], (const double*)Dc, (double*)(ws + L.B[l - 1]), rt);
+    *last = Dc;
+  }
+  HIPCHK(hipGetLastError());
+  return PTS_OK;
+}
+
+// One Newton step in the explicit-product form: assemble, scale and factor every level's
+// P^l, solve, U += dU. res (host) receives max |R(U_in)|; the zero-pivot flag is checked.
+int prod_step(const pts_problem* p, double* U, const double* u0, char* ws, const ProdLayout& L, pts_stats* st,
+              int it, hipStream_t s, double* hs) {
+  const size_t ns = (size_t)p->nx * p->ny;
+  // band descriptors and zeroed bands, flag
+  std::vector<BandLevel> bl(p->nt);
+  for (int l = 1; l <= p->nt; ++l) bl[l - 1] = BandLevel{(double*)(ws + L.B[l - 1]), L.w[l - 1]};
+  HIPCHK(hipMemcpyAsync(ws + L.desc, bl.data(), bl.size() * sizeof(BandLevel), hipMemcpyHostToDevice, s));
+  {
+    const size_t words = (L.total - L.band) / 8;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>((words + 255) / 256, 65535)), dim3(256), 0, s,
+                       (unsigned long long*)(ws + L.band), (int)std::min<size_t>(words, 0x7fffffff));
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (unsigned long long*)(ws + L.flag), 1);
+  }
+  const double* last = nullptr;
+  int rc = prod_products(p, L, ws, U, u0, p->nt, true, s, &last);
+  if (rc) return rc;
+  double* RT = (double*)(ws + L.RT);
+  // blocked band LU of every level, then the solves
+  const BandLevel* dl = (const BandLevel*)(ws + L.desc);
+  int* flag = (int*)(ws + L.flag);
+  const int wmax = L.w.back();
+  const int tmax = (wmax + 63) / 64;
+  for (int k0 = 0; k0 < (int)ns; k0 += kPb) {
+    hipLaunchKernelGGL(k_blu_panel, dim3((unsigned)p->nt), dim3(256), 0, s, dl, (int)ns, k0, flag);
+    hipLaunchKernelGGL(k_blu_trsm, dim3((unsigned)((wmax + 255) / 256), (unsigned)p->nt), dim3(256), 0, s, dl,
+                       (int)ns, k0);
+    hipLaunchKernelGGL(k_blu_gemm, dim3((unsigned)(tmax * tmax), (unsigned)p->nt), dim3(256), 0, s, dl, (int)ns,
+                       k0);
+  }
+  double* dU = (double*)(ws + L.dU);
+  hipLaunchKernelGGL(k_blu_solve, dim3((unsigned)p->nt), dim3(256), 0, s, dl, (int)ns, (const double*)RT, dU);
+  const size_t count = ns * p->nt;
+  hipLaunchKernelGGL(k_update, dim3(kUpdateBlocks), dim3(256), 0, s, count, U, dU, (double*)(ws + L.partial));
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, (const double*)(ws + L.partial), kUpdateBlocks,
+                     (double*)(ws + L.rms));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(hs, ws + L.scal, 16, hipMemcpyDeviceToHost, s));  // max |R(U_in)|
+  HIPCHK(hipMemcpyAsync(hs + 2, ws + L.rms, 8, hipMemcpyDeviceToHost, s));
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(&fl, flag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st && it < PTS_MAX_HIST) {
+    st->res_inf[it] = hs[0];
+    if (it + 1 < PTS_MAX_HIST) st->upd_rms[it + 1] = std::sqrt(hs[2] / (double)count);
+  }
+  if (!std::isfinite(hs[0])) return fail(PTS_ERR_NONFINITE, "explicit products: non-finite residual at step %d", it);
+  if (fl) return fail(PTS_ERR_SINGULAR, "explicit products: zero pivot in the banded LU of a product P^l");
+  return PTS_OK;
+}
+
 // ---------------------------------------------------------------- batched bulk solve
 // Workspace of a batch: a header with the instance descriptors and the (instance, tile)
 // work items, then every instance's own workspace.
-// Dirichlet heat on square grids with equal spacings: the spectral (DST-preconditioned)
-// level solve applies.
-bool dst_eligible(const pts_problem* probs, int nprob) {
+// Dirichlet heat on square grids with equal spacings: the multigrid-preconditioned level
+// solve applies.
+bool mg_eligible(const pts_problem* probs, int nprob) {
   for (int i = 0; i < nprob; ++i) {
     const pts_problem& q = probs[i];
-    if (q.kind != PTS_HEAT || q.bc != PTS_DIRICHLET || q.nx != q.ny || q.hx != q.hy || !(q.mu_a > 0)) return false;
+    if (q.kind != PTS_HEAT || q.bc != PTS_DIRICHLET || q.nx != q.ny || q.hx != q.hy || !(q.mu_a > 0) || q.dt_levels)
+      return false;
   }
   return true;
 }
 
-// Row stride of the spectral solve's float32 arrays (16-byte rows for vector loads).
-int dst_ld(int N) { return (N + 3) / 4 * 4; }
+// V-cycle hierarchy of an N x N grid for M = I + c (-Delta_h) (array pointers left NULL).
+MgDesc mg_hierarchy(int N, double c) {
+  MgDesc d;
+  std::memset(&d, 0, sizeof d);
+  int n = N, l = 0;
+  d.G = -1;
+  for (;;) {
+    d.n[l] = n;
+    d.a[l] = (float)(c * (double)(n + 1) * (double)(n + 1));
+    if (d.G < 0 && n <= kMgLds) d.G = l;
+    ++l;
+    if (n <= kMgCoarsest || l == kMgLevels) break;
+    n = mg_coarse(n);
+  }
+  d.levels = l;
+  return d;
+}
 
-// Layout of the spectral solve's part of a batch header (after the level-solve part).
-struct DstLayout {
-  size_t desc, gemm, items_g, items_e, inst0, total;
-  std::vector<size_t> S, lam, r, z, t1, t2, d, K, coef, lmax;
-  size_t ng = 0, ne = 0;  // work items of the products and of the node kernels
+// Transfer tables of a hierarchy, grid after grid: k, w, own (n_l words each), sup (n_{l+1}
+// int2), each array 16-byte aligned.
+size_t mg_table_words(int n) { return (size_t)(n + 3) / 4 * 4; }
+size_t mg_table_bytes(const MgDesc& h) {
+  size_t b = 0;
+  for (int l = 0; l + 1 < h.levels; ++l) b += 4 * (3 * mg_table_words(h.n[l]) + 2 * mg_table_words(h.n[l + 1]));
+  return b;
+}
+// Fills the tables into host memory `host` and points h's table pointers at `dev`, the device
+// copy of the same bytes.
+void mg_fill_tables(MgDesc& h, char* host, char* dev) {
+  size_t o = 0;
+  for (int l = 0; l + 1 < h.levels; ++l) {
+    const int nf = h.n[l], nc = h.n[l + 1];
+    int* k = (int*)(host + o);
+    float* w = (float*)(host + o + 4 * mg_table_words(nf));
+    int* own = (int*)(host + o + 8 * mg_table_words(nf));
+    int2* sup = (int2*)(host + o + 12 * mg_table_words(nf));
+    mg_tables(nf, nc, k, w, own, sup);
+    h.tk[l] = (const int*)(dev + o);
+    h.tw[l] = (const float*)(dev + o + 4 * mg_table_words(nf));
+    h.to[l] = (const int*)(dev + o + 8 * mg_table_words(nf));
+    h.ts[l] = (const int2*)(dev + o + 12 * mg_table_words(nf));
+    o += 4 * (3 * mg_table_words(nf) + 2 * mg_table_words(nc));
+  }
+}
+
+// Tiles of grid l of a hierarchy for the down kernel (coarse tiles of grid l+1) and the up
+// kernel (fine tiles of grid l).
+int mg_down_tiles(const MgDesc& d, int l) {
+  const int t = (d.n[l + 1] + kMgTC - 1) / kMgTC;
+  return t * t;
+}
+int mg_up_tiles(const MgDesc& d, int l) {
+  const int t = (d.n[l] + kMgTF - 1) / kMgTF;
+  return t * t;
+}
+
+// Layout of the multigrid solve's part of a batch header (after the level-solve part).
+struct MgLayout {
+  size_t desc, mgdesc, items_e, items_e0, items_d, items_u, items_l, total;
+  std::vector<size_t> d, K, coef, lmax, tab;
+  std::vector<std::vector<size_t>> x, f, e;  // per instance, grids 0..G (e: 1..G-1)
+  size_t ne = 0, nd = 0, nu = 0;          // work item capacities
+  int gmax = 0;                           // most grids above the LDS part
 };
-DstLayout dst_layout(const pts_problem* probs, int nprob) {
-  DstLayout L;
+MgLayout mg_layout(const pts_problem* probs, int nprob) {
+  MgLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -1371,23 +1682,36 @@ DstLayout dst_layout(const pts_problem* probs, int nprob) {
     return at;
   };
   for (int i = 0; i < nprob; ++i) {
-    const size_t N = probs[i].nx, t = (N + pts_mm::BM - 1) / pts_mm::BM;
-    L.ng += t * t;
+    const size_t N = probs[i].nx;
     L.ne += (N * N + 255) / 256;
+    const MgDesc h = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
+    for (int l = 0; l < h.G; ++l) {
+      L.nd += mg_down_tiles(h, l);
+      L.nu += mg_up_tiles(h, l);
+    }
+    L.gmax = std::max(L.gmax, h.G);
   }
-  L.desc = take((size_t)nprob * sizeof(DstDesc));
-  L.gemm = take((size_t)4 * nprob * sizeof(pts_mm::Gemm));
-  L.items_g = take((size_t)nprob * L.ng * sizeof(int4));  // one list per prefix of the instances
+  L.desc = take((size_t)nprob * sizeof(PcDesc));
+  L.mgdesc = take((size_t)nprob * sizeof(MgDesc));
   L.items_e = take(L.ne * sizeof(int2));
+  L.items_e0 = take(L.ne * sizeof(int2));
+  L.items_d = take(std::max<size_t>(L.nd, 1) * sizeof(int4));
+  L.items_u = take(std::max<size_t>(L.nu, 1) * sizeof(int4));
+  L.items_l = take((size_t)nprob * sizeof(int));
+  L.x.resize(nprob);
+  L.f.resize(nprob);
+  L.e.resize(nprob);
   for (int i = 0; i < nprob; ++i) {
-    const size_t N = probs[i].nx, nn = N * N, nl = N * dst_ld(probs[i].nx);
-    L.S.push_back(take(nl * 4));
-    L.lam.push_back(take(N * 4));
-    L.r.push_back(take(nl * 4));
-    L.z.push_back(take(nl * 4));
-    L.t1.push_back(take(nl * 4));
-    L.t2.push_back(take(nl * 4));
-    L.d.push_back(take(nn * 8));
+    const size_t N = probs[i].nx;
+    const MgDesc h = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
+    for (int l = 0; l <= h.G; ++l) {
+      const size_t nn = (size_t)h.n[l] * h.n[l];
+      L.x[i].push_back(take(nn * 4));
+      L.f[i].push_back(take(nn * 4));
+      L.e[i].push_back(l >= 1 && l < h.G ? take(nn * 4) : 0);
+    }
+    L.tab.push_back(take(mg_table_bytes(h)));
+    L.d.push_back(take(N * N * 8));
     L.K.push_back(take((size_t)probs[i].nt * 4));
     L.coef.push_back(take((size_t)probs[i].nt * kMaxCheb * sizeof(float2)));
     L.lmax.push_back(take((size_t)probs[i].nt * 8));
@@ -1400,7 +1724,7 @@ size_t batch_header_bytes(const pts_problem* probs, int nprob) {
   size_t tiles_total = 0;
   for (int i = 0; i < nprob; ++i) tiles_total += (size_t)tiles(probs + i, geometry(probs + i));
   size_t b = align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
-  if (dst_eligible(probs, nprob)) b += dst_layout(probs, nprob).total;
+  if (mg_eligible(probs, nprob)) b += mg_layout(probs, nprob).total;
   return b;
 }
 
@@ -1446,9 +1770,10 @@ int host_stage(size_t bytes, char** out) {
 // Newton on every instance at once: per step, the all-level residuals, then for each level n
 // and launch l of the inner plans one launch over the tiles of every instance that has them
 // (k_level_solve_batched), then the updates. Instances leave the batch when they converge.
-// Stiff Dirichlet heat batches (Gershgorin radius >= kDstRho) solve their levels with the
-// DST-preconditioned Chebyshev iteration instead (k_dst_*), also in shared launches.
-constexpr double kDstRho = 0.97;
+// Stiff Dirichlet heat batches (Gershgorin radius >= kMgRho) solve their levels with the
+// multigrid-preconditioned Chebyshev iteration instead (k_pc_*, k_mg_*), also in shared
+// launches.
+constexpr double kMgRho = 0.97;
 int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, const double* const* u0, double tol,
                        int max_iter, char* header, char* wsb, const pts_options* o, pts_stats* stats,
                        hipStream_t s) {
@@ -1465,12 +1790,12 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     maxnt = std::max(maxnt, probs[i].nt);
     if (stats) std::memset(stats + i, 0, sizeof(pts_stats));
   }
-  const bool eligible = dst_eligible(probs, nprob);
+  const bool eligible = mg_eligible(probs, nprob);
   BatchDesc* d_desc = (BatchDesc*)header;
   int2* d_items = (int2*)(header + align_up((size_t)nprob * sizeof(BatchDesc)));
-  char* dst_base = header + align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
-  DstLayout DL;
-  if (eligible) DL = dst_layout(probs, nprob);
+  char* mg_base = header + align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
+  MgLayout DL;
+  if (eligible) DL = mg_layout(probs, nprob);
   // host staging: descriptors and items of both solvers, then the scalars read back
   size_t so = 0;
   auto stake = [&](size_t bytes) {
@@ -1479,10 +1804,17 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     return at;
   };
   const size_t s_desc = stake((size_t)nprob * sizeof(BatchDesc)), s_items = stake(tiles_total * sizeof(int2));
-  const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(DstDesc) : 0);
-  const size_t s_gm = stake(eligible ? (size_t)4 * nprob * sizeof(pts_mm::Gemm) : 0);
-  const size_t s_ig = stake(eligible ? (size_t)nprob * DL.ng * sizeof(int4) : 0);
+  const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(PcDesc) : 0);
+  const size_t s_mg = stake(eligible ? (size_t)nprob * sizeof(MgDesc) : 0);
+  const size_t s_id = stake(eligible ? DL.nd * sizeof(int4) : 0);
+  const size_t s_iu = stake(eligible ? DL.nu * sizeof(int4) : 0);
+  const size_t s_il = stake(eligible ? (size_t)nprob * sizeof(int) : 0);
   const size_t s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  const size_t s_ie0 = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  size_t tab_bytes = 0;
+  if (eligible)
+    for (int i = 0; i < nprob; ++i) tab_bytes += mg_table_bytes(mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a));
+  const size_t s_tab = stake(tab_bytes);
   size_t sum_nt = 0;
   for (int i = 0; i < nprob; ++i) sum_nt += probs[i].nt;
   const size_t s_kt = stake(eligible ? sum_nt * 4 : 0);
@@ -1494,17 +1826,26 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   if (rc) return rc;
   BatchDesc* h_desc = (BatchDesc*)(stage + s_desc);
   int2* h_items = (int2*)(stage + s_items);
-  DstDesc* h_dd = (DstDesc*)(stage + s_dd);
-  pts_mm::Gemm* h_gm = (pts_mm::Gemm*)(stage + s_gm);
-  int4* h_ig = (int4*)(stage + s_ig);
+  PcDesc* h_dd = (PcDesc*)(stage + s_dd);
+  MgDesc* h_mg = (MgDesc*)(stage + s_mg);
+  int4* h_id = (int4*)(stage + s_id);
+  int4* h_iu = (int4*)(stage + s_iu);
+  int* h_il = (int*)(stage + s_il);
   int2* h_ie = (int2*)(stage + s_ie);
+  int2* h_ie0 = (int2*)(stage + s_ie0);
   double* h_sc = (double*)(stage + s_sc);  // per instance: max|r|, rho_max, rms, max|u^0|
   std::vector<size_t> ofs_nt(nprob, 0);      // instance i's levels start at ofs_nt[i] in the per-level tables
   for (int i = 1; i < nprob; ++i) ofs_nt[i] = ofs_nt[i - 1] + probs[i - 1].nt;
   int* h_kt = (int*)(stage + s_kt);
   float2* h_cf = (float2*)(stage + s_cf);
   double* h_lm = (double*)(stage + s_lm);
-  bool use_dst = false;
+  bool use_mg = false;
+  // profiling (pts_options.profile): every launch of the multigrid-preconditioned level solves
+  // bracketed by HIP events, the intervals collected after each Newton step
+  Prof prof_obj;
+  Prof* prof = (o && o->profile) ? &prof_obj : nullptr;
+  pts_stats pstat;
+  std::memset(&pstat, 0, sizeof pstat);
   const bool fp32 = probs[0].precision == PTS_MIXED;
   const bool per = probs[0].bc == PTS_PERIODIC;
   auto kern = fp32 ? (per ? k_level_solve_batched<float, 1> : k_level_solve_batched<float, 0>)
@@ -1520,7 +1861,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       if (with_rms) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 2, in[i].rms, 8, hipMemcpyDeviceToHost, s));
       if (with_u0) HIPCHK(hipMemcpyAsync(h_sc + 4 * i + 3, in[i].scal + 3, 8, hipMemcpyDeviceToHost, s));
       if (with_levels)
-        HIPCHK(hipMemcpyAsync(h_lm + ofs_nt[i], dst_base + DL.lmax[i], (size_t)probs[i].nt * 8, hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(h_lm + ofs_nt[i], mg_base + DL.lmax[i], (size_t)probs[i].nt * 8, hipMemcpyDeviceToHost,
                               s));
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1529,7 +1870,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   // max |u^n| per level of the current iterate (the spectral solve's Chebyshev intervals)
   auto level_max = [&](int i) {
     hipLaunchKernelGGL(k_level_absmax, dim3((unsigned)probs[i].nt), dim3(256), 0, s, U[i],
-                       (size_t)probs[i].nx * probs[i].ny, (unsigned long long*)(dst_base + DL.lmax[i]));
+                       (size_t)probs[i].nx * probs[i].ny, (unsigned long long*)(mg_base + DL.lmax[i]));
     ++launches;
   };
   for (int i = 0; i < nprob; ++i) {
@@ -1539,56 +1880,24 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   if ((rc = read_all(false, false, eligible))) return rc;
   double rho0 = 0.0;
   for (int i = 0; i < nprob; ++i) rho0 = std::max(rho0, h_sc[4 * i + 1]);
-  use_dst = eligible && rho0 >= kDstRho;
-  if (use_dst) {
-    // bases, and the four products of M^{-1} per instance (fixed for the solve)
+  use_mg = eligible && rho0 >= kMgRho;
+  if (use_mg) {
+    // hierarchies (fixed for the solve)
+    size_t to = 0;
     for (int i = 0; i < nprob; ++i) {
-      const int N = probs[i].nx, ld = dst_ld(N);
-      float* S = (float*)(dst_base + DL.S[i]);
-      float* lam = (float*)(dst_base + DL.lam[i]);
-      hipLaunchKernelGGL(k_dst_setup, dim3((unsigned)(((size_t)N * ld + 255) / 256)), dim3(256), 0, s, N, ld,
-                         probs[i].hx, S, lam);
-      // r, z and the two intermediates: the columns beyond N are read as zeros by the products
-      for (size_t off : {DL.r[i], DL.z[i], DL.t1[i], DL.t2[i]}) {
-        const int words = (int)((size_t)N * ld * 4 / 8);
-        hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0, s,
-                           (unsigned long long*)(dst_base + off), words);
+      MgDesc& m = h_mg[i];
+      m = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
+      for (int l = 0; l <= m.G; ++l) {
+        m.x[l] = (float*)(mg_base + DL.x[i][l]);
+        m.f[l] = (float*)(mg_base + DL.f[i][l]);
+        m.e[l] = l >= 1 && l < m.G ? (float*)(mg_base + DL.e[i][l]) : nullptr;
       }
-      launches += 5;
-      const float c = (float)(probs[i].dt * probs[i].mu_a);  // M = I + tau mu_a (-Delta_h)
-      float* r = (float*)(dst_base + DL.r[i]);
-      float* z = (float*)(dst_base + DL.z[i]);
-      float* t1 = (float*)(dst_base + DL.t1[i]);
-      float* t2 = (float*)(dst_base + DL.t2[i]);
-      auto mk = [&](const float* A, const float* B, float* C, bool scale) {
-        pts_mm::Gemm g{};
-        g.A = A;
-        g.B = B;
-        g.C = C;
-        g.M = g.N = g.K = N;
-        g.sam = ld;
-        g.sak = 1;
-        g.sbk = ld;
-        g.sbn = 1;
-        g.scm = ld;
-        g.scn = 1;
-        g.alpha = 1.f;
-        g.beta = 0.f;
-        g.ksplit = 1;
-        if (scale) {
-          g.lam_m = lam;
-          g.lam_n = lam;
-          g.lam_c = c;
-        }
-        return g;
-      };
-      h_gm[0 * nprob + i] = mk(S, r, t1, false);
-      h_gm[1 * nprob + i] = mk(t1, S, t2, true);
-      h_gm[2 * nprob + i] = mk(S, t2, t1, false);
-      h_gm[3 * nprob + i] = mk(t1, S, z, false);
+      const size_t tb = mg_table_bytes(m);
+      mg_fill_tables(m, stage + s_tab + to, mg_base + DL.tab[i]);
+      HIPCHK(hipMemcpyAsync(mg_base + DL.tab[i], stage + s_tab + to, tb, hipMemcpyHostToDevice, s));
+      to += tb;
     }
-    HIPCHK(hipMemcpyAsync(dst_base + DL.gemm, h_gm, (size_t)4 * nprob * sizeof(pts_mm::Gemm), hipMemcpyHostToDevice,
-                          s));
+    HIPCHK(hipMemcpyAsync(mg_base + DL.mgdesc, h_mg, (size_t)nprob * sizeof(MgDesc), hipMemcpyHostToDevice, s));
   }
   for (int it = 0;; ++it) {
     int nactive = 0;
@@ -1617,7 +1926,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         active[i] = 0;
         continue;
       } else if (rhom >= 1.0) {
-        err = fail(PTS_ERR_SINGULAR, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom);
+        err = fail(PTS_ERR_NOT_DOMINANT, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom);
       } else if (it >= max_iter) {
         err = fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i, it,
                    res);
@@ -1627,7 +1936,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         active[i] = 0;
         continue;
       }
-      if (!use_dst) {
+      if (!use_mg) {
         plans[i] = make_plan(p, o, std::min(rhom * 1.02, 0.999), in[i].g);
         if (st) {
           st->sweeps = plans[i].sweeps;
@@ -1647,88 +1956,167 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       while (k > 0 && probs[order[k - 1]].nt <= n) --k;
       kpref[n] = k;
     }
-    if (use_dst) {
+    if (use_mg) {
       // inexact Newton: each level solve reduces its residual 1e3-fold by default (measured on
       // the heat batch: one Newton step more than at 1e-6, 30 % less time, same converged result)
       const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
-      std::vector<size_t> cg(order.size() + 1, 0), og(order.size() + 1, 0), ce(order.size() + 1, 0);
-      size_t ng = 0, ne = 0;
+      const size_t no = order.size();
+      std::vector<size_t> ce(no + 1, 0), ce0(no + 1, 0);
+      // down/up items of step g (g = 0..gmax-1): instance i takes part when g >= gmax - G_i, on
+      // grid g - (gmax - G_i); cumulative counts per prefix of `order`
+      const int gmax = DL.gmax;
+      std::vector<std::vector<size_t>> cd(gmax, std::vector<size_t>(no + 1, 0)), cu = cd;
+      std::vector<size_t> od(gmax, 0), ou(gmax, 0);
+      size_t ne = 0, ne0 = 0, nd = 0, nu = 0;
       for (int i = 0; i < nprob; ++i) {
-        DstDesc& d = h_dd[i];
+        PcDesc& d = h_dd[i];
         std::memset(&d, 0, sizeof d);
         d.p = in[i].kp;
         d.U = U[i];
         d.R = in[i].R;
         d.dU = in[i].dU;
-        d.r = (float*)(dst_base + DL.r[i]);
-        d.z = (float*)(dst_base + DL.z[i]);
-        d.d = (double*)(dst_base + DL.d[i]);
-        d.K = (const int*)(dst_base + DL.K[i]);
-        d.c = (const float2*)(dst_base + DL.coef[i]);
+        d.r = (float*)(mg_base + DL.f[i][0]);
+        d.z = (float*)(mg_base + DL.x[i][0]);
+        d.d = (double*)(mg_base + DL.d[i]);
+        d.K = (const int*)(mg_base + DL.K[i]);
+        d.c = (const float2*)(mg_base + DL.coef[i]);
         d.active = active[i];
-        d.ld = dst_ld(probs[i].nx);
+        d.ld = probs[i].nx;
         if (!active[i]) continue;
         // level n: with M = I + tau mu_a (-Delta_h) the preconditioned spectrum lies in
         // [1, mu_hi / mu_a], mu_hi = mu(1.1 max |u^n|); the margin m covers the non-symmetric
-        // mu' terms of the Jacobian (they grow with u) and the bfloat16 products
+        // mu' terms of the Jacobian (they grow with u) and float32 rounding; the V-cycle moves
+        // the lower end to kMgLow (1 - m)
         int kmax_i = 0;
         for (int n = 0; n < probs[i].nt; ++n) {
           const double um = 1.1 * h_lm[ofs_nt[i] + n];
           const double ratio = (probs[i].mu_a + probs[i].mu_b * um * um) / probs[i].mu_a;
           const double m = 0.05 + 0.15 * (ratio - 1.0);
           float c0[kMaxCheb], c1[kMaxCheb];
-          const int K = cheb_coefficients(1.0 - std::min(m, 0.5), ratio * (1.0 + m), lin_tol, c0, c1);
+          const int K = cheb_coefficients(kMgLow * (1.0 - std::min(m, 0.5)), ratio * (1.0 + m), lin_tol, c0, c1);
           h_kt[ofs_nt[i] + n] = K;
           for (int k = 0; k < K; ++k) h_cf[(ofs_nt[i] + n) * kMaxCheb + k] = make_float2(c0[k], c1[k]);
           kmax_i = std::max(kmax_i, K);
         }
-        HIPCHK(hipMemcpyAsync(dst_base + DL.K[i], h_kt + ofs_nt[i], (size_t)probs[i].nt * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(dst_base + DL.coef[i], h_cf + ofs_nt[i] * kMaxCheb,
+        HIPCHK(hipMemcpyAsync(mg_base + DL.K[i], h_kt + ofs_nt[i], (size_t)probs[i].nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(mg_base + DL.coef[i], h_cf + ofs_nt[i] * kMaxCheb,
                               (size_t)probs[i].nt * kMaxCheb * sizeof(float2), hipMemcpyHostToDevice, s));
         if (stats) {
           stats[i].sweeps = kmax_i;
           stats[i].refine = 0;
         }
       }
-      // node items: the instances that have level n are a prefix of `order`
-      for (size_t q = 0; q < order.size(); ++q) {
+      // node items and LDS items: the instances that have level n are a prefix of `order`
+      for (size_t q = 0; q < no; ++q) {
         const int i = order[q];
         const int N = probs[i].nx, ch = (N * N + 255) / 256;
         for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(i, c);
+        // a stored z (k_pc_update) only where the V-cycle is all in LDS; elsewhere the last
+        // up kernel applies the Chebyshev step
+        if (h_mg[i].G == 0)
+          for (int c = 0; c < ch; ++c) h_ie0[ne0++] = make_int2(i, c);
         ce[q + 1] = ne;
+        ce0[q + 1] = ne0;
+        h_il[q] = i;
       }
-      // product items: one list per prefix, its instances' tiles by grid size, largest first, so
-      // the longest chains of dependent K steps are dispatched in the first round of a launch
-      for (size_t k = 1; k <= order.size(); ++k) {
-        std::vector<int> inst(order.begin(), order.begin() + k);
-        std::stable_sort(inst.begin(), inst.end(), [&](int a, int b) { return probs[a].nx > probs[b].nx; });
-        og[k] = ng;
-        for (int i : inst) {
-          const int t = (probs[i].nx + pts_mm::BM - 1) / pts_mm::BM;
-          for (int a = 0; a < t; ++a)
-            for (int b = 0; b < t; ++b) h_ig[ng++] = make_int4(i, a, b, 0);
+      for (int g = 0; g < gmax; ++g) {
+        od[g] = nd;
+        ou[g] = nu;
+        for (size_t q = 0; q < no; ++q) {
+          const int i = order[q];
+          const MgDesc& m = h_mg[i];
+          const int l = g - (gmax - m.G);
+          if (l >= 0) {
+            const int td = (m.n[l + 1] + kMgTC - 1) / kMgTC, tu = (m.n[l] + kMgTF - 1) / kMgTF;
+            for (int ty = 0; ty < td; ++ty)
+              for (int tx = 0; tx < td; ++tx) h_id[nd++] = make_int4(i, l, tx, ty);
+            for (int ty = 0; ty < tu; ++ty)
+              for (int tx = 0; tx < tu; ++tx) h_iu[nu++] = make_int4(i, l, tx, ty);
+          }
+          cd[g][q + 1] = nd - od[g];
+          cu[g][q + 1] = nu - ou[g];
         }
-        cg[k] = ng - og[k];
       }
-      HIPCHK(hipMemcpyAsync(dst_base + DL.desc, h_dd, (size_t)nprob * sizeof(DstDesc), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(dst_base + DL.items_g, h_ig, ng * sizeof(int4), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(dst_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
-      const DstDesc* dd = (const DstDesc*)(dst_base + DL.desc);
-      const pts_mm::Gemm* gm = (const pts_mm::Gemm*)(dst_base + DL.gemm);
-      const int4* ig = (const int4*)(dst_base + DL.items_g);
-      const int2* ie = (const int2*)(dst_base + DL.items_e);
+      HIPCHK(hipMemcpyAsync(mg_base + DL.desc, h_dd, (size_t)nprob * sizeof(PcDesc), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(mg_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
+      if (ne0) HIPCHK(hipMemcpyAsync(mg_base + DL.items_e0, h_ie0, ne0 * sizeof(int2), hipMemcpyHostToDevice, s));
+      if (nd) HIPCHK(hipMemcpyAsync(mg_base + DL.items_d, h_id, nd * sizeof(int4), hipMemcpyHostToDevice, s));
+      if (nu) HIPCHK(hipMemcpyAsync(mg_base + DL.items_u, h_iu, nu * sizeof(int4), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(mg_base + DL.items_l, h_il, no * sizeof(int), hipMemcpyHostToDevice, s));
+      const PcDesc* dd = (const PcDesc*)(mg_base + DL.desc);
+      const MgDesc* dm = (const MgDesc*)(mg_base + DL.mgdesc);
+      const int2* ie = (const int2*)(mg_base + DL.items_e);
+      const int2* ie0 = (const int2*)(mg_base + DL.items_e0);
+      const int4* id = (const int4*)(mg_base + DL.items_d);
+      const int4* iu = (const int4*)(mg_base + DL.items_u);
+      const int* il = (const int*)(mg_base + DL.items_l);
+      // algorithmic bytes per node of the grid a launch works on (profiling): k_pc_resid reads
+      // u^n, r^n, du^{n-1}, x (8 B each) and writes r (4); k_mg_down reads f_l, writes x_l and
+      // f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l, x_{l+1}
+      // and writes e_l, on the finest grid instead the Chebyshev step's reads and writes of d and
+      // du^n (8 each); k_pc_update reads z (4), d, du^n and writes d, du^n (8 each)
+      auto kb = [&](int kind, int k, int n, int kk, int g) {
+        double b = 0.0;
+        for (int q = 0; q < k; ++q) {
+          const int i = order[q];
+          if (kk >= h_kt[ofs_nt[i] + n]) continue;
+          const MgDesc& m = h_mg[i];
+          const double N2 = (double)probs[i].nx * probs[i].nx;
+          const int l = g - (gmax - m.G);
+          switch (kind) {
+            case 0: b += N2 * (kk == 0 ? 20.0 : 36.0); break;
+            case 1: if (l >= 0) b += (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0; break;
+            case 2: b += (double)m.n[m.G] * m.n[m.G] * 8.0; break;
+            case 3:
+              if (l >= 0)
+                b += (double)m.n[l] * m.n[l] * (l == 0 ? 40.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0;
+              break;
+            default: b += N2 * (kk == 0 ? 28.0 : 36.0); break;
+          }
+        }
+        return b;
+      };
+      auto pb = [&](int kind) { prof_begin(prof, Prof::kKern + kind, s); };
+      auto pe = [&](int kind, double bytes) {
+        if (prof) {
+          prof->end(s);
+          prof->recs.back().bytes = bytes;
+        }
+      };
       for (int n = 0; n < maxnt; ++n) {
         const int k = kpref[n];
         if (k == 0) continue;
         int kn = 0;  // iterations of level n: the most any instance in the prefix needs
         for (int q = 0; q < k; ++q) kn = std::max(kn, h_kt[ofs_nt[order[q]] + n]);
         for (int kk = 0; kk < kn; ++kk) {
-          hipLaunchKernelGGL(k_dst_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
-          for (int stg = 0; stg < 4; ++stg)
-            hipLaunchKernelGGL(k_dst_gemm, dim3((unsigned)cg[k]), dim3(256), 0, s, gm, dd, ig + og[k], nprob, stg,
-                               n, kk);
-          hipLaunchKernelGGL(k_dst_update, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
-          launches += 6;
+          pb(0);
+          hipLaunchKernelGGL(k_pc_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
+          pe(0, prof ? kb(0, k, n, kk, 0) : 0.0);
+          ++launches;
+          for (int g = 0; g < gmax; ++g) {
+            if (!cd[g][k]) continue;
+            pb(1);
+            hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][k]), dim3(256), 0, s, dm, dd, id + od[g], n, kk);
+            pe(1, prof ? kb(1, k, n, kk, g) : 0.0);
+            ++launches;
+          }
+          pb(2);
+          hipLaunchKernelGGL(k_mg_lds, dim3((unsigned)k), dim3(1024), 0, s, dm, dd, il, n, kk);
+          pe(2, prof ? kb(2, k, n, kk, 0) : 0.0);
+          ++launches;
+          for (int g = gmax - 1; g >= 0; --g) {
+            if (!cu[g][k]) continue;
+            pb(3);
+            hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][k]), dim3(256), 0, s, dm, dd, iu + ou[g], n, kk);
+            pe(3, prof ? kb(3, k, n, kk, g) : 0.0);
+            ++launches;
+          }
+          if (ce0[k]) {
+            pb(4);
+            hipLaunchKernelGGL(k_pc_update, dim3((unsigned)ce0[k]), dim3(256), 0, s, dd, ie0, n, kk);
+            pe(4, prof ? kb(4, k, n, kk, 0) : 0.0);
+            ++launches;
+          }
         }
       }
     } else {
@@ -1772,17 +2160,44 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     HIPCHK(hipGetLastError());
     for (int i : order) {
       const size_t count = (size_t)probs[i].nx * probs[i].ny * probs[i].nt;
+      if (use_mg) prof_begin(prof, Prof::kKern + 6, s);
       hipLaunchKernelGGL(k_update, dim3(kUpdateBlocks), dim3(256), 0, s, count, U[i], in[i].dU, in[i].partial);
       hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in[i].partial, kUpdateBlocks, in[i].rms);
+      if (use_mg && prof) {  // read U, dU, write U
+        prof->end(s);
+        prof->recs.back().count = 2;
+        prof->recs.back().bytes = 24.0 * (double)count;
+      }
       launches += 2;
+      if (use_mg) prof_begin(prof, Prof::kKern + 5, s);
       if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
-      if (use_dst) level_max(i);
+      if (use_mg && prof) {  // read U, write R
+        prof->end(s);
+        prof->recs.back().count = 3;
+        prof->recs.back().bytes = 16.0 * (double)count;
+      }
+      if (use_mg) {
+        prof_begin(prof, Prof::kKern + 7, s);
+        level_max(i);
+        if (prof) {
+          prof->end(s);
+          prof->recs.back().bytes = 8.0 * (double)count;
+        }
+      }
     }
     HIPCHK(hipGetLastError());
-    if ((rc = read_all(true, false, use_dst))) return rc;
+    if ((rc = read_all(true, false, use_mg))) return rc;
+    if (prof) prof->collect(&pstat);
   }
   if (stats)
-    for (int i = 0; i < nprob; ++i) stats[i].launches = launches;
+    for (int i = 0; i < nprob; ++i) {
+      stats[i].launches = launches;
+      for (int j = 0; j < 8; ++j) {
+        stats[i].kern_ms[j] = pstat.kern_ms[j];
+        stats[i].kern_count[j] = pstat.kern_count[j];
+        stats[i].kern_bytes[j] = pstat.kern_bytes[j];
+      }
+    }
   return worst;
 }
 
@@ -1795,7 +2210,7 @@ bool same_problem(const pts_problem* probs, int nprob) {
     const pts_problem& b = probs[i];
     if (a.kind != b.kind || a.bc != b.bc || a.nx != b.nx || a.ny != b.ny || a.nt != b.nt ||
         a.precision != b.precision || a.hx != b.hx || a.hy != b.hy || a.dt != b.dt || a.mu_a != b.mu_a ||
-        a.mu_b != b.mu_b || a.bdata != b.bdata)
+        a.mu_b != b.mu_b || a.bdata != b.bdata || a.dt_levels != b.dt_levels)
       return false;
   }
   return true;
@@ -1814,6 +2229,12 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
   const pts_problem* p = probs;
   for (int i = 0; i < nprob; ++i) codes[i] = PTS_OK;
   const bool use_graph = !o || o->use_graph != 0;
+  // profiling: HIP events around each sequence (its replayed graph) on `s`; time / launches is
+  // the mean launch interval of k_level_wave_batch
+  Prof wprof;
+  const bool profiling = o && o->profile;
+  pts_stats wst;
+  std::memset(&wst, 0, sizeof wst);
   const size_t ns = (size_t)p->nx * p->ny, st_count = ns * p->nt;
   std::vector<Instance> in(nprob);
   std::vector<char*> base(nprob);
@@ -1878,7 +2299,7 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
         if (st) st->converged = 1;
         drop(i, PTS_OK);
       } else if (rhom >= 1.0) {
-        drop(i, fail(PTS_ERR_SINGULAR, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom));
+        drop(i, fail(PTS_ERR_NOT_DOMINANT, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom));
       } else if (it >= max_iter) {
         drop(i, fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i,
                      it, res));
@@ -1900,7 +2321,7 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
         return PTS_ERR_INVALID_ARG;
       }
       for (int i : act)
-        drop(i, fail(PTS_ERR_SINGULAR, "instance %d: inner solve cannot reach the requested reduction", i));
+        drop(i, fail(PTS_ERR_NOT_DOMINANT, "instance %d: inner solve cannot reach the requested reduction", i));
       break;
     }
     const Geo g = in[0].g.whole ? in[0].g : geometry(p, wave_halo(pl));
@@ -1937,6 +2358,7 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
       HIPCHK(hipGetLastError());
       return PTS_OK;
     };
+    if (profiling) wprof.begin(1, s);
     if (use_graph) {
       // the arguments are read from the header at run time: the key holds what the
       // launches themselves carry
@@ -1947,6 +2369,11 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
     } else {
       rc = launch_seq(s);
       launches += ndiag;
+    }
+    if (profiling) {
+      wprof.end(s);
+      wprof.recs.back().count = ndiag;
+      for (int d = 0; d < ndiag; ++d) wprof.bytes += nb * wave_bytes(p, K, d);
     }
     if (rc) return rc;
     for (int i : act) {
@@ -1998,8 +2425,16 @@ int solve_wave_batched(const pts_problem* probs, int nprob, double* const* U, co
     if (!ce || (ce->sweeps == plan_used.sweeps && ce->passes == plan_used.passes) || ce->sweeps == 0)
       g_stage_cache.put(p, tol, ctag(o), plan_used.sweeps, plan_used.passes, std::max(most, 1), true, 1);
   }
+  if (profiling) wprof.collect(&wst);
   if (stats)
-    for (int i = 0; i < nprob; ++i) stats[i].launches = launches;
+    for (int i = 0; i < nprob; ++i) {
+      stats[i].launches = launches;
+      if (profiling) {
+        stats[i].prof_ms[1] = wst.prof_ms[1];
+        stats[i].prof_count[1] = wst.prof_count[1];
+        stats[i].level_solve_bytes = wst.level_solve_bytes;
+      }
+    }
   return worst;
 }
 
@@ -2241,6 +2676,7 @@ void axis_dev_fill(const AxisSpline& A, bool edges, const AxisDev& D, char* host
 // The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve).
 int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
   if (cf < 2 || p->nt % cf) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must be >= 2 and divide nt");
+  if (p->dt_levels) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: uniform steps only (dt_levels is set)");
   *pc = *p;
   if (p->bc == PTS_PERIODIC) {
     if (p->nx % cf || p->ny % cf || p->nx / cf < 3 || p->ny / cf < 3)
@@ -2532,7 +2968,12 @@ int pts_newton_step(const pts_problem* p, double* U, const double* u0, void* wor
   if (!rc) rc = check_ws(p, workspace, workspace_bytes);
   if (rc) return rc;
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_newton_step: NULL array");
-  return solve_bulk(p, U, u0, 0.0, 1, workspace, opts, stats, (hipStream_t)stream, true);
+  double* hs;
+  bool cplx = false;
+  rc = host_scalars(&hs);
+  if (!rc) rc = convection_flag(p, u0, workspace, (hipStream_t)stream, hs, &cplx);
+  if (rc) return rc;
+  return solve_bulk(p, U, u0, 0.0, 1, workspace, opts, stats, (hipStream_t)stream, true, cplx);
 }
 
 int pts_newton_step_static(const pts_problem* p, double* U, const double* u0, const pts_options* opts,
@@ -2552,7 +2993,109 @@ int pts_newton_step_static(const pts_problem* p, double* U, const double* u0, co
   rc = static_scratch(&ws);
   if (rc) return rc;
   double hs[4] = {0.0, 0.0, 0.0, 0.0};
-  return solve_bulk(p, U, u0, 0.0, 1, ws, opts, stats, (hipStream_t)stream, true, hs);
+  bool cplx = false;
+  rc = convection_flag(p, u0, ws, (hipStream_t)stream, hs, &cplx);
+  if (rc) return rc;
+  return solve_bulk(p, U, u0, 0.0, 1, ws, opts, stats, (hipStream_t)stream, true, cplx, hs);
+}
+
+size_t pts_products_workspace_bytes(const pts_problem* p) {
+  if (prod_check(p)) return 0;
+  const ProdLayout L = prod_layout(p);
+  if ((L.total - L.band) / 8 > 0x7fffffffull) {
+    fail(PTS_ERR_INVALID_ARG, "explicit products: the bands exceed 2^31 words");
+    return 0;
+  }
+  return L.total;
+}
+
+}  // extern "C"
+
+namespace {
+int prod_args(const pts_problem* p, const double* U, const double* u0, void* ws, size_t bytes) {
+  int rc = prod_check(p);
+  if (rc) return rc;
+  if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "explicit products: NULL array");
+  const size_t need = pts_products_workspace_bytes(p);
+  if (need == 0) return PTS_ERR_INVALID_ARG;
+  if (!ws || bytes < need) return fail(PTS_ERR_WORKSPACE, "explicit products: workspace %zu < %zu bytes", bytes, need);
+  if ((uintptr_t)ws % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return PTS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pts_newton_step_products(const pts_problem* p, double* U, const double* u0, void* workspace,
+                             size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  int rc = prod_args(p, U, u0, workspace, workspace_bytes);
+  if (rc) return rc;
+  double* hs;
+  if ((rc = host_scalars(&hs))) return rc;
+  const ProdLayout L = prod_layout(p);
+  rc = prod_step(p, U, u0, (char*)workspace, L, stats, 0, (hipStream_t)stream, hs);
+  if (stats) {
+    stats->iterations = 1;
+    stats->hist = 1;
+    stats->window = p->nt;
+    stats->schedule = PTS_SCHED_BULK;
+  }
+  return rc;
+}
+
+int pts_solve_products(const pts_problem* p, double* U, const double* u0, double tol, int max_iter,
+                       void* workspace, size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
+  if (stats) std::memset(stats, 0, sizeof *stats);
+  int rc = prod_args(p, U, u0, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
+  hipStream_t s = (hipStream_t)stream;
+  double* hs;
+  if ((rc = host_scalars(&hs))) return rc;
+  const ProdLayout L = prod_layout(p);
+  char* ws = (char*)workspace;
+  const auto t0 = std::chrono::steady_clock::now();
+  int it = 0;
+  for (;; ++it) {
+    // max |R| of the current iterate
+    rc = launch_residual(p, kprob(p), U, u0, nullptr, nullptr, (unsigned long long*)(ws + L.lvl),
+                         (unsigned long long*)(ws + L.scal), s);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(hs, ws + L.scal, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats && it < PTS_MAX_HIST) stats->res_inf[it] = hs[0];
+    if (stats) {
+      stats->iterations = it;
+      stats->hist = std::min(it + 1, PTS_MAX_HIST);
+      stats->window = p->nt;
+      stats->schedule = PTS_SCHED_BULK;
+    }
+    if (!std::isfinite(hs[0])) return fail(PTS_ERR_NONFINITE, "explicit products: non-finite residual at step %d", it);
+    if (hs[0] <= tol) {
+      if (stats) stats->converged = 1;
+      break;
+    }
+    if (it >= max_iter) return fail(PTS_ERR_NOT_CONVERGED, "explicit products: not converged after %d steps", it);
+    if ((rc = prod_step(p, U, u0, ws, L, stats, it, s, hs))) return rc;
+  }
+  if (stats)
+    stats->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return PTS_OK;
+}
+
+int pts_product_diamond(const pts_problem* p, const double* U, const double* u0, int n, double* out,
+                        void* workspace, size_t workspace_bytes, pts_stream_t stream) {
+  int rc = prod_args(p, U, u0, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (n < 1 || n > p->nt || !out) return fail(PTS_ERR_INVALID_ARG, "pts_product_diamond: level %d", n);
+  const ProdLayout L = prod_layout(p);
+  const double* last = nullptr;
+  rc = prod_products(p, L, (char*)workspace, U, u0, n, false, (hipStream_t)stream, &last);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(out, last, (size_t)dia_count(n) * p->nx * p->ny * 8, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return PTS_OK;
 }
 
 int pts_solve(const pts_problem* p, double* U, const double* u0, double tol, int max_iter, void* workspace,
@@ -2578,6 +3121,8 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
   if (!rc) rc = check_ws(p, workspace, workspace_bytes);
   if (rc) return rc;
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_autotune: NULL array");
+  if (p->dt_levels)
+    return fail(PTS_ERR_INVALID_ARG, "pts_autotune tunes the wavefront schedule, which takes uniform steps");
   hipStream_t s = (hipStream_t)stream;
   const size_t ns = (size_t)p->nx * p->ny;
   const size_t bytes = ns * p->nt * 8;
@@ -2624,6 +3169,7 @@ int pts_no_initial_iterate(const pts_problem* p, const pts_no_config* cfg, const
   if (rc) return rc;
   if (!cfg || p->bc != PTS_PERIODIC || cfg->nx != p->nx || cfg->ny != p->ny || cfg->nt != p->nt)
     return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: network and problem disagree");
+  if (p->dt_levels) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: uniform steps only");
   if (judge != PTS_NO_JUDGE_RESIDUAL && judge != PTS_NO_JUDGE_ACCUMULATED)
     return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: judge %d", judge);
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate: NULL array");
@@ -2641,6 +3187,7 @@ int pts_no_initial_iterate_batched(const pts_problem* p, const pts_no_config* cf
   if (rc) return rc;
   if (!cfg || p->bc != PTS_PERIODIC || cfg->nx != p->nx || cfg->ny != p->ny || cfg->nt != p->nt)
     return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: network and problem disagree");
+  if (p->dt_levels) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: uniform steps only");
   if (judge != PTS_NO_JUDGE_RESIDUAL && judge != PTS_NO_JUDGE_ACCUMULATED)
     return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: judge %d", judge);
   if (batch < 1 || !U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_no_initial_iterate_batched: NULL array");
@@ -2744,8 +3291,8 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, con
   const int sched = opts ? opts->schedule : PTS_SCHED_AUTO;
   char* w = (char*)workspace + batch_header_bytes(probs, nprob);
   // one problem with different initial conditions: batched wavefront sequences
-  if (same_problem(probs, nprob) && sched != PTS_SCHED_BULK &&
-      !(opts && (opts->window > 1 || opts->profile || opts->wave_launch == 1)) &&
+  if (same_problem(probs, nprob) && sched != PTS_SCHED_BULK && !probs[0].dt_levels &&
+      !(opts && (opts->window > 1 || opts->wave_launch == 1)) &&
       g_slab_cache.get(probs) >= probs[0].nt) {
     std::vector<int> codes(nprob);
     bool fb = false;
@@ -2758,7 +3305,7 @@ int pts_solve_batched(const pts_problem* probs, int nprob, double* const* U, con
       const size_t b = layout(probs).total;
       for (int i = 0; i < nprob; ++i) {
         int r = codes[i];
-        if (r == PTS_ERR_NONFINITE || r == PTS_ERR_SINGULAR) {
+        if (r == PTS_ERR_NONFINITE || r == PTS_ERR_SINGULAR || r == PTS_ERR_NOT_DOMINANT) {
           pts_stats one;
           pts_stats* sp = stats ? stats + i : &one;
           std::memset(sp, 0, sizeof *sp);

@@ -26,7 +26,31 @@ struct KProb {
   // 1 + 2 (ax + ay), vp = 2 (vx + vy))
   double cx, cy, vx, vy, ax, ay, bx, by, c0, ic0, vp;  // ic0 = 1 / c0
   double axs, ays, bxs, bys;  // ax, ay, bx, by times 1 / c0: the rows of D^{-1} A
+  const double* dts;          // [nt] step sizes tau_n (Eq. (3)), or nullptr: dt on every level
 };
+
+// The step-dependent constants of the constant-viscosity form, from k.dt.
+__host__ __device__ inline void fold_tau(KProb& k) {
+  k.ax = k.dt * k.vx;
+  k.ay = k.dt * k.vy;
+  k.bx = k.dt * k.cf * k.ihx;
+  k.by = k.dt * k.cf * k.ihy;
+  k.c0 = 1.0 + 2.0 * (k.ax + k.ay);
+  k.ic0 = 1.0 / k.c0;
+  k.axs = k.ax * k.ic0;
+  k.ays = k.ay * k.ic0;
+  k.bxs = k.bx * k.ic0;
+  k.bys = k.by * k.ic0;
+}
+
+// The problem as level n (0-based) sees it: its own step tau_n when the steps vary.
+__device__ __forceinline__ KProb at_level(const KProb& p, int n) {
+  if (!p.dts) return p;
+  KProb q = p;
+  q.dt = p.dts[n];
+  fold_tau(q);
+  return q;
+}
 
 // Tiling of a level for the register-resident solve: a 64 x 64 region per work-group,
 // of which the central TX x TY tile is written.

@@ -15,7 +15,7 @@
 //  k_update        U += dU at every level and per-block sums of dU^2 (the RMS update
 //                  norm of Section 8.1), reduced in fixed order by k_reduce_sum.
 #include "pts_device.hpp"
-#include "pts_mfma.hpp"
+#include "pts_mg.hpp"
 
 namespace pts {
 
@@ -27,11 +27,12 @@ namespace pts {
 constexpr int kResRows = 16;
 
 template <int BC, int FORM>
-__global__ __launch_bounds__(256) void k_residual(KProb p, const double* __restrict__ U,
+__global__ __launch_bounds__(256) void k_residual(KProb p0, const double* __restrict__ U,
                                                   const double* __restrict__ u0,
                                                   double* __restrict__ R, double* __restrict__ coef,
                                                   unsigned long long* __restrict__ lvl_bits) {
   const int n = blockIdx.y;
+  const KProb p = at_level(p0, n);
   const int tilesx = (p.nx + 63) >> 6;
   const int x = (blockIdx.x % tilesx) * 64 + (threadIdx.x & 63);
   const int y0 = (blockIdx.x / tilesx) * kResRows + (threadIdx.x >> 6);
@@ -365,7 +366,8 @@ __global__ __launch_bounds__(kThreads) void k_level_solve(KProb p, int n, const 
                                                           int passes, int sweeps) {
   __shared__ double lds_raw[2 * kWaves * 2 * 64];
   __shared__ double om[kMaxSweeps];
-  level_solve_tile<T, BC>(p, n, blockIdx.x, U, rn, dUprev, Xin, Xout, rho_lvl, g, passes, sweeps, lds_raw, om);
+  level_solve_tile<T, BC>(at_level(p, n), n, blockIdx.x, U, rn, dUprev, Xin, Xout, rho_lvl, g, passes, sweeps,
+                          lds_raw, om);
 }
 
 // Batched bulk schedule: independent instances with their own sizes, level counts and
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
   const BatchDesc* d = descs + it.x;
   const int nl = d->npacks;
   if (n >= d->p.nt || l >= nl) return;  // uniform over the work-group
-  const KProb p = d->p;
+  const KProb p = at_level(d->p, n);
   const Geo g = d->g;
   const size_t ns = (size_t)p.nx * p.ny;
   double* out = d->dU + (size_t)n * ns;
@@ -407,28 +409,29 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
                           lds_raw, om);
 }
 
-// ------------------------------------------------ spectral level solves (Dirichlet heat)
+// ---------------------------------------- multigrid-preconditioned level solves (Dirichlet heat)
 // For stiff Dirichlet heat levels the block A_n = I + tau dF/du is solved by Chebyshev
-// iteration preconditioned with M = I + tau mu_ref (-Delta_h), the constant-coefficient
-// five-point operator. The orthonormal DST-I matrix S (S = S^T = S^{-1}) diagonalises the
-// Dirichlet Laplacian: -Delta_h = S diag(lam_i + lam_j) S with
-// lam_k = (4 / h^2) sin^2(pi k / (2 (N + 1))), so M^{-1} r = S ((S r S) ./ (1 + tau mu_ref
-// (lam_i + lam_j))) S: four dense N x N products (MFMA) and a diagonal scaling.
-// With mu in [mu_lo, mu_hi] and mu_ref their midpoint, the preconditioned spectrum lies near
-// [mu_lo, mu_hi] / mu_ref (times a margin for the non-symmetric mu' terms of the Jacobian).
+// iteration preconditioned with M = I + tau mu_a (-Delta_h), the constant-coefficient
+// five-point operator, whose inverse is approximated by one multigrid V-cycle (pts_mg.hpp).
+// With mu in [mu_a, mu_hi] the spectrum of M^{-1} A lies near [1, mu_hi / mu_a] (times a
+// margin for the non-symmetric mu' terms of the Jacobian); the V-cycle B has spec(B M) in
+// [kMgLow, 1], which widens the interval's lower end.
+// Iteration k of level n: r = b - A x in FP64 from U (k_pc_resid, float32 r), z = B r (the
+// V-cycle launches), d = c0 d + c1 z, x += d in FP64 (ChebStep, applied where the V-cycle
+// writes its finest grid; k_pc_update for a z stored in memory).
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
-struct DstDesc {
+struct PcDesc {
   KProb p;
   const double* U;    // iterate [nt][N][N]
   const double* R;    // residual [nt][N][N]
   double* dU;         // update [nt][N][N]; the level solve iterates in dU[n]
-  float* r;           // [N][ld] level residual b - A x (float32; columns N..ld-1 stay zero)
-  float* z;           // [N][ld] M^{-1} r
+  float* r;           // [N][ld] level residual b - A x (float32)
+  float* z;           // [N][ld] B r
   double* d;          // [N][N] Chebyshev direction
   const int* K;       // [nt] iterations of level n (the interval follows the level's max |u|)
   const float2* c;    // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
   int active;
-  int ld;             // row stride of the float32 arrays: N rounded up to a multiple of 4
+  int ld;             // row stride of the float32 arrays (N)
 };
 
 // out[n] = max |U^n| (bit pattern of a non-negative double), one work-group per level
@@ -444,31 +447,14 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
   if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
 }
 
-// S[i][j] = sqrt(2/(N+1)) sin(pi (i+1)(j+1) / (N+1)) (row stride ld, zero beyond column N),
-// lam[k] = (4/h^2) sin^2(pi (k+1) / (2(N+1)))
-__global__ __launch_bounds__(256) void k_dst_setup(int N, int ld, double h, float* __restrict__ S,
-                                                   float* __restrict__ lam) {
-  const long t = (long)blockIdx.x * 256 + threadIdx.x;
-  const long nn = (long)N * ld;
-  if (t < nn) {
-    const int i = (int)(t / ld), j = (int)(t % ld);
-    S[t] = j < N ? (float)(sqrt(2.0 / (N + 1)) * sin(M_PI * (double)(i + 1) * (double)(j + 1) / (double)(N + 1)))
-                 : 0.f;
-  }
-  if (t < N) {
-    const double sv = sin(M_PI * (double)(t + 1) / (2.0 * (N + 1)));
-    lam[t] = (float)(4.0 / (h * h) * sv * sv);
-  }
-}
-
 // Work items (instance, chunk of 256 nodes), sorted by level count. Iteration k of level n:
 // r = b - A x with b = r^n + du^{n-1} (Eq. (7)) and x = du^n (x = 0 at k = 0, written here).
-__global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ ds, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                    int n, int k) {
   const int2 it = items[blockIdx.x];
-  const DstDesc* d = ds + it.x;
+  const PcDesc* d = ds + it.x;
   if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
-  const KProb p = d->p;
+  const KProb p = at_level(d->p, n);
   const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
   if (i >= ns) return;
@@ -482,7 +468,7 @@ __global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ d
     const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
     const Nb u = gather<0>(p, d->U + lev, bd, x, y);
     Row5 a;
-    (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // spectral solves are for heat only (no convection)
+    (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // these solves are for heat only (no convection)
     double ax = a.C * X[i];
     if (x > 0) ax += a.W * X[i - 1];
     if (x < p.nx - 1) ax += a.E * X[i + 1];
@@ -494,10 +480,10 @@ __global__ __launch_bounds__(256) void k_dst_resid(const DstDesc* __restrict__ d
 }
 
 // d = c0 d + c1 z, x += d
-__global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ ds, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                     int n, int k) {
   const int2 it = items[blockIdx.x];
-  const DstDesc* d = ds + it.x;
+  const PcDesc* d = ds + it.x;
   if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
   const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
@@ -509,16 +495,64 @@ __global__ __launch_bounds__(256) void k_dst_update(const DstDesc* __restrict__ 
   d->dU[(size_t)n * ns + i] += dir;
 }
 
-// One 64 x 64 tile of the product of group it.x (instance) in stage `stage`'s descriptors;
-// items (instance, tile row, tile column) of the instances that have level n, largest grids
-// first. Groups whose instance has no level n or no iteration k return.
-__global__ __launch_bounds__(256) void k_dst_gemm(const pts_mm::Gemm* __restrict__ gs, const DstDesc* __restrict__ ds,
-                                                  const int4* __restrict__ items, int nprob, int stage, int n, int k) {
+// V-cycle launches of iteration k of level n. Items (instance, grid l, tile x, tile y) of the
+// instances that have level n; instances without level n or iteration k return.
+__global__ __launch_bounds__(256) void k_mg_down(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
+                                                 const int4* __restrict__ items, int n, int k) {
   const int4 it = items[blockIdx.x];
-  const DstDesc* d = ds + it.x;
+  const PcDesc* d = ds + it.x;
   if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
-  const pts_mm::Gemm g = gs[(size_t)stage * nprob + it.x];
-  pts_mm::mm_tile_vec(g, it.y * pts_mm::BM, it.z * pts_mm::BN);
+  __shared__ float F[kMgDS * kMgDS], X[kMgDS * kMgDS], T[kMgDS * kMgTC];
+  __shared__ MgDownAux aux;
+  mg_down_tile(mg[it.x], it.y, it.z, it.w, F, X, T, aux);
+}
+
+// The Chebyshev step of iteration k at node (i, j), given z = B r there: d = c0 d + c1 z,
+// du^n += d (FP64). Applied by the V-cycle's last kernel on the finest grid.
+struct ChebStep {
+  const PcDesc* d;
+  int n, k, N;
+  __device__ void operator()(int i, int j, float z) const {
+    const size_t idx = (size_t)j * N + i;
+    const float2 c = d->c[(size_t)n * kMaxCheb + k];
+    const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[idx]) + (double)c.y * (double)z;
+    d->d[idx] = dir;
+    d->dU[(size_t)n * N * N + idx] += dir;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_mg_up(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
+                                               const int4* __restrict__ items, int n, int k) {
+  const int4 it = items[blockIdx.x];
+  const PcDesc* d = ds + it.x;
+  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  __shared__ float X[kMgUS * kMgUS], F[kMgUS * kMgUS], X1[kMgUS * kMgUS], E[kMgUE * kMgUE];
+  const MgDesc& m = mg[it.x];
+  const int l = it.y;
+  if (l == 0) {
+    mg_up_tile(m, 0, it.z, it.w, X, F, X1, E, ChebStep{d, n, k, m.n[0]});
+  } else {
+    float* e = m.e[l];
+    const int nl = m.n[l];
+    mg_up_tile(m, l, it.z, it.w, X, F, X1, E, [=](int i, int j, float v) { e[(size_t)j * nl + i] = v; });
+  }
+}
+
+// One work-group per instance: the V-cycle's grids from G down (LDS).
+__global__ __launch_bounds__(1024) void k_mg_lds(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
+                                                 const int* __restrict__ items, int n, int k) {
+  const int i = items[blockIdx.x];
+  const PcDesc* d = ds + i;
+  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  __shared__ float X[kMgLdsWords], F[kMgLdsWords], T[kMgLdsWords];
+  const MgDesc& m = mg[i];
+  if (m.G == 0) {
+    mg_lds_cycle(m, X, F, T, ChebStep{d, n, k, m.n[0]});
+  } else {
+    float* x = m.x[m.G];
+    const int nl = m.n[m.G];
+    mg_lds_cycle(m, X, F, T, [=](int a, int b, float v) { x[b * nl + a] = v; });
+  }
 }
 
 // ---------------------------------------------------------- wavefront schedule
@@ -760,8 +794,9 @@ __global__ __launch_bounds__(kThreads) void k_level_wave_batch(KProb p, const Wa
 // y = A_m x at every node of level m (rows from U_m, Eq. (6)); products P^{w-1} r^w of
 // the Section 5 recursion are chains of these. One thread per node.
 template <int BC>
-__global__ __launch_bounds__(256) void k_apply(KProb p, int m, const double* __restrict__ U,
+__global__ __launch_bounds__(256) void k_apply(KProb p0, int m, const double* __restrict__ U,
                                                const double* __restrict__ x, double* __restrict__ y) {
+  const KProb p = at_level(p0, m);
   const unsigned i = blockIdx.x * 256u + threadIdx.x;
   const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
   if (i >= ns) return;

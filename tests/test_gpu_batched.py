@@ -86,8 +86,8 @@ def test_nonconverging_instance_reports_and_others_finish():
 
 
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-8)])
-def test_stiff_heat_batch_spectral_level_solves_match_oracle(precision, bar):
-    """Stiff Dirichlet heat levels (Gershgorin radius >= 0.976) take the DST-preconditioned
+def test_stiff_heat_batch_multigrid_level_solves_match_oracle(precision, bar):
+    """Stiff Dirichlet heat levels (Gershgorin radius >= 0.976) take the multigrid-preconditioned
     Chebyshev solve: few iterations per level, no restarted passes, same converged result."""
     probs = _heat_batch(12, [(128, 3), (100, 4), (150, 2)])
     Us = [dev(p.plain_iterate()) for p in probs]
@@ -100,6 +100,21 @@ def test_stiff_heat_batch_spectral_level_solves_match_oracle(precision, bar):
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err)
         assert err <= bar, (p.name, err)
+
+
+def test_stiff_heat_batch_deep_hierarchies_match_oracle():
+    """Grids whose V-cycle has three tile-kernel grids above the in-LDS part (260 -> 130 -> 65
+    -> 32 ...), one odd grid (nested coarsening) and one with an even grid on the way down."""
+    probs = _heat_batch(16, [(260, 2), (131, 3)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print("[batched] stiff heat 260^2 x 2 + 131^2 x 3, mixed", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision="mixed")
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"] and st["refine"] == 0 and st["sweeps"] <= 32, st
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err, flush=True)
+        assert err <= 1e-8, (p.name, err)
 
 
 def test_windows_option_solves_instances_one_after_another():

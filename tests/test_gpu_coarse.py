@@ -81,7 +81,7 @@ def _mms(kind, nint, nt):
     return p, ex
 
 
-# (The Section 8.2 Burgers problem is not a case here: at its step sizes tau |u| / h reaches 5,
+# (The Section 8.2 Burgers problem: at its step sizes tau |u| / h reaches 5,
 # the blocks are not diagonally dominant and the Jacobi-preconditioned level solves refuse them.)
 @pytest.mark.parametrize("kind,nint,nt,cf", [("heat", 64, 8, 4), ("heat", 64, 8, 2)])
 def test_coarse_iterate_with_dirichlet_data_matches_oracle(kind, nint, nt, cf):
@@ -116,6 +116,32 @@ def test_table3_newton_counts_from_the_coarse_start():
         counts.append(k)
     print("Newton iterations", counts)
     assert counts[1:] == [2, 2, 2, 2] and counts[0] <= 3, counts
+
+
+def test_table6_newton_counts_from_the_coarse_start():
+    """Section 8.2, Table 6: from the coarse-grid start (c_f = 3) ParaDIn needs 3, 3, 3, 3, 4
+    Newton iterations at N_t = 6, 12, 18, 24, 30 (63 x 63 intervals) to bring the error of the
+    iteration below a tenth of the discretization error (read here as: the RMS update norm of
+    Section 8.1 below a tenth of the L1 space-time error of Table 4's norm). The level solves are
+    the banded LU (the blocks are not diagonally dominant). Soft pin: every count within one
+    of the printed one."""
+    printed = {6: 3, 12: 3, 18: 3, 24: 3, 30: 4}
+    counts = {}
+    for nt in printed:
+        p, ex = _mms("burgers", 63, nt)
+        bd, u0 = dev(p.bdata), dev(p.u0)
+        U = torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        print(f"[coarse] table 6, N_t = {nt}", flush=True)
+        P.coarse_initial_iterate(p, U, u0, 3, tol=1e-12, bdata=bd)
+        st = P.solve(p, U, u0, tol=1e-12, max_iter=12, bdata=bd, schedule="bulk")
+        assert st["converged"] and st["sweeps"] == 0, st
+        X, Y = p.mesh()
+        exact = np.stack([ex(X, Y, (n + 1) * p.dt) for n in range(p.nt)])
+        err = float(np.sum(np.abs(host(U) - exact))) * p.hx * p.hy * p.dt
+        counts[nt] = next(k + 1 for k, r in enumerate(st["upd_rms"]) if r <= 0.1 * err)
+        print(f"  L1 error {err:.3e}, RMS updates {[f'{r:.1e}' for r in st['upd_rms']]}", flush=True)
+    print("Newton iterations", counts, "printed", printed)
+    assert all(abs(counts[k] - printed[k]) <= 1 for k in printed), counts
 
 
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
