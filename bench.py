@@ -475,6 +475,8 @@ def bench_heatbatch(args, extras=None):
     def step(**kw):
         for p, U, u0 in zip(probs, Us, u0s):
             P.init_plain(p, U, u0)
+        if args.lin_tol > 0:
+            kw["lin_tol"] = args.lin_tol
         return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed", ws=ws, **kw)
 
     for _ in range(args.warmup):
@@ -560,6 +562,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="skip the inner-plan autotuner")
     ap.add_argument("--sweeps", type=int, default=0, help="explicit inner Chebyshev sweeps (0 = tuned/auto)")
+    ap.add_argument("--lin-tol", type=float, default=0.0,
+                    help="heatbatch: residual reduction asked of each level solve (0 = the library default)")
     ap.add_argument("--passes", type=int, default=0, help="explicit inner passes (0 = tuned/auto)")
     ap.add_argument("--instances", type=int, default=64, help="heatbatch: first instances of the batch")
     ap.add_argument("--hbm-calibration", action="store_true",

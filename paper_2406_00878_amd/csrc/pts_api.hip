@@ -2096,7 +2096,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           for (int g = 0; g < gmax; ++g) {
             if (!cd[g][k]) continue;
             pb(1);
-            hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][k]), dim3(256), 0, s, dm, dd, id + od[g], n, kk);
+            hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][k]), dim3(kMgThreads), 0, s, dm, dd, id + od[g], n, kk);
             pe(1, prof ? kb(1, k, n, kk, g) : 0.0);
             ++launches;
           }
@@ -2107,7 +2107,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           for (int g = gmax - 1; g >= 0; --g) {
             if (!cu[g][k]) continue;
             pb(3);
-            hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][k]), dim3(256), 0, s, dm, dd, iu + ou[g], n, kk);
+            hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][k]), dim3(kMgThreads), 0, s, dm, dd, iu + ou[g], n, kk);
             pe(3, prof ? kb(3, k, n, kk, g) : 0.0);
             ++launches;
           }

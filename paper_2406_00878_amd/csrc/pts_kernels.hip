@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds
 
 // V-cycle launches of iteration k of level n. Items (instance, grid l, tile x, tile y) of the
 // instances that have level n; instances without level n or iteration k return.
-__global__ __launch_bounds__(256) void k_mg_down(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
+__global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
                                                  const int4* __restrict__ items, int n, int k) {
   const int4 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
@@ -521,7 +521,7 @@ struct ChebStep {
   }
 };
 
-__global__ __launch_bounds__(256) void k_mg_up(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
+__global__ __launch_bounds__(kMgThreads) void k_mg_up(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
                                                const int4* __restrict__ items, int n, int k) {
   const int4 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;

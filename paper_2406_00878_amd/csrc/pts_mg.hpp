@@ -37,6 +37,7 @@ constexpr int kMgDS = 72;           // k_mg_down: LDS row stride (fine region <=
 constexpr int kMgUS = 68;           // k_mg_up: LDS row stride (fine region <= 68 wide)
 constexpr int kMgUE = 40;           // k_mg_up: LDS row stride of the coarse correction
 constexpr int kMgLdsWords = 5504;   // k_mg_lds: floats per LDS array (64^2 + 32^2 + ...)
+constexpr int kMgThreads = 512;     // k_mg_down, k_mg_up: threads per work-group
 
 __host__ __device__ inline int mg_coarse(int n) { return (n & 1) ? (n - 1) >> 1 : n >> 1; }
 

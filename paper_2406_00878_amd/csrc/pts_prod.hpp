@@ -139,11 +139,12 @@ __global__ __launch_bounds__(256) void k_blu_panel(const BandLevel* __restrict__
     const int rend = min(ns, c + L.w + 1);
     for (int r = c + 1 + threadIdx.x; r < rend; r += blockDim.x) bel(L, r, c) /= piv;
     __syncthreads();
-    // rows c+1..rend-1, panel columns c+1..kend-1 (all inside the band: |r - c2| <= w)
-    const int nr = rend - c - 1, nc = kend - c - 1;
+    // rows c+1..rend-1, panel columns c+1..min(kend, c+w+1)-1: u_{c,c2} lies in the band, and
+    // then so does a_{r,c2}
+    const int nr = rend - c - 1, nc = min(kend, c + L.w + 1) - c - 1;
     for (int t = threadIdx.x; t < nr * nc; t += blockDim.x) {
       const int r = c + 1 + t / nc, c2 = c + 1 + t % nc;
-      if (c2 - r <= L.w) bel(L, r, c2) -= bel(L, r, c) * bel(L, c, c2);
+      bel(L, r, c2) -= bel(L, r, c) * bel(L, c, c2);
     }
     __syncthreads();
   }
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_blu_trsm(const BandLevel* __restrict__ 
   if (c2 >= min(ns, kend + L.w)) return;
   for (int r = max(k0, c2 - L.w); r < kend; ++r) {
     double s = bel(L, r, c2);
-    for (int m = max(k0, c2 - L.w); m < r; ++m) s -= bel(L, r, m) * bel(L, m, c2);
+    for (int m = max(max(k0, c2 - L.w), r - L.w); m < r; ++m) s -= bel(L, r, m) * bel(L, m, c2);
     bel(L, r, c2) = s;
   }
 }
