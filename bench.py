@@ -503,6 +503,10 @@ def bench_heatbatch(args, extras=None):
         errs.append(float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo))))
     # per-kernel split: one more solve with every launch bracketed by HIP events on the launch
     # stream (the library's profile option); achieved GB/s = algorithmic bytes / event time
+    if args.no_split:
+        out = {"metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": ms, "config": {"workload": "heatbatch64"}}
+        return out
     pst = step(profile=True)[0]
     torch.cuda.synchronize()
     split = {}
@@ -586,6 +590,8 @@ def main():
     ap.add_argument("--infer-streams", type=int, default=0,
                     help="--learned: 0 = the batch's starts as one batched forward pass, then the judges; "
                          "N > 0 = one-sample inference + judge calls spread over N streams")
+    ap.add_argument("--no-split", action="store_true",
+                    help="heatbatch: skip the profiled solve (per-kernel split); for counter runs")
     ap.add_argument("--no-extras", action="store_true",
                     help="heatbatch: skip the other workloads (Burgers 256^2 x 512 FP64, 512^2 x 1024 mixed, learned "
                          "iterate), which are otherwise measured after the batch and reported under other_workloads")

@@ -1464,7 +1464,7 @@ int solve_slabs(const pts_problem* p, double* U, const double* u0, double tol, i
 // A_n, two diamonds (P^{l-1}, P^l), the right-hand sides rt^l, the update, every level's band,
 // reduction slots, the zero-pivot flag and the band descriptors.
 struct ProdLayout {
-  size_t R, coef, D0, D1, RT, dU, lvl, scal, partial, rms, flag, desc, band, total;
+  size_t R, coef, D0, D1, RT, RS, dU, lvl, scal, partial, rms, flag, desc, band, total;
   std::vector<size_t> B;  // band of level l
   std::vector<int> w;     // half-bandwidth of level l
 };
@@ -1486,6 +1486,7 @@ ProdLayout prod_layout(const pts_problem* p) {
   L.D0 = take((size_t)dia_count(p->nt) * ns * 8);
   L.D1 = take((size_t)dia_count(p->nt) * ns * 8);
   L.RT = take(st * 8);
+  L.RS = take(st * 8);
   L.dU = take(st * 8);
   L.lvl = take((size_t)p->nt * 16);
   L.scal = take(4 * 8);
@@ -1536,7 +1537,8 @@ int prod_products(const pts_problem* p, const ProdLayout& L, char* ws, const dou
                        coef + (size_t)(l - 1) * 5 * ns, Dc);
     if (band)
       hipLaunchKernelGGL(k_prod_band, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, p->nx, p->ny, l,
-                         L.w[l - 1], (const double*)Dc, (double*)(ws + L.B[l - 1]), rt);
+                         L.w[l - 1], (const double*)Dc, (double*)(ws + L.B[l - 1]), (const double*)rt,
+                         (double*)(ws + L.RS) + (size_t)(l - 1) * ns);
     *last = Dc;
   }
   HIPCHK(hipGetLastError());
@@ -1561,7 +1563,7 @@ int prod_step(const pts_problem* p, double* U, const double* u0, char* ws, const
   const double* last = nullptr;
   int rc = prod_products(p, L, ws, U, u0, p->nt, true, s, &last);
   if (rc) return rc;
-  double* RT = (double*)(ws + L.RT);
+  double* RS = (double*)(ws + L.RS);  // diagonally scaled right-hand sides
   // blocked band LU of every level, then the solves
   const BandLevel* dl = (const BandLevel*)(ws + L.desc);
   int* flag = (int*)(ws + L.flag);
@@ -1575,7 +1577,7 @@ int prod_step(const pts_problem* p, double* U, const double* u0, char* ws, const
                        k0);
   }
   double* dU = (double*)(ws + L.dU);
-  hipLaunchKernelGGL(k_blu_solve, dim3((unsigned)p->nt), dim3(256), 0, s, dl, (int)ns, (const double*)RT, dU);
+  hipLaunchKernelGGL(k_blu_solve, dim3((unsigned)p->nt), dim3(256), 0, s, dl, (int)ns, (const double*)RS, dU);
   const size_t count = ns * p->nt;
   hipLaunchKernelGGL(k_update, dim3(kUpdateBlocks), dim3(256), 0, s, count, U, dU, (double*)(ws + L.partial));
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, (const double*)(ws + L.partial), kUpdateBlocks,

@@ -1,4 +1,4 @@
-// Dense products on MFMA for gfx950, shared by the network kernels and the spectral solves:
+// Dense products on MFMA for gfx950, used by the network kernels of the learned iterate:
 // float32 operands in memory, rounded to bfloat16 (nearest even) when staged into LDS,
 // 16 x 16 x 16 bf16 MFMA tiles, float32 accumulation.
 #pragma once
@@ -28,9 +28,6 @@ struct Gemm {
   float* P;         // [batch][ksplit][M][N] partials (ksplit > 1)
   const float* bias;  // optional epilogue (ksplit == 1): c += bias[m], then act = GELU(c)
   float* act;         // same layout as C
-  const float* lam_m;  // optional epilogue (ksplit == 1): c *= 1 / (1 + lam_c (lam_m[m] + lam_n[n]))
-  const float* lam_n;
-  float lam_c;
 };
 
 // GELU, tanh form: z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3)))
@@ -133,93 +130,10 @@ __device__ __forceinline__ void mm_tile(const Gemm& g, int m0, int n0, int b, in
             val += g.bias[gm];
             g.act[off] = gelu(val);
           }
-          if (g.lam_m) val *= 1.f / (1.f + g.lam_c * (g.lam_m[gm] + g.lam_n[gn]));
           *c = val;
         }
       }
 }
 
-
-// Vectorised variant for row-major operands: A contiguous along k, B contiguous along n, all
-// row strides multiples of 4 floats and every array 16-byte aligned; columns up to the row
-// stride may be read (they must hold zeros beyond K or N). K steps of 64, loaded four floats
-// at a time, the next step prefetched into registers. No split K, no epilogue but alpha, beta
-// and the lam scaling.
-__device__ __forceinline__ void mm_tile_vec(const Gemm& g, int m0, int n0) {
-  constexpr int BKV = 64;
-  // A tile row-major (k contiguous); B tile transposed (k contiguous per column), so both MFMA
-  // fragments (four consecutive k) are single 8-byte LDS reads
-  __shared__ unsigned short As[BM][BKV + 4];
-  __shared__ unsigned short Bt[BN][BKV + 4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float4_t acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  float4 ra[4], rb[4];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + r * 256;
-      const int am = e >> 4, ak = (e & 15) * 4;  // 16 vectors per 64-wide row
-      const int gm = m0 + am, gk = k0 + ak;
-      ra[r] = (gm < g.M && gk < g.K) ? *reinterpret_cast<const float4*>(g.A + (long)gm * g.sam + gk)
-                                     : make_float4(0.f, 0.f, 0.f, 0.f);
-      const int bk = e >> 4, bn = (e & 15) * 4;
-      const int gk2 = k0 + bk, gn = n0 + bn;
-      rb[r] = (gk2 < g.K && gn < g.N) ? *reinterpret_cast<const float4*>(g.B + (long)gk2 * g.sbk + gn)
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  };
-  load(0);
-  for (int k0 = 0; k0 < g.K; k0 += BKV) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + r * 256;
-      const int am = e >> 4, ak = (e & 15) * 4;
-      uint2 pk;  // four consecutive k of row am, one 8-byte store
-      pk.x = (unsigned)f2bf(ra[r].x) | ((unsigned)f2bf(ra[r].y) << 16);
-      pk.y = (unsigned)f2bf(ra[r].z) | ((unsigned)f2bf(ra[r].w) << 16);
-      *reinterpret_cast<uint2*>(&As[am][ak]) = pk;
-      const int bk = e >> 4, bn = (e & 15) * 4;
-      Bt[bn][bk] = f2bf(rb[r].x);
-      Bt[bn + 1][bk] = f2bf(rb[r].y);
-      Bt[bn + 2][bk] = f2bf(rb[r].z);
-      Bt[bn + 3][bk] = f2bf(rb[r].w);
-    }
-    __syncthreads();
-    if (k0 + BKV < g.K) load(k0 + BKV);
-#pragma unroll
-    for (int kk = 0; kk < BKV; kk += 16) {
-      const int kq = kk + 4 * (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = wm + 16 * i + (lane & 15);
-        const short4_t a = *reinterpret_cast<const short4_t*>(&As[row][kq]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int col = wn + 16 * j + (lane & 15);
-          const short4_t bb = *reinterpret_cast<const short4_t*>(&Bt[col][kq]);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[i][j], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
-        const int gn = n0 + wn + 16 * j + (lane & 15);
-        if (gm >= g.M || gn >= g.N) continue;
-        float* c = g.C + (long)gm * g.scm + gn;
-        float val = g.alpha * acc[i][j][r] + (g.beta != 0.f ? g.beta * *c : 0.f);
-        if (g.lam_m) val *= 1.f / (1.f + g.lam_c * (g.lam_m[gm] + g.lam_n[gn]));
-        *c = val;
-      }
-}
 
 }  // namespace pts_mm

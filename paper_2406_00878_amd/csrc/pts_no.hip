@@ -600,8 +600,7 @@ unsigned eblocks(long n) { return (unsigned)std::min<long>((n + 255) / 256, 8192
 int gemm(hipStream_t s, int M, int N, int K, float alpha, const float* A, long sam, long sak, long bsa,
          const float* B, long sbk, long sbn, long bsb, float beta, float* C, long scm, long scn, long bsc,
          int batch = 1, int ksplit = 1, float* P = nullptr, const float* bias = nullptr, float* act = nullptr) {
-  Gemm g{A, B, C, M, N, K, sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc, alpha, beta, ksplit, P, bias, act,
-         nullptr, nullptr, 0.f};
+  Gemm g{A, B, C, M, N, K, sam, sak, bsa, sbk, sbn, bsb, scm, scn, bsc, alpha, beta, ksplit, P, bias, act};
   dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)(batch * ksplit));
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
   if (ksplit > 1) hipLaunchKernelGGL(k_gemm_reduce, dim3(eblocks((long)batch * M * N)), dim3(256), 0, s, g, batch);

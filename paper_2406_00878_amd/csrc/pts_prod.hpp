@@ -95,11 +95,13 @@ __global__ __launch_bounds__(256) void k_prod_rhs(int nx, int ny, int l, const d
   rt[i] = s + rt_prev[i];
 }
 
-// Band storage of P^l with the diagonal preconditioner: row i divided by p_ii, and rt_i too.
-// One thread per (entry, node); the band (zeroed beforehand) takes the entries whose column
-// node lies inside the grid.
+// Band storage of P^l with the diagonal preconditioner: row i divided by p_ii, and rs_i =
+// rt_i / p_ii (rt itself stays unscaled: the recursion reads it for the next level). One thread
+// per (entry, node); the band (zeroed beforehand) takes the entries whose column node lies
+// inside the grid.
 __global__ __launch_bounds__(256) void k_prod_band(int nx, int ny, int l, int w, const double* __restrict__ Dc,
-                                                   double* __restrict__ B, double* __restrict__ rt) {
+                                                   double* __restrict__ B, const double* __restrict__ rt,
+                                                   double* __restrict__ rs) {
   const size_t ns = (size_t)nx * ny;
   const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (size_t)dia_count(l) * ns) return;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void k_prod_band(int nx, int ny, int l, int w,
     const long col = (long)ky * nx + kx;
     B[(size_t)i * (2 * w + 1) + (size_t)(w + col - i)] = Dc[t] / d;
   }
-  if (a == 0 && b == 0) rt[i] /= d;
+  if (a == 0 && b == 0) rs[i] = rt[i] / d;
 }
 
 // Per-level parameters of the blocked band LU.
