@@ -28,6 +28,15 @@
  *     returns a message for the calling thread. No C++ exception crosses the
  *     ABI. On any error the output arrays are left in an unspecified but
  *     finite-or-untouched state, except where stated.
+ *   - State the library keeps between calls (all per calling thread, freed at
+ *     thread exit): a 4 KiB pinned host buffer for the scalars read back per
+ *     Newton step and a pinned staging buffer for batch descriptors (both
+ *     hipHostMalloc, grown on demand); up to 32 instantiated HIP graphs of
+ *     wavefront sequences (keyed by their launch arguments, oldest dropped);
+ *     autotuned plans, stage counts and slab lengths per problem signature.
+ *     pts_autotune additionally allocates one device copy of U for the
+ *     duration of the call. Device memory beyond that is the caller's
+ *     workspace, except for pts_newton_step_static (see there).
  */
 #ifndef PTS_H
 #define PTS_H

@@ -28,7 +28,7 @@ namespace pts {
 constexpr int kMgLevels = 12;
 constexpr int kMgLds = 64;          // grids with N <= kMgLds: rest of the V-cycle in LDS
 constexpr int kMgCoarsest = 8;      // hierarchy ends at N <= 8
-constexpr int kMgCoarseSweeps = 12; // Jacobi sweeps on the coarsest grid
+constexpr int kMgCoarseSweeps = 8;  // Jacobi sweeps on the coarsest grid
 constexpr float kMgOmega = 0.8f;
 constexpr double kMgLow = 0.75;     // lower end of spec(B M)
 constexpr int kMgTC = 32;           // k_mg_down: coarse tile edge
