@@ -105,3 +105,15 @@ def test_coarse_workspace_bytes_validates_on_host():
     h = W.heat_dirichlet(31, 12, 1e-3, np.zeros((31, 31)))
     assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 4) > 0
     assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 5) == 0
+
+
+def test_binding_error_codes_match_the_header():
+    """Every PTS_OK / PTS_ERR_* value of include/pts.h (PTS_ERR_NOT_DOMINANT included) is the
+    binding's constant of the same name, and the codes are distinct."""
+    import paper_2406_00878_amd._lib as L
+    src = open(os.path.join(ROOT, "include", "pts.h")).read()
+    codes = dict((n, int(v)) for n, v in re.findall(r"\b(PTS_(?:OK|ERR_[A-Z_]+))\s*=\s*(-?\d+)", src))
+    assert codes["PTS_ERR_NOT_DOMINANT"] == -7 and len(codes) == 8, codes
+    for n, v in codes.items():
+        assert getattr(L, n, None if n != "PTS_OK" else 0) == v, n
+    assert len(set(codes.values())) == len(codes)

@@ -175,3 +175,51 @@ def test_spectral_mix_adjoint_is_the_transpose():
     # the mix is linear in R as well: <mix(R', x), y> = <R', dR>
     R2 = rng.standard_normal(R.shape)
     assert abs(np.sum(neural.spectral_mix(R2, x, m) * y) - np.sum(R2 * dR)) < 1e-12
+
+
+# ------------------------------------------------------------ the staged bfloat16 form
+
+def test_bf16_rounding_matches_torch_conversion():
+    """oracle.neural_bf16.bf16 is round-to-nearest-even to bfloat16, as torch converts."""
+    import torch
+
+    from oracle import neural_bf16 as OB
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 1e-40, -3e-39,
+                         3.4e38, np.inf, -np.inf]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = OB.bf16(x)
+    np.testing.assert_array_equal(got, ref)
+    assert np.isnan(OB.bf16(np.array([np.nan], dtype=np.float32)))[0]
+    # ties go to the even neighbour: 1 + 2^-8 -> 1, 1 + 3 2^-8 -> 1 + 2^-6
+    assert got[20002] == 1.0 and got[20003] == 1.0 + 2.0 ** -6
+
+
+def test_staged_network_without_rounding_is_the_network():
+    """With exact products the staged order (x transform first, intermediates as operands)
+    is the network of oracle.neural; the only difference is its float32 basis tables."""
+    from oracle import neural_bf16 as OB
+    lay, flat, u0, Ut, L, m = _setup(seed=9, nx=12, ny=10, nt=6, width=4, modes=3, layers=2, tmodes=3)
+    p = neural.unflatten(flat, lay)
+    ident = lambda a: np.asarray(a, dtype=np.float64)
+    U = neural.forward(p, u0, 6, L, m)
+    Us = OB.forward(p, u0, 6, L, m, rnd=ident)
+    assert np.max(np.abs(Us - U)) <= 1e-6 * np.max(np.abs(U - u0[None]))
+    lo, go = neural.loss_and_grads(p, u0, Ut, L, m)
+    ls, gs = OB.loss_grads(p, u0, Ut, L, m, rnd=ident)
+    assert abs(ls - lo) <= 1e-6 * lo
+    for name, _ in lay:
+        assert np.max(np.abs(gs[name] - go[name])) <= 1e-5 * np.max(np.abs(go[name])), name
+
+
+def test_staged_network_rounds_at_bfloat16_size():
+    """Rounded products move the output by the bfloat16 unit (2^-9) times a modest factor:
+    more than float32 rounding, far less than the output."""
+    from oracle import neural_bf16 as OB
+    lay, flat, u0, Ut, L, m = _setup(seed=10, nx=16, ny=12, nt=6, width=8, modes=3, layers=2, tmodes=3)
+    p = neural.unflatten(flat, lay)
+    U = neural.forward(p, u0, 6, L, m)
+    Ub = OB.forward(p, u0, 6, L, m)
+    e = np.linalg.norm(Ub - U) / np.linalg.norm(U - u0[None])
+    assert 1e-5 < e < 5e-2, e
