@@ -445,6 +445,8 @@ def bench_learned(args):
 
 KERNEL_NAMES = ["k_pc_resid", "k_mg_down", "k_mg_lds", "k_mg_up", "k_pc_update", "k_residual", "k_update",
                 "k_level_absmax"]
+# the pipelined schedule's own kernels take the last three slots
+KERNEL_NAMES_PIPE = KERNEL_NAMES[:5] + ["k_pipe_residual", "k_pipe_update", "k_pipe_cheb"]
 
 
 def bench_heatbatch(args, extras=None):
@@ -477,7 +479,8 @@ def bench_heatbatch(args, extras=None):
             P.init_plain(p, U, u0)
         if args.lin_tol > 0:
             kw["lin_tol"] = args.lin_tol
-        return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed", ws=ws, **kw)
+        return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed", ws=ws,
+                               schedule=args.schedule, stages=args.stages, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -509,8 +512,10 @@ def bench_heatbatch(args, extras=None):
         return out
     pst = step(profile=True)[0]
     torch.cuda.synchronize()
+    pipelined = pst["schedule"] == P.PTS_SCHED_PIPELINE
+    names = KERNEL_NAMES_PIPE if pipelined else KERNEL_NAMES
     split = {}
-    for j, name in enumerate(KERNEL_NAMES):
+    for j, name in enumerate(names):
         if pst["kern_count"][j]:
             t = pst["kern_ms"][j]
             split[name] = {"ms": t, "launches": pst["kern_count"][j],
@@ -530,10 +535,11 @@ def bench_heatbatch(args, extras=None):
                    "grids": [min(p.nx for p in probs), max(p.nx for p in probs)],
                    "levels": [min(p.nt for p in probs), max(p.nt for p in probs)], "dt": 1e-3, "k": "1+u^2",
                    "seed": 2406004, "tol": args.tol, "precision": "mixed (FP32 multigrid-preconditioned level "
-                   "solves, FP64 residuals and updates)", "schedule": "batched bulk",
+                   "solves, FP64 residuals and updates)",
+                   "schedule": "pipelined Newton stages" if pipelined else "batched bulk",
                    "newton_steps_min_max": [min(its), max(its)],
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl},
         "kernel_split": split,
@@ -563,6 +569,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="auto")
+    ap.add_argument("--stages", type=int, default=0,
+                    help="heat batch: Newton stages per pipelined pass (0: the library's default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="skip the inner-plan autotuner")
     ap.add_argument("--sweeps", type=int, default=0, help="explicit inner Chebyshev sweeps (0 = tuned/auto)")

@@ -1668,12 +1668,18 @@ int mg_up_tiles(const MgDesc& d, int l) {
 }
 
 // Layout of the multigrid solve's part of a batch header (after the level-solve part).
+// Every instance has kLanes level solvers ("lanes", descriptor index i kLanes + s): the bulk
+// schedule uses lane 0; the pipelined schedule lanes 0..S-1 for its Newton stages and lane S
+// for the update and residual after the last one (S <= kLanes - 1).
+constexpr int kLanes = 8;
 struct MgLayout {
-  size_t desc, mgdesc, items_e, items_e0, items_d, items_u, items_l, total;
-  std::vector<size_t> d, K, coef, lmax, tab;
-  std::vector<std::vector<size_t>> x, f, e;  // per instance, grids 0..G (e: 1..G-1)
-  size_t ne = 0, nd = 0, nu = 0;          // work item capacities
-  int gmax = 0;                           // most grids above the LDS part
+  size_t desc, mgdesc, items_e, items_e0, items_d, items_u, items_l, items_a, items_k, stat, total;
+  size_t stat_words = 0;                        // [nt][3] per lane, lanes one after another
+  std::vector<size_t> tab, lmax, lstat;         // per instance (lstat: its lane 0's stat words)
+  std::vector<size_t> d, K, coef, R, ring, park;  // per lane
+  std::vector<std::vector<size_t>> x, f, e;     // per lane, grids 0..G (e: 1..G-1)
+  size_t ne = 0, nd = 0, nu = 0;                // work item capacities (all lanes)
+  int gmax = 0;                                 // most grids above the LDS part
 };
 MgLayout mg_layout(const pts_problem* probs, int nprob) {
   MgLayout L;
@@ -1685,38 +1691,50 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
   };
   for (int i = 0; i < nprob; ++i) {
     const size_t N = probs[i].nx;
-    L.ne += (N * N + 255) / 256;
+    L.ne += kLanes * ((N * N + 255) / 256);
     const MgDesc h = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
     for (int l = 0; l < h.G; ++l) {
-      L.nd += mg_down_tiles(h, l);
-      L.nu += mg_up_tiles(h, l);
+      L.nd += kLanes * mg_down_tiles(h, l);
+      L.nu += kLanes * mg_up_tiles(h, l);
     }
     L.gmax = std::max(L.gmax, h.G);
+    L.lstat.push_back(L.stat_words);
+    L.stat_words += (size_t)kLanes * 3 * probs[i].nt;
   }
-  L.desc = take((size_t)nprob * sizeof(PcDesc));
-  L.mgdesc = take((size_t)nprob * sizeof(MgDesc));
+  const size_t nl = (size_t)nprob * kLanes;
+  L.desc = take(nl * sizeof(PcDesc));
+  L.mgdesc = take(nl * sizeof(MgDesc));
   L.items_e = take(L.ne * sizeof(int2));
   L.items_e0 = take(L.ne * sizeof(int2));
+  L.items_a = take(L.ne * sizeof(int2));
   L.items_d = take(std::max<size_t>(L.nd, 1) * sizeof(int4));
   L.items_u = take(std::max<size_t>(L.nu, 1) * sizeof(int4));
-  L.items_l = take((size_t)nprob * sizeof(int));
-  L.x.resize(nprob);
-  L.f.resize(nprob);
-  L.e.resize(nprob);
+  L.items_l = take(nl * sizeof(int));
+  L.items_k = take(nl * sizeof(int));
+  L.stat = take(L.stat_words * 8);
+  L.x.resize(nl);
+  L.f.resize(nl);
+  L.e.resize(nl);
   for (int i = 0; i < nprob; ++i) {
-    const size_t N = probs[i].nx;
+    const size_t N = probs[i].nx, nt = probs[i].nt;
     const MgDesc h = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
-    for (int l = 0; l <= h.G; ++l) {
-      const size_t nn = (size_t)h.n[l] * h.n[l];
-      L.x[i].push_back(take(nn * 4));
-      L.f[i].push_back(take(nn * 4));
-      L.e[i].push_back(l >= 1 && l < h.G ? take(nn * 4) : 0);
-    }
     L.tab.push_back(take(mg_table_bytes(h)));
-    L.d.push_back(take(N * N * 8));
-    L.K.push_back(take((size_t)probs[i].nt * 4));
-    L.coef.push_back(take((size_t)probs[i].nt * kMaxCheb * sizeof(float2)));
-    L.lmax.push_back(take((size_t)probs[i].nt * 8));
+    L.lmax.push_back(take(nt * 8));
+    for (int s = 0; s < kLanes; ++s) {
+      const size_t q = (size_t)i * kLanes + s;
+      for (int l = 0; l <= h.G; ++l) {
+        const size_t nn = (size_t)h.n[l] * h.n[l];
+        L.x[q].push_back(take(nn * 4));
+        L.f[q].push_back(take(nn * 4));
+        L.e[q].push_back(l >= 1 && l < h.G ? take(nn * 4) : 0);
+      }
+      L.d.push_back(take(N * N * 8));
+      L.K.push_back(take(nt * 4));
+      L.coef.push_back(take(nt * kMaxCheb * sizeof(float2)));
+      L.R.push_back(take(N * N * 8));
+      L.ring.push_back(take(2 * N * N * 8));
+      L.park.push_back(take(N * N * 8));
+    }
   }
   L.total = o;
   return L;
@@ -1728,26 +1746,6 @@ size_t batch_header_bytes(const pts_problem* probs, int nprob) {
   size_t b = align_up((size_t)nprob * sizeof(BatchDesc)) + align_up(tiles_total * sizeof(int2));
   if (mg_eligible(probs, nprob)) b += mg_layout(probs, nprob).total;
   return b;
-}
-
-// Chebyshev for a spectrum in [a, b]: d_0 = z_0 / theta; d_k = rho_k rho_{k-1} d_{k-1} +
-// (2 rho_k / delta) z_k, rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
-// Returns the iterations that reach `target` (error bound 2 q^K, q = (sqrt(b/a) - 1) / (sqrt(b/a) + 1)).
-int cheb_coefficients(double a, double b, double target, float* c0, float* c1) {
-  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
-  const double q = (std::sqrt(b / a) - 1.0) / (std::sqrt(b / a) + 1.0);
-  int K = q > 0 ? (int)std::ceil(std::log(0.5 * target) / std::log(q)) : 1;
-  K = std::max(1, std::min(K, kMaxCheb));
-  double rho = delta / theta;
-  c0[0] = 0.f;
-  c1[0] = (float)(1.0 / theta);
-  for (int k = 1; k < K; ++k) {
-    const double rn = 1.0 / (2.0 * theta / delta - rho);
-    c0[k] = (float)(rn * rho);
-    c1[k] = (float)(2.0 * rn / delta);
-    rho = rn;
-  }
-  return K;
 }
 
 // Pinned staging for the descriptor upload (the batched solve synchronises every Newton step
@@ -1806,13 +1804,15 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     return at;
   };
   const size_t s_desc = stake((size_t)nprob * sizeof(BatchDesc)), s_items = stake(tiles_total * sizeof(int2));
-  const size_t s_dd = stake(eligible ? (size_t)nprob * sizeof(PcDesc) : 0);
-  const size_t s_mg = stake(eligible ? (size_t)nprob * sizeof(MgDesc) : 0);
+  const size_t nlanes = (size_t)nprob * kLanes;
+  const size_t s_dd = stake(eligible ? nlanes * sizeof(PcDesc) : 0);
+  const size_t s_mg = stake(eligible ? nlanes * sizeof(MgDesc) : 0);
   const size_t s_id = stake(eligible ? DL.nd * sizeof(int4) : 0);
   const size_t s_iu = stake(eligible ? DL.nu * sizeof(int4) : 0);
-  const size_t s_il = stake(eligible ? (size_t)nprob * sizeof(int) : 0);
+  const size_t s_il = stake(eligible ? nlanes * sizeof(int) : 0);
   const size_t s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
   const size_t s_ie0 = stake(eligible ? DL.ne * sizeof(int2) : 0);
+  const size_t s_ia = stake(eligible ? DL.ne * sizeof(int2) : 0);
   size_t tab_bytes = 0;
   if (eligible)
     for (int i = 0; i < nprob; ++i) tab_bytes += mg_table_bytes(mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a));
@@ -1835,6 +1835,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   int* h_il = (int*)(stage + s_il);
   int2* h_ie = (int2*)(stage + s_ie);
   int2* h_ie0 = (int2*)(stage + s_ie0);
+  int2* h_ia = (int2*)(stage + s_ia);
   double* h_sc = (double*)(stage + s_sc);  // per instance: max|r|, rho_max, rms, max|u^0|
   std::vector<size_t> ofs_nt(nprob, 0);      // instance i's levels start at ofs_nt[i] in the per-level tables
   for (int i = 1; i < nprob; ++i) ofs_nt[i] = ofs_nt[i - 1] + probs[i - 1].nt;
@@ -1884,23 +1885,51 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   for (int i = 0; i < nprob; ++i) rho0 = std::max(rho0, h_sc[4 * i + 1]);
   use_mg = eligible && rho0 >= kMgRho;
   if (use_mg) {
-    // hierarchies (fixed for the solve)
+    // hierarchies (fixed for the solve): one transfer table per instance, grids per lane
     size_t to = 0;
     for (int i = 0; i < nprob; ++i) {
-      MgDesc& m = h_mg[i];
-      m = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
-      for (int l = 0; l <= m.G; ++l) {
-        m.x[l] = (float*)(mg_base + DL.x[i][l]);
-        m.f[l] = (float*)(mg_base + DL.f[i][l]);
-        m.e[l] = l >= 1 && l < m.G ? (float*)(mg_base + DL.e[i][l]) : nullptr;
-      }
+      MgDesc m = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
       const size_t tb = mg_table_bytes(m);
       mg_fill_tables(m, stage + s_tab + to, mg_base + DL.tab[i]);
       HIPCHK(hipMemcpyAsync(mg_base + DL.tab[i], stage + s_tab + to, tb, hipMemcpyHostToDevice, s));
       to += tb;
+      for (int ln = 0; ln < kLanes; ++ln) {
+        const size_t q = (size_t)i * kLanes + ln;
+        for (int l = 0; l <= m.G; ++l) {
+          m.x[l] = (float*)(mg_base + DL.x[q][l]);
+          m.f[l] = (float*)(mg_base + DL.f[q][l]);
+          m.e[l] = l >= 1 && l < m.G ? (float*)(mg_base + DL.e[q][l]) : nullptr;
+        }
+        h_mg[q] = m;
+      }
     }
-    HIPCHK(hipMemcpyAsync(mg_base + DL.mgdesc, h_mg, (size_t)nprob * sizeof(MgDesc), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(mg_base + DL.mgdesc, h_mg, nlanes * sizeof(MgDesc), hipMemcpyHostToDevice, s));
   }
+  // descriptor of lane ln of instance i (pipelined lanes set their stage fields afterwards)
+  auto lane_desc = [&](int i, int ln) {
+    PcDesc d;
+    std::memset(&d, 0, sizeof d);
+    const size_t q = (size_t)i * kLanes + ln;
+    d.p = in[i].kp;
+    d.U = U[i];
+    d.R = in[i].R;
+    d.dU = in[i].dU;
+    d.r = (float*)(mg_base + DL.f[q][0]);
+    d.z = (float*)(mg_base + DL.x[q][0]);
+    d.d = (double*)(mg_base + DL.d[q]);
+    d.K = (int*)(mg_base + DL.K[q]);
+    d.c = (float2*)(mg_base + DL.coef[q]);
+    d.active = active[i];
+    d.ld = probs[i].nx;
+    d.rmask = -1;
+    d.dmask = -1;
+    d.u0 = u0[i];
+    d.stat = (unsigned long long*)(mg_base + DL.stat) + DL.lstat[i] + (size_t)ln * 3 * probs[i].nt;
+    return d;
+  };
+  const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
+  const bool pipelined = o == nullptr || o->schedule != PTS_SCHED_BULK;
+  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages : kLanes - 1);
   for (int it = 0;; ++it) {
     int nactive = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -1918,7 +1947,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         st->hist = std::min(it + 1, PTS_MAX_HIST);
         st->slab = p->nt;
         st->window = 1;
-        st->schedule = PTS_SCHED_BULK;
+        st->schedule = use_mg && pipelined ? PTS_SCHED_PIPELINE : PTS_SCHED_BULK;
       }
       int err = PTS_OK;
       if (!std::isfinite(res) || !std::isfinite(rhom)) {
@@ -1958,170 +1987,315 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       while (k > 0 && probs[order[k - 1]].nt <= n) --k;
       kpref[n] = k;
     }
-    if (use_mg) {
-      // inexact Newton: each level solve reduces its residual 1e3-fold by default (measured on
-      // the heat batch: one Newton step more than at 1e-6, 30 % less time, same converged result;
-      // a forcing term that starts at 0.1 and tightens with the residual ratio (Eisenstat-Walker)
-      // left an early iterate whose blocks lost diagonal dominance)
-      const size_t no = order.size();
-      std::vector<size_t> ce(no + 1, 0), ce0(no + 1, 0);
-      // down/up items of step g (g = 0..gmax-1): instance i takes part when g >= gmax - G_i, on
-      // grid g - (gmax - G_i); cumulative counts per prefix of `order`
-      const int gmax = DL.gmax;
-      std::vector<std::vector<size_t>> cd(gmax, std::vector<size_t>(no + 1, 0)), cu = cd;
-      std::vector<size_t> od(gmax, 0), ou(gmax, 0);
+    // profiling brackets of the multigrid launches (kinds: pts_stats.kern_* slots)
+    auto pb = [&](int kind) { prof_begin(prof, Prof::kKern + kind, s); };
+    auto pe = [&](double bytes) {
+      if (prof) {
+        prof->end(s);
+        prof->recs.back().bytes = bytes;
+      }
+    };
+    const int gmax = use_mg ? DL.gmax : 0;
+    const PcDesc* dd = (const PcDesc*)(mg_base + DL.desc);
+    const MgDesc* dm = (const MgDesc*)(mg_base + DL.mgdesc);
+    const int2* ie = (const int2*)(mg_base + DL.items_e);
+    const int2* ie0 = (const int2*)(mg_base + DL.items_e0);
+    const int2* ia = (const int2*)(mg_base + DL.items_a);
+    const int4* id = (const int4*)(mg_base + DL.items_d);
+    const int4* iu = (const int4*)(mg_base + DL.items_u);
+    const int* il = (const int*)(mg_base + DL.items_l);
+    // algorithmic bytes per node of the grid a launch works on (profiling), for lane q (index
+    // i kLanes + s) of instance i at Chebyshev iteration kk: k_pc_resid reads r^n, du^{n-1} and
+    // (kk > 0) u^n, x (8 B each), writes r (4) and (kk = 0) x; k_mg_down reads f_l, writes x_l
+    // and f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l,
+    // x_{l+1} and writes e_l, on the finest grid instead the Chebyshev step's reads and writes
+    // of d and du^n (8 each); k_pc_update reads z (4), d, du^n and writes d, du^n (8 each)
+    auto kb = [&](int kind, int i, int kk, int g) {
+      const MgDesc& m = h_mg[(size_t)i * kLanes];
+      const double N2 = (double)probs[i].nx * probs[i].nx;
+      const int l = g - (gmax - m.G);
+      switch (kind) {
+        case 0: return N2 * (kk == 0 ? 28.0 : 36.0);
+        case 1: return l >= 0 ? (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0 : 0.0;
+        case 2: return (double)m.n[m.G] * m.n[m.G] * 8.0;
+        case 3:
+          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 40.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0
+                        : 0.0;
+        default: return N2 * (kk == 0 ? 28.0 : 36.0);
+      }
+    };
+    // the V-cycle launches of Chebyshev iteration kk for the first ks lanes of a lane order
+    // (k_pc_resid, the down kernels, the LDS part, the up kernels, k_pc_update); m is the level
+    // (bulk) or the diagonal (pipelined); bytes(kind, g) gives the profiled launches' bytes
+    auto vcycle = [&](int m, int kk, size_t ks, const std::vector<size_t>& ce, const std::vector<size_t>& ce0,
+                      const std::vector<std::vector<size_t>>& cd, const std::vector<std::vector<size_t>>& cu,
+                      const std::vector<size_t>& od, const std::vector<size_t>& ou, auto&& bytes) {
+      pb(0);
+      hipLaunchKernelGGL(k_pc_resid, dim3((unsigned)ce[ks]), dim3(256), 0, s, dd, ie, m, kk);
+      pe(prof ? bytes(0, 0) : 0.0);
+      ++launches;
+      for (int g = 0; g < gmax; ++g) {
+        if (!cd[g][ks]) continue;
+        pb(1);
+        hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][ks]), dim3(kMgThreads), 0, s, dm, dd, id + od[g], m, kk);
+        pe(prof ? bytes(1, g) : 0.0);
+        ++launches;
+      }
+      pb(2);
+      hipLaunchKernelGGL(k_mg_lds, dim3((unsigned)ks), dim3(1024), 0, s, dm, dd, il, m, kk);
+      pe(prof ? bytes(2, 0) : 0.0);
+      ++launches;
+      for (int g = gmax - 1; g >= 0; --g) {
+        if (!cu[g][ks]) continue;
+        pb(3);
+        hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][ks]), dim3(kMgThreads), 0, s, dm, dd, iu + ou[g], m, kk);
+        pe(prof ? bytes(3, g) : 0.0);
+        ++launches;
+      }
+      if (ce0[ks]) {
+        pb(4);
+        hipLaunchKernelGGL(k_pc_update, dim3((unsigned)ce0[ks]), dim3(256), 0, s, dd, ie0, m, kk);
+        pe(prof ? bytes(4, 0) : 0.0);
+        ++launches;
+      }
+    };
+    // work items of a lane order: node chunks (ce), node chunks of lanes whose V-cycle is all
+    // in LDS (ce0, they keep z in memory), lane ids, and per step g the down/up tiles (an
+    // instance takes part when g >= gmax - G_i, on grid g - (gmax - G_i)); cumulative counts
+    // per prefix of the order, the items uploaded to the header
+    auto build_items = [&](const std::vector<int>& lanes, std::vector<size_t>& ce, std::vector<size_t>& ce0,
+                           std::vector<std::vector<size_t>>& cd, std::vector<std::vector<size_t>>& cu,
+                           std::vector<size_t>& od, std::vector<size_t>& ou) -> int {
+      const size_t no = lanes.size();
+      ce.assign(no + 1, 0);
+      ce0.assign(no + 1, 0);
+      cd.assign(gmax, std::vector<size_t>(no + 1, 0));
+      cu = cd;
+      od.assign(gmax, 0);
+      ou.assign(gmax, 0);
       size_t ne = 0, ne0 = 0, nd = 0, nu = 0;
+      for (size_t q = 0; q < no; ++q) {
+        const int ln = lanes[q], i = ln / kLanes;
+        const int N = probs[i].nx, ch = (N * N + 255) / 256;
+        for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(ln, c);
+        if (h_mg[ln].G == 0)
+          for (int c = 0; c < ch; ++c) h_ie0[ne0++] = make_int2(ln, c);
+        ce[q + 1] = ne;
+        ce0[q + 1] = ne0;
+        h_il[q] = ln;
+      }
+      for (int g = 0; g < gmax; ++g) {
+        od[g] = nd;
+        ou[g] = nu;
+        for (size_t q = 0; q < no; ++q) {
+          const int ln = lanes[q];
+          const MgDesc& m = h_mg[ln];
+          const int l = g - (gmax - m.G);
+          if (l >= 0) {
+            const int td = (m.n[l + 1] + kMgTC - 1) / kMgTC, tu = (m.n[l] + kMgTF - 1) / kMgTF;
+            for (int ty = 0; ty < td; ++ty)
+              for (int tx = 0; tx < td; ++tx) h_id[nd++] = make_int4(ln, l, tx, ty);
+            for (int ty = 0; ty < tu; ++ty)
+              for (int tx = 0; tx < tu; ++tx) h_iu[nu++] = make_int4(ln, l, tx, ty);
+          }
+          cd[g][q + 1] = nd - od[g];
+          cu[g][q + 1] = nu - ou[g];
+        }
+      }
+      HIPCHK(hipMemcpyAsync(mg_base + DL.desc, h_dd, nlanes * sizeof(PcDesc), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(mg_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
+      if (ne0) HIPCHK(hipMemcpyAsync(mg_base + DL.items_e0, h_ie0, ne0 * sizeof(int2), hipMemcpyHostToDevice, s));
+      if (nd) HIPCHK(hipMemcpyAsync(mg_base + DL.items_d, h_id, nd * sizeof(int4), hipMemcpyHostToDevice, s));
+      if (nu) HIPCHK(hipMemcpyAsync(mg_base + DL.items_u, h_iu, nu * sizeof(int4), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(mg_base + DL.items_l, h_il, no * sizeof(int), hipMemcpyHostToDevice, s));
+      return PTS_OK;
+    };
+    if (use_mg && pipelined) {
+      // nstages Newton steps in one pass over the diagonals D = n + s (k_pipe_* kernels): lanes
+      // (i, s), s = 0..S, ordered by nt_i + s, longest first; lane (i, s) has a level at D while
+      // D < nt_i + s, so the lanes of a diagonal are a prefix of the order (lanes with D < s
+      // return at once)
+      const int S = nstages;
+      std::vector<int> all, solving;
+      for (int i : order)
+        for (int sg = 0; sg <= S; ++sg) all.push_back(i * kLanes + sg);
+      auto key = [&](int ln) { return probs[ln / kLanes].nt + ln % kLanes; };
+      std::stable_sort(all.begin(), all.end(), [&](int a, int b) { return key(a) > key(b); });
+      for (int ln : all)
+        if (ln % kLanes < S) solving.push_back(ln);
+      // iterations launched per diagonal: the plan of max |u| 1.25 times the largest level
+      // maximum of the iterate the pass starts from (each lane plans from its own level's
+      // maximum and stops there if that needs fewer)
+      int kcap = 1;
+      for (int i : order) {
+        double um = 0.0;
+        for (int n = 0; n < probs[i].nt; ++n) um = std::max(um, h_lm[ofs_nt[i] + n]);
+        float2 c[kMaxCheb];
+        kcap = std::max(kcap, mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, 1.25 * um, lin_tol, c));
+      }
+      for (int i = 0; i < nprob; ++i)
+        for (int ln = 0; ln < kLanes; ++ln) {
+          const size_t q = (size_t)i * kLanes + ln;
+          PcDesc d = lane_desc(i, ln);
+          d.active = active[i] && ln <= S;
+          d.stage = ln;
+          d.rmask = 0;
+          d.dmask = 1;
+          d.last = ln == S;
+          d.R = (double*)(mg_base + DL.R[q]);
+          d.dU = (double*)(mg_base + DL.ring[q]);
+          d.park_out = ln >= 1 ? (double*)(mg_base + DL.park[q - 1]) : nullptr;
+          d.park_in = ln < S ? (const double*)(mg_base + DL.park[q]) : nullptr;
+          d.dprev = ln >= 1 ? (const double*)(mg_base + DL.ring[q - 1]) : nullptr;
+          d.tgt = lin_tol;
+          d.kcap = kcap;
+          h_dd[q] = d;
+        }
+      std::vector<size_t> ce, ce0, od, ou;
+      std::vector<std::vector<size_t>> cd, cu;
+      if ((rc = build_items(solving, ce, ce0, cd, cu, od, ou))) return rc;
+      // node chunks of every lane (the update and residual launches)
+      std::vector<size_t> ca(all.size() + 1, 0);
+      size_t na = 0;
+      for (size_t q = 0; q < all.size(); ++q) {
+        const int N = probs[all[q] / kLanes].nx, ch = (N * N + 255) / 256;
+        for (int c = 0; c < ch; ++c) h_ia[na++] = make_int2(all[q], c);
+        ca[q + 1] = na;
+      }
+      HIPCHK(hipMemcpyAsync(mg_base + DL.items_a, h_ia, na * sizeof(int2), hipMemcpyHostToDevice, s));
+      unsigned long long* stat = (unsigned long long*)(mg_base + DL.stat);
+      hipLaunchKernelGGL(k_zero, dim3((unsigned)((DL.stat_words + 255) / 256)), dim3(256), 0, s, stat,
+                         (int)DL.stat_words);
+      ++launches;
+      // profiling: the iteration counts the lanes planned, read back per diagonal
+      std::vector<int> kq(solving.size(), 0);
+      int* d_kq = (int*)(mg_base + DL.items_k);
+      auto lane_level = [&](int ln, int D) {
+        const int n = D - ln % kLanes;
+        return (n >= 0 && n < probs[ln / kLanes].nt) ? n : -1;
+      };
+      const int Dend = key(all.front());
+      size_t ka = all.size(), ks = solving.size();
+      for (int D = 0; D < Dend; ++D) {
+        while (ka > 0 && key(all[ka - 1]) <= D) --ka;
+        while (ks > 0 && key(solving[ks - 1]) <= D) --ks;
+        double b5 = 0.0, b6 = 0.0;
+        if (prof)
+          for (size_t q = 0; q < ka; ++q) {
+            const int ln = all[q], sg = ln % kLanes;
+            if (lane_level(ln, D) < 0) continue;
+            const double N2 = (double)probs[ln / kLanes].nx * probs[ln / kLanes].nx;
+            b5 += N2 * (sg == S ? 16.0 : 24.0);  // reads u^n, u^{n-1}; writes r
+            if (sg >= 1) b6 += N2 * 32.0;        // reads u^n, du; writes the park and u^n
+          }
+        pb(6);
+        hipLaunchKernelGGL(k_pipe_update, dim3((unsigned)ca[ka]), dim3(256), 0, s, dd, ia, D);
+        pe(b6);
+        pb(5);
+        hipLaunchKernelGGL(k_pipe_residual, dim3((unsigned)ca[ka]), dim3(256), 0, s, dd, ia, D);
+        pe(b5);
+        launches += 2;
+        if (ks == 0) continue;
+        pb(7);
+        hipLaunchKernelGGL(k_pipe_cheb, dim3((unsigned)((ks + 63) / 64)), dim3(64), 0, s, dd, il, (int)ks, D, d_kq);
+        pe(0.0);
+        ++launches;
+        if (prof) {
+          HIPCHK(hipMemcpyAsync(kq.data(), d_kq, ks * sizeof(int), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+        }
+        for (int kk = 0; kk < kcap; ++kk)
+          vcycle(D, kk, ks, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
+            double b = 0.0;
+            for (size_t q = 0; q < ks; ++q)
+              if (lane_level(solving[q], D) >= 0 && kk < kq[q]) b += kb(kind, solving[q] / kLanes, kk, g);
+            return b;
+          });
+      }
+      HIPCHK(hipGetLastError());
+      // the result: max |R| of U^(S) (lane S), the largest radius and any NaN of every lane
+      std::vector<unsigned long long> hst(DL.stat_words);
+      HIPCHK(hipMemcpyAsync(hst.data(), stat, DL.stat_words * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      auto val = [](unsigned long long b) {
+        double v;
+        std::memcpy(&v, &b, 8);
+        return v;
+      };
+      for (int i : order) {
+        const unsigned long long* st = hst.data() + DL.lstat[i];
+        const int nt = probs[i].nt;
+        // bit patterns of non-negative doubles: at or above that of +inf means not finite
+        constexpr unsigned long long kInf = 0x7ff0000000000000ull;
+        unsigned long long res = 0, rho = 0;
+        bool finite = true;
+        for (int sg = 0; sg <= S; ++sg)
+          for (int n = 0; n < nt; ++n) {
+            const unsigned long long* q = st + ((size_t)sg * nt + n) * 3;
+            finite = finite && q[0] < kInf && q[1] < kInf && q[2] < kInf;
+            rho = std::max(rho, q[2]);
+            if (sg == S) {
+              res = std::max(res, q[1]);
+              h_lm[ofs_nt[i] + n] = val(q[0]);
+            }
+          }
+        h_sc[4 * i] = finite ? val(res) : std::nan("");
+        h_sc[4 * i + 1] = val(rho);
+        h_sc[4 * i + 2] = std::nan("");
+        if (stats) {
+          stats[i].schedule = PTS_SCHED_PIPELINE;
+          stats[i].sweeps = kcap;
+          stats[i].refine = 0;
+          for (int j = it + 1; j < it + S && j < PTS_MAX_HIST; ++j) {
+            stats[i].res_inf[j] = std::nan("");
+            stats[i].rho_max[j] = std::nan("");
+          }
+        }
+      }
+      if (prof) prof->collect(&pstat);
+      it += S - 1;
+      continue;
+    }
+    if (use_mg) {
+      // one Newton step: level after level, every lane-0 solver of the active instances; the
+      // Chebyshev plans of every level from the current iterate's level maxima (host)
+      std::vector<int> lanes;
+      for (int i : order) lanes.push_back(i * kLanes);
+      std::memset((void*)h_dd, 0, nlanes * sizeof(PcDesc));  // lanes 1.. stay inactive
       for (int i = 0; i < nprob; ++i) {
-        PcDesc& d = h_dd[i];
-        std::memset(&d, 0, sizeof d);
-        d.p = in[i].kp;
-        d.U = U[i];
-        d.R = in[i].R;
-        d.dU = in[i].dU;
-        d.r = (float*)(mg_base + DL.f[i][0]);
-        d.z = (float*)(mg_base + DL.x[i][0]);
-        d.d = (double*)(mg_base + DL.d[i]);
-        d.K = (const int*)(mg_base + DL.K[i]);
-        d.c = (const float2*)(mg_base + DL.coef[i]);
-        d.active = active[i];
-        d.ld = probs[i].nx;
+        h_dd[(size_t)i * kLanes] = lane_desc(i, 0);
         if (!active[i]) continue;
-        const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
-        // level n: with M = I + tau mu_a (-Delta_h) the preconditioned spectrum lies in
-        // [1, mu_hi / mu_a], mu_hi = mu(1.1 max |u^n|); the margin m covers the non-symmetric
-        // mu' terms of the Jacobian (they grow with u) and float32 rounding; the V-cycle moves
-        // the lower end to kMgLow (1 - m)
         int kmax_i = 0;
         for (int n = 0; n < probs[i].nt; ++n) {
-          const double um = 1.1 * h_lm[ofs_nt[i] + n];
-          const double ratio = (probs[i].mu_a + probs[i].mu_b * um * um) / probs[i].mu_a;
-          const double m = 0.05 + 0.15 * (ratio - 1.0);
-          float c0[kMaxCheb], c1[kMaxCheb];
-          const int K = cheb_coefficients(kMgLow * (1.0 - std::min(m, 0.5)), ratio * (1.0 + m), lin_tol, c0, c1);
+          const int K = mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, h_lm[ofs_nt[i] + n], lin_tol,
+                                     h_cf + (ofs_nt[i] + n) * kMaxCheb);
           h_kt[ofs_nt[i] + n] = K;
-          for (int k = 0; k < K; ++k) h_cf[(ofs_nt[i] + n) * kMaxCheb + k] = make_float2(c0[k], c1[k]);
           kmax_i = std::max(kmax_i, K);
         }
-        HIPCHK(hipMemcpyAsync(mg_base + DL.K[i], h_kt + ofs_nt[i], (size_t)probs[i].nt * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(mg_base + DL.coef[i], h_cf + ofs_nt[i] * kMaxCheb,
+        const size_t q = (size_t)i * kLanes;
+        HIPCHK(hipMemcpyAsync(mg_base + DL.K[q], h_kt + ofs_nt[i], (size_t)probs[i].nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(mg_base + DL.coef[q], h_cf + ofs_nt[i] * kMaxCheb,
                               (size_t)probs[i].nt * kMaxCheb * sizeof(float2), hipMemcpyHostToDevice, s));
         if (stats) {
           stats[i].sweeps = kmax_i;
           stats[i].refine = 0;
         }
       }
-      // node items and LDS items: the instances that have level n are a prefix of `order`
-      for (size_t q = 0; q < no; ++q) {
-        const int i = order[q];
-        const int N = probs[i].nx, ch = (N * N + 255) / 256;
-        for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(i, c);
-        // a stored z (k_pc_update) only where the V-cycle is all in LDS; elsewhere the last
-        // up kernel applies the Chebyshev step
-        if (h_mg[i].G == 0)
-          for (int c = 0; c < ch; ++c) h_ie0[ne0++] = make_int2(i, c);
-        ce[q + 1] = ne;
-        ce0[q + 1] = ne0;
-        h_il[q] = i;
-      }
-      for (int g = 0; g < gmax; ++g) {
-        od[g] = nd;
-        ou[g] = nu;
-        for (size_t q = 0; q < no; ++q) {
-          const int i = order[q];
-          const MgDesc& m = h_mg[i];
-          const int l = g - (gmax - m.G);
-          if (l >= 0) {
-            const int td = (m.n[l + 1] + kMgTC - 1) / kMgTC, tu = (m.n[l] + kMgTF - 1) / kMgTF;
-            for (int ty = 0; ty < td; ++ty)
-              for (int tx = 0; tx < td; ++tx) h_id[nd++] = make_int4(i, l, tx, ty);
-            for (int ty = 0; ty < tu; ++ty)
-              for (int tx = 0; tx < tu; ++tx) h_iu[nu++] = make_int4(i, l, tx, ty);
-          }
-          cd[g][q + 1] = nd - od[g];
-          cu[g][q + 1] = nu - ou[g];
-        }
-      }
-      HIPCHK(hipMemcpyAsync(mg_base + DL.desc, h_dd, (size_t)nprob * sizeof(PcDesc), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(mg_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
-      if (ne0) HIPCHK(hipMemcpyAsync(mg_base + DL.items_e0, h_ie0, ne0 * sizeof(int2), hipMemcpyHostToDevice, s));
-      if (nd) HIPCHK(hipMemcpyAsync(mg_base + DL.items_d, h_id, nd * sizeof(int4), hipMemcpyHostToDevice, s));
-      if (nu) HIPCHK(hipMemcpyAsync(mg_base + DL.items_u, h_iu, nu * sizeof(int4), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(mg_base + DL.items_l, h_il, no * sizeof(int), hipMemcpyHostToDevice, s));
-      const PcDesc* dd = (const PcDesc*)(mg_base + DL.desc);
-      const MgDesc* dm = (const MgDesc*)(mg_base + DL.mgdesc);
-      const int2* ie = (const int2*)(mg_base + DL.items_e);
-      const int2* ie0 = (const int2*)(mg_base + DL.items_e0);
-      const int4* id = (const int4*)(mg_base + DL.items_d);
-      const int4* iu = (const int4*)(mg_base + DL.items_u);
-      const int* il = (const int*)(mg_base + DL.items_l);
-      // algorithmic bytes per node of the grid a launch works on (profiling): k_pc_resid reads
-      // u^n, r^n, du^{n-1}, x (8 B each) and writes r (4); k_mg_down reads f_l, writes x_l and
-      // f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l, x_{l+1}
-      // and writes e_l, on the finest grid instead the Chebyshev step's reads and writes of d and
-      // du^n (8 each); k_pc_update reads z (4), d, du^n and writes d, du^n (8 each)
-      auto kb = [&](int kind, int k, int n, int kk, int g) {
-        double b = 0.0;
-        for (int q = 0; q < k; ++q) {
-          const int i = order[q];
-          if (kk >= h_kt[ofs_nt[i] + n]) continue;
-          const MgDesc& m = h_mg[i];
-          const double N2 = (double)probs[i].nx * probs[i].nx;
-          const int l = g - (gmax - m.G);
-          switch (kind) {
-            case 0: b += N2 * (kk == 0 ? 20.0 : 36.0); break;
-            case 1: if (l >= 0) b += (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0; break;
-            case 2: b += (double)m.n[m.G] * m.n[m.G] * 8.0; break;
-            case 3:
-              if (l >= 0)
-                b += (double)m.n[l] * m.n[l] * (l == 0 ? 40.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0;
-              break;
-            default: b += N2 * (kk == 0 ? 28.0 : 36.0); break;
-          }
-        }
-        return b;
-      };
-      auto pb = [&](int kind) { prof_begin(prof, Prof::kKern + kind, s); };
-      auto pe = [&](int kind, double bytes) {
-        if (prof) {
-          prof->end(s);
-          prof->recs.back().bytes = bytes;
-        }
-      };
+      std::vector<size_t> ce, ce0, od, ou;
+      std::vector<std::vector<size_t>> cd, cu;
+      if ((rc = build_items(lanes, ce, ce0, cd, cu, od, ou))) return rc;
       for (int n = 0; n < maxnt; ++n) {
         const int k = kpref[n];
         if (k == 0) continue;
         int kn = 0;  // iterations of level n: the most any instance in the prefix needs
         for (int q = 0; q < k; ++q) kn = std::max(kn, h_kt[ofs_nt[order[q]] + n]);
-        for (int kk = 0; kk < kn; ++kk) {
-          pb(0);
-          hipLaunchKernelGGL(k_pc_resid, dim3((unsigned)ce[k]), dim3(256), 0, s, dd, ie, n, kk);
-          pe(0, prof ? kb(0, k, n, kk, 0) : 0.0);
-          ++launches;
-          for (int g = 0; g < gmax; ++g) {
-            if (!cd[g][k]) continue;
-            pb(1);
-            hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][k]), dim3(kMgThreads), 0, s, dm, dd, id + od[g], n, kk);
-            pe(1, prof ? kb(1, k, n, kk, g) : 0.0);
-            ++launches;
-          }
-          pb(2);
-          hipLaunchKernelGGL(k_mg_lds, dim3((unsigned)k), dim3(1024), 0, s, dm, dd, il, n, kk);
-          pe(2, prof ? kb(2, k, n, kk, 0) : 0.0);
-          ++launches;
-          for (int g = gmax - 1; g >= 0; --g) {
-            if (!cu[g][k]) continue;
-            pb(3);
-            hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][k]), dim3(kMgThreads), 0, s, dm, dd, iu + ou[g], n, kk);
-            pe(3, prof ? kb(3, k, n, kk, g) : 0.0);
-            ++launches;
-          }
-          if (ce0[k]) {
-            pb(4);
-            hipLaunchKernelGGL(k_pc_update, dim3((unsigned)ce0[k]), dim3(256), 0, s, dd, ie0, n, kk);
-            pe(4, prof ? kb(4, k, n, kk, 0) : 0.0);
-            ++launches;
-          }
-        }
+        for (int kk = 0; kk < kn; ++kk)
+          vcycle(n, kk, (size_t)k, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
+            double b = 0.0;
+            for (int q = 0; q < k; ++q)
+              if (kk < h_kt[ofs_nt[order[q]] + n]) b += kb(kind, order[q], kk, g);
+            return b;
+          });
       }
     } else {
       // descriptors (inactive instances have no launches) and work items, longest first

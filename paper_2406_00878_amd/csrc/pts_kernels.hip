@@ -420,19 +420,63 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
 // V-cycle launches), d = c0 d + c1 z, x += d in FP64 (ChebStep, applied where the V-cycle
 // writes its finest grid; k_pc_update for a z stored in memory).
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
+// One level solver's arrays. In the bulk schedule there is one per instance (stage 0, full
+// space-time R and dU). In the pipelined schedule there is one per (instance, Newton stage s),
+// a "lane": a launch for diagonal D has lane s work on level n = D - s, with its residual in a
+// level buffer (rmask 0) and its update in a ring of two levels (dmask 1).
 struct PcDesc {
   KProb p;
-  const double* U;    // iterate [nt][N][N]
-  const double* R;    // residual [nt][N][N]
-  double* dU;         // update [nt][N][N]; the level solve iterates in dU[n]
+  double* U;          // iterate [nt][N][N]
+  double* R;          // residual: level n at R + (n & rmask) N^2
+  double* dU;         // update: level n at dU + (n & dmask) N^2; the level solve iterates in it
   float* r;           // [N][ld] level residual b - A x (float32)
   float* z;           // [N][ld] B r
   double* d;          // [N][N] Chebyshev direction
-  const int* K;       // [nt] iterations of level n (the interval follows the level's max |u|)
-  const float2* c;    // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
+  int* K;             // [nt] iterations of level n (the interval follows the level's max |u|)
+  float2* c;          // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
   int active;
   int ld;             // row stride of the float32 arrays (N)
+  int stage;          // the lane's Newton stage s (0 in the bulk schedule)
+  int rmask, dmask;   // -1 in the bulk schedule
+  // pipelined schedule only
+  int last;                // the lane after the last stage: update and residual, no level solve
+  const double* u0;        // the initial condition (level -1)
+  double* park_out;        // lane s-1's park: U^(s-1) of the level this lane updates
+  const double* park_in;   // U^(s) of level n-1, parked by lane s+1 (NULL: read U)
+  const double* dprev;     // lane s-1's update ring
+  unsigned long long* stat;  // [nt][3] max |U^(s)_n|, max |R^(s)_n|, Gershgorin radius (bits)
+  double tgt;              // residual reduction asked of a level solve
+  int kcap;                // at most this many iterations (the launches the host issues)
 };
+
+// Chebyshev for a spectrum in [a, b]: d_0 = z_0 / theta; d_k = rho_k rho_{k-1} d_{k-1} +
+// (2 rho_k / delta) z_k, rho_0 = delta / theta, rho_k = 1 / (2 theta / delta - rho_{k-1}).
+// Returns the iterations that reach `target` (error bound 2 q^K, q = (sqrt(b/a) - 1) / (sqrt(b/a) + 1)).
+__host__ __device__ inline int cheb_coefficients(double a, double b, double target, float2* c) {
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double q = (sqrt(b / a) - 1.0) / (sqrt(b / a) + 1.0);
+  int K = q > 0 ? (int)ceil(log(0.5 * target) / log(q)) : 1;
+  K = K < 1 ? 1 : (K > kMaxCheb ? kMaxCheb : K);
+  double rho = delta / theta;
+  c[0] = make_float2(0.f, (float)(1.0 / theta));
+  for (int k = 1; k < K; ++k) {
+    const double rn = 1.0 / (2.0 * theta / delta - rho);
+    c[k] = make_float2((float)(rn * rho), (float)(2.0 * rn / delta));
+    rho = rn;
+  }
+  return K;
+}
+
+// Chebyshev plan of a multigrid-preconditioned level solve whose iterate has max |u| = umax:
+// with M = I + tau mu_a (-Delta_h) the preconditioned spectrum lies in [1, mu_hi / mu_a],
+// mu_hi = mu(1.1 umax); the margin m covers the non-symmetric mu' terms of the Jacobian (they
+// grow with u) and float32 rounding; the V-cycle moves the lower end to kMgLow (1 - m).
+__host__ __device__ inline int mg_cheb_plan(double mu_a, double mu_b, double umax, double target, float2* c) {
+  const double um = 1.1 * umax;
+  const double ratio = (mu_a + mu_b * um * um) / mu_a;
+  const double m = 0.05 + 0.15 * (ratio - 1.0);
+  return cheb_coefficients(kMgLow * (1.0 - (m < 0.5 ? m : 0.5)), ratio * (1.0 + m), target, c);
+}
 
 // out[n] = max |U^n| (bit pattern of a non-negative double), one work-group per level
 __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__ U, size_t ns,
@@ -447,21 +491,23 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
   if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
 }
 
-// Work items (instance, chunk of 256 nodes), sorted by level count. Iteration k of level n:
+// Work items (lane, chunk of 256 nodes), sorted by level count. Iteration k of level n:
 // r = b - A x with b = r^n + du^{n-1} (Eq. (7)) and x = du^n (x = 0 at k = 0, written here).
+// m: the level (bulk) or the diagonal (pipelined); the lane's level is m - stage.
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                   int n, int k) {
+                                                   int m, int k) {
   const int2 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
-  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  const int n = m - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   const KProb p = at_level(d->p, n);
   const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
   if (i >= ns) return;
   const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
   const size_t lev = (size_t)n * ns;
-  double b = d->R[lev + i] + (n > 0 ? d->dU[lev - ns + i] : 0.0);
-  double* X = d->dU + lev;
+  double b = d->R[(size_t)(n & d->rmask) * ns + i] + (n > 0 ? d->dU[(size_t)((n - 1) & d->dmask) * ns + i] : 0.0);
+  double* X = d->dU + (size_t)(n & d->dmask) * ns;
   if (k == 0) {
     X[i] = 0.0;
   } else {
@@ -481,10 +527,11 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
 
 // d = c0 d + c1 z, x += d
 __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                    int n, int k) {
+                                                    int m, int k) {
   const int2 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
-  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  const int n = m - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
   const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
   if (i >= ns) return;
@@ -492,16 +539,17 @@ __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds
   const float zi = d->z[(size_t)(i / (unsigned)d->p.nx) * d->ld + (i % (unsigned)d->p.nx)];
   const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)zi;
   d->d[i] = dir;
-  d->dU[(size_t)n * ns + i] += dir;
+  d->dU[(size_t)(n & d->dmask) * ns + i] += dir;
 }
 
-// V-cycle launches of iteration k of level n. Items (instance, grid l, tile x, tile y) of the
-// instances that have level n; instances without level n or iteration k return.
+// V-cycle launches of iteration k of level n. Items (lane, grid l, tile x, tile y) of the
+// lanes that have level n; lanes without level n or iteration k return.
 __global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
-                                                 const int4* __restrict__ items, int n, int k) {
+                                                 const int4* __restrict__ items, int m, int k) {
   const int4 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
-  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  const int n = m - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   __shared__ float F[kMgDS * kMgDS], X[kMgDS * kMgDS], T[kMgDS * kMgTC];
   __shared__ MgDownAux aux;
   mg_down_tile(mg[it.x], it.y, it.z, it.w, F, X, T, aux);
@@ -517,42 +565,131 @@ struct ChebStep {
     const float2 c = d->c[(size_t)n * kMaxCheb + k];
     const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[idx]) + (double)c.y * (double)z;
     d->d[idx] = dir;
-    d->dU[(size_t)n * N * N + idx] += dir;
+    d->dU[(size_t)(n & d->dmask) * N * N + idx] += dir;
   }
 };
 
 __global__ __launch_bounds__(kMgThreads) void k_mg_up(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
-                                               const int4* __restrict__ items, int n, int k) {
+                                               const int4* __restrict__ items, int m, int k) {
   const int4 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
-  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  const int n = m - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   __shared__ float X[kMgUS * kMgUS], F[kMgUS * kMgUS], X1[kMgUS * kMgUS], E[kMgUE * kMgUE];
-  const MgDesc& m = mg[it.x];
+  const MgDesc& mg_ = mg[it.x];
   const int l = it.y;
   if (l == 0) {
-    mg_up_tile(m, 0, it.z, it.w, X, F, X1, E, ChebStep{d, n, k, m.n[0]});
+    mg_up_tile(mg_, 0, it.z, it.w, X, F, X1, E, ChebStep{d, n, k, mg_.n[0]});
   } else {
-    float* e = m.e[l];
-    const int nl = m.n[l];
-    mg_up_tile(m, l, it.z, it.w, X, F, X1, E, [=](int i, int j, float v) { e[(size_t)j * nl + i] = v; });
+    float* e = mg_.e[l];
+    const int nl = mg_.n[l];
+    mg_up_tile(mg_, l, it.z, it.w, X, F, X1, E, [=](int i, int j, float v) { e[(size_t)j * nl + i] = v; });
   }
 }
 
-// One work-group per instance: the V-cycle's grids from G down (LDS).
+// One work-group per lane: the V-cycle's grids from G down (LDS).
 __global__ __launch_bounds__(1024) void k_mg_lds(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
-                                                 const int* __restrict__ items, int n, int k) {
+                                                 const int* __restrict__ items, int m, int k) {
   const int i = items[blockIdx.x];
   const PcDesc* d = ds + i;
-  if (!d->active || n >= d->p.nt || k >= d->K[n]) return;
+  const int n = m - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   __shared__ float X[kMgLdsWords], F[kMgLdsWords], T[kMgLdsWords];
-  const MgDesc& m = mg[i];
-  if (m.G == 0) {
-    mg_lds_cycle(m, X, F, T, ChebStep{d, n, k, m.n[0]});
+  const MgDesc& mg_ = mg[i];
+  if (mg_.G == 0) {
+    mg_lds_cycle(mg_, X, F, T, ChebStep{d, n, k, mg_.n[0]});
   } else {
-    float* x = m.x[m.G];
-    const int nl = m.n[m.G];
-    mg_lds_cycle(m, X, F, T, [=](int a, int b, float v) { x[b * nl + a] = v; });
+    float* x = mg_.x[mg_.G];
+    const int nl = mg_.n[mg_.G];
+    mg_lds_cycle(mg_, X, F, T, [=](int a, int b, float v) { x[b * nl + a] = v; });
   }
+}
+
+// ---------------------------------------------- pipelined Newton stages (multigrid lanes)
+// Newton stage s at level n needs U^(s) at levels n and n-1 and du^(s) of level n-1; it
+// produces du^(s)_n, from which U^(s+1)_n = U^(s)_n + du^(s)_n. Stage s therefore runs on
+// level n at diagonal D = n + s: lane s of an instance applies the update of stage s-1 to level
+// n (k_pipe_update), forms r^(s)_n (k_pipe_residual), plans its Chebyshev iteration from
+// max |U^(s)_n| (k_pipe_cheb) and solves (k_pc_resid and the V-cycle launches), all in the
+// launches of diagonal D. Lane s-1 works on level n+1 at the same diagonal and needs the
+// U^(s-1)_n that lane s overwrites: lane s parks it first. Lane S (after the last stage) only
+// updates and forms the residual of the result. The update rings hold two levels: du^(s)_n is
+// read at diagonal D+1 (by lane s at level n+1 and by lane s+1 at level n) and overwritten at
+// D+2.
+__global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
+                                                      int D) {
+  const int2 it = items[blockIdx.x];
+  const PcDesc* d = ds + it.x;
+  const int n = D - d->stage;
+  if (!d->active || d->stage == 0 || n < 0 || n >= d->p.nt) return;
+  const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
+  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
+  if (i >= ns) return;
+  double* u = d->U + (size_t)n * ns + i;
+  const double old = *u;
+  d->park_out[i] = old;
+  *u = old + d->dprev[(size_t)(n & 1) * ns + i];
+}
+
+// r^(s)_n = -(U^(s)_n - U^(s)_{n-1} + tau F(U^(s)_n)) into the lane's level buffer, with
+// max |U^(s)_n|, max |r| and the Gershgorin radius of the level's rows into stat[n].
+__global__ __launch_bounds__(256) void k_pipe_residual(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
+                                                        int D) {
+  const int2 it = items[blockIdx.x];
+  const PcDesc* d = ds + it.x;
+  const int n = D - d->stage;
+  if (!d->active || n < 0 || n >= d->p.nt) return;
+  const KProb p = at_level(d->p, n);
+  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
+  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
+  double uabs = 0.0, rabs = 0.0, rho = 0.0;
+  if (i < ns) {
+    const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
+    const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+    const Nb u = gather<0>(p, d->U + (size_t)n * ns, bd, x, y);
+    const double* up = n == 0 ? d->u0 : (d->park_in ? d->park_in : d->U + (size_t)(n - 1) * ns);
+    Row5 a;
+    const double F = eval_point<0, kFormNoConv>(p, u, x, y, a);
+    const double r = -(u.P - up[i] + p.dt * F);
+    if (!d->last) d->R[i] = r;
+    uabs = fabs(u.P);
+    rabs = fabs(r);
+    rho = gersh(a);
+  }
+  __shared__ double red[3][4];
+  uabs = wave_max(uabs);
+  rabs = wave_max(rabs);
+  rho = wave_max(rho);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = uabs;
+    red[1][w] = rabs;
+    red[2][w] = rho;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const double* q = red[threadIdx.x];
+    atomic_max_nonneg(d->stat + 3 * (size_t)n + threadIdx.x, nanmax(nanmax(q[0], q[1]), nanmax(q[2], q[3])));
+  }
+}
+
+// Chebyshev plan of each solving lane's level (one thread per lane); kq[q]: the iterations
+// lane q runs at this diagonal (0 without a level).
+__global__ __launch_bounds__(64) void k_pipe_cheb(const PcDesc* __restrict__ ds, const int* __restrict__ lanes, int nl,
+                                                  int D, int* __restrict__ kq) {
+  const int q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= nl) return;
+  const PcDesc* d = ds + lanes[q];
+  const int n = D - d->stage;
+  if (!d->active || d->last || n < 0 || n >= d->p.nt) {
+    kq[q] = 0;
+    return;
+  }
+  const double umax = __longlong_as_double((long long)d->stat[3 * (size_t)n]);
+  int K = mg_cheb_plan(d->p.mu_a, d->p.mu_b, umax, d->tgt, d->c + (size_t)n * kMaxCheb);
+  K = K < d->kcap ? K : d->kcap;
+  d->K[n] = K;
+  kq[q] = K;
 }
 
 // ---------------------------------------------------------- wavefront schedule

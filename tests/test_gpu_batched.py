@@ -85,17 +85,21 @@ def test_nonconverging_instance_reports_and_others_finish():
         P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-30, max_iter=2)
 
 
-@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-8)])
-def test_stiff_heat_batch_multigrid_level_solves_match_oracle(precision, bar):
+@pytest.mark.parametrize("precision,bar,schedule", [("fp64", 1e-10, "auto"), ("mixed", 1e-8, "auto"),
+                                                     ("mixed", 1e-8, "bulk")])
+def test_stiff_heat_batch_multigrid_level_solves_match_oracle(precision, bar, schedule):
     """Stiff Dirichlet heat levels (Gershgorin radius >= 0.976) take the multigrid-preconditioned
-    Chebyshev solve: few iterations per level, no restarted passes, same converged result."""
+    Chebyshev solve: few iterations per level, no restarted passes, same converged result; by
+    default as pipelined Newton stages, with schedule="bulk" one Newton step after another."""
     probs = _heat_batch(12, [(128, 3), (100, 4), (150, 2)])
     Us = [dev(p.plain_iterate()) for p in probs]
-    print(f"[batched] stiff heat {precision}", flush=True)
-    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision=precision)
+    print(f"[batched] stiff heat {precision} {schedule}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision=precision,
+                          schedule=schedule)
     for p, U, st in zip(probs, Us, sts):
         assert st["converged"], st
         assert st["refine"] == 0 and st["sweeps"] <= 32, st  # spectral path: Chebyshev iterations, one pass
+        assert st["schedule"] == (P.PTS_SCHED_BULK if schedule == "bulk" else P.PTS_SCHED_PIPELINE), st
         Uo, _ = sequential.solve_sequential(p)
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err)
@@ -111,6 +115,25 @@ def test_stiff_heat_batch_deep_hierarchies_match_oracle():
     sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision="mixed")
     for p, U, st in zip(probs, Us, sts):
         assert st["converged"] and st["refine"] == 0 and st["sweeps"] <= 32, st
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err, flush=True)
+        assert err <= 1e-8, (p.name, err)
+
+
+@pytest.mark.parametrize("stages", [0, 3])
+def test_stiff_heat_batch_pipelined_stages_match_oracle(stages):
+    """Pipelined Newton stages over many levels: instances with more levels than stages (the
+    lanes of all stages overlap on consecutive levels) and fewer (lanes idle at the ends), the
+    default stage count (7) and a short one that needs several passes over the diagonals."""
+    probs = _heat_batch(21, [(128, 20), (66, 33), (100, 9), (90, 1)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print(f"[batched] stiff heat pipelined, stages {stages}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision="mixed",
+                          stages=stages)
+    for p, U, st in zip(probs, Us, sts):
+        assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
+        assert st["iterations"] % (stages or 7) == 0, st
         Uo, _ = sequential.solve_sequential(p)
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err, flush=True)
