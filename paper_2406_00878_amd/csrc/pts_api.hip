@@ -1691,7 +1691,7 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
   };
   for (int i = 0; i < nprob; ++i) {
     const size_t N = probs[i].nx;
-    L.ne += kLanes * ((N * N + 255) / 256);
+    L.ne += kLanes * std::max<size_t>(pc_tiles((int)N, (int)N), (N * N + 255) / 256);
     const MgDesc h = mg_hierarchy(probs[i].nx, probs[i].dt * probs[i].mu_a);
     for (int l = 0; l < h.G; ++l) {
       L.nd += kLanes * mg_down_tiles(h, l);
@@ -2076,7 +2076,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       size_t ne = 0, ne0 = 0, nd = 0, nu = 0;
       for (size_t q = 0; q < no; ++q) {
         const int ln = lanes[q], i = ln / kLanes;
-        const int N = probs[i].nx, ch = (N * N + 255) / 256;
+        const int N = probs[i].nx, ch = pc_tiles(N, N);
         for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(ln, c);
         if (h_mg[ln].G == 0)
           for (int c = 0; c < ch; ++c) h_ie0[ne0++] = make_int2(ln, c);

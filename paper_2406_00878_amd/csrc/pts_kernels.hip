@@ -491,9 +491,13 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
   if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
 }
 
-// Work items (lane, chunk of 256 nodes), sorted by level count. Iteration k of level n:
-// r = b - A x with b = r^n + du^{n-1} (Eq. (7)) and x = du^n (x = 0 at k = 0, written here).
-// m: the level (bulk) or the diagonal (pipelined); the lane's level is m - stage.
+// Work items (lane, tile of 64 x kPcTileY nodes), sorted by level count; thread (c, g) of the
+// 64 x 4 work-group walks kPcRows rows of column c, keeping the column's u and x of the rows
+// above and below in registers. Iteration k of level n: r = b - A x with b = r^n + du^{n-1}
+// (Eq. (7)) and x = du^n (x = 0 at k = 0, written here). m: the level (bulk) or the diagonal
+// (pipelined); the lane's level is m - stage.
+constexpr int kPcRows = 4, kPcTileY = 4 * kPcRows;
+__host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                    int m, int k) {
   const int2 it = items[blockIdx.x];
@@ -501,45 +505,72 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
   const KProb p = at_level(d->p, n);
-  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
-  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
-  if (i >= ns) return;
-  const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
-  const size_t lev = (size_t)n * ns;
-  double b = d->R[(size_t)(n & d->rmask) * ns + i] + (n > 0 ? d->dU[(size_t)((n - 1) & d->dmask) * ns + i] : 0.0);
-  double* X = d->dU + (size_t)(n & d->dmask) * ns;
+  const int nx = p.nx, ny = p.ny, tilesx = (nx + 63) >> 6;
+  const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
+  const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
+  if (x >= nx || y0 >= ny) return;
+  const unsigned ns = (unsigned)nx * (unsigned)ny;
+  const double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
+  const double* __restrict__ prev = n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr;
+  double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
+  float* __restrict__ r = d->r;
   if (k == 0) {
-    X[i] = 0.0;
-  } else {
-    const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
-    const Nb u = gather<0>(p, d->U + lev, bd, x, y);
+    for (int y = y0; y < y1; ++y) {
+      const unsigned i = (unsigned)y * nx + x;
+      X[i] = 0.0;
+      r[(size_t)y * d->ld + x] = (float)(R[i] + (prev ? prev[i] : 0.0));
+    }
+    return;
+  }
+  const double* __restrict__ Un = d->U + (size_t)n * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+  double uS = node_value(p, Un, bd, x, y0 - 1), uP = Un[(unsigned)y0 * nx + x];
+  double xS = y0 > 0 ? X[(unsigned)(y0 - 1) * nx + x] : 0.0, xP = X[(unsigned)y0 * nx + x];
+  for (int y = y0; y < y1; ++y) {
+    const unsigned i = (unsigned)y * nx + x;
+    const double uN = y + 1 < ny ? Un[i + nx] : node_value(p, Un, bd, x, y + 1);
+    const double xN = y + 1 < ny ? X[i + nx] : 0.0;
+    Nb u;
+    u.P = uP;
+    u.S = uS;
+    u.N = uN;
+    u.W = x > 0 ? Un[i - 1] : node_value(p, Un, bd, x - 1, y);
+    u.E = x + 1 < nx ? Un[i + 1] : node_value(p, Un, bd, x + 1, y);
     Row5 a;
     (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // these solves are for heat only (no convection)
-    double ax = a.C * X[i];
+    double ax = a.C * xP;
     if (x > 0) ax += a.W * X[i - 1];
-    if (x < p.nx - 1) ax += a.E * X[i + 1];
-    if (y > 0) ax += a.S * X[i - p.nx];
-    if (y < p.ny - 1) ax += a.N * X[i + p.nx];
-    b -= ax;
+    if (x < nx - 1) ax += a.E * X[i + 1];
+    if (y > 0) ax += a.S * xS;
+    if (y < ny - 1) ax += a.N * xN;
+    r[(size_t)y * d->ld + x] = (float)(R[i] + (prev ? prev[i] : 0.0) - ax);
+    uS = uP;
+    uP = uN;
+    xS = xP;
+    xP = xN;
   }
-  d->r[(size_t)y * d->ld + x] = (float)b;
 }
 
-// d = c0 d + c1 z, x += d
+// d = c0 d + c1 z, x += d (tiles as k_pc_resid)
 __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                     int m, int k) {
   const int2 it = items[blockIdx.x];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
-  const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
-  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
-  if (i >= ns) return;
+  const int nx = d->p.nx, ny = d->p.ny, tilesx = (nx + 63) >> 6;
+  const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
+  const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
+  if (x >= nx) return;
+  const unsigned ns = (unsigned)nx * (unsigned)ny;
   const float2 c = d->c[(size_t)n * kMaxCheb + k];
-  const float zi = d->z[(size_t)(i / (unsigned)d->p.nx) * d->ld + (i % (unsigned)d->p.nx)];
-  const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)zi;
-  d->d[i] = dir;
-  d->dU[(size_t)(n & d->dmask) * ns + i] += dir;
+  double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
+  for (int y = y0; y < y1; ++y) {
+    const unsigned i = (unsigned)y * nx + x;
+    const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)d->z[(size_t)y * d->ld + x];
+    d->d[i] = dir;
+    X[i] += dir;
+  }
 }
 
 // V-cycle launches of iteration k of level n. Items (lane, grid l, tile x, tile y) of the
@@ -575,15 +606,15 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_up(const MgDesc* __restrict__
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
-  __shared__ float X[kMgUS * kMgUS], F[kMgUS * kMgUS], X1[kMgUS * kMgUS], E[kMgUE * kMgUE];
+  __shared__ float X[kMgUS * kMgUS], X1[kMgUS * kMgUS], E[kMgUE * kMgUE];
   const MgDesc& mg_ = mg[it.x];
   const int l = it.y;
   if (l == 0) {
-    mg_up_tile(mg_, 0, it.z, it.w, X, F, X1, E, ChebStep{d, n, k, mg_.n[0]});
+    mg_up_tile(mg_, 0, it.z, it.w, X, X1, E, ChebStep{d, n, k, mg_.n[0]});
   } else {
     float* e = mg_.e[l];
     const int nl = mg_.n[l];
-    mg_up_tile(mg_, l, it.z, it.w, X, F, X1, E, [=](int i, int j, float v) { e[(size_t)j * nl + i] = v; });
+    mg_up_tile(mg_, l, it.z, it.w, X, X1, E, [=](int i, int j, float v) { e[(size_t)j * nl + i] = v; });
   }
 }
 

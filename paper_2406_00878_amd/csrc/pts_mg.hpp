@@ -196,28 +196,42 @@ __device__ void mg_down_tile(const MgDesc& d, int l, int tx, int ty, float* F, f
 // a two-node halo (e_{l+1}: x_G from the LDS part, else the corrected iterate of grid l+1),
 // then two damped Jacobi sweeps on M_l x = f_l; emit(i, j, x) receives the tile's values (the
 // caller stores them in e_l, never in x_l, which neighbouring tiles still read).
+// Thread (lx, ly) of the 32 x 16 work-group owns the window points (lx + 32 a, ly + 16 b) in
+// every phase, so its f values stay in registers; its x_l and f_l loads are issued before the
+// coarse window is staged.
+constexpr int kMgUA = (kMgUS + 31) / 32, kMgUB = (kMgUS + 15) / 16;  // window points per thread
+static_assert(kMgThreads == 512, "k_mg_up maps 32 x 16 threads onto its window");
 template <typename Emit>
-__device__ void mg_up_tile(const MgDesc& d, int l, int tx, int ty, float* X, float* Fs, float* X1, float* E,
-                           Emit emit) {
+__device__ void mg_up_tile(const MgDesc& d, int l, int tx, int ty, float* X, float* X1, float* E, Emit emit) {
   const int nf = d.n[l], nc = d.n[l + 1];
   const float a = d.a[l], D = 1.f + 4.f * a, wD = kMgOmega / D;
   const int* __restrict__ tk = d.tk[l];
   const float* __restrict__ tw = d.tw[l];
   const int i0 = tx * kMgTF, i1 = min(i0 + kMgTF, nf), j0 = ty * kMgTF, j1 = min(j0 + kMgTF, nf);
   const int ox = i0 - 2, oy = j0 - 2, wx = i1 - i0 + 4, wy = j1 - j0 + 4;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  const float* __restrict__ xf = d.x[l];
+  const float* __restrict__ f = d.f[l];
+  float xv[kMgUB][kMgUA], fv[kMgUB][kMgUA];
+#pragma unroll
+  for (int b = 0; b < kMgUB; ++b)
+#pragma unroll
+    for (int q = 0; q < kMgUA; ++q) {
+      const int ii = lx + 32 * q, jj = ly + 16 * b, gi = ox + ii, gj = oy + jj;
+      const bool in = ii < wx && jj < wy && gi >= 0 && gi < nf && gj >= 0 && gj < nf;
+      xv[b][q] = in ? xf[(size_t)gj * nf + gi] : 0.f;
+      fv[b][q] = in ? f[(size_t)gj * nf + gi] : 0.f;
+    }
   // coarse window covering the interpolation of the region: indices kxa..kxb+1
   const int kxa = tk[max(ox, 0)], kya = tk[max(oy, 0)];
   const int kxb = tk[min(ox + wx - 1, nf - 1)], kyb = tk[min(oy + wy - 1, nf - 1)];
   const int ex = kxb + 2 - kxa, ey = kyb + 2 - kya;
   const float* __restrict__ xc = l + 1 == d.G ? d.x[l + 1] : d.e[l + 1];
-  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5, sy = blockDim.x >> 5;
-  for (int ej = ly; ej < ey; ej += sy)
+  for (int ej = ly; ej < ey; ej += 16)
     for (int ei = lx; ei < ex; ei += 32) {
       const int kx = kxa + ei, ky = kya + ej;
       E[ej * kMgUE + ei] = (kx >= 0 && kx < nc && ky >= 0 && ky < nc) ? xc[(size_t)ky * nc + kx] : 0.f;
     }
-  const float* __restrict__ xf = d.x[l];
-  const float* __restrict__ f = d.f[l];
   // prolongation tables of the region's columns and rows, staged in LDS
   __shared__ int pk[2][kMgUS];
   __shared__ float pw[2][kMgUS];
@@ -229,34 +243,42 @@ __device__ void mg_up_tile(const MgDesc& d, int l, int tx, int ty, float* X, flo
     pw[isx ? 0 : 1][q] = tw[gc];
   }
   __syncthreads();
-  for (int jj = ly; jj < wy; jj += sy)
-    for (int ii = lx; ii < wx; ii += 32) {
-    const int gi = ox + ii, gj = oy + jj;
-    float v = 0.f, fv = 0.f;
-    if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
-      const float wx_ = pw[0][ii], wy_ = pw[1][jj];
-      const float* e = E + pk[1][jj] * kMgUE + pk[0][ii];
-      const float pe = (1.f - wy_) * ((1.f - wx_) * e[0] + wx_ * e[1]) + wy_ * ((1.f - wx_) * e[kMgUE] + wx_ * e[kMgUE + 1]);
-      v = xf[(size_t)gj * nf + gi] + pe;
-      fv = f[(size_t)gj * nf + gi];
-    }
-    X[jj * kMgUS + ii] = v;
-    Fs[jj * kMgUS + ii] = fv;
+#pragma unroll
+  for (int b = 0; b < kMgUB; ++b)
+#pragma unroll
+    for (int q = 0; q < kMgUA; ++q) {
+      const int ii = lx + 32 * q, jj = ly + 16 * b, gi = ox + ii, gj = oy + jj;
+      if (ii >= wx || jj >= wy) continue;
+      float v = 0.f;
+      if (gi >= 0 && gi < nf && gj >= 0 && gj < nf) {
+        const float wx_ = pw[0][ii], wy_ = pw[1][jj];
+        const float* e = E + pk[1][jj] * kMgUE + pk[0][ii];
+        const float pe = (1.f - wy_) * ((1.f - wx_) * e[0] + wx_ * e[1]) + wy_ * ((1.f - wx_) * e[kMgUE] + wx_ * e[kMgUE + 1]);
+        v = xv[b][q] + pe;
+      }
+      X[jj * kMgUS + ii] = v;
     }
   __syncthreads();
-  for (int jj = 1 + ly; jj < wy - 1; jj += sy)
-    for (int ii = 1 + lx; ii < wx - 1; ii += 32) {
-      const int gi = ox + ii, gj = oy + jj;
+#pragma unroll
+  for (int b = 0; b < kMgUB; ++b)
+#pragma unroll
+    for (int q = 0; q < kMgUA; ++q) {
+      const int ii = lx + 32 * q, jj = ly + 16 * b, gi = ox + ii, gj = oy + jj;
+      if (ii < 1 || ii >= wx - 1 || jj < 1 || jj >= wy - 1) continue;
       const float* c = X + jj * kMgUS + ii;
       const float mx = D * c[0] - a * ((c[-1] + c[1]) + (c[-kMgUS] + c[kMgUS]));
-      X1[jj * kMgUS + ii] = (gi >= 0 && gi < nf && gj >= 0 && gj < nf) ? c[0] + wD * (Fs[jj * kMgUS + ii] - mx) : 0.f;
+      X1[jj * kMgUS + ii] = (gi >= 0 && gi < nf && gj >= 0 && gj < nf) ? c[0] + wD * (fv[b][q] - mx) : 0.f;
     }
   __syncthreads();
-  for (int jj = 2 + ly; jj < wy - 2; jj += sy)
-    for (int ii = 2 + lx; ii < wx - 2; ii += 32) {
+#pragma unroll
+  for (int b = 0; b < kMgUB; ++b)
+#pragma unroll
+    for (int q = 0; q < kMgUA; ++q) {
+      const int ii = lx + 32 * q, jj = ly + 16 * b;
+      if (ii < 2 || ii >= wx - 2 || jj < 2 || jj >= wy - 2) continue;
       const float* c = X1 + jj * kMgUS + ii;
       const float mx = D * c[0] - a * ((c[-1] + c[1]) + (c[-kMgUS] + c[kMgUS]));
-      emit(ox + ii, oy + jj, c[0] + wD * (Fs[jj * kMgUS + ii] - mx));
+      emit(ox + ii, oy + jj, c[0] + wD * (fv[b][q] - mx));
     }
 }
 
