@@ -1753,6 +1753,9 @@ size_t batch_header_bytes(const pts_problem* probs, int nprob) {
 struct HostStage {
   char* h = nullptr;
   size_t n = 0;
+  ~HostStage() {
+    if (h) (void)hipHostFree(h);
+  }
 };
 thread_local HostStage g_stage;
 int host_stage(size_t bytes, char** out) {
@@ -1764,6 +1767,20 @@ int host_stage(size_t bytes, char** out) {
     g_stage.n = bytes;
   }
   *out = g_stage.h;
+  return PTS_OK;
+}
+
+// Pinned host buffer for the iteration counts the pipelined lanes plan (read every diagonal).
+thread_local HostStage g_stage_k;
+int host_stage_k(size_t bytes, int** out) {
+  if (g_stage_k.n < bytes) {
+    if (g_stage_k.h) HIPCHK(hipHostFree(g_stage_k.h));
+    g_stage_k.h = nullptr;
+    g_stage_k.n = 0;
+    HIPCHK(hipHostMalloc((void**)&g_stage_k.h, bytes, hipHostMallocDefault));
+    g_stage_k.n = bytes;
+  }
+  *out = (int*)g_stage_k.h;
   return PTS_OK;
 }
 
@@ -2123,15 +2140,16 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       std::stable_sort(all.begin(), all.end(), [&](int a, int b) { return key(a) > key(b); });
       for (int ln : all)
         if (ln % kLanes < S) solving.push_back(ln);
-      // iterations launched per diagonal: the plan of max |u| 1.25 times the largest level
-      // maximum of the iterate the pass starts from (each lane plans from its own level's
-      // maximum and stops there if that needs fewer)
+      // each lane plans its level's iterations from that level's max |u| (k_pipe_cheb); the
+      // host reads the plans back and launches the most any lane needs. A lane's plan is
+      // capped at the plan for twice the largest level maximum of the iterate the pass starts
+      // from (the heat iterates do not grow: the cap only bounds a run-away iterate's work).
       int kcap = 1;
       for (int i : order) {
         double um = 0.0;
         for (int n = 0; n < probs[i].nt; ++n) um = std::max(um, h_lm[ofs_nt[i] + n]);
         float2 c[kMaxCheb];
-        kcap = std::max(kcap, mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, 1.25 * um, lin_tol, c));
+        kcap = std::max(kcap, mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, 2.0 * um, lin_tol, c));
       }
       for (int i = 0; i < nprob; ++i)
         for (int ln = 0; ln < kLanes; ++ln) {
@@ -2167,8 +2185,10 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       hipLaunchKernelGGL(k_zero, dim3((unsigned)((DL.stat_words + 255) / 256)), dim3(256), 0, s, stat,
                          (int)DL.stat_words);
       ++launches;
-      // profiling: the iteration counts the lanes planned, read back per diagonal
-      std::vector<int> kq(solving.size(), 0);
+      // the iteration counts the lanes planned, read back per diagonal
+      int* kq = nullptr;
+      if ((rc = host_stage_k(solving.size() * sizeof(int), &kq))) return rc;
+      int kmax_all = 0;
       int* d_kq = (int*)(mg_base + DL.items_k);
       auto lane_level = [&](int ln, int D) {
         const int n = D - ln % kLanes;
@@ -2200,11 +2220,12 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         hipLaunchKernelGGL(k_pipe_cheb, dim3((unsigned)((ks + 63) / 64)), dim3(64), 0, s, dd, il, (int)ks, D, d_kq);
         pe(0.0);
         ++launches;
-        if (prof) {
-          HIPCHK(hipMemcpyAsync(kq.data(), d_kq, ks * sizeof(int), hipMemcpyDeviceToHost, s));
-          HIPCHK(hipStreamSynchronize(s));
-        }
-        for (int kk = 0; kk < kcap; ++kk)
+        HIPCHK(hipMemcpyAsync(kq, d_kq, ks * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int kn = 0;
+        for (size_t q = 0; q < ks; ++q) kn = std::max(kn, kq[q]);
+        kmax_all = std::max(kmax_all, kn);
+        for (int kk = 0; kk < kn; ++kk)
           vcycle(D, kk, ks, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (size_t q = 0; q < ks; ++q)
@@ -2244,7 +2265,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         h_sc[4 * i + 2] = std::nan("");
         if (stats) {
           stats[i].schedule = PTS_SCHED_PIPELINE;
-          stats[i].sweeps = kcap;
+          stats[i].sweeps = kmax_all;
           stats[i].refine = 0;
           for (int j = it + 1; j < it + S && j < PTS_MAX_HIST; ++j) {
             stats[i].res_inf[j] = std::nan("");
