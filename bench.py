@@ -50,16 +50,35 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
                     "// ------------------------------------------------------------ batched wavefront")]
 
 
-def kernel_sha256():
+# HBM bytes per k_mg_up launch of the heat batch (pipelined Newton stages), the mean over the
+# dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
+# fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
+MG_TRAFFIC = {"kernel_sha256": None, "fetch_bytes": None, "write_bytes": None}
+MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
+MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
+               ("// V-cycle launches of iteration k of level n.", "// One work-group per lane: the V-cycle's")]
+
+
+def kernel_sha256(headers=(KERNEL_HEADER,), sections=KERNEL_SECTIONS):
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, KERNEL_HEADER), "rb") as fh:
-        h.update(fh.read())
+    for name in headers:
+        with open(os.path.join(ROOT, name), "rb") as fh:
+            h.update(fh.read())
     src = open(os.path.join(ROOT, KERNEL_FILE)).read()
-    for a, b in KERNEL_SECTIONS:
+    for a, b in sections:
         i = src.index(a)
         h.update(src[i:src.index(b, i)].encode())
     return h.hexdigest()
+
+
+def mg_traffic():
+    """Counter-measured HBM bytes per k_mg_up launch of the heat batch, or None when the kernel
+    sources differ from the ones the counters were taken with."""
+    if MG_TRAFFIC["kernel_sha256"] != kernel_sha256(MG_HEADERS, MG_SECTIONS):
+        return None
+    return MG_TRAFFIC["fetch_bytes"] + MG_TRAFFIC["write_bytes"]
 
 
 def measured_traffic(plan):
@@ -540,7 +559,8 @@ def bench_heatbatch(args, extras=None):
                    "newton_steps_min_max": [min(its), max(its)],
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
         "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": mg_traffic() if names[j] == "k_mg_up" and pipelined else None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl},
         "kernel_split": split,
     }

@@ -2172,11 +2172,11 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       std::vector<size_t> ce, ce0, od, ou;
       std::vector<std::vector<size_t>> cd, cu;
       if ((rc = build_items(solving, ce, ce0, cd, cu, od, ou))) return rc;
-      // node chunks of every lane (the update and residual launches)
+      // node tiles of every lane (the update and residual launches)
       std::vector<size_t> ca(all.size() + 1, 0);
       size_t na = 0;
       for (size_t q = 0; q < all.size(); ++q) {
-        const int N = probs[all[q] / kLanes].nx, ch = (N * N + 255) / 256;
+        const int N = probs[all[q] / kLanes].nx, ch = pc_tiles(N, N);
         for (int c = 0; c < ch; ++c) h_ia[na++] = make_int2(all[q], c);
         ca[q + 1] = na;
       }

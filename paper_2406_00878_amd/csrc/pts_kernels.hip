@@ -491,12 +491,12 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
   if (threadIdx.x == 0) out[blockIdx.x] = __double_as_longlong(nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
 }
 
-// Work items (lane, tile of 64 x kPcTileY nodes), sorted by level count; thread (c, g) of the
+// Work items (lane, tile of 64 x 32 nodes), sorted by level count; thread (c, g) of the
 // 64 x 4 work-group walks kPcRows rows of column c, keeping the column's u and x of the rows
 // above and below in registers. Iteration k of level n: r = b - A x with b = r^n + du^{n-1}
 // (Eq. (7)) and x = du^n (x = 0 at k = 0, written here). m: the level (bulk) or the diagonal
 // (pipelined); the lane's level is m - stage.
-constexpr int kPcRows = 4, kPcTileY = 4 * kPcRows;
+constexpr int kPcRows = 8, kPcTileY = 4 * kPcRows;
 __host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                    int m, int k) {
@@ -653,17 +653,24 @@ __global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ 
   const PcDesc* d = ds + it.x;
   const int n = D - d->stage;
   if (!d->active || d->stage == 0 || n < 0 || n >= d->p.nt) return;
-  const unsigned ns = (unsigned)d->p.nx * (unsigned)d->p.ny;
-  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
-  if (i >= ns) return;
-  double* u = d->U + (size_t)n * ns + i;
-  const double old = *u;
-  d->park_out[i] = old;
-  *u = old + d->dprev[(size_t)(n & 1) * ns + i];
+  const int nx = d->p.nx, ny = d->p.ny, tilesx = (nx + 63) >> 6;
+  const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
+  const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
+  if (x >= nx) return;
+  const unsigned ns = (unsigned)nx * (unsigned)ny;
+  double* __restrict__ u = d->U + (size_t)n * ns;
+  const double* __restrict__ du = d->dprev + (size_t)(n & 1) * ns;
+  for (int y = y0; y < y1; ++y) {
+    const unsigned i = (unsigned)y * nx + x;
+    const double old = u[i];
+    d->park_out[i] = old;
+    u[i] = old + du[i];
+  }
 }
 
 // r^(s)_n = -(U^(s)_n - U^(s)_{n-1} + tau F(U^(s)_n)) into the lane's level buffer, with
-// max |U^(s)_n|, max |r| and the Gershgorin radius of the level's rows into stat[n].
+// max |U^(s)_n|, max |r| and the Gershgorin radius of the level's rows into stat[n]
+// (tiles as k_pc_resid, the column's u of the rows above and below kept in registers).
 __global__ __launch_bounds__(256) void k_pipe_residual(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                         int D) {
   const int2 it = items[blockIdx.x];
@@ -671,21 +678,34 @@ __global__ __launch_bounds__(256) void k_pipe_residual(const PcDesc* __restrict_
   const int n = D - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt) return;
   const KProb p = at_level(d->p, n);
-  const unsigned ns = (unsigned)p.nx * (unsigned)p.ny;
-  const unsigned i = (unsigned)it.y * 256u + threadIdx.x;
+  const int nx = p.nx, ny = p.ny, tilesx = (nx + 63) >> 6;
+  const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
+  const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
+  const unsigned ns = (unsigned)nx * (unsigned)ny;
   double uabs = 0.0, rabs = 0.0, rho = 0.0;
-  if (i < ns) {
-    const int x = (int)(i % (unsigned)p.nx), y = (int)(i / (unsigned)p.nx);
+  if (x < nx && y0 < ny) {
+    const double* __restrict__ Un = d->U + (size_t)n * ns;
+    const double* __restrict__ up = n == 0 ? d->u0 : (d->park_in ? d->park_in : d->U + (size_t)(n - 1) * ns);
     const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
-    const Nb u = gather<0>(p, d->U + (size_t)n * ns, bd, x, y);
-    const double* up = n == 0 ? d->u0 : (d->park_in ? d->park_in : d->U + (size_t)(n - 1) * ns);
-    Row5 a;
-    const double F = eval_point<0, kFormNoConv>(p, u, x, y, a);
-    const double r = -(u.P - up[i] + p.dt * F);
-    if (!d->last) d->R[i] = r;
-    uabs = fabs(u.P);
-    rabs = fabs(r);
-    rho = gersh(a);
+    double uS = node_value(p, Un, bd, x, y0 - 1), uP = Un[(unsigned)y0 * nx + x];
+    for (int y = y0; y < y1; ++y) {
+      const unsigned i = (unsigned)y * nx + x;
+      Nb u;
+      u.P = uP;
+      u.S = uS;
+      u.N = y + 1 < ny ? Un[i + nx] : node_value(p, Un, bd, x, y + 1);
+      u.W = x > 0 ? Un[i - 1] : node_value(p, Un, bd, x - 1, y);
+      u.E = x + 1 < nx ? Un[i + 1] : node_value(p, Un, bd, x + 1, y);
+      Row5 a;
+      const double F = eval_point<0, kFormNoConv>(p, u, x, y, a);
+      const double r = -(u.P - up[i] + p.dt * F);
+      if (!d->last) d->R[i] = r;
+      uabs = nanmax(uabs, fabs(u.P));
+      rabs = nanmax(rabs, fabs(r));
+      rho = nanmax(rho, gersh(a));
+      uS = uP;
+      uP = u.N;
+    }
   }
   __shared__ double red[3][4];
   uabs = wave_max(uabs);
