@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken with: sha256 of the device header and of
 # the parts of the kernel file the wavefront kernel is built from (the register-resident
 # region solve and the wavefront section).
-TRAFFIC = {"kernel_sha256": "e5ffdafd5e7b19adb4d0ad9a096edbd3f33598cf2b1fcf73b1ecf82550caac69",
-           "plans": {(8, 1, 6): {"fetch_bytes": 17717472, "write_bytes": 3099024},
-                     (7, 1, 7): {"fetch_bytes": 19729470, "write_bytes": 3769821}}}
+TRAFFIC = {"kernel_sha256": "351d094019296215bf3a04caf34ca0184ac7d06eff4d377b0bc80873a3eb4938",
+           "plans": {(8, 1, 6): {"fetch_bytes": 17727497, "write_bytes": 3099034},
+                     (7, 1, 7): {"fetch_bytes": 19737173, "write_bytes": 3769856}}}
 KERNEL_HEADER = "paper_2406_00878_amd/csrc/pts_device.hpp"
 KERNEL_FILE = "paper_2406_00878_amd/csrc/pts_kernels.hip"
 KERNEL_SECTIONS = [("// -------------------------------------------------------------- level solve",
@@ -54,7 +54,8 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
 # dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
 # fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
-MG_TRAFFIC = {"kernel_sha256": None, "fetch_bytes": None, "write_bytes": None}
+MG_TRAFFIC = {"kernel_sha256": "cd3ad00e195dec7c7e98165118b95bca657398e5579f5150194e60681f366d82",
+              "fetch_bytes": 171392972, "write_bytes": 80209408}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
                ("// V-cycle launches of iteration k of level n.", "// One work-group per lane: the V-cycle's")]
