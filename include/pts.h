@@ -295,7 +295,17 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    Chebyshev iteration preconditioned by I + tau mu_a (-Delta_h), applied
    approximately by one geometric multigrid V-cycle in float32 (residuals and
    updates in float64; inexact, residual reduced 1e3-fold per level solve unless
-   opts->lin_tol says otherwise). Instances with different
+   opts->lin_tol says otherwise). Unless opts->schedule is PTS_SCHED_BULK (one
+   Newton step at a time), such a batch runs opts->stages Newton steps (default
+   and at most 7) per pass over the diagonals D = n + s: Newton stage s works on
+   level n at diagonal D, every stage of every instance with its own level
+   solver ("lane", in the workspace header), the launches of a diagonal
+   carrying all lanes that have a level there; after each pass the residual of
+   the result decides which instances run another pass (stats: schedule
+   PTS_SCHED_PIPELINE, iterations a multiple of the stage count, res_inf and
+   rho_max NaN for the steps inside a pass, upd_rms NaN). This path
+   synchronises the stream once per diagonal (it reads back the iteration
+   counts the lanes planned). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for
    instances that are not one problem) or opts->window > 1 are solved one after
    another with pts_solve.

@@ -2132,7 +2132,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       // (i, s), s = 0..S, ordered by nt_i + s, longest first; lane (i, s) has a level at D while
       // D < nt_i + s, so the lanes of a diagonal are a prefix of the order (lanes with D < s
       // return at once)
-      const int S = nstages;
+      const int S = std::min(nstages, std::max(1, max_iter - it));  // no more steps than max_iter allows
       std::vector<int> all, solving;
       for (int i : order)
         for (int sg = 0; sg <= S; ++sg) all.push_back(i * kLanes + sg);
@@ -2270,6 +2270,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           for (int j = it + 1; j < it + S && j < PTS_MAX_HIST; ++j) {
             stats[i].res_inf[j] = std::nan("");
             stats[i].rho_max[j] = std::nan("");
+            stats[i].upd_rms[j] = std::nan("");
           }
         }
       }

@@ -581,9 +581,11 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
-  __shared__ float F[kMgDS * kMgDS], X[kMgDS * kMgDS], T[kMgDS * kMgTC];
+  // the x-restriction (T, kMgDS x kMgTC) reuses X, which is dead once the residual is formed
+  static_assert(kMgTC <= kMgDS, "T fits in X");
+  __shared__ float F[kMgDS * kMgDS], X[kMgDS * kMgDS];
   __shared__ MgDownAux aux;
-  mg_down_tile(mg[it.x], it.y, it.z, it.w, F, X, T, aux);
+  mg_down_tile(mg[it.x], it.y, it.z, it.w, F, X, X, aux);
 }
 
 // The Chebyshev step of iteration k at node (i, j), given z = B r there: d = c0 d + c1 z,

@@ -31,11 +31,11 @@ constexpr int kMgCoarsest = 8;      // hierarchy ends at N <= 8
 constexpr int kMgCoarseSweeps = 8;  // Jacobi sweeps on the coarsest grid
 constexpr float kMgOmega = 0.8f;
 constexpr double kMgLow = 0.75;     // lower end of spec(B M)
-constexpr int kMgTC = 32;           // k_mg_down: coarse tile edge
-constexpr int kMgTF = 64;           // k_mg_up: fine tile edge
-constexpr int kMgDS = 72;           // k_mg_down: LDS row stride (fine region <= 71 wide)
-constexpr int kMgUS = 68;           // k_mg_up: LDS row stride (fine region <= 68 wide)
-constexpr int kMgUE = 40;           // k_mg_up: LDS row stride of the coarse correction
+constexpr int kMgTC = 28;           // k_mg_down: coarse tile edge
+constexpr int kMgTF = 60;           // k_mg_up: fine tile edge
+constexpr int kMgDS = 64;           // k_mg_down: LDS row stride (fine region <= 62 wide)
+constexpr int kMgUS = 64;           // k_mg_up: LDS row stride (fine region <= 64 wide)
+constexpr int kMgUE = 36;           // k_mg_up: LDS row stride of the coarse correction
 constexpr int kMgLdsWords = 5504;   // k_mg_lds: floats per LDS array (64^2 + 32^2 + ...)
 constexpr int kMgThreads = 512;     // k_mg_down, k_mg_up: threads per work-group
 
@@ -131,7 +131,7 @@ __device__ void mg_down_tile(const MgDesc& d, int l, int tx, int ty, float* F, f
     }
   // the tile's transfer tables, staged in LDS
   if (threadIdx.x < 2 * kMgTC) {
-    const int kk = threadIdx.x & (kMgTC - 1);
+    const int kk = threadIdx.x % kMgTC;
     const bool isx = threadIdx.x < kMgTC;
     const int kc = (isx ? k0x : k0y) + kk, o = isx ? ox : oy;
     if (kk < (isx ? tcx : tcy)) {

@@ -36,7 +36,9 @@ def test_uneven_heat_batch_matches_oracle(precision, tol, bar):
     sts = P.solve_batched(probs, Us, u0s, tol=tol, max_iter=40, precision=precision)
     for p, U, st in zip(probs, Us, sts):
         assert st["converged"], st
-        assert st["schedule"] == 1  # bulk, shared launches
+        # the 100^2 instance's blocks are stiff (radius 0.976): multigrid level solves for the
+        # batch, Newton stages pipelined in shared launches
+        assert st["schedule"] == P.PTS_SCHED_PIPELINE, st
         Uo, _ = sequential.solve_sequential(p)
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         assert err <= bar, (p.name, err)
