@@ -1728,7 +1728,7 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
         L.f[q].push_back(take(nn * 4));
         L.e[q].push_back(l >= 1 && l < h.G ? take(nn * 4) : 0);
       }
-      L.d.push_back(take(N * N * 8));
+      L.d.push_back(take(N * N * 4));
       L.K.push_back(take(nt * 4));
       L.coef.push_back(take(nt * kMaxCheb * sizeof(float2)));
       L.R.push_back(take(N * N * 8));
@@ -1933,7 +1933,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     d.dU = in[i].dU;
     d.r = (float*)(mg_base + DL.f[q][0]);
     d.z = (float*)(mg_base + DL.x[q][0]);
-    d.d = (double*)(mg_base + DL.d[q]);
+    d.d = (float*)(mg_base + DL.d[q]);
     d.K = (int*)(mg_base + DL.K[q]);
     d.c = (float2*)(mg_base + DL.coef[q]);
     d.active = active[i];
@@ -2022,23 +2022,25 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     const int4* iu = (const int4*)(mg_base + DL.items_u);
     const int* il = (const int*)(mg_base + DL.items_l);
     // algorithmic bytes per node of the grid a launch works on (profiling), for lane q (index
-    // i kLanes + s) of instance i at Chebyshev iteration kk: k_pc_resid reads r^n, du^{n-1} and
-    // (kk > 0) u^n, x (8 B each), writes r (4) and (kk = 0) x; k_mg_down reads f_l, writes x_l
+    // i kLanes + s) of instance i at Chebyshev iteration kk: k_pc_resid at kk = 0 reads r^n and
+    // du^{n-1}, writes b = r^n + du^{n-1} over r^n, x = 0 and r (8 + 8 + 8 + 8 + 4), at kk > 0
+    // reads b, u^n, x (8 each) and writes r (4); k_mg_down reads f_l, writes x_l
     // and f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l,
     // x_{l+1} and writes e_l, on the finest grid instead the Chebyshev step's reads and writes
-    // of d and du^n (8 each); k_pc_update reads z (4), d, du^n and writes d, du^n (8 each)
+    // of d (4 each) and du^n (8 each); k_pc_update reads z, d (4 each), du^n (8) and writes d
+    // (4), du^n (8)
     auto kb = [&](int kind, int i, int kk, int g) {
       const MgDesc& m = h_mg[(size_t)i * kLanes];
       const double N2 = (double)probs[i].nx * probs[i].nx;
       const int l = g - (gmax - m.G);
       switch (kind) {
-        case 0: return N2 * (kk == 0 ? 28.0 : 36.0);
+        case 0: return N2 * (kk == 0 ? 36.0 : 28.0);
         case 1: return l >= 0 ? (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0 : 0.0;
         case 2: return (double)m.n[m.G] * m.n[m.G] * 8.0;
         case 3:
-          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 40.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0
+          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 32.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0
                         : 0.0;
-        default: return N2 * (kk == 0 ? 28.0 : 36.0);
+        default: return N2 * (kk == 0 ? 24.0 : 28.0);
       }
     };
     // the V-cycle launches of Chebyshev iteration kk for the first ks lanes of a lane order

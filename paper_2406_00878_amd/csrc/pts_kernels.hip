@@ -431,7 +431,7 @@ struct PcDesc {
   double* dU;         // update: level n at dU + (n & dmask) N^2; the level solve iterates in it
   float* r;           // [N][ld] level residual b - A x (float32)
   float* z;           // [N][ld] B r
-  double* d;          // [N][N] Chebyshev direction
+  float* d;           // [N][N] Chebyshev direction (float32: the inner solve's precision)
   int* K;             // [nt] iterations of level n (the interval follows the level's max |u|)
   float2* c;          // [nt][kMaxCheb]: d_k = c.x d_{k-1} + c.y z_k (c.x = 0 at k = 0)
   int active;
@@ -494,8 +494,9 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
 // Work items (lane, tile of 64 x 32 nodes), sorted by level count; thread (c, g) of the
 // 64 x 4 work-group walks kPcRows rows of column c, keeping the column's u and x of the rows
 // above and below in registers. Iteration k of level n: r = b - A x with b = r^n + du^{n-1}
-// (Eq. (7)) and x = du^n (x = 0 at k = 0, written here). m: the level (bulk) or the diagonal
-// (pipelined); the lane's level is m - stage.
+// (Eq. (7)) and x = du^n (x = 0 at k = 0, written here; b replaces r^n then, so that later
+// iterations read one array for it). m: the level (bulk) or the diagonal (pipelined); the
+// lane's level is m - stage.
 constexpr int kPcRows = 8, kPcTileY = 4 * kPcRows;
 __host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
@@ -510,15 +511,17 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
   const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
   if (x >= nx || y0 >= ny) return;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
-  const double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
+  double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
   const double* __restrict__ prev = n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr;
   double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
   float* __restrict__ r = d->r;
-  if (k == 0) {
+  if (k == 0) {  // b = r^n + du^{n-1} is kept in place of r^n for the later iterations
     for (int y = y0; y < y1; ++y) {
       const unsigned i = (unsigned)y * nx + x;
+      const double b = R[i] + (prev ? prev[i] : 0.0);
+      R[i] = b;
       X[i] = 0.0;
-      r[(size_t)y * d->ld + x] = (float)(R[i] + (prev ? prev[i] : 0.0));
+      r[(size_t)y * d->ld + x] = (float)b;
     }
     return;
   }
@@ -543,7 +546,7 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
     if (x < nx - 1) ax += a.E * X[i + 1];
     if (y > 0) ax += a.S * xS;
     if (y < ny - 1) ax += a.N * xN;
-    r[(size_t)y * d->ld + x] = (float)(R[i] + (prev ? prev[i] : 0.0) - ax);
+    r[(size_t)y * d->ld + x] = (float)(R[i] - ax);
     uS = uP;
     uP = uN;
     xS = xP;
@@ -567,9 +570,9 @@ __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds
   double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
   for (int y = y0; y < y1; ++y) {
     const unsigned i = (unsigned)y * nx + x;
-    const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[i]) + (double)c.y * (double)d->z[(size_t)y * d->ld + x];
+    const float dir = (k == 0 ? 0.f : c.x * d->d[i]) + c.y * d->z[(size_t)y * d->ld + x];
     d->d[i] = dir;
-    X[i] += dir;
+    X[i] += (double)dir;
   }
 }
 
@@ -588,17 +591,17 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict
   mg_down_tile(mg[it.x], it.y, it.z, it.w, F, X, X, aux);
 }
 
-// The Chebyshev step of iteration k at node (i, j), given z = B r there: d = c0 d + c1 z,
-// du^n += d (FP64). Applied by the V-cycle's last kernel on the finest grid.
+// The Chebyshev step of iteration k at node (i, j), given z = B r there: d = c0 d + c1 z in
+// float32, du^n += d in FP64. Applied by the V-cycle's last kernel on the finest grid.
 struct ChebStep {
   const PcDesc* d;
   int n, k, N;
   __device__ void operator()(int i, int j, float z) const {
     const size_t idx = (size_t)j * N + i;
     const float2 c = d->c[(size_t)n * kMaxCheb + k];
-    const double dir = (k == 0 ? 0.0 : (double)c.x * d->d[idx]) + (double)c.y * (double)z;
+    const float dir = (k == 0 ? 0.f : c.x * d->d[idx]) + c.y * z;
     d->d[idx] = dir;
-    d->dU[(size_t)(n & d->dmask) * N * N + idx] += dir;
+    d->dU[(size_t)(n & d->dmask) * N * N + idx] += (double)dir;
   }
 };
 
