@@ -54,10 +54,11 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
 # dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
 # fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
-MG_TRAFFIC = {"kernel_sha256": "cd3ad00e195dec7c7e98165118b95bca657398e5579f5150194e60681f366d82",
-              "fetch_bytes": 171392972, "write_bytes": 80209408}
+MG_TRAFFIC = {"kernel_sha256": "8e11dc586a6eb2562500b67477b8b1b9deb68060477f513fc0c76e038bb6bb09",
+              "fetch_bytes": 159998884, "write_bytes": 63162266}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
+               ("// Chebyshev plan of a multigrid-preconditioned level solve", "// Work items (lane, tile of"),
                ("// V-cycle launches of iteration k of level n.", "// One work-group per lane: the V-cycle's")]
 
 
