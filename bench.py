@@ -54,8 +54,8 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
 # dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
 # fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
-MG_TRAFFIC = {"kernel_sha256": "8e11dc586a6eb2562500b67477b8b1b9deb68060477f513fc0c76e038bb6bb09",
-              "fetch_bytes": 159998884, "write_bytes": 63162266}
+MG_TRAFFIC = {"kernel_sha256": "d890f8a5369f5aba7924cf2178caa4d6cb583311fc65f14a2d3792867f857e4f",
+              "fetch_bytes": 197004864, "write_bytes": 78138470}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
                ("// Chebyshev plan of a multigrid-preconditioned level solve", "// Work items (lane, tile of"),
@@ -518,7 +518,9 @@ def bench_heatbatch(args, extras=None):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     its = [st["iterations"] for st in sts]
-    log(f"{ms:.0f} ms per batch, Newton steps {min(its)}..{max(its)}")
+    need = [st["needed"] for st in sts if st["needed"] is not None]
+    log(f"{ms:.0f} ms per batch, Newton steps {min(its)}..{max(its)}"
+        + (f" (max|R| <= tol first after {min(need)}..{max(need)})" if need else ""))
     # accuracy: every level the CPU baseline solved (the first levels of its instances), against
     # the GPU result of the last timed solve
     errs = []
@@ -559,6 +561,7 @@ def bench_heatbatch(args, extras=None):
                    "solves, FP64 residuals and updates)",
                    "schedule": "pipelined Newton stages" if pipelined else "batched bulk",
                    "newton_steps_min_max": [min(its), max(its)],
+                   "newton_steps_needed_min_max": [min(need), max(need)] if need else None,
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
         "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

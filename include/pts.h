@@ -303,7 +303,8 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    carrying all lanes that have a level there; after each pass the residual of
    the result decides which instances run another pass (stats: schedule
    PTS_SCHED_PIPELINE, iterations a multiple of the stage count, res_inf and
-   rho_max NaN for the steps inside a pass, upd_rms NaN). This path
+   rho_max of the steps inside a pass from the stage residuals the lanes formed,
+   upd_rms NaN). This path
    synchronises the stream once per diagonal (it reads back the iteration
    counts the lanes planned). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for

@@ -2266,13 +2266,21 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         h_sc[4 * i + 1] = val(rho);
         h_sc[4 * i + 2] = std::nan("");
         if (stats) {
+          // lane s formed the residual of U^(s) at every level from U^(s) of the level before:
+          // its maxima are the Newton history inside the pass
           stats[i].schedule = PTS_SCHED_PIPELINE;
           stats[i].sweeps = kmax_all;
           stats[i].refine = 0;
-          for (int j = it + 1; j < it + S && j < PTS_MAX_HIST; ++j) {
-            stats[i].res_inf[j] = std::nan("");
-            stats[i].rho_max[j] = std::nan("");
-            stats[i].upd_rms[j] = std::nan("");
+          for (int sg = 1; sg < S && it + sg < PTS_MAX_HIST; ++sg) {
+            unsigned long long r = 0, g = 0;
+            for (int n = 0; n < nt; ++n) {
+              const unsigned long long* q = st + ((size_t)sg * nt + n) * 3;
+              r = std::max(r, q[1]);
+              g = std::max(g, q[2]);
+            }
+            stats[i].res_inf[it + sg] = val(r);
+            stats[i].rho_max[it + sg] = val(g);
+            stats[i].upd_rms[it + sg] = std::nan("");
           }
         }
       }
