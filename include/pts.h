@@ -30,10 +30,12 @@
  *     finite-or-untouched state, except where stated.
  *   - State the library keeps between calls (all per calling thread, freed at
  *     thread exit): a 4 KiB pinned host buffer for the scalars read back per
- *     Newton step and a pinned staging buffer for batch descriptors (both
+ *     Newton step, a pinned staging buffer for batch descriptors and one for
+ *     the iteration counts the pipelined multigrid lanes plan (all
  *     hipHostMalloc, grown on demand); up to 32 instantiated HIP graphs of
  *     wavefront sequences (keyed by their launch arguments, oldest dropped);
- *     autotuned plans, stage counts and slab lengths per problem signature.
+ *     autotuned plans, stage counts and slab lengths per problem signature,
+ *     and the Newton stages per pipelined pass per batch signature.
  *     pts_autotune additionally allocates one device copy of U for the
  *     duration of the call. Device memory beyond that is the caller's
  *     workspace, except for pts_newton_step_static (see there).
@@ -304,7 +306,9 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    the result decides which instances run another pass (stats: schedule
    PTS_SCHED_PIPELINE, iterations a multiple of the stage count, res_inf and
    rho_max of the steps inside a pass from the stage residuals the lanes formed,
-   upd_rms NaN). This path
+   upd_rms NaN). Without opts->stages, a batch solved again with the same
+   signature (kinds, sizes, coefficients, precision, tol) runs as many stages per
+   pass as its first pass needed last time (a per-thread cache). This path
    synchronises the stream once per diagonal (it reads back the iteration
    counts the lanes planned). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for

@@ -1770,6 +1770,44 @@ int host_stage(size_t bytes, char** out) {
   return PTS_OK;
 }
 
+// Newton stages a pipelined pass of a multigrid batch needed the last time the same batch
+// (instances' kinds, sizes, coefficients, precision) was solved to the same tolerance from
+// its first pass: the next solve runs that many stages per pass.
+struct PassCache {
+  std::vector<std::pair<unsigned long long, int>> v;
+  static unsigned long long key(const pts_problem* probs, int nprob, double tol) {
+    unsigned long long h = 1469598103934665603ull;  // FNV-1a over the fields that fix the work
+    auto mix = [&](const void* p, size_t n) {
+      for (size_t i = 0; i < n; ++i) h = (h ^ ((const unsigned char*)p)[i]) * 1099511628211ull;
+    };
+    mix(&nprob, sizeof nprob);
+    mix(&tol, sizeof tol);
+    for (int i = 0; i < nprob; ++i) {
+      const pts_problem& q = probs[i];
+      const int iv[6] = {q.kind, q.bc, q.nx, q.ny, q.nt, q.precision};
+      const double dv[5] = {q.hx, q.hy, q.dt, q.mu_a, q.mu_b};
+      mix(iv, sizeof iv);
+      mix(dv, sizeof dv);
+    }
+    return h;
+  }
+  int get(unsigned long long k) const {
+    for (auto& e : v)
+      if (e.first == k) return e.second;
+    return 0;
+  }
+  void put(unsigned long long k, int stages) {
+    for (auto& e : v)
+      if (e.first == k) {
+        e.second = stages;
+        return;
+      }
+    if (v.size() > 64) v.clear();
+    v.push_back({k, stages});
+  }
+};
+thread_local PassCache g_pass_cache;
+
 // Pinned host buffer for the iteration counts the pipelined lanes plan (read every diagonal).
 thread_local HostStage g_stage_k;
 int host_stage_k(size_t bytes, int** out) {
@@ -1946,7 +1984,9 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   };
   const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
   const bool pipelined = o == nullptr || o->schedule != PTS_SCHED_BULK;
-  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages : kLanes - 1);
+  const unsigned long long skey = PassCache::key(probs, nprob, tol);
+  const int cached = g_pass_cache.get(skey);
+  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages : (cached > 0 ? cached : kLanes - 1));
   for (int it = 0;; ++it) {
     int nactive = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -2004,6 +2044,9 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       while (k > 0 && probs[order[k - 1]].nt <= n) --k;
       kpref[n] = k;
     }
+    // grids of the tile kernels: a multiple of the 8 XCDs, so that the kernels hand each XCD one
+    // contiguous band of work items (xcd_band); the surplus work-groups return
+    auto grid8 = [](size_t n) { return dim3((unsigned)((n + kXcds - 1) / kXcds * kXcds)); };
     // profiling brackets of the multigrid launches (kinds: pts_stats.kern_* slots)
     auto pb = [&](int kind) { prof_begin(prof, Prof::kKern + kind, s); };
     auto pe = [&](double bytes) {
@@ -2050,13 +2093,14 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
                       const std::vector<std::vector<size_t>>& cd, const std::vector<std::vector<size_t>>& cu,
                       const std::vector<size_t>& od, const std::vector<size_t>& ou, auto&& bytes) {
       pb(0);
-      hipLaunchKernelGGL(k_pc_resid, dim3((unsigned)ce[ks]), dim3(256), 0, s, dd, ie, m, kk);
+      hipLaunchKernelGGL(k_pc_resid, grid8(ce[ks]), dim3(256), 0, s, dd, ie, m, kk, (int)ce[ks]);
       pe(prof ? bytes(0, 0) : 0.0);
       ++launches;
       for (int g = 0; g < gmax; ++g) {
         if (!cd[g][ks]) continue;
         pb(1);
-        hipLaunchKernelGGL(k_mg_down, dim3((unsigned)cd[g][ks]), dim3(kMgThreads), 0, s, dm, dd, id + od[g], m, kk);
+        hipLaunchKernelGGL(k_mg_down, grid8(cd[g][ks]), dim3(kMgThreads), 0, s, dm, dd, id + od[g], m, kk,
+                           (int)cd[g][ks]);
         pe(prof ? bytes(1, g) : 0.0);
         ++launches;
       }
@@ -2067,13 +2111,14 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       for (int g = gmax - 1; g >= 0; --g) {
         if (!cu[g][ks]) continue;
         pb(3);
-        hipLaunchKernelGGL(k_mg_up, dim3((unsigned)cu[g][ks]), dim3(kMgThreads), 0, s, dm, dd, iu + ou[g], m, kk);
+        hipLaunchKernelGGL(k_mg_up, grid8(cu[g][ks]), dim3(kMgThreads), 0, s, dm, dd, iu + ou[g], m, kk,
+                           (int)cu[g][ks]);
         pe(prof ? bytes(3, g) : 0.0);
         ++launches;
       }
       if (ce0[ks]) {
         pb(4);
-        hipLaunchKernelGGL(k_pc_update, dim3((unsigned)ce0[ks]), dim3(256), 0, s, dd, ie0, m, kk);
+        hipLaunchKernelGGL(k_pc_update, grid8(ce0[ks]), dim3(256), 0, s, dd, ie0, m, kk, (int)ce0[ks]);
         pe(prof ? bytes(4, 0) : 0.0);
         ++launches;
       }
@@ -2211,10 +2256,10 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
             if (sg >= 1) b6 += N2 * 32.0;        // reads u^n, du; writes the park and u^n
           }
         pb(6);
-        hipLaunchKernelGGL(k_pipe_update, dim3((unsigned)ca[ka]), dim3(256), 0, s, dd, ia, D);
+        hipLaunchKernelGGL(k_pipe_update, grid8(ca[ka]), dim3(256), 0, s, dd, ia, D, (int)ca[ka]);
         pe(b6);
         pb(5);
-        hipLaunchKernelGGL(k_pipe_residual, dim3((unsigned)ca[ka]), dim3(256), 0, s, dd, ia, D);
+        hipLaunchKernelGGL(k_pipe_residual, grid8(ca[ka]), dim3(256), 0, s, dd, ia, D, (int)ca[ka]);
         pe(b5);
         launches += 2;
         if (ks == 0) continue;
@@ -2245,6 +2290,22 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         std::memcpy(&v, &b, 8);
         return v;
       };
+      // stages the pass needed: per instance the first s whose iterate meets tol at every level
+      int need = 0;
+      bool all_met = true;
+      for (int i : order) {
+        const unsigned long long* st = hst.data() + DL.lstat[i];
+        const int nt = probs[i].nt;
+        int first = -1;
+        for (int sg = 0; sg <= S && first < 0; ++sg) {
+          unsigned long long r = 0;
+          for (int n = 0; n < nt; ++n) r = std::max(r, st[((size_t)sg * nt + n) * 3 + 1]);
+          if (val(r) <= tol) first = sg;
+        }
+        if (first < 0) all_met = false;
+        need = std::max(need, first);
+      }
+      if (it == 0 && all_met && need >= 1 && !(o && o->stages > 0)) g_pass_cache.put(skey, need);
       for (int i : order) {
         const unsigned long long* st = hst.data() + DL.lstat[i];
         const int nt = probs[i].nt;

@@ -501,8 +501,10 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
 constexpr int kPcRows = 8, kPcTileY = 4 * kPcRows;
 __host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                   int m, int k) {
-  const int2 it = items[blockIdx.x];
+                                                   int m, int k, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int2 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
@@ -557,8 +559,10 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
 
 // d = c0 d + c1 z, x += d (tiles as k_pc_resid)
 __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                    int m, int k) {
-  const int2 it = items[blockIdx.x];
+                                                    int m, int k, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int2 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
@@ -580,8 +584,10 @@ __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds
 // V-cycle launches of iteration k of level n. Items (lane, grid l, tile x, tile y) of the
 // lanes that have level n; lanes without level n or iteration k return.
 __global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
-                                                 const int4* __restrict__ items, int m, int k) {
-  const int4 it = items[blockIdx.x];
+                                                 const int4* __restrict__ items, int m, int k, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int4 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
@@ -607,8 +613,10 @@ struct ChebStep {
 };
 
 __global__ __launch_bounds__(kMgThreads) void k_mg_up(const MgDesc* __restrict__ mg, const PcDesc* __restrict__ ds,
-                                               const int4* __restrict__ items, int m, int k) {
-  const int4 it = items[blockIdx.x];
+                                               const int4* __restrict__ items, int m, int k, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int4 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
@@ -654,8 +662,10 @@ __global__ __launch_bounds__(1024) void k_mg_lds(const MgDesc* __restrict__ mg, 
 // read at diagonal D+1 (by lane s at level n+1 and by lane s+1 at level n) and overwritten at
 // D+2.
 __global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                      int D) {
-  const int2 it = items[blockIdx.x];
+                                                      int D, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int2 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = D - d->stage;
   if (!d->active || d->stage == 0 || n < 0 || n >= d->p.nt) return;
@@ -678,8 +688,10 @@ __global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ 
 // max |U^(s)_n|, max |r| and the Gershgorin radius of the level's rows into stat[n]
 // (tiles as k_pc_resid, the column's u of the rows above and below kept in registers).
 __global__ __launch_bounds__(256) void k_pipe_residual(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                        int D) {
-  const int2 it = items[blockIdx.x];
+                                                        int D, int count) {
+  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
+  if (wi >= (unsigned)count) return;
+  const int2 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = D - d->stage;
   if (!d->active || n < 0 || n >= d->p.nt) return;

