@@ -1732,7 +1732,7 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
       L.K.push_back(take(nt * 4));
       L.coef.push_back(take(nt * kMaxCheb * sizeof(float2)));
       L.R.push_back(take(N * N * 8));
-      L.ring.push_back(take(2 * N * N * 8));
+      L.ring.push_back(take(2 * N * N * 4));
       L.park.push_back(take(N * N * 8));
     }
   }
@@ -2065,25 +2065,26 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     const int4* iu = (const int4*)(mg_base + DL.items_u);
     const int* il = (const int*)(mg_base + DL.items_l);
     // algorithmic bytes per node of the grid a launch works on (profiling), for lane q (index
-    // i kLanes + s) of instance i at Chebyshev iteration kk: k_pc_resid at kk = 0 reads r^n and
-    // du^{n-1}, writes b = r^n + du^{n-1} over r^n, x = 0 and r (8 + 8 + 8 + 8 + 4), at kk > 0
-    // reads b, u^n, x (8 each) and writes r (4); k_mg_down reads f_l, writes x_l
+    // i kLanes + s) of instance i at Chebyshev iteration kk (x, du: xb bytes each): k_pc_resid
+    // at kk = 0 reads r^n and du^{n-1}, writes b = r^n + du^{n-1} over r^n, x = 0 and r, at
+    // kk > 0 reads b, u^n (8 each), x and writes r (4); k_mg_down reads f_l, writes x_l
     // and f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l,
     // x_{l+1} and writes e_l, on the finest grid instead the Chebyshev step's reads and writes
-    // of d (4 each) and du^n (8 each); k_pc_update reads z, d (4 each), du^n (8) and writes d
-    // (4), du^n (8)
-    auto kb = [&](int kind, int i, int kk, int g) {
+    // of d (4 each) and du^n; k_pc_update reads z, d (4 each), du^n and writes d (4), du^n
+    // (the pipelined lanes hold x and du in float32: xb = 4 bytes per node, else 8)
+    auto kb = [&](int kind, int i, int kk, int g, double xb) {
       const MgDesc& m = h_mg[(size_t)i * kLanes];
       const double N2 = (double)probs[i].nx * probs[i].nx;
       const int l = g - (gmax - m.G);
       switch (kind) {
-        case 0: return N2 * (kk == 0 ? 36.0 : 28.0);
+        case 0: return N2 * (kk == 0 ? 20.0 + 2.0 * xb : 20.0 + xb);
         case 1: return l >= 0 ? (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0 : 0.0;
         case 2: return (double)m.n[m.G] * m.n[m.G] * 8.0;
         case 3:
-          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 32.0 : 12.0) + (double)m.n[l + 1] * m.n[l + 1] * 4.0
+          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 16.0 + 2.0 * xb : 12.0) +
+                              (double)m.n[l + 1] * m.n[l + 1] * 4.0
                         : 0.0;
-        default: return N2 * (kk == 0 ? 24.0 : 28.0);
+        default: return N2 * (kk == 0 ? 8.0 + 2.0 * xb : 12.0 + 2.0 * xb);
       }
     };
     // the V-cycle launches of Chebyshev iteration kk for the first ks lanes of a lane order
@@ -2208,10 +2209,11 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           d.dmask = 1;
           d.last = ln == S;
           d.R = (double*)(mg_base + DL.R[q]);
-          d.dU = (double*)(mg_base + DL.ring[q]);
+          d.dU = nullptr;
+          d.dxf = (float*)(mg_base + DL.ring[q]);
           d.park_out = ln >= 1 ? (double*)(mg_base + DL.park[q - 1]) : nullptr;
           d.park_in = ln < S ? (const double*)(mg_base + DL.park[q]) : nullptr;
-          d.dprev = ln >= 1 ? (const double*)(mg_base + DL.ring[q - 1]) : nullptr;
+          d.dprev = ln >= 1 ? (const float*)(mg_base + DL.ring[q - 1]) : nullptr;
           d.tgt = lin_tol;
           d.kcap = kcap;
           h_dd[q] = d;
@@ -2253,7 +2255,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
             if (lane_level(ln, D) < 0) continue;
             const double N2 = (double)probs[ln / kLanes].nx * probs[ln / kLanes].nx;
             b5 += N2 * (sg == S ? 16.0 : 24.0);  // reads u^n, u^{n-1}; writes r
-            if (sg >= 1) b6 += N2 * 32.0;        // reads u^n, du; writes the park and u^n
+            if (sg >= 1) b6 += N2 * 28.0;        // reads u^n, du (float32); writes the park and u^n
           }
         pb(6);
         hipLaunchKernelGGL(k_pipe_update, grid8(ca[ka]), dim3(256), 0, s, dd, ia, D, (int)ca[ka]);
@@ -2276,7 +2278,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           vcycle(D, kk, ks, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (size_t q = 0; q < ks; ++q)
-              if (lane_level(solving[q], D) >= 0 && kk < kq[q]) b += kb(kind, solving[q] / kLanes, kk, g);
+              if (lane_level(solving[q], D) >= 0 && kk < kq[q]) b += kb(kind, solving[q] / kLanes, kk, g, 4.0);
             return b;
           });
       }
@@ -2386,7 +2388,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           vcycle(n, kk, (size_t)k, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (int q = 0; q < k; ++q)
-              if (kk < h_kt[ofs_nt[order[q]] + n]) b += kb(kind, order[q], kk, g);
+              if (kk < h_kt[ofs_nt[order[q]] + n]) b += kb(kind, order[q], kk, g, 8.0);
             return b;
           });
       }

@@ -429,6 +429,7 @@ struct PcDesc {
   double* U;          // iterate [nt][N][N]
   double* R;          // residual: level n at R + (n & rmask) N^2
   double* dU;         // update: level n at dU + (n & dmask) N^2; the level solve iterates in it
+                      // (bulk schedule; pipelined lanes iterate in the float32 ring dxf)
   float* r;           // [N][ld] level residual b - A x (float32)
   float* z;           // [N][ld] B r
   float* d;           // [N][N] Chebyshev direction (float32: the inner solve's precision)
@@ -443,7 +444,8 @@ struct PcDesc {
   const double* u0;        // the initial condition (level -1)
   double* park_out;        // lane s-1's park: U^(s-1) of the level this lane updates
   const double* park_in;   // U^(s) of level n-1, parked by lane s+1 (NULL: read U)
-  const double* dprev;     // lane s-1's update ring
+  float* dxf;              // the lane's update ring (float32, two levels): the level solve's iterate
+  const float* dprev;      // lane s-1's update ring
   unsigned long long* stat;  // [nt][3] max |U^(s)_n|, max |R^(s)_n|, Gershgorin radius (bits)
   double tgt;              // residual reduction asked of a level solve
   int kcap;                // at most this many iterations (the launches the host issues)
@@ -500,6 +502,53 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
 // lane's level is m - stage.
 constexpr int kPcRows = 8, kPcTileY = 4 * kPcRows;
 __host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
+// Column (x, rows y0..y1-1) of k_pc_resid; XT: the type of the iterate x and of du^{n-1}.
+template <typename XT>
+__device__ __forceinline__ void pc_resid_column(const PcDesc* d, const KProb& p, int n, int k, int x, int y0, int y1,
+                                                XT* __restrict__ X, const XT* __restrict__ prev) {
+  const int nx = p.nx, ny = p.ny;
+  const unsigned ns = (unsigned)nx * (unsigned)ny;
+  double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
+  float* __restrict__ r = d->r;
+  if (k == 0) {  // b = r^n + du^{n-1} is kept in place of r^n for the later iterations
+    for (int y = y0; y < y1; ++y) {
+      const unsigned i = (unsigned)y * nx + x;
+      const double b = R[i] + (prev ? (double)prev[i] : 0.0);
+      R[i] = b;
+      X[i] = (XT)0;
+      r[(size_t)y * d->ld + x] = (float)b;
+    }
+    return;
+  }
+  const double* __restrict__ Un = d->U + (size_t)n * ns;
+  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
+  double uS = node_value(p, Un, bd, x, y0 - 1), uP = Un[(unsigned)y0 * nx + x];
+  double xS = y0 > 0 ? (double)X[(unsigned)(y0 - 1) * nx + x] : 0.0, xP = (double)X[(unsigned)y0 * nx + x];
+  for (int y = y0; y < y1; ++y) {
+    const unsigned i = (unsigned)y * nx + x;
+    const double uN = y + 1 < ny ? Un[i + nx] : node_value(p, Un, bd, x, y + 1);
+    const double xN = y + 1 < ny ? (double)X[i + nx] : 0.0;
+    Nb u;
+    u.P = uP;
+    u.S = uS;
+    u.N = uN;
+    u.W = x > 0 ? Un[i - 1] : node_value(p, Un, bd, x - 1, y);
+    u.E = x + 1 < nx ? Un[i + 1] : node_value(p, Un, bd, x + 1, y);
+    Row5 a;
+    (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // these solves are for heat only (no convection)
+    double ax = a.C * xP;
+    if (x > 0) ax += a.W * (double)X[i - 1];
+    if (x < nx - 1) ax += a.E * (double)X[i + 1];
+    if (y > 0) ax += a.S * xS;
+    if (y < ny - 1) ax += a.N * xN;
+    r[(size_t)y * d->ld + x] = (float)(R[i] - ax);
+    uS = uP;
+    uP = uN;
+    xS = xP;
+    xP = xN;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                    int m, int k, int count) {
   const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
@@ -514,47 +563,12 @@ __global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds,
   const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
   if (x >= nx || y0 >= ny) return;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
-  double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
-  const double* __restrict__ prev = n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr;
-  double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
-  float* __restrict__ r = d->r;
-  if (k == 0) {  // b = r^n + du^{n-1} is kept in place of r^n for the later iterations
-    for (int y = y0; y < y1; ++y) {
-      const unsigned i = (unsigned)y * nx + x;
-      const double b = R[i] + (prev ? prev[i] : 0.0);
-      R[i] = b;
-      X[i] = 0.0;
-      r[(size_t)y * d->ld + x] = (float)b;
-    }
-    return;
-  }
-  const double* __restrict__ Un = d->U + (size_t)n * ns;
-  const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
-  double uS = node_value(p, Un, bd, x, y0 - 1), uP = Un[(unsigned)y0 * nx + x];
-  double xS = y0 > 0 ? X[(unsigned)(y0 - 1) * nx + x] : 0.0, xP = X[(unsigned)y0 * nx + x];
-  for (int y = y0; y < y1; ++y) {
-    const unsigned i = (unsigned)y * nx + x;
-    const double uN = y + 1 < ny ? Un[i + nx] : node_value(p, Un, bd, x, y + 1);
-    const double xN = y + 1 < ny ? X[i + nx] : 0.0;
-    Nb u;
-    u.P = uP;
-    u.S = uS;
-    u.N = uN;
-    u.W = x > 0 ? Un[i - 1] : node_value(p, Un, bd, x - 1, y);
-    u.E = x + 1 < nx ? Un[i + 1] : node_value(p, Un, bd, x + 1, y);
-    Row5 a;
-    (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // these solves are for heat only (no convection)
-    double ax = a.C * xP;
-    if (x > 0) ax += a.W * X[i - 1];
-    if (x < nx - 1) ax += a.E * X[i + 1];
-    if (y > 0) ax += a.S * xS;
-    if (y < ny - 1) ax += a.N * xN;
-    r[(size_t)y * d->ld + x] = (float)(R[i] - ax);
-    uS = uP;
-    uP = uN;
-    xS = xP;
-    xP = xN;
-  }
+  if (d->dxf)
+    pc_resid_column<float>(d, p, n, k, x, y0, y1, d->dxf + (size_t)(n & 1) * ns,
+                           n > 0 ? d->dxf + (size_t)((n - 1) & 1) * ns : nullptr);
+  else
+    pc_resid_column<double>(d, p, n, k, x, y0, y1, d->dU + (size_t)(n & d->dmask) * ns,
+                            n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr);
 }
 
 // d = c0 d + c1 z, x += d (tiles as k_pc_resid)
@@ -572,12 +586,14 @@ __global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds
   if (x >= nx) return;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
   const float2 c = d->c[(size_t)n * kMaxCheb + k];
-  double* __restrict__ X = d->dU + (size_t)(n & d->dmask) * ns;
   for (int y = y0; y < y1; ++y) {
     const unsigned i = (unsigned)y * nx + x;
     const float dir = (k == 0 ? 0.f : c.x * d->d[i]) + c.y * d->z[(size_t)y * d->ld + x];
     d->d[i] = dir;
-    X[i] += (double)dir;
+    if (d->dxf)
+      d->dxf[(size_t)(n & 1) * ns + i] += dir;
+    else
+      d->dU[(size_t)(n & d->dmask) * ns + i] += (double)dir;
   }
 }
 
@@ -599,7 +615,8 @@ __global__ __launch_bounds__(kMgThreads) void k_mg_down(const MgDesc* __restrict
 }
 
 // The Chebyshev step of iteration k at node (i, j), given z = B r there: d = c0 d + c1 z in
-// float32, du^n += d in FP64. Applied by the V-cycle's last kernel on the finest grid.
+// float32, du^n += d (FP64 in the bulk schedule, float32 in a pipelined lane's ring). Applied
+// by the V-cycle's last kernel on the finest grid.
 struct ChebStep {
   const PcDesc* d;
   int n, k, N;
@@ -608,7 +625,10 @@ struct ChebStep {
     const float2 c = d->c[(size_t)n * kMaxCheb + k];
     const float dir = (k == 0 ? 0.f : c.x * d->d[idx]) + c.y * z;
     d->d[idx] = dir;
-    d->dU[(size_t)(n & d->dmask) * N * N + idx] += (double)dir;
+    if (d->dxf)
+      d->dxf[(size_t)(n & 1) * N * N + idx] += dir;
+    else
+      d->dU[(size_t)(n & d->dmask) * N * N + idx] += (double)dir;
   }
 };
 
@@ -675,12 +695,12 @@ __global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ 
   if (x >= nx) return;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
   double* __restrict__ u = d->U + (size_t)n * ns;
-  const double* __restrict__ du = d->dprev + (size_t)(n & 1) * ns;
+  const float* __restrict__ du = d->dprev + (size_t)(n & 1) * ns;
   for (int y = y0; y < y1; ++y) {
     const unsigned i = (unsigned)y * nx + x;
     const double old = u[i];
     d->park_out[i] = old;
-    u[i] = old + du[i];
+    u[i] = old + (double)du[i];
   }
 }
 
