@@ -54,8 +54,8 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
 # dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
 # fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
-MG_TRAFFIC = {"kernel_sha256": "d890f8a5369f5aba7924cf2178caa4d6cb583311fc65f14a2d3792867f857e4f",
-              "fetch_bytes": 197004864, "write_bytes": 78138470}
+MG_TRAFFIC = {"kernel_sha256": "9c1400c011a27ef04efd4493a03fb8519d148b547beec13a0db0fd13cfc52e5d",
+              "fetch_bytes": 90944702, "write_bytes": 44341350}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
                ("// Chebyshev plan of a multigrid-preconditioned level solve", "// Work items (lane, tile of"),
