@@ -425,7 +425,8 @@ def bench_learned(args):
             ach = bpl / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": "k_level_wave_batch", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_ms * 1e3,
-                    "bytes_per_launch": bpl}
+                    "bytes_per_launch": bpl,
+                    "limiter": "occupancy: one 1024-thread work-group per CU (register-resident region solve)"}
         if not args.no_cpu_baseline:  # the oracle on the first levels of held-out instance 0
             cb, oerr, lv = cpu_baseline(probs_b[0], args.cpu_seconds, U_b[0].cpu().numpy())
             oerr = {"value": oerr, "levels_checked": lv, "instance": 0, "form": "learned + mixed"}
@@ -503,8 +504,18 @@ def bench_heatbatch(args, extras=None):
         return P.solve_batched(probs, Us, u0s, tol=args.tol, max_iter=60, precision="mixed", ws=ws,
                                schedule=args.schedule, stages=args.stages, **kw)
 
-    for _ in range(args.warmup):
-        step()
+    # the first solve of the batch runs seven Newton stages per pass and records the steps the
+    # batch needed; later solves of the same batch run that many (a per-signature cache of the
+    # library, like the autotuned plans); the first solve's time is reported as well
+    first_ms, first_its = None, None
+    for w in range(args.warmup):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stw = step()
+        torch.cuda.synchronize()
+        if w == 0:
+            first_ms, first_its = (time.perf_counter() - t0) * 1e3, max(st["iterations"] for st in stw)
+            log(f"first solve {first_ms:.0f} ms, Newton steps {first_its}")
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     gc.collect()
@@ -562,11 +573,16 @@ def bench_heatbatch(args, extras=None):
                    "schedule": "pipelined Newton stages" if pipelined else "batched bulk",
                    "newton_steps_min_max": [min(its), max(its)],
                    "newton_steps_needed_min_max": [min(need), max(need)] if need else None,
+                   "first_solve_ms": first_ms, "first_solve_newton_steps": first_its,
+                   "stages_per_pass_source": "the Newton steps the first solve of this batch needed "
+                                             "(per-signature cache in the library)",
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
         "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": mg_traffic() if names[j] == "k_mg_up" and pipelined else None,
-                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl},
+                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl,
+                     "limiter": "latency: dependent global loads and three LDS phases per tile at four "
+                                "work-groups per CU; bytes past L2 match the algorithmic bytes"},
         "kernel_split": split,
     }
     if errs:
@@ -696,6 +712,11 @@ def bench_single(args):
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
 
     tuned = None
+    # the first call on this problem pays for what the library then keeps per problem signature
+    # (the autotuner's plan and stage count; where the whole-domain Newton iteration diverges,
+    # the discovery of the slab length): its time is reported beside the timed solves
+    torch.cuda.synchronize()
+    t_first = time.perf_counter()
     if args.schedule in ("auto", "pipeline") and not args.no_autotune:
         P.init_plain(prob, U, u0)
         tuned = P.autotune(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws)
@@ -705,8 +726,12 @@ def bench_single(args):
         P.init_plain(prob, U, u0)
         return P.solve(prob, U, u0, tol=args.tol, max_iter=60, precision=args.precision, ws=ws, **opts)
 
-    for _ in range(args.warmup):
+    first_ms = None
+    for w in range(args.warmup):
         st = step()
+        if w == 0:
+            torch.cuda.synchronize()
+            first_ms = (time.perf_counter() - t_first) * 1e3
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     gc.collect()
@@ -763,12 +788,18 @@ def bench_single(args):
                    "precision": args.precision, "tol": args.tol, "newton_steps": st["iterations"],
                    "inner_sweeps": st["sweeps"], "inner_passes": st["refine"] + 1,
                    "schedule": {1: "bulk", 2: "wavefront"}.get(st["schedule"], st["schedule"]),
-                   "autotuned": tuned is not None, **extra},
+                   "autotuned": tuned is not None,
+                   "first_call_ms": first_ms, "first_call": "autotuning (if any) and the first solve, "
+                   "which find what the library keeps per problem signature (plan, stages, slab length)",
+                   **extra},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic((st["sweeps"], st["refine"] + 1, stages))
                      if (args.workload == "burgers256" and args.precision == "fp64" and stages) else None,
-                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch},
+                     "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
+                     "limiter": "occupancy: one 1024-thread work-group per CU (107-121 VGPRs for the "
+                                "register-resident region solve), tiles of one anti-diagonal fewer "
+                                "than the 256 CUs"},
     }
     if not args.no_cpu_baseline:
         cb, err, levels = cpu_baseline(prob, args.cpu_seconds, U_host)

@@ -307,8 +307,9 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    PTS_SCHED_PIPELINE, iterations a multiple of the stage count, res_inf and
    rho_max of the steps inside a pass from the stage residuals the lanes formed,
    upd_rms NaN). Without opts->stages, a batch solved again with the same
-   signature (kinds, sizes, coefficients, precision, tol) runs as many stages per
-   pass as its first pass needed last time (a per-thread cache). This path
+   signature (kinds, sizes, coefficients, precision, tol) runs the Newton steps
+   it needed last time, in as few passes of at most 7 stages as possible (a
+   per-thread cache). This path
    synchronises the stream once per diagonal (it reads back the iteration
    counts the lanes planned). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for

@@ -1986,7 +1986,12 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   const bool pipelined = o == nullptr || o->schedule != PTS_SCHED_BULK;
   const unsigned long long skey = PassCache::key(probs, nprob, tol);
   const int cached = g_pass_cache.get(skey);
-  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages : (cached > 0 ? cached : kLanes - 1));
+  // stages per pass: asked for; else from the Newton steps this batch needed last time, split
+  // into as few passes of at most kLanes - 1 stages as possible; else kLanes - 1
+  const int npass_c = cached > 0 ? (cached + kLanes - 2) / (kLanes - 1) : 1;
+  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages
+                                           : (cached > 0 ? (cached + npass_c - 1) / npass_c : kLanes - 1));
+  std::vector<int> conv_it(nprob, -1);  // Newton step at which each instance met tol (pipelined)
   for (int it = 0;; ++it) {
     int nactive = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -2293,7 +2298,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         return v;
       };
       // stages the pass needed: per instance the first s whose iterate meets tol at every level
-      int need = 0;
       bool all_met = true;
       for (int i : order) {
         const unsigned long long* st = hst.data() + DL.lstat[i];
@@ -2304,10 +2308,17 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           for (int n = 0; n < nt; ++n) r = std::max(r, st[((size_t)sg * nt + n) * 3 + 1]);
           if (val(r) <= tol) first = sg;
         }
-        if (first < 0) all_met = false;
-        need = std::max(need, first);
+        if (first < 0)
+          all_met = false;
+        else
+          conv_it[i] = it + first;
       }
-      if (it == 0 && all_met && need >= 1 && !(o && o->stages > 0)) g_pass_cache.put(skey, need);
+      // all instances met tol: keep the Newton steps the batch needed (from the first iterate)
+      if (all_met && !(o && o->stages > 0)) {
+        int need = 0;
+        for (int i = 0; i < nprob; ++i) need = std::max(need, conv_it[i]);
+        if (need >= 1) g_pass_cache.put(skey, need);
+      }
       for (int i : order) {
         const unsigned long long* st = hst.data() + DL.lstat[i];
         const int nt = probs[i].nt;
