@@ -165,6 +165,26 @@ def test_stiff_heat_batch_pipelined_with_boundary_data_matches_oracle():
         assert err <= 1e-8, (p.name, err)
 
 
+def test_stiff_heat_pipelined_limits_and_single_instance():
+    """Pipelined multigrid stages at their limits: max_iter below the stage count (the pass is
+    shortened, the iterate stays finite and the solve reports PTS_ERR_NOT_CONVERGED), and a
+    batch of one stiff instance with one level."""
+    probs = _heat_batch(33, [(128, 5), (100, 3)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print("[batched] stiff heat pipelined, max_iter 3", flush=True)
+    with pytest.raises(P.PTSError) as e:
+        P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-30, max_iter=3, precision="mixed")
+    assert e.value.code == P._lib.PTS_ERR_NOT_CONVERGED, e.value
+    assert all(np.all(np.isfinite(host(U))) for U in Us)
+    one = _heat_batch(34, [(150, 1)])
+    U1 = [dev(one[0].plain_iterate())]
+    print("[batched] stiff heat pipelined, one instance, one level", flush=True)
+    st = P.solve_batched(one, U1, [dev(one[0].u0)], tol=1e-12, max_iter=40, precision="mixed")[0]
+    assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
+    Uo, _ = sequential.solve_sequential(one[0])
+    assert np.max(np.abs(host(U1[0]) - Uo)) <= 1e-8 * np.max(np.abs(Uo))
+
+
 def test_windows_option_solves_instances_one_after_another():
     probs = _heat_batch(14, [(20, 5), (33, 4)])
     Us = [dev(p.plain_iterate()) for p in probs]
