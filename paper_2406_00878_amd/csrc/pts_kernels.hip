@@ -549,7 +549,7 @@ __device__ __forceinline__ void pc_resid_column(const PcDesc* d, const KProb& p,
   }
 }
 
-__global__ __launch_bounds__(256) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pc_resid(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                    int m, int k, int count) {
   const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
   if (wi >= (unsigned)count) return;
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256) void k_pipe_update(const PcDesc* __restrict__ 
 // r^(s)_n = -(U^(s)_n - U^(s)_{n-1} + tau F(U^(s)_n)) into the lane's level buffer, with
 // max |U^(s)_n|, max |r| and the Gershgorin radius of the level's rows into stat[n]
 // (tiles as k_pc_resid, the column's u of the rows above and below kept in registers).
-__global__ __launch_bounds__(256) void k_pipe_residual(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pipe_residual(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
                                                         int D, int count) {
   const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
   if (wi >= (unsigned)count) return;
