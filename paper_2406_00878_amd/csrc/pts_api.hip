@@ -1673,7 +1673,7 @@ int mg_up_tiles(const MgDesc& d, int l) {
 // for the update and residual after the last one (S <= kLanes - 1).
 constexpr int kLanes = 8;
 struct MgLayout {
-  size_t desc, mgdesc, items_e, items_e0, items_d, items_u, items_l, items_a, items_k, stat, total;
+  size_t desc, mgdesc, items_e, items_d, items_u, items_l, items_a, items_k, stat, total;
   size_t stat_words = 0;                        // [nt][3] per lane, lanes one after another
   std::vector<size_t> tab, lmax, lstat;         // per instance (lstat: its lane 0's stat words)
   std::vector<size_t> d, K, coef, R, ring, park;  // per lane
@@ -1705,7 +1705,6 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
   L.desc = take(nl * sizeof(PcDesc));
   L.mgdesc = take(nl * sizeof(MgDesc));
   L.items_e = take(L.ne * sizeof(int2));
-  L.items_e0 = take(L.ne * sizeof(int2));
   L.items_a = take(L.ne * sizeof(int2));
   L.items_d = take(std::max<size_t>(L.nd, 1) * sizeof(int4));
   L.items_u = take(std::max<size_t>(L.nu, 1) * sizeof(int4));
@@ -1866,7 +1865,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   const size_t s_iu = stake(eligible ? DL.nu * sizeof(int4) : 0);
   const size_t s_il = stake(eligible ? nlanes * sizeof(int) : 0);
   const size_t s_ie = stake(eligible ? DL.ne * sizeof(int2) : 0);
-  const size_t s_ie0 = stake(eligible ? DL.ne * sizeof(int2) : 0);
   const size_t s_ia = stake(eligible ? DL.ne * sizeof(int2) : 0);
   size_t tab_bytes = 0;
   if (eligible)
@@ -1889,7 +1887,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   int4* h_iu = (int4*)(stage + s_iu);
   int* h_il = (int*)(stage + s_il);
   int2* h_ie = (int2*)(stage + s_ie);
-  int2* h_ie0 = (int2*)(stage + s_ie0);
   int2* h_ia = (int2*)(stage + s_ia);
   double* h_sc = (double*)(stage + s_sc);  // per instance: max|r|, rho_max, rms, max|u^0|
   std::vector<size_t> ofs_nt(nprob, 0);      // instance i's levels start at ofs_nt[i] in the per-level tables
@@ -2064,7 +2061,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     const PcDesc* dd = (const PcDesc*)(mg_base + DL.desc);
     const MgDesc* dm = (const MgDesc*)(mg_base + DL.mgdesc);
     const int2* ie = (const int2*)(mg_base + DL.items_e);
-    const int2* ie0 = (const int2*)(mg_base + DL.items_e0);
     const int2* ia = (const int2*)(mg_base + DL.items_a);
     const int4* id = (const int4*)(mg_base + DL.items_d);
     const int4* iu = (const int4*)(mg_base + DL.items_u);
@@ -2075,7 +2071,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     // kk > 0 reads b, u^n (8 each), x and writes r (4); k_mg_down reads f_l, writes x_l
     // and f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l,
     // x_{l+1} and writes e_l, on the finest grid instead the Chebyshev step's reads and writes
-    // of d (4 each) and du^n; k_pc_update reads z, d (4 each), du^n and writes d (4), du^n
+    // of d (4 each) and du^n
     // (the pipelined lanes hold x and du in float32: xb = 4 bytes per node, else 8)
     auto kb = [&](int kind, int i, int kk, int g, double xb) {
       const MgDesc& m = h_mg[(size_t)i * kLanes];
@@ -2093,9 +2089,10 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       }
     };
     // the V-cycle launches of Chebyshev iteration kk for the first ks lanes of a lane order
-    // (k_pc_resid, the down kernels, the LDS part, the up kernels, k_pc_update); m is the level
+    // (k_pc_resid, the down kernels, the LDS part, the up kernels; the last of them applies the
+    // Chebyshev step on the finest grid, k_mg_lds where the whole V-cycle is in LDS); m is the level
     // (bulk) or the diagonal (pipelined); bytes(kind, g) gives the profiled launches' bytes
-    auto vcycle = [&](int m, int kk, size_t ks, const std::vector<size_t>& ce, const std::vector<size_t>& ce0,
+    auto vcycle = [&](int m, int kk, size_t ks, const std::vector<size_t>& ce,
                       const std::vector<std::vector<size_t>>& cd, const std::vector<std::vector<size_t>>& cu,
                       const std::vector<size_t>& od, const std::vector<size_t>& ou, auto&& bytes) {
       pb(0);
@@ -2122,36 +2119,25 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         pe(prof ? bytes(3, g) : 0.0);
         ++launches;
       }
-      if (ce0[ks]) {
-        pb(4);
-        hipLaunchKernelGGL(k_pc_update, grid8(ce0[ks]), dim3(256), 0, s, dd, ie0, m, kk, (int)ce0[ks]);
-        pe(prof ? bytes(4, 0) : 0.0);
-        ++launches;
-      }
     };
-    // work items of a lane order: node chunks (ce), node chunks of lanes whose V-cycle is all
-    // in LDS (ce0, they keep z in memory), lane ids, and per step g the down/up tiles (an
+    // work items of a lane order: node tiles (ce), lane ids, and per step g the down/up tiles (an
     // instance takes part when g >= gmax - G_i, on grid g - (gmax - G_i)); cumulative counts
     // per prefix of the order, the items uploaded to the header
-    auto build_items = [&](const std::vector<int>& lanes, std::vector<size_t>& ce, std::vector<size_t>& ce0,
+    auto build_items = [&](const std::vector<int>& lanes, std::vector<size_t>& ce,
                            std::vector<std::vector<size_t>>& cd, std::vector<std::vector<size_t>>& cu,
                            std::vector<size_t>& od, std::vector<size_t>& ou) -> int {
       const size_t no = lanes.size();
       ce.assign(no + 1, 0);
-      ce0.assign(no + 1, 0);
       cd.assign(gmax, std::vector<size_t>(no + 1, 0));
       cu = cd;
       od.assign(gmax, 0);
       ou.assign(gmax, 0);
-      size_t ne = 0, ne0 = 0, nd = 0, nu = 0;
+      size_t ne = 0, nd = 0, nu = 0;
       for (size_t q = 0; q < no; ++q) {
         const int ln = lanes[q], i = ln / kLanes;
         const int N = probs[i].nx, ch = pc_tiles(N, N);
         for (int c = 0; c < ch; ++c) h_ie[ne++] = make_int2(ln, c);
-        if (h_mg[ln].G == 0)
-          for (int c = 0; c < ch; ++c) h_ie0[ne0++] = make_int2(ln, c);
         ce[q + 1] = ne;
-        ce0[q + 1] = ne0;
         h_il[q] = ln;
       }
       for (int g = 0; g < gmax; ++g) {
@@ -2174,7 +2160,6 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       }
       HIPCHK(hipMemcpyAsync(mg_base + DL.desc, h_dd, nlanes * sizeof(PcDesc), hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(mg_base + DL.items_e, h_ie, ne * sizeof(int2), hipMemcpyHostToDevice, s));
-      if (ne0) HIPCHK(hipMemcpyAsync(mg_base + DL.items_e0, h_ie0, ne0 * sizeof(int2), hipMemcpyHostToDevice, s));
       if (nd) HIPCHK(hipMemcpyAsync(mg_base + DL.items_d, h_id, nd * sizeof(int4), hipMemcpyHostToDevice, s));
       if (nu) HIPCHK(hipMemcpyAsync(mg_base + DL.items_u, h_iu, nu * sizeof(int4), hipMemcpyHostToDevice, s));
       HIPCHK(hipMemcpyAsync(mg_base + DL.items_l, h_il, no * sizeof(int), hipMemcpyHostToDevice, s));
@@ -2223,9 +2208,9 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           d.kcap = kcap;
           h_dd[q] = d;
         }
-      std::vector<size_t> ce, ce0, od, ou;
+      std::vector<size_t> ce, od, ou;
       std::vector<std::vector<size_t>> cd, cu;
-      if ((rc = build_items(solving, ce, ce0, cd, cu, od, ou))) return rc;
+      if ((rc = build_items(solving, ce, cd, cu, od, ou))) return rc;
       // node tiles of every lane (the update and residual launches)
       std::vector<size_t> ca(all.size() + 1, 0);
       size_t na = 0;
@@ -2280,7 +2265,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         for (size_t q = 0; q < ks; ++q) kn = std::max(kn, kq[q]);
         kmax_all = std::max(kmax_all, kn);
         for (int kk = 0; kk < kn; ++kk)
-          vcycle(D, kk, ks, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
+          vcycle(D, kk, ks, ce, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (size_t q = 0; q < ks; ++q)
               if (lane_level(solving[q], D) >= 0 && kk < kq[q]) b += kb(kind, solving[q] / kLanes, kk, g, 4.0);
@@ -2387,16 +2372,16 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           stats[i].refine = 0;
         }
       }
-      std::vector<size_t> ce, ce0, od, ou;
+      std::vector<size_t> ce, od, ou;
       std::vector<std::vector<size_t>> cd, cu;
-      if ((rc = build_items(lanes, ce, ce0, cd, cu, od, ou))) return rc;
+      if ((rc = build_items(lanes, ce, cd, cu, od, ou))) return rc;
       for (int n = 0; n < maxnt; ++n) {
         const int k = kpref[n];
         if (k == 0) continue;
         int kn = 0;  // iterations of level n: the most any instance in the prefix needs
         for (int q = 0; q < k; ++q) kn = std::max(kn, h_kt[ofs_nt[order[q]] + n]);
         for (int kk = 0; kk < kn; ++kk)
-          vcycle(n, kk, (size_t)k, ce, ce0, cd, cu, od, ou, [&](int kind, int g) {
+          vcycle(n, kk, (size_t)k, ce, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (int q = 0; q < k; ++q)
               if (kk < h_kt[ofs_nt[order[q]] + n]) b += kb(kind, order[q], kk, g, 8.0);

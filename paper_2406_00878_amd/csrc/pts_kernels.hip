@@ -417,8 +417,8 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
 // margin for the non-symmetric mu' terms of the Jacobian); the V-cycle B has spec(B M) in
 // [kMgLow, 1], which widens the interval's lower end.
 // Iteration k of level n: r = b - A x in FP64 from U (k_pc_resid, float32 r), z = B r (the
-// V-cycle launches), d = c0 d + c1 z, x += d in FP64 (ChebStep, applied where the V-cycle
-// writes its finest grid; k_pc_update for a z stored in memory).
+// V-cycle launches), d = c0 d + c1 z, x += d (ChebStep, applied once, where the V-cycle writes
+// its finest grid: k_mg_up, or k_mg_lds where the whole V-cycle runs in LDS).
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
 // One level solver's arrays. In the bulk schedule there is one per instance (stage 0, full
 // space-time R and dU). In the pipelined schedule there is one per (instance, Newton stage s),
@@ -569,32 +569,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   else
     pc_resid_column<double>(d, p, n, k, x, y0, y1, d->dU + (size_t)(n & d->dmask) * ns,
                             n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr);
-}
-
-// d = c0 d + c1 z, x += d (tiles as k_pc_resid)
-__global__ __launch_bounds__(256) void k_pc_update(const PcDesc* __restrict__ ds, const int2* __restrict__ items,
-                                                    int m, int k, int count) {
-  const unsigned wi = xcd_band(blockIdx.x, gridDim.x);  // neighbouring tiles share an XCD's L2
-  if (wi >= (unsigned)count) return;
-  const int2 it = items[wi];
-  const PcDesc* d = ds + it.x;
-  const int n = m - d->stage;
-  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
-  const int nx = d->p.nx, ny = d->p.ny, tilesx = (nx + 63) >> 6;
-  const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
-  const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
-  if (x >= nx) return;
-  const unsigned ns = (unsigned)nx * (unsigned)ny;
-  const float2 c = d->c[(size_t)n * kMaxCheb + k];
-  for (int y = y0; y < y1; ++y) {
-    const unsigned i = (unsigned)y * nx + x;
-    const float dir = (k == 0 ? 0.f : c.x * d->d[i]) + c.y * d->z[(size_t)y * d->ld + x];
-    d->d[i] = dir;
-    if (d->dxf)
-      d->dxf[(size_t)(n & 1) * ns + i] += dir;
-    else
-      d->dU[(size_t)(n & d->dmask) * ns + i] += (double)dir;
-  }
 }
 
 // V-cycle launches of iteration k of level n. Items (lane, grid l, tile x, tile y) of the

@@ -185,6 +185,24 @@ def test_stiff_heat_pipelined_limits_and_single_instance():
     assert np.max(np.abs(host(U1[0]) - Uo)) <= 1e-8 * np.max(np.abs(Uo))
 
 
+@pytest.mark.parametrize("schedule", ["auto", "bulk"])
+def test_stiff_batch_with_whole_vcycle_in_lds(schedule):
+    """Instances of at most 64^2 nodes in a multigrid batch run their whole V-cycle in LDS,
+    which applies the Chebyshev step itself (once): their level solves are as accurate as the
+    others', so their Newton counts stay those of the stiff instance."""
+    probs = _heat_batch(35, [(40, 12), (64, 10), (150, 3)])
+    Us = [dev(p.plain_iterate()) for p in probs]
+    print(f"[batched] stiff heat with LDS-only hierarchies, {schedule}", flush=True)
+    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40, precision="mixed",
+                          schedule=schedule)
+    for p, U, st in zip(probs, Us, sts):
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        print(p.name, "needed", st["needed"], "iterations", st["iterations"], "err", err, flush=True)
+        assert st["converged"] and err <= 1e-8, (p.name, st, err)
+        assert st["needed"] is not None and st["needed"] <= 7, (p.name, st["needed"])
+
+
 def test_windows_option_solves_instances_one_after_another():
     probs = _heat_batch(14, [(20, 5), (33, 4)])
     Us = [dev(p.plain_iterate()) for p in probs]
