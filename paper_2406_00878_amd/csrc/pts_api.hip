@@ -1699,7 +1699,7 @@ MgLayout mg_layout(const pts_problem* probs, int nprob) {
     }
     L.gmax = std::max(L.gmax, h.G);
     L.lstat.push_back(L.stat_words);
-    L.stat_words += (size_t)kLanes * 3 * probs[i].nt;
+    L.stat_words += (size_t)kLanes * kStat * probs[i].nt;
   }
   const size_t nl = (size_t)nprob * kLanes;
   L.desc = take(nl * sizeof(PcDesc));
@@ -1976,7 +1976,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     d.rmask = -1;
     d.dmask = -1;
     d.u0 = u0[i];
-    d.stat = (unsigned long long*)(mg_base + DL.stat) + DL.lstat[i] + (size_t)ln * 3 * probs[i].nt;
+    d.stat = (unsigned long long*)(mg_base + DL.stat) + DL.lstat[i] + (size_t)ln * kStat * probs[i].nt;
     return d;
   };
   const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
@@ -2092,13 +2092,15 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     // (k_pc_resid, the down kernels, the LDS part, the up kernels; the last of them applies the
     // Chebyshev step on the finest grid, k_mg_lds where the whole V-cycle is in LDS); m is the level
     // (bulk) or the diagonal (pipelined); bytes(kind, g) gives the profiled launches' bytes
-    auto vcycle = [&](int m, int kk, size_t ks, const std::vector<size_t>& ce,
+    auto vcycle = [&](int m, int kk, bool resid, size_t ks, const std::vector<size_t>& ce,
                       const std::vector<std::vector<size_t>>& cd, const std::vector<std::vector<size_t>>& cu,
                       const std::vector<size_t>& od, const std::vector<size_t>& ou, auto&& bytes) {
-      pb(0);
-      hipLaunchKernelGGL(k_pc_resid, grid8(ce[ks]), dim3(256), 0, s, dd, ie, m, kk, (int)ce[ks]);
-      pe(prof ? bytes(0, 0) : 0.0);
-      ++launches;
+      if (resid) {
+        pb(0);
+        hipLaunchKernelGGL(k_pc_resid, grid8(ce[ks]), dim3(256), 0, s, dd, ie, m, kk, (int)ce[ks]);
+        pe(prof ? bytes(0, 0) : 0.0);
+        ++launches;
+      }
       for (int g = 0; g < gmax; ++g) {
         if (!cd[g][ks]) continue;
         pb(1);
@@ -2255,6 +2257,19 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         pe(b5);
         launches += 2;
         if (ks == 0) continue;
+        // the first iteration's residual, from x0 = du^{n-1} (n > 0), before the plans
+        double b0 = 0.0;
+        if (prof)
+          for (size_t q = 0; q < ks; ++q) {
+            const int ln = solving[q], n = lane_level(ln, D);
+            if (n < 0) continue;
+            const double N2 = (double)probs[ln / kLanes].nx * probs[ln / kLanes].nx;
+            b0 += N2 * (n > 0 ? 36.0 : 24.0);  // r^n (read and rewritten as b), u^n, du^{n-1}, x, r
+          }
+        pb(0);
+        hipLaunchKernelGGL(k_pc_resid, grid8(ce[ks]), dim3(256), 0, s, dd, ie, D, 0, (int)ce[ks]);
+        pe(b0);
+        ++launches;
         pb(7);
         hipLaunchKernelGGL(k_pipe_cheb, dim3((unsigned)((ks + 63) / 64)), dim3(64), 0, s, dd, il, (int)ks, D, d_kq);
         pe(0.0);
@@ -2265,7 +2280,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         for (size_t q = 0; q < ks; ++q) kn = std::max(kn, kq[q]);
         kmax_all = std::max(kmax_all, kn);
         for (int kk = 0; kk < kn; ++kk)
-          vcycle(D, kk, ks, ce, cd, cu, od, ou, [&](int kind, int g) {
+          vcycle(D, kk, kk > 0, ks, ce, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (size_t q = 0; q < ks; ++q)
               if (lane_level(solving[q], D) >= 0 && kk < kq[q]) b += kb(kind, solving[q] / kLanes, kk, g, 4.0);
@@ -2290,7 +2305,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         int first = -1;
         for (int sg = 0; sg <= S && first < 0; ++sg) {
           unsigned long long r = 0;
-          for (int n = 0; n < nt; ++n) r = std::max(r, st[((size_t)sg * nt + n) * 3 + 1]);
+          for (int n = 0; n < nt; ++n) r = std::max(r, st[((size_t)sg * nt + n) * kStat + 1]);
           if (val(r) <= tol) first = sg;
         }
         if (first < 0)
@@ -2313,7 +2328,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         bool finite = true;
         for (int sg = 0; sg <= S; ++sg)
           for (int n = 0; n < nt; ++n) {
-            const unsigned long long* q = st + ((size_t)sg * nt + n) * 3;
+            const unsigned long long* q = st + ((size_t)sg * nt + n) * kStat;
             finite = finite && q[0] < kInf && q[1] < kInf && q[2] < kInf;
             rho = std::max(rho, q[2]);
             if (sg == S) {
@@ -2333,7 +2348,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           for (int sg = 1; sg < S && it + sg < PTS_MAX_HIST; ++sg) {
             unsigned long long r = 0, g = 0;
             for (int n = 0; n < nt; ++n) {
-              const unsigned long long* q = st + ((size_t)sg * nt + n) * 3;
+              const unsigned long long* q = st + ((size_t)sg * nt + n) * kStat;
               r = std::max(r, q[1]);
               g = std::max(g, q[2]);
             }
@@ -2381,7 +2396,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         int kn = 0;  // iterations of level n: the most any instance in the prefix needs
         for (int q = 0; q < k; ++q) kn = std::max(kn, h_kt[ofs_nt[order[q]] + n]);
         for (int kk = 0; kk < kn; ++kk)
-          vcycle(n, kk, (size_t)k, ce, cd, cu, od, ou, [&](int kind, int g) {
+          vcycle(n, kk, true, (size_t)k, ce, cd, cu, od, ou, [&](int kind, int g) {
             double b = 0.0;
             for (int q = 0; q < k; ++q)
               if (kk < h_kt[ofs_nt[order[q]] + n]) b += kb(kind, order[q], kk, g, 8.0);

@@ -420,6 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
 // V-cycle launches), d = c0 d + c1 z, x += d (ChebStep, applied once, where the V-cycle writes
 // its finest grid: k_mg_up, or k_mg_lds where the whole V-cycle runs in LDS).
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
+constexpr int kStat = 5;      // words of a pipelined lane's statistics per level
 // One level solver's arrays. In the bulk schedule there is one per instance (stage 0, full
 // space-time R and dU). In the pipelined schedule there is one per (instance, Newton stage s),
 // a "lane": a launch for diagonal D has lane s work on level n = D - s, with its residual in a
@@ -446,7 +447,8 @@ struct PcDesc {
   const double* park_in;   // U^(s) of level n-1, parked by lane s+1 (NULL: read U)
   float* dxf;              // the lane's update ring (float32, two levels): the level solve's iterate
   const float* dprev;      // lane s-1's update ring
-  unsigned long long* stat;  // [nt][3] max |U^(s)_n|, max |R^(s)_n|, Gershgorin radius (bits)
+  unsigned long long* stat;  // [nt][kStat] max |U^(s)_n|, max |R^(s)_n|, Gershgorin radius, max |b|,
+                             // max |b - A x0| of the level solve (bit patterns)
   double tgt;              // residual reduction asked of a level solve
   int kcap;                // at most this many iterations (the launches the host issues)
 };
@@ -503,31 +505,39 @@ __global__ __launch_bounds__(256) void k_level_absmax(const double* __restrict__
 constexpr int kPcRows = 8, kPcTileY = 4 * kPcRows;
 __host__ __device__ inline int pc_tiles(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kPcTileY - 1) / kPcTileY); }
 // Column (x, rows y0..y1-1) of k_pc_resid; XT: the type of the iterate x and of du^{n-1}.
+// With warm (the pipelined lanes, n > 0) the first iteration starts from x0 = du^{n-1}: it
+// writes x = x0 and r = b - A x0, and returns max |b| and max |r| of the column in bm, rm.
 template <typename XT>
 __device__ __forceinline__ void pc_resid_column(const PcDesc* d, const KProb& p, int n, int k, int x, int y0, int y1,
-                                                XT* __restrict__ X, const XT* __restrict__ prev) {
+                                                XT* __restrict__ X, const XT* __restrict__ prev, bool warm,
+                                                double& bm, double& rm) {
   const int nx = p.nx, ny = p.ny;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
   double* __restrict__ R = d->R + (size_t)(n & d->rmask) * ns;
   float* __restrict__ r = d->r;
-  if (k == 0) {  // b = r^n + du^{n-1} is kept in place of r^n for the later iterations
+  if (k == 0 && !warm) {  // b = r^n + du^{n-1} is kept in place of r^n for the later iterations
     for (int y = y0; y < y1; ++y) {
       const unsigned i = (unsigned)y * nx + x;
       const double b = R[i] + (prev ? (double)prev[i] : 0.0);
       R[i] = b;
       X[i] = (XT)0;
       r[(size_t)y * d->ld + x] = (float)b;
+      bm = nanmax(bm, fabs(b));
+      rm = nanmax(rm, fabs(b));
     }
     return;
   }
+  // the iterate the residual is formed from: x, or x0 = du^{n-1} at a warm first iteration
+  // (read from du^{n-1}, which no thread writes here; x is set to it alongside)
+  const XT* __restrict__ Xr = (k == 0) ? prev : X;
   const double* __restrict__ Un = d->U + (size_t)n * ns;
   const double* bd = p.bdata ? p.bdata + (size_t)n * 2 * (p.nx + p.ny) : nullptr;
   double uS = node_value(p, Un, bd, x, y0 - 1), uP = Un[(unsigned)y0 * nx + x];
-  double xS = y0 > 0 ? (double)X[(unsigned)(y0 - 1) * nx + x] : 0.0, xP = (double)X[(unsigned)y0 * nx + x];
+  double xS = y0 > 0 ? (double)Xr[(unsigned)(y0 - 1) * nx + x] : 0.0, xP = (double)Xr[(unsigned)y0 * nx + x];
   for (int y = y0; y < y1; ++y) {
     const unsigned i = (unsigned)y * nx + x;
     const double uN = y + 1 < ny ? Un[i + nx] : node_value(p, Un, bd, x, y + 1);
-    const double xN = y + 1 < ny ? (double)X[i + nx] : 0.0;
+    const double xN = y + 1 < ny ? (double)Xr[i + nx] : 0.0;
     Nb u;
     u.P = uP;
     u.S = uS;
@@ -537,11 +547,19 @@ __device__ __forceinline__ void pc_resid_column(const PcDesc* d, const KProb& p,
     Row5 a;
     (void)eval_point<0, kFormNoConv>(p, u, x, y, a);  // these solves are for heat only (no convection)
     double ax = a.C * xP;
-    if (x > 0) ax += a.W * (double)X[i - 1];
-    if (x < nx - 1) ax += a.E * (double)X[i + 1];
+    if (x > 0) ax += a.W * (double)Xr[i - 1];
+    if (x < nx - 1) ax += a.E * (double)Xr[i + 1];
     if (y > 0) ax += a.S * xS;
     if (y < ny - 1) ax += a.N * xN;
-    r[(size_t)y * d->ld + x] = (float)(R[i] - ax);
+    double b = R[i];
+    if (k == 0) {  // warm first iteration
+      b += xP;
+      R[i] = b;
+      X[i] = Xr[i];
+      bm = nanmax(bm, fabs(b));
+      rm = nanmax(rm, fabs(b - ax));
+    }
+    r[(size_t)y * d->ld + x] = (float)(b - ax);
     uS = uP;
     uP = uN;
     xS = xP;
@@ -556,19 +574,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int2 it = items[wi];
   const PcDesc* d = ds + it.x;
   const int n = m - d->stage;
-  if (!d->active || n < 0 || n >= d->p.nt || k >= d->K[n]) return;
+  // iteration 0 runs before the lanes plan their iteration counts (pipelined) or with them
+  if (!d->active || n < 0 || n >= d->p.nt || (k > 0 && k >= d->K[n])) return;
   const KProb p = at_level(d->p, n);
   const int nx = p.nx, ny = p.ny, tilesx = (nx + 63) >> 6;
   const int x = (it.y % tilesx) * 64 + (threadIdx.x & 63);
   const int y0 = (it.y / tilesx) * kPcTileY + (threadIdx.x >> 6) * kPcRows, y1 = min(y0 + kPcRows, ny);
-  if (x >= nx || y0 >= ny) return;
   const unsigned ns = (unsigned)nx * (unsigned)ny;
-  if (d->dxf)
-    pc_resid_column<float>(d, p, n, k, x, y0, y1, d->dxf + (size_t)(n & 1) * ns,
-                           n > 0 ? d->dxf + (size_t)((n - 1) & 1) * ns : nullptr);
-  else
-    pc_resid_column<double>(d, p, n, k, x, y0, y1, d->dU + (size_t)(n & d->dmask) * ns,
-                            n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr);
+  double bm = 0.0, rm = 0.0;
+  if (x < nx && y0 < ny) {
+    if (d->dxf)
+      pc_resid_column<float>(d, p, n, k, x, y0, y1, d->dxf + (size_t)(n & 1) * ns,
+                             n > 0 ? d->dxf + (size_t)((n - 1) & 1) * ns : nullptr, n > 0, bm, rm);
+    else
+      pc_resid_column<double>(d, p, n, k, x, y0, y1, d->dU + (size_t)(n & d->dmask) * ns,
+                              n > 0 ? d->dU + (size_t)((n - 1) & d->dmask) * ns : nullptr, false, bm, rm);
+  }
+  if (k != 0 || !d->dxf) return;  // uniform over the work-group
+  // the first iteration of a pipelined lane: max |b| and max |b - A x0| of the level
+  __shared__ double red[2][4];
+  bm = wave_max(bm);
+  rm = wave_max(rm);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = bm;
+    red[1][threadIdx.x >> 6] = rm;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const double* q = red[threadIdx.x];
+    atomic_max_nonneg(d->stat + kStat * (size_t)n + 3 + threadIdx.x, nanmax(nanmax(q[0], q[1]), nanmax(q[2], q[3])));
+  }
 }
 
 // V-cycle launches of iteration k of level n. Items (lane, grid l, tile x, tile y) of the
@@ -732,7 +767,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   __syncthreads();
   if (threadIdx.x < 3) {
     const double* q = red[threadIdx.x];
-    atomic_max_nonneg(d->stat + 3 * (size_t)n + threadIdx.x, nanmax(nanmax(q[0], q[1]), nanmax(q[2], q[3])));
+    atomic_max_nonneg(d->stat + kStat * (size_t)n + threadIdx.x, nanmax(nanmax(q[0], q[1]), nanmax(q[2], q[3])));
   }
 }
 
@@ -748,8 +783,13 @@ __global__ __launch_bounds__(64) void k_pipe_cheb(const PcDesc* __restrict__ ds,
     kq[q] = 0;
     return;
   }
-  const double umax = __longlong_as_double((long long)d->stat[3 * (size_t)n]);
-  int K = mg_cheb_plan(d->p.mu_a, d->p.mu_b, umax, d->tgt, d->c + (size_t)n * kMaxCheb);
+  const unsigned long long* st = d->stat + kStat * (size_t)n;
+  const double umax = __longlong_as_double((long long)st[0]);
+  // the solve starts from x0 = du^{n-1} (k_pc_resid): it has to reduce |b - A x0| to tgt |b|
+  const double bmax = __longlong_as_double((long long)st[3]), r0 = __longlong_as_double((long long)st[4]);
+  double tgt = d->tgt;
+  if (r0 > 0.0 && bmax > 0.0) tgt = fmin(0.5, d->tgt * bmax / r0);
+  int K = mg_cheb_plan(d->p.mu_a, d->p.mu_b, umax, tgt, d->c + (size_t)n * kMaxCheb);
   K = K < d->kcap ? K : d->kcap;
   d->K[n] = K;
   kq[q] = K;
