@@ -50,16 +50,24 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
                     "// ------------------------------------------------------------ batched wavefront")]
 
 
-# HBM bytes per k_mg_up launch of the heat batch (pipelined Newton stages), the mean over the
-# dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
-# (profiles/k_mg_up_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
-# fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with.
-MG_TRAFFIC = {"kernel_sha256": "9c1400c011a27ef04efd4493a03fb8519d148b547beec13a0db0fd13cfc52e5d",
-              "fetch_bytes": 90944702, "write_bytes": 44341350}
+# Bytes past L2 per launch of the heat batch's multigrid kernels (pipelined Newton stages, six
+# per pass), the mean over the dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (profiles/mg_kernels_heatbatch64_mixed.md), each scaled by the counter's reading
+# for a 1 GiB fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken
+# with (the device headers and the multigrid section of the kernel file).
+MG_TRAFFIC = {"kernel_sha256": "307dbcfb008ca9e15275ea2fd25dd3ba25798521597813da4a43d0fed1d2d5d4",
+              "kernels": {"k_pc_resid": (296024537, 178059674), "k_mg_up": (73633134, 37238272),
+                          "k_mg_down": (21499692, 26217677)}}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
-MG_SECTIONS = [("struct PcDesc {", "// Chebyshev for a spectrum in [a, b]"),
-               ("// Chebyshev plan of a multigrid-preconditioned level solve", "// Work items (lane, tile of"),
-               ("// V-cycle launches of iteration k of level n.", "// One work-group per lane: the V-cycle's")]
+MG_SECTIONS = [("// ---------------------------------------- multigrid-preconditioned level solves",
+                "// ---------------------------------------------------------- wavefront schedule")]
+MG_LIMITER = {
+    "k_pc_resid": "latency: column sweeps with dependent FP64 loads and the Jacobian row formed per node; "
+                  "bytes past L2 1.36x the algorithmic bytes (partial cache lines of the float32 rows)",
+    "k_mg_up": "latency: dependent global loads and three LDS phases per tile at four work-groups per CU; "
+               "bytes past L2 match the algorithmic bytes",
+    "k_mg_down": "latency: four LDS phases per tile; bytes past L2 match the algorithmic bytes",
+}
 
 
 def kernel_sha256(headers=(KERNEL_HEADER,), sections=KERNEL_SECTIONS):
@@ -75,12 +83,13 @@ def kernel_sha256(headers=(KERNEL_HEADER,), sections=KERNEL_SECTIONS):
     return h.hexdigest()
 
 
-def mg_traffic():
-    """Counter-measured HBM bytes per k_mg_up launch of the heat batch, or None when the kernel
-    sources differ from the ones the counters were taken with."""
-    if MG_TRAFFIC["kernel_sha256"] != kernel_sha256(MG_HEADERS, MG_SECTIONS):
+def mg_traffic(kernel):
+    """Counter-measured bytes per launch of one of the heat batch's multigrid kernels, or None
+    when they were not taken for it or the kernel sources differ from the ones they were taken
+    with."""
+    if MG_TRAFFIC["kernel_sha256"] != kernel_sha256(MG_HEADERS, MG_SECTIONS) or kernel not in MG_TRAFFIC["kernels"]:
         return None
-    return MG_TRAFFIC["fetch_bytes"] + MG_TRAFFIC["write_bytes"]
+    return sum(MG_TRAFFIC["kernels"][kernel])
 
 
 def measured_traffic(plan):
@@ -579,10 +588,9 @@ def bench_heatbatch(args, extras=None):
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
         "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": mg_traffic() if names[j] == "k_mg_up" and pipelined else None,
+                     "traffic": mg_traffic(names[j]) if pipelined else None,
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl,
-                     "limiter": "latency: dependent global loads and three LDS phases per tile at four "
-                                "work-groups per CU; bytes past L2 match the algorithmic bytes"},
+                     "limiter": MG_LIMITER.get(names[j])},
         "kernel_split": split,
     }
     if errs:
