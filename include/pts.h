@@ -162,9 +162,10 @@ typedef struct pts_stats {
   double level_solve_bytes;
   /* filled by pts_solve_batched with pts_options.profile = 1 on batches whose levels take
      the multigrid-preconditioned solve (every instance's entry holds the batch totals):
-     per kernel [0] k_pc_resid, [1] k_mg_down, [2] k_mg_lds, [3] k_mg_up, [4] k_pc_update,
-     [5] k_residual, [6] k_update + k_reduce_sum, [7] other: summed time (ms) of the
-     launches, each bracketed by HIP events on `stream`, their number, and their
+     per kernel [0] k_pc_resid, [1] k_mg_down, [2] k_mg_lds, [3] k_mg_up, [4] unused;
+     bulk schedule: [5] k_residual, [6] k_update + k_reduce_sum, [7] k_level_absmax;
+     pipelined schedule: [5] k_pipe_residual, [6] k_pipe_update, [7] k_pipe_cheb: summed time (ms)
+     of the launches, each bracketed by HIP events on `stream`, their number, and their
      algorithmic bytes (the reads and writes the operation needs, once each)          */
   double kern_ms[8];
   int32_t kern_count[8];

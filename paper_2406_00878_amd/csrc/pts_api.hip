@@ -2071,18 +2071,19 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     // kk > 0 reads b, u^n (8 each), x and writes r (4); k_mg_down reads f_l, writes x_l
     // and f_{l+1} (a quarter node); k_mg_lds reads f_G, writes x_G; k_mg_up reads x_l, f_l,
     // x_{l+1} and writes e_l, on the finest grid instead the Chebyshev step's reads and writes
-    // of d (4 each) and du^n
-    // (the pipelined lanes hold x and du in float32: xb = 4 bytes per node, else 8)
+    // of d (4 each) and du^n; where k_mg_lds holds the whole V-cycle (G = 0) it reads r and takes
+    // that step (the pipelined lanes hold x and du in float32: xb = 4 bytes per node, else 8)
     auto kb = [&](int kind, int i, int kk, int g, double xb) {
       const MgDesc& m = h_mg[(size_t)i * kLanes];
       const double N2 = (double)probs[i].nx * probs[i].nx;
       const int l = g - (gmax - m.G);
+      const double step = 8.0 + 2.0 * xb;  // the Chebyshev step, per node
       switch (kind) {
         case 0: return N2 * (kk == 0 ? 20.0 + 2.0 * xb : 20.0 + xb);
         case 1: return l >= 0 ? (double)m.n[l] * m.n[l] * 8.0 + (double)m.n[l + 1] * m.n[l + 1] * 4.0 : 0.0;
-        case 2: return (double)m.n[m.G] * m.n[m.G] * 8.0;
+        case 2: return m.G == 0 ? N2 * (4.0 + step) : (double)m.n[m.G] * m.n[m.G] * 8.0;
         case 3:
-          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 16.0 + 2.0 * xb : 12.0) +
+          return l >= 0 ? (double)m.n[l] * m.n[l] * (l == 0 ? 8.0 + step : 12.0) +
                               (double)m.n[l + 1] * m.n[l + 1] * 4.0
                         : 0.0;
         default: return N2 * (kk == 0 ? 8.0 + 2.0 * xb : 12.0 + 2.0 * xb);
