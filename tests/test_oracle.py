@@ -321,8 +321,75 @@ def test_coarse_problem_sizes_and_injection():
     qc = coarse.coarse_problem(q, 4)
     assert (qc.nx, qc.nt) == (8, 2)
     np.testing.assert_array_equal(qc.x_nodes(), q.x_nodes()[::4])
+    # grids and levels that cf does not divide: the same domain with floor(32 / 3) = 10 nodes,
+    # ceil(8 / 3) = 3 levels of step 3 tau
+    q3 = coarse.coarse_problem(q, 3)
+    assert (q3.nx, q3.ny, q3.nt) == (10, 10, 3) and q3.dt == 3 * q.dt
+    assert abs(q3.nx * q3.hx - 1.0) < 1e-15
+    p5 = coarse.coarse_problem(p, 5)  # 32 / 5: 5 interior nodes spaced 1 / 6
+    assert (p5.nx, p5.nt) == (5, 3) and abs(p5.hx - 1.0 / 6.0) < 1e-15
+    with pytest.raises(ValueError):  # Dirichlet data need nesting grids
+        coarse.coarse_problem(dataclasses.replace(p, bdata=np.zeros((12, 4 * 31))), 5)
     with pytest.raises(ValueError):
-        coarse.coarse_problem(q, 3)
+        coarse.coarse_problem(q, 11)  # fewer than 3 coarse nodes
+
+
+@pytest.mark.parametrize("bc,n", [("dirichlet", 50), ("periodic", 45)])
+def test_coarse_sample_is_bilinear_and_injects_on_nesting_grids(bc, n):
+    """u^0 on coarse nodes that are no fine nodes: the bilinear interpolant, exact for fields
+    a + b x + c y + d x y (periodic: on the nodes whose interval does not wrap); on grids that
+    nest, the fine values themselves."""
+    from oracle import coarse
+    f = lambda x, y: 0.3 + 1.7 * x - 0.6 * y + 2.2 * x * y
+    p = _field_problem(bc, n, 8)
+    p = dataclasses.replace(p, u0=_sample(p, lambda x, y, t: f(x, y), 0.0))
+    pc = coarse.coarse_problem(p, 4)
+    Xc, Yc = pc.mesh()
+    inner = Xc < (n - 1) * p.hx + 1e-12  # periodic: no wrap into x = 1
+    inner &= Yc < (n - 1) * p.hy + 1e-12
+    np.testing.assert_allclose(pc.u0[inner], f(Xc, Yc)[inner], rtol=0, atol=1e-14)
+    m = 4 * (n // 4) - (1 if bc == "dirichlet" else 0)  # a grid that nests
+    q = _field_problem(bc, m, 8)
+    q = dataclasses.replace(q, u0=np.random.default_rng(1).standard_normal((m, m)))
+    qc = coarse.coarse_problem(q, 4)
+    sl = slice(None, None, 4) if bc == "periodic" else slice(3, None, 4)
+    np.testing.assert_array_equal(qc.u0, q.u0[sl, sl][:qc.ny, :qc.nx])
+
+
+def test_coarse_interpolation_on_grids_that_do_not_nest_reproduces_cubics():
+    """Dirichlet grid 50^2 and 10 levels with cf = 4 (11 coarse nodes spaced 51 h / 12, three
+    coarse levels reaching 12 tau): the field g(t) x(1-x)(1+x) y(1-y)(2-y), cubic in x, y and t
+    and zero on the boundary, is recovered at every fine node and level (the coarse spacing,
+    the edges, the t = 0 node and the coarse level past the end all enter)."""
+    from oracle import coarse
+    g = lambda t: 1.0 + 3.0 * t - 40.0 * t * t + 500.0 * t ** 3
+    f = lambda x, y, t: g(t) * x * (1 - x) * (1 + x) * y * (1 - y) * (2 - y)
+    p = _field_problem("dirichlet", 50, 10, dt=1e-2)
+    p = dataclasses.replace(p, u0=_sample(p, f, 0.0))
+    pc = coarse.coarse_problem(p, 4)
+    assert (pc.nx, pc.nt) == (11, 3)
+    Uc = np.stack([_sample(pc, f, (m + 1) * pc.dt) for m in range(pc.nt)])
+    U = coarse.interpolate(p, 4, Uc)
+    exact = np.stack([_sample(p, f, (k + 1) * p.dt) for k in range(p.nt)])
+    np.testing.assert_allclose(U, exact, rtol=0, atol=1e-13)
+
+
+def test_periodic_interpolation_on_grids_that_do_not_nest_is_fourth_order():
+    """Periodic grids 45^2 and 90^2 with cf = 4 (11 and 22 coarse nodes): the spline error of a
+    smooth field falls about 16-fold per halving of the coarse spacing (a misplaced coarse node
+    would leave an O(h) error)."""
+    from oracle import coarse
+    f = lambda x, y, t: (1.0 + t) * np.sin(2 * np.pi * x + 0.3) * np.cos(2 * np.pi * y) + 0.2
+    errs = []
+    for n in (45, 90):
+        p = _field_problem("periodic", n, 6)
+        p = dataclasses.replace(p, u0=_sample(p, f, 0.0))
+        pc = coarse.coarse_problem(p, 4)
+        Uc = np.stack([_sample(pc, f, (m + 1) * pc.dt) for m in range(pc.nt)])
+        U = coarse.interpolate(p, 4, Uc)
+        exact = np.stack([_sample(p, f, (k + 1) * p.dt) for k in range(p.nt)])
+        errs.append(np.max(np.abs(U - exact)))
+    assert errs[0] / errs[1] > 12.0, errs
 
 
 def test_coarse_initial_iterate_is_close_to_the_solution():
