@@ -347,19 +347,23 @@ int pts_autotune_batched(const pts_problem* probs, int nprob, double* const* U,
 /* Section 4: the paper's initial iterate. The problem is solved on a grid coarsened
    by cf in each spatial direction and in time, and the coarse solution is carried to
    the fine space-time grid by 1-D cubic splines.
-   Coarse grid: node k is fine node k cf (periodic) or fine interior node (k+1) cf - 1
-   (Dirichlet: the domain edges stay), step cf dt, u0 and the Dirichlet data by
-   injection (coarse level m takes fine level m cf); solved in FP64 by the all-at-once
-   Newton iteration of pts_solve from its plain iterate (by Theorem 1 the root is the
-   sequential coarse solution) to max|R| <= tol within max_iter steps.
+   Coarse grid: where cf divides nx (periodic) or nx + 1 (Dirichlet; likewise ny),
+   node k is fine node k cf (periodic) or fine interior node (k+1) cf - 1 (Dirichlet:
+   the domain edges stay); otherwise the coarse grid spans the same domain with nx / cf
+   (periodic) or (nx + 1) / cf - 1 (Dirichlet) evenly spaced nodes. ceil(nt / cf)
+   coarse levels of step cf dt (coarse level m at t = m cf dt; the last may lie past the
+   fine end time). u0 at a coarse node: the bilinear interpolant of the fine u0 (the
+   fine value where the node is a fine node); Dirichlet data by injection (coarse level
+   m takes fine level m cf; these need cf to divide nx + 1, ny + 1 and nt). Solved in
+   FP64 by the all-at-once Newton iteration from its plain iterate (by Theorem 1 the
+   root is the sequential coarse solution) to max|R| <= tol within max_iter steps.
    Splines: along x, then y (periodic lines closed with the period; Dirichlet lines
    through the edge values, coarse west/east data for x lines and fine south/north
    data for y lines, not-a-knot end conditions), then along t through u0 (t = 0) and
-   the coarse levels (t = m cf dt), not-a-knot end conditions, evaluated at every fine
-   node and level.
-   Requirements: cf >= 2 divides nt, and nx and ny leaving >= 3 coarse nodes
-   (periodic) or nx + 1 and ny + 1 (Dirichlet; bdata NULL for zero data); otherwise
-   PTS_ERR_INVALID_ARG (pts_coarse_workspace_bytes then returns 0).
+   the coarse levels, not-a-knot end conditions, evaluated at every fine node and level.
+   Requirements: cf >= 2 leaving >= 3 coarse nodes per periodic axis or >= 1 per
+   Dirichlet axis, uniform steps (dt_levels NULL); otherwise PTS_ERR_INVALID_ARG
+   (pts_coarse_workspace_bytes then returns 0).
    u0: device [ny][nx]; U: device [nt][ny][nx], written; workspace: device, 256-byte
    aligned, pts_coarse_workspace_bytes(p, cf) bytes; stats (host, may be NULL): the
    coarse solve's statistics. An error of the coarse solve is returned as it is (U is
@@ -369,14 +373,15 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
                                double tol, int max_iter, void* workspace,
                                size_t workspace_bytes, pts_stats* stats, pts_stream_t stream);
 
-/* The coarse-grid start of nprob instances of the problem p (one description; the
-   instances differ in u0[i] and receive U[i], device arrays): the coarse problems
-   share batched wavefront launches (pts_solve_batched) and the interpolation weights.
-   workspace: pts_coarse_workspace_bytes_batched(p, cf, nprob) bytes, 256-byte aligned;
-   stats: host array of nprob entries or NULL. Errors as pts_coarse_initial_iterate (an
-   instance's coarse solve error is returned as pts_solve_batched returns it). */
-size_t pts_coarse_workspace_bytes_batched(const pts_problem* p, int cf, int nprob);
-int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf,
+/* The coarse-grid start of nprob instances, instance i described by probs[i] (grids
+   and level counts may differ; kind and boundary kind are shared), with u0[i] and
+   U[i] device arrays: the coarse problems share batched launches (pts_solve_batched),
+   then each instance's splines run. workspace: pts_coarse_workspace_bytes_batched(probs,
+   nprob, cf) bytes, 256-byte aligned; stats: host array of nprob entries or NULL.
+   Errors as pts_coarse_initial_iterate (an instance's coarse solve error is returned as
+   pts_solve_batched returns it). */
+size_t pts_coarse_workspace_bytes_batched(const pts_problem* probs, int nprob, int cf);
+int pts_coarse_initial_iterate_batched(const pts_problem* probs, int nprob, int cf,
                                        const double* const* u0, double* const* U, double tol,
                                        int max_iter, void* workspace, size_t workspace_bytes,
                                        pts_stats* stats, pts_stream_t stream);

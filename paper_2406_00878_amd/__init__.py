@@ -369,10 +369,23 @@ def coarse_initial_iterate(prob, U, u0, cf, tol=1e-12, max_iter=50, ws=None, bda
     return _stats_dict(st)
 
 
+def _coarse_problems(prob, n, bdata):
+    """pts_problem array of n instances: one problem for all, or a list of n problems."""
+    probs = list(prob) if isinstance(prob, (list, tuple)) else [prob] * n
+    if len(probs) != n:
+        raise ValueError(f"{len(probs)} problems for {n} instances")
+    bdatas = list(bdata) if isinstance(bdata, (list, tuple)) else [bdata] * n
+    structs = [make_problem(q, "fp64", b) for q, b in zip(probs, bdatas)]
+    arr = (pts_problem * n)(*structs)
+    arr._keep = structs
+    return probs, arr
+
+
 def coarse_workspace_batched(prob, cf, n, device="cuda") -> torch.Tensor:
-    """Device workspace of coarse_initial_iterate_batched for n instances of `prob`."""
-    p = make_problem(prob)
-    nbytes = _lib_checked().pts_coarse_workspace_bytes_batched(C.byref(p), int(cf), int(n))
+    """Device workspace of coarse_initial_iterate_batched for n instances of `prob` (one
+    problem, or a list of n problems)."""
+    _, arr = _coarse_problems(prob, n, None)
+    nbytes = _lib_checked().pts_coarse_workspace_bytes_batched(arr, int(n), int(cf))
     if nbytes == 0:
         _check(_lib.PTS_ERR_INVALID_ARG)
     return _aligned_bytes(nbytes, device)
@@ -380,20 +393,21 @@ def coarse_workspace_batched(prob, cf, n, device="cuda") -> torch.Tensor:
 
 def coarse_initial_iterate_batched(prob, Us, u0s, cf, tol=1e-12, max_iter=50, bdata=None, ws=None,
                                    stream=None) -> list:
-    """The coarse-grid start of several instances of one problem (different u^0): the coarse
-    solves share batched launches. Returns the coarse solves' statistics. ws: a
-    coarse_workspace_batched (allocated per call when None)."""
+    """The coarse-grid start of several instances (prob: one problem for all, or one per
+    instance; grids and level counts may differ): the coarse solves share batched launches.
+    Returns the coarse solves' statistics. ws: a coarse_workspace_batched (allocated per call
+    when None). bdata: one array for all, or a list."""
     n = len(Us)
-    p = make_problem(prob, "fp64", bdata)
-    for U, u0 in zip(Us, u0s):
-        _dev_f64(U, (p.nt, p.ny, p.nx), "U")
-        _dev_f64(u0, (p.ny, p.nx), "u0")
+    probs, arr = _coarse_problems(prob, n, bdata)
+    for q, U, u0 in zip(probs, Us, u0s):
+        _dev_f64(U, (q.nt, q.ny, q.nx), "U")
+        _dev_f64(u0, (q.ny, q.nx), "u0")
     lib = _lib_checked()
-    ws = coarse_workspace_batched(prob, cf, n, Us[0].device) if ws is None else ws
+    ws = coarse_workspace_batched(probs, cf, n, Us[0].device) if ws is None else ws
     uptr = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
     u0ptr = (C.c_void_p * n)(*[u.data_ptr() for u in u0s])
     sts = (pts_stats * n)()
-    _check(lib.pts_coarse_initial_iterate_batched(C.byref(p), n, int(cf), u0ptr, uptr, float(tol), int(max_iter),
+    _check(lib.pts_coarse_initial_iterate_batched(arr, n, int(cf), u0ptr, uptr, float(tol), int(max_iter),
                                                   _ptr(ws), ws.numel(), sts, _stream(stream)))
     return [_stats_dict(s) for s in sts]
 

@@ -1769,18 +1769,19 @@ int host_stage(size_t bytes, char** out) {
   return PTS_OK;
 }
 
-// Newton stages a pipelined pass of a multigrid batch needed the last time the same batch
-// (instances' kinds, sizes, coefficients, precision) was solved to the same tolerance from
-// its first pass: the next solve runs that many stages per pass.
+// Newton steps each instance of a pipelined multigrid batch needed the last time the same batch
+// (instances' kinds, sizes, coefficients, precision; the caller's cache tag) was solved to the
+// same tolerance: the next solve gives each instance that many stages.
 struct PassCache {
-  std::vector<std::pair<unsigned long long, int>> v;
-  static unsigned long long key(const pts_problem* probs, int nprob, double tol) {
+  std::vector<std::pair<unsigned long long, std::vector<int>>> v;  // per instance: Newton steps
+  static unsigned long long key(const pts_problem* probs, int nprob, double tol, int tag) {
     unsigned long long h = 1469598103934665603ull;  // FNV-1a over the fields that fix the work
     auto mix = [&](const void* p, size_t n) {
       for (size_t i = 0; i < n; ++i) h = (h ^ ((const unsigned char*)p)[i]) * 1099511628211ull;
     };
     mix(&nprob, sizeof nprob);
     mix(&tol, sizeof tol);
+    mix(&tag, sizeof tag);  // the caller's tag: starts of another kind need other step counts
     for (int i = 0; i < nprob; ++i) {
       const pts_problem& q = probs[i];
       const int iv[6] = {q.kind, q.bc, q.nx, q.ny, q.nt, q.precision};
@@ -1790,19 +1791,19 @@ struct PassCache {
     }
     return h;
   }
-  int get(unsigned long long k) const {
+  const std::vector<int>* get(unsigned long long k) const {
     for (auto& e : v)
-      if (e.first == k) return e.second;
-    return 0;
+      if (e.first == k) return &e.second;
+    return nullptr;
   }
-  void put(unsigned long long k, int stages) {
+  void put(unsigned long long k, const std::vector<int>& steps) {
     for (auto& e : v)
       if (e.first == k) {
-        e.second = stages;
+        e.second = steps;
         return;
       }
     if (v.size() > 64) v.clear();
-    v.push_back({k, stages});
+    v.push_back({k, steps});
   }
 };
 thread_local PassCache g_pass_cache;
@@ -1981,44 +1982,60 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
   };
   const double lin_tol = (o && o->lin_tol > 0) ? o->lin_tol : 1e-3;
   const bool pipelined = o == nullptr || o->schedule != PTS_SCHED_BULK;
-  const unsigned long long skey = PassCache::key(probs, nprob, tol);
-  const int cached = g_pass_cache.get(skey);
-  // stages per pass: asked for; else from the Newton steps this batch needed last time, split
-  // into as few passes of at most kLanes - 1 stages as possible; else kLanes - 1
-  const int npass_c = cached > 0 ? (cached + kLanes - 2) / (kLanes - 1) : 1;
-  const int nstages = std::min(kLanes - 1, (o && o->stages > 0) ? o->stages
-                                           : (cached > 0 ? (cached + npass_c - 1) / npass_c : kLanes - 1));
+  const unsigned long long skey = PassCache::key(probs, nprob, tol, ctag(o));
+  const std::vector<int>* cached = g_pass_cache.get(skey);
+  // stages per pass of instance i: asked for; else from the Newton steps it needed last time,
+  // split into as many passes as the instance that needed the most takes (at most kLanes - 1
+  // stages each); else kLanes - 1
+  int cmax = 0;
+  if (cached)
+    for (int c : *cached) cmax = std::max(cmax, c);
+  const int npass_c = cmax > 0 ? (cmax + kLanes - 2) / (kLanes - 1) : 1;
+  std::vector<int> nstages(nprob, kLanes - 1);
+  for (int i = 0; i < nprob; ++i) {
+    if (o && o->stages > 0)
+      nstages[i] = std::min(kLanes - 1, o->stages);
+    else if (cmax > 0)
+      nstages[i] = std::min(kLanes - 1, std::max(1, ((*cached)[i] + npass_c - 1) / npass_c));
+  }
   std::vector<int> conv_it(nprob, -1);  // Newton step at which each instance met tol (pipelined)
+  std::vector<int> done(nprob, 0);      // Newton steps applied to each instance
+  bool was_pass = false;                // the last step was a pipelined pass (done[] advanced)
   for (int it = 0;; ++it) {
+    if (it > 0 && !was_pass)
+      for (int i = 0; i < nprob; ++i)
+        if (active[i]) ++done[i];
+    was_pass = false;
     int nactive = 0;
     for (int i = 0; i < nprob; ++i) {
       if (!active[i]) continue;
       const pts_problem* p = probs + i;
       const double res = h_sc[4 * i], rhom = h_sc[4 * i + 1];
       pts_stats* st = stats ? stats + i : nullptr;
+      const int ki = done[i];
       if (st) {
-        if (it < PTS_MAX_HIST) {
-          st->res_inf[it] = res;
-          st->rho_max[it] = rhom;
-          if (it > 0) st->upd_rms[it] = std::sqrt(h_sc[4 * i + 2] / ((double)p->nx * p->ny * p->nt));
+        if (ki < PTS_MAX_HIST) {
+          st->res_inf[ki] = res;
+          st->rho_max[ki] = rhom;
+          if (ki > 0) st->upd_rms[ki] = std::sqrt(h_sc[4 * i + 2] / ((double)p->nx * p->ny * p->nt));
         }
-        st->iterations = it;
-        st->hist = std::min(it + 1, PTS_MAX_HIST);
+        st->iterations = ki;
+        st->hist = std::min(ki + 1, PTS_MAX_HIST);
         st->slab = p->nt;
         st->window = 1;
         st->schedule = use_mg && pipelined ? PTS_SCHED_PIPELINE : PTS_SCHED_BULK;
       }
       int err = PTS_OK;
       if (!std::isfinite(res) || !std::isfinite(rhom)) {
-        err = fail(PTS_ERR_NONFINITE, "instance %d: non-finite residual at Newton step %d", i, it);
+        err = fail(PTS_ERR_NONFINITE, "instance %d: non-finite residual at Newton step %d", i, ki);
       } else if (res <= tol) {
         if (st) st->converged = 1;
         active[i] = 0;
         continue;
       } else if (rhom >= 1.0) {
         err = fail(PTS_ERR_NOT_DOMINANT, "instance %d: block not diagonally dominant (radius %.3g)", i, rhom);
-      } else if (it >= max_iter) {
-        err = fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i, it,
+      } else if (ki >= max_iter) {
+        err = fail(PTS_ERR_NOT_CONVERGED, "instance %d: not converged after %d Newton steps (|R| = %.3e)", i, ki,
                    res);
       }
       if (err) {
@@ -2169,18 +2186,23 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       return PTS_OK;
     };
     if (use_mg && pipelined) {
-      // nstages Newton steps in one pass over the diagonals D = n + s (k_pipe_* kernels): lanes
-      // (i, s), s = 0..S, ordered by nt_i + s, longest first; lane (i, s) has a level at D while
-      // D < nt_i + s, so the lanes of a diagonal are a prefix of the order (lanes with D < s
-      // return at once)
-      const int S = std::min(nstages, std::max(1, max_iter - it));  // no more steps than max_iter allows
+      // S_i Newton steps of instance i in one pass over the diagonals D = n + s (k_pipe_* kernels):
+      // lanes (i, s), s = 0..S_i, ordered by nt_i + s, longest first; lane (i, s) has a level at
+      // D while D < nt_i + s, so the lanes of a diagonal are a prefix of the order (lanes with
+      // D < s return at once)
+      std::vector<int> Si(nprob, 0);
+      int S = 0;
+      for (int i : order) {
+        Si[i] = std::min(nstages[i], std::max(1, max_iter - done[i]));  // no more steps than max_iter allows
+        S = std::max(S, Si[i]);
+      }
       std::vector<int> all, solving;
       for (int i : order)
-        for (int sg = 0; sg <= S; ++sg) all.push_back(i * kLanes + sg);
+        for (int sg = 0; sg <= Si[i]; ++sg) all.push_back(i * kLanes + sg);
       auto key = [&](int ln) { return probs[ln / kLanes].nt + ln % kLanes; };
       std::stable_sort(all.begin(), all.end(), [&](int a, int b) { return key(a) > key(b); });
       for (int ln : all)
-        if (ln % kLanes < S) solving.push_back(ln);
+        if (ln % kLanes < Si[ln / kLanes]) solving.push_back(ln);
       // each lane plans its level's iterations from that level's max |u| (k_pipe_cheb); the
       // host reads the plans back and launches the most any lane needs. A lane's plan is
       // capped at the plan for twice the largest level maximum of the iterate the pass starts
@@ -2196,16 +2218,16 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         for (int ln = 0; ln < kLanes; ++ln) {
           const size_t q = (size_t)i * kLanes + ln;
           PcDesc d = lane_desc(i, ln);
-          d.active = active[i] && ln <= S;
+          d.active = active[i] && ln <= Si[i];
           d.stage = ln;
           d.rmask = 0;
           d.dmask = 1;
-          d.last = ln == S;
+          d.last = ln == Si[i];
           d.R = (double*)(mg_base + DL.R[q]);
           d.dU = nullptr;
           d.dxf = (float*)(mg_base + DL.ring[q]);
           d.park_out = ln >= 1 ? (double*)(mg_base + DL.park[q - 1]) : nullptr;
-          d.park_in = ln < S ? (const double*)(mg_base + DL.park[q]) : nullptr;
+          d.park_in = ln < Si[i] ? (const double*)(mg_base + DL.park[q]) : nullptr;
           d.dprev = ln >= 1 ? (const float*)(mg_base + DL.ring[q - 1]) : nullptr;
           d.tgt = lin_tol;
           d.kcap = kcap;
@@ -2247,7 +2269,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
             const int ln = all[q], sg = ln % kLanes;
             if (lane_level(ln, D) < 0) continue;
             const double N2 = (double)probs[ln / kLanes].nx * probs[ln / kLanes].nx;
-            b5 += N2 * (sg == S ? 16.0 : 24.0);  // reads u^n, u^{n-1}; writes r
+            b5 += N2 * (sg == Si[ln / kLanes] ? 16.0 : 24.0);  // reads u^n, u^{n-1}; writes r
             if (sg >= 1) b6 += N2 * 28.0;        // reads u^n, du (float32); writes the park and u^n
           }
         pb(6);
@@ -2289,7 +2311,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           });
       }
       HIPCHK(hipGetLastError());
-      // the result: max |R| of U^(S) (lane S), the largest radius and any NaN of every lane
+      // the result: max |R| of U^(S_i) (lane S_i), the largest radius and any NaN of every lane
       std::vector<unsigned long long> hst(DL.stat_words);
       HIPCHK(hipMemcpyAsync(hst.data(), stat, DL.stat_words * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -2304,7 +2326,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         const unsigned long long* st = hst.data() + DL.lstat[i];
         const int nt = probs[i].nt;
         int first = -1;
-        for (int sg = 0; sg <= S && first < 0; ++sg) {
+        for (int sg = 0; sg <= Si[i] && first < 0; ++sg) {
           unsigned long long r = 0;
           for (int n = 0; n < nt; ++n) r = std::max(r, st[((size_t)sg * nt + n) * kStat + 1]);
           if (val(r) <= tol) first = sg;
@@ -2312,13 +2334,13 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         if (first < 0)
           all_met = false;
         else
-          conv_it[i] = it + first;
+          conv_it[i] = done[i] + first;
       }
-      // all instances met tol: keep the Newton steps the batch needed (from the first iterate)
+      // all instances met tol: keep the Newton steps each instance needed (from its first iterate)
       if (all_met && !(o && o->stages > 0)) {
-        int need = 0;
-        for (int i = 0; i < nprob; ++i) need = std::max(need, conv_it[i]);
-        if (need >= 1) g_pass_cache.put(skey, need);
+        bool ok = true;
+        for (int i = 0; i < nprob; ++i) ok = ok && conv_it[i] >= 0;
+        if (ok) g_pass_cache.put(skey, conv_it);
       }
       for (int i : order) {
         const unsigned long long* st = hst.data() + DL.lstat[i];
@@ -2327,12 +2349,12 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         constexpr unsigned long long kInf = 0x7ff0000000000000ull;
         unsigned long long res = 0, rho = 0;
         bool finite = true;
-        for (int sg = 0; sg <= S; ++sg)
+        for (int sg = 0; sg <= Si[i]; ++sg)
           for (int n = 0; n < nt; ++n) {
             const unsigned long long* q = st + ((size_t)sg * nt + n) * kStat;
             finite = finite && q[0] < kInf && q[1] < kInf && q[2] < kInf;
             rho = std::max(rho, q[2]);
-            if (sg == S) {
+            if (sg == Si[i]) {
               res = std::max(res, q[1]);
               h_lm[ofs_nt[i] + n] = val(q[0]);
             }
@@ -2346,20 +2368,22 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           stats[i].schedule = PTS_SCHED_PIPELINE;
           stats[i].sweeps = kmax_all;
           stats[i].refine = 0;
-          for (int sg = 1; sg < S && it + sg < PTS_MAX_HIST; ++sg) {
+          for (int sg = 1; sg < Si[i] && done[i] + sg < PTS_MAX_HIST; ++sg) {
             unsigned long long r = 0, g = 0;
             for (int n = 0; n < nt; ++n) {
               const unsigned long long* q = st + ((size_t)sg * nt + n) * kStat;
               r = std::max(r, q[1]);
               g = std::max(g, q[2]);
             }
-            stats[i].res_inf[it + sg] = val(r);
-            stats[i].rho_max[it + sg] = val(g);
-            stats[i].upd_rms[it + sg] = std::nan("");
+            stats[i].res_inf[done[i] + sg] = val(r);
+            stats[i].rho_max[done[i] + sg] = val(g);
+            stats[i].upd_rms[done[i] + sg] = std::nan("");
           }
         }
+        done[i] += Si[i];
       }
       if (prof) prof->collect(&pstat);
+      was_pass = true;
       it += S - 1;
       continue;
     }
@@ -2914,12 +2938,14 @@ AxisSpline axis_spline(int N, bool periodic, const std::vector<double>& s) {
   return A;
 }
 
-// The spline of a spatial axis with n fine and nc coarse nodes: periodic (nodes = the coarse
-// nodes, fine node i at i / cf), or Dirichlet (nodes: edge, the coarse nodes, edge; fine node i
-// at (i + 1) / cf).
-AxisSpline space_spline(bool periodic, int n, int nc, int cf) {
+// The spline of a spatial axis with n fine and nc coarse nodes spanning the same domain:
+// periodic (nodes = the coarse nodes, fine node i at i nc / n coarse spacings; i / cf where the
+// grids nest), or Dirichlet (nodes: edge, the coarse nodes, edge; fine node i at
+// (i + 1)(nc + 1) / (n + 1); (i + 1) / cf where they nest).
+AxisSpline space_spline(bool periodic, int n, int nc) {
   std::vector<double> s(n);
-  for (int i = 0; i < n; ++i) s[i] = periodic ? (double)i / cf : (double)(i + 1) / cf;
+  for (int i = 0; i < n; ++i)
+    s[i] = periodic ? (double)((long)i * nc) / n : (double)((long)(i + 1) * (nc + 1)) / (n + 1);
   return axis_spline(periodic ? nc : nc + 2, periodic, s);
 }
 
@@ -2958,44 +2984,61 @@ void axis_dev_fill(const AxisSpline& A, bool edges, const AxisDev& D, char* host
   std::memcpy(host + D.zz, A.zz.data(), A.zz.size() * 4);
 }
 
-// The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve).
+// The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve). Where cf divides
+// the grid (nx for periodic, nx + 1 for Dirichlet axes) the coarse nodes are every cf-th fine
+// node; otherwise the coarse grid spans the same domain with nx / cf (periodic) or
+// (nx + 1) / cf - 1 (Dirichlet) evenly spaced nodes. ceil(nt / cf) coarse levels of step
+// cf dt (the last may end past the fine end time). Dirichlet data need nesting grids and levels.
 int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
-  if (cf < 2 || p->nt % cf) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must be >= 2 and divide nt");
+  if (cf < 2) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must be >= 2");
   if (p->dt_levels) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: uniform steps only (dt_levels is set)");
   *pc = *p;
-  if (p->bc == PTS_PERIODIC) {
-    if (p->nx % cf || p->ny % cf || p->nx / cf < 3 || p->ny / cf < 3)
-      return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must divide nx and ny, leaving >= 3 nodes");
-    pc->nx = p->nx / cf;
-    pc->ny = p->ny / cf;
-  } else {
-    if ((p->nx + 1) % cf || (p->ny + 1) % cf || (p->nx + 1) / cf < 2 || (p->ny + 1) / cf < 2)
-      return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf must divide nx + 1 and ny + 1");
-    pc->nx = (p->nx + 1) / cf - 1;
-    pc->ny = (p->ny + 1) / cf - 1;
-  }
-  pc->nt = p->nt / cf;
-  pc->hx = cf * p->hx;
-  pc->hy = cf * p->hy;
+  const bool per = p->bc == PTS_PERIODIC;
+  auto axis = [&](int n, double h, int* nc, double* hc) -> bool {  // false: no coarse grid
+    if (per) {
+      *nc = n / cf;
+      *hc = n % cf == 0 ? cf * h : n * h / *nc;
+      return *nc >= 3;
+    }
+    *nc = (n + 1) / cf - 1;
+    *hc = (n + 1) % cf == 0 ? cf * h : (n + 1) * h / (*nc + 1);
+    return *nc >= 1;
+  };
+  if (!axis(p->nx, p->hx, &pc->nx, &pc->hx) || !axis(p->ny, p->hy, &pc->ny, &pc->hy))
+    return fail(PTS_ERR_INVALID_ARG, "coarse iterate: cf leaves fewer than %s coarse nodes", per ? "3" : "1");
+  const bool nested = p->nt % cf == 0 && (per ? p->nx % cf == 0 && p->ny % cf == 0
+                                              : (p->nx + 1) % cf == 0 && (p->ny + 1) % cf == 0);
+  if (p->bdata && !nested)
+    return fail(PTS_ERR_INVALID_ARG, "coarse iterate: Dirichlet data need cf to divide nx + 1, ny + 1 and nt");
+  pc->nt = (p->nt + cf - 1) / cf;
   pc->dt = cf * p->dt;
   pc->bdata = nullptr;
   pc->precision = PTS_FP64;
   return validate(pc);
 }
 
-// Workspace of the coarse start of nprob instances of one problem: the coarse solve's (one
-// instance: pts_solve's; several: pts_solve_batched's), each instance's coarse iterate and
-// u^0, and the interpolation buffers and weights the instances share (used one after another).
-struct CoarseLayout {
-  size_t solver, Uc, u0c, T1, V, Mx, My, Mt, Sx, Sy, St, Th, bdc, edges, total;
+// Workspace of the coarse start of nprob instances (each its own problem): the coarse solve's
+// (one instance: pts_solve's; several: pts_solve_batched's), per instance the coarse iterate,
+// u^0, Dirichlet data and spline tables, and the interpolation buffers the instances share
+// (used one after another in stream order, sized for the largest).
+struct CoarseInst {
+  pts_problem pc;
+  size_t Uc, u0c, Sx, Sy, St, Th, bdc, edges;
   AxisDev dx, dy, dt;
 };
-size_t coarse_solver_bytes(const pts_problem* pc, int nprob) {
-  if (nprob == 1) return layout(pc).total;
-  const std::vector<pts_problem> pcs(nprob, *pc);
-  return batch_header_bytes(pcs.data(), nprob) + (size_t)nprob * layout(pc).total;
+struct CoarseLayout {
+  size_t solver, tab, tab_end, T1, V, Mx, My, Mt, total;  // [tab, tab_end): every spline table
+  std::vector<CoarseInst> in;
+};
+size_t coarse_solver_bytes(const std::vector<pts_problem>& pcs) {
+  const int n = (int)pcs.size();
+  if (n == 1) return layout(&pcs[0]).total;
+  size_t t = batch_header_bytes(pcs.data(), n);
+  for (const pts_problem& q : pcs) t += layout(&q).total;
+  return t;
 }
-CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc, int nprob = 1) {
+// rc: PTS_OK or the error of an instance's coarse problem
+CoarseLayout coarse_layout(const pts_problem* p, int nprob, int cf, int* rc) {
   CoarseLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -3003,26 +3046,56 @@ CoarseLayout coarse_layout(const pts_problem* p, const pts_problem* pc, int npro
     o = align_up(o + bytes);
     return at;
   };
-  const size_t nsc = (size_t)pc->nx * pc->ny;
-  L.solver = take(coarse_solver_bytes(pc, nprob));
-  L.Uc = take((size_t)nprob * align_up(nsc * pc->nt * 8));
-  L.u0c = take((size_t)nprob * align_up(nsc * 8));
-  L.T1 = take((size_t)pc->nt * pc->ny * p->nx * 8);
-  L.V = take((size_t)pc->nt * p->ny * p->nx * 8);
-  const bool dir = p->bc != PTS_PERIODIC;
-  const int Nx = pc->nx + (dir ? 2 : 0), Ny = pc->ny + (dir ? 2 : 0), Nt = pc->nt + 1;
-  L.Mx = take((size_t)pc->nt * pc->ny * Nx * 8);  // second derivatives along each axis
-  L.My = take((size_t)pc->nt * Ny * p->nx * 8);
-  L.Mt = take((size_t)Nt * p->nx * p->ny * 8);
-  L.dx = axis_dev_layout(Nx, p->nx, dir);
-  L.dy = axis_dev_layout(Ny, p->ny, dir);
-  L.dt = axis_dev_layout(Nt, p->nt, false);
-  L.Sx = take(L.dx.total);
-  L.Sy = take(L.dy.total);
-  L.St = take(L.dt.total);
-  L.Th = take((size_t)2 * Nt * 8);  // Thomas elimination of the time spline
-  L.bdc = take(dir ? (size_t)pc->nt * 2 * (pc->nx + pc->ny) * 8 : 0);
-  L.edges = take(dir ? (size_t)pc->nt * 2 * (pc->ny + p->nx) * 8 : 0);  // west_c, east_c, south_f, north_f
+  L.in.resize(nprob);
+  std::vector<pts_problem> pcs(nprob);
+  *rc = PTS_OK;
+  for (int i = 0; i < nprob && !*rc; ++i) {
+    if ((*rc = validate(p + i))) break;
+    *rc = coarse_problem(p + i, cf, &pcs[i]);
+  }
+  if (*rc) return L;
+  L.solver = take(coarse_solver_bytes(pcs));
+  L.tab = o;
+  for (int i = 0; i < nprob; ++i) {
+    const pts_problem& f = p[i];
+    const pts_problem& c = pcs[i];
+    CoarseInst& q = L.in[i];
+    q.pc = c;
+    const bool dir = f.bc != PTS_PERIODIC;
+    q.dx = axis_dev_layout(c.nx + (dir ? 2 : 0), f.nx, dir);
+    q.dy = axis_dev_layout(c.ny + (dir ? 2 : 0), f.ny, dir);
+    q.dt = axis_dev_layout(c.nt + 1, f.nt, false);
+    q.Sx = take(q.dx.total);
+    q.Sy = take(q.dy.total);
+    q.St = take(q.dt.total);
+    q.Th = take((size_t)2 * (c.nt + 1) * 8);  // Thomas elimination of the time spline
+  }
+  L.tab_end = o;
+  size_t t1 = 0, v = 0, mx = 0, my = 0, mt = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const pts_problem& f = p[i];
+    const pts_problem& c = pcs[i];
+    CoarseInst& q = L.in[i];
+    const bool dir = f.bc != PTS_PERIODIC;
+    const size_t nsc = (size_t)c.nx * c.ny;
+    const int Nx = c.nx + (dir ? 2 : 0), Ny = c.ny + (dir ? 2 : 0), Nt = c.nt + 1;
+    q.Uc = take(nsc * c.nt * 8);
+    q.u0c = take(nsc * 8);
+    // Dirichlet data (the size does not depend on whether the caller passes any, so that a
+    // workspace sized from the problem alone fits)
+    q.bdc = take(dir ? (size_t)c.nt * 2 * (c.nx + c.ny) * 8 : 0);
+    q.edges = take(dir ? (size_t)c.nt * 2 * (c.ny + f.nx) * 8 : 0);  // west_c, east_c, south_f, north_f
+    t1 = std::max(t1, (size_t)c.nt * c.ny * f.nx);
+    v = std::max(v, (size_t)c.nt * f.ny * f.nx);
+    mx = std::max(mx, (size_t)c.nt * c.ny * Nx);  // second derivatives along each axis
+    my = std::max(my, (size_t)c.nt * Ny * f.nx);
+    mt = std::max(mt, (size_t)Nt * f.nx * f.ny);
+  }
+  L.T1 = take(t1 * 8);
+  L.V = take(v * 8);
+  L.Mx = take(mx * 8);
+  L.My = take(my * 8);
+  L.Mt = take(mt * 8);
   L.total = o;
   return L;
 }
@@ -3078,13 +3151,16 @@ int pts_window_bound(double h, double mu, double tau, double c, double eps, int 
   return best;
 }
 
-size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf) { return pts_coarse_workspace_bytes_batched(p, cf, 1); }
+size_t pts_coarse_workspace_bytes(const pts_problem* p, int cf) { return pts_coarse_workspace_bytes_batched(p, 1, cf); }
 
-size_t pts_coarse_workspace_bytes_batched(const pts_problem* p, int cf, int nprob) {
-  if (validate(p) || nprob < 1) return 0;
-  pts_problem pc;
-  if (coarse_problem(p, cf, &pc)) return 0;
-  return coarse_layout(p, &pc, nprob).total;
+size_t pts_coarse_workspace_bytes_batched(const pts_problem* probs, int nprob, int cf) {
+  if (!probs || nprob < 1) {
+    fail(PTS_ERR_INVALID_ARG, "coarse iterate: no instances");
+    return 0;
+  }
+  int rc;
+  const CoarseLayout L = coarse_layout(probs, nprob, cf, &rc);
+  return rc ? 0 : L.total;
 }
 
 int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, double* U, double tol, int max_iter,
@@ -3093,120 +3169,131 @@ int pts_coarse_initial_iterate(const pts_problem* p, int cf, const double* u0, d
                                             stream);
 }
 
-int pts_coarse_initial_iterate_batched(const pts_problem* p, int nprob, int cf, const double* const* u0,
+int pts_coarse_initial_iterate_batched(const pts_problem* probs, int nprob, int cf, const double* const* u0,
                                        double* const* U, double tol, int max_iter, void* workspace,
                                        size_t workspace_bytes, pts_stats* stats, pts_stream_t stream) {
   if (stats && nprob > 0) std::memset(stats, 0, (size_t)nprob * sizeof(pts_stats));
-  int rc = validate(p);
+  if (!probs || nprob < 1) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: no instances");
+  int rc;
+  const CoarseLayout L = coarse_layout(probs, nprob, cf, &rc);
   if (rc) return rc;
-  if (nprob < 1) return fail(PTS_ERR_INVALID_ARG, "coarse iterate: no instances");
-  pts_problem pc;
-  if ((rc = coarse_problem(p, cf, &pc))) return rc;
+  for (int i = 1; i < nprob; ++i)
+    if (probs[i].kind != probs[0].kind || probs[i].bc != probs[0].bc)
+      return fail(PTS_ERR_INVALID_ARG, "coarse iterate: instance %d: kind and boundary kind differ", i);
   if (!U || !u0) return fail(PTS_ERR_INVALID_ARG, "pts_coarse_initial_iterate: NULL array");
   for (int i = 0; i < nprob; ++i)
     if (!U[i] || !u0[i]) return fail(PTS_ERR_INVALID_ARG, "pts_coarse_initial_iterate: instance %d: NULL array", i);
   if (!(tol >= 0) || max_iter < 0) return fail(PTS_ERR_INVALID_ARG, "tol/max_iter");
-  const CoarseLayout L = coarse_layout(p, &pc, nprob);
   if (!workspace || workspace_bytes < L.total)
     return fail(PTS_ERR_WORKSPACE, "coarse workspace %zu bytes < required %zu", workspace_bytes, L.total);
   if ((uintptr_t)workspace % kAlign) return fail(PTS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)workspace;
-  const size_t nsc = (size_t)pc.nx * pc.ny;
-  std::vector<double*> Uc(nprob), u0c(nprob);
-  for (int i = 0; i < nprob; ++i) {
-    Uc[i] = (double*)(w + L.Uc + (size_t)i * align_up(nsc * pc.nt * 8));
-    u0c[i] = (double*)(w + L.u0c + (size_t)i * align_up(nsc * 8));
-  }
   double* T1 = (double*)(w + L.T1);
   double* V = (double*)(w + L.V);
   double* Mx = (double*)(w + L.Mx);
   double* My = (double*)(w + L.My);
   double* Mt = (double*)(w + L.Mt);
-  const char* Sx = w + L.Sx;
-  const char* Sy = w + L.Sy;
-  const char* St = w + L.St;
-  const bool per = p->bc == PTS_PERIODIC, dir = !per;
-  // splines: x and y (Dirichlet axes with edge nodes), time (nodes t = m cf tau, m = 0..nt/cf;
-  // fine level n at n / cf)
-  const AxisSpline ax = space_spline(per, p->nx, pc.nx, cf), ay = space_spline(per, p->ny, pc.ny, cf);
-  std::vector<double> stimes(p->nt);
-  for (int n = 0; n < p->nt; ++n) stimes[n] = (double)(n + 1) / cf;
-  const AxisSpline at = axis_spline(pc.nt + 1, false, stimes);
-  // the Thomas elimination of the time spline's inner rows (not-a-knot: first and last rows
-  // 6 M = d, no coupling; the others 1, 4, 1): eliminated super-diagonal and reciprocal pivots
-  const int nth = std::max(pc.nt + 1 - 2, 0);
-  std::vector<double> th(2 * (size_t)(pc.nt + 1), 0.0);
-  for (int i = 0; i < nth; ++i) {
-    const bool end = i == 0 || i == nth - 1;
-    const double sub = (i == 0 || i == nth - 1) ? 0.0 : 1.0, sup = i == 0 ? 0.0 : 1.0;
-    const double den = (end ? 6.0 : 4.0) - (i ? sub * th[i - 1] : 0.0);
-    th[i] = sup / den;
-    th[nth + i] = 1.0 / den;
-  }
+  const bool per = probs[0].bc == PTS_PERIODIC, dir = !per;
+  // spline tables of every instance: x and y (Dirichlet axes with edge nodes), time (nodes
+  // t = m cf tau, m = 0..ceil(nt/cf); fine level n at (n + 1) / cf), and the Thomas
+  // elimination of the time spline's inner rows (not-a-knot: first and last rows 6 M = d, no
+  // coupling; the others 1, 4, 1): eliminated super-diagonal and reciprocal pivots; one upload
   {
-    std::vector<char> host(L.dx.total + L.dy.total + L.dt.total);
-    axis_dev_fill(ax, dir, L.dx, host.data());
-    axis_dev_fill(ay, dir, L.dy, host.data() + L.dx.total);
-    axis_dev_fill(at, false, L.dt, host.data() + L.dx.total + L.dy.total);
-    HIPCHK(hipMemcpyAsync(w + L.Sx, host.data(), L.dx.total, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w + L.Sy, host.data() + L.dx.total, L.dy.total, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w + L.St, host.data() + L.dx.total + L.dy.total, L.dt.total, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w + L.Th, th.data(), th.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));  // pageable sources: complete before they go
+    const size_t base = L.tab;
+    std::vector<char> host(L.tab_end - base, 0);
+    for (int i = 0; i < nprob; ++i) {
+      const pts_problem& p = probs[i];
+      const CoarseInst& q = L.in[i];
+      const AxisSpline ax = space_spline(per, p.nx, q.pc.nx), ay = space_spline(per, p.ny, q.pc.ny);
+      std::vector<double> stimes(p.nt);
+      for (int n = 0; n < p.nt; ++n) stimes[n] = (double)(n + 1) / cf;
+      const AxisSpline at = axis_spline(q.pc.nt + 1, false, stimes);
+      axis_dev_fill(ax, dir, q.dx, host.data() + (q.Sx - base));
+      axis_dev_fill(ay, dir, q.dy, host.data() + (q.Sy - base));
+      axis_dev_fill(at, false, q.dt, host.data() + (q.St - base));
+      const int Nt = q.pc.nt + 1, nth = std::max(Nt - 2, 0);
+      double* th = (double*)(host.data() + (q.Th - base));
+      for (int k = 0; k < nth; ++k) {
+        const bool end = k == 0 || k == nth - 1;
+        const double sub = end ? 0.0 : 1.0, sup = k == 0 ? 0.0 : 1.0;
+        const double den = (end ? 6.0 : 4.0) - (k ? sub * th[k - 1] : 0.0);
+        th[k] = sup / den;
+        th[nth + k] = 1.0 / den;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(w + base, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before it goes
   }
-  // Dirichlet data of the coarse problem and the ends of the spline lines (shared)
-  double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
-  if (!per && p->bdata) {
-    double* bdc = (double*)(w + L.bdc);
-    west_c = (double*)(w + L.edges);
-    east_c = west_c + (size_t)pc.nt * pc.ny;
-    south_f = east_c + (size_t)pc.nt * pc.ny;
-    north_f = south_f + (size_t)pc.nt * p->nx;
-    const int count = pc.nt * (2 * (pc.nx + pc.ny) + 2 * p->nx);
-    hipLaunchKernelGGL(k_cf_bdata, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p->bdata, p->nx, p->ny,
-                       pc.nx, pc.ny, cf, pc.nt, bdc, west_c, east_c, south_f, north_f);
-    pc.bdata = bdc;
-  }
-  // coarse u^0 by injection and the plain coarse iterates
-  const unsigned bb = (unsigned)std::min<size_t>((nsc * pc.nt + 255) / 256, 8192);
+  // coarse u^0 (bilinear sampling; injection where the grids nest), Dirichlet data and the ends
+  // of the spline lines, plain coarse iterates
+  std::vector<double*> Uc(nprob), u0c(nprob);
+  std::vector<pts_problem> pcs(nprob);
   for (int i = 0; i < nprob; ++i) {
-    hipLaunchKernelGGL(k_cf_inject, dim3((unsigned)((nsc + 255) / 256)), dim3(256), 0, s, u0[i], p->nx, pc.nx,
-                       pc.ny, cf, per ? 0 : cf - 1, u0c[i]);
-    hipLaunchKernelGGL(k_broadcast, dim3(bb), dim3(256), 0, s, nsc, pc.nt, Uc[i], (const double*)u0c[i]);
+    const pts_problem& p = probs[i];
+    const CoarseInst& q = L.in[i];
+    pcs[i] = q.pc;
+    Uc[i] = (double*)(w + q.Uc);
+    u0c[i] = (double*)(w + q.u0c);
+    const size_t nsc = (size_t)q.pc.nx * q.pc.ny;
+    if (dir && p.bdata) {
+      double* west_c = (double*)(w + q.edges);
+      double* east_c = west_c + (size_t)q.pc.nt * q.pc.ny;
+      double* south_f = east_c + (size_t)q.pc.nt * q.pc.ny;
+      double* north_f = south_f + (size_t)q.pc.nt * p.nx;
+      const int count = q.pc.nt * (2 * (q.pc.nx + q.pc.ny) + 2 * p.nx);
+      hipLaunchKernelGGL(k_cf_bdata, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p.bdata, p.nx, p.ny,
+                         q.pc.nx, q.pc.ny, cf, q.pc.nt, (double*)(w + q.bdc), west_c, east_c, south_f, north_f);
+      pcs[i].bdata = (const double*)(w + q.bdc);
+    }
+    hipLaunchKernelGGL(k_cf_sample, dim3((unsigned)((nsc + 255) / 256)), dim3(256), 0, s, u0[i], p.nx, p.ny,
+                       q.pc.nx, q.pc.ny, per ? 1 : 0, u0c[i]);
+    const unsigned bb = (unsigned)std::min<size_t>((nsc * q.pc.nt + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_broadcast, dim3(bb), dim3(256), 0, s, nsc, q.pc.nt, Uc[i], (const double*)u0c[i]);
   }
   HIPCHK(hipGetLastError());
   // the coarse solves (all-at-once Newton: by Theorem 1 the root is the sequential coarse
-  // solution); several instances share batched wavefront launches
-  if (nprob == 1) {
-    rc = solve_slabs(&pc, Uc[0], u0c[0], tol, max_iter, w + L.solver, nullptr, stats, s);
-  } else {
-    const std::vector<pts_problem> pcs(nprob, pc);
+  // solution); several instances share batched launches
+  if (nprob == 1)
+    rc = solve_slabs(&pcs[0], Uc[0], u0c[0], tol, max_iter, w + L.solver, nullptr, stats, s);
+  else
     rc = pts_solve_batched(pcs.data(), nprob, Uc.data(), (const double* const*)u0c.data(), tol, max_iter,
-                           w + L.solver, coarse_solver_bytes(&pc, nprob), nullptr, stats, stream);
-  }
+                           w + L.solver, coarse_solver_bytes(pcs), nullptr, stats, stream);
   if (rc) return rc;
   // splines per instance, each as second derivatives then evaluation: x (coarse rows ->
   // T1[m][yc][x]), y (-> V[m][y][x]), t (u^0 and V -> U[n]); x lines of row yc at level m end in
   // west_c/east_c[m][yc], y lines of column x in south_f/north_f[m][x]. The instances reuse the
   // buffers in stream order.
-  const long nx = p->nx, ny = p->ny, ns = nx * ny;
-  const int Nx = ax.N, Ny = ay.N, Nt = at.N, zoff = dir ? 1 : 0;
-  const long nax = (long)pc.nt * pc.ny;
   for (int i = 0; i < nprob; ++i) {
-    launch_interp(s, (const double*)(Sx + L.dx.g), Nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, Mx, Nx, 1, 0, nax, 1,
-                  dir ? (const double*)(Sx + L.dx.glo) : nullptr, (const double*)(Sx + L.dx.ghi), west_c, east_c, 1,
+    const pts_problem& p = probs[i];
+    const CoarseInst& q = L.in[i];
+    const pts_problem& pc = q.pc;
+    const char* Sx = w + q.Sx;
+    const char* Sy = w + q.Sy;
+    const char* St = w + q.St;
+    const double *west_c = nullptr, *east_c = nullptr, *south_f = nullptr, *north_f = nullptr;
+    if (dir && p.bdata) {
+      west_c = (const double*)(w + q.edges);
+      east_c = west_c + (size_t)pc.nt * pc.ny;
+      south_f = east_c + (size_t)pc.nt * pc.ny;
+      north_f = south_f + (size_t)pc.nt * p.nx;
+    }
+    const long nx = p.nx, ns = nx * p.ny;
+    const int Nx = pc.nx + (dir ? 2 : 0), Ny = pc.ny + (dir ? 2 : 0), Nt = pc.nt + 1, zoff = dir ? 1 : 0;
+    const long nax = (long)pc.nt * pc.ny;
+    launch_interp(s, (const double*)(Sx + q.dx.g), Nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, Mx, Nx, 1, 0, nax, 1,
+                  dir ? (const double*)(Sx + q.dx.glo) : nullptr, (const double*)(Sx + q.dx.ghi), west_c, east_c, 1,
                   0);
-    launch_spline_eval(s, Sx, L.dx, p->nx, Nx, dir, Uc[i], pc.nx, 1, 0, zoff, nullptr, west_c, east_c, 1, 0, Mx, Nx,
+    launch_spline_eval(s, Sx, q.dx, p.nx, Nx, dir, Uc[i], pc.nx, 1, 0, zoff, nullptr, west_c, east_c, 1, 0, Mx, Nx,
                        1, 0, T1, nx, 1, 0, nax, 1);
-    launch_interp(s, (const double*)(Sy + L.dy.g), Ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, My,
-                  (long)Ny * nx, nx, 1, pc.nt, nx, dir ? (const double*)(Sy + L.dy.glo) : nullptr,
-                  (const double*)(Sy + L.dy.ghi), south_f, north_f, nx, 1);
-    launch_spline_eval(s, Sy, L.dy, p->ny, Ny, dir, T1, (long)pc.ny * nx, nx, 1, zoff, nullptr, south_f, north_f,
+    launch_interp(s, (const double*)(Sy + q.dy.g), Ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, My,
+                  (long)Ny * nx, nx, 1, pc.nt, nx, dir ? (const double*)(Sy + q.dy.glo) : nullptr,
+                  (const double*)(Sy + q.dy.ghi), south_f, north_f, nx, 1);
+    launch_spline_eval(s, Sy, q.dy, p.ny, Ny, dir, T1, (long)pc.ny * nx, nx, 1, zoff, nullptr, south_f, north_f,
                        nx, 1, My, (long)Ny * nx, nx, 1, V, ns, nx, 1, pc.nt, nx);
     hipLaunchKernelGGL(k_spline_m_time, dim3((unsigned)std::min<long>((ns + 255) / 256, 65536)), dim3(256), 0, s,
-                       (const double*)(w + L.Th), Nt, u0[i], (const double*)V, ns, Mt);
-    launch_spline_eval(s, St, L.dt, p->nt, Nt, false, V, 0, ns, 1, 1, u0[i], nullptr, nullptr, 0, 0, Mt, 0, ns, 1,
+                       (const double*)(w + q.Th), Nt, u0[i], (const double*)V, ns, Mt);
+    launch_spline_eval(s, St, q.dt, p.nt, Nt, false, V, 0, ns, 1, 1, u0[i], nullptr, nullptr, 0, 0, Mt, 0, ns, 1,
                        U[i], 0, ns, 1, 1, ns);
   }
   HIPCHK(hipGetLastError());

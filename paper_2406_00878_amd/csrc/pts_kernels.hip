@@ -1238,14 +1238,36 @@ __global__ __launch_bounds__(256) void k_broadcast(size_t ns, int nt, double* __
 }
 
 // ------------------------------------------------ coarse-grid initial iterate (Section 4)
-// u0c[yc][xc] = u0[yc cf + off][xc cf + off]: injection onto every cf-th node (off = 0 for a
-// periodic grid, cf - 1 for the interior nodes of a Dirichlet grid).
-__global__ __launch_bounds__(256) void k_cf_inject(const double* __restrict__ u0, int nx, int nxc, int nyc, int cf,
-                                                   int off, double* __restrict__ u0c) {
+// u^0 at the coarse nodes: the bilinear interpolant of the fine u^0. Coarse node k of an axis
+// with n fine and nc coarse nodes lies at k n / nc (periodic) or (k + 1)(n + 1) / (nc + 1) - 1
+// (Dirichlet interior nodes) fine spacings from fine node 0; the whole part and the remainder
+// are taken in integers, so a coarse node that is a fine node (every node where the grids
+// nest) takes that node's value unchanged. Dirichlet coarse nodes lie between fine nodes 0
+// and n - 1, periodic ones wrap.
+struct CfPos {
+  int i0, i1;
+  double t;  // weight of i1 (0: the node itself)
+};
+__device__ inline CfPos cf_pos(int k, int n, int nc, bool per) {
+  const long num = per ? (long)k * n : (long)(k + 1) * (n + 1), den = per ? nc : nc + 1;
+  CfPos q;
+  q.i0 = (int)(num / den) - (per ? 0 : 1);
+  const long r = num % den;
+  q.t = (double)r / (double)den;
+  q.i1 = r == 0 ? q.i0 : (per ? (q.i0 + 1) % n : q.i0 + 1);
+  return q;
+}
+__global__ __launch_bounds__(256) void k_cf_sample(const double* __restrict__ u0, int nx, int ny, int nxc, int nyc,
+                                                   int per, double* __restrict__ u0c) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= nxc * nyc) return;
-  const int xc = i % nxc, yc = i / nxc;
-  u0c[i] = u0[(size_t)(yc * cf + off) * nx + (xc * cf + off)];
+  const CfPos px = cf_pos(i % nxc, nx, nxc, per), py = cf_pos(i / nxc, ny, nyc, per);
+  auto row = [&](int y) {
+    const double* r = u0 + (size_t)y * nx;
+    return px.t == 0.0 ? r[px.i0] : (1.0 - px.t) * r[px.i0] + px.t * r[px.i1];
+  };
+  const double a = row(py.i0);
+  u0c[i] = py.t == 0.0 ? a : (1.0 - py.t) * a + py.t * row(py.i1);
 }
 
 // Dirichlet data restricted to the coarse grid, for coarse levels m = 0..ntc-1 (fine level

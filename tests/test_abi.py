@@ -93,18 +93,30 @@ def test_solver_option_validation_on_host():
 
 
 def test_coarse_workspace_bytes_validates_on_host():
-    """pts_coarse_workspace_bytes is host-only: 0 when cf does not divide the sizes."""
+    """pts_coarse_workspace_bytes is host-only: 0 for cf < 2, for fewer than 3 periodic or 1
+    Dirichlet coarse nodes, and for Dirichlet data on grids cf does not divide; grids that cf
+    does not divide are otherwise accepted."""
     import paper_2406_00878_amd as P
     import workloads as W
     lib = P._lib.load()
     q = W.burgers_periodic(32, 8, 5e-4, 0.01, np.zeros((32, 32)))
     p = P.make_problem(q)
     assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 4) > 0
-    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 3) == 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 3) > 0  # 10 coarse nodes, 3 levels
     assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 1) == 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(p), 11) == 0  # 2 coarse nodes
     h = W.heat_dirichlet(31, 12, 1e-3, np.zeros((31, 31)))
-    assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 4) > 0
-    assert lib.pts_coarse_workspace_bytes(ctypes.byref(P.make_problem(h)), 5) == 0
+    ph = P.make_problem(h)
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(ph), 4) > 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(ph), 5) > 0  # 5 coarse nodes
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(ph), 17) == 0  # no coarse node
+    ph.bdata = 256  # host check only: the address is never read
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(ph), 4) > 0
+    assert lib.pts_coarse_workspace_bytes(ctypes.byref(ph), 5) == 0
+    assert b"Dirichlet data" in lib.pts_last_error()
+    # per-instance problems of different sizes
+    arr = (P.pts_problem * 2)(P.make_problem(h), P.make_problem(W.heat_dirichlet(50, 9, 1e-3, np.zeros((50, 50)))))
+    assert lib.pts_coarse_workspace_bytes_batched(arr, 2, 4) > lib.pts_coarse_workspace_bytes(ctypes.byref(arr[0]), 4)
 
 
 def test_binding_error_codes_match_the_header():

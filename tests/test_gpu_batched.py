@@ -143,6 +143,31 @@ def test_stiff_heat_batch_pipelined_stages_match_oracle(stages):
         assert err <= 1e-8, (p.name, err)
 
 
+def test_stiff_heat_batch_gives_each_instance_its_own_stage_count():
+    """The first solve of a batch records the Newton steps each instance needed; a second solve
+    of the same batch runs each instance for its own count (an instance whose u^0 is small
+    needs fewer steps than one of amplitude 1), with the same results as the oracle."""
+    rng = np.random.default_rng(41)
+    probs = []
+    for n, L, amp in [(128, 14, 1.0), (100, 9, 1e-4), (90, 11, 0.3)]:
+        probs.append(W.heat_dirichlet(n, L, 1e-3, amp * W.sine_u0_dirichlet(n, rng), name=f"h{n}x{L}a{amp:g}"))
+    u0s = [dev(p.u0) for p in probs]
+    print("[batched] per-instance stage counts", flush=True)
+    first = P.solve_batched(probs, [dev(p.plain_iterate()) for p in probs], u0s, tol=1e-12, max_iter=40,
+                            precision="mixed")
+    need = [st["needed"] for st in first]
+    assert len(set(need)) > 1, need  # the instances need different step counts
+    Us = [dev(p.plain_iterate()) for p in probs]
+    sts = P.solve_batched(probs, Us, u0s, tol=1e-12, max_iter=40, precision="mixed")
+    for p, U, st, k in zip(probs, Us, sts, need):
+        assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
+        assert st["iterations"] == k, (p.name, st["iterations"], k)
+        Uo, _ = sequential.solve_sequential(p)
+        err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
+        print(p.name, "needed", k, "iterations", st["iterations"], "err", err, flush=True)
+        assert err <= 1e-8, (p.name, err)
+
+
 def test_stiff_heat_batch_pipelined_with_boundary_data_matches_oracle():
     """Pipelined multigrid stages on stiff heat instances whose Dirichlet data vary in space and
     time (the level residuals read the data; the V-cycles solve for updates with zero data)."""

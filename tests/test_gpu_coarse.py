@@ -29,6 +29,10 @@ def _cases():
         ("heat_dir31_cf4", W.heat_dirichlet(31, 12, 1e-3, W.sine_u0_dirichlet(31, rng)), 4),
         ("heat_dir31_cf2", W.heat_dirichlet(31, 6, 1e-3, W.sine_u0_dirichlet(31, rng)), 2),
         ("heat_dir71x8_cf8", W.heat_dirichlet(71, 16, 2e-3, W.sine_u0_dirichlet(71, rng)), 8),
+        # grids and level counts that cf does not divide (evenly spaced coarse grids, bilinear u^0)
+        ("heat_dir50x10_cf4_unnested", W.heat_dirichlet(50, 10, 1e-3, W.sine_u0_dirichlet(50, rng)), 4),
+        ("burgers_per45x7_cf4_unnested", W.burgers_periodic(45, 7, 5e-4, 0.01, W.fourier_u0_periodic(45, 76, kmax=3)),
+         4),
     ]
 
 
@@ -60,13 +64,45 @@ def test_newton_from_the_coarse_iterate_reaches_the_oracle_solution():
     assert st_c["iterations"] < st_p["iterations"], (st_c["iterations"], st_p["iterations"])
 
 
-def test_coarse_iterate_rejects_sizes_cf_does_not_divide():
+def test_coarse_iterate_rejects_unusable_sizes():
     p = W.burgers_periodic(32, 8, 5e-4, 0.01, W.fourier_u0_periodic(32, 75, kmax=3))
     U = torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda")
     with pytest.raises(P.PTSError):
-        P.coarse_initial_iterate(p, U, dev(p.u0), 3)  # 3 divides neither 32 nor 8
-    with pytest.raises(P.PTSError):
         P.coarse_initial_iterate(p, U, dev(p.u0), 16)  # 2 coarse nodes per direction
+    q, _ = _mms("heat", 64, 8)
+    V = torch.empty((q.nt, q.ny, q.nx), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PTSError, match="Dirichlet data"):  # 63 + 1 and 8 are no multiples of 3
+        P.coarse_initial_iterate(q, V, dev(q.u0), 3, bdata=dev(q.bdata))
+
+
+def test_batched_coarse_start_of_uneven_instances_and_newton_from_it():
+    """Instances of different grids and level counts that cf = 4 mostly does not divide (the
+    largest with multigrid-preconditioned coarse level solves): each start equals the oracle's;
+    the batched Newton iteration from these starts reaches the sequential solution in fewer
+    steps than from the plain start."""
+    rng = np.random.default_rng(85)
+    sizes = [(40, 9), (63, 12), (57, 13), (255, 37)]
+    probs = [W.heat_dirichlet(n, nt, 1e-3, W.sine_u0_dirichlet(n, rng)) for n, nt in sizes]
+    Us = [torch.empty((q.nt, q.ny, q.nx), dtype=torch.float64, device="cuda") for q in probs]
+    u0s = [dev(q.u0) for q in probs]
+    print("[coarse] uneven batch", sizes, flush=True)
+    sts = P.coarse_initial_iterate_batched(probs, Us, u0s, 4, tol=1e-13)
+    assert all(st["converged"] for st in sts), sts
+    for q, U in zip(probs, Us):
+        Ug, _ = coarse.coarse_initial_iterate(q, 4)
+        err = np.max(np.abs(host(U) - Ug)) / np.max(np.abs(Ug))
+        assert err <= 1e-10, (q.nx, q.nt, err)
+    print("[coarse] Newton from the coarse starts", flush=True)
+    st_c = P.solve_batched(probs, Us, u0s, tol=1e-12, max_iter=40, precision="mixed", stages=7)
+    Vs = [dev(q.plain_iterate()) for q in probs]
+    st_p = P.solve_batched(probs, Vs, u0s, tol=1e-12, max_iter=40, precision="mixed", stages=7)
+    for q, U in zip(probs[:3], Us[:3]):
+        Uo, _ = sequential.solve_sequential(q)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-8 * np.max(np.abs(Uo)), q.nx
+    need_c = max(st["needed"] for st in st_c)
+    need_p = max(st["needed"] for st in st_p)
+    print("Newton steps needed: coarse start", need_c, "plain start", need_p)
+    assert need_c < need_p, (need_c, need_p)
 
 
 def _mms(kind, nint, nt):
