@@ -50,14 +50,16 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
                     "// ------------------------------------------------------------ batched wavefront")]
 
 
-# Bytes past L2 per launch of the heat batch's multigrid kernels (pipelined Newton stages, six
-# per pass), the mean over the dispatches of one solve, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE runs (profiles/mg_kernels_heatbatch64_mixed.md), each scaled by the counter's reading
-# for a 1 GiB fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken
-# with (the device headers and the multigrid section of the kernel file).
+# Bytes past L2 per launch of the heat batch's multigrid kernels (pipelined Newton stages, each
+# instance's own count, from coarse-grid starts with c_f = 4), the mean over the dispatches of
+# the fine solve of one timed step, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# (profiles/mg_kernels_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
+# fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with (the
+# device headers and the multigrid section of the kernel file) and for that form of the batch.
 MG_TRAFFIC = {"kernel_sha256": "307dbcfb008ca9e15275ea2fd25dd3ba25798521597813da4a43d0fed1d2d5d4",
-              "kernels": {"k_pc_resid": (296024537, 178059674), "k_mg_up": (73633134, 37238272),
-                          "k_mg_down": (21499692, 26217677)}}
+              "form": ("coarse", 4),
+              "kernels": {"k_pc_resid": (240716675, 147111322), "k_mg_up": (59549328, 30230016),
+                          "k_mg_down": (17468434, 21267354)}}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("// ---------------------------------------- multigrid-preconditioned level solves",
                 "// ---------------------------------------------------------- wavefront schedule")]
@@ -474,8 +476,6 @@ def bench_learned(args):
     return out
 
 
-COARSE_TOL = 1e-10  # the coarse solves of the heat batch's coarse-grid starts (a start, not the answer)
-
 KERNEL_NAMES = ["k_pc_resid", "k_mg_down", "k_mg_lds", "k_mg_up", "(unused)", "k_residual", "k_update",
                 "k_level_absmax"]
 # the pipelined schedule's own kernels take the last three slots
@@ -515,7 +515,7 @@ def bench_heatbatch(args, extras=None):
 
     def step(**kw):
         if coarse:
-            P.coarse_initial_iterate_batched(probs, Us, u0s, args.cf, tol=COARSE_TOL, max_iter=60, ws=cws)
+            P.coarse_initial_iterate_batched(probs, Us, u0s, args.cf, tol=args.coarse_tol, max_iter=60, ws=cws)
             kw["cache_tag"] = 2
         else:
             for p, U, u0 in zip(probs, Us, u0s):
@@ -559,11 +559,24 @@ def bench_heatbatch(args, extras=None):
     for i, Uo in oracle_levels:
         Ug = Us[i][:Uo.shape[0]].cpu().numpy()
         errs.append(float(np.max(np.abs(Ug - Uo)) / np.max(np.abs(Uo))))
+    start_ms = None
+    if coarse:  # the coarse-grid starts alone (part of every timed step above; after the
+        # accuracy check, which reads the solution)
+        e0.record()
+        P.coarse_initial_iterate_batched(probs, Us, u0s, args.cf, tol=args.coarse_tol, max_iter=60, ws=cws)
+        e1.record()
+        torch.cuda.synchronize()
+        start_ms = e0.elapsed_time(e1)
+        log(f"coarse starts alone: {start_ms:.0f} ms")
     # per-kernel split: one more solve with every launch bracketed by HIP events on the launch
     # stream (the library's profile option); achieved GB/s = algorithmic bytes / event time
     if args.no_split:
         out = {"metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
-               "warmup": args.warmup, "ms_per_step": ms, "config": {"workload": "heatbatch64"}}
+               "warmup": args.warmup, "ms_per_step": ms,
+               "config": {"workload": "heatbatch64", "start": args.start, "newton_steps_min_max": [min(its), max(its)],
+                          "first_solve_ms": first_ms, "coarse_start_ms": start_ms}}
+        if errs:
+            out["rel_err_vs_oracle"] = max(errs)
         return out
     pst = step(profile=True)[0]
     torch.cuda.synchronize()
@@ -592,17 +605,19 @@ def bench_heatbatch(args, extras=None):
                    "seed": 2406004, "tol": args.tol, "precision": "mixed (FP32 multigrid-preconditioned level "
                    "solves, FP64 residuals and updates)",
                    "schedule": "pipelined Newton stages" if pipelined else "batched bulk",
-                   "start": (f"coarse grid (Section 4), c_f = {args.cf}, coarse solves to {COARSE_TOL:g}, inside "
+                   "start": (f"coarse grid (Section 4), c_f = {args.cf}, coarse solves to {args.coarse_tol:g}, inside "
                              "every timed step" if coarse else "plain (u^n = u^0)"),
                    "newton_steps_min_max": [min(its), max(its)],
                    "newton_steps_needed_min_max": [min(need), max(need)] if need else None,
                    "first_solve_ms": first_ms, "first_solve_newton_steps": first_its,
-                   "stages_per_pass_source": "the Newton steps the first solve of this batch needed "
-                                             "(per-signature cache in the library)",
+                   "coarse_start_ms": start_ms,
+                   "stages_per_pass_source": "per instance, the Newton steps the first solve of this batch "
+                                             "needed (per-signature cache in the library)",
                    "chebyshev_iterations_max": max(st["sweeps"] for st in sts)},
         "roofline": {"bound": "hbm", "kernel": names[j], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": mg_traffic(names[j]) if pipelined else None,
+                     "traffic": (mg_traffic(names[j]) if pipelined and (args.start, args.cf) == MG_TRAFFIC["form"]
+                                 else None),
                      "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bpl,
                      "limiter": MG_LIMITER.get(names[j])},
         "kernel_split": split,
@@ -632,9 +647,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="auto")
-    ap.add_argument("--start", choices=["plain", "coarse"], default="plain",
-                    help="initial iterate of every solve (coarse: Section 4)")
-    ap.add_argument("--cf", type=int, default=8, help="coarsening factor of --start coarse")
+    ap.add_argument("--start", choices=["plain", "coarse"], default=None,
+                    help="initial iterate of every solve (coarse: Section 4); default coarse for the heat "
+                         "batch, plain for the single-problem workloads")
+    ap.add_argument("--cf", type=int, default=None,
+                    help="coarsening factor of --start coarse (default 4 for the heat batch, else 8)")
+    ap.add_argument("--coarse-tol", type=float, default=1e-10,
+                    help="heat batch: tolerance of the coarse solves of --start coarse (a start, not the answer)")
     ap.add_argument("--stages", type=int, default=0,
                     help="heat batch: Newton stages per pipelined pass (0: the library's default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of a HIP graph")
@@ -681,8 +700,12 @@ def main():
             args.tol = 1e-10
         out = bench_learned(args)
     elif args.workload == "heatbatch":
+        args.start = args.start or "coarse"
+        args.cf = args.cf or 4
         out = bench_heatbatch(args, None if args.no_extras else (lambda: other_workloads(args)))
     else:
+        args.start = args.start or "plain"
+        args.cf = args.cf or 8
         out = bench_single(args)
     print(json.dumps(out), flush=True)
     if args.hbm_calibration:
@@ -690,13 +713,16 @@ def main():
 
 
 def other_workloads(args):
-    """The other measured workloads of the default run, each with its roofline and CPU baseline:
-    Burgers 256^2 x 512 FP64, Burgers 512^2 x 1024 mixed precision, and the learned initial
-    iterate on Burgers 256^2 x 256 (batched held-out starts). Fewer timed steps than the
-    headline; an error in one is reported in its entry."""
+    """The other measured workloads of the default run: the heat batch from the plain start
+    (timing only), then each with its roofline and CPU baseline Burgers 256^2 x 512 FP64,
+    Burgers 512^2 x 1024 mixed precision, and the learned initial iterate on Burgers 256^2 x 256
+    (batched held-out starts). Fewer timed steps than the headline; an error in one is reported
+    in its entry."""
     import copy
     res = {}
-    jobs = [("burgers256_fp64", dict(workload="burgers256", precision="fp64", tol=1e-12), bench_single),
+    jobs = [("heatbatch64_plain_start", dict(start="plain", no_cpu_baseline=True, no_split=True), bench_heatbatch),
+            ("burgers256_fp64", dict(workload="burgers256", precision="fp64", tol=1e-12, start="plain"),
+             bench_single),
             ("burgers512_mixed", dict(workload="burgers512", precision="mixed", tol=1e-12, start="coarse", cf=8),
              bench_single),
             ("burgers256nu005_learned", dict(learned=True, tol=1e-10, learned_kinds="plain,learned",

@@ -1992,11 +1992,13 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
     for (int c : *cached) cmax = std::max(cmax, c);
   const int npass_c = cmax > 0 ? (cmax + kLanes - 2) / (kLanes - 1) : 1;
   std::vector<int> nstages(nprob, kLanes - 1);
+  const bool from_cache = !(o && o->stages > 0) && cmax > 0;
+  std::vector<int> cache_old = from_cache ? *cached : std::vector<int>();
   for (int i = 0; i < nprob; ++i) {
     if (o && o->stages > 0)
       nstages[i] = std::min(kLanes - 1, o->stages);
-    else if (cmax > 0)
-      nstages[i] = std::min(kLanes - 1, std::max(1, ((*cached)[i] + npass_c - 1) / npass_c));
+    else if (from_cache)
+      nstages[i] = std::min(kLanes - 1, std::max(1, (cache_old[i] + npass_c - 1) / npass_c));
   }
   std::vector<int> conv_it(nprob, -1);  // Newton step at which each instance met tol (pipelined)
   std::vector<int> done(nprob, 0);      // Newton steps applied to each instance
@@ -2193,7 +2195,10 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       std::vector<int> Si(nprob, 0);
       int S = 0;
       for (int i : order) {
-        Si[i] = std::min(nstages[i], std::max(1, max_iter - done[i]));  // no more steps than max_iter allows
+        // a pass after the stages the cache predicted: the prediction fell short by little (the
+        // residual of a step near tol varies with the start), two more stages
+        const int want = from_cache && done[i] > 0 && done[i] >= cache_old[i] ? 2 : nstages[i];
+        Si[i] = std::min(want, std::max(1, max_iter - done[i]));  // no more steps than max_iter allows
         S = std::max(S, Si[i]);
       }
       std::vector<int> all, solving;
@@ -2336,11 +2341,17 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
         else
           conv_it[i] = done[i] + first;
       }
-      // all instances met tol: keep the Newton steps each instance needed (from its first iterate)
+      // all instances met tol: keep the Newton steps each instance needed (from its first
+      // iterate), never fewer than kept before (a pass that falls short costs a sweep over
+      // every diagonal of the instance; a stage too many costs one level solve per level)
       if (all_met && !(o && o->stages > 0)) {
         bool ok = true;
-        for (int i = 0; i < nprob; ++i) ok = ok && conv_it[i] >= 0;
-        if (ok) g_pass_cache.put(skey, conv_it);
+        std::vector<int> keep = conv_it;
+        for (int i = 0; i < nprob; ++i) {
+          ok = ok && keep[i] >= 0;
+          if (from_cache) keep[i] = std::max(keep[i], cache_old[i]);
+        }
+        if (ok) g_pass_cache.put(skey, keep);
       }
       for (int i : order) {
         const unsigned long long* st = hst.data() + DL.lstat[i];

@@ -161,11 +161,43 @@ def test_stiff_heat_batch_gives_each_instance_its_own_stage_count():
     sts = P.solve_batched(probs, Us, u0s, tol=1e-12, max_iter=40, precision="mixed")
     for p, U, st, k in zip(probs, Us, sts, need):
         assert st["converged"] and st["schedule"] == P.PTS_SCHED_PIPELINE, st
-        assert st["iterations"] == k, (p.name, st["iterations"], k)
+        assert st["needed"] == k and st["iterations"] == k, (p.name, st["iterations"], k)
         Uo, _ = sequential.solve_sequential(p)
         err = np.max(np.abs(host(U) - Uo)) / np.max(np.abs(Uo))
         print(p.name, "needed", k, "iterations", st["iterations"], "err", err, flush=True)
         assert err <= 1e-8, (p.name, err)
+
+
+def test_stiff_heat_batch_stage_cache_falls_short_then_grows():
+    """The stage cache is keyed by the problem, not by u^0: a batch first solved from a small
+    u^0 (few Newton steps) and then from u^0 of amplitude 1 gets too few stages from the
+    cache; the solve goes on in short passes of two stages, converges to the oracle's
+    solution, and the cache grows to the larger count for the next solve."""
+    rng = np.random.default_rng(43)
+    shape = [(120, 10), (96, 13)]
+    base = [W.sine_u0_dirichlet(n, rng) for n, _ in shape]
+    small = [W.heat_dirichlet(n, L, 1e-3, 1e-4 * b, name=f"s{n}") for (n, L), b in zip(shape, base)]
+    full = [W.heat_dirichlet(n, L, 1e-3, b, name=f"f{n}") for (n, L), b in zip(shape, base)]
+    tag = 5
+
+    def run(probs):
+        Us = [dev(p.plain_iterate()) for p in probs]
+        return Us, P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=1e-12, max_iter=40,
+                                   precision="mixed", cache_tag=tag)
+
+    print("[batched] stage cache shortfall", flush=True)
+    _, st_small = run(small)
+    k_small = [st["needed"] for st in st_small]
+    Us, st_full = run(full)  # cache: k_small stages, too few
+    k_full = [st["needed"] for st in st_full]
+    assert all(a < b for a, b in zip(k_small, k_full)), (k_small, k_full)
+    for p, U, st, a in zip(full, Us, st_full, k_small):
+        assert st["converged"], st
+        assert st["iterations"] > a and (st["iterations"] - a) % 2 == 0, (st["iterations"], a)  # passes of 2
+        Uo, _ = sequential.solve_sequential(p)
+        assert np.max(np.abs(host(U) - Uo)) <= 1e-8 * np.max(np.abs(Uo)), p.name
+    _, st_again = run(full)  # the cache now holds the larger counts: one pass of exactly those
+    assert [st["iterations"] for st in st_again] == k_full, (st_again, k_full)
 
 
 def test_stiff_heat_batch_pipelined_with_boundary_data_matches_oracle():

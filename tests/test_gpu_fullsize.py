@@ -113,15 +113,24 @@ def test_fullsize_burgers512_disc_mixed():
 
 
 @pytest.mark.timeout(900)
-def test_fullsize_heat_batch_mixed():
+@pytest.mark.parametrize("start", ["plain", "coarse"])
+def test_fullsize_heat_batch_mixed(start):
     """The 64 uneven nonlinear heat instances (grids 66^2..507^2, 128..1010 levels, 3.35 G
-    space-time nodes), solved as one batch with the multigrid-preconditioned FP32 level solves:
-    (a) at every level of every instance; (b) at 32 levels spread over the instances (one
-    level of every other instance, evenly spaced in its own level range)."""
+    space-time nodes), solved as one batch with the multigrid-preconditioned FP32 level solves,
+    from the plain start and from the coarse-grid start (Section 4, c_f = 4; most grids and
+    level counts are no multiples of 4): (a) at every level of every instance; (b) at 32 levels
+    spread over the instances (one level of every other instance, evenly spaced in its own
+    level range)."""
     probs = W.heat_batch()
-    Us = [dev(p.plain_iterate()) for p in probs]
-    print("[fullsize] heat batch 64 instances mixed solve", flush=True)
-    sts = P.solve_batched(probs, Us, [dev(p.u0) for p in probs], tol=TOL, max_iter=60, precision="mixed")
+    u0s = [dev(p.u0) for p in probs]
+    if start == "plain":
+        Us = [dev(p.plain_iterate()) for p in probs]
+    else:
+        Us = [torch.empty((p.nt, p.ny, p.nx), dtype=torch.float64, device="cuda") for p in probs]
+        print("[fullsize] heat batch coarse starts", flush=True)
+        P.coarse_initial_iterate_batched(probs, Us, u0s, 4, tol=1e-10)
+    print(f"[fullsize] heat batch 64 instances mixed solve ({start} start)", flush=True)
+    sts = P.solve_batched(probs, Us, u0s, tol=TOL, max_iter=60, precision="mixed", cache_tag=0 if start == "plain" else 2)
     assert all(st["converged"] for st in sts)
     jobs, worst = [], 0.0
     for i, (p, Ud) in enumerate(zip(probs, Us)):
