@@ -2995,6 +2995,21 @@ void axis_dev_fill(const AxisSpline& A, bool edges, const AxisDev& D, char* host
   std::memcpy(host + D.zz, A.zz.data(), A.zz.size() * 4);
 }
 
+// The Thomas elimination of the not-a-knot spline through N evenly spaced nodes, as the
+// k_spline_m_* kernels read it: the inner rows M_{z-1} + 4 M_z + M_{z+1} = d_z with the first
+// and last reduced to 6 M = d; th[0..n): eliminated super-diagonal, th[n..2n): reciprocal
+// pivots, n = N - 2.
+void thomas_table(int N, double* th) {
+  const int n = std::max(N - 2, 0);
+  for (int k = 0; k < n; ++k) {
+    const bool end = k == 0 || k == n - 1;
+    const double sub = end ? 0.0 : 1.0, sup = k == 0 ? 0.0 : 1.0;
+    const double den = (end ? 6.0 : 4.0) - (k ? sub * th[k - 1] : 0.0);
+    th[k] = sup / den;
+    th[n + k] = 1.0 / den;
+  }
+}
+
 // The problem on the grid coarsened by cf in x, y and t (FP64 coarse solve). Where cf divides
 // the grid (nx for periodic, nx + 1 for Dirichlet axes) the coarse nodes are every cf-th fine
 // node; otherwise the coarse grid spans the same domain with nx / cf (periodic) or
@@ -3034,7 +3049,7 @@ int coarse_problem(const pts_problem* p, int cf, pts_problem* pc) {
 // (used one after another in stream order, sized for the largest).
 struct CoarseInst {
   pts_problem pc;
-  size_t Uc, u0c, Sx, Sy, St, Th, bdc, edges;
+  size_t Uc, u0c, Sx, Sy, St, Th, Thx, Thy, bdc, edges;  // Th*: Thomas tables of the t, x, y splines
   AxisDev dx, dy, dt;
 };
 struct CoarseLayout {
@@ -3080,6 +3095,8 @@ CoarseLayout coarse_layout(const pts_problem* p, int nprob, int cf, int* rc) {
     q.Sy = take(q.dy.total);
     q.St = take(q.dt.total);
     q.Th = take((size_t)2 * (c.nt + 1) * 8);  // Thomas elimination of the time spline
+    q.Thx = take((size_t)2 * (c.nx + 2) * 8);  // and of the Dirichlet x and y splines
+    q.Thy = take((size_t)2 * (c.ny + 2) * 8);
   }
   L.tab_end = o;
   size_t t1 = 0, v = 0, mx = 0, my = 0, mt = 0;
@@ -3223,15 +3240,9 @@ int pts_coarse_initial_iterate_batched(const pts_problem* probs, int nprob, int 
       axis_dev_fill(ax, dir, q.dx, host.data() + (q.Sx - base));
       axis_dev_fill(ay, dir, q.dy, host.data() + (q.Sy - base));
       axis_dev_fill(at, false, q.dt, host.data() + (q.St - base));
-      const int Nt = q.pc.nt + 1, nth = std::max(Nt - 2, 0);
-      double* th = (double*)(host.data() + (q.Th - base));
-      for (int k = 0; k < nth; ++k) {
-        const bool end = k == 0 || k == nth - 1;
-        const double sub = end ? 0.0 : 1.0, sup = k == 0 ? 0.0 : 1.0;
-        const double den = (end ? 6.0 : 4.0) - (k ? sub * th[k - 1] : 0.0);
-        th[k] = sup / den;
-        th[nth + k] = 1.0 / den;
-      }
+      thomas_table(q.pc.nt + 1, (double*)(host.data() + (q.Th - base)));
+      thomas_table(q.pc.nx + 2, (double*)(host.data() + (q.Thx - base)));
+      thomas_table(q.pc.ny + 2, (double*)(host.data() + (q.Thy - base)));
     }
     HIPCHK(hipMemcpyAsync(w + base, host.data(), host.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));  // pageable source: complete before it goes
@@ -3292,20 +3303,35 @@ int pts_coarse_initial_iterate_batched(const pts_problem* probs, int nprob, int 
     const long nx = p.nx, ns = nx * p.ny;
     const int Nx = pc.nx + (dir ? 2 : 0), Ny = pc.ny + (dir ? 2 : 0), Nt = pc.nt + 1, zoff = dir ? 1 : 0;
     const long nax = (long)pc.nt * pc.ny;
-    launch_interp(s, (const double*)(Sx + q.dx.g), Nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, Mx, Nx, 1, 0, nax, 1,
-                  dir ? (const double*)(Sx + q.dx.glo) : nullptr, (const double*)(Sx + q.dx.ghi), west_c, east_c, 1,
-                  0);
+    // second derivatives along x: a tridiagonal solve per Dirichlet line, the dense weights of the
+    // periodic spline otherwise
+    const unsigned lbx = (unsigned)std::min<long>((nax + 255) / 256, 65536);
+    if (dir)
+      hipLaunchKernelGGL(k_spline_m_line, dim3(lbx), dim3(256), 0, s, (const double*)(w + q.Thx), Nx,
+                         (const double*)Uc[i], (long)pc.nx, 1L, 0L, west_c, east_c, 1L, 0L, Mx, (long)Nx, 1L, 0L, nax,
+                         1L);
+    else
+      launch_interp(s, (const double*)(Sx + q.dx.g), Nx, pc.nx, Uc[i], pc.nx, 1, 0, nullptr, Mx, Nx, 1, 0, nax, 1,
+                    nullptr, (const double*)(Sx + q.dx.ghi), west_c, east_c, 1, 0);
     launch_spline_eval(s, Sx, q.dx, p.nx, Nx, dir, Uc[i], pc.nx, 1, 0, zoff, nullptr, west_c, east_c, 1, 0, Mx, Nx,
                        1, 0, T1, nx, 1, 0, nax, 1);
-    launch_interp(s, (const double*)(Sy + q.dy.g), Ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, My,
-                  (long)Ny * nx, nx, 1, pc.nt, nx, dir ? (const double*)(Sy + q.dy.glo) : nullptr,
-                  (const double*)(Sy + q.dy.ghi), south_f, north_f, nx, 1);
+    const unsigned lby = (unsigned)std::min<long>(((long)pc.nt * nx + 255) / 256, 65536);
+    if (dir)
+      hipLaunchKernelGGL(k_spline_m_line, dim3(lby), dim3(256), 0, s, (const double*)(w + q.Thy), Ny,
+                         (const double*)T1, (long)pc.ny * nx, nx, 1L, south_f, north_f, nx, 1L, My, (long)Ny * nx, nx,
+                         1L, (long)pc.nt, nx);
+    else
+      launch_interp(s, (const double*)(Sy + q.dy.g), Ny, pc.ny, T1, (long)pc.ny * nx, nx, 1, nullptr, My,
+                    (long)Ny * nx, nx, 1, pc.nt, nx, nullptr, (const double*)(Sy + q.dy.ghi), south_f, north_f, nx, 1);
     launch_spline_eval(s, Sy, q.dy, p.ny, Ny, dir, T1, (long)pc.ny * nx, nx, 1, zoff, nullptr, south_f, north_f,
                        nx, 1, My, (long)Ny * nx, nx, 1, V, ns, nx, 1, pc.nt, nx);
     hipLaunchKernelGGL(k_spline_m_time, dim3((unsigned)std::min<long>((ns + 255) / 256, 65536)), dim3(256), 0, s,
                        (const double*)(w + q.Th), Nt, u0[i], (const double*)V, ns, Mt);
-    launch_spline_eval(s, St, q.dt, p.nt, Nt, false, V, 0, ns, 1, 1, u0[i], nullptr, nullptr, 0, 0, Mt, 0, ns, 1,
-                       U[i], 0, ns, 1, 1, ns);
+    const int run = std::max(kSplineRun, (p.nt + 65534) / 65535);
+    hipLaunchKernelGGL(k_spline_eval_time,
+                       dim3((unsigned)std::min<long>((ns + 255) / 256, 65536), (unsigned)((p.nt + run - 1) / run)),
+                       dim3(256), 0, s, (const int2*)(St + q.dt.zz), (const double4*)(St + q.dt.w), p.nt, run, u0[i],
+                       (const double*)V, ns, (const double*)Mt, U[i]);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));

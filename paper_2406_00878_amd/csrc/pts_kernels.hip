@@ -1379,6 +1379,55 @@ __global__ __launch_bounds__(256) void k_spline_m_time(const double* __restrict_
   }
 }
 
+// The same not-a-knot second derivatives along the lines of a Dirichlet axis (one thread per
+// line (a, b)): node 0 is the low edge value elo[a esa + b esb], node N - 1 the high one (zero
+// when NULL), nodes 1..N-2 in[a isa + (z - 1) isk + b isb]; M[a osa + z osi + b osb]. In place
+// of a dense N x N weight product per line, 4N operations.
+__global__ __launch_bounds__(256) void k_spline_m_line(const double* __restrict__ th, int N,
+                                                       const double* __restrict__ in, long isa, long isk, long isb,
+                                                       const double* __restrict__ elo, const double* __restrict__ ehi,
+                                                       long esa, long esb, double* __restrict__ M, long osa, long osi,
+                                                       long osb, long na, long nb) {
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < na * nb; t += (long)gridDim.x * 256) {
+    const long a = t / nb, b = t % nb, e = a * esa + b * esb, ib = a * isa + b * isb;
+    double* __restrict__ m = M + a * osa + b * osb;
+    auto y = [&](int z) -> double {
+      if (z == 0) return elo ? elo[e] : 0.0;
+      if (z == N - 1) return ehi ? ehi[e] : 0.0;
+      return in[ib + (long)(z - 1) * isk];
+    };
+    if (N < 3) {
+      for (int z = 0; z < N; ++z) m[(long)z * osi] = 0.0;
+      continue;
+    }
+    if (N == 3) {
+      const double c = y(0) - 2.0 * y(1) + y(2);
+      for (int z = 0; z < 3; ++z) m[(long)z * osi] = c;
+      continue;
+    }
+    const int n = N - 2;
+    double ym = y(0), y0 = y(1), dpp = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double yp = y(i + 2);
+      const double d = 6.0 * (ym - 2.0 * y0 + yp);
+      const double sub = (i == 0 || i == n - 1) ? 0.0 : 1.0;
+      const double dp = (d - sub * dpp) * th[n + i];
+      m[(long)(i + 1) * osi] = dp;
+      dpp = dp;
+      ym = y0;
+      y0 = yp;
+    }
+    double mnext = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double v = m[(long)(i + 1) * osi] - (i + 1 < n ? th[i] * mnext : 0.0);
+      m[(long)(i + 1) * osi] = v;
+      mnext = v;
+    }
+    m[0] = 2.0 * m[osi] - m[2 * osi];
+    m[(long)(N - 1) * osi] = 2.0 * m[(long)(N - 2) * osi] - m[(long)(N - 3) * osi];
+  }
+}
+
 // Evaluation of 1-D cubic splines from node values and second derivatives: fine point i lies
 // in the interval (z0, z1) = zz[i] of the N spline nodes, and out[a][i][b] = w.x y(z0) + w.y
 // y(z1) + w.z M(z0) + w.w M(z1) (w = wt[i]). Node z holds, with edges set, the edge values
@@ -1393,10 +1442,7 @@ __global__ __launch_bounds__(256) void k_spline_eval(const int2* __restrict__ zz
                                                      double* __restrict__ out, long osa, long osi, long osb, long na,
                                                      long nb) {
   const long total = na * nf * nb;
-  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
-    const long b = t % nb, r = t / nb;
-    const int i = (int)(r % nf);
-    const long a = r / nf;
+  auto point = [&](long a, int i, long b) {
     const int2 z = zz[i];
     const double4 w = wt[i];
     auto node = [&](int k) -> double {
@@ -1413,6 +1459,52 @@ __global__ __launch_bounds__(256) void k_spline_eval(const int2* __restrict__ zz
     v = fma(w.z, m[(long)z.x * msk], v);
     v = fma(w.w, m[(long)z.y * msk], v);
     out[a * osa + (long)i * osi + b * osb] = v;
+  };
+  if (total < (1L << 31)) {  // 32-bit index arithmetic (t + stride stays below 2^32)
+    const unsigned nb32 = (unsigned)nb, nf32 = (unsigned)nf;
+    for (unsigned t = blockIdx.x * 256u + threadIdx.x; t < (unsigned)total; t += gridDim.x * 256u) {
+      const unsigned b = t % nb32, r = t / nb32;
+      point((long)(r / nf32), (int)(r % nf32), (long)b);
+    }
+    return;
+  }
+  for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long b = t % nb, r = t / nb;
+    point(r / nf, (int)(r % nf), b);
+  }
+}
+
+// The time pass of the evaluation: one thread per node b and run of `run` fine levels
+// (blockIdx.y), walking its levels in order; the two spline nodes of the current interval and
+// their second derivatives stay in registers and are read again only when the interval changes
+// (where the general kernel reads four values per fine level). Node 0 is in0[b] (u^0), node
+// z > 0 is in[(z - 1) ns + b]; M is [z][ns]; out[i ns + b] for fine level i.
+constexpr int kSplineRun = 16;  // fine levels per thread (more where gridDim.y would exceed 65535)
+__global__ __launch_bounds__(256) void k_spline_eval_time(const int2* __restrict__ zz, const double4* __restrict__ wt,
+                                                          int nf, int run, const double* __restrict__ in0,
+                                                          const double* __restrict__ in, long ns,
+                                                          const double* __restrict__ M, double* __restrict__ out) {
+  const int i0 = blockIdx.y * run, i1 = min(nf, i0 + run);
+  for (long b = (long)blockIdx.x * 256 + threadIdx.x; b < ns; b += (long)gridDim.x * 256) {
+    auto y = [&](int z) -> double { return z == 0 ? in0[b] : in[(long)(z - 1) * ns + b]; };
+    int cur = -1;
+    double y0 = 0.0, y1 = 0.0, m0 = 0.0, m1 = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      const int2 z = zz[i];
+      if (z.x != cur) {
+        cur = z.x;
+        y0 = y(z.x);
+        y1 = y(z.y);
+        m0 = M[(long)z.x * ns + b];
+        m1 = M[(long)z.y * ns + b];
+      }
+      const double4 w = wt[i];
+      double v = w.x * y0;
+      v = fma(w.y, y1, v);
+      v = fma(w.z, m0, v);
+      v = fma(w.w, m1, v);
+      out[(long)i * ns + b] = v;
+    }
   }
 }
 
