@@ -35,7 +35,7 @@
  *     hipHostMalloc, grown on demand); up to 32 instantiated HIP graphs of
  *     wavefront sequences (keyed by their launch arguments, oldest dropped);
  *     autotuned plans, stage counts and slab lengths per problem signature,
- *     and the Newton stages per pipelined pass per batch signature.
+ *     and each instance's Newton stage count per pipelined batch signature.
  *     pts_autotune additionally allocates one device copy of U for the
  *     duration of the call. Device memory beyond that is the caller's
  *     workspace, except for pts_newton_step_static (see there).
@@ -116,8 +116,9 @@ typedef struct pts_options {
                         schedule without graph); totals land in pts_stats      */
   int32_t cache_tag; /* solves with different tags keep separate autotuned plans
                         and Newton step counts for the same problem signature
-                        (e.g. 1 for starts from a learned initial iterate, which
-                        need fewer steps than the plain one); 0 = default      */
+                        (e.g. 1 for starts from a learned initial iterate, 2 for
+                        coarse-grid starts, which need fewer steps than the
+                        plain one); 0 = default                                 */
   int32_t wave_launch; /* PIPELINE: 0 = one launch per anti-diagonal, replayed
                         from a HIP graph (the faster form on MI355X); 1 = each
                         wavefront sequence as one cooperative launch with a
@@ -308,9 +309,10 @@ int pts_autotune(const pts_problem* p, double* U, const double* u0, double tol, 
    PTS_SCHED_PIPELINE, iterations a multiple of the stage count, res_inf and
    rho_max of the steps inside a pass from the stage residuals the lanes formed,
    upd_rms NaN). Without opts->stages, a batch solved again with the same
-   signature (kinds, sizes, coefficients, precision, tol) runs the Newton steps
-   it needed last time, in as few passes of at most 7 stages as possible (a
-   per-thread cache). This path
+   signature (kinds, sizes, coefficients, precision, tol, opts->cache_tag) gives
+   each instance the Newton steps it needed before (the largest count seen; in
+   as many passes of at most 7 stages as the largest needs; a pass that falls
+   short is followed by passes of 2 stages; a per-thread cache). This path
    synchronises the stream once per diagonal (it reads back the iteration
    counts the lanes planned). Instances with different
    boundary kinds or precisions, opts->schedule = PTS_SCHED_PIPELINE (for
