@@ -1929,14 +1929,21 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
                        (size_t)probs[i].nx * probs[i].ny, (unsigned long long*)(mg_base + DL.lmax[i]));
     ++launches;
   };
+  // the initial residual's maxima (convergence, Gershgorin radius, level maxima); the pipelined
+  // multigrid lanes form each level's residual themselves, so a batch that may take them stores
+  // none here (and forms it again below if its blocks turn out not to be stiff)
+  const bool may_pipe = eligible && (o == nullptr || o->schedule != PTS_SCHED_BULK);
   for (int i = 0; i < nprob; ++i) {
-    if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
+    if ((rc = in[i].residual(U[i], u0[i], s, &launches, !may_pipe))) return rc;
     if (eligible) level_max(i);
   }
   if ((rc = read_all(false, false, eligible))) return rc;
   double rho0 = 0.0;
   for (int i = 0; i < nprob; ++i) rho0 = std::max(rho0, h_sc[4 * i + 1]);
   use_mg = eligible && rho0 >= kMgRho;
+  if (may_pipe && !use_mg)
+    for (int i = 0; i < nprob; ++i)
+      if ((rc = in[i].residual(U[i], u0[i], s, &launches))) return rc;
   if (use_mg) {
     // hierarchies (fixed for the solve): one transfer table per instance, grids per lane
     size_t to = 0;
