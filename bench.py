@@ -56,10 +56,10 @@ KERNEL_SECTIONS = [("// --------------------------------------------------------
 # (profiles/mg_kernels_heatbatch64_mixed.md), each scaled by the counter's reading for a 1 GiB
 # fill / 1 GiB sum; valid for the sources of the multigrid kernels they were taken with (the
 # device headers and the multigrid section of the kernel file) and for that form of the batch.
-MG_TRAFFIC = {"kernel_sha256": "307dbcfb008ca9e15275ea2fd25dd3ba25798521597813da4a43d0fed1d2d5d4",
+MG_TRAFFIC = {"kernel_sha256": "790b70b0c350127a2e992bedbc4de9391949014de142b804fb83bcadf727d024",
               "form": ("coarse", 4),
-              "kernels": {"k_pc_resid": (239978075, 146780467), "k_mg_up": (59413364, 30162125),
-                          "k_mg_down": (17426047, 21220454)}}
+              "kernels": {"k_pc_resid": (248962956, 152870707), "k_mg_up": (61529756, 31275110),
+                          "k_mg_down": (18065777, 22011392)}}
 MG_HEADERS = ["paper_2406_00878_amd/csrc/pts_device.hpp", "paper_2406_00878_amd/csrc/pts_mg.hpp"]
 MG_SECTIONS = [("// ---------------------------------------- multigrid-preconditioned level solves",
                 "// ---------------------------------------------------------- wavefront schedule")]

@@ -2218,13 +2218,14 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
       // each lane plans its level's iterations from that level's max |u| (k_pipe_cheb); the
       // host reads the plans back and launches the most any lane needs. A lane's plan is
       // capped at the plan for twice the largest level maximum of the iterate the pass starts
-      // from (the heat iterates do not grow: the cap only bounds a run-away iterate's work).
+      // from and the tightest reduction a lane asks, lin_tol / 10 (the heat iterates do not
+      // grow: the cap only bounds a run-away iterate's work).
       int kcap = 1;
       for (int i : order) {
         double um = 0.0;
         for (int n = 0; n < probs[i].nt; ++n) um = std::max(um, h_lm[ofs_nt[i] + n]);
         float2 c[kMaxCheb];
-        kcap = std::max(kcap, mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, 2.0 * um, lin_tol, c));
+        kcap = std::max(kcap, mg_cheb_plan(probs[i].mu_a, probs[i].mu_b, 2.0 * um, lin_tol / 10.0, c));
       }
       for (int i = 0; i < nprob; ++i)
         for (int ln = 0; ln < kLanes; ++ln) {
@@ -2242,6 +2243,7 @@ int solve_batched_bulk(const pts_problem* probs, int nprob, double* const* U, co
           d.park_in = ln < Si[i] ? (const double*)(mg_base + DL.park[q]) : nullptr;
           d.dprev = ln >= 1 ? (const float*)(mg_base + DL.ring[q - 1]) : nullptr;
           d.tgt = lin_tol;
+          d.ntol = tol / 3.0;
           d.kcap = kcap;
           h_dd[q] = d;
         }

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_level_solve_batched(const BatchDes
 // V-cycle launches), d = c0 d + c1 z, x += d (ChebStep, applied once, where the V-cycle writes
 // its finest grid: k_mg_up, or k_mg_lds where the whole V-cycle runs in LDS).
 constexpr int kMaxCheb = 48;  // Chebyshev iterations per level solve
-constexpr int kStat = 5;      // words of a pipelined lane's statistics per level
+constexpr int kStat = 6;      // words of a pipelined lane's statistics per level
 // One level solver's arrays. In the bulk schedule there is one per instance (stage 0, full
 // space-time R and dU). In the pipelined schedule there is one per (instance, Newton stage s),
 // a "lane": a launch for diagonal D has lane s work on level n = D - s, with its residual in a
@@ -448,8 +448,9 @@ struct PcDesc {
   float* dxf;              // the lane's update ring (float32, two levels): the level solve's iterate
   const float* dprev;      // lane s-1's update ring
   unsigned long long* stat;  // [nt][kStat] max |U^(s)_n|, max |R^(s)_n|, Gershgorin radius, max |b|,
-                             // max |b - A x0| of the level solve (bit patterns)
+                             // max |b - A x0| of the level solve, max |b| over levels 0..n (bit patterns)
   double tgt;              // residual reduction asked of a level solve
+  double ntol;             // a third of the Newton tolerance (the last step's linear residual)
   int kcap;                // at most this many iterations (the launches the host issues)
 };
 
@@ -783,12 +784,21 @@ __global__ __launch_bounds__(64) void k_pipe_cheb(const PcDesc* __restrict__ ds,
     kq[q] = 0;
     return;
   }
-  const unsigned long long* st = d->stat + kStat * (size_t)n;
+  unsigned long long* st = d->stat + kStat * (size_t)n;
   const double umax = __longlong_as_double((long long)st[0]);
   // the solve starts from x0 = du^{n-1} (k_pc_resid): it has to reduce |b - A x0| to tgt |b|
   const double bmax = __longlong_as_double((long long)st[3]), r0 = __longlong_as_double((long long)st[4]);
+  // max |b| over this lane's levels so far (level n-1's entry: written by this thread's lane at
+  // the previous diagonal)
+  const double run = n > 0 ? fmax(bmax, __longlong_as_double((long long)st[5 - kStat])) : bmax;
+  st[5] = (unsigned long long)__double_as_longlong(run);
   double tgt = d->tgt;
-  if (r0 > 0.0 && bmax > 0.0) tgt = fmin(0.5, d->tgt * bmax / r0);
+  // where the reduction asked leaves a linear residual tgt max|b| within a factor 10 of tol over
+  // all of the lane's levels so far, this Newton step can be the instance's last: each level
+  // solves to ntol instead (at most 10x tighter), so that the step's result meets tol rather than
+  // missing it narrowly and taking one more step
+  if (bmax > 0.0 && d->ntol > 0.0 && 10.0 * d->ntol >= d->tgt * run) tgt = fmin(tgt, d->ntol / bmax);
+  if (r0 > 0.0 && bmax > 0.0) tgt = fmin(0.5, tgt * bmax / r0);
   int K = mg_cheb_plan(d->p.mu_a, d->p.mu_b, umax, tgt, d->c + (size_t)n * kMaxCheb);
   K = K < d->kcap ? K : d->kcap;
   d->K[n] = K;
