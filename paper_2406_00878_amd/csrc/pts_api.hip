@@ -3234,8 +3234,8 @@ int pts_coarse_initial_iterate_batched(const pts_problem* probs, int nprob, int 
   const bool per = probs[0].bc == PTS_PERIODIC, dir = !per;
   // spline tables of every instance: x and y (Dirichlet axes with edge nodes), time (nodes
   // t = m cf tau, m = 0..ceil(nt/cf); fine level n at (n + 1) / cf), and the Thomas
-  // elimination of the time spline's inner rows (not-a-knot: first and last rows 6 M = d, no
-  // coupling; the others 1, 4, 1): eliminated super-diagonal and reciprocal pivots; one upload
+  // eliminations of the time spline's and the Dirichlet x and y splines' inner rows
+  // (thomas_table); one upload
   {
     const size_t base = L.tab;
     std::vector<char> host(L.tab_end - base, 0);
